@@ -1,0 +1,21 @@
+"""Seeded synthetic inputs shared by the FP64 oracle and the HIP library.
+
+This package holds mesh generators (vertex coordinates, element-to-vertex
+connectivity, boundary tags), the seeded draws of the batched workload and
+seeded random arrays.  It contains none of the discretisation's arithmetic:
+no quadrature, no basis, no geometry factors, no flux.  Both sides derive
+everything else from these arrays on their own.
+"""
+
+from .meshes import (  # noqa: F401
+    TAG_INTERIOR,
+    TAG_WALL,
+    TAG_FARFIELD,
+    TAG_EXACT,
+    Mesh,
+    ogrid,
+    cubed_sphere_shell,
+    box,
+    radial_map,
+)
+from .draws import batch_draws, seeded_array  # noqa: F401

@@ -1,0 +1,220 @@
+"""Synthetic straight-sided quad / hex meshes standing in for the paper's
+cylinder (Section 5.1) and sphere (Section 5.2) grids.
+
+Conventions shared by every consumer (they are the input format, not method
+arithmetic):
+
+* ``xyz`` is ``float64[n_vert, dim]``.
+* ``elem_vert`` is ``int32[n_elem, 2**dim]``; local vertex ``a + 2 b (+ 4 c)``
+  sits at reference corner ``xi = (2a-1, 2b-1[, 2c-1])`` of ``[-1, 1]^dim``.
+  Elements are positively oriented (the trilinear map has positive Jacobian).
+* ``bface_tag`` is ``int8[n_elem, 2*dim]``; local face ``2 r + s`` is the face
+  ``xi_r = -1`` (s = 0) or ``xi_r = +1`` (s = 1).  Tags: 0 interior (matched
+  to a neighbour through its shared vertices), 1 slip wall, 2 far-field,
+  3 exact-state ghost (manufactured-solution tests of the oracle only).
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+TAG_INTERIOR = 0
+TAG_WALL = 1
+TAG_FARFIELD = 2
+TAG_EXACT = 3
+
+
+@dataclasses.dataclass
+class Mesh:
+    dim: int
+    xyz: np.ndarray        # float64 [n_vert, dim]
+    elem_vert: np.ndarray  # int32 [n_elem, 2**dim]
+    bface_tag: np.ndarray  # int8 [n_elem, 2*dim]
+    name: str = ""
+
+    @property
+    def n_elem(self) -> int:
+        return int(self.elem_vert.shape[0])
+
+    @property
+    def n_vert(self) -> int:
+        return int(self.xyz.shape[0])
+
+    def contiguous(self) -> "Mesh":
+        return Mesh(self.dim,
+                    np.ascontiguousarray(self.xyz, dtype=np.float64),
+                    np.ascontiguousarray(self.elem_vert, dtype=np.int32),
+                    np.ascontiguousarray(self.bface_tag, dtype=np.int8),
+                    self.name)
+
+
+def radial_map(n_r: int, r_in: float = 0.5, r_out: float = 20.0,
+               stretch: float = 1.2, n_ref: int = 12) -> np.ndarray:
+    """Radial node positions r_0..r_{n_r}.
+
+    Geometric spacing with ratio ``stretch`` between consecutive cells when
+    ``n_r == n_ref``; other ``n_r`` sample the same continuous map
+    r(s) = r_in + (r_out - r_in) (stretch^(n_ref s) - 1) / (stretch^n_ref - 1).
+    """
+    s = np.arange(n_r + 1, dtype=np.float64) / n_r
+    g = stretch ** n_ref
+    r = r_in + (r_out - r_in) * (np.power(stretch, n_ref * s) - 1.0) / (g - 1.0)
+    r[0] = r_in
+    r[-1] = r_out
+    return r
+
+
+def ogrid(n_theta: int, n_r: int, r_in: float = 0.5, r_out: float = 20.0,
+          stretch: float = 1.2, n_ref: int = 12, inner: int = TAG_WALL,
+          outer: int = TAG_FARFIELD) -> Mesh:
+    """Structured O-grid of quads around a circle of radius ``r_in``.
+
+    Element (i, j), i circumferential (periodic), j radial (j = 0 touches the
+    body) has index ``j * n_theta + i``.  Reference xi runs outward in r, eta
+    counter-clockwise in theta, so the map is positively oriented; face 0 is
+    the inner arc (``inner`` tag at j = 0), face 1 the outer arc (``outer`` tag
+    at j = n_r - 1), faces 2/3 the two radial edges.
+    """
+    if n_theta < 3 or n_r < 1:
+        raise ValueError("ogrid needs n_theta >= 3 and n_r >= 1")
+    r = radial_map(n_r, r_in, r_out, stretch, n_ref)
+    th = 2.0 * math.pi * np.arange(n_theta, dtype=np.float64) / n_theta
+    c, s = np.cos(th), np.sin(th)
+    # exact axis points keep the mesh mirror-symmetric about y = 0
+    for i in range(n_theta):
+        if 4 * i == n_theta:
+            c[i], s[i] = 0.0, 1.0
+        elif 2 * i == n_theta:
+            c[i], s[i] = -1.0, 0.0
+        elif 4 * i == 3 * n_theta:
+            c[i], s[i] = 0.0, -1.0
+    c[0], s[0] = 1.0, 0.0
+    # vertex (i, j) -> j * n_theta + i
+    xyz = np.empty(((n_r + 1) * n_theta, 2))
+    for j in range(n_r + 1):
+        xyz[j * n_theta:(j + 1) * n_theta, 0] = r[j] * c
+        xyz[j * n_theta:(j + 1) * n_theta, 1] = r[j] * s
+    ev = np.empty((n_r * n_theta, 4), dtype=np.int32)
+    tag = np.zeros((n_r * n_theta, 4), dtype=np.int8)
+    for j in range(n_r):
+        for i in range(n_theta):
+            e = j * n_theta + i
+            ip = (i + 1) % n_theta
+            ev[e] = (j * n_theta + i, (j + 1) * n_theta + i,
+                     j * n_theta + ip, (j + 1) * n_theta + ip)
+            if j == 0:
+                tag[e, 0] = inner
+            if j == n_r - 1:
+                tag[e, 1] = outer
+    return Mesh(2, xyz, ev, tag, f"ogrid{n_theta}x{n_r}")
+
+
+_PANELS = (
+    # (normal, t1, t2) with normal = t1 x t2 (right handed)
+    ((1, 0, 0), (0, 1, 0), (0, 0, 1)),
+    ((-1, 0, 0), (0, 0, 1), (0, 1, 0)),
+    ((0, 1, 0), (0, 0, 1), (1, 0, 0)),
+    ((0, -1, 0), (1, 0, 0), (0, 0, 1)),
+    ((0, 0, 1), (1, 0, 0), (0, 1, 0)),
+    ((0, 0, -1), (0, 1, 0), (1, 0, 0)),
+)
+
+
+def cubed_sphere_shell(n: int, n_r: int, r_in: float = 0.5, r_out: float = 20.0,
+                       stretch: float = 1.2, n_ref: int = 12,
+                       inner: int = TAG_WALL, outer: int = TAG_FARFIELD) -> Mesh:
+    """Equiangular gnomonic cubed-sphere hex shell: 6 panels of n x n columns
+    and ``n_r`` radial layers (6 n^2 n_r hexes).  Vertices on panel seams are
+    shared.  xi runs outward in r; face 0 is on the body (``inner`` tag),
+    face 1 on the outer sphere (``outer`` tag)."""
+    if n < 1 or n_r < 1:
+        raise ValueError("cubed_sphere_shell needs n >= 1 and n_r >= 1")
+    r = radial_map(n_r, r_in, r_out, stretch, n_ref)
+    t = np.tan(-math.pi / 4 + (math.pi / 2) * np.arange(n + 1) / n)
+    t[0], t[-1] = -1.0, 1.0
+    if n % 2 == 0:
+        t[n // 2] = 0.0
+    # unit directions per panel grid point, deduplicated across seams
+    key_to_id: dict = {}
+    dirs = []
+    pid = np.empty((6, n + 1, n + 1), dtype=np.int64)
+    for P, (nv, t1, t2) in enumerate(_PANELS):
+        nv, t1, t2 = (np.array(a, dtype=np.float64) for a in (nv, t1, t2))
+        for a in range(n + 1):
+            for b in range(n + 1):
+                v = nv + t[a] * t1 + t[b] * t2
+                v = v / math.sqrt(float(v @ v))
+                k = tuple(np.round(v * 1e9).astype(np.int64))
+                if k not in key_to_id:
+                    key_to_id[k] = len(dirs)
+                    dirs.append(v)
+                pid[P, a, b] = key_to_id[k]
+    dirs = np.array(dirs)
+    nd = dirs.shape[0]
+    xyz = np.concatenate([r[j] * dirs for j in range(n_r + 1)], axis=0)
+    ne = 6 * n * n * n_r
+    ev = np.empty((ne, 8), dtype=np.int32)
+    tag = np.zeros((ne, 6), dtype=np.int8)
+    e = 0
+    # element order: layer-major, then panel, then (b, a) so neighbours in a
+    # panel are close in memory
+    for j in range(n_r):
+        for P in range(6):
+            for b in range(n):
+                for a in range(n):
+                    for cz in range(2):
+                        for cy in range(2):
+                            for cx in range(2):
+                                ev[e, cx + 2 * cy + 4 * cz] = (
+                                    (j + cx) * nd + pid[P, a + cy, b + cz])
+                    if j == 0:
+                        tag[e, 0] = inner
+                    if j == n_r - 1:
+                        tag[e, 1] = outer
+                    e += 1
+    return Mesh(3, xyz, ev, tag, f"cubedsphere6x{n}x{n}x{n_r}")
+
+
+def box(dim: int, n: int, lo: float = 0.0, hi: float = 1.0, tag: int = TAG_EXACT,
+        skew: float = 0.0, seed: int | None = None) -> Mesh:
+    """Uniform n^dim box of quads/hexes with every boundary face tagged ``tag``.
+
+    ``skew`` > 0 moves interior vertices by a seeded random offset of that
+    fraction of the spacing (still straight-sided, positively oriented for
+    skew < 0.25), so tests do not only see affine elements.
+    """
+    m = n + 1
+    h = (hi - lo) / n
+    grid = np.stack(np.meshgrid(*([lo + h * np.arange(m)] * dim), indexing="ij"),
+                    axis=-1).reshape(-1, dim)
+    # vertex id: lexicographic with the first axis fastest
+    idx = np.arange(m ** dim).reshape([m] * dim, order="F")
+    pts = np.empty((m ** dim, dim))
+    it = np.ndindex(*([m] * dim))
+    for mi in it:
+        pts[idx[mi]] = lo + h * np.array(mi, dtype=np.float64)
+    del grid
+    if skew > 0.0:
+        rng = np.random.Generator(np.random.PCG64(0 if seed is None else seed))
+        off = rng.uniform(-skew * h, skew * h, size=pts.shape)
+        interior = np.all((pts > lo + 0.5 * h) & (pts < hi - 0.5 * h), axis=1)
+        pts[interior] += off[interior]
+    ne = n ** dim
+    ev = np.empty((ne, 2 ** dim), dtype=np.int32)
+    tg = np.zeros((ne, 2 * dim), dtype=np.int8)
+    e = 0
+    for ei in np.ndindex(*([n] * dim)[::-1]):
+        ei = ei[::-1]  # first axis fastest
+        for c in range(2 ** dim):
+            off = [(c >> r) & 1 for r in range(dim)]
+            ev[e, c] = idx[tuple(ei[r] + off[r] for r in range(dim))]
+        for r in range(dim):
+            if ei[r] == 0:
+                tg[e, 2 * r] = tag
+            if ei[r] == n - 1:
+                tg[e, 2 * r + 1] = tag
+        e += 1
+    return Mesh(dim, pts, ev, tg, f"box{dim}d{n}")

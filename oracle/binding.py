@@ -1,0 +1,302 @@
+"""ctypes binding of the C++ oracle (test infrastructure only)."""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "eg_oracle.cpp")
+_LIB = os.path.join(_HERE, "libeg_oracle.so")
+_lib = None
+
+_d = C.POINTER(C.c_double)
+_i32 = C.POINTER(C.c_int32)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with plain FP64 semantics (no contraction, no fast math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["g++", "-std=c++17", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+               "-shared", "-fPIC", "-Wall", "-Wno-unused-function", "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=False)
+        L = C.CDLL(_LIB)
+        L.orc_create.restype = C.c_void_p
+        L.orc_create.argtypes = [C.c_int, C.c_int, _d, C.c_int, _i32, C.POINTER(C.c_int8), C.c_int,
+                                 C.c_double, C.c_double, C.c_double, C.c_double, C.c_char_p, C.c_int]
+        L.orc_free.argtypes = [C.c_void_p]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
+        L.orc_nmodes.restype = C.c_int
+        L.orc_nmodes.argtypes = [C.c_int, C.c_int]
+        L.orc_nfaces.restype = C.c_int
+        L.orc_nfaces.argtypes = [C.c_void_p]
+        L.orc_gauss.argtypes = [C.c_int, _d, _d]
+        L.orc_modes.argtypes = [C.c_int, C.c_int, _i32]
+        L.orc_geometry.argtypes = [C.c_void_p, _d, _d, _d, _d]
+        L.orc_basis_T.argtypes = [C.c_void_p, _d]
+        L.orc_neighbours.argtypes = [C.c_void_p, _i32]
+        L.orc_eval_point.argtypes = [C.c_void_p, C.c_int, C.c_int, _d, _d, _d, _d]
+        L.orc_freestream_state.argtypes = [C.c_void_p, _d]
+        L.orc_freestream.argtypes = [C.c_void_p, C.c_int, _d]
+        L.orc_residual.argtypes = [C.c_void_p, C.c_int, _d, _d]
+        L.orc_residual_complex.argtypes = [C.c_void_p, C.c_int, _d, _d, _d, _d]
+        L.orc_jacobian_blocks.argtypes = [C.c_void_p, C.c_int, _d, _d, _d]
+        L.orc_flux_jac.argtypes = [C.c_int, C.c_double, _d, _d, _d]
+        L.orc_rusanov.argtypes = [C.c_int, C.c_double, _d, _d, _d, _d]
+        L.orc_ghost.argtypes = [C.c_void_p, C.c_int, _d, _d, _d, _d]
+        L.orc_timestep.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, _d, _d]
+        L.orc_rnorm.restype = C.c_double
+        L.orc_rnorm.argtypes = [C.c_void_p, C.c_int, _d]
+        L.orc_cfl_ramp.restype = C.c_double
+        L.orc_cfl_ramp.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int]
+        L.orc_prk.restype = C.c_int
+        L.orc_prk.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, _d, _d]
+        L.orc_exp1.restype = C.c_int
+        L.orc_exp1.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, _d, _d, C.POINTER(C.c_int), _d]
+        L.orc_expm.restype = C.c_int
+        L.orc_expm.argtypes = [C.c_int, _d, _d]
+        L.orc_phi1_e1.restype = C.c_int
+        L.orc_phi1_e1.argtypes = [C.c_int, _d, _d]
+        L.orc_arnoldi_dense.restype = C.c_int
+        L.orc_arnoldi_dense.argtypes = [C.c_int, C.c_int, _d, _d, _d, _d, _d]
+        L.orc_vcycle.restype = C.c_int
+        L.orc_vcycle.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, _d, _d, _d, _d]
+        L.orc_solve.restype = C.c_int
+        L.orc_solve.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, C.c_int,
+                                _d, _d, _d, C.POINTER(C.c_int)]
+        L.orc_mms_project.argtypes = [C.c_void_p, C.c_int, _d]
+        L.orc_mms_forcing.argtypes = [C.c_void_p, C.c_int, _d]
+        L.orc_mms_error.restype = C.c_double
+        L.orc_mms_error.argtypes = [C.c_void_p, C.c_int, _d]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"], "array must be C-contiguous"
+    if a.dtype == np.float64:
+        return a.ctypes.data_as(_d)
+    if a.dtype == np.int32:
+        return a.ctypes.data_as(_i32)
+    if a.dtype == np.int8:
+        return a.ctypes.data_as(C.POINTER(C.c_int8))
+    raise TypeError(a.dtype)
+
+
+def gauss(Q: int):
+    x = np.zeros(Q)
+    w = np.zeros(Q)
+    lib().orc_gauss(Q, _p(x), _p(w))
+    return x, w
+
+
+def modes(dim: int, p: int) -> np.ndarray:
+    n = (p + 1) ** dim
+    a = np.zeros((n, 3), dtype=np.int32)
+    lib().orc_modes(dim, p, _p(a))
+    return a
+
+
+def expm(A: np.ndarray) -> np.ndarray:
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    E = np.zeros_like(A)
+    if lib().orc_expm(A.shape[0], _p(A), _p(E)) != 0:
+        raise RuntimeError("expm failed")
+    return E
+
+
+def phi1_e1(H: np.ndarray) -> np.ndarray:
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    y = np.zeros(H.shape[0])
+    if lib().orc_phi1_e1(H.shape[0], _p(H), _p(y)) != 0:
+        raise RuntimeError("phi1 failed")
+    return y
+
+
+def arnoldi_dense(A: np.ndarray, b: np.ndarray, m: int):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    K = A.shape[0]
+    Vb = np.zeros((m + 1, K))
+    H = np.zeros((m + 1, m))
+    beta = C.c_double(0.0)
+    mu = lib().orc_arnoldi_dense(K, m, _p(A), _p(b), _p(Vb), _p(H), C.byref(beta))
+    return mu, Vb, H, beta.value
+
+
+def rusanov(dim, gamma, UL, UR, nh):
+    UL, UR, nh = (np.ascontiguousarray(a, dtype=np.float64) for a in (UL, UR, nh))
+    F = np.zeros(dim + 2)
+    lib().orc_rusanov(dim, gamma, _p(UL), _p(UR), _p(nh), _p(F))
+    return F
+
+
+def flux_jac(dim, gamma, U, g):
+    U, g = (np.ascontiguousarray(a, dtype=np.float64) for a in (U, g))
+    K = np.zeros((dim + 2, dim + 2))
+    lib().orc_flux_jac(dim, gamma, _p(U), _p(g), _p(K))
+    return K
+
+
+class Oracle:
+    """One mesh + free stream + p_max.  Level-p vectors are float64[E, V, N_p]."""
+
+    def __init__(self, mesh, pmax: int, gamma: float = 1.4, mach: float = 0.3,
+                 alpha_deg: float = 0.0, beta_deg: float = 0.0):
+        m = mesh.contiguous()
+        self.mesh = m
+        self.dim = m.dim
+        self.V = m.dim + 2
+        self.ne = m.n_elem
+        self.pmax = pmax
+        self.gamma = gamma
+        err = C.create_string_buffer(256)
+        h = lib().orc_create(m.dim, m.n_vert, _p(m.xyz), m.n_elem, _p(m.elem_vert), _p(m.bface_tag), pmax,
+                             gamma, mach, alpha_deg, beta_deg, err, 256)
+        if not h:
+            raise ValueError("oracle mesh set-up failed: " + err.value.decode())
+        self._h = C.c_void_p(h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc_free(h)
+            self._h = None
+
+    def N(self, p: int) -> int:
+        return (p + 1) ** self.dim
+
+    def zeros(self, p: int) -> np.ndarray:
+        return np.zeros((self.ne, self.V, self.N(p)))
+
+    def geometry(self):
+        vol, surf, h = (np.zeros(self.ne) for _ in range(3))
+        om = C.c_double(0.0)
+        lib().orc_geometry(self._h, _p(vol), _p(surf), _p(h), C.byref(om))
+        return vol, surf, h, om.value
+
+    def basis_T(self) -> np.ndarray:
+        n = self.N(self.pmax)
+        T = np.zeros((self.ne, n, n))
+        lib().orc_basis_T(self._h, _p(T))
+        return T
+
+    def neighbours(self) -> np.ndarray:
+        nb = np.zeros((self.ne, 2 * self.dim), dtype=np.int32)
+        lib().orc_neighbours(self._h, _p(nb))
+        return nb
+
+    def eval_point(self, p, e, u, xi):
+        U = np.zeros(self.V)
+        x = np.zeros(self.dim)
+        xi = np.ascontiguousarray(xi, dtype=np.float64)
+        lib().orc_eval_point(self._h, p, e, _p(np.ascontiguousarray(u)), _p(xi), _p(U), _p(x))
+        return U, x
+
+    def freestream_state(self) -> np.ndarray:
+        U = np.zeros(self.V)
+        lib().orc_freestream_state(self._h, _p(U))
+        return U
+
+    def freestream(self, p: int) -> np.ndarray:
+        u = self.zeros(p)
+        lib().orc_freestream(self._h, p, _p(u))
+        return u
+
+    def residual(self, p: int, u: np.ndarray) -> np.ndarray:
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        assert u.shape == (self.ne, self.V, self.N(p))
+        r = np.zeros_like(u)
+        lib().orc_residual(self._h, p, _p(u), _p(r))
+        return r
+
+    def residual_complex(self, p: int, u: np.ndarray) -> np.ndarray:
+        ure = np.ascontiguousarray(u.real, dtype=np.float64)
+        uim = np.ascontiguousarray(u.imag, dtype=np.float64)
+        rre, rim = np.zeros_like(ure), np.zeros_like(ure)
+        lib().orc_residual_complex(self._h, p, _p(ure), _p(uim), _p(rre), _p(rim))
+        return rre + 1j * rim
+
+    def jacobian_blocks(self, p: int, u: np.ndarray, offdiag: bool = False):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        n = self.V * self.N(p)
+        D = np.zeros((self.ne, n, n))
+        Off = np.zeros((self.ne, 2 * self.dim, n, n)) if offdiag else None
+        lib().orc_jacobian_blocks(self._h, p, _p(u), _p(D), _p(Off))
+        return (D, Off) if offdiag else D
+
+    def ghost(self, tag, U, nh, x):
+        Ug = np.zeros(self.V)
+        lib().orc_ghost(self._h, tag, _p(np.ascontiguousarray(U, dtype=np.float64)),
+                        _p(np.ascontiguousarray(nh, dtype=np.float64)),
+                        _p(np.ascontiguousarray(x, dtype=np.float64)), _p(Ug))
+        return Ug
+
+    def timestep(self, p: int, cfl: float, u: np.ndarray) -> np.ndarray:
+        dt = np.zeros(self.ne)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        lib().orc_timestep(self._h, p, u.shape[2], cfl, _p(u), _p(dt))
+        return dt
+
+    def rnorm(self, p: int, r: np.ndarray) -> float:
+        return lib().orc_rnorm(self._h, p, _p(np.ascontiguousarray(r)))
+
+    def prk(self, p, s, cfl, u, f=None):
+        u = np.array(u, dtype=np.float64, copy=True, order="C")
+        if lib().orc_prk(self._h, p, s, cfl, _p(u), _p(f)) != 0:
+            raise RuntimeError("PRK failed (singular block)")
+        return u
+
+    def exp1(self, m, cfl, u0, f0=None):
+        u0 = np.array(u0, dtype=np.float64, copy=True, order="C")
+        mu = C.c_int(0)
+        beta = C.c_double(0.0)
+        if lib().orc_exp1(self._h, self.pmax, m, cfl, _p(u0), _p(f0), C.byref(mu), C.byref(beta)) != 0:
+            raise RuntimeError("EXP1 failed")
+        return u0, mu.value, beta.value
+
+    def vcycle(self, u, n, s=4, m=30, cfl_max=100.0, rref=1.0, f=None):
+        u = np.array(u, dtype=np.float64, copy=True, order="C")
+        rn = C.c_double(0.0)
+        cfl = C.c_double(0.0)
+        st = lib().orc_vcycle(self._h, self.pmax, s, m, cfl_max, rref, n, _p(u), _p(f), C.byref(rn), C.byref(cfl))
+        if st != 0:
+            raise RuntimeError(f"V-cycle failed ({st})")
+        return u, rn.value, cfl.value
+
+    def solve(self, u, s=4, m=30, cfl_max=100.0, drop=1e-10, max_cycles=200, f=None, relative_ramp=True):
+        u = np.array(u, dtype=np.float64, copy=True, order="C")
+        hist = np.zeros(max_cycles + 1)
+        nc = C.c_int(0)
+        st = lib().orc_solve(self._h, self.pmax, s, m, cfl_max, int(relative_ramp), drop, max_cycles, _p(u), _p(f),
+                             _p(hist), C.byref(nc))
+        return u, hist[: nc.value + 1], st
+
+    def mms_project(self, p):
+        u = self.zeros(p)
+        lib().orc_mms_project(self._h, p, _p(u))
+        return u
+
+    def mms_forcing(self, p):
+        f = self.zeros(p)
+        lib().orc_mms_forcing(self._h, p, _p(f))
+        return f
+
+    def mms_error(self, p, u):
+        return lib().orc_mms_error(self._h, p, _p(np.ascontiguousarray(u)))

@@ -1,0 +1,1431 @@
+// FP64 CPU oracle for the exponential p-multigrid (eMG) hot path.
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, deliberately
+// unoptimised statement of what the method computes.  It is loaded by the
+// test-suite, by the smoke check and by the CPU-baseline leg of the benchmark;
+// the product library never links, loads or calls it, and it shares no code,
+// header, table or helper with the HIP path.
+//
+// Every function states the passage of the paper (arXiv:1807.01151) it
+// follows.  Where the paper is silent or garbled, the reading taken is named
+// in the comment (the same reading binds the HIP path).
+//
+// Conventions:
+//   * d = 2 or 3, V = d + 2 conserved variables (rho, rho v, rho E).
+//   * Level-p vectors are [E][V][N_p], N_p = (p+1)^d, modes in hierarchical
+//     order (sort key (max degree, a0, a1, a2)), so level p-1 is a leading
+//     slice of level p.
+//   * Basis: tensor Legendre phi_k on the reference cube, orthonormalised per
+//     element in the physical L2 inner product: psi = T phi with T = L^{-1},
+//     G = L L^T the element Gram matrix (Section 3.2, eq. (basis): psi_i is
+//     s_i [chi_i + sum_{j<i} c_ij chi_j], i.e. a lower-triangular transform).
+//   * Numerical flux: Rusanov (local Lax-Friedrichs); boundary fluxes use the
+//     same flux with a ghost state (Section 3.3, boundary flux equation).
+//
+// Build: g++ -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC.
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------------------
+// Scalar helpers usable with double and with complex<double> (complex-step
+// differentiation).  Branches decide on the real part; the derivative of |x|
+// is taken as +1 at x = 0 and max(a, b) picks a when re(a) >= re(b).
+// ---------------------------------------------------------------------------
+inline double re(double x) { return x; }
+inline double re(const cd& z) { return z.real(); }
+template <class S> S cs_abs(const S& x) { return re(x) < 0.0 ? -x : x; }
+template <class S> S cs_max(const S& a, const S& b) { return re(a) >= re(b) ? a : b; }
+inline double cs_sqrt(double x) { return std::sqrt(x); }
+inline cd cs_sqrt(const cd& z) { return std::sqrt(z); }
+inline double cs_pow(double x, double y) { return std::pow(x, y); }
+inline cd cs_pow(const cd& z, double y) { return std::exp(y * std::log(z)); }
+
+constexpr int MAXD = 3;
+constexpr int MAXV = 5;
+
+// ---------------------------------------------------------------------------
+// Gauss-Legendre rule on [-1, 1] (the paper's "Gaussian quadrature points",
+// Section 3.2).  Newton iteration on P_Q from the Chebyshev-like guess; nodes
+// ascending, symmetric pairs made exactly symmetric.
+// ---------------------------------------------------------------------------
+void gauss_legendre(int Q, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(Q, 0.0);
+  w.assign(Q, 0.0);
+  for (int i = 0; i < Q; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (Q + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= Q; ++k) {
+        double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      if (Q == 1) { p0 = 1.0; p1 = z; }
+      dp = Q * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-17) break;
+    }
+    {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= Q; ++k) {
+        double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      if (Q == 1) { p0 = 1.0; p1 = z; }
+      dp = Q * (z * p1 - p0) / (z * z - 1.0);
+    }
+    x[Q - 1 - i] = z;
+    w[Q - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+  for (int i = 0; i < Q / 2; ++i) {
+    x[i] = -x[Q - 1 - i];
+    w[i] = w[Q - 1 - i];
+  }
+  if (Q % 2 == 1) x[Q / 2] = 0.0;
+}
+
+// Orthonormal Legendre L_a = sqrt((2a+1)/2) P_a and its derivative, a <= pm.
+void legendre_on(int pm, double x, double* L, double* dL) {
+  double P[16], dP[16];
+  P[0] = 1.0; dP[0] = 0.0;
+  if (pm >= 1) { P[1] = x; dP[1] = 1.0; }
+  for (int n = 1; n < pm; ++n) {
+    P[n + 1] = ((2.0 * n + 1.0) * x * P[n] - n * P[n - 1]) / (n + 1.0);
+    dP[n + 1] = dP[n - 1] + (2.0 * n + 1.0) * P[n];
+  }
+  for (int a = 0; a <= pm; ++a) {
+    double s = std::sqrt((2.0 * a + 1.0) / 2.0);
+    L[a] = s * P[a];
+    dL[a] = s * dP[a];
+  }
+}
+
+int nmodes(int d, int p) { int n = 1; for (int r = 0; r < d; ++r) n *= (p + 1); return n; }
+
+// Multi-indices of the tensor space Q_p, hierarchical order.
+std::vector<std::array<int, 3>> mode_list(int d, int p) {
+  std::vector<std::array<int, 3>> m;
+  int n = nmodes(d, p);
+  for (int k = 0; k < n; ++k) {
+    std::array<int, 3> a{0, 0, 0};
+    int t = k;
+    for (int r = 0; r < d; ++r) { a[r] = t % (p + 1); t /= (p + 1); }
+    m.push_back(a);
+  }
+  std::sort(m.begin(), m.end(), [](const std::array<int, 3>& x, const std::array<int, 3>& y) {
+    int mx = std::max(x[0], std::max(x[1], x[2]));
+    int my = std::max(y[0], std::max(y[1], y[2]));
+    if (mx != my) return mx < my;
+    return x < y;
+  });
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// Mesh, faces and per-element basis
+// ---------------------------------------------------------------------------
+struct Face {
+  int eL, fL, eR, fR, tag;
+  int M[2][2];  // face-local coordinates of R = M * face-local coordinates of L
+};
+
+struct Oracle {
+  int d = 2, V = 4, nv = 0, ne = 0, pmax = 1;
+  double gam = 1.4, mach = 0.3, alpha = 0.0, beta = 0.0;
+  std::vector<double> xyz;
+  std::vector<int> ev;
+  std::vector<signed char> tag;
+  std::vector<Face> faces;
+  std::vector<int> efc, eside;  // [E][2d] face id and side (0 = L, 1 = R)
+  std::vector<double> T;        // [E][N][N], N = N_pmax, lower triangular
+  std::vector<double> vol, surf, hE;
+  double omega = 0.0;
+  std::vector<std::array<int, 3>> modes;  // at pmax
+  int Nmax = 0;
+  double Uinf[MAXV];
+  std::string err;
+};
+
+int nface(const Oracle& O) { return 2 * O.d; }
+
+// Tangential axes of face f = 2 r + s, ascending.
+void face_axes(int d, int f, int* ax) {
+  int r = f / 2, k = 0;
+  for (int a = 0; a < d; ++a) if (a != r) ax[k++] = a;
+}
+
+void embed(int d, int f, const double* s, double* xi) {
+  int ax[2];
+  face_axes(d, f, ax);
+  xi[f / 2] = (f % 2) ? 1.0 : -1.0;
+  for (int k = 0; k < d - 1; ++k) xi[ax[k]] = s[k];
+}
+
+// Multilinear map x(xi), tangents t[r] = dx/dxi_r, det and the vectors
+// c[r] with c[r] . t[r'] = det delta_{r r'} (det * grad_x = sum_r c[r] d/dxi_r;
+// the scaled outward normal of face (r, s) is (2s - 1) c[r]).
+void geom(const Oracle& O, int e, const double* xi, double* x, double t[MAXD][MAXD],
+          double& det, double c[MAXD][MAXD]) {
+  const int d = O.d, nc = 1 << d;
+  for (int a = 0; a < d; ++a) { x[a] = 0.0; for (int r = 0; r < d; ++r) t[r][a] = 0.0; }
+  for (int k = 0; k < nc; ++k) {
+    const double* X = &O.xyz[(size_t)O.ev[(size_t)e * nc + k] * d];
+    double N = 1.0, dN[MAXD];
+    for (int r = 0; r < d; ++r) {
+      double sg = ((k >> r) & 1) ? 1.0 : -1.0;
+      N *= 0.5 * (1.0 + sg * xi[r]);
+    }
+    for (int r = 0; r < d; ++r) {
+      double v = 1.0;
+      for (int q = 0; q < d; ++q) {
+        double sg = ((k >> q) & 1) ? 1.0 : -1.0;
+        v *= (q == r) ? 0.5 * sg : 0.5 * (1.0 + sg * xi[q]);
+      }
+      dN[r] = v;
+    }
+    for (int a = 0; a < d; ++a) {
+      x[a] += N * X[a];
+      for (int r = 0; r < d; ++r) t[r][a] += dN[r] * X[a];
+    }
+  }
+  if (d == 2) {
+    det = t[0][0] * t[1][1] - t[0][1] * t[1][0];
+    c[0][0] = t[1][1]; c[0][1] = -t[1][0];
+    c[1][0] = -t[0][1]; c[1][1] = t[0][0];
+  } else {
+    auto cross = [](const double* a, const double* b, double* o) {
+      o[0] = a[1] * b[2] - a[2] * b[1];
+      o[1] = a[2] * b[0] - a[0] * b[2];
+      o[2] = a[0] * b[1] - a[1] * b[0];
+    };
+    cross(t[1], t[2], c[0]);
+    cross(t[2], t[0], c[1]);
+    cross(t[0], t[1], c[2]);
+    det = t[0][0] * c[0][0] + t[0][1] * c[0][1] + t[0][2] * c[0][2];
+  }
+}
+
+// Reference basis phi_k and its reference gradient at xi (level-p modes are
+// the first N_p of O.modes).
+void ref_basis(const Oracle& O, int N, const double* xi, double* phi, double* dphi /*[N][d]*/) {
+  const int d = O.d;
+  double L[MAXD][16], dL[MAXD][16];
+  for (int r = 0; r < d; ++r) legendre_on(O.pmax, xi[r], L[r], dL[r]);
+  for (int k = 0; k < N; ++k) {
+    const auto& a = O.modes[k];
+    double v = 1.0;
+    for (int r = 0; r < d; ++r) v *= L[r][a[r]];
+    phi[k] = v;
+    if (dphi) {
+      for (int r = 0; r < d; ++r) {
+        double g = 1.0;
+        for (int q = 0; q < d; ++q) g *= (q == r) ? dL[q][a[q]] : L[q][a[q]];
+        dphi[k * d + r] = g;
+      }
+    }
+  }
+}
+
+// psi_i(x(xi)) = sum_j T_ij phi_j(xi) and det * grad_x psi_i.
+void elem_basis(const Oracle& O, int e, int N, const double* xi, double* psi, double* gpsi /*[N][d] or null*/,
+                double* xout = nullptr, double* detout = nullptr, double cout_[MAXD][MAXD] = nullptr) {
+  const int d = O.d;
+  double phi[128], dphi[128 * MAXD];
+  ref_basis(O, N, xi, phi, gpsi ? dphi : nullptr);
+  const double* T = &O.T[(size_t)e * O.Nmax * O.Nmax];
+  for (int i = 0; i < N; ++i) {
+    double s = 0.0;
+    for (int j = 0; j <= i; ++j) s += T[i * O.Nmax + j] * phi[j];
+    psi[i] = s;
+  }
+  if (gpsi || xout || detout || cout_) {
+    double x[MAXD], t[MAXD][MAXD], det, c[MAXD][MAXD];
+    geom(O, e, xi, x, t, det, c);
+    if (xout) for (int a = 0; a < d; ++a) xout[a] = x[a];
+    if (detout) *detout = det;
+    if (cout_) for (int r = 0; r < d; ++r) for (int a = 0; a < d; ++a) cout_[r][a] = c[r][a];
+    if (gpsi) {
+      for (int i = 0; i < N; ++i) {
+        double gr[MAXD];
+        for (int r = 0; r < d; ++r) {
+          double s = 0.0;
+          for (int j = 0; j <= i; ++j) s += T[i * O.Nmax + j] * dphi[j * d + r];
+          gr[r] = s;
+        }
+        for (int a = 0; a < d; ++a) {
+          double s = 0.0;
+          for (int r = 0; r < d; ++r) s += c[r][a] * gr[r];
+          gpsi[i * d + a] = s;
+        }
+      }
+    }
+  }
+}
+
+// Cholesky G = L L^T and T = L^{-1} (dense, row-major, n x n).
+bool chol_inverse(int n, const double* G, double* T) {
+  std::vector<double> L((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double s = G[j * n + j];
+    for (int k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
+    if (!(s > 0.0)) return false;
+    L[j * n + j] = std::sqrt(s);
+    for (int i = j + 1; i < n; ++i) {
+      double t = G[i * n + j];
+      for (int k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = t / L[j * n + j];
+    }
+  }
+  for (int i = 0; i < n * n; ++i) T[i] = 0.0;
+  for (int c = 0; c < n; ++c) {  // solve L x = e_c by forward substitution
+    for (int i = 0; i < n; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) s -= L[i * n + k] * T[k * n + c];
+      T[i * n + c] = s / L[i * n + i];
+    }
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Physics (Section 3, eq. (euler) with omega = 0; perfect gas, gamma = 7/5)
+// ---------------------------------------------------------------------------
+template <class S> S pressure(int d, double g, const S* U) {
+  S ke = 0.0;
+  for (int a = 0; a < d; ++a) ke += U[1 + a] * U[1 + a];
+  return (g - 1.0) * (U[d + 1] - 0.5 * ke / U[0]);
+}
+
+// F(U) . n for any vector n.
+template <class S> void flux_n(int d, double g, const S* U, const double* n, S* Fn) {
+  S rho = U[0];
+  S vn = 0.0;
+  for (int a = 0; a < d; ++a) vn += (U[1 + a] / rho) * n[a];
+  S p = pressure(d, g, U);
+  Fn[0] = rho * vn;
+  for (int a = 0; a < d; ++a) Fn[1 + a] = U[1 + a] * vn + p * n[a];
+  Fn[d + 1] = (U[d + 1] + p) * vn;
+}
+
+// Rusanov flux F~(UL, UR; n^) = 1/2 (F(UL) + F(UR)) . n^ - 1/2 lambda (UR - UL),
+// lambda = max(|vL . n^| + cL, |vR . n^| + cR).
+template <class S> void rusanov(int d, double g, const S* UL, const S* UR, const double* nh, S* F) {
+  S FL[MAXV], FR[MAXV];
+  flux_n(d, g, UL, nh, FL);
+  flux_n(d, g, UR, nh, FR);
+  S vnL = 0.0, vnR = 0.0;
+  for (int a = 0; a < d; ++a) { vnL += (UL[1 + a] / UL[0]) * nh[a]; vnR += (UR[1 + a] / UR[0]) * nh[a]; }
+  S cL = cs_sqrt(g * pressure(d, g, UL) / UL[0]);
+  S cR = cs_sqrt(g * pressure(d, g, UR) / UR[0]);
+  S lam = cs_max(S(cs_abs(vnL) + cL), S(cs_abs(vnR) + cR));
+  for (int v = 0; v < d + 2; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * (UR[v] - UL[v]);
+}
+
+// Manufactured smooth state (tests of the convergence rate only).
+template <class S> void mms_state(int d, double g, const S* x, S* U) {
+  const double pi = M_PI;
+  S sx = std::sin(pi * x[0]), cx = std::cos(pi * x[0]);
+  S sy = std::sin(pi * x[1]), cy = std::cos(pi * x[1]);
+  S cz = (d == 3) ? S(std::cos(pi * x[2])) : S(1.0);
+  S rho = 1.0 + 0.1 * sx * cy * cz;
+  S vel[3];
+  vel[0] = 0.3 + 0.05 * cx * sy;
+  vel[1] = 0.1 + 0.05 * sx * sy * cz;
+  vel[2] = 0.05 + 0.03 * cx * cy;
+  S p = 1.0 / g + 0.05 * cx * cy * cz;
+  S ke = 0.0;
+  for (int a = 0; a < d; ++a) ke += vel[a] * vel[a];
+  U[0] = rho;
+  for (int a = 0; a < d; ++a) U[1 + a] = rho * vel[a];
+  U[d + 1] = p / (g - 1.0) + 0.5 * rho * ke;
+}
+
+// Ghost state for boundary faces (Section 3.3: U_ghost is a function of U_L).
+//  tag 1 slip wall: mirror state, rho v_g = rho v - 2 (rho v . n^) n^.
+//  tag 2 far-field: Riemann invariants R+ = v_n + 2c/(g-1) from inside,
+//        R- = v_n,inf - 2 c_inf/(g-1) from the free stream; outflow iff the
+//        boundary normal velocity is > 0, taking tangential velocity and
+//        entropy p/rho^g from inside, else from the free stream.
+//  tag 3 exact state of the manufactured solution (tests only).
+template <class S> void ghost(const Oracle& O, int tg, const S* U, const double* nh, const double* x, S* Ug) {
+  const int d = O.d;
+  const double g = O.gam;
+  if (tg == 1) {
+    S mn = 0.0;
+    for (int a = 0; a < d; ++a) mn += U[1 + a] * nh[a];
+    Ug[0] = U[0];
+    for (int a = 0; a < d; ++a) Ug[1 + a] = U[1 + a] - 2.0 * mn * nh[a];
+    Ug[d + 1] = U[d + 1];
+  } else if (tg == 2) {
+    const double* Ui = O.Uinf;
+    S rho = U[0];
+    S vi[MAXD];
+    S vni = 0.0;
+    for (int a = 0; a < d; ++a) { vi[a] = U[1 + a] / rho; vni += vi[a] * nh[a]; }
+    S pi = pressure(d, g, U);
+    S ci = cs_sqrt(g * pi / rho);
+    double rinf = Ui[0], vinf[MAXD], vninf = 0.0;
+    for (int a = 0; a < d; ++a) { vinf[a] = Ui[1 + a] / rinf; vninf += vinf[a] * nh[a]; }
+    double pinf = pressure(d, g, Ui);
+    double cinf = std::sqrt(g * pinf / rinf);
+    S Rp = vni + 2.0 * ci / (g - 1.0);
+    double Rm = vninf - 2.0 * cinf / (g - 1.0);
+    S vnb = 0.5 * (Rp + Rm);
+    S cb = 0.25 * (g - 1.0) * (Rp - Rm);
+    S vt[MAXD], ent;
+    if (re(vnb) > 0.0) {
+      for (int a = 0; a < d; ++a) vt[a] = vi[a] - vni * nh[a];
+      ent = pi / cs_pow(rho, g);
+    } else {
+      for (int a = 0; a < d; ++a) vt[a] = S(vinf[a] - vninf * nh[a]);
+      ent = S(pinf / std::pow(rinf, g));
+    }
+    S rb = cs_pow(S(cb * cb / (g * ent)), 1.0 / (g - 1.0));
+    S pb = rb * cb * cb / g;
+    S ke = 0.0;
+    Ug[0] = rb;
+    for (int a = 0; a < d; ++a) {
+      S vb = vt[a] + vnb * nh[a];
+      Ug[1 + a] = rb * vb;
+      ke += vb * vb;
+    }
+    Ug[d + 1] = pb / (g - 1.0) + 0.5 * rb * ke;
+  } else {
+    (void)x;
+    for (int v = 0; v < d + 2; ++v) Ug[v] = U[v];
+  }
+}
+
+// The exact-state ghost cannot go through the template above for complex S
+// (it does not depend on U), so it is handled here.
+template <class S> void ghost_any(const Oracle& O, int tg, const S* U, const double* nh, const double* x, S* Ug) {
+  if (tg == 3) {
+    double Um[MAXV];
+    mms_state<double>(O.d, O.gam, x, Um);
+    for (int v = 0; v < O.V; ++v) Ug[v] = Um[v];
+  } else {
+    ghost(O, tg, U, nh, x, Ug);
+  }
+}
+
+// Euler flux Jacobian contracted with a vector g: sum_a g_a dF_a/dU
+// (Appendix A, eq. (dfdu), omega = 0, with a_1 read as gamma E - a_0 = H, the
+// total enthalpy, which is what differentiating the energy flux gives).
+void flux_jac(int d, double gm, const double* U, const double* gv, double* K /*[V][V]*/) {
+  const int V = d + 2;
+  double rho = U[0], vel[MAXD], q2 = 0.0;
+  for (int a = 0; a < d; ++a) { vel[a] = U[1 + a] / rho; q2 += vel[a] * vel[a]; }
+  double E = U[d + 1] / rho;
+  double a0 = 0.5 * (gm - 1.0) * q2;
+  double a1 = gm * E - a0;
+  double a2 = gm - 1.0, a3 = gm - 2.0;
+  double B1 = 0.0;
+  for (int a = 0; a < d; ++a) B1 += vel[a] * gv[a];
+  for (int i = 0; i < V * V; ++i) K[i] = 0.0;
+  for (int a = 0; a < d; ++a) K[0 * V + 1 + a] = gv[a];
+  for (int r = 0; r < d; ++r) {
+    K[(1 + r) * V + 0] = a0 * gv[r] - B1 * vel[r];
+    for (int c = 0; c < d; ++c) {
+      if (c == r) K[(1 + r) * V + 1 + c] = B1 - a3 * vel[r] * gv[r];
+      else K[(1 + r) * V + 1 + c] = vel[r] * gv[c] - a2 * vel[c] * gv[r];
+    }
+    K[(1 + r) * V + d + 1] = a2 * gv[r];
+  }
+  K[(d + 1) * V + 0] = (a0 - a1) * B1;
+  for (int c = 0; c < d; ++c) K[(d + 1) * V + 1 + c] = a1 * gv[c] - a2 * B1 * vel[c];
+  K[(d + 1) * V + d + 1] = gm * B1;
+}
+
+// Complex-step derivative of a map R^V -> R^V at U: Jac[v][w] = dF_v/dU_w.
+template <class Fn> void cs_jac(int V, const double* U, Fn f, double* Jac) {
+  const double h = 1e-30;
+  for (int w = 0; w < V; ++w) {
+    cd Uc[MAXV], Fc[MAXV];
+    for (int v = 0; v < V; ++v) Uc[v] = cd(U[v], 0.0);
+    Uc[w] = cd(U[w], h);
+    f(Uc, Fc);
+    for (int v = 0; v < V; ++v) Jac[v * V + w] = Fc[v].imag() / h;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up: faces (matched through shared vertices), geometry, Gram / T.
+// ---------------------------------------------------------------------------
+bool setup(Oracle& O) {
+  const int d = O.d, nfc = 2 * d, nc = 1 << d, ncf = 1 << (d - 1);
+  O.V = d + 2;
+  O.modes = mode_list(d, O.pmax);
+  O.Nmax = nmodes(d, O.pmax);
+  O.efc.assign((size_t)O.ne * nfc, -1);
+  O.eside.assign((size_t)O.ne * nfc, 0);
+  // face vertices in face-local lexicographic order
+  auto fverts = [&](int e, int f, int* vv) {
+    int ax[2];
+    face_axes(d, f, ax);
+    for (int c = 0; c < ncf; ++c) {
+      int k = (f % 2) << (f / 2);
+      for (int q = 0; q < d - 1; ++q) if ((c >> q) & 1) k |= 1 << ax[q];
+      vv[c] = O.ev[(size_t)e * nc + k];
+    }
+  };
+  std::map<std::vector<int>, std::pair<int, int>> open;
+  for (int e = 0; e < O.ne; ++e) {
+    for (int f = 0; f < nfc; ++f) {
+      int tg = O.tag[(size_t)e * nfc + f];
+      if (tg != 0) {
+        Face F{e, f, -1, -1, tg, {{1, 0}, {0, 1}}};
+        O.efc[(size_t)e * nfc + f] = (int)O.faces.size();
+        O.eside[(size_t)e * nfc + f] = 0;
+        O.faces.push_back(F);
+        continue;
+      }
+      int vv[4];
+      fverts(e, f, vv);
+      std::vector<int> key(vv, vv + ncf);
+      std::sort(key.begin(), key.end());
+      auto it = open.find(key);
+      if (it == open.end()) { open[key] = {e, f}; continue; }
+      int e0 = it->second.first, f0 = it->second.second;
+      open.erase(it);
+      // L = earlier element, R = this one; build the signed permutation M
+      int vL[4], vR[4];
+      fverts(e0, f0, vL);
+      fverts(e, f, vR);
+      auto corner_of = [&](int vid, const int* vlist, double* s) {
+        for (int c = 0; c < ncf; ++c) if (vlist[c] == vid) {
+          for (int q = 0; q < d - 1; ++q) s[q] = ((c >> q) & 1) ? 1.0 : -1.0;
+          return true;
+        }
+        return false;
+      };
+      Face F{e0, f0, e, f, 0, {{0, 0}, {0, 0}}};
+      double s0[2] = {0, 0}, sq[2] = {0, 0};
+      if (!corner_of(vL[0], vR, s0)) { O.err = "face matching failed"; return false; }
+      for (int q = 0; q < d - 1; ++q) {
+        if (!corner_of(vL[1 << q], vR, sq)) { O.err = "face matching failed"; return false; }
+        for (int k = 0; k < d - 1; ++k) F.M[k][q] = (int)std::lround(0.5 * (sq[k] - s0[k]));
+      }
+      // check every corner maps through M (offset must vanish)
+      for (int c = 0; c < ncf; ++c) {
+        double sl[2], sr[2], sm[2];
+        for (int q = 0; q < d - 1; ++q) sl[q] = ((c >> q) & 1) ? 1.0 : -1.0;
+        if (!corner_of(vL[c], vR, sr)) { O.err = "face matching failed"; return false; }
+        for (int k = 0; k < d - 1; ++k) {
+          sm[k] = 0.0;
+          for (int q = 0; q < d - 1; ++q) sm[k] += F.M[k][q] * sl[q];
+          if (sm[k] != sr[k]) { O.err = "non-conforming face"; return false; }
+        }
+      }
+      int id = (int)O.faces.size();
+      O.faces.push_back(F);
+      O.efc[(size_t)e0 * nfc + f0] = id; O.eside[(size_t)e0 * nfc + f0] = 0;
+      O.efc[(size_t)e * nfc + f] = id; O.eside[(size_t)e * nfc + f] = 1;
+    }
+  }
+  if (!open.empty()) { O.err = "unmatched interior face"; return false; }
+
+  // Geometry and per-element orthonormalisation with the (pmax+2)-point rule,
+  // which integrates phi_i phi_j det exactly on multilinear elements.
+  const int N = O.Nmax, Q = O.pmax + 2;
+  std::vector<double> xg, wg;
+  gauss_legendre(Q, xg, wg);
+  O.T.assign((size_t)O.ne * N * N, 0.0);
+  O.vol.assign(O.ne, 0.0);
+  O.surf.assign(O.ne, 0.0);
+  O.hE.assign(O.ne, 0.0);
+  int nq = 1;
+  for (int r = 0; r < d; ++r) nq *= Q;
+  int nqf = nq / Q;
+  bool ok = true;
+#pragma omp parallel for schedule(static) reduction(&& : ok)
+  for (int e = 0; e < O.ne; ++e) {
+    std::vector<double> G((size_t)N * N, 0.0), phi(N);
+    double vol = 0.0;
+    for (int q = 0; q < nq; ++q) {
+      double xi[MAXD], w = 1.0;
+      int t = q;
+      for (int r = 0; r < d; ++r) { xi[r] = xg[t % Q]; w *= wg[t % Q]; t /= Q; }
+      double x[MAXD], tt[MAXD][MAXD], det, c[MAXD][MAXD];
+      geom(O, e, xi, x, tt, det, c);
+      if (!(det > 0.0)) ok = false;
+      ref_basis(O, N, xi, phi.data(), nullptr);
+      vol += w * det;
+      for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) G[i * N + j] += w * det * phi[i] * phi[j];
+    }
+    double surf = 0.0;
+    for (int f = 0; f < nfc; ++f) {
+      for (int k = 0; k < nqf; ++k) {
+        double s[2], w = 1.0, xi[MAXD];
+        int t = k;
+        for (int q = 0; q < d - 1; ++q) { s[q] = xg[t % Q]; w *= wg[t % Q]; t /= Q; }
+        embed(d, f, s, xi);
+        double x[MAXD], tt[MAXD][MAXD], det, c[MAXD][MAXD];
+        geom(O, e, xi, x, tt, det, c);
+        double a2 = 0.0;
+        for (int a = 0; a < d; ++a) a2 += c[f / 2][a] * c[f / 2][a];
+        surf += w * std::sqrt(a2);
+      }
+    }
+    O.vol[e] = vol;
+    O.surf[e] = surf;
+    O.hE[e] = 2.0 * d * vol / surf;
+    if (!chol_inverse(N, G.data(), &O.T[(size_t)e * N * N])) ok = false;
+  }
+  if (!ok) { O.err = "non-positive Jacobian or Gram matrix"; return false; }
+  O.omega = 0.0;
+  for (int e = 0; e < O.ne; ++e) O.omega += O.vol[e];
+  // free stream (rho = 1, p = 1/gamma so c = 1)
+  double vinf[3] = {O.mach * std::cos(O.alpha) * std::cos(O.beta), O.mach * std::sin(O.alpha) * std::cos(O.beta),
+                    O.mach * std::sin(O.beta)};
+  O.Uinf[0] = 1.0;
+  double ke = 0.0;
+  for (int a = 0; a < d; ++a) { O.Uinf[1 + a] = vinf[a]; ke += vinf[a] * vinf[a]; }
+  O.Uinf[d + 1] = (1.0 / O.gam) / (O.gam - 1.0) + 0.5 * ke;
+  return true;
+}
+
+// Reference coordinates of face point k (tensor order, first axis fastest)
+// for the L side and, through M, for the R side.
+void face_point(const Oracle& O, const Face& F, int Q, const std::vector<double>& xg, const std::vector<double>& wg,
+                int k, double* xiL, double* xiR, double& w) {
+  const int d = O.d;
+  double s[2] = {0, 0};
+  w = 1.0;
+  int t = k;
+  for (int q = 0; q < d - 1; ++q) { s[q] = xg[t % Q]; w *= wg[t % Q]; t /= Q; }
+  embed(d, F.fL, s, xiL);
+  if (F.eR >= 0) {
+    double sr[2] = {0, 0};
+    for (int a = 0; a < d - 1; ++a) {
+      sr[a] = 0.0;
+      for (int b = 0; b < d - 1; ++b) sr[a] += F.M[a][b] * s[b];
+    }
+    embed(d, F.fR, sr, xiR);
+  }
+}
+
+template <class S> void eval_state(const Oracle& O, int e, int N, const S* u, const double* psi, S* U) {
+  for (int v = 0; v < O.V; ++v) {
+    S s = 0.0;
+    for (int i = 0; i < N; ++i) s += u[((size_t)e * O.V + v) * N + i] * psi[i];
+    U[v] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// DG residual R_p(u) (Section 3.1, eq. (euler3), S = 0):
+//   R_{E,i} = - sum_faces int psi_i F~ . n^ dsigma + int_E F . grad psi_i dx,
+// with (p+2)^d Gauss points in the volume and (p+2)^(d-1) per face.  Each
+// interior face flux is computed once with the L element's normal and added to
+// both sides.
+// ---------------------------------------------------------------------------
+template <class S> void residual_t(const Oracle& O, int p, const S* u, S* r) {
+  const int d = O.d, V = O.V, N = nmodes(d, p), Q = p + 2, nfc = 2 * d;
+  std::vector<double> xg, wg;
+  gauss_legendre(Q, xg, wg);
+  int nq = 1;
+  for (int k = 0; k < d; ++k) nq *= Q;
+  const int nqf = nq / Q;
+  // volume term
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < O.ne; ++e) {
+    S* re_ = r + (size_t)e * V * N;
+    for (int i = 0; i < V * N; ++i) re_[i] = 0.0;
+    double psi[128], gpsi[128 * MAXD];
+    for (int q = 0; q < nq; ++q) {
+      double xi[MAXD], w = 1.0;
+      int t = q;
+      for (int k = 0; k < d; ++k) { xi[k] = xg[t % Q]; w *= wg[t % Q]; t /= Q; }
+      elem_basis(O, e, N, xi, psi, gpsi);
+      S U[MAXV];
+      eval_state(O, e, N, u, psi, U);
+      S F[MAXD][MAXV];
+      for (int a = 0; a < d; ++a) {
+        double ea[MAXD] = {0, 0, 0};
+        ea[a] = 1.0;
+        flux_n(d, O.gam, U, ea, F[a]);
+      }
+      for (int v = 0; v < V; ++v)
+        for (int i = 0; i < N; ++i) {
+          S s = 0.0;
+          for (int a = 0; a < d; ++a) s += F[a][v] * gpsi[i * d + a];
+          re_[v * N + i] += w * s;
+        }
+    }
+  }
+  // face fluxes, weighted by w |n dsigma|
+  const int nf = (int)O.faces.size();
+  std::vector<S> flux((size_t)nf * nqf * V);
+#pragma omp parallel for schedule(static)
+  for (int fc = 0; fc < nf; ++fc) {
+    const Face& F = O.faces[fc];
+    double psiL[128], psiR[128];
+    for (int k = 0; k < nqf; ++k) {
+      double xiL[MAXD], xiR[MAXD], w;
+      face_point(O, F, Q, xg, wg, k, xiL, xiR, w);
+      double x[MAXD], det, c[MAXD][MAXD];
+      elem_basis(O, F.eL, N, xiL, psiL, nullptr, x, &det, c);
+      double sg = (F.fL % 2) ? 1.0 : -1.0, nh[MAXD], area2 = 0.0;
+      for (int a = 0; a < d; ++a) { nh[a] = sg * c[F.fL / 2][a]; area2 += nh[a] * nh[a]; }
+      double area = std::sqrt(area2);
+      for (int a = 0; a < d; ++a) nh[a] /= area;
+      S UL[MAXV], UR[MAXV], Fl[MAXV];
+      eval_state(O, F.eL, N, u, psiL, UL);
+      if (F.eR >= 0) {
+        elem_basis(O, F.eR, N, xiR, psiR, nullptr);
+        eval_state(O, F.eR, N, u, psiR, UR);
+      } else {
+        ghost_any(O, F.tag, UL, nh, x, UR);
+      }
+      rusanov(d, O.gam, UL, UR, nh, Fl);
+      for (int v = 0; v < V; ++v) flux[((size_t)fc * nqf + k) * V + v] = (w * area) * Fl[v];
+    }
+  }
+  // lift to the elements
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < O.ne; ++e) {
+    S* re_ = r + (size_t)e * V * N;
+    double psi[128];
+    for (int lf = 0; lf < nfc; ++lf) {
+      int fc = O.efc[(size_t)e * nfc + lf], side = O.eside[(size_t)e * nfc + lf];
+      const Face& F = O.faces[fc];
+      for (int k = 0; k < nqf; ++k) {
+        double xiL[MAXD], xiR[MAXD], w;
+        face_point(O, F, Q, xg, wg, k, xiL, xiR, w);
+        elem_basis(O, e, N, side == 0 ? xiL : xiR, psi, nullptr);
+        double sg = side == 0 ? -1.0 : 1.0;
+        for (int v = 0; v < V; ++v)
+          for (int i = 0; i < N; ++i) re_[v * N + i] += sg * psi[i] * flux[((size_t)fc * nqf + k) * V + v];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exact Jacobian blocks (Section 3.3, eqs. (jac1) and (jac2)).
+//   D_E = dR_E/du_E:  volume  int psi_j grad psi_i . dF/dU dx   (Appendix A)
+//                     faces  -int psi_i psi_j dF~/dU_own dsigma (with the
+//                     boundary chain rule dF~/dU_L + dF~/dU_g dU_g/dU_L)
+//   O_{E,f} = dR_E/du_nb(f):  -int psi_i^E psi_j^nb dF~/dU_nb dsigma.
+// The Riemann-flux and ghost Jacobians are obtained by complex-step
+// differentiation, which is exact to rounding (the paper uses AD).
+// Blocks are [(v,i)][(w,j)], n = V N_p.
+// ---------------------------------------------------------------------------
+void jacobian_blocks(const Oracle& O, int p, const double* u, double* D, double* Off /*nullable [E][2d][n][n]*/) {
+  const int d = O.d, V = O.V, N = nmodes(d, p), Q = p + 2, nfc = 2 * d, n = V * N;
+  std::vector<double> xg, wg;
+  gauss_legendre(Q, xg, wg);
+  int nq = 1;
+  for (int k = 0; k < d; ++k) nq *= Q;
+  const int nqf = nq / Q;
+#pragma omp parallel for schedule(dynamic)
+  for (int e = 0; e < O.ne; ++e) {
+    double* De = D + (size_t)e * n * n;
+    for (int i = 0; i < n * n; ++i) De[i] = 0.0;
+    if (Off) for (size_t i = 0; i < (size_t)nfc * n * n; ++i) Off[(size_t)e * nfc * n * n + i] = 0.0;
+    double psi[128], gpsi[128 * MAXD];
+    for (int q = 0; q < nq; ++q) {
+      double xi[MAXD], w = 1.0;
+      int t = q;
+      for (int k = 0; k < d; ++k) { xi[k] = xg[t % Q]; w *= wg[t % Q]; t /= Q; }
+      elem_basis(O, e, N, xi, psi, gpsi);
+      double U[MAXV];
+      eval_state(O, e, N, u, psi, U);
+      for (int i = 0; i < N; ++i) {
+        double K[MAXV * MAXV];
+        flux_jac(d, O.gam, U, &gpsi[i * d], K);
+        for (int v = 0; v < V; ++v)
+          for (int wv = 0; wv < V; ++wv)
+            for (int j = 0; j < N; ++j) De[(v * N + i) * n + wv * N + j] += w * K[v * V + wv] * psi[j];
+      }
+    }
+    double psiE[128], psiO[128];
+    for (int lf = 0; lf < nfc; ++lf) {
+      int fc = O.efc[(size_t)e * nfc + lf], side = O.eside[(size_t)e * nfc + lf];
+      const Face& F = O.faces[fc];
+      for (int k = 0; k < nqf; ++k) {
+        double xiL[MAXD], xiR[MAXD], w;
+        face_point(O, F, Q, xg, wg, k, xiL, xiR, w);
+        double x[MAXD], det, c[MAXD][MAXD], psiL[128];
+        elem_basis(O, F.eL, N, xiL, psiL, nullptr, x, &det, c);
+        double sg = (F.fL % 2) ? 1.0 : -1.0, nh[MAXD], area2 = 0.0;
+        for (int a = 0; a < d; ++a) { nh[a] = sg * c[F.fL / 2][a]; area2 += nh[a] * nh[a]; }
+        double area = std::sqrt(area2);
+        for (int a = 0; a < d; ++a) nh[a] /= area;
+        double UL[MAXV], UR[MAXV];
+        eval_state(O, F.eL, N, u, psiL, UL);
+        double Jown[MAXV * MAXV], Joth[MAXV * MAXV];
+        int other = -1;
+        if (F.eR >= 0) {
+          double psiR[128];
+          elem_basis(O, F.eR, N, xiR, psiR, nullptr);
+          eval_state(O, F.eR, N, u, psiR, UR);
+          // dF~/dUL and dF~/dUR
+          double JL[MAXV * MAXV], JR[MAXV * MAXV];
+          cs_jac(V, UL, [&](const cd* Uc, cd* Fc) {
+            cd URc[MAXV];
+            for (int v = 0; v < V; ++v) URc[v] = UR[v];
+            rusanov(d, O.gam, Uc, URc, nh, Fc);
+          }, JL);
+          cs_jac(V, UR, [&](const cd* Uc, cd* Fc) {
+            cd ULc[MAXV];
+            for (int v = 0; v < V; ++v) ULc[v] = UL[v];
+            rusanov(d, O.gam, ULc, Uc, nh, Fc);
+          }, JR);
+          if (side == 0) { std::memcpy(Jown, JL, sizeof JL); std::memcpy(Joth, JR, sizeof JR); other = F.eR; for (int i = 0; i < N; ++i) psiE[i] = psiL[i], psiO[i] = psiR[i]; }
+          else { std::memcpy(Jown, JR, sizeof JR); std::memcpy(Joth, JL, sizeof JL); other = F.eL; for (int i = 0; i < N; ++i) psiE[i] = psiR[i], psiO[i] = psiL[i]; }
+        } else {
+          double Ug[MAXV];
+          ghost_any(O, F.tag, UL, nh, x, Ug);
+          double JL[MAXV * MAXV], Jg[MAXV * MAXV], Gg[MAXV * MAXV];
+          cs_jac(V, UL, [&](const cd* Uc, cd* Fc) {
+            cd Ugc[MAXV];
+            for (int v = 0; v < V; ++v) Ugc[v] = Ug[v];
+            rusanov(d, O.gam, Uc, Ugc, nh, Fc);
+          }, JL);
+          cs_jac(V, Ug, [&](const cd* Uc, cd* Fc) {
+            cd ULc[MAXV];
+            for (int v = 0; v < V; ++v) ULc[v] = UL[v];
+            rusanov(d, O.gam, ULc, Uc, nh, Fc);
+          }, Jg);
+          cs_jac(V, UL, [&](const cd* Uc, cd* Fc) { ghost_any(O, F.tag, Uc, nh, x, Fc); }, Gg);
+          for (int v = 0; v < V; ++v)
+            for (int wv = 0; wv < V; ++wv) {
+              double s = JL[v * V + wv];
+              for (int k2 = 0; k2 < V; ++k2) s += Jg[v * V + k2] * Gg[k2 * V + wv];
+              Jown[v * V + wv] = s;
+            }
+          for (int i = 0; i < N; ++i) psiE[i] = psiL[i];
+        }
+        double sgn = side == 0 ? -1.0 : 1.0, wa = w * area;
+        for (int v = 0; v < V; ++v)
+          for (int wv = 0; wv < V; ++wv)
+            for (int i = 0; i < N; ++i)
+              for (int j = 0; j < N; ++j)
+                De[(v * N + i) * n + wv * N + j] += sgn * wa * psiE[i] * psiE[j] * Jown[v * V + wv];
+        if (Off && other >= 0) {
+          double* Oe = Off + ((size_t)e * nfc + lf) * n * n;
+          for (int v = 0; v < V; ++v)
+            for (int wv = 0; wv < V; ++wv)
+              for (int i = 0; i < N; ++i)
+                for (int j = 0; j < N; ++j)
+                  Oe[(v * N + i) * n + wv * N + j] += sgn * wa * psiE[i] * psiO[j] * Joth[v * V + wv];
+        }
+      }
+    }
+  }
+}
+
+int neighbour(const Oracle& O, int e, int lf) {
+  const Face& F = O.faces[O.efc[(size_t)e * 2 * O.d + lf]];
+  if (F.eR < 0) return -1;
+  return O.eside[(size_t)e * 2 * O.d + lf] == 0 ? F.eR : F.eL;
+}
+
+// ---------------------------------------------------------------------------
+// Pseudo-time step (Section 4, eq. (x3d)): dtau_E = CFL h_E / ((2p+1)(|v| + c))
+// with h_E = 2 d |E| / |dE| and v, c from the cell-mean state u_0 psi_0.
+// ---------------------------------------------------------------------------
+void timestep(const Oracle& O, int p, int Np, double cfl, const double* u, double* dtau) {
+  const int d = O.d, V = O.V;
+  for (int e = 0; e < O.ne; ++e) {
+    double phi0 = std::pow(0.5, 0.5 * d);  // phi_0 = L_0^d, constant
+    double psi0 = O.T[(size_t)e * O.Nmax * O.Nmax] * phi0;
+    double U[MAXV];
+    for (int v = 0; v < V; ++v) U[v] = u[((size_t)e * V + v) * Np] * psi0;
+    double q2 = 0.0;
+    for (int a = 0; a < d; ++a) q2 += (U[1 + a] / U[0]) * (U[1 + a] / U[0]);
+    double c = std::sqrt(O.gam * pressure(d, O.gam, U) / U[0]);
+    dtau[e] = cfl * O.hE[e] / ((2.0 * p + 1.0) * (std::sqrt(q2) + c));
+  }
+}
+
+// Density-residual norm (Section 4, eq. (cfl)): (1/|Omega|) [int R(rho)^2]^(1/2);
+// with an orthonormal basis the integral is the sum of squared coefficients.
+double rnorm(const Oracle& O, int Np, const double* r) {
+  double s = 0.0;
+  for (int e = 0; e < O.ne; ++e)
+    for (int i = 0; i < Np; ++i) {
+      double x = r[((size_t)e * O.V + 0) * Np + i];
+      s += x * x;
+    }
+  return std::sqrt(s) / O.omega;
+}
+
+// Dense LU with partial pivoting (row-major), and solve.
+bool lu_factor(int n, double* A, int* piv) {
+  for (int k = 0; k < n; ++k) {
+    int pr = k;
+    double mx = std::fabs(A[k * n + k]);
+    for (int i = k + 1; i < n; ++i) if (std::fabs(A[i * n + k]) > mx) { mx = std::fabs(A[i * n + k]); pr = i; }
+    piv[k] = pr;
+    if (mx == 0.0) return false;
+    if (pr != k) for (int j = 0; j < n; ++j) std::swap(A[k * n + j], A[pr * n + j]);
+    for (int i = k + 1; i < n; ++i) {
+      A[i * n + k] /= A[k * n + k];
+      double l = A[i * n + k];
+      for (int j = k + 1; j < n; ++j) A[i * n + j] -= l * A[k * n + j];
+    }
+  }
+  return true;
+}
+void lu_solve(int n, const double* A, const int* piv, double* b) {
+  for (int k = 0; k < n; ++k) if (piv[k] != k) std::swap(b[k], b[piv[k]]);
+  for (int i = 0; i < n; ++i) { double s = b[i]; for (int j = 0; j < i; ++j) s -= A[i * n + j] * b[j]; b[i] = s; }
+  for (int i = n - 1; i >= 0; --i) { double s = b[i]; for (int j = i + 1; j < n; ++j) s -= A[i * n + j] * b[j]; b[i] = s / A[i * n + i]; }
+}
+
+void add_forcing(size_t n, double* r, const double* f) { if (f) for (size_t i = 0; i < n; ++i) r[i] += f[i]; }
+
+// ---------------------------------------------------------------------------
+// s-stage preconditioned Runge-Kutta step (Section 2.3, eq. (prk_scalar)):
+//   u^(k) = u^n + beta_k P^{-1}(u^n) [R(u^(k-1)) + f],  beta_k = 1/(s-k+1),
+// with P the element block of I/dtau - dR/du (the diagonal shift of the end of
+// Section 2.3; sign read so that P is the backward-Euler block of du/dt = R),
+// frozen at u^n.  R1 (optional) is the stage-1 residual R(u^n) + f.
+// ---------------------------------------------------------------------------
+bool prk(const Oracle& O, int p, int s, double cfl, double* u, const double* f, const double* R1) {
+  const int V = O.V, N = nmodes(O.d, p), n = V * N;
+  const size_t K = (size_t)O.ne * n;
+  std::vector<double> dtau(O.ne), D((size_t)O.ne * n * n), un(u, u + K), R(K);
+  std::vector<int> piv((size_t)O.ne * n);
+  timestep(O, p, N, cfl, u, dtau.data());
+  jacobian_blocks(O, p, u, D.data(), nullptr);
+  bool ok = true;
+#pragma omp parallel for schedule(static) reduction(&& : ok)
+  for (int e = 0; e < O.ne; ++e) {
+    double* P = &D[(size_t)e * n * n];
+    for (int i = 0; i < n * n; ++i) P[i] = -P[i];
+    for (int i = 0; i < n; ++i) P[i * n + i] += 1.0 / dtau[e];
+    if (!lu_factor(n, P, &piv[(size_t)e * n])) ok = false;
+  }
+  if (!ok) return false;
+  for (int k = 1; k <= s; ++k) {
+    if (k == 1 && R1) {
+      std::copy(R1, R1 + K, R.begin());
+    } else {
+      residual_t<double>(O, p, u, R.data());
+      add_forcing(K, R.data(), f);
+    }
+    double bk = 1.0 / (s - k + 1.0);
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < O.ne; ++e) {
+      double x[640];
+      for (int i = 0; i < n; ++i) x[i] = R[(size_t)e * n + i];
+      lu_solve(n, &D[(size_t)e * n * n], &piv[(size_t)e * n], x);
+      for (int i = 0; i < n; ++i) u[(size_t)e * n + i] = un[(size_t)e * n + i] + bk * x[i];
+    }
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Small dense matrix exponential: diagonal Pade approximant of degree 13 with
+// scaling and squaring (Higham, SIAM J. Matrix Anal. Appl. 26 (2005) 1179).
+// This stands in for the paper's rational approximation of exp(dt H_m)
+// (end of Section 2.2).
+// ---------------------------------------------------------------------------
+void matmul(int n, const double* A, const double* B, double* C) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < n; ++k) s += A[i * n + k] * B[k * n + j];
+      C[i * n + j] = s;
+    }
+}
+
+bool expm(int n, const double* A, double* E) {
+  static const double b[14] = {64764752532480000.0, 32382376266240000.0, 7771770303897600.0,
+                               1187353796428800.0,  129060195264000.0,   10559470521600.0,
+                               670442572800.0,      33522128640.0,       1323241920.0,
+                               40840800.0,          960960.0,            16380.0,
+                               182.0,               1.0};
+  const double theta13 = 5.371920351148152;
+  double nrm = 0.0;
+  for (int j = 0; j < n; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += std::fabs(A[i * n + j]);
+    nrm = std::max(nrm, s);
+  }
+  int sq = 0;
+  if (nrm > theta13) sq = std::max(0, (int)std::ceil(std::log2(nrm / theta13)));
+  const size_t nn = (size_t)n * n;
+  std::vector<double> B(nn), B2(nn), B4(nn), B6(nn), U(nn), Vm(nn), W(nn), Tm(nn);
+  double sc = std::ldexp(1.0, -sq);
+  for (size_t i = 0; i < nn; ++i) B[i] = A[i] * sc;
+  matmul(n, B.data(), B.data(), B2.data());
+  matmul(n, B2.data(), B2.data(), B4.data());
+  matmul(n, B4.data(), B2.data(), B6.data());
+  for (size_t i = 0; i < nn; ++i) W[i] = b[13] * B6[i] + b[11] * B4[i] + b[9] * B2[i];
+  matmul(n, B6.data(), W.data(), Tm.data());
+  for (size_t i = 0; i < nn; ++i) Tm[i] += b[7] * B6[i] + b[5] * B4[i] + b[3] * B2[i];
+  for (int i = 0; i < n; ++i) Tm[(size_t)i * n + i] += b[1];
+  matmul(n, B.data(), Tm.data(), U.data());
+  for (size_t i = 0; i < nn; ++i) W[i] = b[12] * B6[i] + b[10] * B4[i] + b[8] * B2[i];
+  matmul(n, B6.data(), W.data(), Vm.data());
+  for (size_t i = 0; i < nn; ++i) Vm[i] += b[6] * B6[i] + b[4] * B4[i] + b[2] * B2[i];
+  for (int i = 0; i < n; ++i) Vm[(size_t)i * n + i] += b[0];
+  // (V - U) X = (V + U)
+  std::vector<double> Pm(nn), Rhs(nn);
+  for (size_t i = 0; i < nn; ++i) { Pm[i] = Vm[i] - U[i]; Rhs[i] = Vm[i] + U[i]; }
+  std::vector<int> piv(n);
+  if (!lu_factor(n, Pm.data(), piv.data())) return false;
+  std::vector<double> col(n);
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) col[i] = Rhs[(size_t)i * n + j];
+    lu_solve(n, Pm.data(), piv.data(), col.data());
+    for (int i = 0; i < n; ++i) E[(size_t)i * n + j] = col[i];
+  }
+  for (int k = 0; k < sq; ++k) {
+    matmul(n, E, E, Tm.data());
+    std::copy(Tm.begin(), Tm.end(), E);
+  }
+  return true;
+}
+
+// phi_1(H) e_1 for an m x m matrix H (row-major), from the exponential of the
+// augmented matrix [[H, e_1], [0, 0]] whose last column holds phi_1(H) e_1.
+bool phi1_e1(int m, const double* H, double* y) {
+  const int n = m + 1;
+  std::vector<double> A((size_t)n * n, 0.0), E((size_t)n * n);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) A[(size_t)i * n + j] = H[(size_t)i * m + j];
+  A[(size_t)0 * n + m] = 1.0;
+  if (!expm(n, A.data(), E.data())) return false;
+  for (int i = 0; i < m; ++i) y[i] = E[(size_t)i * n + m];
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Arnoldi with modified Gram-Schmidt (Section 2.2, eqs. (vm)-(vm2)):
+// A V_m = V_{m+1} H~_m, v_1 = b / ||b||.  Stops early (happy breakdown) when
+// h_{j+1,j} <= 1e-12 ||A v_j||.  Returns the number of columns used.
+// ---------------------------------------------------------------------------
+template <class MatVec>
+int arnoldi(size_t K, int m, const double* b, MatVec Av, std::vector<double>& Vb, std::vector<double>& H, double& beta) {
+  Vb.assign(K * (m + 1), 0.0);
+  H.assign((size_t)(m + 1) * m, 0.0);
+  double s = 0.0;
+  for (size_t i = 0; i < K; ++i) s += b[i] * b[i];
+  beta = std::sqrt(s);
+  if (beta == 0.0) return 0;
+  for (size_t i = 0; i < K; ++i) Vb[i] = b[i] / beta;
+  std::vector<double> w(K);
+  for (int j = 0; j < m; ++j) {
+    Av(&Vb[(size_t)j * K], w.data());
+    double w0 = 0.0;
+    for (size_t i = 0; i < K; ++i) w0 += w[i] * w[i];
+    w0 = std::sqrt(w0);
+    for (int i = 0; i <= j; ++i) {
+      double h = 0.0;
+      const double* vi = &Vb[(size_t)i * K];
+      for (size_t k = 0; k < K; ++k) h += w[k] * vi[k];
+      H[(size_t)i * m + j] = h;
+      for (size_t k = 0; k < K; ++k) w[k] -= h * vi[k];
+    }
+    double hn = 0.0;
+    for (size_t k = 0; k < K; ++k) hn += w[k] * w[k];
+    hn = std::sqrt(hn);
+    H[(size_t)(j + 1) * m + j] = hn;
+    if (hn <= 1e-12 * w0) return j + 1;
+    for (size_t k = 0; k < K; ++k) Vb[(size_t)(j + 1) * K + k] = w[k] / hn;
+  }
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// EXP1 step on the p = 0 level (Section 2.1, eq. (EXP1); Section 2.2,
+// eq. (final)):  u <- u + phi_1(A) b with A = T J_0, b = T (R_0(u) + f),
+// T = diag(dt_E), dt_E = (pmax+1) dtau_E (Section 4; dtau with p = pmax,
+// element-local), J_0 the exact first-order Jacobian.  phi_1(A) b is
+// approximated by beta V_m phi_1(H_m) e_1.
+// ---------------------------------------------------------------------------
+struct Exp1Info { int m_used; double beta; };
+
+bool exp1(const Oracle& O, int pmax, int m, double cfl, double* u0, const double* f0, Exp1Info* info) {
+  const int d = O.d, V = O.V, nfc = 2 * d;
+  const size_t K = (size_t)O.ne * V;
+  std::vector<double> dtau(O.ne), R(K), Dg((size_t)O.ne * V * V), Off((size_t)O.ne * nfc * V * V), b(K);
+  timestep(O, pmax, 1, cfl, u0, dtau.data());
+  for (int e = 0; e < O.ne; ++e) dtau[e] *= (pmax + 1.0);
+  residual_t<double>(O, 0, u0, R.data());
+  add_forcing(K, R.data(), f0);
+  jacobian_blocks(O, 0, u0, Dg.data(), Off.data());
+  for (int e = 0; e < O.ne; ++e) for (int v = 0; v < V; ++v) b[(size_t)e * V + v] = dtau[e] * R[(size_t)e * V + v];
+  auto Av = [&](const double* x, double* y) {
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < O.ne; ++e) {
+      for (int v = 0; v < V; ++v) {
+        double s = 0.0;
+        for (int w = 0; w < V; ++w) s += Dg[((size_t)e * V + v) * V + w] * x[(size_t)e * V + w];
+        for (int lf = 0; lf < nfc; ++lf) {
+          int nb = neighbour(O, e, lf);
+          if (nb < 0) continue;
+          for (int w = 0; w < V; ++w) s += Off[(((size_t)e * nfc + lf) * V + v) * V + w] * x[(size_t)nb * V + w];
+        }
+        y[(size_t)e * V + v] = dtau[e] * s;
+      }
+    }
+  };
+  std::vector<double> Vb, H;
+  double beta = 0.0;
+  int mu = arnoldi(K, m, b.data(), Av, Vb, H, beta);
+  if (info) { info->m_used = mu; info->beta = beta; }
+  if (mu == 0) return true;
+  std::vector<double> Hm((size_t)mu * mu), y(mu);
+  for (int i = 0; i < mu; ++i)
+    for (int j = 0; j < mu; ++j) Hm[(size_t)i * mu + j] = H[(size_t)i * m + j];
+  if (!phi1_e1(mu, Hm.data(), y.data())) return false;
+  for (size_t k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int j = 0; j < mu; ++j) s += Vb[(size_t)j * K + k] * y[j];
+    u0[k] += beta * s;
+  }
+  return true;
+}
+
+// Modal restriction (truncation) and prolongation (zero padding) between
+// levels p and p-1 (Section 2.4, steps 2 and 6): with a hierarchical
+// orthonormal basis these are the L2 projection and the natural injection.
+void truncate(const Oracle& O, int Nf, int Nc, const double* x, double* y) {
+  for (int e = 0; e < O.ne; ++e)
+    for (int v = 0; v < O.V; ++v)
+      for (int i = 0; i < Nc; ++i) y[((size_t)e * O.V + v) * Nc + i] = x[((size_t)e * O.V + v) * Nf + i];
+}
+void add_padded(const Oracle& O, int Nf, int Nc, const double* x, double* y) {
+  for (int e = 0; e < O.ne; ++e)
+    for (int v = 0; v < O.V; ++v)
+      for (int i = 0; i < Nc; ++i) y[((size_t)e * O.V + v) * Nf + i] += x[((size_t)e * O.V + v) * Nc + i];
+}
+
+struct Cyc { int pmax, s, m; double cfl_max; };
+
+// ---------------------------------------------------------------------------
+// V-cycle (Section 2.4): PRK on p >= 1, EXP1 on p = 0, FAS coarse forcing.
+// The forcing is read as f_{p-1} = Trunc(R_p(u) + f_p) - R_{p-1}(Trunc u), so
+// the coarse residual at the restricted state equals the restricted fine
+// residual (the printed s^{p-1} has its sign garbled).  One PRK step before
+// restriction, no post-smoothing.
+// ---------------------------------------------------------------------------
+bool vcycle_rec(const Oracle& O, const Cyc& C, int p, double cfl, double* u, const double* f, const double* R1) {
+  const int V = O.V, N = nmodes(O.d, p);
+  if (p == 0) return exp1(O, C.pmax, C.m, cfl, u, f, nullptr);
+  if (!prk(O, p, C.s, cfl, u, f, R1)) return false;
+  const int Nc = nmodes(O.d, p - 1);
+  const size_t K = (size_t)O.ne * V * N, Kc = (size_t)O.ne * V * Nc;
+  std::vector<double> r(K), v0(Kc), rc(Kc), fc(Kc), Rc(Kc);
+  residual_t<double>(O, p, u, r.data());
+  add_forcing(K, r.data(), f);
+  truncate(O, N, Nc, u, v0.data());
+  truncate(O, N, Nc, r.data(), rc.data());
+  residual_t<double>(O, p - 1, v0.data(), Rc.data());
+  for (size_t i = 0; i < Kc; ++i) fc[i] = rc[i] - Rc[i];
+  std::vector<double> v(v0);
+  if (!vcycle_rec(O, C, p - 1, cfl, v.data(), fc.data(), (p - 1 >= 1) ? rc.data() : nullptr)) return false;
+  for (size_t i = 0; i < Kc; ++i) v[i] -= v0[i];
+  add_padded(O, N, Nc, v.data(), u);
+  return true;
+}
+
+// CFL ramp (Section 4, eq. (cfl)).  The residual norm entering the ramp is
+// divided by rref: rref = 1 is the literal formula; rref = r_1 (the norm at
+// the first iteration) makes the ramp start at CFL = 1 and grow as the
+// residual falls, which is the behaviour the text describes.
+double cfl_ramp(double cfl_max, double rn, double rref, int n, int pmax) {
+  double a = (rn > 0.0) ? rref / rn : HUGE_VAL;
+  double b = 1.0 + (n - 1.0) / (2.0 * pmax + 1.0);
+  return std::min(cfl_max, std::max(a, b));
+}
+
+}  // namespace
+
+// ===========================================================================
+// C interface (used by the tests through ctypes)
+// ===========================================================================
+extern "C" {
+
+void* orc_create(int dim, int n_vert, const double* xyz, int n_elem, const int32_t* ev, const int8_t* tag, int pmax,
+                 double gamma, double mach, double alpha_deg, double beta_deg, char* errbuf, int errlen) {
+  Oracle* O = new Oracle;
+  O->d = dim;
+  O->nv = n_vert;
+  O->ne = n_elem;
+  O->pmax = pmax;
+  O->gam = gamma;
+  O->mach = mach;
+  O->alpha = alpha_deg * M_PI / 180.0;
+  O->beta = beta_deg * M_PI / 180.0;
+  O->xyz.assign(xyz, xyz + (size_t)n_vert * dim);
+  O->ev.assign(ev, ev + (size_t)n_elem * (1 << dim));
+  O->tag.assign(tag, tag + (size_t)n_elem * 2 * dim);
+  if ((dim != 2 && dim != 3) || pmax < 0 || pmax > 6 || !setup(*O)) {
+    if (errbuf && errlen > 0) std::snprintf(errbuf, errlen, "%s", O->err.c_str());
+    delete O;
+    return nullptr;
+  }
+  return O;
+}
+
+void orc_free(void* h) { delete static_cast<Oracle*>(h); }
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+int orc_get_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+int orc_nmodes(int dim, int p) { return nmodes(dim, p); }
+int orc_nfaces(void* h) { return (int)static_cast<Oracle*>(h)->faces.size(); }
+
+void orc_gauss(int Q, double* x, double* w) {
+  std::vector<double> xg, wg;
+  gauss_legendre(Q, xg, wg);
+  for (int i = 0; i < Q; ++i) { x[i] = xg[i]; w[i] = wg[i]; }
+}
+
+void orc_modes(int dim, int p, int32_t* a /*[N][3]*/) {
+  auto m = mode_list(dim, p);
+  for (size_t k = 0; k < m.size(); ++k) for (int r = 0; r < 3; ++r) a[k * 3 + r] = m[k][r];
+}
+
+void orc_geometry(void* h, double* vol, double* surf, double* hE, double* omega) {
+  Oracle& O = *static_cast<Oracle*>(h);
+  for (int e = 0; e < O.ne; ++e) { vol[e] = O.vol[e]; surf[e] = O.surf[e]; hE[e] = O.hE[e]; }
+  *omega = O.omega;
+}
+
+void orc_basis_T(void* h, double* T) {
+  Oracle& O = *static_cast<Oracle*>(h);
+  std::memcpy(T, O.T.data(), O.T.size() * sizeof(double));
+}
+
+void orc_neighbours(void* h, int32_t* nb /*[E][2d]*/) {
+  Oracle& O = *static_cast<Oracle*>(h);
+  for (int e = 0; e < O.ne; ++e) for (int f = 0; f < 2 * O.d; ++f) nb[(size_t)e * 2 * O.d + f] = neighbour(O, e, f);
+}
+
+// Evaluate the level-p state of element e at reference point xi.
+void orc_eval_point(void* h, int p, int e, const double* u, const double* xi, double* U, double* x) {
+  Oracle& O = *static_cast<Oracle*>(h);
+  int N = nmodes(O.d, p);
+  double psi[128], det, c[MAXD][MAXD];
+  elem_basis(O, e, N, xi, psi, nullptr, x, &det, c);
+  eval_state(O, e, N, u, psi, U);
+}
+
+void orc_freestream_state(void* h, double* U) {
+  Oracle& O = *static_cast<Oracle*>(h);
+  for (int v = 0; v < O.V; ++v) U[v] = O.Uinf[v];
+}
+
+// Uniform free stream as a level-p coefficient vector: u_{E,v,0} = U_v / psi_0.
+void orc_freestream(void* h, int p, double* u) {
+  Oracle& O = *static_cast<Oracle*>(h);
+  int N = nmodes(O.d, p);
+  double phi0 = std::pow(0.5, 0.5 * O.d);
+  for (int e = 0; e < O.ne; ++e) {
+    double psi0 = O.T[(size_t)e * O.Nmax * O.Nmax] * phi0;
+    for (int v = 0; v < O.V; ++v)
+      for (int i = 0; i < N; ++i) u[((size_t)e * O.V + v) * N + i] = (i == 0) ? O.Uinf[v] / psi0 : 0.0;
+  }
+}
+
+void orc_residual(void* h, int p, const double* u, double* r) {
+  residual_t<double>(*static_cast<Oracle*>(h), p, u, r);
+}
+
+// Complex residual for brute-force complex-step tests.
+void orc_residual_complex(void* h, int p, const double* ure, const double* uim, double* rre, double* rim) {
+  Oracle& O = *static_cast<Oracle*>(h);
+  size_t K = (size_t)O.ne * O.V * nmodes(O.d, p);
+  std::vector<cd> u(K), r(K);
+  for (size_t i = 0; i < K; ++i) u[i] = cd(ure[i], uim[i]);
+  residual_t<cd>(O, p, u.data(), r.data());
+  for (size_t i = 0; i < K; ++i) { rre[i] = r[i].real(); rim[i] = r[i].imag(); }
+}
+
+void orc_jacobian_blocks(void* h, int p, const double* u, double* D, double* Off) {
+  jacobian_blocks(*static_cast<Oracle*>(h), p, u, D, Off);
+}
+
+void orc_flux_jac(int dim, double gamma, const double* U, const double* g, double* K) { flux_jac(dim, gamma, U, g, K); }
+
+void orc_rusanov(int dim, double gamma, const double* UL, const double* UR, const double* nh, double* F) {
+  rusanov<double>(dim, gamma, UL, UR, nh, F);
+}
+
+void orc_ghost(void* h, int tg, const double* U, const double* nh, const double* x, double* Ug) {
+  ghost_any<double>(*static_cast<Oracle*>(h), tg, U, nh, x, Ug);
+}
+
+// dtau for order p from a level vector with Nu modes per variable.
+void orc_timestep(void* h, int p, int Nu, double cfl, const double* u, double* dtau) {
+  Oracle& O = *static_cast<Oracle*>(h);
+  timestep(O, p, Nu, cfl, u, dtau);
+}
+
+double orc_rnorm(void* h, int p, const double* r) {
+  Oracle& O = *static_cast<Oracle*>(h);
+  return rnorm(O, nmodes(O.d, p), r);
+}
+
+double orc_cfl_ramp(double cfl_max, double rn, double rref, int n, int pmax) { return cfl_ramp(cfl_max, rn, rref, n, pmax); }
+
+int orc_prk(void* h, int p, int s, double cfl, double* u, const double* f) {
+  return prk(*static_cast<Oracle*>(h), p, s, cfl, u, f, nullptr) ? 0 : 1;
+}
+
+int orc_exp1(void* h, int pmax, int m, double cfl, double* u0, const double* f0, int* m_used, double* beta) {
+  Exp1Info inf{0, 0.0};
+  bool ok = exp1(*static_cast<Oracle*>(h), pmax, m, cfl, u0, f0, &inf);
+  if (m_used) *m_used = inf.m_used;
+  if (beta) *beta = inf.beta;
+  return ok ? 0 : 1;
+}
+
+int orc_expm(int n, const double* A, double* E) { return expm(n, A, E) ? 0 : 1; }
+int orc_phi1_e1(int m, const double* H, double* y) { return phi1_e1(m, H, y) ? 0 : 1; }
+
+// Arnoldi on an explicit dense matrix (tests of the Krylov identities).
+int orc_arnoldi_dense(int K, int m, const double* A, const double* b, double* Vout, double* Hout, double* beta) {
+  std::vector<double> Vb, H;
+  auto Av = [&](const double* x, double* y) {
+    for (int i = 0; i < K; ++i) { double s = 0.0; for (int j = 0; j < K; ++j) s += A[(size_t)i * K + j] * x[j]; y[i] = s; }
+  };
+  int mu = arnoldi((size_t)K, m, b, Av, Vb, H, *beta);
+  std::memcpy(Vout, Vb.data(), Vb.size() * sizeof(double));
+  std::memcpy(Hout, H.data(), H.size() * sizeof(double));
+  return mu;
+}
+
+// One V-cycle.  rn_out receives r_n = ||R_rho(u)||/|Omega| of the state on
+// entry; the CFL number of the cycle follows the ramp with that r_n.
+int orc_vcycle(void* h, int pmax, int s, int m, double cfl_max, double rref, int n, double* u, const double* f,
+               double* rn_out, double* cfl_out) {
+  Oracle& O = *static_cast<Oracle*>(h);
+  const size_t K = (size_t)O.ne * O.V * nmodes(O.d, pmax);
+  std::vector<double> R(K);
+  residual_t<double>(O, pmax, u, R.data());
+  add_forcing(K, R.data(), f);
+  double rn = rnorm(O, nmodes(O.d, pmax), R.data());
+  if (rn_out) *rn_out = rn;
+  if (!std::isfinite(rn)) return 2;
+  double cfl = cfl_ramp(cfl_max, rn, rref, n, pmax);
+  if (cfl_out) *cfl_out = cfl;
+  Cyc C{pmax, s, m, cfl_max};
+  return vcycle_rec(O, C, pmax, cfl, u, f, R.data()) ? 0 : 1;
+}
+
+// Steady solve: cycle n computes r_n at its entry state, stops if
+// r_n <= drop r_1, else performs the V-cycle.  hist[0..] = r_1, r_2, ...
+// relative_ramp != 0 feeds r_n / r_1 to the CFL ramp (else r_n).
+// Returns 0 converged, 3 not converged after max_cycles, 2 diverged, 1 error.
+int orc_solve(void* h, int pmax, int s, int m, double cfl_max, int relative_ramp, double drop, int max_cycles, double* u,
+              const double* f, double* hist, int* n_cycles) {
+  Oracle& O = *static_cast<Oracle*>(h);
+  const size_t K = (size_t)O.ne * O.V * nmodes(O.d, pmax);
+  std::vector<double> R(K);
+  double r1 = 0.0;
+  Cyc C{pmax, s, m, cfl_max};
+  for (int n = 1;; ++n) {
+    residual_t<double>(O, pmax, u, R.data());
+    add_forcing(K, R.data(), f);
+    double rn = rnorm(O, nmodes(O.d, pmax), R.data());
+    hist[n - 1] = rn;
+    if (n == 1) r1 = rn;
+    *n_cycles = n - 1;
+    if (!std::isfinite(rn)) return 2;
+    if (rn <= drop * r1) return 0;
+    if (n - 1 == max_cycles) return 3;
+    double cfl = cfl_ramp(cfl_max, rn, relative_ramp ? r1 : 1.0, n, pmax);
+    if (!vcycle_rec(O, C, pmax, cfl, u, f, R.data())) return 1;
+  }
+}
+
+// Manufactured-solution support: L2 projection of the exact state, source
+// forcing f_i = int psi_i div F(U_m) dx (divergence by complex step in x),
+// and the L2 error of a level-p state, all with a (p+4)-point rule.
+static void mms_loop(Oracle& O, int p, int mode, const double* uin, double* out, double* err) {
+  const int d = O.d, V = O.V, N = nmodes(d, p), Q = p + 4;
+  std::vector<double> xg, wg;
+  gauss_legendre(Q, xg, wg);
+  int nq = 1;
+  for (int k = 0; k < d; ++k) nq *= Q;
+  double esum = 0.0;
+  for (int e = 0; e < O.ne; ++e) {
+    if (out) for (int i = 0; i < V * N; ++i) out[(size_t)e * V * N + i] = 0.0;
+    double psi[128];
+    for (int q = 0; q < nq; ++q) {
+      double xi[MAXD], w = 1.0;
+      int t = q;
+      for (int k = 0; k < d; ++k) { xi[k] = xg[t % Q]; w *= wg[t % Q]; t /= Q; }
+      double x[MAXD], det, c[MAXD][MAXD];
+      elem_basis(O, e, N, xi, psi, nullptr, x, &det, c);
+      double val[MAXV];
+      if (mode == 0) {
+        mms_state<double>(d, O.gam, x, val);
+      } else if (mode == 1) {
+        for (int v = 0; v < V; ++v) val[v] = 0.0;
+        for (int a = 0; a < d; ++a) {
+          cd xc[MAXD], Uc[MAXV], Fc[MAXV];
+          for (int b = 0; b < d; ++b) xc[b] = x[b];
+          xc[a] = cd(x[a], 1e-30);
+          mms_state<cd>(d, O.gam, xc, Uc);
+          double ea[MAXD] = {0, 0, 0};
+          ea[a] = 1.0;
+          flux_n<cd>(d, O.gam, Uc, ea, Fc);
+          for (int v = 0; v < V; ++v) val[v] += Fc[v].imag() / 1e-30;
+        }
+      } else {
+        double Um[MAXV], Uh[MAXV];
+        mms_state<double>(d, O.gam, x, Um);
+        eval_state(O, e, N, uin, psi, Uh);
+        for (int v = 0; v < V; ++v) esum += w * det * (Uh[v] - Um[v]) * (Uh[v] - Um[v]);
+        continue;
+      }
+      for (int v = 0; v < V; ++v)
+        for (int i = 0; i < N; ++i) out[((size_t)e * V + v) * N + i] += w * det * psi[i] * val[v];
+    }
+  }
+  if (err) *err = std::sqrt(esum);
+}
+
+void orc_mms_project(void* h, int p, double* u) { mms_loop(*static_cast<Oracle*>(h), p, 0, nullptr, u, nullptr); }
+void orc_mms_forcing(void* h, int p, double* f) { mms_loop(*static_cast<Oracle*>(h), p, 1, nullptr, f, nullptr); }
+double orc_mms_error(void* h, int p, const double* u) {
+  double e = 0.0;
+  mms_loop(*static_cast<Oracle*>(h), p, 2, u, nullptr, &e);
+  return e;
+}
+
+}  // extern "C"
