@@ -1,0 +1,153 @@
+/*
+ * eg.h -- C ABI of the MI355X exponential p-multigrid (eMG) library.
+ *
+ * The library solves the steady compressible Euler equations discretised by
+ * a modal discontinuous Galerkin method (arXiv:1807.01151, Section 3) with
+ * the eMG V-cycle (Section 2.4): an s-stage element-block-preconditioned
+ * Runge-Kutta smoother (Section 2.3) on orders p >= 1 and the EXP1
+ * exponential step (Sections 2.1-2.2) on p = 0.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - d = 2 (quads) or 3 (hexes); V = d + 2 conserved variables
+ *    (rho, rho v_1..rho v_d, rho E); gamma from eg_params.
+ *  - A level-p coefficient vector holds N_p = (p+1)^d modes per variable,
+ *    contiguous FP64, layout [elem][var][mode], modes in hierarchical order
+ *    (sort key: largest 1D degree, then the degrees along axes 0, 1, 2), so
+ *    level p-1 is the leading N_{p-1} slice of each [elem][var] row.
+ *    Coefficients refer to the per-element orthonormal basis psi_i of
+ *    Section 3.2 (mass matrix = identity), built from tensor Legendre
+ *    polynomials on the reference element.
+ *  - Pointers named *_dev are HIP device pointers owned by the caller; *_host
+ *    are host pointers.  Every entry point enqueues its work on the stream
+ *    passed to eg_init_mesh; entry points returning host values synchronise
+ *    that stream.
+ *  - Errors: a non-EG_OK status leaves caller buffers untouched when it is
+ *    EG_ERR_ARG or EG_ERR_MESH (all checks precede any launch); the message is
+ *    available from eg_last_error().  No C++ exception crosses this ABI.
+ *  - One handle per stream; a handle is not safe for concurrent use.
+ */
+#ifndef EG_H
+#define EG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eg_handle eg_handle;
+
+typedef enum {
+  EG_OK = 0,
+  EG_ERR_ARG = 1,            /* invalid argument (null pointer, size, order) */
+  EG_ERR_MESH = 2,           /* unmatched / non-conforming face, inverted element */
+  EG_ERR_ALLOC = 3,          /* device allocation failed */
+  EG_ERR_HIP = 4,            /* a HIP call failed; message has hipGetErrorString */
+  EG_ERR_NOT_CONVERGED = 5,  /* eg_solve_steady hit max_cycles (history filled) */
+  EG_ERR_DIVERGED = 6,       /* non-finite residual norm (history filled) */
+  EG_ERR_UNSUPPORTED = 7     /* valid request this build does not implement */
+} eg_status;
+
+/* Boundary tags of eg_mesh.bface_tag. */
+enum { EG_FACE_INTERIOR = 0, EG_FACE_WALL = 1, EG_FACE_FARFIELD = 2 };
+
+typedef struct {
+  int dim;                  /* 2 or 3 */
+  int n_vert;
+  const double* xyz;        /* host, [n_vert][dim]; copied */
+  int n_elem;
+  const int32_t* elem_vert; /* host, [n_elem][2^dim]; local vertex a+2b(+4c) sits at
+                               reference corner (2a-1, 2b-1[, 2c-1]); copied */
+  const int8_t* bface_tag;  /* host, [n_elem][2 dim]; local face 2r+s is xi_r = -1 (s=0)
+                               or +1 (s=1).  0 interior (matched to the neighbour
+                               that shares its vertices), 1 slip wall, 2 far-field */
+} eg_mesh;
+
+typedef struct {
+  int p_max;          /* highest order, 0..4 (2D) or 0..2 (3D) */
+  int rk_stages;      /* s of the PRK smoother (Section 2.3); paper: 4 */
+  double cfl_max;     /* upper bound of the CFL ramp (Section 4, eq. (cfl)); paper: 100 */
+  int krylov_m;       /* Krylov dimension of EXP1 (Section 5: m = 30), 1..48 */
+  int relative_ramp;  /* 1: the ramp uses ||R(rho_n)|| / ||R(rho_1)||; 0: the printed absolute norm */
+  double gamma;       /* ratio of specific heats (paper: 7/5) */
+  double mach;        /* free-stream Mach number; rho_inf = 1, p_inf = 1/gamma */
+  double alpha_deg;   /* free-stream angle in the x-y plane */
+  double beta_deg;    /* 3D only: angle out of the x-y plane */
+} eg_params;
+
+/* Builds faces, orientation codes, geometry and per-element basis data, and
+ * allocates every device workspace.  hip_stream may be NULL (default stream).
+ * On failure *out may still receive a handle (so that eg_last_error can be
+ * read); release it with eg_free. */
+eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* params, void* hip_stream, eg_handle** out);
+
+void eg_free(eg_handle* h);
+
+const char* eg_last_error(const eg_handle* h);
+
+/* Sizes: number of elements, modes per variable at level p, variables. */
+eg_status eg_sizes(const eg_handle* h, int p, int* n_elem, int* n_modes, int* n_vars);
+
+/* u_dev <- uniform free stream at level p (all higher modes zero). */
+eg_status eg_set_freestream(eg_handle* h, int p, double* u_dev);
+
+/* DG residual R_p(u) of Section 3.1, eq. (euler3) (no source term):
+ *   R_{E,i} = -sum_faces int psi_i F~.n dsigma + int_E F . grad psi_i dx,
+ * Rusanov flux, (p+2)^d Gauss points per element and (p+2)^(d-1) per face.
+ * u_dev, r_dev: level-p vectors.  Asynchronous. */
+eg_status eg_residual(eg_handle* h, int p, const double* u_dev, double* r_dev);
+
+/* Local pseudo-time step of Section 4, eq. (x3d):
+ *   dtau_E = cfl h_E / ((2 p + 1)(|v| + c)),  h_E = 2 d |E| / |dE|,
+ * v and c from the element-mean state of the level-p_level vector u_dev.
+ * dtau_dev: [n_elem].  Asynchronous. */
+eg_status eg_timestep(eg_handle* h, int p, int p_level, double cfl, const double* u_dev, double* dtau_dev);
+
+/* Element-diagonal Jacobian blocks D_E = dR_E/du_E at level p
+ * (Section 3.3, eq. (jac1)), layout [elem][(var,mode)][(var,mode)], row
+ * (v, i) = v N_p + i.  Asynchronous. */
+eg_status eg_element_jacobian(eg_handle* h, int p, const double* u_dev, double* D_dev);
+
+/* One s-stage PRK step at level p >= 1 (Section 2.3, eq. (prk_scalar)):
+ *   u^(k) = u^n + beta_k P^{-1} [R_p(u^(k-1)) + f],  beta_k = 1/(s-k+1),
+ * P_E = I/dtau_E - D_E(u^n) (dtau at order p and the given cfl).
+ * u_dev is updated in place; f_dev (level p) may be NULL.  Asynchronous. */
+eg_status eg_prk_step(eg_handle* h, int p, double cfl, double* u_dev, const double* f_dev);
+
+/* p = 0 Jacobian (Section 3.3 at p = 0): diagonal blocks [elem][V][V] and
+ * neighbour blocks [elem][2d][V][V] (zero on boundary faces); nbr_dev
+ * (may be NULL) receives [elem][2d] neighbour indices, -1 on boundaries. */
+eg_status eg_jacobian_p0(eg_handle* h, const double* u0_dev, double* diag_dev, double* off_dev, int32_t* nbr_dev);
+
+/* One EXP1 step on the p = 0 level (Sections 2.1-2.2, eqs. (EXP1), (final)):
+ *   u0 <- u0 + phi_1(A) b,  A = T J_0(u0),  b = T [R_0(u0) + f0],
+ * T = diag(dt_E), dt_E = (p_max + 1) dtau_E (dtau at order p_max, Section 4),
+ * phi_1(A) b ~ beta V_m phi_1(H_m) e_1 with krylov_m Arnoldi steps.
+ * f0_dev may be NULL.  m_used_host (may be NULL) gets the Krylov dimension
+ * actually used (smaller after a happy breakdown); synchronises if non-NULL. */
+eg_status eg_exp1_step(eg_handle* h, double cfl, double* u0_dev, const double* f0_dev, int* m_used_host);
+
+/* Density-residual norm of Section 4: ||R(rho)|| = (1/|Omega|) (int R_rho^2)^(1/2)
+ * of a level-p_max residual vector.  Synchronises. */
+eg_status eg_rnorm(eg_handle* h, const double* r_dev, double* rn_host);
+
+/* One eMG V-cycle (Section 2.4) on the level-p_max state u_dev, cycle index
+ * n >= 1 (enters the CFL ramp).  rref is the reference norm of the ramp
+ * (r_1 for the relative ramp, 1 for the absolute one; 0 = use the state's
+ * own norm, i.e. a first cycle).  rn_host receives r_n of the entry state,
+ * cfl_host (may be NULL) the CFL used.  Synchronises once. */
+eg_status eg_vcycle(eg_handle* h, double* u_dev, int n, double rref, double* rn_host, double* cfl_host);
+
+/* Steady solve: repeat V-cycles until r_n <= drop_tol r_1 or max_cycles.
+ * hist_host[0..*n_cycles_host] receives r_1, r_2, ... (caller provides
+ * max_cycles + 1 entries).  Returns EG_OK, EG_ERR_NOT_CONVERGED or
+ * EG_ERR_DIVERGED (history filled in every case). */
+eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
+                          int* n_cycles_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EG_H */

@@ -1,0 +1,200 @@
+"""ctypes binding of libeg.so: argument marshalling only."""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libeg.so")
+_lib = None
+
+# every symbol include/eg.h declares
+EXPORTED_SYMBOLS = (
+    "eg_init_mesh", "eg_free", "eg_last_error", "eg_sizes", "eg_set_freestream", "eg_residual",
+    "eg_timestep", "eg_element_jacobian", "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm",
+    "eg_vcycle", "eg_solve_steady",
+)
+
+STATUS = {0: "EG_OK", 1: "EG_ERR_ARG", 2: "EG_ERR_MESH", 3: "EG_ERR_ALLOC", 4: "EG_ERR_HIP",
+          5: "EG_ERR_NOT_CONVERGED", 6: "EG_ERR_DIVERGED", 7: "EG_ERR_UNSUPPORTED"}
+
+
+class EgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_vert", C.c_int), ("xyz", C.POINTER(C.c_double)), ("n_elem", C.c_int),
+                ("elem_vert", C.POINTER(C.c_int32)), ("bface_tag", C.POINTER(C.c_int8))]
+
+
+class _Params(C.Structure):
+    _fields_ = [("p_max", C.c_int), ("rk_stages", C.c_int), ("cfl_max", C.c_double), ("krylov_m", C.c_int),
+                ("relative_ramp", C.c_int), ("gamma", C.c_double), ("mach", C.c_double),
+                ("alpha_deg", C.c_double), ("beta_deg", C.c_double)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libeg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with paper_1807_01151_amd/build.py")
+        L = C.CDLL(_LIB_PATH)
+        vp, d, i = C.c_void_p, C.c_double, C.c_int
+        pd = C.POINTER(C.c_double)
+        L.eg_init_mesh.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), vp, C.POINTER(vp)]
+        L.eg_init_mesh.restype = i
+        L.eg_free.argtypes = [vp]
+        L.eg_free.restype = None
+        L.eg_last_error.argtypes = [vp]
+        L.eg_last_error.restype = C.c_char_p
+        L.eg_sizes.argtypes = [vp, i, C.POINTER(i), C.POINTER(i), C.POINTER(i)]
+        L.eg_set_freestream.argtypes = [vp, i, vp]
+        L.eg_residual.argtypes = [vp, i, vp, vp]
+        L.eg_timestep.argtypes = [vp, i, i, d, vp, vp]
+        L.eg_element_jacobian.argtypes = [vp, i, vp, vp]
+        L.eg_prk_step.argtypes = [vp, i, d, vp, vp]
+        L.eg_jacobian_p0.argtypes = [vp, vp, vp, vp, vp]
+        L.eg_exp1_step.argtypes = [vp, d, vp, vp, C.POINTER(i)]
+        L.eg_rnorm.argtypes = [vp, vp, pd]
+        L.eg_vcycle.argtypes = [vp, vp, i, d, pd, pd]
+        L.eg_solve_steady.argtypes = [vp, vp, d, i, pd, C.POINTER(i)]
+        for name in ("eg_sizes", "eg_set_freestream", "eg_residual", "eg_timestep", "eg_element_jacobian",
+                     "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm", "eg_vcycle",
+                     "eg_solve_steady"):
+            getattr(L, name).restype = i
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or not t.is_contiguous():
+        raise TypeError("expected a contiguous device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One mesh on one device stream.  Level-p state tensors are float64
+    [n_elem, V, N_p] on the device (C ABI layout [elem][var][mode])."""
+
+    def __init__(self, mesh, p_max: int, rk_stages: int = 4, cfl_max: float = 100.0, krylov_m: int = 30,
+                 relative_ramp: bool = True, gamma: float = 1.4, mach: float = 0.3, alpha_deg: float = 0.0,
+                 beta_deg: float = 0.0, stream=None):
+        import numpy as np
+        import torch
+        L = lib()
+        m = mesh.contiguous()
+        self._keep = (m.xyz, m.elem_vert, m.bface_tag)
+        cm = _Mesh(m.dim, m.n_vert, m.xyz.ctypes.data_as(C.POINTER(C.c_double)), m.n_elem,
+                   m.elem_vert.ctypes.data_as(C.POINTER(C.c_int32)),
+                   m.bface_tag.ctypes.data_as(C.POINTER(C.c_int8)))
+        cp = _Params(p_max, rk_stages, cfl_max, krylov_m, int(relative_ramp), gamma, mach, alpha_deg, beta_deg)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        st = L.eg_init_mesh(C.byref(cm), C.byref(cp), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        self._h = h
+        if st != 0:
+            msg = L.eg_last_error(h).decode() if h.value else ""
+            if h.value:
+                L.eg_free(h)
+            self._h = None
+            raise EgError(st, msg)
+        self.dim, self.p_max, self.n_elem, self.V = m.dim, p_max, m.n_elem, m.dim + 2
+        self.krylov_m = krylov_m
+        self._np = np
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().eg_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        if st != 0:
+            raise EgError(st, lib().eg_last_error(self._h).decode())
+
+    def N(self, p: int) -> int:
+        return (p + 1) ** self.dim
+
+    def empty(self, p: int):
+        import torch
+        return torch.empty((self.n_elem, self.V, self.N(p)), dtype=torch.float64, device="cuda")
+
+    def freestream(self, p: int):
+        u = self.empty(p)
+        self._chk(lib().eg_set_freestream(self._h, p, _ptr(u)))
+        return u
+
+    def residual(self, p: int, u, out=None):
+        r = self.empty(p) if out is None else out
+        self._chk(lib().eg_residual(self._h, p, _ptr(u), _ptr(r)))
+        return r
+
+    def timestep(self, p: int, cfl: float, u):
+        import torch
+        dt = torch.empty(self.n_elem, dtype=torch.float64, device="cuda")
+        p_level = round(u.shape[2] ** (1.0 / self.dim)) - 1
+        self._chk(lib().eg_timestep(self._h, p, p_level, cfl, _ptr(u), _ptr(dt)))
+        return dt
+
+    def element_jacobian(self, p: int, u):
+        import torch
+        n = self.V * self.N(p)
+        D = torch.empty((self.n_elem, n, n), dtype=torch.float64, device="cuda")
+        self._chk(lib().eg_element_jacobian(self._h, p, _ptr(u), _ptr(D)))
+        return D
+
+    def prk_step(self, p: int, cfl: float, u, f=None):
+        self._chk(lib().eg_prk_step(self._h, p, cfl, _ptr(u), _ptr(f)))
+        return u
+
+    def jacobian_p0(self, u0):
+        import torch
+        V, nf = self.V, 2 * self.dim
+        Dg = torch.empty((self.n_elem, V, V), dtype=torch.float64, device="cuda")
+        Off = torch.empty((self.n_elem, nf, V, V), dtype=torch.float64, device="cuda")
+        nb = torch.empty((self.n_elem, nf), dtype=torch.int32, device="cuda")
+        self._chk(lib().eg_jacobian_p0(self._h, _ptr(u0), _ptr(Dg), _ptr(Off), _ptr(nb)))
+        return Dg, Off, nb
+
+    def exp1_step(self, cfl: float, u0, f0=None):
+        mu = C.c_int(0)
+        self._chk(lib().eg_exp1_step(self._h, cfl, _ptr(u0), _ptr(f0), C.byref(mu)))
+        return u0, mu.value
+
+    def rnorm(self, r) -> float:
+        v = C.c_double(0.0)
+        self._chk(lib().eg_rnorm(self._h, _ptr(r), C.byref(v)))
+        return v.value
+
+    def vcycle(self, u, n: int, rref: float = 0.0):
+        rn = C.c_double(0.0)
+        cfl = C.c_double(0.0)
+        self._chk(lib().eg_vcycle(self._h, _ptr(u), n, rref, C.byref(rn), C.byref(cfl)))
+        return rn.value, cfl.value
+
+    def solve_steady(self, u, drop_tol: float = 1e-10, max_cycles: int = 1000, raise_on_fail: bool = False):
+        np = self._np
+        hist = np.zeros(max_cycles + 1)
+        nc = C.c_int(0)
+        st = lib().eg_solve_steady(self._h, _ptr(u), drop_tol, max_cycles,
+                                   hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nc))
+        if st not in (0, 5, 6) or (raise_on_fail and st != 0):
+            self._chk(st)
+        return hist[: nc.value + 1], st

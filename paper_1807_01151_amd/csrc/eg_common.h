@@ -1,0 +1,49 @@
+// Shared compile-time configuration and reference tables of the HIP path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eg {
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// Sizes of order P in dimension D: V variables, Q Gauss points per axis,
+// N = (P+1)^D modes, QV volume points, QF points per face, NF faces, NC corners.
+template <int D, int P>
+struct Cfg {
+  static constexpr int V = D + 2;
+  static constexpr int Q = P + 2;
+  static constexpr int N = ipow(P + 1, D);
+  static constexpr int QV = ipow(Q, D);
+  static constexpr int QF = ipow(Q, D - 1);
+  static constexpr int NF = 2 * D;
+  static constexpr int NC = 1 << D;
+  static constexpr int NB = V * N;  // block size of the element operator
+};
+
+// One-dimensional tables of order P, copied to LDS by every kernel:
+// Gauss points / weights of the (P+2)-point rule, orthonormal Legendre
+// values and derivatives at those points and at the interval ends, and the
+// multi-index of every mode in hierarchical order.
+template <int D, int P>
+struct Tab {
+  double x[P + 2];
+  double w[P + 2];
+  double L[P + 1][P + 2];
+  double dL[P + 1][P + 2];
+  double Lb[P + 1][2];
+  int8_t m[Cfg<D, P>::N][3];
+};
+
+// Free stream and gas constant passed to kernels by value.
+struct Gas {
+  double g;
+  double Uinf[5];
+};
+
+// Boundary codes stored in the neighbour array for faces without neighbour.
+constexpr int NB_WALL = -1;
+constexpr int NB_FAR = -2;
+
+}  // namespace eg

@@ -1,0 +1,773 @@
+// Host side of the MI355X eMG library: mesh set-up, device workspaces, the
+// C ABI declared in include/eg.h and the V-cycle driver (arXiv:1807.01151,
+// Section 2.4).  Every floating-point step of the hot path runs in the HIP
+// kernels of eg_kernels.hip; the host only prepares mesh data once, launches
+// kernels and reads back the residual norm.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/eg.h"
+#include "eg_launch.h"
+
+using eg::DevMesh;
+using eg::TabData;
+
+struct eg_handle {
+  DevMesh M;
+  int pmax = 1, s = 4, m = 30, relr = 1;
+  double cfl_max = 100.0;
+  hipStream_t st = nullptr;
+  std::string err;
+  std::vector<TabData> tabs;
+  std::vector<std::array<int, 3>> modes;  // p_max modes
+  double* ut[5] = {};
+  double* un[5] = {};
+  double* rt[5] = {};
+  double* ft[5] = {};
+  double* uc0[5] = {};
+  double* F[5] = {};
+  int* perm[5] = {};
+  double* dtau = nullptr;
+  double* tmp = nullptr;
+  double* tmp2 = nullptr;
+  double* u0 = nullptr;
+  double* b0 = nullptr;
+  double* Ad = nullptr;
+  double* Ao = nullptr;
+  double* dt0 = nullptr;
+  double* Vb = nullptr;
+  double* H = nullptr;
+  double* part1 = nullptr;
+  double* part2 = nullptr;
+  double* info = nullptr;
+  double* y = nullptr;
+  double* npart = nullptr;
+  double* nout = nullptr;
+  int* dfail = nullptr;
+  double* hpin = nullptr;
+  int nblk_arn = 0;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+int nmodes_of(int d, int p) { return d == 2 ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1); }
+
+// Gauss-Legendre nodes (ascending) and weights: Newton on P_Q started from
+// the asymptotic root estimate; the rule is symmetrised exactly.
+void gauss_rule(int Q, double* x, double* w) {
+  for (int k = 0; k < (Q + 1) / 2; ++k) {
+    double z = std::cos(M_PI * (4.0 * k + 3.0) / (4.0 * Q + 2.0));
+    double dP = 1.0;
+    for (int it = 0; it < 50; ++it) {
+      double pm = 1.0, p = z;
+      for (int j = 1; j < Q; ++j) {
+        double pn = ((2 * j + 1) * z * p - j * pm) / (j + 1);
+        pm = p;
+        p = pn;
+      }
+      if (Q == 1) { p = z; pm = 1.0; }
+      dP = Q * (pm - z * p) / (1.0 - z * z);
+      double dz = p / dP;
+      z -= dz;
+      if (std::fabs(dz) <= 1e-16 * std::max(1.0, std::fabs(z))) break;
+    }
+    double pm = 1.0, p = z;
+    for (int j = 1; j < Q; ++j) {
+      double pn = ((2 * j + 1) * z * p - j * pm) / (j + 1);
+      pm = p;
+      p = pn;
+    }
+    if (Q == 1) { p = z; pm = 1.0; }
+    dP = Q * (pm - z * p) / (1.0 - z * z);
+    double wk = 2.0 / ((1.0 - z * z) * dP * dP);
+    x[Q - 1 - k] = z;
+    x[k] = -z;
+    w[Q - 1 - k] = wk;
+    w[k] = wk;
+  }
+  if (Q % 2 == 1) x[Q / 2] = 0.0;
+}
+
+// Orthonormal Legendre sqrt((2a+1)/2) P_a(t) and derivative, a = 0..pm.
+void legendre_values(int pm, double t, double* L, double* dL) {
+  double P[10], dP[10];
+  P[0] = 1.0;
+  dP[0] = 0.0;
+  P[1] = t;
+  dP[1] = 1.0;
+  for (int a = 1; a < pm; ++a) {
+    P[a + 1] = ((2 * a + 1) * t * P[a] - a * P[a - 1]) / (a + 1);
+    dP[a + 1] = dP[a - 1] + (2 * a + 1) * P[a];
+  }
+  for (int a = 0; a <= pm; ++a) {
+    double s = std::sqrt(a + 0.5);
+    L[a] = s * P[a];
+    dL[a] = s * dP[a];
+  }
+}
+
+std::vector<std::array<int, 3>> hier_modes(int d, int p) {
+  std::vector<std::array<int, 3>> v;
+  for (int c = 0; c <= (d == 3 ? p : 0); ++c)
+    for (int b = 0; b <= p; ++b)
+      for (int a = 0; a <= p; ++a) v.push_back({a, b, c});
+  std::stable_sort(v.begin(), v.end(), [](const std::array<int, 3>& l, const std::array<int, 3>& r) {
+    int ml = std::max(l[0], std::max(l[1], l[2])), mr = std::max(r[0], std::max(r[1], r[2]));
+    if (ml != mr) return ml < mr;
+    if (l[0] != r[0]) return l[0] < r[0];
+    if (l[1] != r[1]) return l[1] < r[1];
+    return l[2] < r[2];
+  });
+  return v;
+}
+
+void fill_tabdata(TabData& t, int d, int p, const std::vector<std::array<int, 3>>& modes) {
+  std::memset(&t, 0, sizeof t);
+  const int Q = p + 2;
+  gauss_rule(Q, t.x, t.w);
+  for (int i = 0; i < Q; ++i) {
+    double L[10], dL[10];
+    legendre_values(std::max(p, 1), t.x[i], L, dL);
+    for (int a = 0; a <= p; ++a) { t.L[a][i] = L[a]; t.dL[a][i] = dL[a]; }
+  }
+  for (int s = 0; s < 2; ++s) {
+    double L[10], dL[10];
+    legendre_values(std::max(p, 1), s ? 1.0 : -1.0, L, dL);
+    for (int a = 0; a <= p; ++a) t.Lb[a][s] = L[a];
+  }
+  const int N = nmodes_of(d, p);
+  for (int k = 0; k < N; ++k)
+    for (int r = 0; r < 3; ++r) t.m[k][r] = modes[k][r];
+}
+
+// Tangents of the multilinear map at xi; returns det and c[r] (see geom in
+// the kernels).
+double host_geom(int d, const double* X, const double* xi, double c[3][3]) {
+  double t[3][3] = {};
+  for (int k = 0; k < (1 << d); ++k)
+    for (int r = 0; r < d; ++r) {
+      double g = 1.0;
+      for (int q = 0; q < d; ++q) {
+        double s = ((k >> q) & 1) ? 1.0 : -1.0;
+        g *= (q == r) ? 0.5 * s : 0.5 * (1.0 + s * xi[q]);
+      }
+      for (int a = 0; a < d; ++a) t[r][a] += g * X[k * d + a];
+    }
+  if (d == 2) {
+    c[0][0] = t[1][1]; c[0][1] = -t[1][0];
+    c[1][0] = -t[0][1]; c[1][1] = t[0][0];
+    return t[0][0] * t[1][1] - t[0][1] * t[1][0];
+  }
+  for (int r = 0; r < 3; ++r) {
+    const double* a = t[(r + 1) % 3];
+    const double* b = t[(r + 2) % 3];
+    c[r][0] = a[1] * b[2] - a[2] * b[1];
+    c[r][1] = a[2] * b[0] - a[0] * b[2];
+    c[r][2] = a[0] * b[1] - a[1] * b[0];
+  }
+  return t[0][0] * c[0][0] + t[0][1] * c[0][1] + t[0][2] * c[0][2];
+}
+
+eg_status fail(eg_handle* h, eg_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+eg_status hipfail(eg_handle* h, hipError_t e, const char* where) {
+  return fail(h, EG_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(h, call)                                  \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hipfail((h), e_, #call); \
+  } while (0)
+
+template <class T>
+eg_status dalloc(eg_handle* h, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return EG_OK;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) return fail(h, EG_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
+  h->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return EG_OK;
+}
+
+#define ECHK(call)                 \
+  do {                             \
+    eg_status s_ = (call);         \
+    if (s_ != EG_OK) return s_;    \
+  } while (0)
+
+// Mesh set-up: faces matched through their vertex sets, orientation codes of
+// the neighbour's face points, element geometry (|E|, |dE|, h_E) and the
+// Cholesky factor of the phi mass matrix, all with the (p_max+2)-point rule
+// (exact for the mass matrix of multilinear elements).
+eg_status setup_mesh(eg_handle* h, const eg_mesh* mesh, std::vector<double>& xv, std::vector<int>& nbr,
+                     std::vector<uint8_t>& ncode, std::vector<double>& Lpk, std::vector<double>& Gpk,
+                     std::vector<double>& hE, double& omega) {
+  const int d = mesh->dim, ne = mesh->n_elem, nf = 2 * d, nc = 1 << d, ncf = 1 << (d - 1);
+  xv.assign((size_t)ne * nc * d, 0.0);
+  for (int e = 0; e < ne; ++e)
+    for (int k = 0; k < nc; ++k) {
+      int vid = mesh->elem_vert[(size_t)e * nc + k];
+      if (vid < 0 || vid >= mesh->n_vert) return fail(h, EG_ERR_MESH, "vertex index out of range");
+      for (int a = 0; a < d; ++a) xv[((size_t)e * nc + k) * d + a] = mesh->xyz[(size_t)vid * d + a];
+    }
+  nbr.assign((size_t)ne * nf, 0);
+  ncode.assign((size_t)ne * nf, 0);
+  auto face_corners = [&](int e, int lf, int* vv) {
+    int r = lf / 2, s = lf % 2, ta[2], k = 0;
+    for (int a = 0; a < d; ++a) if (a != r) ta[k++] = a;
+    for (int c = 0; c < ncf; ++c) {
+      int loc = s << r;
+      for (int q = 0; q < d - 1; ++q) if ((c >> q) & 1) loc |= 1 << ta[q];
+      vv[c] = mesh->elem_vert[(size_t)e * nc + loc];
+    }
+  };
+  std::map<std::array<int, 4>, std::pair<int, int>> pending;
+  std::vector<std::pair<std::pair<int, int>, std::pair<int, int>>> pairs;
+  for (int e = 0; e < ne; ++e)
+    for (int lf = 0; lf < nf; ++lf) {
+      int tag = mesh->bface_tag[(size_t)e * nf + lf];
+      if (tag == EG_FACE_WALL) { nbr[(size_t)e * nf + lf] = eg::NB_WALL; continue; }
+      if (tag == EG_FACE_FARFIELD) { nbr[(size_t)e * nf + lf] = eg::NB_FAR; continue; }
+      if (tag != EG_FACE_INTERIOR) return fail(h, EG_ERR_MESH, "unknown boundary tag");
+      int vv[4] = {-1, -1, -1, -1};
+      face_corners(e, lf, vv);
+      std::array<int, 4> key{vv[0], vv[1], vv[2], vv[3]};
+      std::sort(key.begin(), key.begin() + ncf);
+      auto it = pending.find(key);
+      if (it == pending.end()) pending.emplace(key, std::make_pair(e, lf));
+      else { pairs.push_back({it->second, {e, lf}}); pending.erase(it); }
+    }
+  if (!pending.empty()) return fail(h, EG_ERR_MESH, "interior face without a matching neighbour face");
+  // orientation code of the map from one side's face coordinates to the other's
+  auto code_of = [&](int e, int lf, int e2, int lf2, uint8_t& code) -> bool {
+    int va[4], vb[4];
+    face_corners(e, lf, va);
+    face_corners(e2, lf2, vb);
+    auto pos = [&](int vid, double* sc) {
+      for (int c = 0; c < ncf; ++c) if (vb[c] == vid) {
+        for (int q = 0; q < d - 1; ++q) sc[q] = ((c >> q) & 1) ? 1.0 : -1.0;
+        return true;
+      }
+      return false;
+    };
+    double s0[2] = {0, 0}, s1[2] = {0, 0}, s2[2] = {0, 0};
+    if (!pos(va[0], s0) || !pos(va[1], s1)) return false;
+    if (d == 3 && !pos(va[2], s2)) return false;
+    int Mx[2][2] = {{0, 0}, {0, 0}};
+    for (int k = 0; k < d - 1; ++k) {
+      Mx[k][0] = (int)std::lround(0.5 * (s1[k] - s0[k]));
+      if (d == 3) Mx[k][1] = (int)std::lround(0.5 * (s2[k] - s0[k]));
+    }
+    // every corner must map through M with zero offset
+    for (int c = 0; c < ncf; ++c) {
+      double sl[2], sr[2] = {0, 0};
+      for (int q = 0; q < d - 1; ++q) sl[q] = ((c >> q) & 1) ? 1.0 : -1.0;
+      if (!pos(va[c], sr)) return false;
+      for (int k = 0; k < d - 1; ++k) {
+        double sm = 0.0;
+        for (int q = 0; q < d - 1; ++q) sm += Mx[k][q] * sl[q];
+        if (sm != sr[k]) return false;
+      }
+    }
+    int swap = 0, f0 = 0, f1 = 0;
+    if (d == 2) {
+      f0 = Mx[0][0] < 0;
+    } else if (Mx[0][0] != 0) {
+      f0 = Mx[0][0] < 0;
+      f1 = Mx[1][1] < 0;
+    } else {
+      swap = 1;
+      f0 = Mx[0][1] < 0;
+      f1 = Mx[1][0] < 0;
+    }
+    code = (uint8_t)(lf2 | (swap << 3) | (f0 << 4) | (f1 << 5));
+    return true;
+  };
+  for (auto& pr : pairs) {
+    int e1 = pr.first.first, l1 = pr.first.second, e2 = pr.second.first, l2 = pr.second.second;
+    uint8_t c12, c21;
+    if (!code_of(e1, l1, e2, l2, c12) || !code_of(e2, l2, e1, l1, c21))
+      return fail(h, EG_ERR_MESH, "non-conforming face");
+    nbr[(size_t)e1 * nf + l1] = e2;
+    ncode[(size_t)e1 * nf + l1] = c12;
+    nbr[(size_t)e2 * nf + l2] = e1;
+    ncode[(size_t)e2 * nf + l2] = c21;
+  }
+  // geometry and basis
+  const int pm = h->pmax, Q = pm + 2, N = nmodes_of(d, pm), NT = N * (N + 1) / 2;
+  double gx[8], gw[8];
+  gauss_rule(Q, gx, gw);
+  Lpk.assign((size_t)ne * NT, 0.0);
+  Gpk.assign((size_t)ne * NT, 0.0);
+  hE.assign(ne, 0.0);
+  std::vector<double> vol(ne, 0.0);
+  int nq = 1;
+  for (int r = 0; r < d; ++r) nq *= Q;
+  // phi at the volume points (element independent)
+  std::vector<double> phi((size_t)nq * N);
+  for (int q = 0; q < nq; ++q) {
+    int iq[3] = {0, 0, 0}, t = q;
+    for (int r = 0; r < d; ++r) { iq[r] = t % Q; t /= Q; }
+    for (int k = 0; k < N; ++k) {
+      double v = 1.0;
+      for (int r = 0; r < d; ++r) {
+        double L[10], dL[10];
+        legendre_values(std::max(pm, 1), gx[iq[r]], L, dL);
+        v *= L[h->modes[k][r]];
+      }
+      phi[(size_t)q * N + k] = v;
+    }
+  }
+  int bad = 0;
+  for (int e = 0; e < ne; ++e) {
+    const double* X = &xv[(size_t)e * nc * d];
+    std::vector<double> G((size_t)N * N, 0.0), L((size_t)N * N, 0.0);
+    double V = 0.0, S = 0.0;
+    for (int q = 0; q < nq; ++q) {
+      int iq[3] = {0, 0, 0}, t = q;
+      double xi[3], wq = 1.0;
+      for (int r = 0; r < d; ++r) { iq[r] = t % Q; t /= Q; xi[r] = gx[iq[r]]; wq *= gw[iq[r]]; }
+      double c[3][3];
+      double det = host_geom(d, X, xi, c);
+      if (!(det > 0.0)) bad++;
+      V += wq * det;
+      const double* ph = &phi[(size_t)q * N];
+      for (int i = 0; i < N; ++i)
+        for (int j = 0; j <= i; ++j) G[(size_t)i * N + j] += wq * det * ph[i] * ph[j];
+    }
+    for (int k = 0; k < nc; ++k) {  // corners
+      double xi[3];
+      for (int r = 0; r < d; ++r) xi[r] = ((k >> r) & 1) ? 1.0 : -1.0;
+      double c[3][3];
+      if (!(host_geom(d, X, xi, c) > 0.0)) bad++;
+    }
+    for (int lf = 0; lf < nf; ++lf) {
+      int r = lf / 2, ta[2], kk = 0;
+      for (int a = 0; a < d; ++a) if (a != r) ta[kk++] = a;
+      int nqf = nq / Q;
+      for (int k = 0; k < nqf; ++k) {
+        double xi[3], wk = 1.0;
+        xi[r] = (lf & 1) ? 1.0 : -1.0;
+        int t = k;
+        for (int q2 = 0; q2 < d - 1; ++q2) { xi[ta[q2]] = gx[t % Q]; wk *= gw[t % Q]; t /= Q; }
+        double c[3][3];
+        host_geom(d, X, xi, c);
+        double a2 = 0.0;
+        for (int a = 0; a < d; ++a) a2 += c[r][a] * c[r][a];
+        S += wk * std::sqrt(a2);
+      }
+    }
+    vol[e] = V;
+    hE[e] = 2.0 * d * V / S;
+    // Cholesky G = L L^T
+    for (int j = 0; j < N; ++j) {
+      double sjj = G[(size_t)j * N + j];
+      for (int k = 0; k < j; ++k) sjj -= L[(size_t)j * N + k] * L[(size_t)j * N + k];
+      if (!(sjj > 0.0)) { bad++; sjj = 1.0; }
+      L[(size_t)j * N + j] = std::sqrt(sjj);
+      for (int i = j + 1; i < N; ++i) {
+        double sij = G[(size_t)i * N + j];
+        for (int k = 0; k < j; ++k) sij -= L[(size_t)i * N + k] * L[(size_t)j * N + k];
+        L[(size_t)i * N + j] = sij / L[(size_t)j * N + j];
+      }
+    }
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j <= i; ++j) {
+        Lpk[(size_t)e * NT + i * (i + 1) / 2 + j] = L[(size_t)i * N + j];
+        Gpk[(size_t)e * NT + i * (i + 1) / 2 + j] = G[(size_t)i * N + j];
+      }
+  }
+  if (bad) return fail(h, EG_ERR_MESH, "inverted element or singular mass matrix");
+  omega = 0.0;
+  for (int e = 0; e < ne; ++e) omega += vol[e];
+  return EG_OK;
+}
+
+eg_status sync_status(eg_handle* h) {
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  return EG_OK;
+}
+
+int NB(const eg_handle* h, int p) { return h->M.V * nmodes_of(h->M.d, p); }
+
+double cfl_ramp(double cfl_max, double rn, double rref, int n, int pmax) {
+  double a = (rn > 0.0) ? rref / rn : HUGE_VAL;
+  double b = 1.0 + (n - 1.0) / (2.0 * pmax + 1.0);
+  return std::min(cfl_max, std::max(a, b));
+}
+
+// EXP1 on the phi-coordinate p = 0 state ut0 with optional forcing ft0.
+eg_status run_exp1(eg_handle* h, double cfl, double* ut0, const double* ft0) {
+  const DevMesh& M = h->M;
+  HIPCHK(h, eg::launch_p0_setup(M, ut0, ft0, h->pmax, cfl, 1, h->u0, h->b0, h->Ad, h->Ao, h->dt0, h->st));
+  HIPCHK(h, eg::launch_exp1_krylov(M, h->m, h->nblk_arn, h->Ad, h->Ao, h->b0, h->Vb, h->H, h->part1, h->part2,
+                                   h->info, h->y, h->dfail, h->st));
+  HIPCHK(h, eg::launch_exp1_update(M, h->Vb, h->y, h->info, h->u0, ut0, h->st));
+  return EG_OK;
+}
+
+// One PRK step at level p on ut[p] with forcing ft (may be null); rt[p] must
+// hold the stage-1 residual R_p(ut) + ft.
+eg_status run_prk(eg_handle* h, int p, double cfl, const double* ft) {
+  const DevMesh& M = h->M;
+  const int N = nmodes_of(M.d, p), n = NB(h, p);
+  const size_t K = (size_t)M.ne * n;
+  HIPCHK(h, eg::launch_timestep(M, p, N, cfl, 1.0, h->ut[p], h->dtau, h->st));
+  HIPCHK(h, eg::launch_jacobian(M, h->tabs[p], p, h->ut[p], h->dtau, h->F[p], h->perm[p], h->dfail, true, h->st));
+  HIPCHK(h, eg::launch_copy(h->ut[p], h->un[p], K, h->st));
+  for (int k = 1; k <= h->s; ++k) {
+    if (k > 1) HIPCHK(h, eg::launch_residual(M, h->tabs[p], p, h->ut[p], ft, h->rt[p], h->st));
+    const double beta = 1.0 / (h->s - k + 1.0);
+    HIPCHK(h, eg::launch_prk_stage(M, n, h->F[p], h->perm[p], h->rt[p], nullptr, h->un[p], h->ut[p], beta, h->st));
+  }
+  return EG_OK;
+}
+
+// V-cycle below level p (Section 2.4): PRK, restriction with FAS forcing,
+// recursion, prolongation of the coarse error.  Requires rt[p] = R_p + f_p.
+eg_status vc_rec(eg_handle* h, int p, double cfl) {
+  const DevMesh& M = h->M;
+  const double* fp = (p == h->pmax) ? nullptr : h->ft[p];
+  if (p == 0) return run_exp1(h, cfl, h->ut[0], fp);
+  ECHK(run_prk(h, p, cfl, fp));
+  const int N = nmodes_of(M.d, p), Nc = nmodes_of(M.d, p - 1), rows = M.ne * M.V;
+  HIPCHK(h, eg::launch_residual(M, h->tabs[p], p, h->ut[p], fp, h->rt[p], h->st));
+  HIPCHK(h, eg::launch_restrict(M, p, h->ut[p], h->ut[p - 1], h->uc0[p - 1], h->st));
+  if (p - 1 >= 1) {
+    HIPCHK(h, eg::launch_residual(M, h->tabs[p - 1], p - 1, h->ut[p - 1], nullptr, h->rt[p - 1], h->st));
+    HIPCHK(h, eg::launch_fas(N, Nc, rows, h->rt[p], h->rt[p - 1], h->ft[p - 1], h->st));
+  } else {
+    // the p = 0 forcing needs R_0(v0): evaluate it with the residual kernel
+    HIPCHK(h, eg::launch_residual(M, h->tabs[0], 0, h->ut[0], nullptr, h->rt[0], h->st));
+    HIPCHK(h, eg::launch_fas(N, Nc, rows, h->rt[p], h->rt[0], h->ft[0], h->st));
+  }
+  ECHK(vc_rec(h, p - 1, cfl));
+  HIPCHK(h, eg::launch_prolong(N, Nc, rows, h->ut[p], h->ut[p - 1], h->uc0[p - 1], h->st));
+  return EG_OK;
+}
+
+// Residual and norm of the phi-coordinate state ut[pmax] -> host value.
+eg_status entry_norm(eg_handle* h, double* rn) {
+  const DevMesh& M = h->M;
+  const int p = h->pmax, N = nmodes_of(M.d, p);
+  HIPCHK(h, eg::launch_residual(M, h->tabs[p], p, h->ut[p], nullptr, h->rt[p], h->st));
+  HIPCHK(h, eg::launch_norm(M, N, h->rt[p], h->npart, h->nout, h->st));
+  HIPCHK(h, hipMemcpyAsync(h->hpin, h->nout, sizeof(double), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(h, hipMemcpyAsync(h->hpin + 1, h->dfail, sizeof(int), hipMemcpyDeviceToHost, h->st));
+  ECHK(sync_status(h));
+  *rn = h->hpin[0];
+  int fl = 0;
+  std::memcpy(&fl, h->hpin + 1, sizeof(int));
+  if (fl) return fail(h, EG_ERR_DIVERGED, "singular pivot in a block factorisation or in phi_1");
+  return EG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stream, eg_handle** out) {
+  if (!out) return EG_ERR_ARG;
+  *out = nullptr;
+  if (!mesh || !prm || !mesh->xyz || !mesh->elem_vert || !mesh->bface_tag) return EG_ERR_ARG;
+  if ((mesh->dim != 2 && mesh->dim != 3) || mesh->n_vert <= 0 || mesh->n_elem <= 0) return EG_ERR_ARG;
+  eg_handle* h = new (std::nothrow) eg_handle;
+  if (!h) return EG_ERR_ALLOC;
+  const int d = mesh->dim;
+  const int pmax_lim = (d == 2) ? 4 : 2;
+  if (prm->p_max < 0 || prm->p_max > pmax_lim || prm->rk_stages < 1 || prm->krylov_m < 1 || prm->krylov_m > 48 ||
+      !(prm->cfl_max > 0.0) || !(prm->gamma > 1.0) || !(prm->mach >= 0.0)) {
+    h->err = "invalid parameters (p_max, rk_stages, krylov_m 1..48, cfl_max, gamma or mach)";
+    *out = h;
+    return EG_ERR_ARG;
+  }
+  h->pmax = prm->p_max;
+  h->s = prm->rk_stages;
+  h->m = prm->krylov_m;
+  h->relr = prm->relative_ramp;
+  h->cfl_max = prm->cfl_max;
+  h->st = static_cast<hipStream_t>(hip_stream);
+  h->modes = hier_modes(d, h->pmax);
+  DevMesh& M = h->M;
+  M.d = d;
+  M.V = d + 2;
+  M.ne = mesh->n_elem;
+  M.NF = 2 * d;
+  M.NC = 1 << d;
+  const int N = nmodes_of(d, h->pmax);
+  M.NT = N * (N + 1) / 2;
+  M.gas.g = prm->gamma;
+  {
+    const double al = prm->alpha_deg * M_PI / 180.0, be = prm->beta_deg * M_PI / 180.0;
+    double v[3] = {prm->mach * std::cos(al) * std::cos(be), prm->mach * std::sin(al) * std::cos(be),
+                   prm->mach * std::sin(be)};
+    double ke = 0.0;
+    M.gas.Uinf[0] = 1.0;
+    for (int a = 0; a < d; ++a) { M.gas.Uinf[1 + a] = v[a]; ke += v[a] * v[a]; }
+    M.gas.Uinf[d + 1] = 1.0 / (prm->gamma * (prm->gamma - 1.0)) + 0.5 * ke;
+  }
+  std::vector<double> xv, Lpk, Gpk, hE;
+  std::vector<int> nbr;
+  std::vector<uint8_t> ncode;
+  double omega = 0.0;
+  eg_status s = setup_mesh(h, mesh, xv, nbr, ncode, Lpk, Gpk, hE, omega);
+  if (s != EG_OK) { *out = h; return s; }
+  M.omega = omega;
+  h->tabs.resize(h->pmax + 1);
+  for (int p = 0; p <= h->pmax; ++p) fill_tabdata(h->tabs[p], d, p, h->modes);
+  // device allocations
+  const int ne = M.ne, V = M.V;
+#define AL(ptr, cnt)                                  \
+  do {                                                \
+    eg_status a_ = dalloc(h, &(ptr), (size_t)(cnt));  \
+    if (a_ != EG_OK) { *out = h; return a_; }         \
+  } while (0)
+  AL(M.xv, xv.size());
+  AL(M.nbr, nbr.size());
+  AL(M.ncode, ncode.size());
+  AL(M.Lpk, Lpk.size());
+  AL(M.Gpk, Gpk.size());
+  AL(M.hE, hE.size());
+  AL(M.g2x, 2);
+  AL(M.g2w, 2);
+  for (int p = 0; p <= h->pmax; ++p) {
+    const size_t K = (size_t)ne * V * nmodes_of(d, p);
+    AL(h->ut[p], K);
+    AL(h->un[p], K);
+    AL(h->rt[p], K);
+    AL(h->ft[p], K);
+    AL(h->uc0[p], K);
+    if (p >= 1) {
+      const size_t n = (size_t)V * nmodes_of(d, p);
+      if (eg::jacobian_supported(d, p)) {
+        AL(h->F[p], (size_t)ne * n * n);
+        AL(h->perm[p], (size_t)ne * n);
+      }
+    }
+  }
+  const size_t Kmax = (size_t)ne * V * N;
+  AL(h->dtau, ne);
+  AL(h->tmp, Kmax);
+  AL(h->tmp2, Kmax);
+  const size_t K0 = (size_t)ne * V;
+  AL(h->u0, K0);
+  AL(h->b0, K0);
+  AL(h->Ad, (size_t)ne * V * V);
+  AL(h->Ao, (size_t)ne * M.NF * V * V);
+  AL(h->dt0, ne);
+  AL(h->Vb, (size_t)(h->m + 1) * K0);
+  AL(h->H, (size_t)(h->m + 1) * h->m);
+  h->nblk_arn = eg::arnoldi_max_blocks(d);
+  {
+    int want = (int)((K0 + 255) / 256);
+    if (h->nblk_arn <= 0) { h->err = "cooperative launch not available"; *out = h; return EG_ERR_HIP; }
+    h->nblk_arn = std::max(1, std::min(h->nblk_arn, want));
+  }
+  AL(h->part1, (size_t)h->nblk_arn * (h->m + 2));
+  AL(h->part2, (size_t)h->nblk_arn * (h->m + 2));
+  AL(h->info, 2);
+  AL(h->y, h->m + 1);
+  AL(h->npart, (size_t)(ne + 255) / 256 + 1);
+  AL(h->nout, 1);
+  AL(h->dfail, 1);
+#undef AL
+  {
+    hipError_t e = hipHostMalloc((void**)&h->hpin, 64, hipHostMallocDefault);
+    if (e != hipSuccess) { h->hpin = nullptr; h->err = "hipHostMalloc failed"; *out = h; return EG_ERR_ALLOC; }
+  }
+  // the p = 0 face rule is the 2-point rule of the order-0 tables
+  double g2x[2] = {h->tabs[0].x[0], h->tabs[0].x[1]}, g2w[2] = {h->tabs[0].w[0], h->tabs[0].w[1]};
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemcpy(M.xv, xv.data(), xv.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(M.nbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(M.ncode, ncode.data(), ncode.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(M.Lpk, Lpk.data(), Lpk.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(M.Gpk, Gpk.data(), Gpk.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(M.hE, hE.data(), hE.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(M.g2x, g2x, 16, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(M.g2w, g2w, 16, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(h->dfail, 0, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(h->info, 0, 2 * sizeof(double));
+  if (e != hipSuccess) { *out = h; return hipfail(h, e, "upload"); }
+  *out = h;
+  return EG_OK;
+}
+
+void eg_free(eg_handle* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->st);
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->hpin) (void)hipHostFree(h->hpin);
+  delete h;
+}
+
+const char* eg_last_error(const eg_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+eg_status eg_sizes(const eg_handle* h, int p, int* n_elem, int* n_modes, int* n_vars) {
+  if (!h || p < 0 || p > h->pmax) return EG_ERR_ARG;
+  if (n_elem) *n_elem = h->M.ne;
+  if (n_modes) *n_modes = nmodes_of(h->M.d, p);
+  if (n_vars) *n_vars = h->M.V;
+  return EG_OK;
+}
+
+eg_status eg_set_freestream(eg_handle* h, int p, double* u_dev) {
+  if (!h || !u_dev) return EG_ERR_ARG;
+  if (p < 0 || p > h->pmax) return fail(h, EG_ERR_ARG, "order out of range");
+  HIPCHK(h, eg::launch_freestream(h->M, nmodes_of(h->M.d, p), u_dev, h->st));
+  return EG_OK;
+}
+
+eg_status eg_residual(eg_handle* h, int p, const double* u_dev, double* r_dev) {
+  if (!h || !u_dev || !r_dev) return EG_ERR_ARG;
+  if (p < 0 || p > h->pmax) return fail(h, EG_ERR_ARG, "order out of range");
+  const int N = nmodes_of(h->M.d, p);
+  HIPCHK(h, eg::launch_basis(h->M, N, u_dev, h->tmp, 0, h->st));
+  HIPCHK(h, eg::launch_residual(h->M, h->tabs[p], p, h->tmp, nullptr, h->tmp2, h->st));
+  HIPCHK(h, eg::launch_basis(h->M, N, h->tmp2, r_dev, 2, h->st));
+  return EG_OK;
+}
+
+eg_status eg_timestep(eg_handle* h, int p, int p_level, double cfl, const double* u_dev, double* dtau_dev) {
+  if (!h || !u_dev || !dtau_dev) return EG_ERR_ARG;
+  if (p < 0 || p_level < 0 || p_level > h->pmax) return fail(h, EG_ERR_ARG, "order out of range");
+  const int N = nmodes_of(h->M.d, p_level);
+  HIPCHK(h, eg::launch_basis(h->M, N, u_dev, h->tmp, 0, h->st));
+  HIPCHK(h, eg::launch_timestep(h->M, p, N, cfl, 1.0, h->tmp, dtau_dev, h->st));
+  return EG_OK;
+}
+
+eg_status eg_element_jacobian(eg_handle* h, int p, const double* u_dev, double* D_dev) {
+  if (!h || !u_dev || !D_dev) return EG_ERR_ARG;
+  if (p < 1 || p > h->pmax) return fail(h, EG_ERR_ARG, "order out of range (p >= 1)");
+  if (!eg::jacobian_supported(h->M.d, p)) return fail(h, EG_ERR_UNSUPPORTED, "element block too large");
+  const int N = nmodes_of(h->M.d, p);
+  HIPCHK(h, eg::launch_basis(h->M, N, u_dev, h->tmp, 0, h->st));
+  HIPCHK(h, eg::launch_jacobian(h->M, h->tabs[p], p, h->tmp, h->dtau, D_dev, nullptr, h->dfail, false, h->st));
+  HIPCHK(h, eg::launch_jac_to_psi(h->M, N, D_dev, h->st));
+  return EG_OK;
+}
+
+eg_status eg_prk_step(eg_handle* h, int p, double cfl, double* u_dev, const double* f_dev) {
+  if (!h || !u_dev) return EG_ERR_ARG;
+  if (p < 1 || p > h->pmax) return fail(h, EG_ERR_ARG, "order out of range (p >= 1)");
+  if (!eg::jacobian_supported(h->M.d, p)) return fail(h, EG_ERR_UNSUPPORTED, "element block too large");
+  const int N = nmodes_of(h->M.d, p);
+  HIPCHK(h, eg::launch_basis(h->M, N, u_dev, h->ut[p], 0, h->st));
+  const double* ft = nullptr;
+  if (f_dev) {
+    HIPCHK(h, eg::launch_basis(h->M, N, f_dev, h->tmp, 3, h->st));
+    ft = h->tmp;
+  }
+  HIPCHK(h, eg::launch_residual(h->M, h->tabs[p], p, h->ut[p], ft, h->rt[p], h->st));
+  ECHK(run_prk(h, p, cfl, ft));
+  HIPCHK(h, eg::launch_basis(h->M, N, h->ut[p], u_dev, 1, h->st));
+  return EG_OK;
+}
+
+eg_status eg_jacobian_p0(eg_handle* h, const double* u0_dev, double* diag_dev, double* off_dev, int32_t* nbr_dev) {
+  if (!h || !u0_dev || !diag_dev || !off_dev) return EG_ERR_ARG;
+  HIPCHK(h, eg::launch_basis(h->M, 1, u0_dev, h->tmp, 0, h->st));
+  HIPCHK(h, eg::launch_p0_setup(h->M, h->tmp, nullptr, h->pmax, 1.0, 0, h->u0, h->b0, diag_dev, off_dev, h->dt0,
+                                h->st));
+  if (nbr_dev) {
+    HIPCHK(h, hipMemcpyAsync(nbr_dev, h->M.nbr, sizeof(int) * h->M.ne * h->M.NF, hipMemcpyDeviceToDevice, h->st));
+  }
+  return EG_OK;
+}
+
+eg_status eg_exp1_step(eg_handle* h, double cfl, double* u0_dev, const double* f0_dev, int* m_used_host) {
+  if (!h || !u0_dev) return EG_ERR_ARG;
+  HIPCHK(h, eg::launch_basis(h->M, 1, u0_dev, h->ut[0], 0, h->st));
+  const double* ft = nullptr;
+  if (f0_dev) {
+    HIPCHK(h, eg::launch_basis(h->M, 1, f0_dev, h->tmp, 3, h->st));
+    ft = h->tmp;
+  }
+  ECHK(run_exp1(h, cfl, h->ut[0], ft));
+  HIPCHK(h, eg::launch_basis(h->M, 1, h->ut[0], u0_dev, 1, h->st));
+  if (m_used_host) {
+    HIPCHK(h, hipMemcpyAsync(h->hpin, h->info, sizeof(double), hipMemcpyDeviceToHost, h->st));
+    ECHK(sync_status(h));
+    *m_used_host = (int)h->hpin[0];
+  }
+  return EG_OK;
+}
+
+eg_status eg_rnorm(eg_handle* h, const double* r_dev, double* rn_host) {
+  if (!h || !r_dev || !rn_host) return EG_ERR_ARG;
+  const int N = nmodes_of(h->M.d, h->pmax);
+  HIPCHK(h, eg::launch_basis(h->M, N, r_dev, h->tmp, 3, h->st));
+  HIPCHK(h, eg::launch_norm(h->M, N, h->tmp, h->npart, h->nout, h->st));
+  HIPCHK(h, hipMemcpyAsync(h->hpin, h->nout, sizeof(double), hipMemcpyDeviceToHost, h->st));
+  ECHK(sync_status(h));
+  *rn_host = h->hpin[0];
+  return EG_OK;
+}
+
+eg_status eg_vcycle(eg_handle* h, double* u_dev, int n, double rref, double* rn_host, double* cfl_host) {
+  if (!h || !u_dev || !rn_host || n < 1) return EG_ERR_ARG;
+  if (!eg::jacobian_supported(h->M.d, h->pmax) && h->pmax > 0)
+    return fail(h, EG_ERR_UNSUPPORTED, "element block too large");
+  const int N = nmodes_of(h->M.d, h->pmax);
+  HIPCHK(h, eg::launch_basis(h->M, N, u_dev, h->ut[h->pmax], 0, h->st));
+  double rn = 0.0;
+  ECHK(entry_norm(h, &rn));
+  *rn_host = rn;
+  if (!std::isfinite(rn)) return fail(h, EG_ERR_DIVERGED, "non-finite residual norm");
+  const double cfl = cfl_ramp(h->cfl_max, rn, rref > 0.0 ? rref : rn, n, h->pmax);
+  if (cfl_host) *cfl_host = cfl;
+  ECHK(vc_rec(h, h->pmax, cfl));
+  HIPCHK(h, eg::launch_basis(h->M, N, h->ut[h->pmax], u_dev, 1, h->st));
+  ECHK(sync_status(h));
+  return EG_OK;
+}
+
+eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
+                          int* n_cycles_host) {
+  if (!h || !u_dev || !hist_host || !n_cycles_host || max_cycles < 0) return EG_ERR_ARG;
+  if (!eg::jacobian_supported(h->M.d, h->pmax) && h->pmax > 0)
+    return fail(h, EG_ERR_UNSUPPORTED, "element block too large");
+  const int N = nmodes_of(h->M.d, h->pmax);
+  HIPCHK(h, eg::launch_basis(h->M, N, u_dev, h->ut[h->pmax], 0, h->st));
+  double r1 = 0.0;
+  eg_status st = EG_OK;
+  for (int n = 1;; ++n) {
+    double rn = 0.0;
+    st = entry_norm(h, &rn);
+    if (st != EG_OK) break;
+    hist_host[n - 1] = rn;
+    *n_cycles_host = n - 1;
+    if (n == 1) r1 = rn;
+    if (!std::isfinite(rn)) { st = fail(h, EG_ERR_DIVERGED, "non-finite residual norm"); break; }
+    if (rn <= drop_tol * r1) break;
+    if (n - 1 == max_cycles) { st = fail(h, EG_ERR_NOT_CONVERGED, "max_cycles reached"); break; }
+    const double cfl = cfl_ramp(h->cfl_max, rn, h->relr ? r1 : 1.0, n, h->pmax);
+    st = vc_rec(h, h->pmax, cfl);
+    if (st != EG_OK) break;
+  }
+  hipError_t e = eg::launch_basis(h->M, N, h->ut[h->pmax], u_dev, 1, h->st);
+  if (e != hipSuccess && st == EG_OK) st = hipfail(h, e, "basis");
+  hipError_t e2 = hipStreamSynchronize(h->st);
+  if (e2 != hipSuccess && st == EG_OK) st = hipfail(h, e2, "sync");
+  return st;
+}
+
+}  // extern "C"

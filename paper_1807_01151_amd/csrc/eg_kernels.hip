@@ -1,0 +1,1527 @@
+// HIP kernels of the eMG hot path for gfx950 (MI355X), FP64.
+//
+// State representation.  The paper's basis is psi = T phi per element
+// (Section 3.2, eq. (basis)): reference tensor-Legendre phi orthonormalised in
+// the physical inner product, T = L^{-1} with G = L L^T the element mass
+// matrix of phi.  The kernels keep the state in the phi coordinates
+// ut = T^T u (= L^{-T} u), an exact change of variables:
+//   residual        Rt(ut) = T^{-1} R(u)            (no T inside the kernel)
+//   element block   Pt = T^{-1} P T^{-T} = G/dtau - dRt/dut
+//   PRK update      ut^(k) = ut^n + beta_k Pt^{-1} [Rt + ft],  ft = T^{-1} f
+// so the smoother never reads T; the restriction of the solution, the norm
+// and the conversions at the C ABI use the Cholesky factor L.  The p = 0
+// level (EXP1) runs in the paper's psi coordinates, where the Euclidean inner
+// product of the Arnoldi process is the L2 inner product.
+//
+// Layouts (all FP64 unless noted):
+//   level-p vector   [E][V][N_p], hierarchical mode order (leading slices)
+//   vertices         [E][2^D][D]
+//   neighbour        int32 [E][2D]: element index, NB_WALL or NB_FAR
+//   face code        uint8 [E][2D]: neighbour face | swap<<3 | flip0<<4 | flip1<<5
+//   Cholesky / mass  packed lower triangle [E][NT], NT = N(N+1)/2 of p_max
+//   block factors    [E][n][n] column-major LU (unit L), perm int32 [E][n]
+
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include "eg_common.h"
+#include "eg_launch.h"
+#include "eg_physics.h"
+
+namespace cg = cooperative_groups;
+
+namespace eg {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+// Multilinear element map: the vectors c[r] with c[r] . (dx/dxi_r') = det
+// delta_rr', i.e. det * grad_x = sum_r c[r] d/dxi_r; (2s-1) c[r] is the scaled
+// outward normal of face (r, s).
+template <int D>
+__device__ __forceinline__ void geom(const double* X, const double* xi, double c[D][D], double& det) {
+  double t[D][D];
+#pragma unroll
+  for (int r = 0; r < D; ++r)
+#pragma unroll
+    for (int a = 0; a < D; ++a) t[r][a] = 0.0;
+#pragma unroll
+  for (int k = 0; k < (1 << D); ++k) {
+    double g[D];
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      double v = 1.0;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        double s = ((k >> q) & 1) ? 1.0 : -1.0;
+        v *= (q == r) ? 0.5 * s : 0.5 * (1.0 + s * xi[q]);
+      }
+      g[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int a = 0; a < D; ++a) t[r][a] += g[r] * X[k * D + a];
+  }
+  if constexpr (D == 2) {
+    c[0][0] = t[1][1]; c[0][1] = -t[1][0];
+    c[1][0] = -t[0][1]; c[1][1] = t[0][0];
+    det = t[0][0] * t[1][1] - t[0][1] * t[1][0];
+  } else {
+    c[0][0] = t[1][1] * t[2][2] - t[1][2] * t[2][1];
+    c[0][1] = t[1][2] * t[2][0] - t[1][0] * t[2][2];
+    c[0][2] = t[1][0] * t[2][1] - t[1][1] * t[2][0];
+    c[1][0] = t[2][1] * t[0][2] - t[2][2] * t[0][1];
+    c[1][1] = t[2][2] * t[0][0] - t[2][0] * t[0][2];
+    c[1][2] = t[2][0] * t[0][1] - t[2][1] * t[0][0];
+    c[2][0] = t[0][1] * t[1][2] - t[0][2] * t[1][1];
+    c[2][1] = t[0][2] * t[1][0] - t[0][0] * t[1][2];
+    c[2][2] = t[0][0] * t[1][1] - t[0][1] * t[1][0];
+    det = t[0][0] * c[0][0] + t[0][1] * c[0][1] + t[0][2] * c[0][2];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void face_axes(int lf, int* ta) {
+  int r = lf >> 1, k = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+    if (a != r) ta[k++] = a;
+}
+
+// Point index on the neighbour's face seen from this element's face point
+// with tangential Gauss indices ik.
+template <int D, int Q>
+__device__ __forceinline__ void nb_face_index(int code, const int* ik, int* jk) {
+  if constexpr (D == 2) {
+    jk[0] = ((code >> 4) & 1) ? Q - 1 - ik[0] : ik[0];
+  } else {
+    int a = ((code >> 3) & 1) ? ik[1] : ik[0];
+    int b = ((code >> 3) & 1) ? ik[0] : ik[1];
+    jk[0] = ((code >> 4) & 1) ? Q - 1 - a : a;
+    jk[1] = ((code >> 5) & 1) ? Q - 1 - b : b;
+  }
+}
+
+// phi_k at face lf, tangential Gauss indices ik.
+template <int D, int P>
+__device__ __forceinline__ double phi_face(const Tab<D, P>& t, int k, int lf, const int* ta, const int* ik) {
+  double v = t.Lb[t.m[k][lf >> 1]][lf & 1];
+#pragma unroll
+  for (int q = 0; q < D - 1; ++q) v *= t.L[t.m[k][ta[q]]][ik[q]];
+  return v;
+}
+
+template <int D, int P>
+__device__ __forceinline__ double phi_vol(const Tab<D, P>& t, int k, const int* iq) {
+  double v = t.L[t.m[k][0]][iq[0]];
+#pragma unroll
+  for (int r = 1; r < D; ++r) v *= t.L[t.m[k][r]][iq[r]];
+  return v;
+}
+
+template <int D, int P>
+__device__ __forceinline__ double dphi_vol(const Tab<D, P>& t, int k, const int* iq, int r) {
+  double v = 1.0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) v *= (q == r) ? t.dL[t.m[k][q]][iq[q]] : t.L[t.m[k][q]][iq[q]];
+  return v;
+}
+
+template <int D, int P>
+__device__ __forceinline__ void copy_tab(Tab<D, P>& dst, const Tab<D, P>& src) {
+  const int n = sizeof(Tab<D, P>) / 4;
+  const uint32_t* s = reinterpret_cast<const uint32_t*>(&src);
+  uint32_t* d = reinterpret_cast<uint32_t*>(&dst);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// DG residual (Section 3.1, eq. (euler3)) in the phi coordinates:
+//   Rt_{v,i} = sum_q w_q sum_r d_r phi_i(q) [F_v(U_q) . c_r(q)]
+//            - sum_faces sum_k w_k |n dsigma| phi_i F~_v(U_own, U_nb; n^)
+// A block handles EB elements: (1) stage ut of the tile in LDS, (2) one
+// thread per volume point evaluates U, the flux and the contravariant flux,
+// (3) one thread per face point evaluates both traces (the neighbour's from
+// global memory at its matching Gauss point) and the Rusanov flux, (4) one
+// thread per output (element, var, mode) projects onto the test functions.
+// Optional: add a forcing vector.
+// ---------------------------------------------------------------------------
+template <int D, int P, int EB>
+__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut, const double* __restrict__ fadd,
+                                                  double* __restrict__ rt, const double* __restrict__ xv,
+                                                  const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
+                                                  int ne, Tab<D, P> tab, Gas gas) {
+  using C = Cfg<D, P>;
+  constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, NC = C::NC;
+  __shared__ double s_u[EB * V * N];
+  __shared__ double s_fc[EB * QV * V * D];
+  __shared__ double s_ff[EB * NF * QF * V];
+  __shared__ double s_x[EB * NC * D];
+  __shared__ Tab<D, P> t;
+  const int tid = threadIdx.x;
+  const int e0 = blockIdx.x * EB;
+  copy_tab(t, tab);
+  for (int i = tid; i < EB * V * N; i += blockDim.x) {
+    int e = e0 + i / (V * N);
+    s_u[i] = (e < ne) ? ut[(size_t)e0 * V * N + i] : 0.0;
+  }
+  for (int i = tid; i < EB * NC * D; i += blockDim.x) {
+    int e = e0 + i / (NC * D);
+    s_x[i] = (e < ne) ? xv[(size_t)e0 * NC * D + i] : 0.0;
+  }
+  __syncthreads();
+  // volume points
+  for (int it = tid; it < EB * QV; it += blockDim.x) {
+    const int el = it / QV, q = it % QV;
+    if (e0 + el >= ne) continue;
+    int iq[D];
+    double xi[D], wq = 1.0;
+    {
+      int r0 = q;
+#pragma unroll
+      for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; xi[r] = t.x[iq[r]]; wq *= t.w[iq[r]]; }
+    }
+    double U[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) U[v] = 0.0;
+    const double* su = &s_u[el * V * N];
+    for (int k = 0; k < N; ++k) {
+      double ph = phi_vol<D, P>(t, k, iq);
+#pragma unroll
+      for (int v = 0; v < V; ++v) U[v] += su[v * N + k] * ph;
+    }
+    double c[D][D], det;
+    geom<D>(&s_x[el * NC * D], xi, c, det);
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      double F[V];
+      flux_n<D>(U, c[r], F, gas.g);
+#pragma unroll
+      for (int v = 0; v < V; ++v) s_fc[((el * QV + q) * V + v) * D + r] = wq * F[v];
+    }
+  }
+  // face points
+  for (int it = tid; it < EB * NF * QF; it += blockDim.x) {
+    const int el = it / (NF * QF), lf = (it / QF) % NF, k = it % QF;
+    const int e = e0 + el;
+    if (e >= ne) continue;
+    int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1];
+    face_axes<D>(lf, ta);
+    double xi[D], wk = 1.0;
+    xi[lf >> 1] = (lf & 1) ? 1.0 : -1.0;
+    {
+      int r0 = k;
+#pragma unroll
+      for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; xi[ta[q]] = t.x[ik[q]]; wk *= t.w[ik[q]]; }
+    }
+    double UL[V], UR[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) UL[v] = 0.0;
+    const double* su = &s_u[el * V * N];
+    for (int j = 0; j < N; ++j) {
+      double ph = phi_face<D, P>(t, j, lf, ta, ik);
+#pragma unroll
+      for (int v = 0; v < V; ++v) UL[v] += su[v * N + j] * ph;
+    }
+    double c[D][D], det;
+    geom<D>(&s_x[el * NC * D], xi, c, det);
+    double nh[D], a2 = 0.0;
+    const double sg = (lf & 1) ? 1.0 : -1.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) { nh[a] = sg * c[lf >> 1][a]; a2 += nh[a] * nh[a]; }
+    const double area = sqrt(a2);
+#pragma unroll
+    for (int a = 0; a < D; ++a) nh[a] /= area;
+    const int nb = nbr[(size_t)e * NF + lf];
+    if (nb >= 0) {
+      const int code = ncode[(size_t)e * NF + lf];
+      const int lf2 = code & 7;
+      int ta2[D - 1 > 0 ? D - 1 : 1], jk[D - 1 > 0 ? D - 1 : 1];
+      face_axes<D>(lf2, ta2);
+      nb_face_index<D, Q>(code, ik, jk);
+#pragma unroll
+      for (int v = 0; v < V; ++v) UR[v] = 0.0;
+      const double* un = ut + (size_t)nb * V * N;
+      for (int j = 0; j < N; ++j) {
+        double ph = phi_face<D, P>(t, j, lf2, ta2, jk);
+#pragma unroll
+        for (int v = 0; v < V; ++v) UR[v] += un[v * N + j] * ph;
+      }
+    } else if (nb == NB_WALL) {
+      ghost_wall<D>(UL, nh, UR);
+    } else {
+      ghost_far<D>(UL, nh, UR, gas.Uinf, gas.g);
+    }
+    double F[V];
+    rusanov<D>(UL, UR, nh, F, gas.g);
+#pragma unroll
+    for (int v = 0; v < V; ++v) s_ff[((el * NF + lf) * QF + k) * V + v] = wk * area * F[v];
+  }
+  __syncthreads();
+  // projection onto the test functions
+  for (int it = tid; it < EB * V * N; it += blockDim.x) {
+    const int el = it / (V * N), v = (it / N) % V, i = it % N;
+    const int e = e0 + el;
+    if (e >= ne) continue;
+    double acc = 0.0;
+    for (int q = 0; q < QV; ++q) {
+      int iq[D];
+      int r0 = q;
+#pragma unroll
+      for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
+      const double* fc = &s_fc[((el * QV + q) * V + v) * D];
+#pragma unroll
+      for (int r = 0; r < D; ++r) acc += dphi_vol<D, P>(t, i, iq, r) * fc[r];
+    }
+    for (int lf = 0; lf < NF; ++lf) {
+      int ta[D - 1 > 0 ? D - 1 : 1];
+      face_axes<D>(lf, ta);
+      for (int k = 0; k < QF; ++k) {
+        int ik[D - 1 > 0 ? D - 1 : 1];
+        int r0 = k;
+#pragma unroll
+        for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
+        acc -= phi_face<D, P>(t, i, lf, ta, ik) * s_ff[((el * NF + lf) * QF + k) * V + v];
+      }
+    }
+    const size_t o = (size_t)e0 * V * N + it;
+    rt[o] = fadd ? acc + fadd[o] : acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Element Jacobian block in phi coordinates (Section 3.3, eq. (jac1)):
+//   Dt[(v,i),(w,j)] = sum_q w_q sum_r d_r phi_i phi_j [dF_v/dU_w . c_r]
+//                   - sum_faces sum_k w_k |n dsigma| phi_i phi_j dF~_v/dU_w,
+// with dF~/dU_own including the ghost chain rule on boundary faces, all flux
+// derivatives by forward-mode dual numbers.  FACTOR: form
+// Pt = G/dtau - Dt (the PRK block) in LDS, LU-factorise it with partial
+// pivoting and write the column-major factors and the row permutation; else
+// write Dt row-major.  One block per element.
+// ---------------------------------------------------------------------------
+template <int D, int P>
+constexpr int jac_lds_doubles() {
+  using C = Cfg<D, P>;
+  constexpr int ph1 = C::V * C::N + C::NC * D + C::QV * D * C::V * C::V + C::NF * C::QF * C::V * C::V;
+  constexpr int ph2 = C::NB * C::NB;
+  return (ph1 > ph2 ? ph1 : ph2);
+}
+
+template <int D, int P, bool FACTOR>
+__global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut, const double* __restrict__ xv,
+                                                  const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
+                                                  const double* __restrict__ Gpk, int NT, const double* __restrict__ dtau,
+                                                  double* __restrict__ out, int* __restrict__ perm, int* __restrict__ fail,
+                                                  int ne, Tab<D, P> tab, Gas gas) {
+  using C = Cfg<D, P>;
+  constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, NC = C::NC, n = C::NB;
+  constexpr int NP = N * N;
+  constexpr int ROUNDS = (NP + 255) / 256;
+  extern __shared__ double smem[];
+  __shared__ Tab<D, P> t;
+  __shared__ int s_perm[n];
+  __shared__ int s_piv;
+  double* s_u = smem;
+  double* s_x = s_u + V * N;
+  double* s_B = s_x + NC * D;
+  double* s_C = s_B + QV * D * V * V;
+  double* s_A = smem;  // phase 2 reuses the whole region
+  const int tid = threadIdx.x;
+  const int e = blockIdx.x;
+  if (e >= ne) return;
+  copy_tab(t, tab);
+  for (int i = tid; i < V * N; i += blockDim.x) s_u[i] = ut[(size_t)e * V * N + i];
+  for (int i = tid; i < NC * D; i += blockDim.x) s_x[i] = xv[(size_t)e * NC * D + i];
+  __syncthreads();
+  for (int q = tid; q < QV; q += blockDim.x) {
+    int iq[D];
+    double xi[D], wq = 1.0;
+    int r0 = q;
+#pragma unroll
+    for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; xi[r] = t.x[iq[r]]; wq *= t.w[iq[r]]; }
+    Dual<V> U[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      double s = 0.0;
+      for (int k = 0; k < N; ++k) s += s_u[v * N + k] * phi_vol<D, P>(t, k, iq);
+      U[v] = Dual<V>(s);
+      U[v].d[v] = 1.0;
+    }
+    double c[D][D], det;
+    geom<D>(s_x, xi, c, det);
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      Dual<V> F[V];
+      flux_n<D>(U, c[r], F, gas.g);
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int w = 0; w < V; ++w) s_B[((q * D + r) * V + v) * V + w] = wq * F[v].d[w];
+    }
+  }
+  for (int it = tid; it < NF * QF; it += blockDim.x) {
+    const int lf = it / QF, k = it % QF;
+    int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1];
+    face_axes<D>(lf, ta);
+    double xi[D], wk = 1.0;
+    xi[lf >> 1] = (lf & 1) ? 1.0 : -1.0;
+    int r0 = k;
+#pragma unroll
+    for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; xi[ta[q]] = t.x[ik[q]]; wk *= t.w[ik[q]]; }
+    Dual<V> UL[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      double s = 0.0;
+      for (int j = 0; j < N; ++j) s += s_u[v * N + j] * phi_face<D, P>(t, j, lf, ta, ik);
+      UL[v] = Dual<V>(s);
+      UL[v].d[v] = 1.0;
+    }
+    double c[D][D], det;
+    geom<D>(s_x, xi, c, det);
+    double nh[D], a2 = 0.0;
+    const double sg = (lf & 1) ? 1.0 : -1.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) { nh[a] = sg * c[lf >> 1][a]; a2 += nh[a] * nh[a]; }
+    const double area = sqrt(a2);
+#pragma unroll
+    for (int a = 0; a < D; ++a) nh[a] /= area;
+    Dual<V> F[V];
+    const int nb = nbr[(size_t)e * NF + lf];
+    if (nb >= 0) {
+      const int code = ncode[(size_t)e * NF + lf];
+      const int lf2 = code & 7;
+      int ta2[D - 1 > 0 ? D - 1 : 1], jk[D - 1 > 0 ? D - 1 : 1];
+      face_axes<D>(lf2, ta2);
+      nb_face_index<D, Q>(code, ik, jk);
+      double UR[V];
+      const double* un = ut + (size_t)nb * V * N;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        double s = 0.0;
+        for (int j = 0; j < N; ++j) s += un[v * N + j] * phi_face<D, P>(t, j, lf2, ta2, jk);
+        UR[v] = s;
+      }
+      rusanov<D>(UL, UR, nh, F, gas.g);
+    } else {
+      Dual<V> UG[V];
+      if (nb == NB_WALL) ghost_wall<D>(UL, nh, UG);
+      else ghost_far<D>(UL, nh, UG, gas.Uinf, gas.g);
+      rusanov<D>(UL, UG, nh, F, gas.g);
+    }
+    const double wa = wk * area;
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int w = 0; w < V; ++w) s_C[((lf * QF + k) * V + v) * V + w] = wa * F[v].d[w];
+  }
+  __syncthreads();
+  // contraction over quadrature points, one (i, j) mode pair per thread and round
+  double acc[ROUNDS][V * V];
+#pragma unroll
+  for (int rd = 0; rd < ROUNDS; ++rd) {
+#pragma unroll
+    for (int x = 0; x < V * V; ++x) acc[rd][x] = 0.0;
+    const int pr = rd * 256 + tid;
+    if (pr < NP) {
+      const int i = pr / N, j = pr % N;
+      for (int q = 0; q < QV; ++q) {
+        int iq[D];
+        int r0 = q;
+#pragma unroll
+        for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
+        const double pj = phi_vol<D, P>(t, j, iq);
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          const double a = dphi_vol<D, P>(t, i, iq, r) * pj;
+          const double* B = &s_B[(q * D + r) * V * V];
+#pragma unroll
+          for (int x = 0; x < V * V; ++x) acc[rd][x] += a * B[x];
+        }
+      }
+      for (int lf = 0; lf < NF; ++lf) {
+        int ta[D - 1 > 0 ? D - 1 : 1];
+        face_axes<D>(lf, ta);
+        for (int k = 0; k < QF; ++k) {
+          int ik[D - 1 > 0 ? D - 1 : 1];
+          int r0 = k;
+#pragma unroll
+          for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
+          const double a = phi_face<D, P>(t, i, lf, ta, ik) * phi_face<D, P>(t, j, lf, ta, ik);
+          const double* Cm = &s_C[(lf * QF + k) * V * V];
+#pragma unroll
+          for (int x = 0; x < V * V; ++x) acc[rd][x] -= a * Cm[x];
+        }
+      }
+    }
+  }
+  if constexpr (!FACTOR) {
+#pragma unroll
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      const int pr = rd * 256 + tid;
+      if (pr < NP) {
+        const int i = pr / N, j = pr % N;
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+          for (int w = 0; w < V; ++w) out[(size_t)e * n * n + (size_t)(v * N + i) * n + w * N + j] = acc[rd][v * V + w];
+      }
+    }
+    return;
+  } else {
+    __syncthreads();  // every thread is done with s_B / s_C
+    const double idt = 1.0 / dtau[e];
+    const double* G = Gpk + (size_t)e * NT;
+#pragma unroll
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+      const int pr = rd * 256 + tid;
+      if (pr < NP) {
+        const int i = pr / N, j = pr % N;
+        const double gij = (i >= j) ? G[i * (i + 1) / 2 + j] : G[j * (j + 1) / 2 + i];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+          for (int w = 0; w < V; ++w)
+            s_A[(v * N + i) * n + w * N + j] = ((v == w) ? gij * idt : 0.0) - acc[rd][v * V + w];
+      }
+    }
+    for (int i = tid; i < n; i += blockDim.x) s_perm[i] = i;
+    __syncthreads();
+    // right-looking LU with partial pivoting
+    for (int k = 0; k < n; ++k) {
+      if (tid < 64) {
+        double best = -1.0;
+        int bi = k;
+        for (int i = k + tid; i < n; i += 64) {
+          double a = fabs(s_A[i * n + k]);
+          if (a > best) { best = a; bi = i; }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          double ob = __shfl_xor(best, o, 64);
+          int oi = __shfl_xor(bi, o, 64);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (tid == 0) {
+          s_piv = bi;
+          if (!(best > 0.0)) atomicOr(fail, 1);
+        }
+      }
+      __syncthreads();
+      const int pv = s_piv;
+      if (pv != k) {
+        for (int j = tid; j < n; j += blockDim.x) {
+          double tmp = s_A[k * n + j];
+          s_A[k * n + j] = s_A[pv * n + j];
+          s_A[pv * n + j] = tmp;
+        }
+        if (tid == 0) { int tp = s_perm[k]; s_perm[k] = s_perm[pv]; s_perm[pv] = tp; }
+      }
+      __syncthreads();
+      const double ipiv = 1.0 / s_A[k * n + k];
+      for (int i = k + 1 + tid; i < n; i += blockDim.x) s_A[i * n + k] *= ipiv;
+      __syncthreads();
+      const int mrem = n - k - 1;
+      for (int it = tid; it < mrem * mrem; it += blockDim.x) {
+        const int i = k + 1 + it / mrem, j = k + 1 + it % mrem;
+        s_A[i * n + j] -= s_A[i * n + k] * s_A[k * n + j];
+      }
+      __syncthreads();
+    }
+    for (int it = tid; it < n * n; it += blockDim.x) {
+      const int j = it / n, i = it % n;
+      out[(size_t)e * n * n + it] = s_A[i * n + j];
+    }
+    for (int i = tid; i < n; i += blockDim.x) perm[(size_t)e * n + i] = s_perm[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// PRK stage (Section 2.3, eq. (prk_scalar)) in phi coordinates:
+//   ut = un + beta Pt^{-1} (rt [+ ft]),
+// one wavefront per element, lane l owning rows l, l+64, ...; forward and
+// back substitution on the column-major LU factors.
+// ---------------------------------------------------------------------------
+template <int NR>
+__global__ __launch_bounds__(256) void k_prk_stage(const double* __restrict__ Fm, const int* __restrict__ perm,
+                                                   const double* __restrict__ rt, const double* __restrict__ ft,
+                                                   const double* __restrict__ un, double* __restrict__ ut, double beta,
+                                                   int n, int ne) {
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (e >= ne) return;
+  const double* F = Fm + (size_t)e * n * n;
+  const double* r = rt + (size_t)e * n;
+  const double* f = ft ? ft + (size_t)e * n : nullptr;
+  const int* pm = perm + (size_t)e * n;
+  double b[NR];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int i = lane + 64 * s;
+    b[s] = 0.0;
+    if (i < n) {
+      const int o = pm[i];
+      b[s] = r[o] + (f ? f[o] : 0.0);
+    }
+  }
+  // L y = b (unit diagonal)
+  for (int j = 0; j < n; ++j) {
+    const int sj = j >> 6;
+    double bj = b[0];
+#pragma unroll
+    for (int s = 1; s < NR; ++s) if (sj == s) bj = b[s];
+    const double xj = __shfl(bj, j & 63, 64);
+    const double* col = F + (size_t)j * n;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      const int i = lane + 64 * s;
+      if (i > j && i < n) b[s] -= col[i] * xj;
+    }
+  }
+  // U x = y
+  for (int j = n - 1; j >= 0; --j) {
+    const int sj = j >> 6;
+    double bj = b[0];
+#pragma unroll
+    for (int s = 1; s < NR; ++s) if (sj == s) bj = b[s];
+    const double* col = F + (size_t)j * n;
+    const double xj = __shfl(bj, j & 63, 64) / col[j];
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      const int i = lane + 64 * s;
+      if (i == j) b[s] = xj;
+      else if (i < j) b[s] -= col[i] * xj;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int i = lane + 64 * s;
+    if (i < n) ut[(size_t)e * n + i] = un[(size_t)e * n + i] + beta * b[s];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Basis changes with the packed Cholesky factor L (leading N x N block of the
+// p_max factor), one thread per (element, variable):
+//   mode 0: ut = L^{-T} u     (psi -> phi coordinates of a state)
+//   mode 1: u  = L^T ut       (phi -> psi of a state)
+//   mode 2: r  = L^{-1} rt    (phi -> psi of a residual / forcing)
+//   mode 3: rt = L r          (psi -> phi of a residual / forcing)
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void k_basis(const double* __restrict__ x, double* __restrict__ y,
+                                               const double* __restrict__ Lpk, int NT, int V, int ne, int mode) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= ne * V) return;
+  const int e = id / V;
+  const double* L = Lpk + (size_t)e * NT;
+  const double* a = x + (size_t)id * N;
+  double* o = y + (size_t)id * N;
+  double r[N];
+  if (mode == 0) {
+    for (int i = N - 1; i >= 0; --i) {
+      double s = a[i];
+      for (int j = i + 1; j < N; ++j) s -= L[j * (j + 1) / 2 + i] * r[j];
+      r[i] = s / L[i * (i + 1) / 2 + i];
+    }
+  } else if (mode == 1) {
+    for (int i = 0; i < N; ++i) {
+      double s = 0.0;
+      for (int j = i; j < N; ++j) s += L[j * (j + 1) / 2 + i] * a[j];
+      r[i] = s;
+    }
+  } else if (mode == 2) {
+    for (int i = 0; i < N; ++i) {
+      double s = a[i];
+      for (int j = 0; j < i; ++j) s -= L[i * (i + 1) / 2 + j] * r[j];
+      r[i] = s / L[i * (i + 1) / 2 + i];
+    }
+  } else {
+    for (int i = 0; i < N; ++i) {
+      double s = 0.0;
+      for (int j = 0; j <= i; ++j) s += L[i * (i + 1) / 2 + j] * a[j];
+      r[i] = s;
+    }
+  }
+  for (int i = 0; i < N; ++i) o[i] = r[i];
+}
+
+// Restriction of the solution from order p (N modes) to p-1 (Nc modes): the
+// L2 projection, which in psi coordinates is truncation: u = L^T ut, keep
+// the leading Nc entries, ut_c = L_c^{-T} u_c.
+template <int N, int Nc>
+__global__ __launch_bounds__(256) void k_restrict(const double* __restrict__ ut, double* __restrict__ uc,
+                                                  double* __restrict__ uc0, const double* __restrict__ Lpk, int NT, int V,
+                                                  int ne) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= ne * V) return;
+  const int e = id / V;
+  const double* L = Lpk + (size_t)e * NT;
+  const double* a = ut + (size_t)id * N;
+  double u[Nc];
+  for (int k = 0; k < Nc; ++k) {
+    double s = 0.0;
+    for (int j = k; j < N; ++j) s += L[j * (j + 1) / 2 + k] * a[j];
+    u[k] = s;
+  }
+  for (int k = Nc - 1; k >= 0; --k) {
+    double s = u[k];
+    for (int j = k + 1; j < Nc; ++j) s -= L[j * (j + 1) / 2 + k] * u[j];
+    u[k] = s / L[k * (k + 1) / 2 + k];
+  }
+  for (int k = 0; k < Nc; ++k) {
+    uc[(size_t)id * Nc + k] = u[k];
+    uc0[(size_t)id * Nc + k] = u[k];
+  }
+}
+
+// FAS coarse forcing (Section 2.4, steps 2-3, standard full approximation
+// form): fc = Trunc(rhat_p) - rc; the coarse stage-1 residual becomes
+// Trunc(rhat_p).  In phi coordinates truncation of a residual is the leading
+// slice.
+__global__ __launch_bounds__(256) void k_fas(const double* __restrict__ rhat, double* __restrict__ rc,
+                                             double* __restrict__ fc, int N, int Nc, int rows) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= rows * Nc) return;
+  const int row = id / Nc, k = id % Nc;
+  const double t = rhat[(size_t)row * N + k];
+  fc[id] = t - rc[id];
+  rc[id] = t;
+}
+
+// Prolongation of the coarse error and correction (Section 2.4, steps 5-6):
+// ut[:, :, :Nc] += uc - uc0.
+__global__ __launch_bounds__(256) void k_prolong(double* __restrict__ ut, const double* __restrict__ uc,
+                                                 const double* __restrict__ uc0, int N, int Nc, int rows) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= rows * Nc) return;
+  const int row = id / Nc, k = id % Nc;
+  ut[(size_t)row * N + k] += uc[id] - uc0[id];
+}
+
+// ---------------------------------------------------------------------------
+// Pseudo-time step (Section 4, eq. (x3d)) from the element mean
+//   Ubar = u_0 psi_0,  u_0 = (L^T ut)_0,  psi_0 = phi_0 / L_00,
+// dtau = cfl h / ((2p+1)(|v| + c)).  mult scales the result (EXP1 uses
+// (p_max + 1) dtau).
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(256) void k_timestep(const double* __restrict__ ut, int N, const double* __restrict__ Lpk,
+                                                  int NT, const double* __restrict__ hE, int p, double cfl, double mult,
+                                                  double* __restrict__ dtau, int ne, double g) {
+  constexpr int V = D + 2;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const double* L = Lpk + (size_t)e * NT;
+  const double psi0 = (D == 2 ? 0.5 : 0.35355339059327373) / L[0];
+  double U[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    double s = 0.0;
+    for (int j = 0; j < N; ++j) s += L[j * (j + 1) / 2] * ut[((size_t)e * V + v) * N + j];
+    U[v] = s * psi0;
+  }
+  double q2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) q2 += (U[1 + a] / U[0]) * (U[1 + a] / U[0]);
+  const double c = sqrt(g * pressure<D>(U, g) / U[0]);
+  dtau[e] = mult * cfl * hE[e] / ((2.0 * p + 1.0) * (sqrt(q2) + c));
+}
+
+// ---------------------------------------------------------------------------
+// Density-residual norm (Section 4): sum over elements of |L^{-1} rt_rho|^2,
+// block partial sums then one deterministic final sum.
+// ---------------------------------------------------------------------------
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_norm_partial(const double* __restrict__ rt, const double* __restrict__ Lpk,
+                                                      int NT, int ne, double* __restrict__ part) {
+  constexpr int V = D + 2;
+  __shared__ double s_w[4];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (e < ne) {
+    const double* L = Lpk + (size_t)e * NT;
+    const double* a = rt + (size_t)e * V * N;
+    double r[N];
+    for (int i = 0; i < N; ++i) {
+      double s = a[i];
+      for (int j = 0; j < i; ++j) s -= L[i * (i + 1) / 2 + j] * r[j];
+      r[i] = s / L[i * (i + 1) / 2 + i];
+      acc += r[i] * r[i];
+    }
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+__global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ part, int nblk, double omega,
+                                                    double* __restrict__ out) {
+  __shared__ double s_w[4];
+  double acc = 0.0;
+  // fixed assignment of partials to threads, fixed reduction tree
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc += part[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = sqrt(s_w[0] + s_w[1] + s_w[2] + s_w[3]) / omega;
+}
+
+// ---------------------------------------------------------------------------
+// p = 0 level set-up for EXP1 (Sections 2.1 and 3.3 at p = 0), psi
+// coordinates, one thread per element:
+//   u0 = L_00 ut0,  R0 = -sum_faces sum_k w |n dsigma| psi_0 F~,
+//   J0 diagonal / neighbour blocks from dual-number flux derivatives,
+//   dt = (p_max+1) dtau(p_max),  b = dt (R0 + f0),  A = dt J0 (row scaling).
+// scale = false: dt = 1 (plain J0 and R0 + f0).
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ __launch_bounds__(128) void k_p0_setup(const double* __restrict__ ut0, const double* __restrict__ ft0,
+                                                  const double* __restrict__ xv, const int* __restrict__ nbr,
+                                                  const double* __restrict__ Lpk, int NT, const double* __restrict__ hE,
+                                                  int pmax, double cfl, int scale, double* __restrict__ u0,
+                                                  double* __restrict__ bvec, double* __restrict__ Ad,
+                                                  double* __restrict__ Ao, double* __restrict__ dtout, int ne, Gas gas,
+                                                  const double* __restrict__ gx, const double* __restrict__ gw) {
+  constexpr int V = D + 2, NF = 2 * D, NC = 1 << D, QF = 1 << (D - 1);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const double phi0 = (D == 2 ? 0.5 : 0.35355339059327373);
+  const double L00 = Lpk[(size_t)e * NT];
+  double X[NC * D];
+#pragma unroll
+  for (int i = 0; i < NC * D; ++i) X[i] = xv[(size_t)e * NC * D + i];
+  double U[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) U[v] = ut0[(size_t)e * V + v] * phi0;
+  double dt = 1.0;
+  if (scale) {
+    double q2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) q2 += (U[1 + a] / U[0]) * (U[1 + a] / U[0]);
+    const double c = sqrt(gas.g * pressure<D>(U, gas.g) / U[0]);
+    dt = (pmax + 1.0) * cfl * hE[e] / ((2.0 * pmax + 1.0) * (sqrt(q2) + c));
+  }
+  double R[V], Jd[V * V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) R[v] = 0.0;
+#pragma unroll
+  for (int x = 0; x < V * V; ++x) Jd[x] = 0.0;
+  for (int lf = 0; lf < NF; ++lf) {
+    double Jo[V * V];
+#pragma unroll
+    for (int x = 0; x < V * V; ++x) Jo[x] = 0.0;
+    const int nb = nbr[(size_t)e * NF + lf];
+    double UN[V];
+    double L00n = 1.0;
+    if (nb >= 0) {
+      L00n = Lpk[(size_t)nb * NT];
+#pragma unroll
+      for (int v = 0; v < V; ++v) UN[v] = ut0[(size_t)nb * V + v] * phi0;
+    }
+    int ta[D - 1];
+    face_axes<D>(lf, ta);
+    for (int k = 0; k < QF; ++k) {
+      double xi[D], wk = 1.0;
+      xi[lf >> 1] = (lf & 1) ? 1.0 : -1.0;
+      int r0 = k;
+#pragma unroll
+      for (int q = 0; q < D - 1; ++q) { xi[ta[q]] = gx[r0 & 1]; wk *= gw[r0 & 1]; r0 >>= 1; }
+      double c[D][D], det;
+      geom<D>(X, xi, c, det);
+      double nh[D], a2 = 0.0;
+      const double sg = (lf & 1) ? 1.0 : -1.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) { nh[a] = sg * c[lf >> 1][a]; a2 += nh[a] * nh[a]; }
+      const double area = sqrt(a2);
+#pragma unroll
+      for (int a = 0; a < D; ++a) nh[a] /= area;
+      const double wa = wk * area * phi0;
+      Dual<V> UL[V], F[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) { UL[v] = Dual<V>(U[v]); UL[v].d[v] = 1.0; }
+      if (nb >= 0) {
+        rusanov<D>(UL, UN, nh, F, gas.g);
+        Dual<V> UR[V], F2[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) { UR[v] = Dual<V>(UN[v]); UR[v].d[v] = 1.0; }
+        rusanov<D>(U, UR, nh, F2, gas.g);
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+          for (int w = 0; w < V; ++w) Jo[v * V + w] -= wa * phi0 * F2[v].d[w];
+      } else {
+        Dual<V> UG[V];
+        if (nb == NB_WALL) ghost_wall<D>(UL, nh, UG);
+        else ghost_far<D>(UL, nh, UG, gas.Uinf, gas.g);
+        rusanov<D>(UL, UG, nh, F, gas.g);
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        R[v] -= wa * F[v].v;
+#pragma unroll
+        for (int w = 0; w < V; ++w) Jd[v * V + w] -= wa * phi0 * F[v].d[w];
+      }
+    }
+    // psi coordinates: dR0_E/du0_F = Jt / (L00_E L00_F)
+    const double so = dt / (L00 * L00n);
+#pragma unroll
+    for (int x = 0; x < V * V; ++x) Ao[((size_t)e * NF + lf) * V * V + x] = (nb >= 0) ? so * Jo[x] : 0.0;
+  }
+  const double sd = dt / (L00 * L00);
+#pragma unroll
+  for (int x = 0; x < V * V; ++x) Ad[(size_t)e * V * V + x] = sd * Jd[x];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const double f = ft0 ? ft0[(size_t)e * V + v] / L00 : 0.0;
+    bvec[(size_t)e * V + v] = dt * (R[v] / L00 + f);
+    u0[(size_t)e * V + v] = L00 * ut0[(size_t)e * V + v];
+  }
+  dtout[e] = dt;
+}
+
+// ---------------------------------------------------------------------------
+// Arnoldi process of EXP1 (Section 2.2, eqs. (vm)-(vm2)) as one cooperative
+// kernel: classical Gram-Schmidt with one re-orthogonalisation (CGS2), the
+// block sparse product y = A x with A = T J0, and deterministic grid
+// reductions (every block sums the per-block partials in the same order, so
+// all blocks take identical decisions).  Three grid barriers per step.
+// Output: basis Vb[j][K], Hessenberg H[(m+1) x m] row-major, info[0] = m
+// used, info[1] = beta = ||b||.
+// ---------------------------------------------------------------------------
+template <int V, int NF>
+__device__ __forceinline__ double spmv_row(int row, const int* __restrict__ nbr, const double* __restrict__ Ad,
+                                           const double* __restrict__ Ao, const double* __restrict__ x) {
+  const int e = row / V, v = row % V;
+  double s = 0.0;
+  const double* a = Ad + (size_t)e * V * V + v * V;
+#pragma unroll
+  for (int w = 0; w < V; ++w) s += a[w] * x[(size_t)e * V + w];
+#pragma unroll
+  for (int lf = 0; lf < NF; ++lf) {
+    const int nb = nbr[(size_t)e * NF + lf];
+    if (nb >= 0) {
+      const double* o = Ao + ((size_t)e * NF + lf) * V * V + v * V;
+#pragma unroll
+      for (int w = 0; w < V; ++w) s += o[w] * x[(size_t)nb * V + w];
+    }
+  }
+  return s;
+}
+
+// Block-wide sums of cnt per-thread values val(i), written to s_out[i].
+template <class F>
+__device__ __forceinline__ void block_multi_sum(int cnt, F val, double* s_wave /*[4][64]*/, double* s_out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = 0; i < cnt; ++i) {
+    double s = wave_sum(val(i));
+    if (lane == 0) s_wave[wv * 64 + i] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < cnt) {
+    const int i = threadIdx.x;
+    s_out[i] = s_wave[i] + s_wave[64 + i] + s_wave[128 + i] + s_wave[192 + i];
+  }
+  __syncthreads();
+}
+
+template <int V, int NF>
+__global__ __launch_bounds__(256) void k_arnoldi(int K, int m, const int* __restrict__ nbr,
+                                                 const double* __restrict__ Ad, const double* __restrict__ Ao,
+                                                 const double* __restrict__ b, double* __restrict__ Vb,
+                                                 double* __restrict__ H, double* __restrict__ part1,
+                                                 double* __restrict__ part2, double* __restrict__ info) {
+  cg::grid_group grid = cg::this_grid();
+  __shared__ double s_wave[4 * 64];
+  __shared__ double s_h[64];
+  __shared__ double s_g[64];
+  const int nblk = gridDim.x;
+  const int stride = nblk * blockDim.x;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int P = m + 2;
+  // beta = ||b||
+  block_multi_sum(1, [&](int) {
+    double s = 0.0;
+    for (int k = gid; k < K; k += stride) s += b[k] * b[k];
+    return s;
+  }, s_wave, s_h);
+  if (threadIdx.x == 0) part1[blockIdx.x * P] = s_h[0];
+  grid.sync();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < nblk; ++q) s += part1[q * P];
+    s_g[0] = s;
+  }
+  __syncthreads();
+  const double beta = sqrt(s_g[0]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) { info[1] = beta; info[0] = 0.0; }
+  if (beta == 0.0) return;  // uniform over the grid
+  for (int k = gid; k < K; k += stride) Vb[k] = b[k] / beta;
+  int mused = m;
+  grid.sync();
+  for (int j = 0; j < m; ++j) {
+    const double* vj = Vb + (size_t)j * K;
+    double* w = Vb + (size_t)(j + 1) * K;
+    // w = A v_j over this thread's rows, then partial <w, v_i> and ||w||^2
+    for (int k = gid; k < K; k += stride) w[k] = spmv_row<V, NF>(k, nbr, Ad, Ao, vj);
+    block_multi_sum(j + 2, [&](int i) {
+      double s = 0.0;
+      if (i <= j) { for (int k = gid; k < K; k += stride) s += w[k] * Vb[(size_t)i * K + k]; }
+      else { for (int k = gid; k < K; k += stride) s += w[k] * w[k]; }
+      return s;
+    }, s_wave, s_h);
+    if (threadIdx.x < j + 2) part1[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
+    grid.sync();
+    if (threadIdx.x < j + 2) {
+      double s = 0.0;
+      for (int q = 0; q < nblk; ++q) s += part1[q * P + threadIdx.x];
+      s_g[threadIdx.x] = s;
+    }
+    __syncthreads();
+    const double wn0 = sqrt(s_g[j + 1]);
+    // first Gram-Schmidt pass, then second-pass partials and ||w||^2
+    for (int k = gid; k < K; k += stride) {
+      double s = w[k];
+      for (int i = 0; i <= j; ++i) s -= s_g[i] * Vb[(size_t)i * K + k];
+      w[k] = s;
+    }
+    if (blockIdx.x == 0 && threadIdx.x <= j) H[threadIdx.x * m + j] = s_g[threadIdx.x];
+    block_multi_sum(j + 2, [&](int i) {
+      double s = 0.0;
+      if (i <= j) { for (int k = gid; k < K; k += stride) s += w[k] * Vb[(size_t)i * K + k]; }
+      else { for (int k = gid; k < K; k += stride) s += w[k] * w[k]; }
+      return s;
+    }, s_wave, s_h);
+    if (threadIdx.x < j + 2) part2[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
+    grid.sync();
+    __syncthreads();
+    if (threadIdx.x < j + 2) {
+      double s = 0.0;
+      for (int q = 0; q < nblk; ++q) s += part2[q * P + threadIdx.x];
+      s_h[threadIdx.x] = s;
+    }
+    __syncthreads();
+    double h2sq = 0.0;
+    for (int i = 0; i <= j; ++i) h2sq += s_h[i] * s_h[i];
+    const double hn = sqrt(fmax(s_h[j + 1] - h2sq, 0.0));
+    for (int k = gid; k < K; k += stride) {
+      double s = w[k];
+      for (int i = 0; i <= j; ++i) s -= s_h[i] * Vb[(size_t)i * K + k];
+      w[k] = (hn > 1e-12 * wn0) ? s / hn : s;
+    }
+    if (blockIdx.x == 0 && threadIdx.x <= j) H[threadIdx.x * m + j] += s_h[threadIdx.x];
+    if (blockIdx.x == 0 && threadIdx.x == 0) H[(j + 1) * m + j] = hn;
+    if (!(hn > 1e-12 * wn0)) { mused = j + 1; break; }
+    grid.sync();
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) info[0] = (double)mused;
+}
+
+// ---------------------------------------------------------------------------
+// phi_1(H_m) e_1 on one block: exponential of the augmented matrix
+// [[H, e_1], [0, 0]] by the degree-13 diagonal Pade approximant with scaling
+// and squaring (Higham 2005); stands in for the paper's rational
+// approximation of exp(dt H_m) (end of Section 2.2).  y[i] = E[i][m].
+// ---------------------------------------------------------------------------
+__device__ void lds_matmul(int n, const double* A, const double* B, double* Cm) {
+  for (int it = threadIdx.x; it < n * n; it += blockDim.x) {
+    const int i = it / n, j = it % n;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += A[i * n + k] * B[k * n + j];
+    Cm[it] = s;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, int mstride,
+                                              const double* __restrict__ info, double* __restrict__ y,
+                                              int* __restrict__ fail) {
+  extern __shared__ double sm[];
+  __shared__ int s_sq, s_piv;
+  __shared__ double s_red[256];
+  const int mu = (int)info[0];
+  if (mu <= 0) return;
+  const int n = mu + 1, nn = n * n;
+  double* B = sm;
+  double* B2 = B + nn;
+  double* B4 = B2 + nn;
+  double* B6 = B4 + nn;
+  double* W = B6 + nn;
+  double* T = W + nn;
+  double* U = T + nn;
+  double* Vm = U + nn;
+  const double b[14] = {64764752532480000.0, 32382376266240000.0, 7771770303897600.0, 1187353796428800.0,
+                        129060195264000.0,   10559470521600.0,    670442572800.0,     33522128640.0,
+                        1323241920.0,        40840800.0,          960960.0,           16380.0,
+                        182.0,               1.0};
+  for (int it = threadIdx.x; it < nn; it += blockDim.x) {
+    const int i = it / n, j = it % n;
+    double v = 0.0;
+    if (i < mu && j < mu) v = H[i * mstride + j];
+    if (i == 0 && j == mu) v = 1.0;
+    B[it] = v;
+  }
+  __syncthreads();
+  // 1-norm
+  double cs = 0.0;
+  if (threadIdx.x < n) for (int i = 0; i < n; ++i) cs += fabs(B[i * n + threadIdx.x]);
+  s_red[threadIdx.x] = cs;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double nrm = 0.0;
+    for (int i = 0; i < n; ++i) nrm = fmax(nrm, s_red[i]);
+    const double theta13 = 5.371920351148152;
+    int sq = 0;
+    if (nrm > theta13) sq = max(0, (int)ceil(log2(nrm / theta13)));
+    s_sq = sq;
+  }
+  __syncthreads();
+  const int sq = s_sq;
+  const double sc = ldexp(1.0, -sq);
+  for (int it = threadIdx.x; it < nn; it += blockDim.x) B[it] *= sc;
+  __syncthreads();
+  lds_matmul(n, B, B, B2);
+  lds_matmul(n, B2, B2, B4);
+  lds_matmul(n, B4, B2, B6);
+  for (int it = threadIdx.x; it < nn; it += blockDim.x) W[it] = b[13] * B6[it] + b[11] * B4[it] + b[9] * B2[it];
+  __syncthreads();
+  lds_matmul(n, B6, W, T);
+  for (int it = threadIdx.x; it < nn; it += blockDim.x) {
+    T[it] += b[7] * B6[it] + b[5] * B4[it] + b[3] * B2[it] + ((it / n == it % n) ? b[1] : 0.0);
+  }
+  __syncthreads();
+  lds_matmul(n, B, T, U);
+  for (int it = threadIdx.x; it < nn; it += blockDim.x) W[it] = b[12] * B6[it] + b[10] * B4[it] + b[8] * B2[it];
+  __syncthreads();
+  lds_matmul(n, B6, W, Vm);
+  for (int it = threadIdx.x; it < nn; it += blockDim.x) {
+    Vm[it] += b[6] * B6[it] + b[4] * B4[it] + b[2] * B2[it] + ((it / n == it % n) ? b[0] : 0.0);
+  }
+  __syncthreads();
+  // (V - U) E = (V + U): Gaussian elimination with partial pivoting
+  double* Pm = B2;
+  double* X = B4;
+  for (int it = threadIdx.x; it < nn; it += blockDim.x) { Pm[it] = Vm[it] - U[it]; X[it] = Vm[it] + U[it]; }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      int pv = k;
+      double best = fabs(Pm[k * n + k]);
+      for (int i = k + 1; i < n; ++i) if (fabs(Pm[i * n + k]) > best) { best = fabs(Pm[i * n + k]); pv = i; }
+      if (!(best > 0.0)) atomicOr(fail, 2);
+      s_piv = pv;
+    }
+    __syncthreads();
+    const int pv = s_piv;
+    if (pv != k) {
+      for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        double t1 = Pm[k * n + j]; Pm[k * n + j] = Pm[pv * n + j]; Pm[pv * n + j] = t1;
+        double t2 = X[k * n + j]; X[k * n + j] = X[pv * n + j]; X[pv * n + j] = t2;
+      }
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < (n - k - 1) * n; it += blockDim.x) {
+      const int i = k + 1 + it / n, j = it % n;
+      const double l = Pm[i * n + k] / Pm[k * n + k];
+      X[i * n + j] -= l * X[k * n + j];
+      if (j > k) Pm[i * n + j] -= l * Pm[k * n + j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) for (int i = k + 1; i < n; ++i) Pm[i * n + k] = 0.0;
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    for (int j = threadIdx.x; j < n; j += blockDim.x) X[k * n + j] /= Pm[k * n + k];
+    __syncthreads();
+    for (int it = threadIdx.x; it < k * n; it += blockDim.x) {
+      const int i = it / n, j = it % n;
+      X[i * n + j] -= Pm[i * n + k] * X[k * n + j];
+    }
+    __syncthreads();
+  }
+  double* E = X;
+  double* Tm = B6;
+  for (int s = 0; s < sq; ++s) {
+    lds_matmul(n, E, E, Tm);
+    for (int it = threadIdx.x; it < nn; it += blockDim.x) E[it] = Tm[it];
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < mu; i += blockDim.x) y[i] = E[i * n + mu];
+}
+
+// u0 += beta V_m y ; then back to phi coordinates: ut0 = u0 / L00.
+__global__ __launch_bounds__(256) void k_exp1_update(int K, int V, const double* __restrict__ Vb,
+                                                     const double* __restrict__ y, const double* __restrict__ info,
+                                                     const double* __restrict__ u0, const double* __restrict__ Lpk,
+                                                     int NT, double* __restrict__ ut0) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int mu = (int)info[0];
+  const double beta = info[1];
+  double s = 0.0;
+  for (int j = 0; j < mu; ++j) s += Vb[(size_t)j * K + k] * y[j];
+  const double u = u0[k] + beta * s;
+  ut0[k] = u / Lpk[(size_t)(k / V) * NT];
+}
+
+__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+// Uniform free stream as level-p coefficients in psi coordinates:
+// u_{E,v,0} = U_v / psi_0 = U_v L_00 / phi_0.
+__global__ void k_freestream(double* __restrict__ u, int V, int N, const double* __restrict__ Lpk, int NT, double phi0,
+                             Gas gas, int ne) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= ne * V * N) return;
+  const int e = id / (V * N), v = (id / N) % V, i = id % N;
+  u[id] = (i == 0) ? gas.Uinf[v] * Lpk[(size_t)e * NT] / phi0 : 0.0;
+}
+
+// D = L^{-1} Dt L^{-T} per (v, w) block (tests of the Jacobian in psi
+// coordinates), one thread per (element, v, w).
+template <int N>
+__global__ __launch_bounds__(128) void k_jac_to_psi(double* __restrict__ Dm, const double* __restrict__ Lpk, int NT,
+                                                    int V, int ne) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= ne * V * V) return;
+  const int e = id / (V * V), v = (id / V) % V, w = id % V;
+  const int n = V * N;
+  double* Db = Dm + (size_t)e * n * n;
+  const double* L = Lpk + (size_t)e * NT;
+  // columns: X = L^{-1} Dt_vw (forward substitution on each column j)
+  for (int j = 0; j < N; ++j) {
+    for (int i = 0; i < N; ++i) {
+      double s = Db[(size_t)(v * N + i) * n + w * N + j];
+      for (int k = 0; k < i; ++k) s -= L[i * (i + 1) / 2 + k] * Db[(size_t)(v * N + k) * n + w * N + j];
+      Db[(size_t)(v * N + i) * n + w * N + j] = s / L[i * (i + 1) / 2 + i];
+    }
+  }
+  // rows: Y = X L^{-T}, i.e. solve L Y^T = X^T row by row
+  for (int i = 0; i < N; ++i) {
+    for (int j = 0; j < N; ++j) {
+      double s = Db[(size_t)(v * N + i) * n + w * N + j];
+      for (int k = 0; k < j; ++k) s -= L[j * (j + 1) / 2 + k] * Db[(size_t)(v * N + i) * n + w * N + k];
+      Db[(size_t)(v * N + i) * n + w * N + j] = s / L[j * (j + 1) / 2 + j];
+    }
+  }
+}
+
+// ===========================================================================
+// launchers
+// ===========================================================================
+namespace {
+
+template <int D, int P>
+constexpr int res_tile() {
+  using C = Cfg<D, P>;
+  constexpr int per = (C::V * C::N + C::QV * C::V * D + C::NF * C::QF * C::V + C::NC * D) * 8;
+  constexpr int eb = 48 * 1024 / per;
+  return eb < 1 ? 1 : (eb > 32 ? 32 : eb);
+}
+
+template <int D, int P>
+void fill_tab(Tab<D, P>& t, const TabData& td) {
+  for (int i = 0; i < P + 2; ++i) { t.x[i] = td.x[i]; t.w[i] = td.w[i]; }
+  for (int a = 0; a <= P; ++a) {
+    for (int i = 0; i < P + 2; ++i) { t.L[a][i] = td.L[a][i]; t.dL[a][i] = td.dL[a][i]; }
+    t.Lb[a][0] = td.Lb[a][0];
+    t.Lb[a][1] = td.Lb[a][1];
+  }
+  for (int k = 0; k < Cfg<D, P>::N; ++k)
+    for (int r = 0; r < 3; ++r) t.m[k][r] = (int8_t)td.m[k][r];
+}
+
+template <int D, int P>
+hipError_t residual_t(const DevMesh& M, const TabData& td, const double* ut, const double* fadd, double* rt,
+                      hipStream_t st) {
+  Tab<D, P> t;
+  fill_tab(t, td);
+  constexpr int EB = res_tile<D, P>();
+  const int grid = (M.ne + EB - 1) / EB;
+  hipLaunchKernelGGL((k_residual<D, P, EB>), dim3(grid), dim3(256), 0, st, ut, fadd, rt, M.xv, M.nbr, M.ncode, M.ne,
+                     t, M.gas);
+  return hipGetLastError();
+}
+
+template <int D, int P>
+hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, const double* dtau, double* out,
+                      int* perm, int* fail, bool factor, hipStream_t st) {
+  Tab<D, P> t;
+  fill_tab(t, td);
+  const size_t lds = (size_t)jac_lds_doubles<D, P>() * 8;
+  if (factor) {
+    auto kf = k_jacobian<D, P, true>;
+    hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
+                       fail, M.ne, t, M.gas);
+  } else {
+    auto kf = k_jacobian<D, P, false>;
+    hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
+                       fail, M.ne, t, M.gas);
+  }
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t basis_t(const DevMesh& M, const double* x, double* y, int mode, hipStream_t st) {
+  const int rows = M.ne * M.V;
+  hipLaunchKernelGGL((k_basis<N>), dim3((rows + 255) / 256), dim3(256), 0, st, x, y, M.Lpk, M.NT, M.V, M.ne, mode);
+  return hipGetLastError();
+}
+
+template <int N, int Nc>
+hipError_t restrict_t(const DevMesh& M, const double* ut, double* uc, double* uc0, hipStream_t st) {
+  const int rows = M.ne * M.V;
+  hipLaunchKernelGGL((k_restrict<N, Nc>), dim3((rows + 255) / 256), dim3(256), 0, st, ut, uc, uc0, M.Lpk, M.NT, M.V,
+                     M.ne);
+  return hipGetLastError();
+}
+
+template <int D, int N>
+hipError_t norm_t(const DevMesh& M, const double* rt, double* part, double* out, hipStream_t st) {
+  const int nblk = (M.ne + 255) / 256;
+  hipLaunchKernelGGL((k_norm_partial<D, N>), dim3(nblk), dim3(256), 0, st, rt, M.Lpk, M.NT, M.ne, part);
+  hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, st, part, nblk, M.omega, out);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t jac_to_psi_t(const DevMesh& M, double* Dm, hipStream_t st) {
+  const int cnt = M.ne * M.V * M.V;
+  hipLaunchKernelGGL((k_jac_to_psi<N>), dim3((cnt + 127) / 128), dim3(128), 0, st, Dm, M.Lpk, M.NT, M.V, M.ne);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define EG_DISPATCH_P(D, p, CALL)                            \
+  switch (p) {                                               \
+    case 0: return CALL(D, 0);                               \
+    case 1: return CALL(D, 1);                               \
+    case 2: return CALL(D, 2);                               \
+    case 3: return CALL(D, 3);                               \
+    case 4: if (D == 2) return CALL(2, 4); break;            \
+    default: break;                                          \
+  }
+
+hipError_t launch_residual(const DevMesh& M, const TabData& td, int p, const double* ut, const double* fadd,
+                           double* rt, hipStream_t st) {
+#define CALL_RES(DD, PP) residual_t<DD, PP>(M, td, ut, fadd, rt, st)
+  if (M.d == 2) { EG_DISPATCH_P(2, p, CALL_RES) }
+  else { EG_DISPATCH_P(3, p, CALL_RES) }
+#undef CALL_RES
+  return hipErrorInvalidValue;
+}
+
+bool jacobian_supported(int d, int p) {
+  if (p < 1) return false;
+  if (d == 2) return p <= 4;
+  return p <= 2;
+}
+
+hipError_t launch_jacobian(const DevMesh& M, const TabData& td, int p, const double* ut, const double* dtau,
+                           double* out, int* perm, int* fail, bool factor, hipStream_t st) {
+  if (!jacobian_supported(M.d, p)) return hipErrorInvalidValue;
+#define CALL_JAC(DD, PP) jacobian_t<DD, (PP < 1 ? 1 : PP)>(M, td, ut, dtau, out, perm, fail, factor, st)
+  if (M.d == 2) {
+    switch (p) {
+      case 1: return CALL_JAC(2, 1);
+      case 2: return CALL_JAC(2, 2);
+      case 3: return CALL_JAC(2, 3);
+      case 4: return CALL_JAC(2, 4);
+      default: break;
+    }
+  } else {
+    switch (p) {
+      case 1: return CALL_JAC(3, 1);
+      case 2: return CALL_JAC(3, 2);
+      default: break;
+    }
+  }
+#undef CALL_JAC
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_prk_stage(const DevMesh& M, int n, const double* F, const int* perm, const double* rt,
+                            const double* ft, const double* un, double* ut, double beta, hipStream_t st) {
+  const int grid = (M.ne + 3) / 4;
+  if (n <= 64) hipLaunchKernelGGL((k_prk_stage<1>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
+  else if (n <= 128) hipLaunchKernelGGL((k_prk_stage<2>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
+  else if (n <= 192) hipLaunchKernelGGL((k_prk_stage<3>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
+  else if (n <= 320) hipLaunchKernelGGL((k_prk_stage<5>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_basis(const DevMesh& M, int N, const double* x, double* y, int mode, hipStream_t st) {
+  switch (N) {
+    case 1: return basis_t<1>(M, x, y, mode, st);
+    case 4: return basis_t<4>(M, x, y, mode, st);
+    case 8: return basis_t<8>(M, x, y, mode, st);
+    case 9: return basis_t<9>(M, x, y, mode, st);
+    case 16: return basis_t<16>(M, x, y, mode, st);
+    case 25: return basis_t<25>(M, x, y, mode, st);
+    case 27: return basis_t<27>(M, x, y, mode, st);
+    case 64: return basis_t<64>(M, x, y, mode, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_restrict(const DevMesh& M, int p, const double* ut, double* uc, double* uc0, hipStream_t st) {
+  if (M.d == 2) {
+    switch (p) {
+      case 1: return restrict_t<4, 1>(M, ut, uc, uc0, st);
+      case 2: return restrict_t<9, 4>(M, ut, uc, uc0, st);
+      case 3: return restrict_t<16, 9>(M, ut, uc, uc0, st);
+      case 4: return restrict_t<25, 16>(M, ut, uc, uc0, st);
+      default: break;
+    }
+  } else {
+    switch (p) {
+      case 1: return restrict_t<8, 1>(M, ut, uc, uc0, st);
+      case 2: return restrict_t<27, 8>(M, ut, uc, uc0, st);
+      case 3: return restrict_t<64, 27>(M, ut, uc, uc0, st);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fas(int N, int Nc, int rows, const double* rhat, double* rc, double* fc, hipStream_t st) {
+  const int cnt = rows * Nc;
+  hipLaunchKernelGGL(k_fas, dim3((cnt + 255) / 256), dim3(256), 0, st, rhat, rc, fc, N, Nc, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(int N, int Nc, int rows, double* ut, const double* uc, const double* uc0, hipStream_t st) {
+  const int cnt = rows * Nc;
+  hipLaunchKernelGGL(k_prolong, dim3((cnt + 255) / 256), dim3(256), 0, st, ut, uc, uc0, N, Nc, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_timestep(const DevMesh& M, int p, int N, double cfl, double mult, const double* ut, double* dtau,
+                           hipStream_t st) {
+  const int grid = (M.ne + 255) / 256;
+  if (M.d == 2)
+    hipLaunchKernelGGL((k_timestep<2>), dim3(grid), dim3(256), 0, st, ut, N, M.Lpk, M.NT, M.hE, p, cfl, mult, dtau,
+                       M.ne, M.gas.g);
+  else
+    hipLaunchKernelGGL((k_timestep<3>), dim3(grid), dim3(256), 0, st, ut, N, M.Lpk, M.NT, M.hE, p, cfl, mult, dtau,
+                       M.ne, M.gas.g);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm(const DevMesh& M, int N, const double* rt, double* part, double* out, hipStream_t st) {
+  if (M.d == 2) {
+    switch (N) {
+      case 1: return norm_t<2, 1>(M, rt, part, out, st);
+      case 4: return norm_t<2, 4>(M, rt, part, out, st);
+      case 9: return norm_t<2, 9>(M, rt, part, out, st);
+      case 16: return norm_t<2, 16>(M, rt, part, out, st);
+      case 25: return norm_t<2, 25>(M, rt, part, out, st);
+      default: break;
+    }
+  } else {
+    switch (N) {
+      case 1: return norm_t<3, 1>(M, rt, part, out, st);
+      case 8: return norm_t<3, 8>(M, rt, part, out, st);
+      case 27: return norm_t<3, 27>(M, rt, part, out, st);
+      case 64: return norm_t<3, 64>(M, rt, part, out, st);
+      default: break;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_p0_setup(const DevMesh& M, const double* ut0, const double* ft0, int pmax, double cfl, int scale,
+                           double* u0, double* b, double* Ad, double* Ao, double* dt, hipStream_t st) {
+  const int grid = (M.ne + 127) / 128;
+  if (M.d == 2)
+    hipLaunchKernelGGL((k_p0_setup<2>), dim3(grid), dim3(128), 0, st, ut0, ft0, M.xv, M.nbr, M.Lpk, M.NT, M.hE, pmax,
+                       cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w);
+  else
+    hipLaunchKernelGGL((k_p0_setup<3>), dim3(grid), dim3(128), 0, st, ut0, ft0, M.xv, M.nbr, M.Lpk, M.NT, M.hE, pmax,
+                       cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w);
+  return hipGetLastError();
+}
+
+int arnoldi_max_blocks(int d) {
+  int nb = 0, dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  hipError_t e;
+  if (d == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_arnoldi<4, 4>, 256, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_arnoldi<5, 6>, 256, 0);
+  if (e != hipSuccess) return 0;
+  return nb * prop.multiProcessorCount;
+}
+
+hipError_t launch_exp1_krylov(const DevMesh& M, int m, int nblk, const double* Ad, const double* Ao, const double* b,
+                              double* Vb, double* H, double* part1, double* part2, double* info, double* y, int* fail,
+                              hipStream_t st) {
+  int K = M.ne * M.V;
+  const int* nbr = M.nbr;
+  void* args[] = {&K, &m, (void*)&nbr, (void*)&Ad, (void*)&Ao, (void*)&b, (void*)&Vb, (void*)&H,
+                  (void*)&part1, (void*)&part2, (void*)&info};
+  hipError_t e;
+  if (M.d == 2)
+    e = hipLaunchCooperativeKernel((const void*)k_arnoldi<4, 4>, dim3(nblk), dim3(256), args, 0, st);
+  else
+    e = hipLaunchCooperativeKernel((const void*)k_arnoldi<5, 6>, dim3(nblk), dim3(256), args, 0, st);
+  if (e != hipSuccess) return e;
+  const size_t lds = (size_t)8 * (m + 1) * (m + 1) * 8;
+  e = hipFuncSetAttribute((const void*)k_phi1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_phi1, dim3(1), dim3(256), lds, st, H, m, info, y, fail);
+  return hipGetLastError();
+}
+
+hipError_t launch_exp1_update(const DevMesh& M, const double* Vb, const double* y, const double* info,
+                              const double* u0, double* ut0, hipStream_t st) {
+  const int K = M.ne * M.V;
+  hipLaunchKernelGGL(k_exp1_update, dim3((K + 255) / 256), dim3(256), 0, st, K, M.V, Vb, y, info, u0, M.Lpk, M.NT,
+                     ut0);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* a, double* b, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_freestream(const DevMesh& M, int N, double* u, hipStream_t st) {
+  const int cnt = M.ne * M.V * N;
+  const double phi0 = (M.d == 2) ? 0.5 : 0.35355339059327373;
+  hipLaunchKernelGGL(k_freestream, dim3((cnt + 255) / 256), dim3(256), 0, st, u, M.V, N, M.Lpk, M.NT, phi0, M.gas,
+                     M.ne);
+  return hipGetLastError();
+}
+
+hipError_t launch_jac_to_psi(const DevMesh& M, int N, double* Dm, hipStream_t st) {
+  switch (N) {
+    case 4: return jac_to_psi_t<4>(M, Dm, st);
+    case 8: return jac_to_psi_t<8>(M, Dm, st);
+    case 9: return jac_to_psi_t<9>(M, Dm, st);
+    case 16: return jac_to_psi_t<16>(M, Dm, st);
+    case 25: return jac_to_psi_t<25>(M, Dm, st);
+    case 27: return jac_to_psi_t<27>(M, Dm, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace eg

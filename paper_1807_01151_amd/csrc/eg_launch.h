@@ -1,0 +1,61 @@
+// Internal interface between the host driver and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "eg_common.h"
+
+namespace eg {
+
+// Device-resident mesh data and constants (owned by the handle).
+struct DevMesh {
+  int d = 2, V = 4, ne = 0, NF = 4, NC = 4;
+  int NT = 0;              // packed triangle size of the p_max basis
+  double omega = 0.0;      // |Omega|
+  Gas gas{};
+  double* xv = nullptr;    // [E][2^d][d]
+  int* nbr = nullptr;      // [E][2d]
+  uint8_t* ncode = nullptr;
+  double* Lpk = nullptr;   // [E][NT] Cholesky factor of the phi mass matrix
+  double* Gpk = nullptr;   // [E][NT] phi mass matrix
+  double* hE = nullptr;    // [E] 2 d |E| / |dE|
+  double* g2x = nullptr;   // 2-point Gauss rule (p = 0 faces)
+  double* g2w = nullptr;
+};
+
+// Host copy of the 1D tables of one order (filled by the set-up code).
+struct TabData {
+  double x[8], w[8];
+  double L[8][8], dL[8][8], Lb[8][2];
+  int m[128][3];
+};
+
+hipError_t launch_residual(const DevMesh& M, const TabData& td, int p, const double* ut, const double* fadd,
+                           double* rt, hipStream_t st);
+bool jacobian_supported(int d, int p);
+hipError_t launch_jacobian(const DevMesh& M, const TabData& td, int p, const double* ut, const double* dtau,
+                           double* out, int* perm, int* fail, bool factor, hipStream_t st);
+hipError_t launch_prk_stage(const DevMesh& M, int n, const double* F, const int* perm, const double* rt,
+                            const double* ft, const double* un, double* ut, double beta, hipStream_t st);
+hipError_t launch_basis(const DevMesh& M, int N, const double* x, double* y, int mode, hipStream_t st);
+hipError_t launch_restrict(const DevMesh& M, int p, const double* ut, double* uc, double* uc0, hipStream_t st);
+hipError_t launch_fas(int N, int Nc, int rows, const double* rhat, double* rc, double* fc, hipStream_t st);
+hipError_t launch_prolong(int N, int Nc, int rows, double* ut, const double* uc, const double* uc0, hipStream_t st);
+hipError_t launch_timestep(const DevMesh& M, int p, int N, double cfl, double mult, const double* ut, double* dtau,
+                           hipStream_t st);
+hipError_t launch_norm(const DevMesh& M, int N, const double* rt, double* part, double* out, hipStream_t st);
+hipError_t launch_p0_setup(const DevMesh& M, const double* ut0, const double* ft0, int pmax, double cfl, int scale,
+                           double* u0, double* b, double* Ad, double* Ao, double* dt, hipStream_t st);
+int arnoldi_max_blocks(int d);
+hipError_t launch_exp1_krylov(const DevMesh& M, int m, int nblk, const double* Ad, const double* Ao, const double* b,
+                              double* Vb, double* H, double* part1, double* part2, double* info, double* y, int* fail,
+                              hipStream_t st);
+hipError_t launch_exp1_update(const DevMesh& M, const double* Vb, const double* y, const double* info,
+                              const double* u0, double* ut0, hipStream_t st);
+hipError_t launch_copy(const double* a, double* b, size_t n, hipStream_t st);
+hipError_t launch_freestream(const DevMesh& M, int N, double* u, hipStream_t st);
+hipError_t launch_jac_to_psi(const DevMesh& M, int N, double* Dm, hipStream_t st);
+
+}  // namespace eg

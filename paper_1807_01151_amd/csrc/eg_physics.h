@@ -1,0 +1,215 @@
+// Euler physics for the HIP kernels: perfect-gas flux, Rusanov numerical
+// flux, slip-wall and characteristic far-field ghost states (arXiv:1807.01151,
+// Section 3, eq. (euler) with a non-rotating frame; Section 3.3 boundary
+// fluxes F~(U_L, U_ghost(U_L))).
+//
+// Everything is templated on the scalar type S: double for residuals, or the
+// forward-mode dual number Dual<M> below, which carries M tangent components
+// and so returns exact flux and ghost Jacobians (the paper evaluates these
+// Jacobians by automatic differentiation).  Branches decide on the value:
+// d|x|/dx is +1 at x = 0 and max(a, b) takes a when a >= b.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace eg {
+
+template <int M>
+struct Dual {
+  double v;
+  double d[M];
+  __device__ __forceinline__ Dual() {}
+  __device__ __forceinline__ Dual(double c) : v(c) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) d[k] = 0.0;
+  }
+};
+
+__device__ __forceinline__ double val(double x) { return x; }
+template <int M> __device__ __forceinline__ double val(const Dual<M>& x) { return x.v; }
+
+template <int M> __device__ __forceinline__ Dual<M> operator+(const Dual<M>& a, const Dual<M>& b) {
+  Dual<M> r; r.v = a.v + b.v;
+#pragma unroll
+  for (int k = 0; k < M; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+template <int M> __device__ __forceinline__ Dual<M> operator-(const Dual<M>& a, const Dual<M>& b) {
+  Dual<M> r; r.v = a.v - b.v;
+#pragma unroll
+  for (int k = 0; k < M; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+template <int M> __device__ __forceinline__ Dual<M> operator-(const Dual<M>& a) {
+  Dual<M> r; r.v = -a.v;
+#pragma unroll
+  for (int k = 0; k < M; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+template <int M> __device__ __forceinline__ Dual<M> operator*(const Dual<M>& a, const Dual<M>& b) {
+  Dual<M> r; r.v = a.v * b.v;
+#pragma unroll
+  for (int k = 0; k < M; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+template <int M> __device__ __forceinline__ Dual<M> operator/(const Dual<M>& a, const Dual<M>& b) {
+  Dual<M> r; double ib = 1.0 / b.v; r.v = a.v * ib;
+#pragma unroll
+  for (int k = 0; k < M; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
+  return r;
+}
+template <int M> __device__ __forceinline__ Dual<M> operator+(const Dual<M>& a, double b) {
+  Dual<M> r = a; r.v += b; return r;
+}
+template <int M> __device__ __forceinline__ Dual<M> operator+(double b, const Dual<M>& a) { return a + b; }
+template <int M> __device__ __forceinline__ Dual<M> operator-(const Dual<M>& a, double b) {
+  Dual<M> r = a; r.v -= b; return r;
+}
+template <int M> __device__ __forceinline__ Dual<M> operator-(double b, const Dual<M>& a) {
+  Dual<M> r; r.v = b - a.v;
+#pragma unroll
+  for (int k = 0; k < M; ++k) r.d[k] = -a.d[k];
+  return r;
+}
+template <int M> __device__ __forceinline__ Dual<M> operator*(const Dual<M>& a, double b) {
+  Dual<M> r; r.v = a.v * b;
+#pragma unroll
+  for (int k = 0; k < M; ++k) r.d[k] = a.d[k] * b;
+  return r;
+}
+template <int M> __device__ __forceinline__ Dual<M> operator*(double b, const Dual<M>& a) { return a * b; }
+template <int M> __device__ __forceinline__ Dual<M> operator/(const Dual<M>& a, double b) {
+  Dual<M> r; double ib = 1.0 / b; r.v = a.v * ib;
+#pragma unroll
+  for (int k = 0; k < M; ++k) r.d[k] = a.d[k] * ib;
+  return r;
+}
+template <int M> __device__ __forceinline__ Dual<M> operator/(double a, const Dual<M>& b) {
+  Dual<M> r; double ib = 1.0 / b.v; r.v = a * ib; double s = -r.v * ib;
+#pragma unroll
+  for (int k = 0; k < M; ++k) r.d[k] = s * b.d[k];
+  return r;
+}
+
+__device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
+template <int M> __device__ __forceinline__ Dual<M> dsqrt(const Dual<M>& a) {
+  Dual<M> r; r.v = sqrt(a.v); double s = 0.5 / r.v;
+#pragma unroll
+  for (int k = 0; k < M; ++k) r.d[k] = s * a.d[k];
+  return r;
+}
+__device__ __forceinline__ double dpow(double x, double c) { return pow(x, c); }
+template <int M> __device__ __forceinline__ Dual<M> dpow(const Dual<M>& a, double c) {
+  Dual<M> r; r.v = pow(a.v, c); double s = c * r.v / a.v;
+#pragma unroll
+  for (int k = 0; k < M; ++k) r.d[k] = s * a.d[k];
+  return r;
+}
+template <class S> __device__ __forceinline__ S dabs(const S& x) { return val(x) < 0.0 ? -x : x; }
+template <class S> __device__ __forceinline__ S dmax(const S& a, const S& b) { return val(a) >= val(b) ? a : b; }
+
+
+// Pressure of the perfect gas, p = (g - 1)(rho E - |rho v|^2 / (2 rho)).
+template <int D, class S> __device__ __forceinline__ S pressure(const S* U, double g) {
+  S m2 = U[1] * U[1];
+#pragma unroll
+  for (int a = 1; a < D; ++a) m2 = m2 + U[1 + a] * U[1 + a];
+  return (g - 1.0) * (U[D + 1] - 0.5 * m2 / U[0]);
+}
+
+// F(U) . n for an arbitrary (not necessarily unit) vector n.
+template <int D, class S> __device__ __forceinline__ void flux_n(const S* U, const double* n, S* F, double g) {
+  S irho = 1.0 / U[0];
+  S un = U[1] * n[0];
+#pragma unroll
+  for (int a = 1; a < D; ++a) un = un + U[1 + a] * n[a];
+  S vn = un * irho;
+  S p = pressure<D>(U, g);
+  F[0] = un;
+#pragma unroll
+  for (int a = 0; a < D; ++a) F[1 + a] = U[1 + a] * vn + p * n[a];
+  F[D + 1] = (U[D + 1] + p) * vn;
+}
+
+// Rusanov flux: 1/2 (F(UL) + F(UR)) . n - 1/2 lambda (UR - UL),
+// lambda = max over the two sides of |v . n| + c, n a unit vector.
+template <int D, class SL, class SR, class S>
+__device__ __forceinline__ void rusanov(const SL* UL, const SR* UR, const double* nh, S* F, double g) {
+  S ul[D + 2], ur[D + 2];
+#pragma unroll
+  for (int v = 0; v < D + 2; ++v) { ul[v] = S(UL[v]); ur[v] = S(UR[v]); }
+  S FL[D + 2], FR[D + 2];
+  flux_n<D>(ul, nh, FL, g);
+  flux_n<D>(ur, nh, FR, g);
+  S unl = ul[1] * nh[0], unr = ur[1] * nh[0];
+#pragma unroll
+  for (int a = 1; a < D; ++a) { unl = unl + ul[1 + a] * nh[a]; unr = unr + ur[1 + a] * nh[a]; }
+  S cl = dsqrt(g * pressure<D>(ul, g) / ul[0]);
+  S cr = dsqrt(g * pressure<D>(ur, g) / ur[0]);
+  S lam = dmax(S(dabs(S(unl / ul[0])) + cl), S(dabs(S(unr / ur[0])) + cr));
+#pragma unroll
+  for (int v = 0; v < D + 2; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * (ur[v] - ul[v]);
+}
+
+// Slip wall: mirror the momentum about the face, rho v_g = rho v - 2 (rho v . n) n.
+template <int D, class S> __device__ __forceinline__ void ghost_wall(const S* U, const double* nh, S* G) {
+  S mn = U[1] * nh[0];
+#pragma unroll
+  for (int a = 1; a < D; ++a) mn = mn + U[1 + a] * nh[a];
+  G[0] = U[0];
+#pragma unroll
+  for (int a = 0; a < D; ++a) G[1 + a] = U[1 + a] - 2.0 * (mn * nh[a]);
+  G[D + 1] = U[D + 1];
+}
+
+// Characteristic far field from the Riemann invariants normal to the face:
+// the outgoing one (v_n + 2c/(g-1)) from inside, the incoming one from the
+// free stream; on outflow (boundary normal velocity > 0) tangential velocity
+// and entropy p / rho^g come from inside, else from the free stream.
+template <int D, class S>
+__device__ __forceinline__ void ghost_far(const S* U, const double* nh, S* G, const double* Uinf, double g) {
+  S irho = 1.0 / U[0];
+  S vi[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) vi[a] = U[1 + a] * irho;
+  S vni = vi[0] * nh[0];
+#pragma unroll
+  for (int a = 1; a < D; ++a) vni = vni + vi[a] * nh[a];
+  S pin = pressure<D>(U, g);
+  S ci = dsqrt(g * pin * irho);
+  double rinf = Uinf[0];
+  double vinf[D];
+  double vninf = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) { vinf[a] = Uinf[1 + a] / rinf; vninf += vinf[a] * nh[a]; }
+  double pinf = pressure<D>(Uinf, g);
+  double cinf = sqrt(g * pinf / rinf);
+  S rp = vni + (2.0 / (g - 1.0)) * ci;
+  double rm = vninf - (2.0 / (g - 1.0)) * cinf;
+  S vnb = 0.5 * (rp + rm);
+  S cb = (0.25 * (g - 1.0)) * (rp - rm);
+  S vt[D];
+  S ent;
+  if (val(vnb) > 0.0) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) vt[a] = vi[a] - vni * nh[a];
+    ent = pin / dpow(U[0], g);
+  } else {
+#pragma unroll
+    for (int a = 0; a < D; ++a) vt[a] = S(vinf[a] - vninf * nh[a]);
+    ent = S(pinf / pow(rinf, g));
+  }
+  S rb = dpow(S(cb * cb / (g * ent)), 1.0 / (g - 1.0));
+  S pb = rb * cb * cb / g;
+  S ke = S(0.0);
+  G[0] = rb;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    S vb = vt[a] + vnb * nh[a];
+    G[1 + a] = rb * vb;
+    ke = ke + vb * vb;
+  }
+  G[D + 1] = pb / (g - 1.0) + 0.5 * rb * ke;
+}
+
+}  // namespace eg

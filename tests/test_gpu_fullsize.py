@@ -1,0 +1,52 @@
+"""Parity at the full size of the benchmarked workload (O-grid 128 x 64, p = 3,
+8192 quads, s = 3, CFL 10, m = 30) in the launch configuration bench.py
+times: the residual and the PRK step on every element, and the first
+V-cycles from the free stream."""
+
+import numpy as np
+import pytest
+
+import oracle
+from eg_inputs import ogrid
+from tests.gpu_util import perturbed, to_dev, to_host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+MESH = ogrid(128, 64)
+
+
+@pytest.fixture(scope="module")
+def pair():
+    import paper_1807_01151_amd as P
+    O = oracle.Oracle(MESH, 3)
+    S = P.Solver(MESH, 3, rk_stages=3, cfl_max=10.0, krylov_m=30)
+    return O, S
+
+
+def test_c2_residual_full(pair):
+    O, S = pair
+    u = perturbed(O, 3, 900, amp=0.01)
+    r_o = O.residual(3, u)
+    r_g = to_host(S.residual(3, to_dev(u)))
+    assert rel_err(r_g, r_o) < 1e-12
+
+
+def test_c2_prk_full(pair):
+    O, S = pair
+    u = perturbed(O, 3, 901, amp=0.01)
+    out_o = O.prk(3, 3, 10.0, u)
+    ud = to_dev(u)
+    S.prk_step(3, 10.0, ud)
+    assert rel_err(to_host(ud) - u, out_o - u) < 1e-11
+
+
+def test_c2_first_cycles(pair):
+    O, S = pair
+    n = 3
+    u_o, h_o, _ = O.solve(O.freestream(3), s=3, m=30, cfl_max=10.0, drop=1e-10, max_cycles=n)
+    ud = S.freestream(3)
+    h_g, _ = S.solve_steady(ud, drop_tol=1e-10, max_cycles=n)
+    dev = np.abs(h_g - h_o) / h_o[0]
+    print("c2 history deviation", dev, flush=True)
+    assert dev.max() < 1e-12
+    assert rel_err(to_host(ud) - O.freestream(3), u_o - O.freestream(3)) < 1e-9

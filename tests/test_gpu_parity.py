@@ -1,0 +1,171 @@
+"""GPU parity of every step of the eMG hot path against the FP64 oracle,
+through the C ABI, on seeded perturbed states.
+
+Tolerances.  Both sides compute in FP64 with different summation orders and
+the GPU contracts to FMA, so single evaluations differ by a few ulps times the
+conditioning of the sums (cancellation between volume and face terms, <= 1e3
+on these meshes): residuals, time steps and Jacobian blocks are compared at
+1e-12 of their largest entry.  One PRK step adds an LU solve of blocks with
+condition numbers up to ~1e3 (1e-11); EXP1 adds 30 Arnoldi steps (CGS2 on
+the GPU vs MGS in the oracle, equal in exact arithmetic) and a Pade
+exponential (1e-10 of the update)."""
+
+import numpy as np
+import pytest
+
+import oracle
+from eg_inputs import ogrid, cubed_sphere_shell, box, TAG_FARFIELD
+from tests.gpu_util import perturbed, to_dev, to_host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("c1-ogrid24x12-p1", ogrid(24, 12), 1, 0.0),
+    ("ogrid16x6-p3", ogrid(16, 6), 3, 3.0),
+    ("ogrid10x3-p4", ogrid(10, 3), 4, -2.0),
+    ("box2d-skew-p2", box(2, 5, skew=0.2, seed=2, tag=TAG_FARFIELD), 2, 7.0),
+    ("sphere6x2x2x2-p1", cubed_sphere_shell(2, 2), 1, 2.0),
+    ("sphere6x2x2x2-p2", cubed_sphere_shell(2, 2), 2, 2.0),
+]
+
+
+def _solver(mesh, p, alpha, **kw):
+    import paper_1807_01151_amd as P
+    return P.Solver(mesh, p, alpha_deg=alpha, **kw)
+
+
+@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
+def test_residual_parity(name, mesh, p, alpha):
+    print("case", name, flush=True)
+    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
+    S = _solver(mesh, p, alpha)
+    for lev in range(p + 1):
+        u = perturbed(O, lev, 100 + lev)
+        r_o = O.residual(lev, u)
+        r_g = to_host(S.residual(lev, to_dev(u)))
+        assert rel_err(r_g, r_o) < 1e-12, (lev, rel_err(r_g, r_o))
+    # free stream on the GPU matches the oracle's and is preserved on far-field-only meshes
+    uf = to_host(S.freestream(p))
+    assert rel_err(uf, O.freestream(p)) < 1e-14
+
+
+def test_freestream_preservation_gpu():
+    mesh = ogrid(12, 5, inner=TAG_FARFIELD)
+    S = _solver(mesh, 3, 4.0)
+    r = to_host(S.residual(3, S.freestream(3)))
+    assert np.max(np.abs(r)) < 1e-13
+
+
+@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
+def test_timestep_parity(name, mesh, p, alpha):
+    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
+    S = _solver(mesh, p, alpha)
+    for lev in (0, p):
+        u = perturbed(O, lev, 200 + lev)
+        dt_o = O.timestep(p, 37.0, u)
+        dt_g = to_host(S.timestep(p, 37.0, to_dev(u)))
+        assert rel_err(dt_g, dt_o) < 1e-13
+
+
+@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
+def test_element_jacobian_parity(name, mesh, p, alpha):
+    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
+    S = _solver(mesh, p, alpha)
+    for lev in range(1, p + 1):
+        u = perturbed(O, lev, 300 + lev)
+        D_o = O.jacobian_blocks(lev, u)
+        D_g = to_host(S.element_jacobian(lev, to_dev(u)))
+        assert rel_err(D_g, D_o) < 1e-12, (lev, rel_err(D_g, D_o))
+
+
+@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
+def test_prk_step_parity(name, mesh, p, alpha):
+    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
+    S = _solver(mesh, p, alpha, rk_stages=3)
+    for lev in range(1, p + 1):
+        u = perturbed(O, lev, 400 + lev)
+        f = 1e-3 * np.random.default_rng(401 + lev).standard_normal(u.shape)
+        out_o = O.prk(lev, 3, 10.0, u, f)
+        ud = to_dev(u)
+        S.prk_step(lev, 10.0, ud, to_dev(f))
+        out_g = to_host(ud)
+        assert rel_err(out_g - u, out_o - u) < 1e-11, (lev, rel_err(out_g - u, out_o - u))
+
+
+@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
+def test_jacobian_p0_parity(name, mesh, p, alpha):
+    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
+    S = _solver(mesh, p, alpha)
+    u = perturbed(O, 0, 500)
+    D_o, Off_o = O.jacobian_blocks(0, u, offdiag=True)
+    Dg, Og, nb = S.jacobian_p0(to_dev(u))
+    assert rel_err(to_host(Dg), D_o) < 1e-12
+    assert rel_err(to_host(Og), Off_o) < 1e-12
+    assert np.array_equal(to_host(nb), O.neighbours())
+
+
+@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
+def test_exp1_step_parity(name, mesh, p, alpha):
+    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
+    S = _solver(mesh, p, alpha, krylov_m=30)
+    u = perturbed(O, 0, 600)
+    f = 1e-3 * np.random.default_rng(601).standard_normal(u.shape)
+    out_o, mu_o, beta_o = O.exp1(30, 20.0, u, f)
+    ud = to_dev(u)
+    _, mu_g = S.exp1_step(20.0, ud, to_dev(f))
+    out_g = to_host(ud)
+    assert mu_g == mu_o
+    assert rel_err(out_g - u, out_o - u) < 1e-10, rel_err(out_g - u, out_o - u)
+
+
+def test_exp1_happy_breakdown_parity():
+    """A mesh small enough (K_0 = 36) that m = 40 exhausts the Krylov space."""
+    mesh = ogrid(3, 3, inner=TAG_FARFIELD)
+    O = oracle.Oracle(mesh, 1)
+    S = _solver(mesh, 1, 0.0, krylov_m=40)
+    u = perturbed(O, 0, 650)
+    out_o, mu_o, _ = O.exp1(40, 5.0, u)
+    ud = to_dev(u)
+    _, mu_g = S.exp1_step(5.0, ud)
+    assert mu_g == mu_o <= 36
+    assert rel_err(to_host(ud) - u, out_o - u) < 1e-9
+
+
+@pytest.mark.parametrize("name,mesh,p,alpha", CASES[:5], ids=[c[0] for c in CASES[:5]])
+def test_vcycle_parity(name, mesh, p, alpha):
+    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
+    S = _solver(mesh, p, alpha, rk_stages=4, cfl_max=100.0, krylov_m=30)
+    u = perturbed(O, p, 700, amp=0.005)
+    r1 = O.rnorm(p, O.residual(p, u))
+    out_o, rn_o, cfl_o = O.vcycle(u, 3, s=4, m=30, cfl_max=100.0, rref=r1 * 0.5)
+    ud = to_dev(u)
+    rn_g, cfl_g = S.vcycle(ud, 3, rref=r1 * 0.5)
+    assert abs(rn_g - rn_o) <= 1e-13 * rn_o
+    assert abs(cfl_g - cfl_o) <= 1e-12 * cfl_o
+    out_g = to_host(ud)
+    assert rel_err(out_g - u, out_o - u) < 1e-10, rel_err(out_g - u, out_o - u)
+
+
+def test_rnorm_parity():
+    mesh = ogrid(16, 6)
+    O = oracle.Oracle(mesh, 3)
+    S = _solver(mesh, 3, 0.0)
+    r = O.residual(3, perturbed(O, 3, 800))
+    assert abs(S.rnorm(to_dev(r)) - O.rnorm(3, r)) <= 1e-14 * O.rnorm(3, r)
+
+
+def test_c1_history_parity():
+    """The c1 workload (O-grid 24 x 12, p = 1, s = 4, CFL_max = 100, m = 30)
+    from the free stream: residual histories agree to 1e-12 r_1 per cycle."""
+    mesh = ogrid(24, 12)
+    O = oracle.Oracle(mesh, 1)
+    S = _solver(mesh, 1, 0.0, rk_stages=4, cfl_max=100.0, krylov_m=30)
+    n = 40
+    u_o, h_o, st_o = O.solve(O.freestream(1), s=4, m=30, cfl_max=100.0, drop=1e-10, max_cycles=n)
+    ud = S.freestream(1)
+    h_g, st_g = S.solve_steady(ud, drop_tol=1e-10, max_cycles=n)
+    assert len(h_g) == len(h_o) == n + 1
+    dev = np.abs(h_g - h_o) / h_o[0]
+    print("max |dr|/r1 =", dev.max(), "at", dev.argmax(), flush=True)
+    assert dev.max() < 1e-12
+    assert rel_err(to_host(ud), u_o) < 1e-10
