@@ -1,0 +1,192 @@
+"""Benchmark of the eMG V-cycle on one MI355X.
+
+Workload: 2D cylinder, O-grid 128 x 64 quads (radius 0.5 to 20, geometric
+radial stretch), modal DG p = 3 (16 modes x 4 variables per element, 524,288
+DOF), Rusanov flux, slip wall + characteristic far field, Ma = 0.3, FP64,
+V-cycle p3 -> p2 -> p1 -> p0 with a 3-stage PRK smoother and the EXP1 step
+(Krylov dimension 30) on p0, CFL_max = 10, free-stream start.
+
+A step is one V-cycle (entry residual + norm, PRK on p = 3, 2, 1, EXP1 on
+p = 0, transfers).  value = DOF-updates/s = DOF x cycles / wall time of the
+timed cycles.  The run also reports the time to a 1e-10 residual drop from
+the free stream, the event-timed roofline of the dominant kernel, and the
+FP64 CPU oracle timed on a bounded sample on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_VALU_TFLOPS = 78.6      # MI355X FP64 vector peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def work_model(d, p):
+    """Algorithmic work per element of the three main kernels at order p."""
+    V, N, Q = d + 2, (p + 1) ** d, p + 2
+    QV, QF, NF, NC = Q ** d, Q ** (d - 1), 2 * d, 2 ** d
+    n = V * N
+    return {
+        # dense modal contractions: state at volume points, gradient projection,
+        # own and neighbour traces and face projection (2 FLOP per FMA)
+        "residual": {"flop": 2 * V * N * (QV * (1 + d) + 3 * NF * QF),
+                     "bytes": (2 * V * N + NC * d) * 8 + NF * 5},
+        # block assembly contraction + LU (2/3 n^3) of the n x n PRK block
+        "jacobian_lu": {"flop": 2 * N * N * V * V * (QV * d + NF * QF) + (2 * n ** 3) // 3,
+                        "bytes": (V * N + NC * d + N * (N + 1) // 2) * 8 + n * n * 8 + n * 4},
+        # LU solve: read the factors, permutation, residual, base state; write the stage
+        "prk_stage": {"flop": 2 * n * n, "bytes": n * n * 8 + n * 4 + 3 * n * 8},
+    }
+
+
+def roofline_entry(cls, p, ms, launches, ne, d):
+    w = work_model(d, p)[cls]
+    avg_s = ms / launches / 1e3
+    if cls == "prk_stage":
+        ach = w["bytes"] * ne / avg_s / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": None, "kernel": f"{cls} p={p}", "avg_launch_ms": ms / launches,
+                "algorithmic_bytes_per_launch": w["bytes"] * ne}
+    ach = w["flop"] * ne / avg_s / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / FP64_VALU_TFLOPS, "traffic": None, "kernel": f"{cls} p={p}",
+            "avg_launch_ms": ms / launches, "algorithmic_flop_per_launch": w["flop"] * ne}
+
+
+def cpu_baseline(mesh, budget_s=12.0):
+    """The FP64 oracle on the host cores: V-cycles of the same workload from the
+    free stream until about budget_s seconds of work (at least one cycle)."""
+    import oracle
+    O = oracle.Oracle(mesh, 3)
+    u = O.freestream(3)
+    dof = u.size
+    t0 = time.perf_counter()
+    cycles = 0
+    rref = None
+    while True:
+        u, rn, cfl = O.vcycle(u, cycles + 1, s=3, m=30, cfl_max=10.0, rref=rref if rref else 0.0)
+        if rref is None:
+            rref = rn
+        cycles += 1
+        el = time.perf_counter() - t0
+        log(f"[bench] oracle cycle {cycles}: {el:.1f}s")
+        if el > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": dof * cycles / el, "unit": "DOF-updates/s", "cores": int(oracle.lib().orc_get_threads()),
+            "kind": "oracle", "sample": f"{cycles} V-cycles of the same workload from the free stream "
+                                        f"({el:.1f} s, OpenMP threads = cores)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--drop-cycles", type=int, default=6000, help="cycle cap of the time-to-1e-10 run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-drop", action="store_true", help="skip the time-to-1e-10 run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the solver would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1807_01151_amd as P
+    from eg_inputs import ogrid
+
+    torch.cuda.set_device(0)
+    mesh = ogrid(128, 64)
+    d, p = 2, 3
+    log("[bench] init")
+    S = P.Solver(mesh, p, rk_stages=3, cfl_max=10.0, krylov_m=30, mach=0.3, alpha_deg=0.0)
+    dof = mesh.n_elem * 4 * 16
+    u = S.freestream(p)
+    # warm-up cycles
+    S.solve_steady(u, drop_tol=0.0, max_cycles=args.warmup)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {args.warmup} done")
+    # timed cycles
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.solve_steady(u, drop_tol=0.0, max_cycles=args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    log(f"[bench] timed {args.steps} cycles: {ms_per_step:.3f} ms/cycle")
+    # event-timed pass over the same number of cycles for the per-kernel roofline
+    S.profile(True)
+    S.solve_steady(u, drop_tol=0.0, max_cycles=args.steps)
+    prof = {}
+    for cls in P.binding.KERNEL_CLASSES:
+        for lev in range(p + 1):
+            ms, n = S.profile_read(cls, lev)
+            if n:
+                prof[f"{cls}@p{lev}"] = (ms, n)
+    S.profile(False)
+    tot = sum(v[0] for v in prof.values())
+    log("[bench] kernel time per cycle (ms):",
+        ", ".join(f"{k}={v[0] / args.steps:.4f}" for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])))
+    cands = [(v[0], k) for k, v in prof.items() if k.split("@")[0] in ("residual", "jacobian_lu", "prk_stage")]
+    ms_dom, key = max(cands)
+    cls, lev = key.split("@")[0], int(key.split("@p")[1])
+    roof = roofline_entry(cls, lev, prof[key][0], prof[key][1], mesh.n_elem, d)
+    roof["share_of_kernel_time"] = ms_dom / tot
+    extras = {"kernels_ms_per_cycle": {k: round(v[0] / args.steps, 5) for k, v in prof.items()}}
+    for c2 in ("residual", "jacobian_lu", "prk_stage"):
+        k2 = f"{c2}@p{p}"
+        if k2 in prof:
+            e2 = roofline_entry(c2, p, prof[k2][0], prof[k2][1], mesh.n_elem, d)
+            extras[f"roofline_{c2}_p{p}"] = {"achieved": round(e2["achieved"], 3), "unit": e2["unit"],
+                                             "frac": round(e2["frac"], 4), "bound": e2["bound"]}
+    # time to a 1e-10 residual drop from the free stream
+    drop = {}
+    if not args.no_drop:
+        u2 = S.freestream(p)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hist, st = S.solve_steady(u2, drop_tol=1e-10, max_cycles=args.drop_cycles)
+        torch.cuda.synchronize()
+        t_drop = time.perf_counter() - t1
+        drop = {"cycles_to_1e-10": int(len(hist) - 1), "time_to_1e-10_s": round(t_drop, 4),
+                "drop_reached": float(hist[-1] / hist[0]), "converged": st == 0}
+        log(f"[bench] drop run: {drop}")
+    cpu = None if args.no_cpu_baseline else cpu_baseline(mesh)
+    line = {
+        "metric": "V-cycle DOF-updates/s & time to 1e-10 residual drop, FP64 vs mixed precision",
+        "value": dof * args.steps / wall,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D cylinder O-grid 128x64 quads, DG p=3 (16 modes x 4 vars), eMG V-cycle "
+                               "p3->p0, 3-stage PRK, EXP1 Krylov m=30, CFL 10, Ma 0.3, free-stream start, FP64",
+                   "n_elem": mesh.n_elem, "dof": dof, "p_max": p, "rk_stages": 3, "krylov_m": 30,
+                   "cfl_max": 10.0, **drop},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "detail": extras,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -146,6 +146,27 @@ eg_status eg_vcycle(eg_handle* h, double* u_dev, int n, double rref, double* rn_
 eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
                           int* n_cycles_host);
 
+/* Profiling aid: HIP-event timing of the solver's own kernel launches, by
+ * kernel class and level, recorded on the handle's stream while enabled.
+ * eg_profile(h, 1) clears the records and starts recording, eg_profile(h, 0)
+ * stops; eg_profile_read sums the durations of class kernel_class at level p
+ * (p < 0: all levels).  Both synchronise the stream. */
+enum {
+  EG_K_RESIDUAL = 0,     /* DG residual */
+  EG_K_JACOBIAN_LU = 1,  /* element Jacobian block assembly + LU of the PRK block */
+  EG_K_PRK_STAGE = 2,    /* PRK stage block solve and update */
+  EG_K_TRANSFER = 3,     /* restriction, FAS forcing, prolongation, state copies */
+  EG_K_TIMESTEP = 4,     /* pseudo-time step */
+  EG_K_P0_SETUP = 5,     /* p = 0 residual, Jacobian blocks and right-hand side */
+  EG_K_ARNOLDI = 6,      /* Arnoldi process (cooperative) */
+  EG_K_PHI1 = 7,         /* phi_1 of the Hessenberg matrix */
+  EG_K_EXP1_UPDATE = 8,  /* Krylov combination of the EXP1 update */
+  EG_K_NORM = 9,         /* residual norm */
+  EG_K_COUNT = 10
+};
+eg_status eg_profile(eg_handle* h, int enable);
+eg_status eg_profile_read(eg_handle* h, int kernel_class, int p, double* total_ms, int* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,8 +13,11 @@ _lib = None
 EXPORTED_SYMBOLS = (
     "eg_init_mesh", "eg_free", "eg_last_error", "eg_sizes", "eg_set_freestream", "eg_residual",
     "eg_timestep", "eg_element_jacobian", "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm",
-    "eg_vcycle", "eg_solve_steady",
+    "eg_vcycle", "eg_solve_steady", "eg_profile", "eg_profile_read",
 )
+
+KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
+                  "phi1", "exp1_update", "norm")
 
 STATUS = {0: "EG_OK", 1: "EG_ERR_ARG", 2: "EG_ERR_MESH", 3: "EG_ERR_ALLOC", 4: "EG_ERR_HIP",
           5: "EG_ERR_NOT_CONVERGED", 6: "EG_ERR_DIVERGED", 7: "EG_ERR_UNSUPPORTED"}
@@ -67,9 +70,11 @@ def lib():
         L.eg_rnorm.argtypes = [vp, vp, pd]
         L.eg_vcycle.argtypes = [vp, vp, i, d, pd, pd]
         L.eg_solve_steady.argtypes = [vp, vp, d, i, pd, C.POINTER(i)]
+        L.eg_profile.argtypes = [vp, i]
+        L.eg_profile_read.argtypes = [vp, i, i, pd, C.POINTER(i)]
         for name in ("eg_sizes", "eg_set_freestream", "eg_residual", "eg_timestep", "eg_element_jacobian",
                      "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm", "eg_vcycle",
-                     "eg_solve_steady"):
+                     "eg_solve_steady", "eg_profile", "eg_profile_read"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -188,6 +193,16 @@ class Solver:
         cfl = C.c_double(0.0)
         self._chk(lib().eg_vcycle(self._h, _ptr(u), n, rref, C.byref(rn), C.byref(cfl)))
         return rn.value, cfl.value
+
+    def profile(self, enable: bool):
+        self._chk(lib().eg_profile(self._h, int(enable)))
+
+    def profile_read(self, kernel_class: str, p: int = -1):
+        """(total milliseconds, launches) of one kernel class at level p (-1: all)."""
+        ms = C.c_double(0.0)
+        n = C.c_int(0)
+        self._chk(lib().eg_profile_read(self._h, KERNEL_CLASSES.index(kernel_class), p, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     def solve_steady(self, u, drop_tol: float = 1e-10, max_cycles: int = 1000, raise_on_fail: bool = False):
         np = self._np

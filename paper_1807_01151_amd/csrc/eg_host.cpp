@@ -57,6 +57,12 @@ struct eg_handle {
   double* hpin = nullptr;
   int nblk_arn = 0;
   std::vector<void*> allocs;
+  // per-kernel-class event timing (eg_profile)
+  struct ProfRec { int cls, p; hipEvent_t a, b; };
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evused = 0;
+  std::vector<ProfRec> recs;
 };
 
 namespace {
@@ -205,6 +211,30 @@ eg_status dalloc(eg_handle* h, T** p, size_t count) {
   *p = static_cast<T*>(q);
   return EG_OK;
 }
+
+hipEvent_t next_event(eg_handle* h) {
+  if (h->evused == h->evpool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->evpool.push_back(e);
+  }
+  return h->evpool[h->evused++];
+}
+
+// Launch with optional event timing of kernel class cls at level p.
+#define PCALL(h, cls, p, call)                                          \
+  do {                                                                  \
+    hipEvent_t a_ = nullptr;                                            \
+    if ((h)->prof && (a_ = next_event(h))) (void)hipEventRecord(a_, (h)->st); \
+    HIPCHK(h, call);                                                    \
+    if (a_) {                                                           \
+      hipEvent_t b_ = next_event(h);                                    \
+      if (b_) {                                                         \
+        (void)hipEventRecord(b_, (h)->st);                              \
+        (h)->recs.push_back({(cls), (p), a_, b_});                      \
+      }                                                                 \
+    }                                                                   \
+  } while (0)
 
 #define ECHK(call)                 \
   do {                             \
@@ -416,10 +446,11 @@ double cfl_ramp(double cfl_max, double rn, double rref, int n, int pmax) {
 // EXP1 on the phi-coordinate p = 0 state ut0 with optional forcing ft0.
 eg_status run_exp1(eg_handle* h, double cfl, double* ut0, const double* ft0) {
   const DevMesh& M = h->M;
-  HIPCHK(h, eg::launch_p0_setup(M, ut0, ft0, h->pmax, cfl, 1, h->u0, h->b0, h->Ad, h->Ao, h->dt0, h->st));
-  HIPCHK(h, eg::launch_exp1_krylov(M, h->m, h->nblk_arn, h->Ad, h->Ao, h->b0, h->Vb, h->H, h->part1, h->part2,
-                                   h->info, h->y, h->dfail, h->st));
-  HIPCHK(h, eg::launch_exp1_update(M, h->Vb, h->y, h->info, h->u0, ut0, h->st));
+  PCALL(h, EG_K_P0_SETUP, 0, eg::launch_p0_setup(M, ut0, ft0, h->pmax, cfl, 1, h->u0, h->b0, h->Ad, h->Ao, h->dt0, h->st));
+  PCALL(h, EG_K_ARNOLDI, 0, eg::launch_arnoldi(M, h->m, h->nblk_arn, h->Ad, h->Ao, h->b0, h->Vb, h->H, h->part1,
+                                                h->part2, h->info, h->st));
+  PCALL(h, EG_K_PHI1, 0, eg::launch_phi1(h->m, h->H, h->info, h->y, h->dfail, h->st));
+  PCALL(h, EG_K_EXP1_UPDATE, 0, eg::launch_exp1_update(M, h->Vb, h->y, h->info, h->u0, ut0, h->st));
   return EG_OK;
 }
 
@@ -429,13 +460,15 @@ eg_status run_prk(eg_handle* h, int p, double cfl, const double* ft) {
   const DevMesh& M = h->M;
   const int N = nmodes_of(M.d, p), n = NB(h, p);
   const size_t K = (size_t)M.ne * n;
-  HIPCHK(h, eg::launch_timestep(M, p, N, cfl, 1.0, h->ut[p], h->dtau, h->st));
-  HIPCHK(h, eg::launch_jacobian(M, h->tabs[p], p, h->ut[p], h->dtau, h->F[p], h->perm[p], h->dfail, true, h->st));
-  HIPCHK(h, eg::launch_copy(h->ut[p], h->un[p], K, h->st));
+  PCALL(h, EG_K_TIMESTEP, p, eg::launch_timestep(M, p, N, cfl, 1.0, h->ut[p], h->dtau, h->st));
+  PCALL(h, EG_K_JACOBIAN_LU, p,
+        eg::launch_jacobian(M, h->tabs[p], p, h->ut[p], h->dtau, h->F[p], h->perm[p], h->dfail, true, h->st));
+  PCALL(h, EG_K_TRANSFER, p, eg::launch_copy(h->ut[p], h->un[p], K, h->st));
   for (int k = 1; k <= h->s; ++k) {
-    if (k > 1) HIPCHK(h, eg::launch_residual(M, h->tabs[p], p, h->ut[p], ft, h->rt[p], h->st));
+    if (k > 1) PCALL(h, EG_K_RESIDUAL, p, eg::launch_residual(M, h->tabs[p], p, h->ut[p], ft, h->rt[p], h->st));
     const double beta = 1.0 / (h->s - k + 1.0);
-    HIPCHK(h, eg::launch_prk_stage(M, n, h->F[p], h->perm[p], h->rt[p], nullptr, h->un[p], h->ut[p], beta, h->st));
+    PCALL(h, EG_K_PRK_STAGE, p,
+          eg::launch_prk_stage(M, n, h->F[p], h->perm[p], h->rt[p], nullptr, h->un[p], h->ut[p], beta, h->st));
   }
   return EG_OK;
 }
@@ -448,18 +481,19 @@ eg_status vc_rec(eg_handle* h, int p, double cfl) {
   if (p == 0) return run_exp1(h, cfl, h->ut[0], fp);
   ECHK(run_prk(h, p, cfl, fp));
   const int N = nmodes_of(M.d, p), Nc = nmodes_of(M.d, p - 1), rows = M.ne * M.V;
-  HIPCHK(h, eg::launch_residual(M, h->tabs[p], p, h->ut[p], fp, h->rt[p], h->st));
-  HIPCHK(h, eg::launch_restrict(M, p, h->ut[p], h->ut[p - 1], h->uc0[p - 1], h->st));
+  PCALL(h, EG_K_RESIDUAL, p, eg::launch_residual(M, h->tabs[p], p, h->ut[p], fp, h->rt[p], h->st));
+  PCALL(h, EG_K_TRANSFER, p, eg::launch_restrict(M, p, h->ut[p], h->ut[p - 1], h->uc0[p - 1], h->st));
   if (p - 1 >= 1) {
-    HIPCHK(h, eg::launch_residual(M, h->tabs[p - 1], p - 1, h->ut[p - 1], nullptr, h->rt[p - 1], h->st));
-    HIPCHK(h, eg::launch_fas(N, Nc, rows, h->rt[p], h->rt[p - 1], h->ft[p - 1], h->st));
+    PCALL(h, EG_K_RESIDUAL, p - 1,
+          eg::launch_residual(M, h->tabs[p - 1], p - 1, h->ut[p - 1], nullptr, h->rt[p - 1], h->st));
+    PCALL(h, EG_K_TRANSFER, p, eg::launch_fas(N, Nc, rows, h->rt[p], h->rt[p - 1], h->ft[p - 1], h->st));
   } else {
     // the p = 0 forcing needs R_0(v0): evaluate it with the residual kernel
-    HIPCHK(h, eg::launch_residual(M, h->tabs[0], 0, h->ut[0], nullptr, h->rt[0], h->st));
-    HIPCHK(h, eg::launch_fas(N, Nc, rows, h->rt[p], h->rt[0], h->ft[0], h->st));
+    PCALL(h, EG_K_RESIDUAL, 0, eg::launch_residual(M, h->tabs[0], 0, h->ut[0], nullptr, h->rt[0], h->st));
+    PCALL(h, EG_K_TRANSFER, p, eg::launch_fas(N, Nc, rows, h->rt[p], h->rt[0], h->ft[0], h->st));
   }
   ECHK(vc_rec(h, p - 1, cfl));
-  HIPCHK(h, eg::launch_prolong(N, Nc, rows, h->ut[p], h->ut[p - 1], h->uc0[p - 1], h->st));
+  PCALL(h, EG_K_TRANSFER, p, eg::launch_prolong(N, Nc, rows, h->ut[p], h->ut[p - 1], h->uc0[p - 1], h->st));
   return EG_OK;
 }
 
@@ -467,8 +501,8 @@ eg_status vc_rec(eg_handle* h, int p, double cfl) {
 eg_status entry_norm(eg_handle* h, double* rn) {
   const DevMesh& M = h->M;
   const int p = h->pmax, N = nmodes_of(M.d, p);
-  HIPCHK(h, eg::launch_residual(M, h->tabs[p], p, h->ut[p], nullptr, h->rt[p], h->st));
-  HIPCHK(h, eg::launch_norm(M, N, h->rt[p], h->npart, h->nout, h->st));
+  PCALL(h, EG_K_RESIDUAL, p, eg::launch_residual(M, h->tabs[p], p, h->ut[p], nullptr, h->rt[p], h->st));
+  PCALL(h, EG_K_NORM, p, eg::launch_norm(M, N, h->rt[p], h->npart, h->nout, h->st));
   HIPCHK(h, hipMemcpyAsync(h->hpin, h->nout, sizeof(double), hipMemcpyDeviceToHost, h->st));
   HIPCHK(h, hipMemcpyAsync(h->hpin + 1, h->dfail, sizeof(int), hipMemcpyDeviceToHost, h->st));
   ECHK(sync_status(h));
@@ -614,6 +648,7 @@ void eg_free(eg_handle* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->st);
   for (void* p : h->allocs) (void)hipFree(p);
+  for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->hpin) (void)hipHostFree(h->hpin);
   delete h;
 }
@@ -719,6 +754,32 @@ eg_status eg_rnorm(eg_handle* h, const double* r_dev, double* rn_host) {
   HIPCHK(h, hipMemcpyAsync(h->hpin, h->nout, sizeof(double), hipMemcpyDeviceToHost, h->st));
   ECHK(sync_status(h));
   *rn_host = h->hpin[0];
+  return EG_OK;
+}
+
+eg_status eg_profile(eg_handle* h, int enable) {
+  if (!h) return EG_ERR_ARG;
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  h->recs.clear();
+  h->evused = 0;
+  h->prof = enable != 0;
+  return EG_OK;
+}
+
+eg_status eg_profile_read(eg_handle* h, int kernel_class, int p, double* total_ms, int* launches) {
+  if (!h || !total_ms || !launches || kernel_class < 0 || kernel_class >= EG_K_COUNT) return EG_ERR_ARG;
+  HIPCHK(h, hipStreamSynchronize(h->st));
+  double tot = 0.0;
+  int cnt = 0;
+  for (const auto& r : h->recs) {
+    if (r.cls != kernel_class || (p >= 0 && r.p != p)) continue;
+    float ms = 0.0f;
+    HIPCHK(h, hipEventElapsedTime(&ms, r.a, r.b));
+    tot += ms;
+    cnt++;
+  }
+  *total_ms = tot;
+  *launches = cnt;
   return EG_OK;
 }
 

@@ -1065,7 +1065,8 @@ __global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, int 
   for (int it = threadIdx.x; it < nn; it += blockDim.x) {
     const int i = it / n, j = it % n;
     double v = 0.0;
-    if (i < mu && j < mu) v = H[i * mstride + j];
+    // only the Hessenberg part (i <= j + 1) is written by the Arnoldi kernel
+    if (i < mu && j < mu && i <= j + 1) v = H[i * mstride + j];
     if (i == 0 && j == mu) v = 1.0;
     B[it] = v;
   }
@@ -1470,21 +1471,19 @@ int arnoldi_max_blocks(int d) {
   return nb * prop.multiProcessorCount;
 }
 
-hipError_t launch_exp1_krylov(const DevMesh& M, int m, int nblk, const double* Ad, const double* Ao, const double* b,
-                              double* Vb, double* H, double* part1, double* part2, double* info, double* y, int* fail,
-                              hipStream_t st) {
+hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, const double* Ao, const double* b,
+                          double* Vb, double* H, double* part1, double* part2, double* info, hipStream_t st) {
   int K = M.ne * M.V;
   const int* nbr = M.nbr;
   void* args[] = {&K, &m, (void*)&nbr, (void*)&Ad, (void*)&Ao, (void*)&b, (void*)&Vb, (void*)&H,
                   (void*)&part1, (void*)&part2, (void*)&info};
-  hipError_t e;
-  if (M.d == 2)
-    e = hipLaunchCooperativeKernel((const void*)k_arnoldi<4, 4>, dim3(nblk), dim3(256), args, 0, st);
-  else
-    e = hipLaunchCooperativeKernel((const void*)k_arnoldi<5, 6>, dim3(nblk), dim3(256), args, 0, st);
-  if (e != hipSuccess) return e;
+  if (M.d == 2) return hipLaunchCooperativeKernel((const void*)k_arnoldi<4, 4>, dim3(nblk), dim3(256), args, 0, st);
+  return hipLaunchCooperativeKernel((const void*)k_arnoldi<5, 6>, dim3(nblk), dim3(256), args, 0, st);
+}
+
+hipError_t launch_phi1(int m, const double* H, const double* info, double* y, int* fail, hipStream_t st) {
   const size_t lds = (size_t)8 * (m + 1) * (m + 1) * 8;
-  e = hipFuncSetAttribute((const void*)k_phi1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = hipFuncSetAttribute((const void*)k_phi1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_phi1, dim3(1), dim3(256), lds, st, H, m, info, y, fail);
   return hipGetLastError();

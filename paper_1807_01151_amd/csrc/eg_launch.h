@@ -49,9 +49,9 @@ hipError_t launch_norm(const DevMesh& M, int N, const double* rt, double* part, 
 hipError_t launch_p0_setup(const DevMesh& M, const double* ut0, const double* ft0, int pmax, double cfl, int scale,
                            double* u0, double* b, double* Ad, double* Ao, double* dt, hipStream_t st);
 int arnoldi_max_blocks(int d);
-hipError_t launch_exp1_krylov(const DevMesh& M, int m, int nblk, const double* Ad, const double* Ao, const double* b,
-                              double* Vb, double* H, double* part1, double* part2, double* info, double* y, int* fail,
-                              hipStream_t st);
+hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, const double* Ao, const double* b,
+                          double* Vb, double* H, double* part1, double* part2, double* info, hipStream_t st);
+hipError_t launch_phi1(int m, const double* H, const double* info, double* y, int* fail, hipStream_t st);
 hipError_t launch_exp1_update(const DevMesh& M, const double* Vb, const double* y, const double* info,
                               const double* u0, double* ut0, hipStream_t st);
 hipError_t launch_copy(const double* a, double* b, size_t n, hipStream_t st);

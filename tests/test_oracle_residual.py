@@ -22,6 +22,7 @@ def perturbed(O, p, seed, amp=0.02):
 @pytest.mark.parametrize("mesh,p,alpha", [
     (ogrid(12, 5, inner=TAG_FARFIELD), 3, 4.0),
     (ogrid(16, 4, inner=TAG_FARFIELD), 1, -2.0),
+    (ogrid(10, 3, inner=TAG_FARFIELD), 4, 1.0),
     (cubed_sphere_shell(2, 2, inner=TAG_FARFIELD), 2, 3.0),
     (box(2, 4, skew=0.2, seed=1, tag=TAG_FARFIELD), 2, 10.0),
 ])
