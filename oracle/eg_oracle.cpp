@@ -1018,7 +1018,7 @@ bool phi1_e1(int m, const double* H, double* y) {
 }
 
 // ---------------------------------------------------------------------------
-// Arnoldi with modified Gram-Schmidt (Section 2.2, eqs. (vm)-(vm2)):
+// Arnoldi with (twice-swept) modified Gram-Schmidt (Section 2.2, eqs. (vm)-(vm2)):
 // A V_m = V_{m+1} H~_m, v_1 = b / ||b||.  Stops early (happy breakdown) when
 // h_{j+1,j} <= 1e-12 ||A v_j||.  Returns the number of columns used.
 // ---------------------------------------------------------------------------
@@ -1037,12 +1037,17 @@ int arnoldi(size_t K, int m, const double* b, MatVec Av, std::vector<double>& Vb
     double w0 = 0.0;
     for (size_t i = 0; i < K; ++i) w0 += w[i] * w[i];
     w0 = std::sqrt(w0);
-    for (int i = 0; i <= j; ++i) {
-      double h = 0.0;
-      const double* vi = &Vb[(size_t)i * K];
-      for (size_t k = 0; k < K; ++k) h += w[k] * vi[k];
-      H[(size_t)i * m + j] = h;
-      for (size_t k = 0; k < K; ++k) w[k] -= h * vi[k];
+    // modified Gram-Schmidt, swept twice so that V_m^T V_m = I holds to
+    // rounding (eq. (vm2) relies on it; one sweep loses orthogonality once
+    // the Krylov space is nearly exhausted)
+    for (int sweep = 0; sweep < 2; ++sweep) {
+      for (int i = 0; i <= j; ++i) {
+        double h = 0.0;
+        const double* vi = &Vb[(size_t)i * K];
+        for (size_t k = 0; k < K; ++k) h += w[k] * vi[k];
+        H[(size_t)i * m + j] += h;
+        for (size_t k = 0; k < K; ++k) w[k] -= h * vi[k];
+      }
     }
     double hn = 0.0;
     for (size_t k = 0; k < K; ++k) hn += w[k] * w[k];

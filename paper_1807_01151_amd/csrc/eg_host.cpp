@@ -722,9 +722,7 @@ eg_status eg_jacobian_p0(eg_handle* h, const double* u0_dev, double* diag_dev, d
   HIPCHK(h, eg::launch_basis(h->M, 1, u0_dev, h->tmp, 0, h->st));
   HIPCHK(h, eg::launch_p0_setup(h->M, h->tmp, nullptr, h->pmax, 1.0, 0, h->u0, h->b0, diag_dev, off_dev, h->dt0,
                                 h->st));
-  if (nbr_dev) {
-    HIPCHK(h, hipMemcpyAsync(nbr_dev, h->M.nbr, sizeof(int) * h->M.ne * h->M.NF, hipMemcpyDeviceToDevice, h->st));
-  }
+  if (nbr_dev) HIPCHK(h, eg::launch_nbr_export(h->M, nbr_dev, h->st));
   return EG_OK;
 }
 

@@ -1173,6 +1173,12 @@ __global__ __launch_bounds__(256) void k_exp1_update(int K, int V, const double*
   ut0[k] = u / Lpk[(size_t)(k / V) * NT];
 }
 
+// Neighbour table for export: element index, or -1 on any boundary face.
+__global__ void k_nbr_export(const int* __restrict__ nbr, int* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = nbr[i] >= 0 ? nbr[i] : -1;
+}
+
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = a[i];
@@ -1494,6 +1500,12 @@ hipError_t launch_exp1_update(const DevMesh& M, const double* Vb, const double* 
   const int K = M.ne * M.V;
   hipLaunchKernelGGL(k_exp1_update, dim3((K + 255) / 256), dim3(256), 0, st, K, M.V, Vb, y, info, u0, M.Lpk, M.NT,
                      ut0);
+  return hipGetLastError();
+}
+
+hipError_t launch_nbr_export(const DevMesh& M, int* out, hipStream_t st) {
+  const int n = M.ne * M.NF;
+  hipLaunchKernelGGL(k_nbr_export, dim3((n + 255) / 256), dim3(256), 0, st, M.nbr, out, n);
   return hipGetLastError();
 }
 

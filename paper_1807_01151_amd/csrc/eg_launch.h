@@ -54,6 +54,7 @@ hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, c
 hipError_t launch_phi1(int m, const double* H, const double* info, double* y, int* fail, hipStream_t st);
 hipError_t launch_exp1_update(const DevMesh& M, const double* Vb, const double* y, const double* info,
                               const double* u0, double* ut0, hipStream_t st);
+hipError_t launch_nbr_export(const DevMesh& M, int* out, hipStream_t st);
 hipError_t launch_copy(const double* a, double* b, size_t n, hipStream_t st);
 hipError_t launch_freestream(const DevMesh& M, int N, double* u, hipStream_t st);
 hipError_t launch_jac_to_psi(const DevMesh& M, int N, double* Dm, hipStream_t st);
