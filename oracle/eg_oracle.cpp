@@ -45,13 +45,27 @@ using cd = std::complex<double>;
 
 // ---------------------------------------------------------------------------
 // Scalar helpers usable with double and with complex<double> (complex-step
-// differentiation).  Branches decide on the real part; the derivative of |x|
-// is taken as +1 at x = 0 and max(a, b) picks a when re(a) >= re(b).
+// differentiation).  Branches decide on the real part.  Where |x| and
+// max(a, b) are not differentiable the Jacobian takes the symmetric
+// subgradient, so that it does not depend on which side of a face is called
+// L: d|x|/dx = 0 for |x| <= 1e-13, and at a tie of max (relative gap
+// <= 1e-12) the derivative is the average of both arguments' derivatives.
+// Values are unchanged.
 // ---------------------------------------------------------------------------
 inline double re(double x) { return x; }
 inline double re(const cd& z) { return z.real(); }
-template <class S> S cs_abs(const S& x) { return re(x) < 0.0 ? -x : x; }
-template <class S> S cs_max(const S& a, const S& b) { return re(a) >= re(b) ? a : b; }
+inline double cs_abs(double x) { return std::fabs(x); }
+inline cd cs_abs(const cd& x) {
+  if (std::fabs(x.real()) <= 1e-13) return cd(std::fabs(x.real()), 0.0);
+  return x.real() < 0.0 ? -x : x;
+}
+inline double cs_max(double a, double b) { return a >= b ? a : b; }
+inline cd cs_max(const cd& a, const cd& b) {
+  const double ra = a.real(), rb = b.real();
+  if (std::fabs(ra - rb) <= 1e-12 * std::max(std::fabs(ra), std::fabs(rb)))
+    return cd(ra >= rb ? ra : rb, 0.5 * (a.imag() + b.imag()));
+  return ra >= rb ? a : b;
+}
 inline double cs_sqrt(double x) { return std::sqrt(x); }
 inline cd cs_sqrt(const cd& z) { return std::sqrt(z); }
 inline double cs_pow(double x, double y) { return std::pow(x, y); }

@@ -6,8 +6,7 @@
 // Everything is templated on the scalar type S: double for residuals, or the
 // forward-mode dual number Dual<M> below, which carries M tangent components
 // and so returns exact flux and ghost Jacobians (the paper evaluates these
-// Jacobians by automatic differentiation).  Branches decide on the value:
-// d|x|/dx is +1 at x = 0 and max(a, b) takes a when a >= b.
+// Jacobians by automatic differentiation).  Branches decide on the value.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -105,8 +104,26 @@ template <int M> __device__ __forceinline__ Dual<M> dpow(const Dual<M>& a, doubl
   for (int k = 0; k < M; ++k) r.d[k] = s * a.d[k];
   return r;
 }
-template <class S> __device__ __forceinline__ S dabs(const S& x) { return val(x) < 0.0 ? -x : x; }
-template <class S> __device__ __forceinline__ S dmax(const S& a, const S& b) { return val(a) >= val(b) ? a : b; }
+// |x| and max(a, b): plain values; their dual-number derivatives take the
+// symmetric subgradient where the function is not differentiable (zero slope
+// for |x| <= 1e-13, the average of both slopes at a relative tie <= 1e-12 of
+// max), so a face's Jacobian does not depend on which side evaluates it.
+__device__ __forceinline__ double dabs(double x) { return fabs(x); }
+template <int M> __device__ __forceinline__ Dual<M> dabs(const Dual<M>& x) {
+  if (fabs(x.v) <= 1e-13) return Dual<M>(fabs(x.v));
+  return x.v < 0.0 ? -x : x;
+}
+__device__ __forceinline__ double dmax(double a, double b) { return a >= b ? a : b; }
+template <int M> __device__ __forceinline__ Dual<M> dmax(const Dual<M>& a, const Dual<M>& b) {
+  if (fabs(a.v - b.v) <= 1e-12 * fmax(fabs(a.v), fabs(b.v))) {
+    Dual<M> r;
+    r.v = a.v >= b.v ? a.v : b.v;
+#pragma unroll
+    for (int k = 0; k < M; ++k) r.d[k] = 0.5 * (a.d[k] + b.d[k]);
+    return r;
+  }
+  return a.v >= b.v ? a : b;
+}
 
 
 // Pressure of the perfect gas, p = (g - 1)(rho E - |rho v|^2 / (2 rho)).
