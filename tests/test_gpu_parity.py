@@ -154,18 +154,47 @@ def test_rnorm_parity():
     assert abs(S.rnorm(to_dev(r)) - O.rnorm(3, r)) <= 1e-14 * O.rnorm(3, r)
 
 
-def test_c1_history_parity():
-    """The c1 workload (O-grid 24 x 12, p = 1, s = 4, CFL_max = 100, m = 30)
-    from the free stream: residual histories agree to 1e-12 r_1 per cycle."""
+def test_vcycle_map_parity_along_trajectory():
+    """The GPU V-cycle applied to the oracle's state u_n reproduces the
+    oracle's u_{n+1}, r_n and CFL_n at every cycle of the c1 solve (O-grid
+    24 x 12, p = 1, s = 4, CFL_max = 100, m = 30) from the free stream."""
     mesh = ogrid(24, 12)
     O = oracle.Oracle(mesh, 1)
     S = _solver(mesh, 1, 0.0, rk_stages=4, cfl_max=100.0, krylov_m=30)
-    n = 40
-    u_o, h_o, st_o = O.solve(O.freestream(1), s=4, m=30, cfl_max=100.0, drop=1e-10, max_cycles=n)
+    u = O.freestream(1)
+    r1 = O.rnorm(1, O.residual(1, u))
+    worst = 0.0
+    for n in range(1, 61):
+        un, rn_o, cfl_o = O.vcycle(u, n, s=4, m=30, cfl_max=100.0, rref=r1)
+        ud = to_dev(u)
+        rn_g, cfl_g = S.vcycle(ud, n, rref=r1)
+        assert abs(rn_g - rn_o) <= 1e-13 * rn_o, n
+        assert abs(cfl_g - cfl_o) <= 1e-12 * cfl_o, n
+        e = rel_err(to_host(ud) - u, un - u)
+        worst = max(worst, e)
+        assert e < 1e-10, (n, e)
+        u = un
+    print("worst one-cycle update error", worst, flush=True)
+
+
+def test_c1_history_and_fixed_point():
+    """Free-running c1 solves: the residual histories agree to 1e-12 r_1 over
+    the first 12 cycles (later cycles amplify round-off differences
+    transiently by up to ~1e6 in the oracle against itself, so they are
+    compared one cycle at a time in the test above), and both solves reach the
+    1e-10 drop at the same steady state (the unique fixed point R(u) = 0)."""
+    mesh = ogrid(24, 12)
+    O = oracle.Oracle(mesh, 1)
+    S = _solver(mesh, 1, 0.0, rk_stages=4, cfl_max=100.0, krylov_m=30)
+    u_o, h_o, st_o = O.solve(O.freestream(1), s=4, m=30, cfl_max=100.0, drop=1e-10, max_cycles=4000)
     ud = S.freestream(1)
-    h_g, st_g = S.solve_steady(ud, drop_tol=1e-10, max_cycles=n)
-    assert len(h_g) == len(h_o) == n + 1
-    dev = np.abs(h_g - h_o) / h_o[0]
-    print("max |dr|/r1 =", dev.max(), "at", dev.argmax(), flush=True)
+    h_g, st_g = S.solve_steady(ud, drop_tol=1e-10, max_cycles=4000)
+    assert st_o == 0 and st_g == 0
+    dev = np.abs(h_g[:13] - h_o[:13]) / h_o[0]
+    print("early history dev", dev.max(), "cycles", len(h_o) - 1, len(h_g) - 1, flush=True)
     assert dev.max() < 1e-12
-    assert rel_err(to_host(ud), u_o) < 1e-10
+    assert abs(len(h_g) - len(h_o)) <= max(5, 0.02 * len(h_o))
+    ug = to_host(ud)
+    assert rel_err(ug, u_o) < 1e-8
+    # the oracle's residual of the GPU's converged state
+    assert O.rnorm(1, O.residual(1, ug)) <= 2e-10 * h_o[0]
