@@ -610,7 +610,8 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
   AL(h->H, (size_t)(h->m + 1) * h->m);
   h->nblk_arn = eg::arnoldi_max_blocks(d);
   {
-    int want = (int)((K0 + 255) / 256);
+    // a few rows per thread: fewer blocks make the grid barriers cheaper
+    int want = (int)((K0 + 1023) / 1024);
     if (h->nblk_arn <= 0) { h->err = "cooperative launch not available"; *out = h; return EG_ERR_HIP; }
     h->nblk_arn = std::max(1, std::min(h->nblk_arn, want));
   }

@@ -544,6 +544,236 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
 }
 
 // ---------------------------------------------------------------------------
+// PRK block assembly + LU for blocks of size n = V N <= 64, one wavefront per
+// element (four elements per block).  Lane r owns row r = (v, i) of
+//   Pt = G/dtau - Dt,  Dt = dRt/dut  (Section 3.3, eq. (jac1), phi coordinates)
+// in registers: the dual-number flux Jacobians of the element's volume and
+// face points go to LDS, the quadrature contraction accumulates directly
+// into the lane's row, and the LU with partial pivoting runs in registers
+// (pivot search by a wave reduction, pivot row broadcast with readlane; rows
+// are not moved, the pivot order is recorded).  Output as k_jacobian:
+// column-major factors (row k of the factor = k-th pivot row) and perm.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ ut, const double* __restrict__ xv,
+                                                    const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
+                                                    const double* __restrict__ Gpk, int NT,
+                                                    const double* __restrict__ dtau, double* __restrict__ out,
+                                                    int* __restrict__ perm, int* __restrict__ fail, int ne,
+                                                    Tab<D, P> tab, Gas gas) {
+  using C = Cfg<D, P>;
+  constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, NC = C::NC, n = C::NB;
+  static_assert(n <= 64, "one row per lane");
+  constexpr int W = 4;  // elements (wavefronts) per block
+  __shared__ Tab<D, P> t;
+  __shared__ double s_phv[QV * N];        // phi_j at volume points
+  __shared__ double s_dph[QV * D * N];    // d_r phi_i at volume points
+  __shared__ double s_phf[NF * QF * N];   // phi_j at face points
+  __shared__ double s_u[W][V * N];
+  __shared__ double s_x[W][NC * D];
+  __shared__ double s_B[W][QV * D * V * V];
+  __shared__ double s_C[W][NF * QF * V * V];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int e = blockIdx.x * W + wv;
+  const bool live = e < ne;
+  copy_tab(t, tab);
+  if (live) {
+    for (int i = lane; i < V * N; i += 64) s_u[wv][i] = ut[(size_t)e * V * N + i];
+    for (int i = lane; i < NC * D; i += 64) s_x[wv][i] = xv[(size_t)e * NC * D + i];
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < QV * N; it += blockDim.x) {
+    const int q = it / N, j = it % N;
+    int iq[D], r0 = q;
+#pragma unroll
+    for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
+    s_phv[it] = phi_vol<D, P>(t, j, iq);
+#pragma unroll
+    for (int r = 0; r < D; ++r) s_dph[(q * D + r) * N + j] = dphi_vol<D, P>(t, j, iq, r);
+  }
+  for (int it = threadIdx.x; it < NF * QF * N; it += blockDim.x) {
+    const int lf = it / (QF * N), k = (it / N) % QF, j = it % N;
+    int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1], r0 = k;
+    face_axes<D>(lf, ta);
+#pragma unroll
+    for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
+    s_phf[it] = phi_face<D, P>(t, j, lf, ta, ik);
+  }
+  __syncthreads();
+  // pointwise dual-number flux Jacobians of this wave's element
+  if (live) {
+    for (int it = lane; it < QV + NF * QF; it += 64) {
+      if (it < QV) {
+        const int q = it;
+        int iq[D], r0 = q;
+        double xi[D], wq = 1.0;
+#pragma unroll
+        for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; xi[r] = t.x[iq[r]]; wq *= t.w[iq[r]]; }
+        Dual<V> U[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          double sacc = 0.0;
+          for (int k = 0; k < N; ++k) sacc += s_u[wv][v * N + k] * s_phv[q * N + k];
+          U[v] = Dual<V>(sacc);
+          U[v].d[v] = 1.0;
+        }
+        double c[D][D], det;
+        geom<D>(s_x[wv], xi, c, det);
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+          Dual<V> F[V];
+          flux_n<D>(U, c[r], F, gas.g);
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int w = 0; w < V; ++w) s_B[wv][((q * D + r) * V + v) * V + w] = wq * F[v].d[w];
+        }
+      } else {
+        const int fi = it - QV, lf = fi / QF, k = fi % QF;
+        int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1], r0 = k;
+        face_axes<D>(lf, ta);
+        double xi[D], wk = 1.0;
+        xi[lf >> 1] = (lf & 1) ? 1.0 : -1.0;
+#pragma unroll
+        for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; xi[ta[q]] = t.x[ik[q]]; wk *= t.w[ik[q]]; }
+        Dual<V> UL[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          double sacc = 0.0;
+          for (int j = 0; j < N; ++j) sacc += s_u[wv][v * N + j] * s_phf[(lf * QF + k) * N + j];
+          UL[v] = Dual<V>(sacc);
+          UL[v].d[v] = 1.0;
+        }
+        double c[D][D], det;
+        geom<D>(s_x[wv], xi, c, det);
+        double nh[D], a2 = 0.0;
+        const double sg = (lf & 1) ? 1.0 : -1.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) { nh[a] = sg * c[lf >> 1][a]; a2 += nh[a] * nh[a]; }
+        const double area = sqrt(a2);
+#pragma unroll
+        for (int a = 0; a < D; ++a) nh[a] /= area;
+        Dual<V> F[V];
+        const int nb = nbr[(size_t)e * NF + lf];
+        if (nb >= 0) {
+          const int code = ncode[(size_t)e * NF + lf];
+          const int lf2 = code & 7;
+          int jk[D - 1 > 0 ? D - 1 : 1];
+          nb_face_index<D, Q>(code, ik, jk);
+          int jq = 0, mul = 1;
+#pragma unroll
+          for (int q = 0; q < D - 1; ++q) { jq += jk[q] * mul; mul *= Q; }
+          double UR[V];
+          const double* un = ut + (size_t)nb * V * N;
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            double sacc = 0.0;
+            for (int j = 0; j < N; ++j) sacc += un[v * N + j] * s_phf[(lf2 * QF + jq) * N + j];
+            UR[v] = sacc;
+          }
+          rusanov<D>(UL, UR, nh, F, gas.g);
+        } else {
+          Dual<V> UG[V];
+          if (nb == NB_WALL) ghost_wall<D>(UL, nh, UG);
+          else ghost_far<D>(UL, nh, UG, gas.Uinf, gas.g);
+          rusanov<D>(UL, UG, nh, F, gas.g);
+        }
+        const double wa = wk * area;
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+          for (int w = 0; w < V; ++w) s_C[wv][((lf * QF + k) * V + v) * V + w] = wa * F[v].d[w];
+      }
+    }
+  }
+  __syncthreads();
+  if (!live) return;  // no block barrier below
+  // contraction into the lane's row r = (v, i)
+  const int rr = lane < n ? lane : 0;
+  const int v = rr / N, i = rr % N;
+  double acc[n];
+#pragma unroll
+  for (int c = 0; c < n; ++c) acc[c] = 0.0;
+  for (int q = 0; q < QV; ++q) {
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      const double a = s_dph[(q * D + r) * N + i];
+      const double* B = &s_B[wv][((q * D + r) * V + v) * V];
+      double bw[V];
+#pragma unroll
+      for (int w = 0; w < V; ++w) bw[w] = a * B[w];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const double ph = s_phv[q * N + j];
+#pragma unroll
+        for (int w = 0; w < V; ++w) acc[w * N + j] += bw[w] * ph;
+      }
+    }
+  }
+  for (int fk = 0; fk < NF * QF; ++fk) {
+    const double a = s_phf[fk * N + i];
+    const double* Cm = &s_C[wv][(fk * V + v) * V];
+    double cw[V];
+#pragma unroll
+    for (int w = 0; w < V; ++w) cw[w] = a * Cm[w];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const double ph = s_phf[fk * N + j];
+#pragma unroll
+      for (int w = 0; w < V; ++w) acc[w * N + j] -= cw[w] * ph;
+    }
+  }
+  {
+    const double idt = 1.0 / dtau[e];
+    const double* G = Gpk + (size_t)e * NT;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const double gij = (i >= j) ? G[i * (i + 1) / 2 + j] : G[j * (j + 1) / 2 + i];
+#pragma unroll
+      for (int w = 0; w < V; ++w) acc[w * N + j] = ((w == v) ? gij * idt : 0.0) - acc[w * N + j];
+    }
+  }
+  // LU with partial pivoting, rows in registers
+  int mystep = (lane < n) ? -1 : n;
+#pragma unroll
+  for (int k = 0; k < n; ++k) {
+    double best = (mystep < 0) ? fabs(acc[k]) : -1.0;
+    int bl = lane;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int ol = __shfl_xor(bl, o, 64);
+      if (ob > best || (ob == best && ol < bl)) { best = ob; bl = ol; }
+    }
+    const int pl = __builtin_amdgcn_readfirstlane(bl);
+    if (lane == pl) mystep = k;
+    const double piv = readlane_d(acc[k], pl);
+    if (lane == 0 && !(fabs(piv) > 0.0)) atomicOr(fail, 1);
+    const double ipiv = 1.0 / piv;
+    const bool act = mystep < 0;
+    const double l = acc[k] * ipiv;
+    if (act) acc[k] = l;
+#pragma unroll
+    for (int j = k + 1; j < n; ++j) {
+      const double u = readlane_d(acc[j], pl);
+      if (act) acc[j] -= l * u;
+    }
+  }
+  if (lane < n) {
+    double* o = out + (size_t)e * n * n;
+#pragma unroll
+    for (int j = 0; j < n; ++j) o[(size_t)j * n + mystep] = acc[j];
+    perm[(size_t)e * n + mystep] = lane;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // PRK stage (Section 2.3, eq. (prk_scalar)) in phi coordinates:
 //   ut = un + beta Pt^{-1} (rt [+ ft]),
 // one wavefront per element, lane l owning rows l, l+64, ...; forward and
@@ -604,6 +834,53 @@ __global__ __launch_bounds__(256) void k_prk_stage(const double* __restrict__ Fm
   for (int s = 0; s < NR; ++s) {
     const int i = lane + 64 * s;
     if (i < n) ut[(size_t)e * n + i] = un[(size_t)e * n + i] + beta * b[s];
+  }
+}
+
+// PRK stage with the block size NB known at compile time: the substitution
+// loops unroll completely, the factor loads (independent of the recurrence)
+// can be issued ahead of use, and the broadcast of x_j is a readlane at a
+// constant lane.  Same data layout and arithmetic as k_prk_stage.
+template <int NB>
+__global__ __launch_bounds__(256) void k_prk_stage_t(const double* __restrict__ Fm, const int* __restrict__ perm,
+                                                     const double* __restrict__ rt, const double* __restrict__ un,
+                                                     double* __restrict__ ut, double beta, int ne) {
+  constexpr int NR = (NB + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (e >= ne) return;
+  const double* F = Fm + (size_t)e * NB * NB;
+  const double* r = rt + (size_t)e * NB;
+  const int* pm = perm + (size_t)e * NB;
+  double b[NR];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int i = lane + 64 * s;
+    b[s] = (i < NB) ? r[pm[i]] : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const double xj = readlane_d(b[j >> 6], j & 63);
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      const int i = lane + 64 * s;
+      if (i > j && i < NB) b[s] -= F[(size_t)j * NB + i] * xj;
+    }
+  }
+#pragma unroll
+  for (int j = NB - 1; j >= 0; --j) {
+    const double xj = readlane_d(b[j >> 6], j & 63) / F[(size_t)j * NB + j];
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      const int i = lane + 64 * s;
+      if (i == j) b[s] = xj;
+      else if (i < j) b[s] -= F[(size_t)j * NB + i] * xj;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const int i = lane + 64 * s;
+    if (i < NB) ut[(size_t)e * NB + i] = un[(size_t)e * NB + i] + beta * b[s];
   }
 }
 
@@ -933,6 +1210,37 @@ __device__ __forceinline__ void block_multi_sum(int cnt, F val, double* s_wave /
   __syncthreads();
 }
 
+// Deterministic sum over the nblk blocks of cnt per-block partials
+// (part[q * P + i]) into s_out[i]: all loads of a block are issued together
+// (group g of threads sums q = g, g + G, ... with four accumulators), then the
+// G group sums are added in order.  Every block computes bitwise the same
+// totals.
+__device__ __forceinline__ void grid_partials_sum(const double* __restrict__ part, int nblk, int P, int cnt,
+                                                  double* s_tmp /*[256]*/, double* s_out) {
+  const int G = blockDim.x / cnt;
+  const int t = threadIdx.x;
+  if (t < G * cnt) {
+    const int g = t / cnt, i = t % cnt;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int q = g;
+    for (; q + 3 * G < nblk; q += 4 * G) {
+      s0 += part[(size_t)q * P + i];
+      s1 += part[(size_t)(q + G) * P + i];
+      s2 += part[(size_t)(q + 2 * G) * P + i];
+      s3 += part[(size_t)(q + 3 * G) * P + i];
+    }
+    for (; q < nblk; q += G) s0 += part[(size_t)q * P + i];
+    s_tmp[g * cnt + i] = (s0 + s1) + (s2 + s3);
+  }
+  __syncthreads();
+  if (t < cnt) {
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += s_tmp[g * cnt + t];
+    s_out[t] = s;
+  }
+  __syncthreads();
+}
+
 template <int V, int NF>
 __global__ __launch_bounds__(256) void k_arnoldi(int K, int m, const int* __restrict__ nbr,
                                                  const double* __restrict__ Ad, const double* __restrict__ Ao,
@@ -943,6 +1251,7 @@ __global__ __launch_bounds__(256) void k_arnoldi(int K, int m, const int* __rest
   __shared__ double s_wave[4 * 64];
   __shared__ double s_h[64];
   __shared__ double s_g[64];
+  __shared__ double s_tmp[256];
   const int nblk = gridDim.x;
   const int stride = nblk * blockDim.x;
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -955,12 +1264,7 @@ __global__ __launch_bounds__(256) void k_arnoldi(int K, int m, const int* __rest
   }, s_wave, s_h);
   if (threadIdx.x == 0) part1[blockIdx.x * P] = s_h[0];
   grid.sync();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int q = 0; q < nblk; ++q) s += part1[q * P];
-    s_g[0] = s;
-  }
-  __syncthreads();
+  grid_partials_sum(part1, nblk, P, 1, s_tmp, s_g);
   const double beta = sqrt(s_g[0]);
   if (blockIdx.x == 0 && threadIdx.x == 0) { info[1] = beta; info[0] = 0.0; }
   if (beta == 0.0) return;  // uniform over the grid
@@ -980,12 +1284,7 @@ __global__ __launch_bounds__(256) void k_arnoldi(int K, int m, const int* __rest
     }, s_wave, s_h);
     if (threadIdx.x < j + 2) part1[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
     grid.sync();
-    if (threadIdx.x < j + 2) {
-      double s = 0.0;
-      for (int q = 0; q < nblk; ++q) s += part1[q * P + threadIdx.x];
-      s_g[threadIdx.x] = s;
-    }
-    __syncthreads();
+    grid_partials_sum(part1, nblk, P, j + 2, s_tmp, s_g);
     const double wn0 = sqrt(s_g[j + 1]);
     // first Gram-Schmidt pass, then second-pass partials and ||w||^2
     for (int k = gid; k < K; k += stride) {
@@ -1002,13 +1301,7 @@ __global__ __launch_bounds__(256) void k_arnoldi(int K, int m, const int* __rest
     }, s_wave, s_h);
     if (threadIdx.x < j + 2) part2[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
     grid.sync();
-    __syncthreads();
-    if (threadIdx.x < j + 2) {
-      double s = 0.0;
-      for (int q = 0; q < nblk; ++q) s += part2[q * P + threadIdx.x];
-      s_h[threadIdx.x] = s;
-    }
-    __syncthreads();
+    grid_partials_sum(part2, nblk, P, j + 2, s_tmp, s_h);
     double h2sq = 0.0;
     for (int i = 0; i <= j; ++i) h2sq += s_h[i] * s_h[i];
     const double hn = sqrt(fmax(s_h[j + 1] - h2sq, 0.0));
@@ -1266,6 +1559,13 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
   Tab<D, P> t;
   fill_tab(t, td);
   const size_t lds = (size_t)jac_lds_doubles<D, P>() * 8;
+  if constexpr (Cfg<D, P>::NB <= 64) {
+    if (factor) {
+      hipLaunchKernelGGL((k_jaclu_wave<D, P>), dim3((M.ne + 3) / 4), dim3(256), 0, st, ut, M.xv, M.nbr, M.ncode,
+                         M.Gpk, M.NT, dtau, out, perm, fail, M.ne, t, M.gas);
+      return hipGetLastError();
+    }
+  }
   if (factor) {
     auto kf = k_jacobian<D, P, true>;
     hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1365,6 +1665,15 @@ hipError_t launch_jacobian(const DevMesh& M, const TabData& td, int p, const dou
 hipError_t launch_prk_stage(const DevMesh& M, int n, const double* F, const int* perm, const double* rt,
                             const double* ft, const double* un, double* ut, double beta, hipStream_t st) {
   const int grid = (M.ne + 3) / 4;
+  if (!ft) {
+    switch (n) {
+      case 16: hipLaunchKernelGGL((k_prk_stage_t<16>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
+      case 36: hipLaunchKernelGGL((k_prk_stage_t<36>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
+      case 64: hipLaunchKernelGGL((k_prk_stage_t<64>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
+      case 40: hipLaunchKernelGGL((k_prk_stage_t<40>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
+      default: break;
+    }
+  }
   if (n <= 64) hipLaunchKernelGGL((k_prk_stage<1>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
   else if (n <= 128) hipLaunchKernelGGL((k_prk_stage<2>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
   else if (n <= 192) hipLaunchKernelGGL((k_prk_stage<3>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
