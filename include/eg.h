@@ -146,6 +146,14 @@ eg_status eg_vcycle(eg_handle* h, double* u_dev, int n, double rref, double* rn_
 eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
                           int* n_cycles_host);
 
+/* Continues the last eg_solve_steady / eg_solve_resume of this handle on
+ * u_dev: same r_1 and cycle numbering (the CFL ramp carries on), starting by
+ * re-evaluating the norm of the cycle at which the previous call stopped;
+ * hist_host[0..*n_cycles_host] as for eg_solve_steady.  Lets a caller run a
+ * long solve in chunks. */
+eg_status eg_solve_resume(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
+                          int* n_cycles_host);
+
 /* Profiling aid: HIP-event timing of the solver's own kernel launches, by
  * kernel class and level, recorded on the handle's stream while enabled.
  * eg_profile(h, 1) clears the records and starts recording, eg_profile(h, 0)

@@ -13,7 +13,7 @@ _lib = None
 EXPORTED_SYMBOLS = (
     "eg_init_mesh", "eg_free", "eg_last_error", "eg_sizes", "eg_set_freestream", "eg_residual",
     "eg_timestep", "eg_element_jacobian", "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm",
-    "eg_vcycle", "eg_solve_steady", "eg_profile", "eg_profile_read",
+    "eg_vcycle", "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read",
 )
 
 KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
@@ -70,11 +70,12 @@ def lib():
         L.eg_rnorm.argtypes = [vp, vp, pd]
         L.eg_vcycle.argtypes = [vp, vp, i, d, pd, pd]
         L.eg_solve_steady.argtypes = [vp, vp, d, i, pd, C.POINTER(i)]
+        L.eg_solve_resume.argtypes = [vp, vp, d, i, pd, C.POINTER(i)]
         L.eg_profile.argtypes = [vp, i]
         L.eg_profile_read.argtypes = [vp, i, i, pd, C.POINTER(i)]
         for name in ("eg_sizes", "eg_set_freestream", "eg_residual", "eg_timestep", "eg_element_jacobian",
                      "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm", "eg_vcycle",
-                     "eg_solve_steady", "eg_profile", "eg_profile_read"):
+                     "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read"):
             getattr(L, name).restype = i
         _lib = L
     return _lib
@@ -204,12 +205,13 @@ class Solver:
         self._chk(lib().eg_profile_read(self._h, KERNEL_CLASSES.index(kernel_class), p, C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
-    def solve_steady(self, u, drop_tol: float = 1e-10, max_cycles: int = 1000, raise_on_fail: bool = False):
+    def solve_steady(self, u, drop_tol: float = 1e-10, max_cycles: int = 1000, raise_on_fail: bool = False,
+                     resume: bool = False):
         np = self._np
         hist = np.zeros(max_cycles + 1)
         nc = C.c_int(0)
-        st = lib().eg_solve_steady(self._h, _ptr(u), drop_tol, max_cycles,
-                                   hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nc))
+        fn = lib().eg_solve_resume if resume else lib().eg_solve_steady
+        st = fn(self._h, _ptr(u), drop_tol, max_cycles, hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nc))
         if st not in (0, 5, 6) or (raise_on_fail and st != 0):
             self._chk(st)
         return hist[: nc.value + 1], st

@@ -60,6 +60,9 @@ struct eg_handle {
   // per-kernel-class event timing (eg_profile)
   struct ProfRec { int cls, p; hipEvent_t a, b; };
   bool prof = false;
+  // state of the last steady solve (eg_solve_resume continues it)
+  int sv_next = 0;
+  double sv_r1 = 0.0;
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
   std::vector<ProfRec> recs;
@@ -800,25 +803,26 @@ eg_status eg_vcycle(eg_handle* h, double* u_dev, int n, double rref, double* rn_
   return EG_OK;
 }
 
-eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
-                          int* n_cycles_host) {
-  if (!h || !u_dev || !hist_host || !n_cycles_host || max_cycles < 0) return EG_ERR_ARG;
-  if (!eg::jacobian_supported(h->M.d, h->pmax) && h->pmax > 0)
-    return fail(h, EG_ERR_UNSUPPORTED, "element block too large");
+namespace {
+// Cycles n = n0, n0 + 1, ...: entry norm, stop test, V-cycle.  r1 < 0 means
+// "take r_1 from this call's first norm".
+eg_status solve_loop(eg_handle* h, double* u_dev, int n0, double r1, double drop_tol, int max_cycles,
+                     double* hist_host, int* n_cycles_host) {
   const int N = nmodes_of(h->M.d, h->pmax);
   HIPCHK(h, eg::launch_basis(h->M, N, u_dev, h->ut[h->pmax], 0, h->st));
-  double r1 = 0.0;
   eg_status st = EG_OK;
-  for (int n = 1;; ++n) {
+  for (int n = n0;; ++n) {
     double rn = 0.0;
     st = entry_norm(h, &rn);
     if (st != EG_OK) break;
-    hist_host[n - 1] = rn;
-    *n_cycles_host = n - 1;
-    if (n == 1) r1 = rn;
+    hist_host[n - n0] = rn;
+    *n_cycles_host = n - n0;
+    if (r1 < 0.0) r1 = rn;
+    h->sv_next = n;
+    h->sv_r1 = r1;
     if (!std::isfinite(rn)) { st = fail(h, EG_ERR_DIVERGED, "non-finite residual norm"); break; }
     if (rn <= drop_tol * r1) break;
-    if (n - 1 == max_cycles) { st = fail(h, EG_ERR_NOT_CONVERGED, "max_cycles reached"); break; }
+    if (n - n0 == max_cycles) { st = fail(h, EG_ERR_NOT_CONVERGED, "max_cycles reached"); break; }
     const double cfl = cfl_ramp(h->cfl_max, rn, h->relr ? r1 : 1.0, n, h->pmax);
     st = vc_rec(h, h->pmax, cfl);
     if (st != EG_OK) break;
@@ -828,6 +832,22 @@ eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_
   hipError_t e2 = hipStreamSynchronize(h->st);
   if (e2 != hipSuccess && st == EG_OK) st = hipfail(h, e2, "sync");
   return st;
+}
+}  // namespace
+
+eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
+                          int* n_cycles_host) {
+  if (!h || !u_dev || !hist_host || !n_cycles_host || max_cycles < 0) return EG_ERR_ARG;
+  if (!eg::jacobian_supported(h->M.d, h->pmax) && h->pmax > 0)
+    return fail(h, EG_ERR_UNSUPPORTED, "element block too large");
+  return solve_loop(h, u_dev, 1, -1.0, drop_tol, max_cycles, hist_host, n_cycles_host);
+}
+
+eg_status eg_solve_resume(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
+                          int* n_cycles_host) {
+  if (!h || !u_dev || !hist_host || !n_cycles_host || max_cycles < 0) return EG_ERR_ARG;
+  if (h->sv_next < 1) return fail(h, EG_ERR_ARG, "no steady solve to resume");
+  return solve_loop(h, u_dev, h->sv_next, h->sv_r1, drop_tol, max_cycles, hist_host, n_cycles_host);
 }
 
 }  // extern "C"
