@@ -584,6 +584,11 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
   AL(M.hE, hE.size());
   AL(M.g2x, 2);
   AL(M.g2w, 2);
+  {
+    size_t per = 0;
+    for (int p = 1; p <= h->pmax; ++p) per = std::max(per, eg::jac_points_per_elem(d, p));
+    if (per) AL(M.bc, (size_t)ne * per);
+  }
   for (int p = 0; p <= h->pmax; ++p) {
     const size_t K = (size_t)ne * V * nmodes_of(d, p);
     AL(h->ut[p], K);
@@ -613,8 +618,9 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
   AL(h->H, (size_t)(h->m + 1) * h->m);
   h->nblk_arn = eg::arnoldi_max_blocks(d);
   {
-    // a few rows per thread: fewer blocks make the grid barriers cheaper
-    int want = (int)((K0 + 1023) / 1024);
+    // about eight rows per thread, 8..64 blocks: a grid barrier costs ~0.1 us
+    // per participating block, the per-step work is small
+    int want = std::max(8, std::min(64, (int)((K0 + 2047) / 2048)));
     if (h->nblk_arn <= 0) { h->err = "cooperative launch not available"; *out = h; return EG_ERR_HIP; }
     h->nblk_arn = std::max(1, std::min(h->nblk_arn, want));
   }

@@ -543,16 +543,122 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
   }
 }
 
+// Pointwise flux Jacobians of every (element, quadrature point), one thread
+// each: volume point q writes Bq[r][v][w] = w_q d(F_v . c_r)/dU_w (r < D),
+// face point (lf, k) writes Cf[v][w] = w_k |n dsigma| dF~_v/dU_own_w (with the
+// ghost chain rule on boundary faces), all by dual numbers.  Layout per
+// element: [QV][D][V][V] then [NF*QF][V][V].
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ ut, const double* __restrict__ xv,
+                                                    const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
+                                                    double* __restrict__ BC, int ne, Tab<D, P> tab, Gas gas) {
+  using C = Cfg<D, P>;
+  constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, NC = C::NC;
+  constexpr int NPT = QV + NF * QF;
+  constexpr int PER = (QV * D + NF * QF) * V * V;
+  __shared__ Tab<D, P> t;
+  copy_tab(t, tab);
+  __syncthreads();
+  const int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= ne * NPT) return;
+  const int e = it / NPT, pt = it % NPT;
+  const double* ue = ut + (size_t)e * V * N;
+  double X[NC * D];
+#pragma unroll
+  for (int a = 0; a < NC * D; ++a) X[a] = xv[(size_t)e * NC * D + a];
+  double* out = BC + (size_t)e * PER;
+  if (pt < QV) {
+    const int q = pt;
+    int iq[D], r0 = q;
+    double xi[D], wq = 1.0;
+#pragma unroll
+    for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; xi[r] = t.x[iq[r]]; wq *= t.w[iq[r]]; }
+    Dual<V> U[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      double sacc = 0.0;
+      for (int k = 0; k < N; ++k) sacc += ue[v * N + k] * phi_vol<D, P>(t, k, iq);
+      U[v] = Dual<V>(sacc);
+      U[v].d[v] = 1.0;
+    }
+    double c[D][D], det;
+    geom<D>(X, xi, c, det);
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      Dual<V> F[V];
+      flux_n<D>(U, c[r], F, gas.g);
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int w = 0; w < V; ++w) out[((q * D + r) * V + v) * V + w] = wq * F[v].d[w];
+    }
+  } else {
+    const int fi = pt - QV, lf = fi / QF, k = fi % QF;
+    int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1], r0 = k;
+    face_axes<D>(lf, ta);
+    double xi[D], wk = 1.0;
+    xi[lf >> 1] = (lf & 1) ? 1.0 : -1.0;
+#pragma unroll
+    for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; xi[ta[q]] = t.x[ik[q]]; wk *= t.w[ik[q]]; }
+    Dual<V> UL[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      double sacc = 0.0;
+      for (int j = 0; j < N; ++j) sacc += ue[v * N + j] * phi_face<D, P>(t, j, lf, ta, ik);
+      UL[v] = Dual<V>(sacc);
+      UL[v].d[v] = 1.0;
+    }
+    double c[D][D], det;
+    geom<D>(X, xi, c, det);
+    double nh[D], a2 = 0.0;
+    const double sg = (lf & 1) ? 1.0 : -1.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) { nh[a] = sg * c[lf >> 1][a]; a2 += nh[a] * nh[a]; }
+    const double area = sqrt(a2);
+#pragma unroll
+    for (int a = 0; a < D; ++a) nh[a] /= area;
+    Dual<V> F[V];
+    const int nb = nbr[(size_t)e * NF + lf];
+    if (nb >= 0) {
+      const int code = ncode[(size_t)e * NF + lf];
+      const int lf2 = code & 7;
+      int ta2[D - 1 > 0 ? D - 1 : 1], jk[D - 1 > 0 ? D - 1 : 1];
+      face_axes<D>(lf2, ta2);
+      nb_face_index<D, Q>(code, ik, jk);
+      double UR[V];
+      const double* un = ut + (size_t)nb * V * N;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        double sacc = 0.0;
+        for (int j = 0; j < N; ++j) sacc += un[v * N + j] * phi_face<D, P>(t, j, lf2, ta2, jk);
+        UR[v] = sacc;
+      }
+      rusanov<D>(UL, UR, nh, F, gas.g);
+    } else {
+      Dual<V> UG[V];
+      if (nb == NB_WALL) ghost_wall<D>(UL, nh, UG);
+      else ghost_far<D>(UL, nh, UG, gas.Uinf, gas.g);
+      rusanov<D>(UL, UG, nh, F, gas.g);
+    }
+    const double wa = wk * area;
+    double* o = out + QV * D * V * V + fi * V * V;
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int w = 0; w < V; ++w) o[v * V + w] = wa * F[v].d[w];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // PRK block assembly + LU for blocks of size n = V N <= 64, one wavefront per
 // element (four elements per block).  Lane r owns row r = (v, i) of
 //   Pt = G/dtau - Dt,  Dt = dRt/dut  (Section 3.3, eq. (jac1), phi coordinates)
-// in registers: the dual-number flux Jacobians of the element's volume and
-// face points go to LDS, the quadrature contraction accumulates directly
-// into the lane's row, and the LU with partial pivoting runs in registers
-// (pivot search by a wave reduction, pivot row broadcast with readlane; rows
-// are not moved, the pivot order is recorded).  Output as k_jacobian:
-// column-major factors (row k of the factor = k-th pivot row) and perm.
+// in registers: the quadrature contraction of the pointwise flux Jacobians
+// (k_jac_points) accumulates directly into the lane's row, then the LU with
+// partial pivoting runs in registers (pivot by one 32-bit wave max-reduction
+// of |a| keys, pivot row broadcast with readlane; rows are not moved, the
+// pivot order is recorded).  Output as k_jacobian: column-major factors (row
+// k of the factor = k-th pivot row) and perm.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double readlane_d(double x, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
@@ -561,32 +667,26 @@ __device__ __forceinline__ double readlane_d(double x, int lane) {
 }
 
 template <int D, int P>
-__global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ ut, const double* __restrict__ xv,
-                                                    const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
-                                                    const double* __restrict__ Gpk, int NT,
-                                                    const double* __restrict__ dtau, double* __restrict__ out,
+__global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ BC, const double* __restrict__ Gpk,
+                                                    int NT, const double* __restrict__ dtau, double* __restrict__ out,
                                                     int* __restrict__ perm, int* __restrict__ fail, int ne,
-                                                    Tab<D, P> tab, Gas gas) {
+                                                    Tab<D, P> tab) {
   using C = Cfg<D, P>;
-  constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, NC = C::NC, n = C::NB;
+  constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, n = C::NB;
   static_assert(n <= 64, "one row per lane");
   constexpr int W = 4;  // elements (wavefronts) per block
+  constexpr int PER = (QV * D + NF * QF) * V * V;
   __shared__ Tab<D, P> t;
   __shared__ double s_phv[QV * N];        // phi_j at volume points
   __shared__ double s_dph[QV * D * N];    // d_r phi_i at volume points
   __shared__ double s_phf[NF * QF * N];   // phi_j at face points
-  __shared__ double s_u[W][V * N];
-  __shared__ double s_x[W][NC * D];
-  __shared__ double s_B[W][QV * D * V * V];
-  __shared__ double s_C[W][NF * QF * V * V];
+  __shared__ double s_BC[W][PER];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int e = blockIdx.x * W + wv;
   const bool live = e < ne;
   copy_tab(t, tab);
-  if (live) {
-    for (int i = lane; i < V * N; i += 64) s_u[wv][i] = ut[(size_t)e * V * N + i];
-    for (int i = lane; i < NC * D; i += 64) s_x[wv][i] = xv[(size_t)e * NC * D + i];
-  }
+  if (live)
+    for (int i = lane; i < PER; i += 64) s_BC[wv][i] = BC[(size_t)e * PER + i];
   __syncthreads();
   for (int it = threadIdx.x; it < QV * N; it += blockDim.x) {
     const int q = it / N, j = it % N;
@@ -606,94 +706,9 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ u
     s_phf[it] = phi_face<D, P>(t, j, lf, ta, ik);
   }
   __syncthreads();
-  // pointwise dual-number flux Jacobians of this wave's element
-  if (live) {
-    for (int it = lane; it < QV + NF * QF; it += 64) {
-      if (it < QV) {
-        const int q = it;
-        int iq[D], r0 = q;
-        double xi[D], wq = 1.0;
-#pragma unroll
-        for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; xi[r] = t.x[iq[r]]; wq *= t.w[iq[r]]; }
-        Dual<V> U[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          double sacc = 0.0;
-          for (int k = 0; k < N; ++k) sacc += s_u[wv][v * N + k] * s_phv[q * N + k];
-          U[v] = Dual<V>(sacc);
-          U[v].d[v] = 1.0;
-        }
-        double c[D][D], det;
-        geom<D>(s_x[wv], xi, c, det);
-#pragma unroll
-        for (int r = 0; r < D; ++r) {
-          Dual<V> F[V];
-          flux_n<D>(U, c[r], F, gas.g);
-#pragma unroll
-          for (int v = 0; v < V; ++v)
-#pragma unroll
-            for (int w = 0; w < V; ++w) s_B[wv][((q * D + r) * V + v) * V + w] = wq * F[v].d[w];
-        }
-      } else {
-        const int fi = it - QV, lf = fi / QF, k = fi % QF;
-        int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1], r0 = k;
-        face_axes<D>(lf, ta);
-        double xi[D], wk = 1.0;
-        xi[lf >> 1] = (lf & 1) ? 1.0 : -1.0;
-#pragma unroll
-        for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; xi[ta[q]] = t.x[ik[q]]; wk *= t.w[ik[q]]; }
-        Dual<V> UL[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          double sacc = 0.0;
-          for (int j = 0; j < N; ++j) sacc += s_u[wv][v * N + j] * s_phf[(lf * QF + k) * N + j];
-          UL[v] = Dual<V>(sacc);
-          UL[v].d[v] = 1.0;
-        }
-        double c[D][D], det;
-        geom<D>(s_x[wv], xi, c, det);
-        double nh[D], a2 = 0.0;
-        const double sg = (lf & 1) ? 1.0 : -1.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) { nh[a] = sg * c[lf >> 1][a]; a2 += nh[a] * nh[a]; }
-        const double area = sqrt(a2);
-#pragma unroll
-        for (int a = 0; a < D; ++a) nh[a] /= area;
-        Dual<V> F[V];
-        const int nb = nbr[(size_t)e * NF + lf];
-        if (nb >= 0) {
-          const int code = ncode[(size_t)e * NF + lf];
-          const int lf2 = code & 7;
-          int jk[D - 1 > 0 ? D - 1 : 1];
-          nb_face_index<D, Q>(code, ik, jk);
-          int jq = 0, mul = 1;
-#pragma unroll
-          for (int q = 0; q < D - 1; ++q) { jq += jk[q] * mul; mul *= Q; }
-          double UR[V];
-          const double* un = ut + (size_t)nb * V * N;
-#pragma unroll
-          for (int v = 0; v < V; ++v) {
-            double sacc = 0.0;
-            for (int j = 0; j < N; ++j) sacc += un[v * N + j] * s_phf[(lf2 * QF + jq) * N + j];
-            UR[v] = sacc;
-          }
-          rusanov<D>(UL, UR, nh, F, gas.g);
-        } else {
-          Dual<V> UG[V];
-          if (nb == NB_WALL) ghost_wall<D>(UL, nh, UG);
-          else ghost_far<D>(UL, nh, UG, gas.Uinf, gas.g);
-          rusanov<D>(UL, UG, nh, F, gas.g);
-        }
-        const double wa = wk * area;
-#pragma unroll
-        for (int v = 0; v < V; ++v)
-#pragma unroll
-          for (int w = 0; w < V; ++w) s_C[wv][((lf * QF + k) * V + v) * V + w] = wa * F[v].d[w];
-      }
-    }
-  }
-  __syncthreads();
   if (!live) return;  // no block barrier below
+  const double* sB = s_BC[wv];
+  const double* sC = s_BC[wv] + QV * D * V * V;
   // contraction into the lane's row r = (v, i)
   const int rr = lane < n ? lane : 0;
   const int v = rr / N, i = rr % N;
@@ -704,7 +719,7 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ u
 #pragma unroll
     for (int r = 0; r < D; ++r) {
       const double a = s_dph[(q * D + r) * N + i];
-      const double* B = &s_B[wv][((q * D + r) * V + v) * V];
+      const double* B = &sB[((q * D + r) * V + v) * V];
       double bw[V];
 #pragma unroll
       for (int w = 0; w < V; ++w) bw[w] = a * B[w];
@@ -718,7 +733,7 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ u
   }
   for (int fk = 0; fk < NF * QF; ++fk) {
     const double a = s_phf[fk * N + i];
-    const double* Cm = &s_C[wv][(fk * V + v) * V];
+    const double* Cm = &sC[(fk * V + v) * V];
     double cw[V];
 #pragma unroll
     for (int w = 0; w < V; ++w) cw[w] = a * Cm[w];
@@ -743,15 +758,13 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ u
   int mystep = (lane < n) ? -1 : n;
 #pragma unroll
   for (int k = 0; k < n; ++k) {
-    double best = (mystep < 0) ? fabs(acc[k]) : -1.0;
-    int bl = lane;
+    // key: |a| as float with its 6 low mantissa bits replaced by 63 - lane
+    // (largest |a|, ties to the lowest lane); 0 for lanes already used
+    unsigned key = 0u;
+    if (mystep < 0) key = (__float_as_uint((float)fabs(acc[k])) & ~63u) | (unsigned)(63 - lane);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int ol = __shfl_xor(bl, o, 64);
-      if (ob > best || (ob == best && ol < bl)) { best = ob; bl = ol; }
-    }
-    const int pl = __builtin_amdgcn_readfirstlane(bl);
+    for (int o = 32; o > 0; o >>= 1) key = max(key, (unsigned)__shfl_xor((int)key, o, 64));
+    const int pl = __builtin_amdgcn_readfirstlane(63 - (int)(key & 63u));
     if (lane == pl) mystep = k;
     const double piv = readlane_d(acc[k], pl);
     if (lane == 0 && !(fabs(piv) > 0.0)) atomicOr(fail, 1);
@@ -1194,13 +1207,37 @@ __device__ __forceinline__ double spmv_row(int row, const int* __restrict__ nbr,
   return s;
 }
 
-// Block-wide sums of cnt per-thread values val(i), written to s_out[i].
-template <class F>
-__device__ __forceinline__ void block_multi_sum(int cnt, F val, double* s_wave /*[4][64]*/, double* s_out) {
+// Block-wide partial dot products: s_out[i] = sum over this block's rows of
+// w[k] * Vb[i][k] for i < nv, and s_out[nv] = sum of w[k]^2.  The loads of
+// eight basis vectors are issued together and their eight wave reductions
+// interleave, so the latency of global loads is paid once per group of eight.
+__device__ __forceinline__ void block_dots(int nv, int K, int gid, int stride, const double* __restrict__ w,
+                                           const double* __restrict__ Vb, double* s_wave /*[4][64]*/,
+                                           double* s_out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i = 0; i < cnt; ++i) {
-    double s = wave_sum(val(i));
-    if (lane == 0) s_wave[wv * 64 + i] = s;
+  const int cnt = nv + 1;
+  for (int i0 = 0; i0 < cnt; i0 += 8) {
+    double p[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) p[u] = 0.0;
+    for (int k = gid; k < K; k += stride) {
+      const double wk = w[k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u;
+        if (i < nv) p[u] += wk * Vb[(size_t)i * K + k];
+        else if (i == nv) p[u] += wk * wk;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p[u] += __shfl_xor(p[u], o, 64);
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < cnt) s_wave[wv * 64 + i0 + u] = p[u];
+    }
   }
   __syncthreads();
   if (threadIdx.x < cnt) {
@@ -1208,6 +1245,24 @@ __device__ __forceinline__ void block_multi_sum(int cnt, F val, double* s_wave /
     s_out[i] = s_wave[i] + s_wave[64 + i] + s_wave[128 + i] + s_wave[192 + i];
   }
   __syncthreads();
+}
+
+// w[k] -= sum_{i <= j} h[i] Vb[i][k] for this thread's rows (and optionally
+// scale by 1/hn), with independent partial sums so loads overlap.
+__device__ __forceinline__ void rows_update(int j, int K, int gid, int stride, double* __restrict__ w,
+                                            const double* __restrict__ Vb, const double* h, double scale) {
+  for (int k = gid; k < K; k += stride) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int i = 0;
+    for (; i + 3 <= j; i += 4) {
+      s0 += h[i] * Vb[(size_t)i * K + k];
+      s1 += h[i + 1] * Vb[(size_t)(i + 1) * K + k];
+      s2 += h[i + 2] * Vb[(size_t)(i + 2) * K + k];
+      s3 += h[i + 3] * Vb[(size_t)(i + 3) * K + k];
+    }
+    for (; i <= j; ++i) s0 += h[i] * Vb[(size_t)i * K + k];
+    w[k] = (w[k] - ((s0 + s1) + (s2 + s3))) * scale;
+  }
 }
 
 // Deterministic sum over the nblk blocks of cnt per-block partials
@@ -1257,11 +1312,7 @@ __global__ __launch_bounds__(256) void k_arnoldi(int K, int m, const int* __rest
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   const int P = m + 2;
   // beta = ||b||
-  block_multi_sum(1, [&](int) {
-    double s = 0.0;
-    for (int k = gid; k < K; k += stride) s += b[k] * b[k];
-    return s;
-  }, s_wave, s_h);
+  block_dots(0, K, gid, stride, b, Vb, s_wave, s_h);
   if (threadIdx.x == 0) part1[blockIdx.x * P] = s_h[0];
   grid.sync();
   grid_partials_sum(part1, nblk, P, 1, s_tmp, s_g);
@@ -1276,43 +1327,26 @@ __global__ __launch_bounds__(256) void k_arnoldi(int K, int m, const int* __rest
     double* w = Vb + (size_t)(j + 1) * K;
     // w = A v_j over this thread's rows, then partial <w, v_i> and ||w||^2
     for (int k = gid; k < K; k += stride) w[k] = spmv_row<V, NF>(k, nbr, Ad, Ao, vj);
-    block_multi_sum(j + 2, [&](int i) {
-      double s = 0.0;
-      if (i <= j) { for (int k = gid; k < K; k += stride) s += w[k] * Vb[(size_t)i * K + k]; }
-      else { for (int k = gid; k < K; k += stride) s += w[k] * w[k]; }
-      return s;
-    }, s_wave, s_h);
+    block_dots(j + 1, K, gid, stride, w, Vb, s_wave, s_h);
     if (threadIdx.x < j + 2) part1[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
     grid.sync();
     grid_partials_sum(part1, nblk, P, j + 2, s_tmp, s_g);
     const double wn0 = sqrt(s_g[j + 1]);
     // first Gram-Schmidt pass, then second-pass partials and ||w||^2
-    for (int k = gid; k < K; k += stride) {
-      double s = w[k];
-      for (int i = 0; i <= j; ++i) s -= s_g[i] * Vb[(size_t)i * K + k];
-      w[k] = s;
-    }
+    rows_update(j, K, gid, stride, w, Vb, s_g, 1.0);
     if (blockIdx.x == 0 && threadIdx.x <= j) H[threadIdx.x * m + j] = s_g[threadIdx.x];
-    block_multi_sum(j + 2, [&](int i) {
-      double s = 0.0;
-      if (i <= j) { for (int k = gid; k < K; k += stride) s += w[k] * Vb[(size_t)i * K + k]; }
-      else { for (int k = gid; k < K; k += stride) s += w[k] * w[k]; }
-      return s;
-    }, s_wave, s_h);
+    block_dots(j + 1, K, gid, stride, w, Vb, s_wave, s_h);
     if (threadIdx.x < j + 2) part2[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
     grid.sync();
     grid_partials_sum(part2, nblk, P, j + 2, s_tmp, s_h);
     double h2sq = 0.0;
     for (int i = 0; i <= j; ++i) h2sq += s_h[i] * s_h[i];
     const double hn = sqrt(fmax(s_h[j + 1] - h2sq, 0.0));
-    for (int k = gid; k < K; k += stride) {
-      double s = w[k];
-      for (int i = 0; i <= j; ++i) s -= s_h[i] * Vb[(size_t)i * K + k];
-      w[k] = (hn > 1e-12 * wn0) ? s / hn : s;
-    }
+    const bool brk = !(hn > 1e-12 * wn0);
+    rows_update(j, K, gid, stride, w, Vb, s_h, brk ? 1.0 : 1.0 / hn);
     if (blockIdx.x == 0 && threadIdx.x <= j) H[threadIdx.x * m + j] += s_h[threadIdx.x];
     if (blockIdx.x == 0 && threadIdx.x == 0) H[(j + 1) * m + j] = hn;
-    if (!(hn > 1e-12 * wn0)) { mused = j + 1; break; }
+    if (brk) { mused = j + 1; break; }
     grid.sync();
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) info[0] = (double)mused;
@@ -1560,9 +1594,14 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
   fill_tab(t, td);
   const size_t lds = (size_t)jac_lds_doubles<D, P>() * 8;
   if constexpr (Cfg<D, P>::NB <= 64) {
-    if (factor) {
-      hipLaunchKernelGGL((k_jaclu_wave<D, P>), dim3((M.ne + 3) / 4), dim3(256), 0, st, ut, M.xv, M.nbr, M.ncode,
-                         M.Gpk, M.NT, dtau, out, perm, fail, M.ne, t, M.gas);
+    if (factor && M.bc) {
+      using C = Cfg<D, P>;
+      constexpr int NPT = C::QV + C::NF * C::QF;
+      const int items = M.ne * NPT;
+      hipLaunchKernelGGL((k_jac_points<D, P>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.nbr, M.ncode,
+                         M.bc, M.ne, t, M.gas);
+      hipLaunchKernelGGL((k_jaclu_wave<D, P>), dim3((M.ne + 3) / 4), dim3(256), 0, st, M.bc, M.Gpk, M.NT, dtau, out,
+                         perm, fail, M.ne, t);
       return hipGetLastError();
     }
   }
@@ -1631,6 +1670,13 @@ hipError_t launch_residual(const DevMesh& M, const TabData& td, int p, const dou
   else { EG_DISPATCH_P(3, p, CALL_RES) }
 #undef CALL_RES
   return hipErrorInvalidValue;
+}
+
+size_t jac_points_per_elem(int d, int p) {
+  const int V = d + 2, Q = p + 2, N = (d == 2) ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
+  if (p < 1 || V * N > 64) return 0;
+  const int QV = (d == 2) ? Q * Q : Q * Q * Q, QF = (d == 2) ? Q : Q * Q;
+  return (size_t)(QV * d + 2 * d * QF) * V * V;
 }
 
 bool jacobian_supported(int d, int p) {

@@ -23,7 +23,12 @@ struct DevMesh {
   double* hE = nullptr;    // [E] 2 d |E| / |dE|
   double* g2x = nullptr;   // 2-point Gauss rule (p = 0 faces)
   double* g2w = nullptr;
+  double* bc = nullptr;    // pointwise flux-Jacobian scratch of the block assembly
 };
+
+// doubles per element of the pointwise flux-Jacobian scratch at order p (0 if
+// the order uses the single-kernel assembly)
+size_t jac_points_per_elem(int d, int p);
 
 // Host copy of the 1D tables of one order (filled by the set-up code).
 struct TabData {
