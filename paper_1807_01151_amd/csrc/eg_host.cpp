@@ -50,6 +50,8 @@ struct eg_handle {
   double* part1 = nullptr;
   double* part2 = nullptr;
   double* info = nullptr;
+  int* arn_st = nullptr;
+  double* arn_wn0 = nullptr;
   double* y = nullptr;
   double* npart = nullptr;
   double* nout = nullptr;
@@ -451,7 +453,7 @@ eg_status run_exp1(eg_handle* h, double cfl, double* ut0, const double* ft0) {
   const DevMesh& M = h->M;
   PCALL(h, EG_K_P0_SETUP, 0, eg::launch_p0_setup(M, ut0, ft0, h->pmax, cfl, 1, h->u0, h->b0, h->Ad, h->Ao, h->dt0, h->st));
   PCALL(h, EG_K_ARNOLDI, 0, eg::launch_arnoldi(M, h->m, h->nblk_arn, h->Ad, h->Ao, h->b0, h->Vb, h->H, h->part1,
-                                                h->part2, h->info, h->st));
+                                                h->part2, h->info, h->arn_st, h->arn_wn0, h->st));
   PCALL(h, EG_K_PHI1, 0, eg::launch_phi1(h->m, h->H, h->info, h->y, h->dfail, h->st));
   PCALL(h, EG_K_EXP1_UPDATE, 0, eg::launch_exp1_update(M, h->Vb, h->y, h->info, h->u0, ut0, h->st));
   return EG_OK;
@@ -616,17 +618,12 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
   AL(h->dt0, ne);
   AL(h->Vb, (size_t)(h->m + 1) * K0);
   AL(h->H, (size_t)(h->m + 1) * h->m);
-  h->nblk_arn = eg::arnoldi_max_blocks(d);
-  {
-    // about eight rows per thread, 8..64 blocks: a grid barrier costs ~0.1 us
-    // per participating block, the per-step work is small
-    int want = std::max(8, std::min(64, (int)((K0 + 2047) / 2048)));
-    if (h->nblk_arn <= 0) { h->err = "cooperative launch not available"; *out = h; return EG_ERR_HIP; }
-    h->nblk_arn = std::max(1, std::min(h->nblk_arn, want));
-  }
+  h->nblk_arn = eg::arnoldi_blocks((int)K0);
   AL(h->part1, (size_t)h->nblk_arn * (h->m + 2));
   AL(h->part2, (size_t)h->nblk_arn * (h->m + 2));
   AL(h->info, 2);
+  AL(h->arn_st, 2);
+  AL(h->arn_wn0, 1);
   AL(h->y, h->m + 1);
   AL(h->npart, (size_t)(ne + 255) / 256 + 1);
   AL(h->nout, 1);

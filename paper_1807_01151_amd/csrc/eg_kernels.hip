@@ -21,14 +21,12 @@
 //   Cholesky / mass  packed lower triangle [E][NT], NT = N(N+1)/2 of p_max
 //   block factors    [E][n][n] column-major LU (unit L), perm int32 [E][n]
 
-#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "eg_common.h"
 #include "eg_launch.h"
 #include "eg_physics.h"
 
-namespace cg = cooperative_groups;
 
 namespace eg {
 
@@ -1179,13 +1177,13 @@ __global__ __launch_bounds__(128) void k_p0_setup(const double* __restrict__ ut0
 }
 
 // ---------------------------------------------------------------------------
-// Arnoldi process of EXP1 (Section 2.2, eqs. (vm)-(vm2)) as one cooperative
-// kernel: classical Gram-Schmidt with one re-orthogonalisation (CGS2), the
-// block sparse product y = A x with A = T J0, and deterministic grid
-// reductions (every block sums the per-block partials in the same order, so
-// all blocks take identical decisions).  Three grid barriers per step.
-// Output: basis Vb[j][K], Hessenberg H[(m+1) x m] row-major, info[0] = m
-// used, info[1] = beta = ||b||.
+// Arnoldi process of EXP1 (Section 2.2, eqs. (vm)-(vm2)): classical
+// Gram-Schmidt with one re-orthogonalisation (CGS2), the block sparse
+// product y = A x with A = T J0, and deterministic reductions (every block
+// sums the per-block partials in the same order, so all blocks take
+// identical decisions).  Output: basis Vb[j][K], Hessenberg H[(m+1) x m]
+// row-major, info[0] = Krylov dimension used, info[1] = beta = ||b||.
+// Helpers first: one row of the block-sparse product, block partial dots.
 // ---------------------------------------------------------------------------
 template <int V, int NF>
 __device__ __forceinline__ double spmv_row(int row, const int* __restrict__ nbr, const double* __restrict__ Ad,
@@ -1296,60 +1294,97 @@ __device__ __forceinline__ void grid_partials_sum(const double* __restrict__ par
   __syncthreads();
 }
 
+// Arnoldi process of EXP1 as a sequence of full-grid kernels (a kernel
+// boundary is the global barrier; on this GPU it is several times cheaper
+// than a cooperative grid barrier): per step j
+//   a) w = A v_j on every row + per-block partials of <w, v_i>, ||w||^2
+//   b) h1 = sum of partials (every block, same order), w -= V h1, partials again
+//   c) h2, hn = sqrt(||w||^2 - ||h2||^2); H(:, j) = h1 + h2, H(j+1, j) = hn;
+//      w = (w - V h2) / hn, or happy breakdown (hn <= 1e-12 ||A v_j||): the
+//      flag st[0] makes every later kernel return, st[1] = Krylov dimension.
+// info[0] = dimension used, info[1] = beta.
+__global__ __launch_bounds__(256) void k_arn_beta(int K, const double* __restrict__ b, double* __restrict__ part,
+                                                  int P, int* __restrict__ st) {
+  __shared__ double s_wave[4 * 64];
+  __shared__ double s_h[64];
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  block_dots(0, K, gid, gridDim.x * blockDim.x, b, b, s_wave, s_h);
+  if (threadIdx.x == 0) part[blockIdx.x * P] = s_h[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) { st[0] = 0; st[1] = 0; }
+}
+
+__global__ __launch_bounds__(256) void k_arn_start(int K, int m, const double* __restrict__ b,
+                                                   const double* __restrict__ part, int P, double* __restrict__ Vb,
+                                                   double* __restrict__ info, int* __restrict__ st) {
+  __shared__ double s_tmp[256];
+  __shared__ double s_g[64];
+  grid_partials_sum(part, gridDim.x, P, 1, s_tmp, s_g);
+  const double beta = sqrt(s_g[0]);
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    info[1] = beta;
+    info[0] = (beta == 0.0) ? 0.0 : (double)m;
+    if (beta == 0.0) st[0] = 1;
+  }
+  if (beta == 0.0) return;
+  for (int k = gid; k < K; k += gridDim.x * blockDim.x) Vb[k] = b[k] / beta;
+}
+
 template <int V, int NF>
-__global__ __launch_bounds__(256) void k_arnoldi(int K, int m, const int* __restrict__ nbr,
-                                                 const double* __restrict__ Ad, const double* __restrict__ Ao,
-                                                 const double* __restrict__ b, double* __restrict__ Vb,
-                                                 double* __restrict__ H, double* __restrict__ part1,
-                                                 double* __restrict__ part2, double* __restrict__ info) {
-  cg::grid_group grid = cg::this_grid();
+__global__ __launch_bounds__(256) void k_arn_a(int K, int j, const int* __restrict__ nbr,
+                                               const double* __restrict__ Ad, const double* __restrict__ Ao,
+                                               double* __restrict__ Vb, double* __restrict__ part, int P,
+                                               const int* __restrict__ st) {
+  if (st[0]) return;
+  __shared__ double s_wave[4 * 64];
+  __shared__ double s_h[64];
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  const double* vj = Vb + (size_t)j * K;
+  double* w = Vb + (size_t)(j + 1) * K;
+  for (int k = gid; k < K; k += stride) w[k] = spmv_row<V, NF>(k, nbr, Ad, Ao, vj);
+  block_dots(j + 1, K, gid, stride, w, Vb, s_wave, s_h);
+  if (threadIdx.x < j + 2) part[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_arn_b(int K, int m, int j, double* __restrict__ Vb,
+                                               const double* __restrict__ part1, double* __restrict__ part2, int P,
+                                               double* __restrict__ H, double* __restrict__ wn0,
+                                               const int* __restrict__ st) {
+  if (st[0]) return;
   __shared__ double s_wave[4 * 64];
   __shared__ double s_h[64];
   __shared__ double s_g[64];
   __shared__ double s_tmp[256];
-  const int nblk = gridDim.x;
-  const int stride = nblk * blockDim.x;
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int P = m + 2;
-  // beta = ||b||
-  block_dots(0, K, gid, stride, b, Vb, s_wave, s_h);
-  if (threadIdx.x == 0) part1[blockIdx.x * P] = s_h[0];
-  grid.sync();
-  grid_partials_sum(part1, nblk, P, 1, s_tmp, s_g);
-  const double beta = sqrt(s_g[0]);
-  if (blockIdx.x == 0 && threadIdx.x == 0) { info[1] = beta; info[0] = 0.0; }
-  if (beta == 0.0) return;  // uniform over the grid
-  for (int k = gid; k < K; k += stride) Vb[k] = b[k] / beta;
-  int mused = m;
-  grid.sync();
-  for (int j = 0; j < m; ++j) {
-    const double* vj = Vb + (size_t)j * K;
-    double* w = Vb + (size_t)(j + 1) * K;
-    // w = A v_j over this thread's rows, then partial <w, v_i> and ||w||^2
-    for (int k = gid; k < K; k += stride) w[k] = spmv_row<V, NF>(k, nbr, Ad, Ao, vj);
-    block_dots(j + 1, K, gid, stride, w, Vb, s_wave, s_h);
-    if (threadIdx.x < j + 2) part1[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
-    grid.sync();
-    grid_partials_sum(part1, nblk, P, j + 2, s_tmp, s_g);
-    const double wn0 = sqrt(s_g[j + 1]);
-    // first Gram-Schmidt pass, then second-pass partials and ||w||^2
-    rows_update(j, K, gid, stride, w, Vb, s_g, 1.0);
-    if (blockIdx.x == 0 && threadIdx.x <= j) H[threadIdx.x * m + j] = s_g[threadIdx.x];
-    block_dots(j + 1, K, gid, stride, w, Vb, s_wave, s_h);
-    if (threadIdx.x < j + 2) part2[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
-    grid.sync();
-    grid_partials_sum(part2, nblk, P, j + 2, s_tmp, s_h);
-    double h2sq = 0.0;
-    for (int i = 0; i <= j; ++i) h2sq += s_h[i] * s_h[i];
-    const double hn = sqrt(fmax(s_h[j + 1] - h2sq, 0.0));
-    const bool brk = !(hn > 1e-12 * wn0);
-    rows_update(j, K, gid, stride, w, Vb, s_h, brk ? 1.0 : 1.0 / hn);
-    if (blockIdx.x == 0 && threadIdx.x <= j) H[threadIdx.x * m + j] += s_h[threadIdx.x];
-    if (blockIdx.x == 0 && threadIdx.x == 0) H[(j + 1) * m + j] = hn;
-    if (brk) { mused = j + 1; break; }
-    grid.sync();
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  double* w = Vb + (size_t)(j + 1) * K;
+  grid_partials_sum(part1, gridDim.x, P, j + 2, s_tmp, s_g);
+  rows_update(j, K, gid, stride, w, Vb, s_g, 1.0);
+  if (blockIdx.x == 0 && threadIdx.x <= j) H[threadIdx.x * m + j] = s_g[threadIdx.x];
+  if (blockIdx.x == 0 && threadIdx.x == 0) wn0[0] = sqrt(s_g[j + 1]);
+  block_dots(j + 1, K, gid, stride, w, Vb, s_wave, s_h);
+  if (threadIdx.x < j + 2) part2[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_arn_c(int K, int m, int j, double* __restrict__ Vb,
+                                               const double* __restrict__ part2, int P, double* __restrict__ H,
+                                               const double* __restrict__ wn0, double* __restrict__ info,
+                                               int* __restrict__ st) {
+  if (st[0]) return;
+  __shared__ double s_h[64];
+  __shared__ double s_tmp[256];
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  double* w = Vb + (size_t)(j + 1) * K;
+  grid_partials_sum(part2, gridDim.x, P, j + 2, s_tmp, s_h);
+  double h2sq = 0.0;
+  for (int i = 0; i <= j; ++i) h2sq += s_h[i] * s_h[i];
+  const double hn = sqrt(fmax(s_h[j + 1] - h2sq, 0.0));
+  const bool brk = !(hn > 1e-12 * wn0[0]);
+  rows_update(j, K, gid, stride, w, Vb, s_h, brk ? 1.0 : 1.0 / hn);
+  if (blockIdx.x == 0 && threadIdx.x <= j) H[threadIdx.x * m + j] += s_h[threadIdx.x];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    H[(j + 1) * m + j] = hn;
+    if (brk) { st[0] = 1; info[0] = (double)(j + 1); }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) info[0] = (double)mused;
 }
 
 // ---------------------------------------------------------------------------
@@ -1820,26 +1855,24 @@ hipError_t launch_p0_setup(const DevMesh& M, const double* ut0, const double* ft
   return hipGetLastError();
 }
 
-int arnoldi_max_blocks(int d) {
-  int nb = 0, dev = 0;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-  hipError_t e;
-  if (d == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_arnoldi<4, 4>, 256, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_arnoldi<5, 6>, 256, 0);
-  if (e != hipSuccess) return 0;
-  return nb * prop.multiProcessorCount;
-}
+int arnoldi_blocks(int K) { return (K + 255) / 256; }
 
 hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, const double* Ao, const double* b,
-                          double* Vb, double* H, double* part1, double* part2, double* info, hipStream_t st) {
-  int K = M.ne * M.V;
-  const int* nbr = M.nbr;
-  void* args[] = {&K, &m, (void*)&nbr, (void*)&Ad, (void*)&Ao, (void*)&b, (void*)&Vb, (void*)&H,
-                  (void*)&part1, (void*)&part2, (void*)&info};
-  if (M.d == 2) return hipLaunchCooperativeKernel((const void*)k_arnoldi<4, 4>, dim3(nblk), dim3(256), args, 0, st);
-  return hipLaunchCooperativeKernel((const void*)k_arnoldi<5, 6>, dim3(nblk), dim3(256), args, 0, st);
+                          double* Vb, double* H, double* part1, double* part2, double* info, int* st,
+                          double* wn0, hipStream_t stream) {
+  const int K = M.ne * M.V;
+  const int P = m + 2;
+  hipLaunchKernelGGL(k_arn_beta, dim3(nblk), dim3(256), 0, stream, K, b, part1, P, st);
+  hipLaunchKernelGGL(k_arn_start, dim3(nblk), dim3(256), 0, stream, K, m, b, part1, P, Vb, info, st);
+  for (int j = 0; j < m; ++j) {
+    if (M.d == 2)
+      hipLaunchKernelGGL((k_arn_a<4, 4>), dim3(nblk), dim3(256), 0, stream, K, j, M.nbr, Ad, Ao, Vb, part1, P, st);
+    else
+      hipLaunchKernelGGL((k_arn_a<5, 6>), dim3(nblk), dim3(256), 0, stream, K, j, M.nbr, Ad, Ao, Vb, part1, P, st);
+    hipLaunchKernelGGL(k_arn_b, dim3(nblk), dim3(256), 0, stream, K, m, j, Vb, part1, part2, P, H, wn0, st);
+    hipLaunchKernelGGL(k_arn_c, dim3(nblk), dim3(256), 0, stream, K, m, j, Vb, part2, P, H, wn0, info, st);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_phi1(int m, const double* H, const double* info, double* y, int* fail, hipStream_t st) {

@@ -53,9 +53,10 @@ hipError_t launch_timestep(const DevMesh& M, int p, int N, double cfl, double mu
 hipError_t launch_norm(const DevMesh& M, int N, const double* rt, double* part, double* out, hipStream_t st);
 hipError_t launch_p0_setup(const DevMesh& M, const double* ut0, const double* ft0, int pmax, double cfl, int scale,
                            double* u0, double* b, double* Ad, double* Ao, double* dt, hipStream_t st);
-int arnoldi_max_blocks(int d);
+int arnoldi_blocks(int K);
 hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, const double* Ao, const double* b,
-                          double* Vb, double* H, double* part1, double* part2, double* info, hipStream_t st);
+                          double* Vb, double* H, double* part1, double* part2, double* info, int* st, double* wn0,
+                          hipStream_t stream);
 hipError_t launch_phi1(int m, const double* H, const double* info, double* y, int* fail, hipStream_t st);
 hipError_t launch_exp1_update(const DevMesh& M, const double* Vb, const double* y, const double* info,
                               const double* u0, double* ut0, hipStream_t st);
