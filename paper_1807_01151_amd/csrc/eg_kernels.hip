@@ -679,6 +679,7 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ B
   __shared__ double s_dph[QV * D * N];    // d_r phi_i at volume points
   __shared__ double s_phf[NF * QF * N];   // phi_j at face points
   __shared__ double s_BC[W][PER];
+  __shared__ __align__(16) double s_row[W][64];  // pivot row broadcast
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int e = blockIdx.x * W + wv;
   const bool live = e < ne;
@@ -752,7 +753,11 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ B
       for (int w = 0; w < V; ++w) acc[w * N + j] = ((w == v) ? gij * idt : 0.0) - acc[w * N + j];
     }
   }
-  // LU with partial pivoting, rows in registers
+  // LU with partial pivoting, rows in registers.  The pivot lane writes its
+  // (final) U row to LDS once; every lane reads it back with 128-bit
+  // broadcast loads.  Lanes already used as pivots get a zero multiplier, so
+  // the update below leaves their rows unchanged without a branch.
+  double* srow = s_row[wv];
   int mystep = (lane < n) ? -1 : n;
 #pragma unroll
   for (int k = 0; k < n; ++k) {
@@ -763,18 +768,22 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ B
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) key = max(key, (unsigned)__shfl_xor((int)key, o, 64));
     const int pl = __builtin_amdgcn_readfirstlane(63 - (int)(key & 63u));
-    if (lane == pl) mystep = k;
-    const double piv = readlane_d(acc[k], pl);
-    if (lane == 0 && !(fabs(piv) > 0.0)) atomicOr(fail, 1);
-    const double ipiv = 1.0 / piv;
-    const bool act = mystep < 0;
-    const double l = acc[k] * ipiv;
-    if (act) acc[k] = l;
+    if (lane == pl) {
+      mystep = k;
 #pragma unroll
-    for (int j = k + 1; j < n; ++j) {
-      const double u = readlane_d(acc[j], pl);
-      if (act) acc[j] -= l * u;
+      for (int j = k; j < n; ++j) srow[j] = acc[j];
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const double piv = srow[k];
+    if (lane == 0 && !(fabs(piv) > 0.0)) atomicOr(fail, 1);
+    const double l = (mystep < 0) ? acc[k] * (1.0 / piv) : 0.0;
+    if (mystep < 0) acc[k] = l;
+#pragma unroll
+    for (int j = k + 1; j < n; ++j) acc[j] = fma(-l, srow[j], acc[j]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
   if (lane < n) {
     double* o = out + (size_t)e * n * n;
@@ -848,51 +857,38 @@ __global__ __launch_bounds__(256) void k_prk_stage(const double* __restrict__ Fm
   }
 }
 
-// PRK stage with the block size NB known at compile time: the substitution
-// loops unroll completely, the factor loads (independent of the recurrence)
-// can be issued ahead of use, and the broadcast of x_j is a readlane at a
-// constant lane.  Same data layout and arithmetic as k_prk_stage.
+// PRK stage for block sizes NB <= 64: lane i first loads its whole factor
+// row (column-major storage, so each column load is coalesced over the lanes
+// and all NB loads are independent and in flight together), then runs the
+// forward and back substitution in registers, broadcasting x_j with readlane
+// at a constant lane.  Same arithmetic as k_prk_stage.
 template <int NB>
 __global__ __launch_bounds__(256) void k_prk_stage_t(const double* __restrict__ Fm, const int* __restrict__ perm,
                                                      const double* __restrict__ rt, const double* __restrict__ un,
                                                      double* __restrict__ ut, double beta, int ne) {
-  constexpr int NR = (NB + 63) / 64;
+  static_assert(NB <= 64, "one row per lane");
   const int lane = threadIdx.x & 63;
   const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (e >= ne) return;
   const double* F = Fm + (size_t)e * NB * NB;
-  const double* r = rt + (size_t)e * NB;
-  const int* pm = perm + (size_t)e * NB;
-  double b[NR];
+  const int i = lane < NB ? lane : NB - 1;
+  double row[NB];
 #pragma unroll
-  for (int s = 0; s < NR; ++s) {
-    const int i = lane + 64 * s;
-    b[s] = (i < NB) ? r[pm[i]] : 0.0;
-  }
+  for (int j = 0; j < NB; ++j) row[j] = F[(size_t)j * NB + i];
+  double b = rt[(size_t)e * NB + perm[(size_t)e * NB + i]];
+  // L y = b (unit diagonal): rows below j subtract L(i, j) y_j
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const double xj = readlane_d(b[j >> 6], j & 63);
-#pragma unroll
-    for (int s = 0; s < NR; ++s) {
-      const int i = lane + 64 * s;
-      if (i > j && i < NB) b[s] -= F[(size_t)j * NB + i] * xj;
-    }
+    const double xj = readlane_d(b, j);
+    b = fma(-((lane > j) ? row[j] : 0.0), xj, b);
   }
+  // U x = y
 #pragma unroll
   for (int j = NB - 1; j >= 0; --j) {
-    const double xj = readlane_d(b[j >> 6], j & 63) / F[(size_t)j * NB + j];
-#pragma unroll
-    for (int s = 0; s < NR; ++s) {
-      const int i = lane + 64 * s;
-      if (i == j) b[s] = xj;
-      else if (i < j) b[s] -= F[(size_t)j * NB + i] * xj;
-    }
+    const double xj = readlane_d(b, j) / readlane_d(row[j], j);
+    b = (lane == j) ? xj : fma(-((lane < j) ? row[j] : 0.0), xj, b);
   }
-#pragma unroll
-  for (int s = 0; s < NR; ++s) {
-    const int i = lane + 64 * s;
-    if (i < NB) ut[(size_t)e * NB + i] = un[(size_t)e * NB + i] + beta * b[s];
-  }
+  if (lane < NB) ut[(size_t)e * NB + lane] = un[(size_t)e * NB + lane] + beta * b;
 }
 
 // ---------------------------------------------------------------------------
