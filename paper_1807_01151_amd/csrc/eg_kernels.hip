@@ -714,6 +714,7 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ B
   double acc[n];
 #pragma unroll
   for (int c = 0; c < n; ++c) acc[c] = 0.0;
+#pragma unroll 1
   for (int q = 0; q < QV; ++q) {
 #pragma unroll
     for (int r = 0; r < D; ++r) {
@@ -730,6 +731,7 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ B
       }
     }
   }
+#pragma unroll 1
   for (int fk = 0; fk < NF * QF; ++fk) {
     const double a = s_phf[fk * N + i];
     const double* Cm = &sC[(fk * V + v) * V];
