@@ -135,6 +135,24 @@ __device__ __forceinline__ void copy_tab(Tab<D, P>& dst, const Tab<D, P>& src) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
 }
 
+// Copies cnt doubles from global memory into LDS; each thread issues all of
+// its (at most ITEMS) loads before its stores, so the global latency is paid
+// once instead of once per element.
+template <int ITEMS>
+__device__ __forceinline__ void stage(double* dst, const double* __restrict__ src, int cnt, int tid, int nthr) {
+  double r[ITEMS];
+#pragma unroll
+  for (int u = 0; u < ITEMS; ++u) {
+    const int i = tid + u * nthr;
+    r[u] = (i < cnt) ? src[i] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < ITEMS; ++u) {
+    const int i = tid + u * nthr;
+    if (i < cnt) dst[i] = r[u];
+  }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -167,13 +185,10 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
   const int tid = threadIdx.x;
   const int e0 = blockIdx.x * EB;
   copy_tab(t, tab);
-  for (int i = tid; i < EB * V * N; i += blockDim.x) {
-    int e = e0 + i / (V * N);
-    s_u[i] = (e < ne) ? ut[(size_t)e0 * V * N + i] : 0.0;
-  }
-  for (int i = tid; i < EB * NC * D; i += blockDim.x) {
-    int e = e0 + i / (NC * D);
-    s_x[i] = (e < ne) ? xv[(size_t)e0 * NC * D + i] : 0.0;
+  {
+    const int nel = min(EB, ne - e0);
+    stage<(EB * V * N + 255) / 256>(s_u, ut + (size_t)e0 * V * N, nel * V * N, tid, 256);
+    stage<(EB * NC * D + 255) / 256>(s_x, xv + (size_t)e0 * NC * D, nel * NC * D, tid, 256);
   }
   __syncthreads();
   // volume points
@@ -684,8 +699,7 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ B
   const int e = blockIdx.x * W + wv;
   const bool live = e < ne;
   copy_tab(t, tab);
-  if (live)
-    for (int i = lane; i < PER; i += 64) s_BC[wv][i] = BC[(size_t)e * PER + i];
+  if (live) stage<(PER + 63) / 64>(s_BC[wv], BC + (size_t)e * PER, PER, lane, 64);
   __syncthreads();
   for (int it = threadIdx.x; it < QV * N; it += blockDim.x) {
     const int q = it / N, j = it % N;
@@ -1009,11 +1023,23 @@ __global__ __launch_bounds__(256) void k_timestep(const double* __restrict__ ut,
   const double psi0 = (D == 2 ? 0.5 : 0.35355339059327373) / L[0];
   double U[V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) {
-    double s = 0.0;
-    for (int j = 0; j < N; ++j) s += L[j * (j + 1) / 2] * ut[((size_t)e * V + v) * N + j];
-    U[v] = s * psi0;
+  for (int v = 0; v < V; ++v) U[v] = 0.0;
+  for (int j0 = 0; j0 < N; j0 += 8) {
+    double lc[8], uv[8][V];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u < N ? j0 + u : N - 1;
+      lc[u] = (j0 + u < N) ? L[j * (j + 1) / 2] : 0.0;
+#pragma unroll
+      for (int v = 0; v < V; ++v) uv[u][v] = ut[((size_t)e * V + v) * N + j];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int v = 0; v < V; ++v) U[v] += lc[u] * uv[u][v];
   }
+#pragma unroll
+  for (int v = 0; v < V; ++v) U[v] *= psi0;
   double q2 = 0.0;
 #pragma unroll
   for (int a = 0; a < D; ++a) q2 += (U[1 + a] / U[0]) * (U[1 + a] / U[0]);
@@ -1035,11 +1061,17 @@ __global__ __launch_bounds__(256) void k_norm_partial(const double* __restrict__
   if (e < ne) {
     const double* L = Lpk + (size_t)e * NT;
     const double* a = rt + (size_t)e * V * N;
-    double r[N];
+    double r[N], l[N * (N + 1) / 2];
+#pragma unroll
+    for (int i = 0; i < N; ++i) r[i] = a[i];
+#pragma unroll
+    for (int i = 0; i < N * (N + 1) / 2; ++i) l[i] = L[i];
+#pragma unroll
     for (int i = 0; i < N; ++i) {
-      double s = a[i];
-      for (int j = 0; j < i; ++j) s -= L[i * (i + 1) / 2 + j] * r[j];
-      r[i] = s / L[i * (i + 1) / 2 + i];
+      double s = r[i];
+#pragma unroll
+      for (int j = 0; j < i; ++j) s -= l[i * (i + 1) / 2 + j] * r[j];
+      r[i] = s / l[i * (i + 1) / 2 + i];
       acc += r[i] * r[i];
     }
   }
