@@ -673,6 +673,21 @@ __global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ u
 // pivot order is recorded).  Output as k_jacobian: column-major factors (row
 // k of the factor = k-th pivot row) and perm.
 // ---------------------------------------------------------------------------
+// Wave-wide maximum of an unsigned key with DPP moves (no LDS round trip):
+// quad permutations, row shifts by 4 and 8, then the row broadcasts of lanes
+// 15 and 31; lane 63 ends up with the maximum, which is returned uniformly.
+// Lanes whose DPP source is disabled keep their own value (max is idempotent).
+__device__ __forceinline__ unsigned wave_max_u32(unsigned x) {
+  int v = (int)x;
+  v = (int)max((unsigned)v, (unsigned)__builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  v = (int)max((unsigned)v, (unsigned)__builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  v = (int)max((unsigned)v, (unsigned)__builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xE, false));  // row_shr:4
+  v = (int)max((unsigned)v, (unsigned)__builtin_amdgcn_update_dpp(v, v, 0x118, 0xF, 0xC, false));  // row_shr:8
+  v = (int)max((unsigned)v, (unsigned)__builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  v = (int)max((unsigned)v, (unsigned)__builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return (unsigned)__builtin_amdgcn_readlane(v, 63);
+}
+
 __device__ __forceinline__ double readlane_d(double x, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
@@ -781,9 +796,10 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ B
     // (largest |a|, ties to the lowest lane); 0 for lanes already used
     unsigned key = 0u;
     if (mystep < 0) key = (__float_as_uint((float)fabs(acc[k])) & ~63u) | (unsigned)(63 - lane);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) key = max(key, (unsigned)__shfl_xor((int)key, o, 64));
-    const int pl = __builtin_amdgcn_readfirstlane(63 - (int)(key & 63u));
+    const unsigned kmax = wave_max_u32(key);
+    const int pl = __builtin_amdgcn_readfirstlane(63 - (int)(kmax & 63u));
+    // the winner must be a row not yet used as a pivot
+    if (lane == pl && mystep >= 0) atomicOr(fail, 4);
     if (lane == pl) {
       mystep = k;
 #pragma unroll
