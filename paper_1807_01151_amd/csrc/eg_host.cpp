@@ -52,6 +52,8 @@ struct eg_handle {
   double* info = nullptr;
   int* arn_st = nullptr;
   double* arn_wn0 = nullptr;
+  double* arn_W = nullptr;   // two scratch vectors of the Arnoldi products
+  double* H2 = nullptr;      // second Gram-Schmidt pass coefficients
   double* y = nullptr;
   double* npart = nullptr;
   double* nout = nullptr;
@@ -453,8 +455,8 @@ eg_status run_exp1(eg_handle* h, double cfl, double* ut0, const double* ft0) {
   const DevMesh& M = h->M;
   PCALL(h, EG_K_P0_SETUP, 0, eg::launch_p0_setup(M, ut0, ft0, h->pmax, cfl, 1, h->u0, h->b0, h->Ad, h->Ao, h->dt0, h->st));
   PCALL(h, EG_K_ARNOLDI, 0, eg::launch_arnoldi(M, h->m, h->nblk_arn, h->Ad, h->Ao, h->b0, h->Vb, h->H, h->part1,
-                                                h->part2, h->info, h->arn_st, h->arn_wn0, h->st));
-  PCALL(h, EG_K_PHI1, 0, eg::launch_phi1(h->m, h->H, h->info, h->y, h->dfail, h->st));
+                                                h->part2, h->info, h->arn_st, h->arn_wn0, h->arn_W, h->H2, h->st));
+  PCALL(h, EG_K_PHI1, 0, eg::launch_phi1(h->m, h->H, h->H2, h->info, h->y, h->dfail, h->st));
   PCALL(h, EG_K_EXP1_UPDATE, 0, eg::launch_exp1_update(M, h->Vb, h->y, h->info, h->u0, ut0, h->st));
   return EG_OK;
 }
@@ -624,6 +626,8 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
   AL(h->info, 2);
   AL(h->arn_st, 2);
   AL(h->arn_wn0, 1);
+  AL(h->arn_W, 2 * K0);
+  AL(h->H2, (size_t)(h->m + 1) * h->m);
   AL(h->y, h->m + 1);
   AL(h->npart, (size_t)(ne + 255) / 256 + 1);
   AL(h->nout, 1);

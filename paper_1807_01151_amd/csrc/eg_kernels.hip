@@ -1342,13 +1342,19 @@ __device__ __forceinline__ void grid_partials_sum(const double* __restrict__ par
 
 // Arnoldi process of EXP1 as a sequence of full-grid kernels (a kernel
 // boundary is the global barrier; on this GPU it is several times cheaper
-// than a cooperative grid barrier): per step j
-//   a) w = A v_j on every row + per-block partials of <w, v_i>, ||w||^2
-//   b) h1 = sum of partials (every block, same order), w -= V h1, partials again
-//   c) h2, hn = sqrt(||w||^2 - ||h2||^2); H(:, j) = h1 + h2, H(j+1, j) = hn;
-//      w = (w - V h2) / hn, or happy breakdown (hn <= 1e-12 ||A v_j||): the
-//      flag st[0] makes every later kernel return, st[1] = Krylov dimension.
-// info[0] = dimension used, info[1] = beta.
+// than a cooperative grid barrier).  The product w = A v_j lives in scratch
+// vector W[j % 2]; v_{j+1} goes to Vb[j + 1].  Kernels:
+//   a  (j = 0 only): W0 = A v_0, partials of <W0, v_i> and ||W0||^2
+//   b  (step j): h1 = sum of partials, W -= V_j h1 (first Gram-Schmidt
+//      pass), partials of the second pass
+//   ca (step j, then j + 1): h2 and hn = sqrt(||W||^2 - ||h2||^2) finish
+//      column j of H; v_{j+1} = (W - V_j h2)/hn; and, fused, the next
+//      product A v_{j+1} = (A W - V_{j+1} (H~_j h2)) / hn (Arnoldi relation
+//      A V_j = V_{j+1} H~_j), which needs W only at neighbour rows, all final
+//      since the previous kernel; partials of the next first pass.
+//   c  (last step): as ca without the product.
+// Happy breakdown (hn <= 1e-12 ||A v_j||) sets st[0], so every later kernel
+// returns; info[0] = Krylov dimension used, info[1] = beta.
 __global__ __launch_bounds__(256) void k_arn_beta(int K, const double* __restrict__ b, double* __restrict__ part,
                                                   int P, int* __restrict__ st) {
   __shared__ double s_wave[4 * 64];
@@ -1377,59 +1383,103 @@ __global__ __launch_bounds__(256) void k_arn_start(int K, int m, const double* _
 }
 
 template <int V, int NF>
-__global__ __launch_bounds__(256) void k_arn_a(int K, int j, const int* __restrict__ nbr,
-                                               const double* __restrict__ Ad, const double* __restrict__ Ao,
-                                               double* __restrict__ Vb, double* __restrict__ part, int P,
+__global__ __launch_bounds__(256) void k_arn_a(int K, const int* __restrict__ nbr, const double* __restrict__ Ad,
+                                               const double* __restrict__ Ao, const double* __restrict__ Vb,
+                                               double* __restrict__ W, double* __restrict__ part, int P,
                                                const int* __restrict__ st) {
   if (st[0]) return;
   __shared__ double s_wave[4 * 64];
   __shared__ double s_h[64];
   const int gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
-  const double* vj = Vb + (size_t)j * K;
-  double* w = Vb + (size_t)(j + 1) * K;
-  for (int k = gid; k < K; k += stride) w[k] = spmv_row<V, NF>(k, nbr, Ad, Ao, vj);
-  block_dots(j + 1, K, gid, stride, w, Vb, s_wave, s_h);
-  if (threadIdx.x < j + 2) part[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
+  for (int k = gid; k < K; k += stride) W[k] = spmv_row<V, NF>(k, nbr, Ad, Ao, Vb);
+  block_dots(1, K, gid, stride, W, Vb, s_wave, s_h);
+  if (threadIdx.x < 2) part[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(256) void k_arn_b(int K, int m, int j, double* __restrict__ Vb,
-                                               const double* __restrict__ part1, double* __restrict__ part2, int P,
-                                               double* __restrict__ H, double* __restrict__ wn0,
-                                               const int* __restrict__ st) {
+__global__ __launch_bounds__(256) void k_arn_b(int K, int m, int j, const double* __restrict__ Vb,
+                                               double* __restrict__ W, const double* __restrict__ part1,
+                                               double* __restrict__ part2, int P, double* __restrict__ H,
+                                               double* __restrict__ wn0, const int* __restrict__ st) {
   if (st[0]) return;
   __shared__ double s_wave[4 * 64];
   __shared__ double s_h[64];
   __shared__ double s_g[64];
   __shared__ double s_tmp[256];
   const int gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
-  double* w = Vb + (size_t)(j + 1) * K;
   grid_partials_sum(part1, gridDim.x, P, j + 2, s_tmp, s_g);
-  rows_update(j, K, gid, stride, w, Vb, s_g, 1.0);
+  rows_update(j, K, gid, stride, W, Vb, s_g, 1.0);
   if (blockIdx.x == 0 && threadIdx.x <= j) H[threadIdx.x * m + j] = s_g[threadIdx.x];
   if (blockIdx.x == 0 && threadIdx.x == 0) wn0[0] = sqrt(s_g[j + 1]);
-  block_dots(j + 1, K, gid, stride, w, Vb, s_wave, s_h);
+  block_dots(j + 1, K, gid, stride, W, Vb, s_wave, s_h);
   if (threadIdx.x < j + 2) part2[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(256) void k_arn_c(int K, int m, int j, double* __restrict__ Vb,
-                                               const double* __restrict__ part2, int P, double* __restrict__ H,
-                                               const double* __restrict__ wn0, double* __restrict__ info,
-                                               int* __restrict__ st) {
+// Finishes step j (and, when NEXT, starts step j + 1 with the fused product).
+// H holds the first-pass coefficients h1 and the subdiagonal hn; the second
+// pass coefficients h2 go to H2 (the Hessenberg matrix is H + H2), so no
+// kernel reads an entry another block of the same kernel writes.
+template <int V, int NF, bool NEXT>
+__global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* __restrict__ nbr,
+                                                const double* __restrict__ Ad, const double* __restrict__ Ao,
+                                                double* __restrict__ Vb, const double* __restrict__ W,
+                                                double* __restrict__ Wn, const double* __restrict__ part2,
+                                                double* __restrict__ part1, int P, double* __restrict__ H,
+                                                double* __restrict__ H2, const double* __restrict__ wn0,
+                                                double* __restrict__ info, int* __restrict__ st) {
   if (st[0]) return;
+  __shared__ double s_wave[4 * 64];
   __shared__ double s_h[64];
+  __shared__ double s_c[64];
+  __shared__ double s_p[64];
   __shared__ double s_tmp[256];
   const int gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
-  double* w = Vb + (size_t)(j + 1) * K;
   grid_partials_sum(part2, gridDim.x, P, j + 2, s_tmp, s_h);
   double h2sq = 0.0;
   for (int i = 0; i <= j; ++i) h2sq += s_h[i] * s_h[i];
   const double hn = sqrt(fmax(s_h[j + 1] - h2sq, 0.0));
   const bool brk = !(hn > 1e-12 * wn0[0]);
-  rows_update(j, K, gid, stride, w, Vb, s_h, brk ? 1.0 : 1.0 / hn);
-  if (blockIdx.x == 0 && threadIdx.x <= j) H[threadIdx.x * m + j] += s_h[threadIdx.x];
+  if (NEXT && !brk && threadIdx.x <= j + 1) {
+    // c = H~_j h2: c_k = sum_{i >= k-1, i <= j} Hfinal[k][i] h2_i, with column j
+    // from this kernel's own values (h1 in H, h2 in s_h, hn)
+    const int kk = threadIdx.x;
+    double sacc = 0.0;
+    for (int i = (kk > 0 ? kk - 1 : 0); i < j; ++i) {
+      const double hki = (kk <= i) ? H[kk * m + i] + H2[kk * m + i] : H[kk * m + i];
+      sacc += hki * s_h[i];
+    }
+    const double hkj = (kk <= j) ? H[kk * m + j] + s_h[kk] : hn;
+    s_c[kk] = sacc + hkj * s_h[j];
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x <= j) H2[threadIdx.x * m + j] = s_h[threadIdx.x];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     H[(j + 1) * m + j] = hn;
     if (brk) { st[0] = 1; info[0] = (double)(j + 1); }
+  }
+  if (brk) return;  // uniform: every block computed the same hn
+  const double ihn = 1.0 / hn;
+  double* vn = Vb + (size_t)(j + 1) * K;
+  if constexpr (!NEXT) {
+    for (int k = gid; k < K; k += stride) {
+      double acc = 0.0;
+      for (int i = 0; i <= j; ++i) acc += s_h[i] * Vb[(size_t)i * K + k];
+      vn[k] = (W[k] - acc) * ihn;
+    }
+  } else {
+    for (int k = gid; k < K; k += stride) {
+      double acc = 0.0, corr = 0.0;
+      for (int i = 0; i <= j; ++i) {
+        const double vi = Vb[(size_t)i * K + k];
+        acc += s_h[i] * vi;
+        corr += s_c[i] * vi;
+      }
+      const double v = (W[k] - acc) * ihn;
+      vn[k] = v;
+      corr += s_c[j + 1] * v;
+      Wn[k] = (spmv_row<V, NF>(k, nbr, Ad, Ao, W) - corr) * ihn;
+    }
+    block_dots(j + 2, K, gid, stride, Wn, Vb, s_wave, s_p);
+    if (threadIdx.x < j + 3) part1[blockIdx.x * P + threadIdx.x] = s_p[threadIdx.x];
   }
 }
 
@@ -1449,7 +1499,7 @@ __device__ void lds_matmul(int n, const double* A, const double* B, double* Cm) 
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, int mstride,
+__global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, const double* __restrict__ H2, int mstride,
                                               const double* __restrict__ info, double* __restrict__ y,
                                               int* __restrict__ fail) {
   extern __shared__ double sm[];
@@ -1474,7 +1524,7 @@ __global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, int 
     const int i = it / n, j = it % n;
     double v = 0.0;
     // only the Hessenberg part (i <= j + 1) is written by the Arnoldi kernel
-    if (i < mu && j < mu && i <= j + 1) v = H[i * mstride + j];
+    if (i < mu && j < mu && i <= j + 1) v = H[i * mstride + j] + (i <= j ? H2[i * mstride + j] : 0.0);
     if (i == 0 && j == mu) v = 1.0;
     B[it] = v;
   }
@@ -1905,27 +1955,36 @@ int arnoldi_blocks(int K) { return (K + 255) / 256; }
 
 hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, const double* Ao, const double* b,
                           double* Vb, double* H, double* part1, double* part2, double* info, int* st,
-                          double* wn0, hipStream_t stream) {
+                          double* wn0, double* W2, double* H2, hipStream_t stream) {
   const int K = M.ne * M.V;
   const int P = m + 2;
+  double* W[2] = {W2, W2 + K};
   hipLaunchKernelGGL(k_arn_beta, dim3(nblk), dim3(256), 0, stream, K, b, part1, P, st);
   hipLaunchKernelGGL(k_arn_start, dim3(nblk), dim3(256), 0, stream, K, m, b, part1, P, Vb, info, st);
+  if (M.d == 2) hipLaunchKernelGGL((k_arn_a<4, 4>), dim3(nblk), dim3(256), 0, stream, K, M.nbr, Ad, Ao, Vb, W[0], part1, P, st);
+  else hipLaunchKernelGGL((k_arn_a<5, 6>), dim3(nblk), dim3(256), 0, stream, K, M.nbr, Ad, Ao, Vb, W[0], part1, P, st);
   for (int j = 0; j < m; ++j) {
-    if (M.d == 2)
-      hipLaunchKernelGGL((k_arn_a<4, 4>), dim3(nblk), dim3(256), 0, stream, K, j, M.nbr, Ad, Ao, Vb, part1, P, st);
-    else
-      hipLaunchKernelGGL((k_arn_a<5, 6>), dim3(nblk), dim3(256), 0, stream, K, j, M.nbr, Ad, Ao, Vb, part1, P, st);
-    hipLaunchKernelGGL(k_arn_b, dim3(nblk), dim3(256), 0, stream, K, m, j, Vb, part1, part2, P, H, wn0, st);
-    hipLaunchKernelGGL(k_arn_c, dim3(nblk), dim3(256), 0, stream, K, m, j, Vb, part2, P, H, wn0, info, st);
+    double* Wc = W[j & 1];
+    double* Wn = W[(j + 1) & 1];
+    hipLaunchKernelGGL(k_arn_b, dim3(nblk), dim3(256), 0, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st);
+    const bool next = (j + 1 < m);
+    if (M.d == 2) {
+      if (next) hipLaunchKernelGGL((k_arn_ca<4, 4, true>), dim3(nblk), dim3(256), 0, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
+      else hipLaunchKernelGGL((k_arn_ca<4, 4, false>), dim3(nblk), dim3(256), 0, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
+    } else {
+      if (next) hipLaunchKernelGGL((k_arn_ca<5, 6, true>), dim3(nblk), dim3(256), 0, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
+      else hipLaunchKernelGGL((k_arn_ca<5, 6, false>), dim3(nblk), dim3(256), 0, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
+    }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_phi1(int m, const double* H, const double* info, double* y, int* fail, hipStream_t st) {
+hipError_t launch_phi1(int m, const double* H, const double* H2, const double* info, double* y, int* fail,
+                       hipStream_t st) {
   const size_t lds = (size_t)8 * (m + 1) * (m + 1) * 8;
   hipError_t e = hipFuncSetAttribute((const void*)k_phi1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_phi1, dim3(1), dim3(256), lds, st, H, m, info, y, fail);
+  hipLaunchKernelGGL(k_phi1, dim3(1), dim3(256), lds, st, H, H2, m, info, y, fail);
   return hipGetLastError();
 }
 

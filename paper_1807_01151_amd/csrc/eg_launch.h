@@ -56,8 +56,9 @@ hipError_t launch_p0_setup(const DevMesh& M, const double* ut0, const double* ft
 int arnoldi_blocks(int K);
 hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, const double* Ao, const double* b,
                           double* Vb, double* H, double* part1, double* part2, double* info, int* st, double* wn0,
-                          hipStream_t stream);
-hipError_t launch_phi1(int m, const double* H, const double* info, double* y, int* fail, hipStream_t st);
+                          double* W2, double* H2, hipStream_t stream);
+hipError_t launch_phi1(int m, const double* H, const double* H2, const double* info, double* y, int* fail,
+                       hipStream_t st);
 hipError_t launch_exp1_update(const DevMesh& M, const double* Vb, const double* y, const double* info,
                               const double* u0, double* ut0, hipStream_t st);
 hipError_t launch_nbr_export(const DevMesh& M, int* out, hipStream_t st);
