@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--drop-budget", type=float, default=150.0, help="seconds cap of the time-to-1e-10 run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-drop", action="store_true", help="skip the time-to-1e-10 run")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="end with a 256 MiB device-to-device copy (the reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -175,6 +177,15 @@ def main():
                 "time_to_1e-10_s": round(t_drop, 4) if st == 0 else None, "drop_run_s": round(t_drop, 3),
                 "drop_reached": float(last / r1), "converged": st == 0}
         log(f"[bench] drop run: {drop}")
+    if args.calibrate:
+        nb = 256 << 20
+        x = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        extras["calibration_copy_bytes"] = nb
+        log(f"[bench] calibration copy of {nb} bytes done")
     cpu = None if args.no_cpu_baseline else cpu_baseline(mesh)
     line = {
         "metric": "V-cycle DOF-updates/s & time to 1e-10 residual drop, FP64 vs mixed precision",

@@ -1235,101 +1235,145 @@ template <int V, int NF>
 __device__ __forceinline__ double spmv_row(int row, const int* __restrict__ nbr, const double* __restrict__ Ad,
                                            const double* __restrict__ Ao, const double* __restrict__ x) {
   const int e = row / V, v = row % V;
+  int nb[NF];
+#pragma unroll
+  for (int lf = 0; lf < NF; ++lf) nb[lf] = nbr[(size_t)e * NF + lf];
   double s = 0.0;
   const double* a = Ad + (size_t)e * V * V + v * V;
 #pragma unroll
   for (int w = 0; w < V; ++w) s += a[w] * x[(size_t)e * V + w];
+  // boundary faces (nb < 0) read the element's own row and drop the term, so
+  // that every load is issued without a branch
 #pragma unroll
   for (int lf = 0; lf < NF; ++lf) {
-    const int nb = nbr[(size_t)e * NF + lf];
-    if (nb >= 0) {
-      const double* o = Ao + ((size_t)e * NF + lf) * V * V + v * V;
+    const int src = nb[lf] >= 0 ? nb[lf] : e;
+    const double* o = Ao + ((size_t)e * NF + lf) * V * V + v * V;
+    double t = 0.0;
 #pragma unroll
-      for (int w = 0; w < V; ++w) s += o[w] * x[(size_t)nb * V + w];
-    }
+    for (int w = 0; w < V; ++w) t += o[w] * x[(size_t)src * V + w];
+    s += nb[lf] >= 0 ? t : 0.0;
   }
   return s;
 }
 
-// Block-wide partial dot products: s_out[i] = sum over this block's rows of
-// w[k] * Vb[i][k] for i < nv, and s_out[nv] = sum of w[k]^2.  The loads of
-// eight basis vectors are issued together and their eight wave reductions
-// interleave, so the latency of global loads is paid once per group of eight.
-__device__ __forceinline__ void block_dots(int nv, int K, int gid, int stride, const double* __restrict__ w,
-                                           const double* __restrict__ Vb, double* s_wave /*[4][64]*/,
-                                           double* s_out) {
+// Sum over the 64 lanes of a wavefront with DPP moves of the two 32-bit
+// halves (the pattern of wave_max_u32: quad permutations, row shifts by 4
+// and 8, row broadcasts of lanes 15 and 31); lanes whose DPP source is
+// disabled contribute zero.  Lane 63 holds the total, returned uniformly.
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ double dpp_move_d(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, RM, BM, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, RM, BM, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum_d(double x) {
+  x += dpp_move_d<0xB1, 0xF, 0xF>(x);
+  x += dpp_move_d<0x4E, 0xF, 0xF>(x);
+  x += dpp_move_d<0x114, 0xF, 0xE>(x);
+  x += dpp_move_d<0x118, 0xF, 0xC>(x);
+  x += dpp_move_d<0x142, 0xA, 0xF>(x);
+  x += dpp_move_d<0x143, 0xC, 0xF>(x);
+  return readlane_d(x, 63);
+}
+
+// Block sums s_out[i] = sum over the block's threads of f(i), i < cnt <= NV
+// (cnt uniform): wave sums by DPP, then the four waves in a fixed order.
+// Every thread of the block must call it (DPP needs the full wavefront).
+template <int NV, class F>
+__device__ __forceinline__ void block_sums(int cnt, F f, double* s_wave /*[4][64]*/, double* s_out) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int cnt = nv + 1;
-  for (int i0 = 0; i0 < cnt; i0 += 8) {
-    double p[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) p[u] = 0.0;
-    for (int k = gid; k < K; k += stride) {
-      const double wk = w[k];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = i0 + u;
-        if (i < nv) p[u] += wk * Vb[(size_t)i * K + k];
-        else if (i == nv) p[u] += wk * wk;
-      }
+  for (int i = 0; i < NV; ++i)
+    if (i < cnt) {
+      const double t = wave_sum_d(f(i));
+      if (lane == 0) s_wave[wv * 64 + i] = t;
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-      for (int u = 0; u < 8; ++u) p[u] += __shfl_xor(p[u], o, 64);
-    if (lane == 0) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (i0 + u < cnt) s_wave[wv * 64 + i0 + u] = p[u];
-    }
-  }
   __syncthreads();
   if (threadIdx.x < cnt) {
     const int i = threadIdx.x;
-    s_out[i] = s_wave[i] + s_wave[64 + i] + s_wave[128 + i] + s_wave[192 + i];
+    s_out[i] = (s_wave[i] + s_wave[64 + i]) + (s_wave[128 + i] + s_wave[192 + i]);
   }
   __syncthreads();
 }
 
-// w[k] -= sum_{i <= j} h[i] Vb[i][k] for this thread's rows (and optionally
-// scale by 1/hn), with independent partial sums so loads overlap.
-__device__ __forceinline__ void rows_update(int j, int K, int gid, int stride, double* __restrict__ w,
-                                            const double* __restrict__ Vb, const double* h, double scale) {
-  for (int k = gid; k < K; k += stride) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int i = 0;
-    for (; i + 3 <= j; i += 4) {
-      s0 += h[i] * Vb[(size_t)i * K + k];
-      s1 += h[i + 1] * Vb[(size_t)(i + 1) * K + k];
-      s2 += h[i + 2] * Vb[(size_t)(i + 2) * K + k];
-      s3 += h[i + 3] * Vb[(size_t)(i + 3) * K + k];
+// Wave reduce-scatter of NV (a power of two, <= 64) values per lane: at each
+// halving step a lane keeps one half of its values and adds the partner's
+// copy of that half (lane ^ o); after log2(NV) steps a lane holds one value,
+// and the remaining xor steps complete the 64-lane sum.  Lane l ends with the
+// total of value index l >> (6 - log2 NV); p is overwritten.
+template <int H, int NV>
+__device__ __forceinline__ void rs_level(double (&p)[NV], int lane) {
+  if constexpr (H >= 1) {
+    constexpr int O = 64 * H / NV;  // partner offset of this halving step
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double send = up ? p[i] : p[i + H];
+      const double keep = up ? p[i + H] : p[i];
+      p[i] = keep + __shfl_xor(send, O, 64);
     }
-    for (; i <= j; ++i) s0 += h[i] * Vb[(size_t)i * K + k];
-    w[k] = (w[k] - ((s0 + s1) + (s2 + s3))) * scale;
+    rs_level<H / 2, NV>(p, lane);
   }
 }
 
+template <int NV>
+__device__ __forceinline__ double wave_reduce_scatter(double (&p)[NV]) {
+  static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV must be a power of two <= 64");
+  const int lane = threadIdx.x & 63;
+  rs_level<NV / 2, NV>(p, lane);
+  double r = p[0];
+#pragma unroll
+  for (int o = 32 / NV; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+  return r;
+}
+
+// Block sums of NV per-thread values p[i] (i < cnt <= NV) plus one more
+// value x, written to s_out[0..cnt) and s_out[cnt]: wave reduce-scatter,
+// then the four waves in a fixed order.  Every thread must call it.
+template <int NV>
+__device__ __forceinline__ void block_sums_rs(double (&p)[NV], double x, int cnt, double* s_wave /*[4][64]*/,
+                                              double* s_out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int SH = (NV == 64) ? 0 : (NV == 32) ? 1 : (NV == 16) ? 2 : (NV == 8) ? 3 : (NV == 4) ? 4 : (NV == 2) ? 5 : 6;
+  const double r = wave_reduce_scatter<NV>(p);
+  const double xs = wave_sum_d(x);
+  const int idx = lane >> SH;
+  if ((lane & ((1 << SH) - 1)) == 0 && idx < cnt) s_wave[wv * 64 + idx] = r;
+  if (lane == 0) s_wave[wv * 64 + cnt] = xs;
+  __syncthreads();
+  if (threadIdx.x <= cnt) {
+    const int i = threadIdx.x;
+    s_out[i] = (s_wave[i] + s_wave[64 + i]) + (s_wave[128 + i] + s_wave[192 + i]);
+  }
+  __syncthreads();
+}
+
 // Deterministic sum over the nblk blocks of cnt per-block partials
-// (part[q * P + i]) into s_out[i]: all loads of a block are issued together
-// (group g of threads sums q = g, g + G, ... with four accumulators), then the
-// G group sums are added in order.  Every block computes bitwise the same
-// totals.
+// (part[q * P + i]) into s_out[i]: group g of threads sums q = g, g + G, ...
+// with its loads issued sixteen at a time, then the G group sums are added in
+// order.  Every block computes bitwise the same totals.
 __device__ __forceinline__ void grid_partials_sum(const double* __restrict__ part, int nblk, int P, int cnt,
                                                   double* s_tmp /*[256]*/, double* s_out) {
   const int G = blockDim.x / cnt;
   const int t = threadIdx.x;
   if (t < G * cnt) {
     const int g = t / cnt, i = t % cnt;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int q = g;
-    for (; q + 3 * G < nblk; q += 4 * G) {
-      s0 += part[(size_t)q * P + i];
-      s1 += part[(size_t)(q + G) * P + i];
-      s2 += part[(size_t)(q + 2 * G) * P + i];
-      s3 += part[(size_t)(q + 3 * G) * P + i];
+    double s = 0.0;
+    for (int q0 = g; q0 < nblk; q0 += 16 * G) {
+      double a[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int q = q0 + u * G;
+        a[u] = q < nblk ? part[(size_t)q * P + i] : 0.0;
+      }
+#pragma unroll
+      for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+        for (int u = 0; u < w; ++u) a[u] += a[u + w];
+      s += a[0];
     }
-    for (; q < nblk; q += G) s0 += part[(size_t)q * P + i];
-    s_tmp[g * cnt + i] = (s0 + s1) + (s2 + s3);
+    s_tmp[g * cnt + i] = s;
   }
   __syncthreads();
   if (t < cnt) {
@@ -1342,25 +1386,30 @@ __device__ __forceinline__ void grid_partials_sum(const double* __restrict__ par
 
 // Arnoldi process of EXP1 as a sequence of full-grid kernels (a kernel
 // boundary is the global barrier; on this GPU it is several times cheaper
-// than a cooperative grid barrier).  The product w = A v_j lives in scratch
-// vector W[j % 2]; v_{j+1} goes to Vb[j + 1].  Kernels:
-//   a  (j = 0 only): W0 = A v_0, partials of <W0, v_i> and ||W0||^2
+// than a cooperative grid barrier).  One thread per row of the K-vectors
+// (the grid is ceil(K / 256) blocks of 256), which keeps its row of the
+// basis V_j in registers (NVM >= the number of basis vectors the kernel
+// touches), so every global load of a kernel is issued before the first
+// wait.  The product w = A v_j lives in scratch vector W[j % 2]; v_{j+1}
+// goes to Vb[j + 1].  Kernels:
+//   a  (j = 0 only): W0 = A v_0, partials of <W0, v_0> and ||W0||^2
 //   b  (step j): h1 = sum of partials, W -= V_j h1 (first Gram-Schmidt
 //      pass), partials of the second pass
 //   ca (step j, then j + 1): h2 and hn = sqrt(||W||^2 - ||h2||^2) finish
 //      column j of H; v_{j+1} = (W - V_j h2)/hn; and, fused, the next
 //      product A v_{j+1} = (A W - V_{j+1} (H~_j h2)) / hn (Arnoldi relation
 //      A V_j = V_{j+1} H~_j), which needs W only at neighbour rows, all final
-//      since the previous kernel; partials of the next first pass.
-//   c  (last step): as ca without the product.
+//      since the previous kernel; partials of the next first pass.  On the
+//      last step only v_{j+1} is formed.
 // Happy breakdown (hn <= 1e-12 ||A v_j||) sets st[0], so every later kernel
 // returns; info[0] = Krylov dimension used, info[1] = beta.
 __global__ __launch_bounds__(256) void k_arn_beta(int K, const double* __restrict__ b, double* __restrict__ part,
                                                   int P, int* __restrict__ st) {
   __shared__ double s_wave[4 * 64];
   __shared__ double s_h[64];
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  block_dots(0, K, gid, gridDim.x * blockDim.x, b, b, s_wave, s_h);
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const double x = k < K ? b[k] : 0.0;
+  block_sums<1>(1, [&](int) { return x * x; }, s_wave, s_h);
   if (threadIdx.x == 0) part[blockIdx.x * P] = s_h[0];
   if (blockIdx.x == 0 && threadIdx.x == 0) { st[0] = 0; st[1] = 0; }
 }
@@ -1372,14 +1421,14 @@ __global__ __launch_bounds__(256) void k_arn_start(int K, int m, const double* _
   __shared__ double s_g[64];
   grid_partials_sum(part, gridDim.x, P, 1, s_tmp, s_g);
   const double beta = sqrt(s_g[0]);
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     info[1] = beta;
     info[0] = (beta == 0.0) ? 0.0 : (double)m;
     if (beta == 0.0) st[0] = 1;
   }
   if (beta == 0.0) return;
-  for (int k = gid; k < K; k += gridDim.x * blockDim.x) Vb[k] = b[k] / beta;
+  if (k < K) Vb[k] = b[k] / beta;
 }
 
 template <int V, int NF>
@@ -1390,12 +1439,16 @@ __global__ __launch_bounds__(256) void k_arn_a(int K, const int* __restrict__ nb
   if (st[0]) return;
   __shared__ double s_wave[4 * 64];
   __shared__ double s_h[64];
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
-  for (int k = gid; k < K; k += stride) W[k] = spmv_row<V, NF>(k, nbr, Ad, Ao, Vb);
-  block_dots(1, K, gid, stride, W, Vb, s_wave, s_h);
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = k < K;
+  const double v0 = act ? Vb[k] : 0.0;
+  const double w = act ? spmv_row<V, NF>(k, nbr, Ad, Ao, Vb) : 0.0;
+  if (act) W[k] = w;
+  block_sums<2>(2, [&](int i) { return i == 0 ? w * v0 : w * w; }, s_wave, s_h);
   if (threadIdx.x < 2) part[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
 }
 
+template <int NVM>
 __global__ __launch_bounds__(256) void k_arn_b(int K, int m, int j, const double* __restrict__ Vb,
                                                double* __restrict__ W, const double* __restrict__ part1,
                                                double* __restrict__ part2, int P, double* __restrict__ H,
@@ -1405,12 +1458,31 @@ __global__ __launch_bounds__(256) void k_arn_b(int K, int m, int j, const double
   __shared__ double s_h[64];
   __shared__ double s_g[64];
   __shared__ double s_tmp[256];
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = k < K;
+  const int kc = act ? k : K - 1;  // clamped row: loads need no divergent branch
+  double vr[NVM];
+#pragma unroll
+  for (int i = 0; i < NVM; ++i) vr[i] = (i <= j) ? Vb[(size_t)i * K + kc] : 0.0;
+  const double w = act ? W[kc] : 0.0;
+#pragma unroll
+  for (int i = 0; i < NVM; ++i) vr[i] = act ? vr[i] : 0.0;
   grid_partials_sum(part1, gridDim.x, P, j + 2, s_tmp, s_g);
-  rows_update(j, K, gid, stride, W, Vb, s_g, 1.0);
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NVM; i += 2) {
+    if (i <= j) a0 += s_g[i] * vr[i];
+    if (i + 1 <= j) a1 += s_g[i + 1] * vr[i + 1];
+  }
+  const double w1 = w - (a0 + a1);
+  if (act) W[k] = w1;
   if (blockIdx.x == 0 && threadIdx.x <= j) H[threadIdx.x * m + j] = s_g[threadIdx.x];
   if (blockIdx.x == 0 && threadIdx.x == 0) wn0[0] = sqrt(s_g[j + 1]);
-  block_dots(j + 1, K, gid, stride, W, Vb, s_wave, s_h);
+  constexpr int NP = NVM == 48 ? 64 : NVM;
+  double pp[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) pp[i] = (i < NVM) ? w1 * vr[i < NVM ? i : 0] : 0.0;
+  block_sums_rs<NP>(pp, w1 * w1, j + 1, s_wave, s_h);
   if (threadIdx.x < j + 2) part2[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
 }
 
@@ -1418,7 +1490,7 @@ __global__ __launch_bounds__(256) void k_arn_b(int K, int m, int j, const double
 // H holds the first-pass coefficients h1 and the subdiagonal hn; the second
 // pass coefficients h2 go to H2 (the Hessenberg matrix is H + H2), so no
 // kernel reads an entry another block of the same kernel writes.
-template <int V, int NF, bool NEXT>
+template <int V, int NF, bool NEXT, int NVM>
 __global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* __restrict__ nbr,
                                                 const double* __restrict__ Ad, const double* __restrict__ Ao,
                                                 double* __restrict__ Vb, const double* __restrict__ W,
@@ -1432,23 +1504,59 @@ __global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* 
   __shared__ double s_c[64];
   __shared__ double s_p[64];
   __shared__ double s_tmp[256];
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  __shared__ double s_Hf[NEXT ? NVM * NVM : 1];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = k < K;
+  const int kc = act ? k : K - 1;  // clamped row: loads need no divergent branch
+  // every global load first: the basis row, w, the product A w and the
+  // finished columns of the Hessenberg matrix
+  double vr[NVM];
+#pragma unroll
+  for (int i = 0; i < NVM; ++i) vr[i] = (i <= j) ? Vb[(size_t)i * K + kc] : 0.0;
+  const double w1 = act ? W[kc] : 0.0;
+  double aw = 0.0;
+  if (NEXT) aw = act ? spmv_row<V, NF>(kc, nbr, Ad, Ao, W) : 0.0;
+#pragma unroll
+  for (int i = 0; i < NVM; ++i) vr[i] = act ? vr[i] : 0.0;
+  if (NEXT) {
+    // all loads of the staging issued together: (j + 2)(j + 1) <= NVM^2
+    constexpr int IT = (NVM * NVM + 255) / 256;
+    const int nH = (j + 2) * (j + 1);
+    double h1v[IT], h2v[IT];
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+      const int t = threadIdx.x + u * 256;
+      const int kk = t / (j + 1), i = t % (j + 1);
+      const bool in = t < nH && kk <= i + 1;
+      h1v[u] = in ? H[kk * m + i] : 0.0;
+      h2v[u] = (in && i < j && kk <= i) ? H2[kk * m + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+      const int t = threadIdx.x + u * 256;
+      const int kk = t / (j + 1), i = t % (j + 1);
+      // columns < j: final values; column j: h1 only (h2 added below)
+      if (t < nH) s_Hf[kk * NVM + i] = h1v[u] + h2v[u];
+    }
+  }
   grid_partials_sum(part2, gridDim.x, P, j + 2, s_tmp, s_h);
   double h2sq = 0.0;
   for (int i = 0; i <= j; ++i) h2sq += s_h[i] * s_h[i];
   const double hn = sqrt(fmax(s_h[j + 1] - h2sq, 0.0));
   const bool brk = !(hn > 1e-12 * wn0[0]);
-  if (NEXT && !brk && threadIdx.x <= j + 1) {
-    // c = H~_j h2: c_k = sum_{i >= k-1, i <= j} Hfinal[k][i] h2_i, with column j
-    // from this kernel's own values (h1 in H, h2 in s_h, hn)
-    const int kk = threadIdx.x;
+  if (NEXT && !brk) {
+    // c = H~_j h2: columns < j split over the four waves (s_tmp is free
+    // again), column j from this kernel's own values
+    const int kk = threadIdx.x & 63, q = threadIdx.x >> 6;
     double sacc = 0.0;
-    for (int i = (kk > 0 ? kk - 1 : 0); i < j; ++i) {
-      const double hki = (kk <= i) ? H[kk * m + i] + H2[kk * m + i] : H[kk * m + i];
-      sacc += hki * s_h[i];
+    if (kk <= j + 1)
+      for (int i = (kk > 0 ? kk - 1 : 0) + q; i < j; i += 4) sacc += s_Hf[kk * NVM + i] * s_h[i];
+    s_tmp[q * 64 + kk] = sacc;
+    __syncthreads();
+    if (threadIdx.x <= j + 1) {
+      const double hkj = (kk <= j) ? s_Hf[kk * NVM + j] + s_h[kk] : hn;
+      s_c[kk] = ((s_tmp[kk] + s_tmp[64 + kk]) + (s_tmp[128 + kk] + s_tmp[192 + kk])) + hkj * s_h[j];
     }
-    const double hkj = (kk <= j) ? H[kk * m + j] + s_h[kk] : hn;
-    s_c[kk] = sacc + hkj * s_h[j];
   }
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x <= j) H2[threadIdx.x * m + j] = s_h[threadIdx.x];
@@ -1458,27 +1566,22 @@ __global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* 
   }
   if (brk) return;  // uniform: every block computed the same hn
   const double ihn = 1.0 / hn;
-  double* vn = Vb + (size_t)(j + 1) * K;
-  if constexpr (!NEXT) {
-    for (int k = gid; k < K; k += stride) {
-      double acc = 0.0;
-      for (int i = 0; i <= j; ++i) acc += s_h[i] * Vb[(size_t)i * K + k];
-      vn[k] = (W[k] - acc) * ihn;
-    }
-  } else {
-    for (int k = gid; k < K; k += stride) {
-      double acc = 0.0, corr = 0.0;
-      for (int i = 0; i <= j; ++i) {
-        const double vi = Vb[(size_t)i * K + k];
-        acc += s_h[i] * vi;
-        corr += s_c[i] * vi;
-      }
-      const double v = (W[k] - acc) * ihn;
-      vn[k] = v;
-      corr += s_c[j + 1] * v;
-      Wn[k] = (spmv_row<V, NF>(k, nbr, Ad, Ao, W) - corr) * ihn;
-    }
-    block_dots(j + 2, K, gid, stride, Wn, Vb, s_wave, s_p);
+  double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NVM; i += 2) {
+    if (i <= j) { a0 += s_h[i] * vr[i]; c0 += s_c[i] * vr[i]; }
+    if (i + 1 <= j) { a1 += s_h[i + 1] * vr[i + 1]; c1 += s_c[i + 1] * vr[i + 1]; }
+  }
+  const double v = (w1 - (a0 + a1)) * ihn;
+  if (act) Vb[(size_t)(j + 1) * K + k] = v;
+  if constexpr (NEXT) {
+    const double wn = (aw - ((c0 + c1) + s_c[j + 1] * v)) * ihn;
+    if (act) Wn[k] = wn;
+    constexpr int NP = NVM == 48 ? 64 : NVM;
+    double pp[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) pp[i] = (i <= j) ? wn * vr[i < NVM ? i : 0] : (i == j + 1 ? wn * v : 0.0);
+    block_sums_rs<NP>(pp, wn * wn, j + 2, s_wave, s_p);
     if (threadIdx.x < j + 3) part1[blockIdx.x * P + threadIdx.x] = s_p[threadIdx.x];
   }
 }
@@ -1489,12 +1592,34 @@ __global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* 
 // and squaring (Higham 2005); stands in for the paper's rational
 // approximation of exp(dt H_m) (end of Section 2.2).  y[i] = E[i][m].
 // ---------------------------------------------------------------------------
+// Cm = A B for n x n row-major matrices in LDS, by a block of 256 threads.
+// For n <= 32 each thread owns a 2 x 2 tile of the output (four FMAs per
+// four LDS reads); larger n takes one output per thread and pass.
 __device__ void lds_matmul(int n, const double* A, const double* B, double* Cm) {
-  for (int it = threadIdx.x; it < n * n; it += blockDim.x) {
-    const int i = it / n, j = it % n;
-    double s = 0.0;
-    for (int k = 0; k < n; ++k) s += A[i * n + k] * B[k * n + j];
-    Cm[it] = s;
+  if (n <= 32) {
+    const int r0 = 2 * (threadIdx.x >> 4), c0 = 2 * (threadIdx.x & 15);
+    if (r0 < n && c0 < n) {
+      const int r1 = min(r0 + 1, n - 1), c1 = min(c0 + 1, n - 1);
+      double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
+      for (int k = 0; k < n; ++k) {
+        const double a0 = A[r0 * n + k], a1 = A[r1 * n + k];
+        const double b0 = B[k * n + c0], b1 = B[k * n + c1];
+        s00 += a0 * b0; s01 += a0 * b1; s10 += a1 * b0; s11 += a1 * b1;
+      }
+      Cm[r0 * n + c0] = s00;
+      if (c0 + 1 < n) Cm[r0 * n + c0 + 1] = s01;
+      if (r0 + 1 < n) {
+        Cm[(r0 + 1) * n + c0] = s10;
+        if (c0 + 1 < n) Cm[(r0 + 1) * n + c0 + 1] = s11;
+      }
+    }
+  } else {
+    for (int it = threadIdx.x; it < n * n; it += blockDim.x) {
+      const int i = it / n, j = it % n;
+      double s = 0.0;
+      for (int k = 0; k < n; ++k) s += A[i * n + k] * B[k * n + j];
+      Cm[it] = s;
+    }
   }
   __syncthreads();
 }
@@ -1570,13 +1695,24 @@ __global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, cons
   double* X = B4;
   for (int it = threadIdx.x; it < nn; it += blockDim.x) { Pm[it] = Vm[it] - U[it]; X[it] = Vm[it] + U[it]; }
   __syncthreads();
+  __shared__ double s_l[64];
   for (int k = 0; k < n; ++k) {
-    if (threadIdx.x == 0) {
-      int pv = k;
-      double best = fabs(Pm[k * n + k]);
-      for (int i = k + 1; i < n; ++i) if (fabs(Pm[i * n + k]) > best) { best = fabs(Pm[i * n + k]); pv = i; }
-      if (!(best > 0.0)) atomicOr(fail, 2);
-      s_piv = pv;
+    // pivot: wave 0 finds the first row of largest |Pm[i][k]|, i >= k
+    // (n <= 49 rows, one per lane)
+    if (threadIdx.x < 64) {
+      const int i = threadIdx.x;
+      double a = (i >= k && i < n) ? fabs(Pm[i * n + k]) : -1.0;
+      int idx = i;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const double a2 = __shfl_xor(a, o, 64);
+        const int i2 = __shfl_xor(idx, o, 64);
+        if (a2 > a || (a2 == a && i2 < idx)) { a = a2; idx = i2; }
+      }
+      if (threadIdx.x == 0) {
+        if (!(a > 0.0)) atomicOr(fail, 2);
+        s_piv = idx;
+      }
     }
     __syncthreads();
     const int pv = s_piv;
@@ -1585,16 +1721,18 @@ __global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, cons
         double t1 = Pm[k * n + j]; Pm[k * n + j] = Pm[pv * n + j]; Pm[pv * n + j] = t1;
         double t2 = X[k * n + j]; X[k * n + j] = X[pv * n + j]; X[pv * n + j] = t2;
       }
+      __syncthreads();
     }
+    // row multipliers once per row, then the rank-1 update
+    if (threadIdx.x > k && threadIdx.x < n) s_l[threadIdx.x] = Pm[threadIdx.x * n + k] / Pm[k * n + k];
     __syncthreads();
     for (int it = threadIdx.x; it < (n - k - 1) * n; it += blockDim.x) {
       const int i = k + 1 + it / n, j = it % n;
-      const double l = Pm[i * n + k] / Pm[k * n + k];
+      const double l = s_l[i];
       X[i * n + j] -= l * X[k * n + j];
       if (j > k) Pm[i * n + j] -= l * Pm[k * n + j];
+      else if (j == k) Pm[i * n + j] = 0.0;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) for (int i = k + 1; i < n; ++i) Pm[i * n + k] = 0.0;
     __syncthreads();
   }
   for (int k = n - 1; k >= 0; --k) {
@@ -1953,11 +2091,43 @@ hipError_t launch_p0_setup(const DevMesh& M, const double* ut0, const double* ft
 
 int arnoldi_blocks(int K) { return (K + 255) / 256; }
 
+// Smallest register-resident basis size covering `need` vectors.
+static int arn_nvm(int need) { return need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 48; }
+
+template <int NVM>
+static void launch_arn_b(int nblk, hipStream_t s, int K, int m, int j, const double* Vb, double* W,
+                         const double* part1, double* part2, int P, double* H, double* wn0, const int* st) {
+  hipLaunchKernelGGL(k_arn_b<NVM>, dim3(nblk), dim3(256), 0, s, K, m, j, Vb, W, part1, part2, P, H, wn0, st);
+}
+
+template <int V, int NF, bool NEXT, int NVM>
+static void launch_arn_ca(int nblk, hipStream_t s, int K, int m, int j, const int* nbr, const double* Ad,
+                          const double* Ao, double* Vb, const double* W, double* Wn, const double* part2,
+                          double* part1, int P, double* H, double* H2, const double* wn0, double* info, int* st) {
+  hipLaunchKernelGGL((k_arn_ca<V, NF, NEXT, NVM>), dim3(nblk), dim3(256), 0, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn,
+                     part2, part1, P, H, H2, wn0, info, st);
+}
+
+template <int V, int NF, bool NEXT>
+static void dispatch_arn_ca(int nvm, int nblk, hipStream_t s, int K, int m, int j, const int* nbr,
+                            const double* Ad, const double* Ao, double* Vb, const double* W, double* Wn,
+                            const double* part2, double* part1, int P, double* H, double* H2, const double* wn0,
+                            double* info, int* st) {
+  switch (nvm) {
+    case 8: launch_arn_ca<V, NF, NEXT, 8>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st); break;
+    case 16: launch_arn_ca<V, NF, NEXT, 16>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st); break;
+    case 32: launch_arn_ca<V, NF, NEXT, 32>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st); break;
+    default: launch_arn_ca<V, NF, NEXT, 48>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st); break;
+  }
+}
+
 hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, const double* Ao, const double* b,
                           double* Vb, double* H, double* part1, double* part2, double* info, int* st,
                           double* wn0, double* W2, double* H2, hipStream_t stream) {
   const int K = M.ne * M.V;
   const int P = m + 2;
+  // one thread per row, at most 48 basis vectors held in registers
+  if (nblk != arnoldi_blocks(K) || m < 1 || m > 48) return hipErrorInvalidValue;
   double* W[2] = {W2, W2 + K};
   hipLaunchKernelGGL(k_arn_beta, dim3(nblk), dim3(256), 0, stream, K, b, part1, P, st);
   hipLaunchKernelGGL(k_arn_start, dim3(nblk), dim3(256), 0, stream, K, m, b, part1, P, Vb, info, st);
@@ -1966,14 +2136,20 @@ hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, c
   for (int j = 0; j < m; ++j) {
     double* Wc = W[j & 1];
     double* Wn = W[(j + 1) & 1];
-    hipLaunchKernelGGL(k_arn_b, dim3(nblk), dim3(256), 0, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st);
+    switch (arn_nvm(j + 1)) {
+      case 8: launch_arn_b<8>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st); break;
+      case 16: launch_arn_b<16>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st); break;
+      case 32: launch_arn_b<32>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st); break;
+      default: launch_arn_b<48>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st); break;
+    }
     const bool next = (j + 1 < m);
+    const int nvm = arn_nvm(next ? j + 2 : j + 1);
     if (M.d == 2) {
-      if (next) hipLaunchKernelGGL((k_arn_ca<4, 4, true>), dim3(nblk), dim3(256), 0, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
-      else hipLaunchKernelGGL((k_arn_ca<4, 4, false>), dim3(nblk), dim3(256), 0, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
+      if (next) dispatch_arn_ca<4, 4, true>(nvm, nblk, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
+      else dispatch_arn_ca<4, 4, false>(nvm, nblk, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
     } else {
-      if (next) hipLaunchKernelGGL((k_arn_ca<5, 6, true>), dim3(nblk), dim3(256), 0, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
-      else hipLaunchKernelGGL((k_arn_ca<5, 6, false>), dim3(nblk), dim3(256), 0, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
+      if (next) dispatch_arn_ca<5, 6, true>(nvm, nblk, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
+      else dispatch_arn_ca<5, 6, false>(nvm, nblk, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
     }
   }
   return hipGetLastError();
