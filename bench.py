@@ -16,8 +16,10 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -50,17 +52,55 @@ def work_model(d, p):
     }
 
 
+# kernels behind each timed class (bench time classes -> device functions)
+CLASS_KERNELS = {"jacobian_lu": ["k_jac_points", "k_jaclu_wave", "wave_max_u32", "readlane_d"],
+                 "prk_stage": ["k_prk_stage_t", "k_prk_stage"],
+                 "residual": ["k_residual", "stage"]}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobian_lu_c2_pmc_traffic.md")
+
+
+def kernel_source_digest(cls):
+    """sha256 over the shared device headers and the text of the device
+    functions of one kernel class, so that a stored counter reading can be
+    matched to the code it was taken on."""
+    csrc = os.path.join(ROOT, "paper_1807_01151_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("eg_common.h", "eg_physics.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    src = open(os.path.join(csrc, "eg_kernels.hip")).read()
+    for name in CLASS_KERNELS[cls]:
+        for m in re.finditer(r"\b" + name + r"\(", src):
+            start = src.rfind("\n", 0, m.start())
+            end = src.find("\n}\n", m.start())
+            h.update(src[start:end].encode())
+    return h.hexdigest()
+
+
+def stored_traffic(cls, p):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary, or None if it is absent or was taken on other kernel code."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = dict(re.findall(r"^- (.+?): (\S+)$", txt, re.M))
+    if vals.get(f"source_digest[{cls}]") != kernel_source_digest(cls):
+        return None
+    v = vals.get(f"traffic_bytes_per_launch[{cls} p={p}]")
+    return float(v) if v else None
+
+
 def roofline_entry(cls, p, ms, launches, ne, d):
     w = work_model(d, p)[cls]
     avg_s = ms / launches / 1e3
     if cls == "prk_stage":
         ach = w["bytes"] * ne / avg_s / 1e9
         return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": None, "kernel": f"{cls} p={p}", "avg_launch_ms": ms / launches,
+                "traffic": stored_traffic(cls, p), "kernel": f"{cls} p={p}", "avg_launch_ms": ms / launches,
                 "algorithmic_bytes_per_launch": w["bytes"] * ne}
     ach = w["flop"] * ne / avg_s / 1e12
     return {"bound": "alu", "achieved": ach, "peak": FP64_VALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": ach / FP64_VALU_TFLOPS, "traffic": None, "kernel": f"{cls} p={p}",
+            "frac": ach / FP64_VALU_TFLOPS, "traffic": stored_traffic(cls, p), "kernel": f"{cls} p={p}",
             "avg_launch_ms": ms / launches, "algorithmic_flop_per_launch": w["flop"] * ne}
 
 
