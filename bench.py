@@ -129,13 +129,93 @@ def cpu_baseline(mesh, budget_s=12.0):
                                         f"({el:.1f} s, OpenMP threads = cores)"}
 
 
+def drop_run(S, p, max_cycles, budget, tag):
+    """Solve from the free stream to a 1e-10 drop in chunks of 500 cycles (same
+    ramp and cycle numbering), each chunk reporting its progress; stops at the
+    drop, the cycle cap or the time budget."""
+    import torch
+    u2 = S.freestream(p)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    chunk = 500
+    hist, st = S.solve_steady(u2, drop_tol=1e-10, max_cycles=min(chunk, max_cycles))
+    r1, done, last = hist[0], len(hist) - 1, hist[-1]
+    while st == 5 and done < max_cycles and time.perf_counter() - t1 < budget:
+        log(f"[bench] {tag} drop run: {done} cycles, r/r1 = {last / r1:.3e}, {time.perf_counter() - t1:.1f}s")
+        h2, st = S.solve_steady(u2, drop_tol=1e-10, max_cycles=min(chunk, max_cycles - done), resume=True)
+        done += len(h2) - 1
+        last = h2[-1]
+    torch.cuda.synchronize()
+    t_drop = time.perf_counter() - t1
+    out = {"cycles_to_1e-10": int(done) if st == 0 else None, "cycles_run": int(done),
+           "time_to_1e-10_s": round(t_drop, 4) if st == 0 else None, "drop_run_s": round(t_drop, 3),
+           "drop_reached": float(last / r1), "converged": st == 0}
+    log(f"[bench] {tag} drop run: {out}")
+    return out
+
+
+def mixed_measurements(P, mesh, p, dof, args, fp64_ms):
+    """Mixed precision on the benchmark workload: V-cycle cost in phase A
+    (FP32 residuals, blocks and stage solves) from the free stream, and in
+    phase B (FP64 residuals, FP32 blocks and stage solves) once the solve has
+    switched (r <= 1e-4 r_1)."""
+    import torch
+    S = P.Solver(mesh, p, rk_stages=3, cfl_max=10.0, krylov_m=30, mach=0.3, alpha_deg=0.0, precision="mixed")
+    u = S.freestream(p)
+    S.solve_steady(u, drop_tol=0.0, max_cycles=args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h, _ = S.solve_steady(u, drop_tol=0.0, max_cycles=args.steps)
+    torch.cuda.synchronize()
+    ms_a = (time.perf_counter() - t0) / args.steps * 1e3
+    # run on (phase A) until the switch, then time phase-B cycles
+    r1 = h[0]
+    done = 0
+    while h[-1] > 1e-4 * r1 and done < 5000:
+        h, _ = S.solve_steady(u, drop_tol=0.0, max_cycles=250, resume=True)
+        done += 250
+    S.solve_steady(u, drop_tol=0.0, max_cycles=2, resume=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.solve_steady(u, drop_tol=0.0, max_cycles=args.steps, resume=True)
+    torch.cuda.synchronize()
+    ms_b = (time.perf_counter() - t0) / args.steps * 1e3
+    log(f"[bench] mixed: phase A {ms_a:.3f} ms/cycle, phase B {ms_b:.3f} ms/cycle (FP64 {fp64_ms:.3f})")
+    return {"phase_a_ms_per_cycle": round(ms_a, 4), "phase_b_ms_per_cycle": round(ms_b, 4),
+            "phase_a_dof_updates_per_s": dof / ms_a * 1e3, "phase_b_dof_updates_per_s": dof / ms_b * 1e3,
+            "phase_a_speedup_vs_fp64": round(fp64_ms / ms_a, 3), "phase_b_speedup_vs_fp64": round(fp64_ms / ms_b, 3)}
+
+
+def c1_time_to_drop(P):
+    """Time to a 1e-10 FP64 residual drop on the O-grid 24 x 12, p = 1 solve
+    (s = 4, CFL_max = 100, m = 30), which converges, in FP64 and mixed."""
+    import torch
+    from eg_inputs import ogrid
+    m1 = ogrid(24, 12)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        S = P.Solver(m1, 1, rk_stages=4, cfl_max=100.0, krylov_m=30, precision=prec)
+        S.solve_steady(S.freestream(1), drop_tol=0.0, max_cycles=3)  # warm-up (kernel loading)
+        u = S.freestream(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h, st = S.solve_steady(u, drop_tol=1e-10, max_cycles=6000)
+        torch.cuda.synchronize()
+        out[prec] = {"time_s": round(time.perf_counter() - t0, 4), "cycles": len(h) - 1, "converged": st == 0}
+        log(f"[bench] c1 {prec}: {out[prec]}")
+    out["speedup"] = round(out["fp64"]["time_s"] / out["mixed"]["time_s"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--drop-cycles", type=int, default=100000, help="cycle cap of the time-to-1e-10 run")
-    ap.add_argument("--drop-budget", type=float, default=150.0, help="seconds cap of the time-to-1e-10 run")
+    ap.add_argument("--drop-budget", type=float, default=60.0,
+                    help="seconds cap of each (FP64, mixed) time-to-1e-10 run on the benchmark mesh")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-drop", action="store_true", help="skip the time-to-1e-10 run")
     ap.add_argument("--calibrate", action="store_true",
@@ -197,26 +277,17 @@ def main():
     # time to a 1e-10 residual drop from the free stream
     drop = {}
     if not args.no_drop:
-        # the solve runs in chunks of cycles (same ramp and numbering) so that
-        # each chunk reports its progress; stops at the drop, the cycle cap or
-        # the time budget
-        u2 = S.freestream(p)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        chunk = 500
-        hist, st = S.solve_steady(u2, drop_tol=1e-10, max_cycles=min(chunk, args.drop_cycles))
-        r1, done, last = hist[0], len(hist) - 1, hist[-1]
-        while st == 5 and done < args.drop_cycles and time.perf_counter() - t1 < args.drop_budget:
-            log(f"[bench] drop run: {done} cycles, r/r1 = {last / r1:.3e}, {time.perf_counter() - t1:.1f}s")
-            h2, st = S.solve_steady(u2, drop_tol=1e-10, max_cycles=min(chunk, args.drop_cycles - done), resume=True)
-            done += len(h2) - 1
-            last = h2[-1]
-        torch.cuda.synchronize()
-        t_drop = time.perf_counter() - t1
-        drop = {"cycles_to_1e-10": int(done) if st == 0 else None, "cycles_run": int(done),
-                "time_to_1e-10_s": round(t_drop, 4) if st == 0 else None, "drop_run_s": round(t_drop, 3),
-                "drop_reached": float(last / r1), "converged": st == 0}
-        log(f"[bench] drop run: {drop}")
+        drop = drop_run(S, p, args.drop_cycles, args.drop_budget, "fp64")
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_measurements(P, mesh, p, dof, args, ms_per_step)
+        if not args.no_drop:
+            Sm = P.Solver(mesh, p, rk_stages=3, cfl_max=10.0, krylov_m=30, mach=0.3, alpha_deg=0.0,
+                          precision="mixed")
+            mixed["drop_run"] = drop_run(Sm, p, args.drop_cycles, args.drop_budget, "mixed")
+            del Sm
+        mixed["c1_time_to_1e-10"] = c1_time_to_drop(P)
+        extras["mixed"] = mixed
     if args.calibrate:
         nb = 256 << 20
         x = torch.ones(nb // 8, dtype=torch.float64, device="cuda")

@@ -74,7 +74,25 @@ typedef struct {
   double mach;        /* free-stream Mach number; rho_inf = 1, p_inf = 1/gamma */
   double alpha_deg;   /* free-stream angle in the x-y plane */
   double beta_deg;    /* 3D only: angle out of the x-y plane */
+  int precision;      /* EG_FP64 or EG_MIXED (see below) */
 } eg_params;
+
+/* Arithmetic of the smoother (eg_params.precision).
+ *  EG_FP64:  every kernel in FP64.
+ *  EG_MIXED: state, forcings, transfers, the p = 0 level (EXP1, Arnoldi,
+ *            phi_1) and every residual norm stay FP64; the element blocks of
+ *            the levels p >= 1, their LU factors (stored FP32) and the PRK
+ *            stage solves are FP32.  A steady solve runs in two phases:
+ *            phase A also evaluates the residuals of the levels p >= 1 in
+ *            FP32, with an FP64 defect at p_max (d = R64(u^n) - R32(u^n) is
+ *            that level's forcing for the cycle); it ends for good once the
+ *            FP64 norm r_n <= 1e-4 r_1 or has not reached a new minimum for
+ *            100 cycles.  Phase B evaluates every residual in FP64, so the
+ *            FP32 blocks only precondition an FP64 defect correction
+ *            (Section 2.3, eq. (prk_scalar) with P in FP32) and the
+ *            converged state is the FP64 steady state.  eg_vcycle runs
+ *            phase B when r_n <= 1e-4 rref, else phase A. */
+enum { EG_FP64 = 0, EG_MIXED = 1 };
 
 /* Builds faces, orientation codes, geometry and per-element basis data, and
  * allocates every device workspace.  hip_stream may be NULL (default stream).
@@ -95,7 +113,9 @@ eg_status eg_set_freestream(eg_handle* h, int p, double* u_dev);
 /* DG residual R_p(u) of Section 3.1, eq. (euler3) (no source term):
  *   R_{E,i} = -sum_faces int psi_i F~.n dsigma + int_E F . grad psi_i dx,
  * Rusanov flux, (p+2)^d Gauss points per element and (p+2)^(d-1) per face.
- * u_dev, r_dev: level-p vectors.  Asynchronous. */
+ * u_dev, r_dev: level-p vectors.  Evaluated in the smoother's arithmetic:
+ * FP32 for p >= 1 on an EG_MIXED handle (FP64 inputs and outputs), else FP64.
+ * Asynchronous. */
 eg_status eg_residual(eg_handle* h, int p, const double* u_dev, double* r_dev);
 
 /* Local pseudo-time step of Section 4, eq. (x3d):

@@ -37,7 +37,9 @@ class _Mesh(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("p_max", C.c_int), ("rk_stages", C.c_int), ("cfl_max", C.c_double), ("krylov_m", C.c_int),
                 ("relative_ramp", C.c_int), ("gamma", C.c_double), ("mach", C.c_double),
-                ("alpha_deg", C.c_double), ("beta_deg", C.c_double)]
+                ("alpha_deg", C.c_double), ("beta_deg", C.c_double), ("precision", C.c_int)]
+
+PRECISIONS = {"fp64": 0, "mixed": 1}
 
 
 def library_path() -> str:
@@ -96,7 +98,7 @@ class Solver:
 
     def __init__(self, mesh, p_max: int, rk_stages: int = 4, cfl_max: float = 100.0, krylov_m: int = 30,
                  relative_ramp: bool = True, gamma: float = 1.4, mach: float = 0.3, alpha_deg: float = 0.0,
-                 beta_deg: float = 0.0, stream=None):
+                 beta_deg: float = 0.0, precision: str = "fp64", stream=None):
         import numpy as np
         import torch
         L = lib()
@@ -105,7 +107,11 @@ class Solver:
         cm = _Mesh(m.dim, m.n_vert, m.xyz.ctypes.data_as(C.POINTER(C.c_double)), m.n_elem,
                    m.elem_vert.ctypes.data_as(C.POINTER(C.c_int32)),
                    m.bface_tag.ctypes.data_as(C.POINTER(C.c_int8)))
-        cp = _Params(p_max, rk_stages, cfl_max, krylov_m, int(relative_ramp), gamma, mach, alpha_deg, beta_deg)
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        self.precision = precision
+        cp = _Params(p_max, rk_stages, cfl_max, krylov_m, int(relative_ramp), gamma, mach, alpha_deg, beta_deg,
+                     PRECISIONS[precision])
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         st = L.eg_init_mesh(C.byref(cm), C.byref(cp), C.c_void_p(self.stream.cuda_stream), C.byref(h))

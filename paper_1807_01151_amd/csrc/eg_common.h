@@ -25,22 +25,25 @@ struct Cfg {
 // One-dimensional tables of order P, copied to LDS by every kernel:
 // Gauss points / weights of the (P+2)-point rule, orthonormal Legendre
 // values and derivatives at those points and at the interval ends, and the
-// multi-index of every mode in hierarchical order.
-template <int D, int P>
+// multi-index of every mode in hierarchical order.  R is the arithmetic type
+// of the kernel that reads them (double, or float for the FP32 smoother).
+template <int D, int P, class R = double>
 struct Tab {
-  double x[P + 2];
-  double w[P + 2];
-  double L[P + 1][P + 2];
-  double dL[P + 1][P + 2];
-  double Lb[P + 1][2];
+  R x[P + 2];
+  R w[P + 2];
+  R L[P + 1][P + 2];
+  R dL[P + 1][P + 2];
+  R Lb[P + 1][2];
   int8_t m[Cfg<D, P>::N][3];
 };
 
 // Free stream and gas constant passed to kernels by value.
-struct Gas {
-  double g;
-  double Uinf[5];
+template <class R = double>
+struct GasT {
+  R g;
+  R Uinf[5];
 };
+using Gas = GasT<double>;
 
 // Boundary codes stored in the neighbour array for faces without neighbour.
 constexpr int NB_WALL = -1;

@@ -25,6 +25,8 @@ using eg::TabData;
 struct eg_handle {
   DevMesh M;
   int pmax = 1, s = 4, m = 30, relr = 1;
+  int mixed = 0;  // EG_MIXED: FP32 smoother on p >= 1 (phase A), then FP64 residuals (phase B)
+  int phase_b = 0;  // mixed mode: the current V-cycle is a defect-correction (phase B) cycle
   double cfl_max = 100.0;
   hipStream_t st = nullptr;
   std::string err;
@@ -35,7 +37,7 @@ struct eg_handle {
   double* rt[5] = {};
   double* ft[5] = {};
   double* uc0[5] = {};
-  double* F[5] = {};
+  void* F[5] = {};  // block LU factors, FP64 or (mixed) FP32
   int* perm[5] = {};
   double* dtau = nullptr;
   double* tmp = nullptr;
@@ -67,6 +69,8 @@ struct eg_handle {
   // state of the last steady solve (eg_solve_resume continues it)
   int sv_next = 0;
   double sv_r1 = 0.0;
+  int sv_phase_b = 0, sv_nmin = 0;  // mixed mode: phase B reached; cycle of the smallest norm
+  double sv_rmin = 0.0;
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
   std::vector<ProfRec> recs;
@@ -444,6 +448,21 @@ eg_status sync_status(eg_handle* h) {
 
 int NB(const eg_handle* h, int p) { return h->M.V * nmodes_of(h->M.d, p); }
 
+// Arithmetic of the kernels at level p.  Mixed mode, phase A: residuals,
+// blocks, LU and stage solves in FP32 on p >= 1.  Phase B: every residual in
+// FP64 and only the blocks, their LU and the stage solves in FP32, so that
+// the nonlinear evaluations that drive the state carry no FP32 noise.
+int blk_prec(const eg_handle* h, int p) { return (h->mixed && p >= 1) ? eg::PREC_FP32 : eg::PREC_FP64; }
+int res_prec(const eg_handle* h, int p) {
+  return (h->mixed && !h->phase_b && p >= 1) ? eg::PREC_FP32 : eg::PREC_FP64;
+}
+
+// Mixed mode switches to phase B for good once the FP64 residual norm has
+// dropped below this fraction of r_1, or has not reached a new minimum for
+// EG_STALL_CYCLES cycles (the FP32 noise floor of phase A is ~1e-5 r_1).
+constexpr double EG_PHASE_B_DROP = 1e-4;
+constexpr int EG_STALL_CYCLES = 100;
+
 double cfl_ramp(double cfl_max, double rn, double rref, int n, int pmax) {
   double a = (rn > 0.0) ? rref / rn : HUGE_VAL;
   double b = 1.0 + (n - 1.0) / (2.0 * pmax + 1.0);
@@ -468,14 +487,16 @@ eg_status run_prk(eg_handle* h, int p, double cfl, const double* ft) {
   const int N = nmodes_of(M.d, p), n = NB(h, p);
   const size_t K = (size_t)M.ne * n;
   PCALL(h, EG_K_TIMESTEP, p, eg::launch_timestep(M, p, N, cfl, 1.0, h->ut[p], h->dtau, h->st));
+  const int pb = blk_prec(h, p), pr = res_prec(h, p);
   PCALL(h, EG_K_JACOBIAN_LU, p,
-        eg::launch_jacobian(M, h->tabs[p], p, h->ut[p], h->dtau, h->F[p], h->perm[p], h->dfail, true, h->st));
+        eg::launch_jacobian(M, h->tabs[p], p, h->ut[p], h->dtau, h->F[p], h->perm[p], h->dfail, true, pb, h->st));
   PCALL(h, EG_K_TRANSFER, p, eg::launch_copy(h->ut[p], h->un[p], K, h->st));
   for (int k = 1; k <= h->s; ++k) {
-    if (k > 1) PCALL(h, EG_K_RESIDUAL, p, eg::launch_residual(M, h->tabs[p], p, h->ut[p], ft, h->rt[p], h->st));
+    if (k > 1)
+      PCALL(h, EG_K_RESIDUAL, p, eg::launch_residual(M, h->tabs[p], p, h->ut[p], ft, h->rt[p], pr, h->st));
     const double beta = 1.0 / (h->s - k + 1.0);
     PCALL(h, EG_K_PRK_STAGE, p,
-          eg::launch_prk_stage(M, n, h->F[p], h->perm[p], h->rt[p], nullptr, h->un[p], h->ut[p], beta, h->st));
+          eg::launch_prk_stage(M, n, h->F[p], h->perm[p], h->rt[p], nullptr, h->un[p], h->ut[p], beta, pb, h->st));
   }
   return EG_OK;
 }
@@ -486,18 +507,27 @@ eg_status vc_rec(eg_handle* h, int p, double cfl) {
   const DevMesh& M = h->M;
   const double* fp = (p == h->pmax) ? nullptr : h->ft[p];
   if (p == 0) return run_exp1(h, cfl, h->ut[0], fp);
+  const int pr = res_prec(h, p);
+  if (p == h->pmax && pr == eg::PREC_FP32) {
+    // phase A: rt holds R64(u^n) (the entry norm's residual); the top level
+    // takes d = R64(u^n) - R32(u^n) as its forcing for this cycle, so that the
+    // first stage sees the FP64 residual and the later ones R32 + d
+    const size_t K = (size_t)M.ne * NB(h, p);
+    PCALL(h, EG_K_RESIDUAL, p, eg::launch_residual(M, h->tabs[p], p, h->ut[p], nullptr, h->tmp2, pr, h->st));
+    PCALL(h, EG_K_TRANSFER, p, eg::launch_sub(h->rt[p], h->tmp2, h->ft[p], K, h->st));
+    fp = h->ft[p];
+  }
   ECHK(run_prk(h, p, cfl, fp));
   const int N = nmodes_of(M.d, p), Nc = nmodes_of(M.d, p - 1), rows = M.ne * M.V;
-  PCALL(h, EG_K_RESIDUAL, p, eg::launch_residual(M, h->tabs[p], p, h->ut[p], fp, h->rt[p], h->st));
+  PCALL(h, EG_K_RESIDUAL, p, eg::launch_residual(M, h->tabs[p], p, h->ut[p], fp, h->rt[p], pr, h->st));
   PCALL(h, EG_K_TRANSFER, p, eg::launch_restrict(M, p, h->ut[p], h->ut[p - 1], h->uc0[p - 1], h->st));
-  if (p - 1 >= 1) {
+  {
+    // FAS forcing of level p - 1 with that level's own residual R_{p-1}(v0)
+    // (FP32 on p - 1 >= 1 in mixed mode, FP64 on p = 0)
+    const int pc = res_prec(h, p - 1);
     PCALL(h, EG_K_RESIDUAL, p - 1,
-          eg::launch_residual(M, h->tabs[p - 1], p - 1, h->ut[p - 1], nullptr, h->rt[p - 1], h->st));
+          eg::launch_residual(M, h->tabs[p - 1], p - 1, h->ut[p - 1], nullptr, h->rt[p - 1], pc, h->st));
     PCALL(h, EG_K_TRANSFER, p, eg::launch_fas(N, Nc, rows, h->rt[p], h->rt[p - 1], h->ft[p - 1], h->st));
-  } else {
-    // the p = 0 forcing needs R_0(v0): evaluate it with the residual kernel
-    PCALL(h, EG_K_RESIDUAL, 0, eg::launch_residual(M, h->tabs[0], 0, h->ut[0], nullptr, h->rt[0], h->st));
-    PCALL(h, EG_K_TRANSFER, p, eg::launch_fas(N, Nc, rows, h->rt[p], h->rt[0], h->ft[0], h->st));
   }
   ECHK(vc_rec(h, p - 1, cfl));
   PCALL(h, EG_K_TRANSFER, p, eg::launch_prolong(N, Nc, rows, h->ut[p], h->ut[p - 1], h->uc0[p - 1], h->st));
@@ -508,7 +538,9 @@ eg_status vc_rec(eg_handle* h, int p, double cfl) {
 eg_status entry_norm(eg_handle* h, double* rn) {
   const DevMesh& M = h->M;
   const int p = h->pmax, N = nmodes_of(M.d, p);
-  PCALL(h, EG_K_RESIDUAL, p, eg::launch_residual(M, h->tabs[p], p, h->ut[p], nullptr, h->rt[p], h->st));
+  // the norm is always of the FP64 residual
+  PCALL(h, EG_K_RESIDUAL, p,
+        eg::launch_residual(M, h->tabs[p], p, h->ut[p], nullptr, h->rt[p], eg::PREC_FP64, h->st));
   PCALL(h, EG_K_NORM, p, eg::launch_norm(M, N, h->rt[p], h->npart, h->nout, h->st));
   HIPCHK(h, hipMemcpyAsync(h->hpin, h->nout, sizeof(double), hipMemcpyDeviceToHost, h->st));
   HIPCHK(h, hipMemcpyAsync(h->hpin + 1, h->dfail, sizeof(int), hipMemcpyDeviceToHost, h->st));
@@ -534,8 +566,9 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
   const int d = mesh->dim;
   const int pmax_lim = (d == 2) ? 4 : 2;
   if (prm->p_max < 0 || prm->p_max > pmax_lim || prm->rk_stages < 1 || prm->krylov_m < 1 || prm->krylov_m > 48 ||
-      !(prm->cfl_max > 0.0) || !(prm->gamma > 1.0) || !(prm->mach >= 0.0)) {
-    h->err = "invalid parameters (p_max, rk_stages, krylov_m 1..48, cfl_max, gamma or mach)";
+      !(prm->cfl_max > 0.0) || !(prm->gamma > 1.0) || !(prm->mach >= 0.0) ||
+      (prm->precision != EG_FP64 && prm->precision != EG_MIXED)) {
+    h->err = "invalid parameters (p_max, rk_stages, krylov_m 1..48, cfl_max, gamma, mach or precision)";
     *out = h;
     return EG_ERR_ARG;
   }
@@ -543,6 +576,7 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
   h->s = prm->rk_stages;
   h->m = prm->krylov_m;
   h->relr = prm->relative_ramp;
+  h->mixed = prm->precision == EG_MIXED;
   h->cfl_max = prm->cfl_max;
   h->st = static_cast<hipStream_t>(hip_stream);
   h->modes = hier_modes(d, h->pmax);
@@ -591,7 +625,11 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
   {
     size_t per = 0;
     for (int p = 1; p <= h->pmax; ++p) per = std::max(per, eg::jac_points_per_elem(d, p));
-    if (per) AL(M.bc, (size_t)ne * per);
+    if (per) {
+      double* bc = nullptr;  // sized for FP64 values; the FP32 assembly uses the front half
+      AL(bc, (size_t)ne * per);
+      M.bc = bc;
+    }
   }
   for (int p = 0; p <= h->pmax; ++p) {
     const size_t K = (size_t)ne * V * nmodes_of(d, p);
@@ -603,7 +641,15 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
     if (p >= 1) {
       const size_t n = (size_t)V * nmodes_of(d, p);
       if (eg::jacobian_supported(d, p)) {
-        AL(h->F[p], (size_t)ne * n * n);
+        if (h->mixed) {
+          float* f = nullptr;
+          AL(f, (size_t)ne * n * n);
+          h->F[p] = f;
+        } else {
+          double* f = nullptr;
+          AL(f, (size_t)ne * n * n);
+          h->F[p] = f;
+        }
         AL(h->perm[p], (size_t)ne * n);
       }
     }
@@ -686,7 +732,7 @@ eg_status eg_residual(eg_handle* h, int p, const double* u_dev, double* r_dev) {
   if (p < 0 || p > h->pmax) return fail(h, EG_ERR_ARG, "order out of range");
   const int N = nmodes_of(h->M.d, p);
   HIPCHK(h, eg::launch_basis(h->M, N, u_dev, h->tmp, 0, h->st));
-  HIPCHK(h, eg::launch_residual(h->M, h->tabs[p], p, h->tmp, nullptr, h->tmp2, h->st));
+  HIPCHK(h, eg::launch_residual(h->M, h->tabs[p], p, h->tmp, nullptr, h->tmp2, blk_prec(h, p), h->st));
   HIPCHK(h, eg::launch_basis(h->M, N, h->tmp2, r_dev, 2, h->st));
   return EG_OK;
 }
@@ -706,7 +752,8 @@ eg_status eg_element_jacobian(eg_handle* h, int p, const double* u_dev, double* 
   if (!eg::jacobian_supported(h->M.d, p)) return fail(h, EG_ERR_UNSUPPORTED, "element block too large");
   const int N = nmodes_of(h->M.d, p);
   HIPCHK(h, eg::launch_basis(h->M, N, u_dev, h->tmp, 0, h->st));
-  HIPCHK(h, eg::launch_jacobian(h->M, h->tabs[p], p, h->tmp, h->dtau, D_dev, nullptr, h->dfail, false, h->st));
+  HIPCHK(h, eg::launch_jacobian(h->M, h->tabs[p], p, h->tmp, h->dtau, D_dev, nullptr, h->dfail, false,
+                                eg::PREC_FP64, h->st));
   HIPCHK(h, eg::launch_jac_to_psi(h->M, N, D_dev, h->st));
   return EG_OK;
 }
@@ -722,7 +769,8 @@ eg_status eg_prk_step(eg_handle* h, int p, double cfl, double* u_dev, const doub
     HIPCHK(h, eg::launch_basis(h->M, N, f_dev, h->tmp, 3, h->st));
     ft = h->tmp;
   }
-  HIPCHK(h, eg::launch_residual(h->M, h->tabs[p], p, h->ut[p], ft, h->rt[p], h->st));
+  h->phase_b = 0;  // one PRK step in the handle's smoother arithmetic (phase A in mixed mode)
+  HIPCHK(h, eg::launch_residual(h->M, h->tabs[p], p, h->ut[p], ft, h->rt[p], res_prec(h, p), h->st));
   ECHK(run_prk(h, p, cfl, ft));
   HIPCHK(h, eg::launch_basis(h->M, N, h->ut[p], u_dev, 1, h->st));
   return EG_OK;
@@ -804,6 +852,7 @@ eg_status eg_vcycle(eg_handle* h, double* u_dev, int n, double rref, double* rn_
   if (!std::isfinite(rn)) return fail(h, EG_ERR_DIVERGED, "non-finite residual norm");
   const double cfl = cfl_ramp(h->cfl_max, rn, rref > 0.0 ? rref : rn, n, h->pmax);
   if (cfl_host) *cfl_host = cfl;
+  h->phase_b = h->mixed && rn <= EG_PHASE_B_DROP * (rref > 0.0 ? rref : rn);
   ECHK(vc_rec(h, h->pmax, cfl));
   HIPCHK(h, eg::launch_basis(h->M, N, h->ut[h->pmax], u_dev, 1, h->st));
   ECHK(sync_status(h));
@@ -831,6 +880,11 @@ eg_status solve_loop(eg_handle* h, double* u_dev, int n0, double r1, double drop
     if (rn <= drop_tol * r1) break;
     if (n - n0 == max_cycles) { st = fail(h, EG_ERR_NOT_CONVERGED, "max_cycles reached"); break; }
     const double cfl = cfl_ramp(h->cfl_max, rn, h->relr ? r1 : 1.0, n, h->pmax);
+    if (h->mixed && !h->sv_phase_b) {
+      if (!(rn >= h->sv_rmin)) { h->sv_rmin = rn; h->sv_nmin = n; }
+      if (rn <= EG_PHASE_B_DROP * r1 || n - h->sv_nmin >= EG_STALL_CYCLES) h->sv_phase_b = 1;
+    }
+    h->phase_b = h->sv_phase_b;
     st = vc_rec(h, h->pmax, cfl);
     if (st != EG_OK) break;
   }
@@ -847,6 +901,9 @@ eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_
   if (!h || !u_dev || !hist_host || !n_cycles_host || max_cycles < 0) return EG_ERR_ARG;
   if (!eg::jacobian_supported(h->M.d, h->pmax) && h->pmax > 0)
     return fail(h, EG_ERR_UNSUPPORTED, "element block too large");
+  h->sv_phase_b = 0;
+  h->sv_nmin = 1;
+  h->sv_rmin = HUGE_VAL;
   return solve_loop(h, u_dev, 1, -1.0, drop_tol, max_cycles, hist_host, n_cycles_host);
 }
 

@@ -1,4 +1,6 @@
-// HIP kernels of the eMG hot path for gfx950 (MI355X), FP64.
+// HIP kernels of the eMG hot path for gfx950 (MI355X): FP64, with FP32
+// instantiations of the smoother kernels (residual, block assembly + LU, PRK
+// stage) for the mixed-precision mode.
 //
 // State representation.  The paper's basis is psi = T phi per element
 // (Section 3.2, eq. (basis)): reference tensor-Legendre phi orthonormalised in
@@ -37,23 +39,23 @@ namespace eg {
 // Multilinear element map: the vectors c[r] with c[r] . (dx/dxi_r') = det
 // delta_rr', i.e. det * grad_x = sum_r c[r] d/dxi_r; (2s-1) c[r] is the scaled
 // outward normal of face (r, s).
-template <int D>
-__device__ __forceinline__ void geom(const double* X, const double* xi, double c[D][D], double& det) {
-  double t[D][D];
+template <int D, class R>
+__device__ __forceinline__ void geom(const R* X, const R* xi, R c[D][D], R& det) {
+  R t[D][D];
 #pragma unroll
   for (int r = 0; r < D; ++r)
 #pragma unroll
-    for (int a = 0; a < D; ++a) t[r][a] = 0.0;
+    for (int a = 0; a < D; ++a) t[r][a] = R(0);
 #pragma unroll
   for (int k = 0; k < (1 << D); ++k) {
-    double g[D];
+    R g[D];
 #pragma unroll
     for (int r = 0; r < D; ++r) {
-      double v = 1.0;
+      R v = R(1);
 #pragma unroll
       for (int q = 0; q < D; ++q) {
-        double s = ((k >> q) & 1) ? 1.0 : -1.0;
-        v *= (q == r) ? 0.5 * s : 0.5 * (1.0 + s * xi[q]);
+        R s = ((k >> q) & 1) ? R(1) : R(-1);
+        v *= (q == r) ? R(0.5) * s : R(0.5) * (R(1) + s * xi[q]);
       }
       g[r] = v;
     }
@@ -103,53 +105,53 @@ __device__ __forceinline__ void nb_face_index(int code, const int* ik, int* jk) 
 }
 
 // phi_k at face lf, tangential Gauss indices ik.
-template <int D, int P>
-__device__ __forceinline__ double phi_face(const Tab<D, P>& t, int k, int lf, const int* ta, const int* ik) {
-  double v = t.Lb[t.m[k][lf >> 1]][lf & 1];
+template <int D, int P, class R>
+__device__ __forceinline__ R phi_face(const Tab<D, P, R>& t, int k, int lf, const int* ta, const int* ik) {
+  R v = t.Lb[t.m[k][lf >> 1]][lf & 1];
 #pragma unroll
   for (int q = 0; q < D - 1; ++q) v *= t.L[t.m[k][ta[q]]][ik[q]];
   return v;
 }
 
-template <int D, int P>
-__device__ __forceinline__ double phi_vol(const Tab<D, P>& t, int k, const int* iq) {
-  double v = t.L[t.m[k][0]][iq[0]];
+template <int D, int P, class R>
+__device__ __forceinline__ R phi_vol(const Tab<D, P, R>& t, int k, const int* iq) {
+  R v = t.L[t.m[k][0]][iq[0]];
 #pragma unroll
   for (int r = 1; r < D; ++r) v *= t.L[t.m[k][r]][iq[r]];
   return v;
 }
 
-template <int D, int P>
-__device__ __forceinline__ double dphi_vol(const Tab<D, P>& t, int k, const int* iq, int r) {
-  double v = 1.0;
+template <int D, int P, class R>
+__device__ __forceinline__ R dphi_vol(const Tab<D, P, R>& t, int k, const int* iq, int r) {
+  R v = R(1);
 #pragma unroll
   for (int q = 0; q < D; ++q) v *= (q == r) ? t.dL[t.m[k][q]][iq[q]] : t.L[t.m[k][q]][iq[q]];
   return v;
 }
 
-template <int D, int P>
-__device__ __forceinline__ void copy_tab(Tab<D, P>& dst, const Tab<D, P>& src) {
-  const int n = sizeof(Tab<D, P>) / 4;
+template <int D, int P, class R>
+__device__ __forceinline__ void copy_tab(Tab<D, P, R>& dst, const Tab<D, P, R>& src) {
+  const int n = sizeof(Tab<D, P, R>) / 4;
   const uint32_t* s = reinterpret_cast<const uint32_t*>(&src);
   uint32_t* d = reinterpret_cast<uint32_t*>(&dst);
   for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
 }
 
-// Copies cnt doubles from global memory into LDS; each thread issues all of
-// its (at most ITEMS) loads before its stores, so the global latency is paid
-// once instead of once per element.
-template <int ITEMS>
-__device__ __forceinline__ void stage(double* dst, const double* __restrict__ src, int cnt, int tid, int nthr) {
-  double r[ITEMS];
+// Copies cnt values from global memory into LDS (converting to the LDS
+// type); each thread issues all of its (at most ITEMS) loads before its
+// stores, so the global latency is paid once instead of once per element.
+template <int ITEMS, class DT, class ST>
+__device__ __forceinline__ void stage(DT* dst, const ST* __restrict__ src, int cnt, int tid, int nthr) {
+  ST r[ITEMS];
 #pragma unroll
   for (int u = 0; u < ITEMS; ++u) {
     const int i = tid + u * nthr;
-    r[u] = (i < cnt) ? src[i] : 0.0;
+    r[u] = (i < cnt) ? src[i] : ST(0);
   }
 #pragma unroll
   for (int u = 0; u < ITEMS; ++u) {
     const int i = tid + u * nthr;
-    if (i < cnt) dst[i] = r[u];
+    if (i < cnt) dst[i] = DT(r[u]);
   }
 }
 
@@ -170,18 +172,18 @@ __device__ __forceinline__ double wave_sum(double v) {
 // thread per output (element, var, mode) projects onto the test functions.
 // Optional: add a forcing vector.
 // ---------------------------------------------------------------------------
-template <int D, int P, int EB>
+template <int D, int P, int EB, class R>
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut, const double* __restrict__ fadd,
                                                   double* __restrict__ rt, const double* __restrict__ xv,
                                                   const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
-                                                  int ne, Tab<D, P> tab, Gas gas) {
+                                                  int ne, Tab<D, P, R> tab, GasT<R> gas) {
   using C = Cfg<D, P>;
   constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, NC = C::NC;
-  __shared__ double s_u[EB * V * N];
-  __shared__ double s_fc[EB * QV * V * D];
-  __shared__ double s_ff[EB * NF * QF * V];
-  __shared__ double s_x[EB * NC * D];
-  __shared__ Tab<D, P> t;
+  __shared__ R s_u[EB * V * N];
+  __shared__ R s_fc[EB * QV * V * D];
+  __shared__ R s_ff[EB * NF * QF * V];
+  __shared__ R s_x[EB * NC * D];
+  __shared__ Tab<D, P, R> t;
   const int tid = threadIdx.x;
   const int e0 = blockIdx.x * EB;
   copy_tab(t, tab);
@@ -196,26 +198,26 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
     const int el = it / QV, q = it % QV;
     if (e0 + el >= ne) continue;
     int iq[D];
-    double xi[D], wq = 1.0;
+    R xi[D], wq = R(1);
     {
       int r0 = q;
 #pragma unroll
       for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; xi[r] = t.x[iq[r]]; wq *= t.w[iq[r]]; }
     }
-    double U[V];
+    R U[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) U[v] = 0.0;
-    const double* su = &s_u[el * V * N];
+    for (int v = 0; v < V; ++v) U[v] = R(0);
+    const R* su = &s_u[el * V * N];
     for (int k = 0; k < N; ++k) {
-      double ph = phi_vol<D, P>(t, k, iq);
+      R ph = phi_vol<D, P, R>(t, k, iq);
 #pragma unroll
       for (int v = 0; v < V; ++v) U[v] += su[v * N + k] * ph;
     }
-    double c[D][D], det;
+    R c[D][D], det;
     geom<D>(&s_x[el * NC * D], xi, c, det);
 #pragma unroll
     for (int r = 0; r < D; ++r) {
-      double F[V];
+      R F[V];
       flux_n<D>(U, c[r], F, gas.g);
 #pragma unroll
       for (int v = 0; v < V; ++v) s_fc[((el * QV + q) * V + v) * D + r] = wq * F[v];
@@ -228,29 +230,29 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
     if (e >= ne) continue;
     int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1];
     face_axes<D>(lf, ta);
-    double xi[D], wk = 1.0;
-    xi[lf >> 1] = (lf & 1) ? 1.0 : -1.0;
+    R xi[D], wk = R(1);
+    xi[lf >> 1] = (lf & 1) ? R(1) : R(-1);
     {
       int r0 = k;
 #pragma unroll
       for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; xi[ta[q]] = t.x[ik[q]]; wk *= t.w[ik[q]]; }
     }
-    double UL[V], UR[V];
+    R UL[V], UR[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) UL[v] = 0.0;
-    const double* su = &s_u[el * V * N];
+    for (int v = 0; v < V; ++v) UL[v] = R(0);
+    const R* su = &s_u[el * V * N];
     for (int j = 0; j < N; ++j) {
-      double ph = phi_face<D, P>(t, j, lf, ta, ik);
+      R ph = phi_face<D, P, R>(t, j, lf, ta, ik);
 #pragma unroll
       for (int v = 0; v < V; ++v) UL[v] += su[v * N + j] * ph;
     }
-    double c[D][D], det;
+    R c[D][D], det;
     geom<D>(&s_x[el * NC * D], xi, c, det);
-    double nh[D], a2 = 0.0;
-    const double sg = (lf & 1) ? 1.0 : -1.0;
+    R nh[D], a2 = R(0);
+    const R sg = (lf & 1) ? R(1) : R(-1);
 #pragma unroll
     for (int a = 0; a < D; ++a) { nh[a] = sg * c[lf >> 1][a]; a2 += nh[a] * nh[a]; }
-    const double area = sqrt(a2);
+    const R area = dsqrt(a2);
 #pragma unroll
     for (int a = 0; a < D; ++a) nh[a] /= area;
     const int nb = nbr[(size_t)e * NF + lf];
@@ -261,19 +263,19 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
       face_axes<D>(lf2, ta2);
       nb_face_index<D, Q>(code, ik, jk);
 #pragma unroll
-      for (int v = 0; v < V; ++v) UR[v] = 0.0;
+      for (int v = 0; v < V; ++v) UR[v] = R(0);
       const double* un = ut + (size_t)nb * V * N;
       for (int j = 0; j < N; ++j) {
-        double ph = phi_face<D, P>(t, j, lf2, ta2, jk);
+        R ph = phi_face<D, P, R>(t, j, lf2, ta2, jk);
 #pragma unroll
-        for (int v = 0; v < V; ++v) UR[v] += un[v * N + j] * ph;
+        for (int v = 0; v < V; ++v) UR[v] += R(un[v * N + j]) * ph;
       }
     } else if (nb == NB_WALL) {
       ghost_wall<D>(UL, nh, UR);
     } else {
       ghost_far<D>(UL, nh, UR, gas.Uinf, gas.g);
     }
-    double F[V];
+    R F[V];
     rusanov<D>(UL, UR, nh, F, gas.g);
 #pragma unroll
     for (int v = 0; v < V; ++v) s_ff[((el * NF + lf) * QF + k) * V + v] = wk * area * F[v];
@@ -284,15 +286,15 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
     const int el = it / (V * N), v = (it / N) % V, i = it % N;
     const int e = e0 + el;
     if (e >= ne) continue;
-    double acc = 0.0;
+    R acc = R(0);
     for (int q = 0; q < QV; ++q) {
       int iq[D];
       int r0 = q;
 #pragma unroll
       for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
-      const double* fc = &s_fc[((el * QV + q) * V + v) * D];
+      const R* fc = &s_fc[((el * QV + q) * V + v) * D];
 #pragma unroll
-      for (int r = 0; r < D; ++r) acc += dphi_vol<D, P>(t, i, iq, r) * fc[r];
+      for (int r = 0; r < D; ++r) acc += dphi_vol<D, P, R>(t, i, iq, r) * fc[r];
     }
     for (int lf = 0; lf < NF; ++lf) {
       int ta[D - 1 > 0 ? D - 1 : 1];
@@ -302,11 +304,11 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
         int r0 = k;
 #pragma unroll
         for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
-        acc -= phi_face<D, P>(t, i, lf, ta, ik) * s_ff[((el * NF + lf) * QF + k) * V + v];
+        acc -= phi_face<D, P, R>(t, i, lf, ta, ik) * s_ff[((el * NF + lf) * QF + k) * V + v];
       }
     }
     const size_t o = (size_t)e0 * V * N + it;
-    rt[o] = fadd ? acc + fadd[o] : acc;
+    rt[o] = fadd ? double(acc) + fadd[o] : double(acc);
   }
 }
 
@@ -321,32 +323,33 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
 // write Dt row-major.  One block per element.
 // ---------------------------------------------------------------------------
 template <int D, int P>
-constexpr int jac_lds_doubles() {
+constexpr int jac_lds_values() {
   using C = Cfg<D, P>;
   constexpr int ph1 = C::V * C::N + C::NC * D + C::QV * D * C::V * C::V + C::NF * C::QF * C::V * C::V;
   constexpr int ph2 = C::NB * C::NB;
   return (ph1 > ph2 ? ph1 : ph2);
 }
 
-template <int D, int P, bool FACTOR>
+template <int D, int P, bool FACTOR, class R>
 __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut, const double* __restrict__ xv,
                                                   const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
                                                   const double* __restrict__ Gpk, int NT, const double* __restrict__ dtau,
-                                                  double* __restrict__ out, int* __restrict__ perm, int* __restrict__ fail,
-                                                  int ne, Tab<D, P> tab, Gas gas) {
+                                                  R* __restrict__ out, int* __restrict__ perm, int* __restrict__ fail,
+                                                  int ne, Tab<D, P, R> tab, GasT<R> gas) {
   using C = Cfg<D, P>;
   constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, NC = C::NC, n = C::NB;
   constexpr int NP = N * N;
   constexpr int ROUNDS = (NP + 255) / 256;
-  extern __shared__ double smem[];
-  __shared__ Tab<D, P> t;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* smem = reinterpret_cast<R*>(smem_raw);
+  __shared__ Tab<D, P, R> t;
   __shared__ int s_perm[n];
   __shared__ int s_piv;
-  double* s_u = smem;
-  double* s_x = s_u + V * N;
-  double* s_B = s_x + NC * D;
-  double* s_C = s_B + QV * D * V * V;
-  double* s_A = smem;  // phase 2 reuses the whole region
+  R* s_u = smem;
+  R* s_x = s_u + V * N;
+  R* s_B = s_x + NC * D;
+  R* s_C = s_B + QV * D * V * V;
+  R* s_A = smem;  // phase 2 reuses the whole region
   const int tid = threadIdx.x;
   const int e = blockIdx.x;
   if (e >= ne) return;
@@ -356,23 +359,23 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
   __syncthreads();
   for (int q = tid; q < QV; q += blockDim.x) {
     int iq[D];
-    double xi[D], wq = 1.0;
+    R xi[D], wq = R(1);
     int r0 = q;
 #pragma unroll
     for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; xi[r] = t.x[iq[r]]; wq *= t.w[iq[r]]; }
-    Dual<V> U[V];
+    Dual<V, R> U[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      double s = 0.0;
-      for (int k = 0; k < N; ++k) s += s_u[v * N + k] * phi_vol<D, P>(t, k, iq);
-      U[v] = Dual<V>(s);
-      U[v].d[v] = 1.0;
+      R s = R(0);
+      for (int k = 0; k < N; ++k) s += s_u[v * N + k] * phi_vol<D, P, R>(t, k, iq);
+      U[v] = Dual<V, R>(s);
+      U[v].d[v] = R(1);
     }
-    double c[D][D], det;
+    R c[D][D], det;
     geom<D>(s_x, xi, c, det);
 #pragma unroll
     for (int r = 0; r < D; ++r) {
-      Dual<V> F[V];
+      Dual<V, R> F[V];
       flux_n<D>(U, c[r], F, gas.g);
 #pragma unroll
       for (int v = 0; v < V; ++v)
@@ -384,29 +387,29 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
     const int lf = it / QF, k = it % QF;
     int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1];
     face_axes<D>(lf, ta);
-    double xi[D], wk = 1.0;
-    xi[lf >> 1] = (lf & 1) ? 1.0 : -1.0;
+    R xi[D], wk = R(1);
+    xi[lf >> 1] = (lf & 1) ? R(1) : R(-1);
     int r0 = k;
 #pragma unroll
     for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; xi[ta[q]] = t.x[ik[q]]; wk *= t.w[ik[q]]; }
-    Dual<V> UL[V];
+    Dual<V, R> UL[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      double s = 0.0;
-      for (int j = 0; j < N; ++j) s += s_u[v * N + j] * phi_face<D, P>(t, j, lf, ta, ik);
-      UL[v] = Dual<V>(s);
-      UL[v].d[v] = 1.0;
+      R s = R(0);
+      for (int j = 0; j < N; ++j) s += s_u[v * N + j] * phi_face<D, P, R>(t, j, lf, ta, ik);
+      UL[v] = Dual<V, R>(s);
+      UL[v].d[v] = R(1);
     }
-    double c[D][D], det;
+    R c[D][D], det;
     geom<D>(s_x, xi, c, det);
-    double nh[D], a2 = 0.0;
-    const double sg = (lf & 1) ? 1.0 : -1.0;
+    R nh[D], a2 = R(0);
+    const R sg = (lf & 1) ? R(1) : R(-1);
 #pragma unroll
     for (int a = 0; a < D; ++a) { nh[a] = sg * c[lf >> 1][a]; a2 += nh[a] * nh[a]; }
-    const double area = sqrt(a2);
+    const R area = dsqrt(a2);
 #pragma unroll
     for (int a = 0; a < D; ++a) nh[a] /= area;
-    Dual<V> F[V];
+    Dual<V, R> F[V];
     const int nb = nbr[(size_t)e * NF + lf];
     if (nb >= 0) {
       const int code = ncode[(size_t)e * NF + lf];
@@ -414,22 +417,22 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
       int ta2[D - 1 > 0 ? D - 1 : 1], jk[D - 1 > 0 ? D - 1 : 1];
       face_axes<D>(lf2, ta2);
       nb_face_index<D, Q>(code, ik, jk);
-      double UR[V];
+      R UR[V];
       const double* un = ut + (size_t)nb * V * N;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        double s = 0.0;
-        for (int j = 0; j < N; ++j) s += un[v * N + j] * phi_face<D, P>(t, j, lf2, ta2, jk);
+        R s = R(0);
+        for (int j = 0; j < N; ++j) s += R(un[v * N + j]) * phi_face<D, P, R>(t, j, lf2, ta2, jk);
         UR[v] = s;
       }
       rusanov<D>(UL, UR, nh, F, gas.g);
     } else {
-      Dual<V> UG[V];
+      Dual<V, R> UG[V];
       if (nb == NB_WALL) ghost_wall<D>(UL, nh, UG);
       else ghost_far<D>(UL, nh, UG, gas.Uinf, gas.g);
       rusanov<D>(UL, UG, nh, F, gas.g);
     }
-    const double wa = wk * area;
+    const R wa = wk * area;
 #pragma unroll
     for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -437,11 +440,11 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
   }
   __syncthreads();
   // contraction over quadrature points, one (i, j) mode pair per thread and round
-  double acc[ROUNDS][V * V];
+  R acc[ROUNDS][V * V];
 #pragma unroll
   for (int rd = 0; rd < ROUNDS; ++rd) {
 #pragma unroll
-    for (int x = 0; x < V * V; ++x) acc[rd][x] = 0.0;
+    for (int x = 0; x < V * V; ++x) acc[rd][x] = R(0);
     const int pr = rd * 256 + tid;
     if (pr < NP) {
       const int i = pr / N, j = pr % N;
@@ -450,11 +453,11 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
         int r0 = q;
 #pragma unroll
         for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
-        const double pj = phi_vol<D, P>(t, j, iq);
+        const R pj = phi_vol<D, P, R>(t, j, iq);
 #pragma unroll
         for (int r = 0; r < D; ++r) {
-          const double a = dphi_vol<D, P>(t, i, iq, r) * pj;
-          const double* B = &s_B[(q * D + r) * V * V];
+          const R a = dphi_vol<D, P, R>(t, i, iq, r) * pj;
+          const R* B = &s_B[(q * D + r) * V * V];
 #pragma unroll
           for (int x = 0; x < V * V; ++x) acc[rd][x] += a * B[x];
         }
@@ -467,8 +470,8 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
           int r0 = k;
 #pragma unroll
           for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
-          const double a = phi_face<D, P>(t, i, lf, ta, ik) * phi_face<D, P>(t, j, lf, ta, ik);
-          const double* Cm = &s_C[(lf * QF + k) * V * V];
+          const R a = phi_face<D, P, R>(t, i, lf, ta, ik) * phi_face<D, P, R>(t, j, lf, ta, ik);
+          const R* Cm = &s_C[(lf * QF + k) * V * V];
 #pragma unroll
           for (int x = 0; x < V * V; ++x) acc[rd][x] -= a * Cm[x];
         }
@@ -490,19 +493,19 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
     return;
   } else {
     __syncthreads();  // every thread is done with s_B / s_C
-    const double idt = 1.0 / dtau[e];
+    const R idt = R(1.0 / dtau[e]);
     const double* G = Gpk + (size_t)e * NT;
 #pragma unroll
     for (int rd = 0; rd < ROUNDS; ++rd) {
       const int pr = rd * 256 + tid;
       if (pr < NP) {
         const int i = pr / N, j = pr % N;
-        const double gij = (i >= j) ? G[i * (i + 1) / 2 + j] : G[j * (j + 1) / 2 + i];
+        const R gij = R((i >= j) ? G[i * (i + 1) / 2 + j] : G[j * (j + 1) / 2 + i]);
 #pragma unroll
         for (int v = 0; v < V; ++v)
 #pragma unroll
           for (int w = 0; w < V; ++w)
-            s_A[(v * N + i) * n + w * N + j] = ((v == w) ? gij * idt : 0.0) - acc[rd][v * V + w];
+            s_A[(v * N + i) * n + w * N + j] = ((v == w) ? gij * idt : R(0)) - acc[rd][v * V + w];
       }
     }
     for (int i = tid; i < n; i += blockDim.x) s_perm[i] = i;
@@ -510,35 +513,35 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
     // right-looking LU with partial pivoting
     for (int k = 0; k < n; ++k) {
       if (tid < 64) {
-        double best = -1.0;
+        R best = R(-1);
         int bi = k;
         for (int i = k + tid; i < n; i += 64) {
-          double a = fabs(s_A[i * n + k]);
+          R a = dabs(s_A[i * n + k]);
           if (a > best) { best = a; bi = i; }
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
-          double ob = __shfl_xor(best, o, 64);
+          R ob = __shfl_xor(best, o, 64);
           int oi = __shfl_xor(bi, o, 64);
           if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
         }
         if (tid == 0) {
           s_piv = bi;
-          if (!(best > 0.0)) atomicOr(fail, 1);
+          if (!(best > R(0))) atomicOr(fail, 1);
         }
       }
       __syncthreads();
       const int pv = s_piv;
       if (pv != k) {
         for (int j = tid; j < n; j += blockDim.x) {
-          double tmp = s_A[k * n + j];
+          R tmp = s_A[k * n + j];
           s_A[k * n + j] = s_A[pv * n + j];
           s_A[pv * n + j] = tmp;
         }
         if (tid == 0) { int tp = s_perm[k]; s_perm[k] = s_perm[pv]; s_perm[pv] = tp; }
       }
       __syncthreads();
-      const double ipiv = 1.0 / s_A[k * n + k];
+      const R ipiv = R(1) / s_A[k * n + k];
       for (int i = k + 1 + tid; i < n; i += blockDim.x) s_A[i * n + k] *= ipiv;
       __syncthreads();
       const int mrem = n - k - 1;
@@ -561,44 +564,44 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
 // face point (lf, k) writes Cf[v][w] = w_k |n dsigma| dF~_v/dU_own_w (with the
 // ghost chain rule on boundary faces), all by dual numbers.  Layout per
 // element: [QV][D][V][V] then [NF*QF][V][V].
-template <int D, int P>
+template <int D, int P, class R>
 __global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ ut, const double* __restrict__ xv,
                                                     const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
-                                                    double* __restrict__ BC, int ne, Tab<D, P> tab, Gas gas) {
+                                                    R* __restrict__ BC, int ne, Tab<D, P, R> tab, GasT<R> gas) {
   using C = Cfg<D, P>;
   constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, NC = C::NC;
   constexpr int NPT = QV + NF * QF;
   constexpr int PER = (QV * D + NF * QF) * V * V;
-  __shared__ Tab<D, P> t;
+  __shared__ Tab<D, P, R> t;
   copy_tab(t, tab);
   __syncthreads();
   const int it = blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= ne * NPT) return;
   const int e = it / NPT, pt = it % NPT;
   const double* ue = ut + (size_t)e * V * N;
-  double X[NC * D];
+  R X[NC * D];
 #pragma unroll
-  for (int a = 0; a < NC * D; ++a) X[a] = xv[(size_t)e * NC * D + a];
-  double* out = BC + (size_t)e * PER;
+  for (int a = 0; a < NC * D; ++a) X[a] = R(xv[(size_t)e * NC * D + a]);
+  R* out = BC + (size_t)e * PER;
   if (pt < QV) {
     const int q = pt;
     int iq[D], r0 = q;
-    double xi[D], wq = 1.0;
+    R xi[D], wq = R(1);
 #pragma unroll
     for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; xi[r] = t.x[iq[r]]; wq *= t.w[iq[r]]; }
-    Dual<V> U[V];
+    Dual<V, R> U[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      double sacc = 0.0;
-      for (int k = 0; k < N; ++k) sacc += ue[v * N + k] * phi_vol<D, P>(t, k, iq);
-      U[v] = Dual<V>(sacc);
-      U[v].d[v] = 1.0;
+      R sacc = R(0);
+      for (int k = 0; k < N; ++k) sacc += R(ue[v * N + k]) * phi_vol<D, P, R>(t, k, iq);
+      U[v] = Dual<V, R>(sacc);
+      U[v].d[v] = R(1);
     }
-    double c[D][D], det;
+    R c[D][D], det;
     geom<D>(X, xi, c, det);
 #pragma unroll
     for (int r = 0; r < D; ++r) {
-      Dual<V> F[V];
+      Dual<V, R> F[V];
       flux_n<D>(U, c[r], F, gas.g);
 #pragma unroll
       for (int v = 0; v < V; ++v)
@@ -609,28 +612,28 @@ __global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ u
     const int fi = pt - QV, lf = fi / QF, k = fi % QF;
     int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1], r0 = k;
     face_axes<D>(lf, ta);
-    double xi[D], wk = 1.0;
-    xi[lf >> 1] = (lf & 1) ? 1.0 : -1.0;
+    R xi[D], wk = R(1);
+    xi[lf >> 1] = (lf & 1) ? R(1) : R(-1);
 #pragma unroll
     for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; xi[ta[q]] = t.x[ik[q]]; wk *= t.w[ik[q]]; }
-    Dual<V> UL[V];
+    Dual<V, R> UL[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      double sacc = 0.0;
-      for (int j = 0; j < N; ++j) sacc += ue[v * N + j] * phi_face<D, P>(t, j, lf, ta, ik);
-      UL[v] = Dual<V>(sacc);
-      UL[v].d[v] = 1.0;
+      R sacc = R(0);
+      for (int j = 0; j < N; ++j) sacc += R(ue[v * N + j]) * phi_face<D, P, R>(t, j, lf, ta, ik);
+      UL[v] = Dual<V, R>(sacc);
+      UL[v].d[v] = R(1);
     }
-    double c[D][D], det;
+    R c[D][D], det;
     geom<D>(X, xi, c, det);
-    double nh[D], a2 = 0.0;
-    const double sg = (lf & 1) ? 1.0 : -1.0;
+    R nh[D], a2 = R(0);
+    const R sg = (lf & 1) ? R(1) : R(-1);
 #pragma unroll
     for (int a = 0; a < D; ++a) { nh[a] = sg * c[lf >> 1][a]; a2 += nh[a] * nh[a]; }
-    const double area = sqrt(a2);
+    const R area = dsqrt(a2);
 #pragma unroll
     for (int a = 0; a < D; ++a) nh[a] /= area;
-    Dual<V> F[V];
+    Dual<V, R> F[V];
     const int nb = nbr[(size_t)e * NF + lf];
     if (nb >= 0) {
       const int code = ncode[(size_t)e * NF + lf];
@@ -638,23 +641,23 @@ __global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ u
       int ta2[D - 1 > 0 ? D - 1 : 1], jk[D - 1 > 0 ? D - 1 : 1];
       face_axes<D>(lf2, ta2);
       nb_face_index<D, Q>(code, ik, jk);
-      double UR[V];
+      R UR[V];
       const double* un = ut + (size_t)nb * V * N;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        double sacc = 0.0;
-        for (int j = 0; j < N; ++j) sacc += un[v * N + j] * phi_face<D, P>(t, j, lf2, ta2, jk);
+        R sacc = R(0);
+        for (int j = 0; j < N; ++j) sacc += R(un[v * N + j]) * phi_face<D, P, R>(t, j, lf2, ta2, jk);
         UR[v] = sacc;
       }
       rusanov<D>(UL, UR, nh, F, gas.g);
     } else {
-      Dual<V> UG[V];
+      Dual<V, R> UG[V];
       if (nb == NB_WALL) ghost_wall<D>(UL, nh, UG);
       else ghost_far<D>(UL, nh, UG, gas.Uinf, gas.g);
       rusanov<D>(UL, UG, nh, F, gas.g);
     }
-    const double wa = wk * area;
-    double* o = out + QV * D * V * V + fi * V * V;
+    const R wa = wk * area;
+    R* o = out + QV * D * V * V + fi * V * V;
 #pragma unroll
     for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -693,23 +696,26 @@ __device__ __forceinline__ double readlane_d(double x, int lane) {
   const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float readlane_d(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
 
-template <int D, int P>
-__global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ BC, const double* __restrict__ Gpk,
-                                                    int NT, const double* __restrict__ dtau, double* __restrict__ out,
+template <int D, int P, class R>
+__global__ __launch_bounds__(256) void k_jaclu_wave(const R* __restrict__ BC, const double* __restrict__ Gpk,
+                                                    int NT, const double* __restrict__ dtau, R* __restrict__ out,
                                                     int* __restrict__ perm, int* __restrict__ fail, int ne,
-                                                    Tab<D, P> tab) {
+                                                    Tab<D, P, R> tab) {
   using C = Cfg<D, P>;
   constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, n = C::NB;
   static_assert(n <= 64, "one row per lane");
   constexpr int W = 4;  // elements (wavefronts) per block
   constexpr int PER = (QV * D + NF * QF) * V * V;
-  __shared__ Tab<D, P> t;
-  __shared__ double s_phv[QV * N];        // phi_j at volume points
-  __shared__ double s_dph[QV * D * N];    // d_r phi_i at volume points
-  __shared__ double s_phf[NF * QF * N];   // phi_j at face points
-  __shared__ double s_BC[W][PER];
-  __shared__ __align__(16) double s_row[W][64];  // pivot row broadcast
+  __shared__ Tab<D, P, R> t;
+  __shared__ R s_phv[QV * N];        // phi_j at volume points
+  __shared__ R s_dph[QV * D * N];    // d_r phi_i at volume points
+  __shared__ R s_phf[NF * QF * N];   // phi_j at face points
+  __shared__ R s_BC[W][PER];
+  __shared__ __align__(16) R s_row[W][64];  // pivot row broadcast
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int e = blockIdx.x * W + wv;
   const bool live = e < ne;
@@ -721,9 +727,9 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ B
     int iq[D], r0 = q;
 #pragma unroll
     for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
-    s_phv[it] = phi_vol<D, P>(t, j, iq);
+    s_phv[it] = phi_vol<D, P, R>(t, j, iq);
 #pragma unroll
-    for (int r = 0; r < D; ++r) s_dph[(q * D + r) * N + j] = dphi_vol<D, P>(t, j, iq, r);
+    for (int r = 0; r < D; ++r) s_dph[(q * D + r) * N + j] = dphi_vol<D, P, R>(t, j, iq, r);
   }
   for (int it = threadIdx.x; it < NF * QF * N; it += blockDim.x) {
     const int lf = it / (QF * N), k = (it / N) % QF, j = it % N;
@@ -731,30 +737,30 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ B
     face_axes<D>(lf, ta);
 #pragma unroll
     for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
-    s_phf[it] = phi_face<D, P>(t, j, lf, ta, ik);
+    s_phf[it] = phi_face<D, P, R>(t, j, lf, ta, ik);
   }
   __syncthreads();
   if (!live) return;  // no block barrier below
-  const double* sB = s_BC[wv];
-  const double* sC = s_BC[wv] + QV * D * V * V;
+  const R* sB = s_BC[wv];
+  const R* sC = s_BC[wv] + QV * D * V * V;
   // contraction into the lane's row r = (v, i)
   const int rr = lane < n ? lane : 0;
   const int v = rr / N, i = rr % N;
-  double acc[n];
+  R acc[n];
 #pragma unroll
-  for (int c = 0; c < n; ++c) acc[c] = 0.0;
+  for (int c = 0; c < n; ++c) acc[c] = R(0);
 #pragma unroll 1
   for (int q = 0; q < QV; ++q) {
 #pragma unroll
     for (int r = 0; r < D; ++r) {
-      const double a = s_dph[(q * D + r) * N + i];
-      const double* B = &sB[((q * D + r) * V + v) * V];
-      double bw[V];
+      const R a = s_dph[(q * D + r) * N + i];
+      const R* B = &sB[((q * D + r) * V + v) * V];
+      R bw[V];
 #pragma unroll
       for (int w = 0; w < V; ++w) bw[w] = a * B[w];
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        const double ph = s_phv[q * N + j];
+        const R ph = s_phv[q * N + j];
 #pragma unroll
         for (int w = 0; w < V; ++w) acc[w * N + j] += bw[w] * ph;
       }
@@ -762,40 +768,40 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ B
   }
 #pragma unroll 1
   for (int fk = 0; fk < NF * QF; ++fk) {
-    const double a = s_phf[fk * N + i];
-    const double* Cm = &sC[(fk * V + v) * V];
-    double cw[V];
+    const R a = s_phf[fk * N + i];
+    const R* Cm = &sC[(fk * V + v) * V];
+    R cw[V];
 #pragma unroll
     for (int w = 0; w < V; ++w) cw[w] = a * Cm[w];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const double ph = s_phf[fk * N + j];
+      const R ph = s_phf[fk * N + j];
 #pragma unroll
       for (int w = 0; w < V; ++w) acc[w * N + j] -= cw[w] * ph;
     }
   }
   {
-    const double idt = 1.0 / dtau[e];
+    const R idt = R(1.0 / dtau[e]);
     const double* G = Gpk + (size_t)e * NT;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const double gij = (i >= j) ? G[i * (i + 1) / 2 + j] : G[j * (j + 1) / 2 + i];
+      const R gij = R((i >= j) ? G[i * (i + 1) / 2 + j] : G[j * (j + 1) / 2 + i]);
 #pragma unroll
-      for (int w = 0; w < V; ++w) acc[w * N + j] = ((w == v) ? gij * idt : 0.0) - acc[w * N + j];
+      for (int w = 0; w < V; ++w) acc[w * N + j] = ((w == v) ? gij * idt : R(0)) - acc[w * N + j];
     }
   }
   // LU with partial pivoting, rows in registers.  The pivot lane writes its
   // (final) U row to LDS once; every lane reads it back with 128-bit
   // broadcast loads.  Lanes already used as pivots get a zero multiplier, so
   // the update below leaves their rows unchanged without a branch.
-  double* srow = s_row[wv];
+  R* srow = s_row[wv];
   int mystep = (lane < n) ? -1 : n;
 #pragma unroll
   for (int k = 0; k < n; ++k) {
     // key: |a| as float with its 6 low mantissa bits replaced by 63 - lane
     // (largest |a|, ties to the lowest lane); 0 for lanes already used
     unsigned key = 0u;
-    if (mystep < 0) key = (__float_as_uint((float)fabs(acc[k])) & ~63u) | (unsigned)(63 - lane);
+    if (mystep < 0) key = (__float_as_uint((float)dabs(acc[k])) & ~63u) | (unsigned)(63 - lane);
     const unsigned kmax = wave_max_u32(key);
     const int pl = __builtin_amdgcn_readfirstlane(63 - (int)(kmax & 63u));
     // the winner must be a row not yet used as a pivot
@@ -808,9 +814,9 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ B
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const double piv = srow[k];
-    if (lane == 0 && !(fabs(piv) > 0.0)) atomicOr(fail, 1);
-    const double l = (mystep < 0) ? acc[k] * (1.0 / piv) : 0.0;
+    const R piv = srow[k];
+    if (lane == 0 && !(dabs(piv) > R(0))) atomicOr(fail, 1);
+    const R l = (mystep < 0) ? acc[k] * (R(1) / piv) : R(0);
     if (mystep < 0) acc[k] = l;
 #pragma unroll
     for (int j = k + 1; j < n; ++j) acc[j] = fma(-l, srow[j], acc[j]);
@@ -818,7 +824,7 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ B
     __builtin_amdgcn_wave_barrier();
   }
   if (lane < n) {
-    double* o = out + (size_t)e * n * n;
+    R* o = out + (size_t)e * n * n;
 #pragma unroll
     for (int j = 0; j < n; ++j) o[(size_t)j * n + mystep] = acc[j];
     perm[(size_t)e * n + mystep] = lane;
@@ -831,36 +837,36 @@ __global__ __launch_bounds__(256) void k_jaclu_wave(const double* __restrict__ B
 // one wavefront per element, lane l owning rows l, l+64, ...; forward and
 // back substitution on the column-major LU factors.
 // ---------------------------------------------------------------------------
-template <int NR>
-__global__ __launch_bounds__(256) void k_prk_stage(const double* __restrict__ Fm, const int* __restrict__ perm,
+template <int NR, class R>
+__global__ __launch_bounds__(256) void k_prk_stage(const R* __restrict__ Fm, const int* __restrict__ perm,
                                                    const double* __restrict__ rt, const double* __restrict__ ft,
                                                    const double* __restrict__ un, double* __restrict__ ut, double beta,
                                                    int n, int ne) {
   const int lane = threadIdx.x & 63;
   const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (e >= ne) return;
-  const double* F = Fm + (size_t)e * n * n;
+  const R* F = Fm + (size_t)e * n * n;
   const double* r = rt + (size_t)e * n;
   const double* f = ft ? ft + (size_t)e * n : nullptr;
   const int* pm = perm + (size_t)e * n;
-  double b[NR];
+  R b[NR];
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
     const int i = lane + 64 * s;
-    b[s] = 0.0;
+    b[s] = R(0);
     if (i < n) {
       const int o = pm[i];
-      b[s] = r[o] + (f ? f[o] : 0.0);
+      b[s] = R(r[o] + (f ? f[o] : 0.0));
     }
   }
   // L y = b (unit diagonal)
   for (int j = 0; j < n; ++j) {
     const int sj = j >> 6;
-    double bj = b[0];
+    R bj = b[0];
 #pragma unroll
     for (int s = 1; s < NR; ++s) if (sj == s) bj = b[s];
-    const double xj = __shfl(bj, j & 63, 64);
-    const double* col = F + (size_t)j * n;
+    const R xj = __shfl(bj, j & 63, 64);
+    const R* col = F + (size_t)j * n;
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
       const int i = lane + 64 * s;
@@ -870,11 +876,11 @@ __global__ __launch_bounds__(256) void k_prk_stage(const double* __restrict__ Fm
   // U x = y
   for (int j = n - 1; j >= 0; --j) {
     const int sj = j >> 6;
-    double bj = b[0];
+    R bj = b[0];
 #pragma unroll
     for (int s = 1; s < NR; ++s) if (sj == s) bj = b[s];
-    const double* col = F + (size_t)j * n;
-    const double xj = __shfl(bj, j & 63, 64) / col[j];
+    const R* col = F + (size_t)j * n;
+    const R xj = __shfl(bj, j & 63, 64) / col[j];
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
       const int i = lane + 64 * s;
@@ -885,7 +891,7 @@ __global__ __launch_bounds__(256) void k_prk_stage(const double* __restrict__ Fm
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
     const int i = lane + 64 * s;
-    if (i < n) ut[(size_t)e * n + i] = un[(size_t)e * n + i] + beta * b[s];
+    if (i < n) ut[(size_t)e * n + i] = un[(size_t)e * n + i] + beta * double(b[s]);
   }
 }
 
@@ -894,33 +900,33 @@ __global__ __launch_bounds__(256) void k_prk_stage(const double* __restrict__ Fm
 // and all NB loads are independent and in flight together), then runs the
 // forward and back substitution in registers, broadcasting x_j with readlane
 // at a constant lane.  Same arithmetic as k_prk_stage.
-template <int NB>
-__global__ __launch_bounds__(256) void k_prk_stage_t(const double* __restrict__ Fm, const int* __restrict__ perm,
+template <int NB, class R>
+__global__ __launch_bounds__(256) void k_prk_stage_t(const R* __restrict__ Fm, const int* __restrict__ perm,
                                                      const double* __restrict__ rt, const double* __restrict__ un,
                                                      double* __restrict__ ut, double beta, int ne) {
   static_assert(NB <= 64, "one row per lane");
   const int lane = threadIdx.x & 63;
   const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (e >= ne) return;
-  const double* F = Fm + (size_t)e * NB * NB;
+  const R* F = Fm + (size_t)e * NB * NB;
   const int i = lane < NB ? lane : NB - 1;
-  double row[NB];
+  R row[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) row[j] = F[(size_t)j * NB + i];
-  double b = rt[(size_t)e * NB + perm[(size_t)e * NB + i]];
+  R b = R(rt[(size_t)e * NB + perm[(size_t)e * NB + i]]);
   // L y = b (unit diagonal): rows below j subtract L(i, j) y_j
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const double xj = readlane_d(b, j);
-    b = fma(-((lane > j) ? row[j] : 0.0), xj, b);
+    const R xj = readlane_d(b, j);
+    b = fma(-((lane > j) ? row[j] : R(0)), xj, b);
   }
   // U x = y
 #pragma unroll
   for (int j = NB - 1; j >= 0; --j) {
-    const double xj = readlane_d(b, j) / readlane_d(row[j], j);
-    b = (lane == j) ? xj : fma(-((lane < j) ? row[j] : 0.0), xj, b);
+    const R xj = readlane_d(b, j) / readlane_d(row[j], j);
+    b = (lane == j) ? xj : fma(-((lane < j) ? row[j] : R(0)), xj, b);
   }
-  if (lane < NB) ut[(size_t)e * NB + lane] = un[(size_t)e * NB + lane] + beta * b;
+  if (lane < NB) ut[(size_t)e * NB + lane] = un[(size_t)e * NB + lane] + beta * double(b);
 }
 
 // ---------------------------------------------------------------------------
@@ -1775,6 +1781,12 @@ __global__ void k_nbr_export(const int* __restrict__ nbr, int* __restrict__ out,
   if (i < n) out[i] = nbr[i] >= 0 ? nbr[i] : -1;
 }
 
+// out = a - b (the defect of the FP32 residual against the FP64 one)
+__global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, size_t n) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = a[i];
@@ -1824,68 +1836,79 @@ __global__ __launch_bounds__(128) void k_jac_to_psi(double* __restrict__ Dm, con
 // ===========================================================================
 namespace {
 
-template <int D, int P>
+template <int D, int P, class R>
 constexpr int res_tile() {
   using C = Cfg<D, P>;
-  constexpr int per = (C::V * C::N + C::QV * C::V * D + C::NF * C::QF * C::V + C::NC * D) * 8;
+  constexpr int per = (C::V * C::N + C::QV * C::V * D + C::NF * C::QF * C::V + C::NC * D) * (int)sizeof(R);
   constexpr int eb = 48 * 1024 / per;
   return eb < 1 ? 1 : (eb > 32 ? 32 : eb);
 }
 
-template <int D, int P>
-void fill_tab(Tab<D, P>& t, const TabData& td) {
-  for (int i = 0; i < P + 2; ++i) { t.x[i] = td.x[i]; t.w[i] = td.w[i]; }
+template <int D, int P, class R>
+void fill_tab(Tab<D, P, R>& t, const TabData& td) {
+  for (int i = 0; i < P + 2; ++i) { t.x[i] = R(td.x[i]); t.w[i] = R(td.w[i]); }
   for (int a = 0; a <= P; ++a) {
-    for (int i = 0; i < P + 2; ++i) { t.L[a][i] = td.L[a][i]; t.dL[a][i] = td.dL[a][i]; }
-    t.Lb[a][0] = td.Lb[a][0];
-    t.Lb[a][1] = td.Lb[a][1];
+    for (int i = 0; i < P + 2; ++i) { t.L[a][i] = R(td.L[a][i]); t.dL[a][i] = R(td.dL[a][i]); }
+    t.Lb[a][0] = R(td.Lb[a][0]);
+    t.Lb[a][1] = R(td.Lb[a][1]);
   }
   for (int k = 0; k < Cfg<D, P>::N; ++k)
     for (int r = 0; r < 3; ++r) t.m[k][r] = (int8_t)td.m[k][r];
 }
 
-template <int D, int P>
+template <class R>
+GasT<R> gas_as(const Gas& g) {
+  GasT<R> o;
+  o.g = R(g.g);
+  for (int v = 0; v < 5; ++v) o.Uinf[v] = R(g.Uinf[v]);
+  return o;
+}
+
+template <int D, int P, class R>
 hipError_t residual_t(const DevMesh& M, const TabData& td, const double* ut, const double* fadd, double* rt,
                       hipStream_t st) {
-  Tab<D, P> t;
+  Tab<D, P, R> t;
   fill_tab(t, td);
-  constexpr int EB = res_tile<D, P>();
+  constexpr int EB = res_tile<D, P, R>();
   const int grid = (M.ne + EB - 1) / EB;
-  hipLaunchKernelGGL((k_residual<D, P, EB>), dim3(grid), dim3(256), 0, st, ut, fadd, rt, M.xv, M.nbr, M.ncode, M.ne,
-                     t, M.gas);
+  hipLaunchKernelGGL((k_residual<D, P, EB, R>), dim3(grid), dim3(256), 0, st, ut, fadd, rt, M.xv, M.nbr, M.ncode,
+                     M.ne, t, gas_as<R>(M.gas));
   return hipGetLastError();
 }
 
-template <int D, int P>
-hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, const double* dtau, double* out,
+template <int D, int P, class R>
+hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, const double* dtau, void* outv,
                       int* perm, int* fail, bool factor, hipStream_t st) {
-  Tab<D, P> t;
+  Tab<D, P, R> t;
   fill_tab(t, td);
-  const size_t lds = (size_t)jac_lds_doubles<D, P>() * 8;
+  R* out = static_cast<R*>(outv);
+  const GasT<R> gas = gas_as<R>(M.gas);
+  const size_t lds = (size_t)jac_lds_values<D, P>() * sizeof(R);
   if constexpr (Cfg<D, P>::NB <= 64) {
     if (factor && M.bc) {
       using C = Cfg<D, P>;
       constexpr int NPT = C::QV + C::NF * C::QF;
       const int items = M.ne * NPT;
-      hipLaunchKernelGGL((k_jac_points<D, P>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.nbr, M.ncode,
-                         M.bc, M.ne, t, M.gas);
-      hipLaunchKernelGGL((k_jaclu_wave<D, P>), dim3((M.ne + 3) / 4), dim3(256), 0, st, M.bc, M.Gpk, M.NT, dtau, out,
-                         perm, fail, M.ne, t);
+      R* bc = static_cast<R*>(M.bc);
+      hipLaunchKernelGGL((k_jac_points<D, P, R>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.nbr,
+                         M.ncode, bc, M.ne, t, gas);
+      hipLaunchKernelGGL((k_jaclu_wave<D, P, R>), dim3((M.ne + 3) / 4), dim3(256), 0, st, bc, M.Gpk, M.NT, dtau,
+                         out, perm, fail, M.ne, t);
       return hipGetLastError();
     }
   }
   if (factor) {
-    auto kf = k_jacobian<D, P, true>;
+    auto kf = k_jacobian<D, P, true, R>;
     hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
-                       fail, M.ne, t, M.gas);
+                       fail, M.ne, t, gas);
   } else {
-    auto kf = k_jacobian<D, P, false>;
+    auto kf = k_jacobian<D, P, false, R>;
     hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
-                       fail, M.ne, t, M.gas);
+                       fail, M.ne, t, gas);
   }
   return hipGetLastError();
 }
@@ -1933,11 +1956,18 @@ hipError_t jac_to_psi_t(const DevMesh& M, double* Dm, hipStream_t st) {
   }
 
 hipError_t launch_residual(const DevMesh& M, const TabData& td, int p, const double* ut, const double* fadd,
-                           double* rt, hipStream_t st) {
-#define CALL_RES(DD, PP) residual_t<DD, PP>(M, td, ut, fadd, rt, st)
-  if (M.d == 2) { EG_DISPATCH_P(2, p, CALL_RES) }
-  else { EG_DISPATCH_P(3, p, CALL_RES) }
+                           double* rt, int prec, hipStream_t st) {
+  if (prec == PREC_FP32) {
+#define CALL_RES(DD, PP) residual_t<DD, PP, float>(M, td, ut, fadd, rt, st)
+    if (M.d == 2) { EG_DISPATCH_P(2, p, CALL_RES) }
+    else { EG_DISPATCH_P(3, p, CALL_RES) }
 #undef CALL_RES
+  } else {
+#define CALL_RES(DD, PP) residual_t<DD, PP, double>(M, td, ut, fadd, rt, st)
+    if (M.d == 2) { EG_DISPATCH_P(2, p, CALL_RES) }
+    else { EG_DISPATCH_P(3, p, CALL_RES) }
+#undef CALL_RES
+  }
   return hipErrorInvalidValue;
 }
 
@@ -1954,10 +1984,10 @@ bool jacobian_supported(int d, int p) {
   return p <= 2;
 }
 
-hipError_t launch_jacobian(const DevMesh& M, const TabData& td, int p, const double* ut, const double* dtau,
-                           double* out, int* perm, int* fail, bool factor, hipStream_t st) {
-  if (!jacobian_supported(M.d, p)) return hipErrorInvalidValue;
-#define CALL_JAC(DD, PP) jacobian_t<DD, (PP < 1 ? 1 : PP)>(M, td, ut, dtau, out, perm, fail, factor, st)
+template <class R>
+static hipError_t launch_jacobian_r(const DevMesh& M, const TabData& td, int p, const double* ut, const double* dtau,
+                                   void* out, int* perm, int* fail, bool factor, hipStream_t st) {
+#define CALL_JAC(DD, PP) jacobian_t<DD, PP, R>(M, td, ut, dtau, out, perm, fail, factor, st)
   if (M.d == 2) {
     switch (p) {
       case 1: return CALL_JAC(2, 1);
@@ -1977,24 +2007,39 @@ hipError_t launch_jacobian(const DevMesh& M, const TabData& td, int p, const dou
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_prk_stage(const DevMesh& M, int n, const double* F, const int* perm, const double* rt,
-                            const double* ft, const double* un, double* ut, double beta, hipStream_t st) {
+hipError_t launch_jacobian(const DevMesh& M, const TabData& td, int p, const double* ut, const double* dtau,
+                           void* out, int* perm, int* fail, bool factor, int prec, hipStream_t st) {
+  if (!jacobian_supported(M.d, p)) return hipErrorInvalidValue;
+  if (prec == PREC_FP32) return launch_jacobian_r<float>(M, td, p, ut, dtau, out, perm, fail, factor, st);
+  return launch_jacobian_r<double>(M, td, p, ut, dtau, out, perm, fail, factor, st);
+}
+
+template <class R>
+static hipError_t launch_prk_stage_r(const DevMesh& M, int n, const R* F, const int* perm, const double* rt,
+                                     const double* ft, const double* un, double* ut, double beta, hipStream_t st) {
   const int grid = (M.ne + 3) / 4;
   if (!ft) {
     switch (n) {
-      case 16: hipLaunchKernelGGL((k_prk_stage_t<16>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
-      case 36: hipLaunchKernelGGL((k_prk_stage_t<36>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
-      case 64: hipLaunchKernelGGL((k_prk_stage_t<64>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
-      case 40: hipLaunchKernelGGL((k_prk_stage_t<40>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
+      case 16: hipLaunchKernelGGL((k_prk_stage_t<16, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
+      case 36: hipLaunchKernelGGL((k_prk_stage_t<36, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
+      case 64: hipLaunchKernelGGL((k_prk_stage_t<64, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
+      case 40: hipLaunchKernelGGL((k_prk_stage_t<40, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
       default: break;
     }
   }
-  if (n <= 64) hipLaunchKernelGGL((k_prk_stage<1>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
-  else if (n <= 128) hipLaunchKernelGGL((k_prk_stage<2>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
-  else if (n <= 192) hipLaunchKernelGGL((k_prk_stage<3>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
-  else if (n <= 320) hipLaunchKernelGGL((k_prk_stage<5>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
+  if (n <= 64) hipLaunchKernelGGL((k_prk_stage<1, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
+  else if (n <= 128) hipLaunchKernelGGL((k_prk_stage<2, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
+  else if (n <= 192) hipLaunchKernelGGL((k_prk_stage<3, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
+  else if (n <= 320) hipLaunchKernelGGL((k_prk_stage<5, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
   else return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+hipError_t launch_prk_stage(const DevMesh& M, int n, const void* F, const int* perm, const double* rt,
+                            const double* ft, const double* un, double* ut, double beta, int prec, hipStream_t st) {
+  if (prec == PREC_FP32)
+    return launch_prk_stage_r<float>(M, n, static_cast<const float*>(F), perm, rt, ft, un, ut, beta, st);
+  return launch_prk_stage_r<double>(M, n, static_cast<const double*>(F), perm, rt, ft, un, ut, beta, st);
 }
 
 hipError_t launch_basis(const DevMesh& M, int N, const double* x, double* y, int mode, hipStream_t st) {
@@ -2175,6 +2220,12 @@ hipError_t launch_exp1_update(const DevMesh& M, const double* Vb, const double* 
 hipError_t launch_nbr_export(const DevMesh& M, int* out, hipStream_t st) {
   const int n = M.ne * M.NF;
   hipLaunchKernelGGL(k_nbr_export, dim3((n + 255) / 256), dim3(256), 0, st, M.nbr, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub(const double* a, const double* b, double* out, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sub, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, out, n);
   return hipGetLastError();
 }
 

@@ -23,10 +23,14 @@ struct DevMesh {
   double* hE = nullptr;    // [E] 2 d |E| / |dE|
   double* g2x = nullptr;   // 2-point Gauss rule (p = 0 faces)
   double* g2w = nullptr;
-  double* bc = nullptr;    // pointwise flux-Jacobian scratch of the block assembly
+  void* bc = nullptr;      // pointwise flux-Jacobian scratch of the block assembly (FP64 or FP32)
 };
 
-// doubles per element of the pointwise flux-Jacobian scratch at order p (0 if
+// arithmetic precision of a smoother kernel
+constexpr int PREC_FP64 = 0;
+constexpr int PREC_FP32 = 1;
+
+// values per element of the pointwise flux-Jacobian scratch at order p (0 if
 // the order uses the single-kernel assembly)
 size_t jac_points_per_elem(int d, int p);
 
@@ -38,12 +42,13 @@ struct TabData {
 };
 
 hipError_t launch_residual(const DevMesh& M, const TabData& td, int p, const double* ut, const double* fadd,
-                           double* rt, hipStream_t st);
+                           double* rt, int prec, hipStream_t st);
 bool jacobian_supported(int d, int p);
 hipError_t launch_jacobian(const DevMesh& M, const TabData& td, int p, const double* ut, const double* dtau,
-                           double* out, int* perm, int* fail, bool factor, hipStream_t st);
-hipError_t launch_prk_stage(const DevMesh& M, int n, const double* F, const int* perm, const double* rt,
-                            const double* ft, const double* un, double* ut, double beta, hipStream_t st);
+                           void* out, int* perm, int* fail, bool factor, int prec, hipStream_t st);
+hipError_t launch_prk_stage(const DevMesh& M, int n, const void* F, const int* perm, const double* rt,
+                            const double* ft, const double* un, double* ut, double beta, int prec, hipStream_t st);
+hipError_t launch_sub(const double* a, const double* b, double* out, size_t n, hipStream_t st);
 hipError_t launch_basis(const DevMesh& M, int N, const double* x, double* y, int mode, hipStream_t st);
 hipError_t launch_restrict(const DevMesh& M, int p, const double* ut, double* uc, double* uc0, hipStream_t st);
 hipError_t launch_fas(int N, int Nc, int rows, const double* rhat, double* rc, double* fc, hipStream_t st);

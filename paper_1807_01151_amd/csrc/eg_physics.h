@@ -3,103 +3,110 @@
 // Section 3, eq. (euler) with a non-rotating frame; Section 3.3 boundary
 // fluxes F~(U_L, U_ghost(U_L))).
 //
-// Everything is templated on the scalar type S: double for residuals, or the
-// forward-mode dual number Dual<M> below, which carries M tangent components
-// and so returns exact flux and ghost Jacobians (the paper evaluates these
-// Jacobians by automatic differentiation).  Branches decide on the value.
+// Everything is templated on the scalar type S: a real type R (double, or
+// float in the FP32 smoother), or the forward-mode dual number Dual<M, R>
+// below, which carries M tangent components and so returns exact flux and
+// ghost Jacobians (the paper evaluates these Jacobians by automatic
+// differentiation).  Constants and geometry are of the real type R of S.
+// Branches decide on the value.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace eg {
 
-template <int M>
+template <int M, class R = double>
 struct Dual {
-  double v;
-  double d[M];
+  R v;
+  R d[M];
   __device__ __forceinline__ Dual() {}
-  __device__ __forceinline__ Dual(double c) : v(c) {
+  __device__ __forceinline__ Dual(R c) : v(c) {
 #pragma unroll
-    for (int k = 0; k < M; ++k) d[k] = 0.0;
+    for (int k = 0; k < M; ++k) d[k] = R(0);
   }
 };
 
-__device__ __forceinline__ double val(double x) { return x; }
-template <int M> __device__ __forceinline__ double val(const Dual<M>& x) { return x.v; }
+// real type underlying a scalar type
+template <class S> struct RealOf { using type = S; };
+template <int M, class R> struct RealOf<Dual<M, R>> { using type = R; };
+template <class S> using real_t = typename RealOf<S>::type;
 
-template <int M> __device__ __forceinline__ Dual<M> operator+(const Dual<M>& a, const Dual<M>& b) {
-  Dual<M> r; r.v = a.v + b.v;
+__device__ __forceinline__ double val(double x) { return x; }
+__device__ __forceinline__ float val(float x) { return x; }
+template <int M, class R> __device__ __forceinline__ R val(const Dual<M, R>& x) { return x.v; }
+
+#define EG_DUAL template <int M, class R> __device__ __forceinline__
+EG_DUAL Dual<M, R> operator+(const Dual<M, R>& a, const Dual<M, R>& b) {
+  Dual<M, R> r; r.v = a.v + b.v;
 #pragma unroll
   for (int k = 0; k < M; ++k) r.d[k] = a.d[k] + b.d[k];
   return r;
 }
-template <int M> __device__ __forceinline__ Dual<M> operator-(const Dual<M>& a, const Dual<M>& b) {
-  Dual<M> r; r.v = a.v - b.v;
+EG_DUAL Dual<M, R> operator-(const Dual<M, R>& a, const Dual<M, R>& b) {
+  Dual<M, R> r; r.v = a.v - b.v;
 #pragma unroll
   for (int k = 0; k < M; ++k) r.d[k] = a.d[k] - b.d[k];
   return r;
 }
-template <int M> __device__ __forceinline__ Dual<M> operator-(const Dual<M>& a) {
-  Dual<M> r; r.v = -a.v;
+EG_DUAL Dual<M, R> operator-(const Dual<M, R>& a) {
+  Dual<M, R> r; r.v = -a.v;
 #pragma unroll
   for (int k = 0; k < M; ++k) r.d[k] = -a.d[k];
   return r;
 }
-template <int M> __device__ __forceinline__ Dual<M> operator*(const Dual<M>& a, const Dual<M>& b) {
-  Dual<M> r; r.v = a.v * b.v;
+EG_DUAL Dual<M, R> operator*(const Dual<M, R>& a, const Dual<M, R>& b) {
+  Dual<M, R> r; r.v = a.v * b.v;
 #pragma unroll
   for (int k = 0; k < M; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
   return r;
 }
-template <int M> __device__ __forceinline__ Dual<M> operator/(const Dual<M>& a, const Dual<M>& b) {
-  Dual<M> r; double ib = 1.0 / b.v; r.v = a.v * ib;
+EG_DUAL Dual<M, R> operator/(const Dual<M, R>& a, const Dual<M, R>& b) {
+  Dual<M, R> r; R ib = R(1) / b.v; r.v = a.v * ib;
 #pragma unroll
   for (int k = 0; k < M; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
   return r;
 }
-template <int M> __device__ __forceinline__ Dual<M> operator+(const Dual<M>& a, double b) {
-  Dual<M> r = a; r.v += b; return r;
-}
-template <int M> __device__ __forceinline__ Dual<M> operator+(double b, const Dual<M>& a) { return a + b; }
-template <int M> __device__ __forceinline__ Dual<M> operator-(const Dual<M>& a, double b) {
-  Dual<M> r = a; r.v -= b; return r;
-}
-template <int M> __device__ __forceinline__ Dual<M> operator-(double b, const Dual<M>& a) {
-  Dual<M> r; r.v = b - a.v;
+EG_DUAL Dual<M, R> operator+(const Dual<M, R>& a, R b) { Dual<M, R> r = a; r.v += b; return r; }
+EG_DUAL Dual<M, R> operator+(R b, const Dual<M, R>& a) { return a + b; }
+EG_DUAL Dual<M, R> operator-(const Dual<M, R>& a, R b) { Dual<M, R> r = a; r.v -= b; return r; }
+EG_DUAL Dual<M, R> operator-(R b, const Dual<M, R>& a) {
+  Dual<M, R> r; r.v = b - a.v;
 #pragma unroll
   for (int k = 0; k < M; ++k) r.d[k] = -a.d[k];
   return r;
 }
-template <int M> __device__ __forceinline__ Dual<M> operator*(const Dual<M>& a, double b) {
-  Dual<M> r; r.v = a.v * b;
+EG_DUAL Dual<M, R> operator*(const Dual<M, R>& a, R b) {
+  Dual<M, R> r; r.v = a.v * b;
 #pragma unroll
   for (int k = 0; k < M; ++k) r.d[k] = a.d[k] * b;
   return r;
 }
-template <int M> __device__ __forceinline__ Dual<M> operator*(double b, const Dual<M>& a) { return a * b; }
-template <int M> __device__ __forceinline__ Dual<M> operator/(const Dual<M>& a, double b) {
-  Dual<M> r; double ib = 1.0 / b; r.v = a.v * ib;
+EG_DUAL Dual<M, R> operator*(R b, const Dual<M, R>& a) { return a * b; }
+EG_DUAL Dual<M, R> operator/(const Dual<M, R>& a, R b) {
+  Dual<M, R> r; R ib = R(1) / b; r.v = a.v * ib;
 #pragma unroll
   for (int k = 0; k < M; ++k) r.d[k] = a.d[k] * ib;
   return r;
 }
-template <int M> __device__ __forceinline__ Dual<M> operator/(double a, const Dual<M>& b) {
-  Dual<M> r; double ib = 1.0 / b.v; r.v = a * ib; double s = -r.v * ib;
+EG_DUAL Dual<M, R> operator/(R a, const Dual<M, R>& b) {
+  Dual<M, R> r; R ib = R(1) / b.v; r.v = a * ib; R s = -r.v * ib;
 #pragma unroll
   for (int k = 0; k < M; ++k) r.d[k] = s * b.d[k];
   return r;
 }
 
 __device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
-template <int M> __device__ __forceinline__ Dual<M> dsqrt(const Dual<M>& a) {
-  Dual<M> r; r.v = sqrt(a.v); double s = 0.5 / r.v;
+__device__ __forceinline__ float dsqrt(float x) { return sqrtf(x); }
+EG_DUAL Dual<M, R> dsqrt(const Dual<M, R>& a) {
+  Dual<M, R> r; r.v = dsqrt(a.v); R s = R(0.5) / r.v;
 #pragma unroll
   for (int k = 0; k < M; ++k) r.d[k] = s * a.d[k];
   return r;
 }
 __device__ __forceinline__ double dpow(double x, double c) { return pow(x, c); }
-template <int M> __device__ __forceinline__ Dual<M> dpow(const Dual<M>& a, double c) {
-  Dual<M> r; r.v = pow(a.v, c); double s = c * r.v / a.v;
+__device__ __forceinline__ float dpow(float x, float c) { return powf(x, c); }
+EG_DUAL Dual<M, R> dpow(const Dual<M, R>& a, R c) {
+  Dual<M, R> r; r.v = dpow(a.v, c); R s = c * r.v / a.v;
 #pragma unroll
   for (int k = 0; k < M; ++k) r.d[k] = s * a.d[k];
   return r;
@@ -109,34 +116,39 @@ template <int M> __device__ __forceinline__ Dual<M> dpow(const Dual<M>& a, doubl
 // for |x| <= 1e-13, the average of both slopes at a relative tie <= 1e-12 of
 // max), so a face's Jacobian does not depend on which side evaluates it.
 __device__ __forceinline__ double dabs(double x) { return fabs(x); }
-template <int M> __device__ __forceinline__ Dual<M> dabs(const Dual<M>& x) {
-  if (fabs(x.v) <= 1e-13) return Dual<M>(fabs(x.v));
-  return x.v < 0.0 ? -x : x;
+__device__ __forceinline__ float dabs(float x) { return fabsf(x); }
+EG_DUAL Dual<M, R> dabs(const Dual<M, R>& x) {
+  if (dabs(x.v) <= R(1e-13)) return Dual<M, R>(dabs(x.v));
+  return x.v < R(0) ? -x : x;
 }
 __device__ __forceinline__ double dmax(double a, double b) { return a >= b ? a : b; }
-template <int M> __device__ __forceinline__ Dual<M> dmax(const Dual<M>& a, const Dual<M>& b) {
-  if (fabs(a.v - b.v) <= 1e-12 * fmax(fabs(a.v), fabs(b.v))) {
-    Dual<M> r;
+__device__ __forceinline__ float dmax(float a, float b) { return a >= b ? a : b; }
+EG_DUAL Dual<M, R> dmax(const Dual<M, R>& a, const Dual<M, R>& b) {
+  if (dabs(a.v - b.v) <= R(1e-12) * dmax(dabs(a.v), dabs(b.v))) {
+    Dual<M, R> r;
     r.v = a.v >= b.v ? a.v : b.v;
 #pragma unroll
-    for (int k = 0; k < M; ++k) r.d[k] = 0.5 * (a.d[k] + b.d[k]);
+    for (int k = 0; k < M; ++k) r.d[k] = R(0.5) * (a.d[k] + b.d[k]);
     return r;
   }
   return a.v >= b.v ? a : b;
 }
-
+#undef EG_DUAL
 
 // Pressure of the perfect gas, p = (g - 1)(rho E - |rho v|^2 / (2 rho)).
-template <int D, class S> __device__ __forceinline__ S pressure(const S* U, double g) {
+template <int D, class S> __device__ __forceinline__ S pressure(const S* U, real_t<S> g) {
+  using R = real_t<S>;
   S m2 = U[1] * U[1];
 #pragma unroll
   for (int a = 1; a < D; ++a) m2 = m2 + U[1 + a] * U[1 + a];
-  return (g - 1.0) * (U[D + 1] - 0.5 * m2 / U[0]);
+  return (g - R(1)) * (U[D + 1] - R(0.5) * m2 / U[0]);
 }
 
 // F(U) . n for an arbitrary (not necessarily unit) vector n.
-template <int D, class S> __device__ __forceinline__ void flux_n(const S* U, const double* n, S* F, double g) {
-  S irho = 1.0 / U[0];
+template <int D, class S>
+__device__ __forceinline__ void flux_n(const S* U, const real_t<S>* n, S* F, real_t<S> g) {
+  using R = real_t<S>;
+  S irho = R(1) / U[0];
   S un = U[1] * n[0];
 #pragma unroll
   for (int a = 1; a < D; ++a) un = un + U[1 + a] * n[a];
@@ -151,7 +163,8 @@ template <int D, class S> __device__ __forceinline__ void flux_n(const S* U, con
 // Rusanov flux: 1/2 (F(UL) + F(UR)) . n - 1/2 lambda (UR - UL),
 // lambda = max over the two sides of |v . n| + c, n a unit vector.
 template <int D, class SL, class SR, class S>
-__device__ __forceinline__ void rusanov(const SL* UL, const SR* UR, const double* nh, S* F, double g) {
+__device__ __forceinline__ void rusanov(const SL* UL, const SR* UR, const real_t<S>* nh, S* F, real_t<S> g) {
+  using R = real_t<S>;
   S ul[D + 2], ur[D + 2];
 #pragma unroll
   for (int v = 0; v < D + 2; ++v) { ul[v] = S(UL[v]); ur[v] = S(UR[v]); }
@@ -165,17 +178,18 @@ __device__ __forceinline__ void rusanov(const SL* UL, const SR* UR, const double
   S cr = dsqrt(g * pressure<D>(ur, g) / ur[0]);
   S lam = dmax(S(dabs(S(unl / ul[0])) + cl), S(dabs(S(unr / ur[0])) + cr));
 #pragma unroll
-  for (int v = 0; v < D + 2; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * (ur[v] - ul[v]);
+  for (int v = 0; v < D + 2; ++v) F[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * lam * (ur[v] - ul[v]);
 }
 
 // Slip wall: mirror the momentum about the face, rho v_g = rho v - 2 (rho v . n) n.
-template <int D, class S> __device__ __forceinline__ void ghost_wall(const S* U, const double* nh, S* G) {
+template <int D, class S> __device__ __forceinline__ void ghost_wall(const S* U, const real_t<S>* nh, S* G) {
+  using R = real_t<S>;
   S mn = U[1] * nh[0];
 #pragma unroll
   for (int a = 1; a < D; ++a) mn = mn + U[1 + a] * nh[a];
   G[0] = U[0];
 #pragma unroll
-  for (int a = 0; a < D; ++a) G[1 + a] = U[1 + a] - 2.0 * (mn * nh[a]);
+  for (int a = 0; a < D; ++a) G[1 + a] = U[1 + a] - R(2) * (mn * nh[a]);
   G[D + 1] = U[D + 1];
 }
 
@@ -184,8 +198,10 @@ template <int D, class S> __device__ __forceinline__ void ghost_wall(const S* U,
 // free stream; on outflow (boundary normal velocity > 0) tangential velocity
 // and entropy p / rho^g come from inside, else from the free stream.
 template <int D, class S>
-__device__ __forceinline__ void ghost_far(const S* U, const double* nh, S* G, const double* Uinf, double g) {
-  S irho = 1.0 / U[0];
+__device__ __forceinline__ void ghost_far(const S* U, const real_t<S>* nh, S* G, const real_t<S>* Uinf,
+                                          real_t<S> g) {
+  using R = real_t<S>;
+  S irho = R(1) / U[0];
   S vi[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) vi[a] = U[1 + a] * irho;
@@ -194,31 +210,31 @@ __device__ __forceinline__ void ghost_far(const S* U, const double* nh, S* G, co
   for (int a = 1; a < D; ++a) vni = vni + vi[a] * nh[a];
   S pin = pressure<D>(U, g);
   S ci = dsqrt(g * pin * irho);
-  double rinf = Uinf[0];
-  double vinf[D];
-  double vninf = 0.0;
+  R rinf = Uinf[0];
+  R vinf[D];
+  R vninf = R(0);
 #pragma unroll
   for (int a = 0; a < D; ++a) { vinf[a] = Uinf[1 + a] / rinf; vninf += vinf[a] * nh[a]; }
-  double pinf = pressure<D>(Uinf, g);
-  double cinf = sqrt(g * pinf / rinf);
-  S rp = vni + (2.0 / (g - 1.0)) * ci;
-  double rm = vninf - (2.0 / (g - 1.0)) * cinf;
-  S vnb = 0.5 * (rp + rm);
-  S cb = (0.25 * (g - 1.0)) * (rp - rm);
+  R pinf = pressure<D>(Uinf, g);
+  R cinf = dsqrt(g * pinf / rinf);
+  S rp = vni + (R(2) / (g - R(1))) * ci;
+  R rm = vninf - (R(2) / (g - R(1))) * cinf;
+  S vnb = R(0.5) * (rp + rm);
+  S cb = (R(0.25) * (g - R(1))) * (rp - rm);
   S vt[D];
   S ent;
-  if (val(vnb) > 0.0) {
+  if (val(vnb) > R(0)) {
 #pragma unroll
     for (int a = 0; a < D; ++a) vt[a] = vi[a] - vni * nh[a];
     ent = pin / dpow(U[0], g);
   } else {
 #pragma unroll
     for (int a = 0; a < D; ++a) vt[a] = S(vinf[a] - vninf * nh[a]);
-    ent = S(pinf / pow(rinf, g));
+    ent = S(pinf / dpow(rinf, g));
   }
-  S rb = dpow(S(cb * cb / (g * ent)), 1.0 / (g - 1.0));
+  S rb = dpow(S(cb * cb / (g * ent)), R(1) / (g - R(1)));
   S pb = rb * cb * cb / g;
-  S ke = S(0.0);
+  S ke = S(R(0));
   G[0] = rb;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -226,7 +242,7 @@ __device__ __forceinline__ void ghost_far(const S* U, const double* nh, S* G, co
     G[1 + a] = rb * vb;
     ke = ke + vb * vb;
   }
-  G[D + 1] = pb / (g - 1.0) + 0.5 * rb * ke;
+  G[D + 1] = pb / (g - R(1)) + R(0.5) * rb * ke;
 }
 
 }  // namespace eg
