@@ -17,5 +17,6 @@ from .meshes import (  # noqa: F401
     cubed_sphere_shell,
     box,
     radial_map,
+    wall_bumps,
 )
-from .draws import batch_draws, seeded_array  # noqa: F401
+from .draws import batch_draws, bump_centers, seeded_array  # noqa: F401

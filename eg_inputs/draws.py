@@ -30,3 +30,14 @@ def batch_draws(n_solves: int = 64, seed: int = 1807):
         out.append({"n_theta": nt, "n_r": nt // 2, "p": p, "mach": ma,
                     "alpha_deg": al})
     return out
+
+
+def bump_centers(dim: int, n: int, seed: int = 1807) -> np.ndarray:
+    """n seeded unit vectors (bump centres on the body): angles ~ U[0, 2 pi)
+    in 2D; directions uniform on the sphere in 3D (normalised Gaussians)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if dim == 2:
+        th = rng.uniform(0.0, 2.0 * np.pi, size=n)
+        return np.stack([np.cos(th), np.sin(th)], axis=1)
+    v = rng.standard_normal((n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)

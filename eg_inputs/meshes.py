@@ -218,3 +218,29 @@ def box(dim: int, n: int, lo: float = 0.0, hi: float = 1.0, tag: int = TAG_EXACT
                 tg[e, 2 * r + 1] = tag
         e += 1
     return Mesh(dim, pts, ev, tg, f"box{dim}d{n}")
+
+
+def wall_bumps(mesh: Mesh, amps, centers, sigma: float, r_in: float = 0.5,
+               r_out: float = 20.0) -> Mesh:
+    """Radial Gaussian bumps on the body of an O-grid or cubed-sphere shell.
+
+    Vertex x at radius r moves radially by
+        delta(x) = sum_k amps[k] exp(-theta_k(x)^2 / (2 sigma^2)) (r_out - r) / (r_out - r_in),
+    theta_k the angle between x and the unit vector centers[k]: full
+    amplitude on the wall, none on the far-field boundary, so the topology and
+    the boundary tags are unchanged and small amplitudes keep every element
+    positively oriented.
+    """
+    amps = np.asarray(amps, dtype=np.float64)
+    centers = np.asarray(centers, dtype=np.float64).reshape(len(amps), mesh.dim)
+    x = np.array(mesh.xyz, dtype=np.float64)
+    r = np.sqrt(np.sum(x * x, axis=1))
+    xh = x / r[:, None]
+    w = np.clip((r_out - r) / (r_out - r_in), 0.0, 1.0)
+    delta = np.zeros_like(r)
+    for a, c in zip(amps, centers):
+        c = c / np.sqrt(float(c @ c))
+        th = np.arccos(np.clip(xh @ c, -1.0, 1.0))
+        delta += a * np.exp(-th * th / (2.0 * sigma * sigma))
+    xyz = xh * (r + delta * w)[:, None]
+    return Mesh(mesh.dim, xyz, mesh.elem_vert.copy(), mesh.bface_tag.copy(), mesh.name + "+bumps")

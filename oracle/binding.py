@@ -3,6 +3,7 @@
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -63,6 +64,8 @@ def lib():
         L.orc_rnorm.argtypes = [C.c_void_p, C.c_int, _d]
         L.orc_cfl_ramp.restype = C.c_double
         L.orc_cfl_ramp.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int]
+        L.orc_drag.argtypes = [C.c_void_p, C.c_int, _d, _d, C.c_double, _d]
+        L.orc_drag.restype = C.c_double
         L.orc_prk.restype = C.c_int
         L.orc_prk.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, _d, _d]
         L.orc_exp1.restype = C.c_int
@@ -166,6 +169,8 @@ class Oracle:
         self.ne = m.n_elem
         self.pmax = pmax
         self.gamma = gamma
+        self.mach = mach
+        self.alpha_deg, self.beta_deg = alpha_deg, beta_deg
         err = C.create_string_buffer(256)
         h = lib().orc_create(m.dim, m.n_vert, _p(m.xyz), m.n_elem, _p(m.elem_vert), _p(m.bface_tag), pmax,
                              gamma, mach, alpha_deg, beta_deg, err, 256)
@@ -253,6 +258,52 @@ class Oracle:
         u = np.ascontiguousarray(u, dtype=np.float64)
         lib().orc_timestep(self._h, p, u.shape[2], cfl, _p(u), _p(dt))
         return dt
+
+    def drag(self, p: int, u: np.ndarray, direction=None, sref: float = 1.0, grad: bool = False):
+        """Pressure drag coefficient C_D of the level-p state u on the slip
+        walls along ``direction`` (default: the free-stream direction), and
+        optionally dC_D/du."""
+        if direction is None:
+            direction = self.freestream_direction()
+        dv = np.zeros(3)
+        dv[: self.dim] = np.asarray(direction, dtype=np.float64)[: self.dim]
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        g = np.zeros_like(u) if grad else None
+        c = lib().orc_drag(self._h, p, _p(u), _p(dv), float(sref), _p(g) if grad else None)
+        return (c, g) if grad else c
+
+    def jacobian_sparse(self, p: int, u: np.ndarray):
+        """dR_p/du as a scipy CSR matrix assembled from the exact element
+        blocks (Section 3.3, eqs. (jac1), (jac2)); unknowns ordered as the
+        flattened [E][V][N_p] vector."""
+        import scipy.sparse as sp
+        D, Off = self.jacobian_blocks(p, u, offdiag=True)
+        n = self.V * self.N(p)
+        nb = self.neighbours()
+        I, J = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+        rows, cols, vals = [], [], []
+        for e in range(self.ne):
+            rows.append(e * n + I.ravel()); cols.append(e * n + J.ravel()); vals.append(D[e].ravel())
+            for lf in range(2 * self.dim):
+                if nb[e, lf] >= 0:
+                    rows.append(e * n + I.ravel()); cols.append(nb[e, lf] * n + J.ravel())
+                    vals.append(Off[e, lf].ravel())
+        K = self.ne * n
+        return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(K, K))
+
+    def adjoint(self, p: int, u: np.ndarray, g: np.ndarray) -> np.ndarray:
+        """The discrete adjoint: lambda with (dR_p/du)^T lambda + g = 0, by a
+        sparse direct solve (for g = dJ/du, dJ/dtheta = dJ/dtheta|_u +
+        lambda . dR/dtheta|_u)."""
+        import scipy.sparse.linalg as spla
+        Jm = self.jacobian_sparse(p, u)
+        lam = spla.spsolve(Jm.T.tocsc(), -np.ascontiguousarray(g).ravel())
+        return lam.reshape(u.shape)
+
+    def freestream_direction(self) -> np.ndarray:
+        a, b = math.radians(self.alpha_deg), math.radians(self.beta_deg)
+        v = np.array([math.cos(a) * math.cos(b), math.sin(a) * math.cos(b), math.sin(b)])
+        return v[: self.dim]
 
     def rnorm(self, p: int, r: np.ndarray) -> float:
         return lib().orc_rnorm(self._h, p, _p(np.ascontiguousarray(r)))

@@ -42,6 +42,7 @@
 namespace {
 
 using cd = std::complex<double>;
+using cd_t = std::complex<double>;
 
 // ---------------------------------------------------------------------------
 // Scalar helpers usable with double and with complex<double> (complex-step
@@ -887,6 +888,58 @@ double rnorm(const Oracle& O, int Np, const double* r) {
   return std::sqrt(s) / O.omega;
 }
 
+// ---------------------------------------------------------------------------
+// Pressure drag coefficient, the functional of the adjoint study: the force
+// of the fluid on the slip walls projected on the direction dir,
+//   C_D = -(1 / (q_inf S_ref)) sum_{wall faces} int p(U) n^ . dir dsigma,
+// n^ the element's outward unit normal (it points into the body, so -p n^ is
+// the pressure force on the body), q_inf = rho_inf |v_inf|^2 / 2 (rho_inf =
+// 1, |v_inf| = Ma), U the element's trace, with the face quadrature of the
+// residual at level p.  grad (nullable, [E][V][N_p]) receives dC_D/du: the
+// pressure's derivative by complex step at each quadrature point times
+// psi_i(x_k) and the same weight.
+// ---------------------------------------------------------------------------
+double drag(const Oracle& O, int p, const double* u, const double* dir, double sref, double* grad) {
+  const int d = O.d, V = O.V, N = nmodes(d, p), Q = p + 2;
+  std::vector<double> xg, wg;
+  gauss_legendre(Q, xg, wg);
+  int nq = 1;
+  for (int k = 0; k < d; ++k) nq *= Q;
+  const int nqf = nq / Q;
+  const double scale = -1.0 / (0.5 * O.mach * O.mach * sref);
+  if (grad) for (size_t i = 0; i < (size_t)O.ne * V * N; ++i) grad[i] = 0.0;
+  double cd = 0.0;
+  for (const Face& F : O.faces) {
+    if (F.tag != 1) continue;
+    double psi[128];
+    for (int k = 0; k < nqf; ++k) {
+      double xiL[MAXD], xiR[MAXD], w;
+      face_point(O, F, Q, xg, wg, k, xiL, xiR, w);
+      double x[MAXD], det, c[MAXD][MAXD];
+      elem_basis(O, F.eL, N, xiL, psi, nullptr, x, &det, c);
+      double sg = (F.fL % 2) ? 1.0 : -1.0, nh[MAXD], area2 = 0.0;
+      for (int a = 0; a < d; ++a) { nh[a] = sg * c[F.fL / 2][a]; area2 += nh[a] * nh[a]; }
+      double area = std::sqrt(area2), nd = 0.0;
+      for (int a = 0; a < d; ++a) nd += nh[a] / area * dir[a];
+      double U[MAXV];
+      eval_state(O, F.eL, N, u, psi, U);
+      const double wt = scale * w * area * nd;
+      cd += wt * pressure(d, O.gam, U);
+      if (grad) {
+        double dp[MAXV];
+        for (int v = 0; v < V; ++v) {
+          cd_t Uc[MAXV];
+          for (int q = 0; q < V; ++q) Uc[q] = cd_t(U[q], q == v ? 1e-30 : 0.0);
+          dp[v] = pressure(d, O.gam, Uc).imag() / 1e-30;
+        }
+        for (int v = 0; v < V; ++v)
+          for (int i = 0; i < N; ++i) grad[((size_t)F.eL * V + v) * N + i] += wt * dp[v] * psi[i];
+      }
+    }
+  }
+  return cd;
+}
+
 // Dense LU with partial pivoting (row-major), and solve.
 bool lu_factor(int n, double* A, int* piv) {
   for (int k = 0; k < n; ++k) {
@@ -1319,6 +1372,10 @@ double orc_rnorm(void* h, int p, const double* r) {
 }
 
 double orc_cfl_ramp(double cfl_max, double rn, double rref, int n, int pmax) { return cfl_ramp(cfl_max, rn, rref, n, pmax); }
+
+double orc_drag(void* h, int p, const double* u, const double* dir, double sref, double* grad) {
+  return drag(*static_cast<Oracle*>(h), p, u, dir, sref, grad);
+}
 
 int orc_prk(void* h, int p, int s, double cfl, double* u, const double* f) {
   return prk(*static_cast<Oracle*>(h), p, s, cfl, u, f, nullptr) ? 0 : 1;
