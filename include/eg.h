@@ -174,6 +174,40 @@ eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_
 eg_status eg_solve_resume(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
                           int* n_cycles_host);
 
+/* ---- Adjoint drag sensitivity (discrete adjoint of the steady problem) ----
+ * The paper solves R(u) = 0 (Section 2.1, eq. (starteq) at steady state);
+ * these entries give d(functional)/d(parameter) for a converged u by the
+ * discrete adjoint: (dR/du)^T lambda + dJ/du = 0, then
+ * dJ/dtheta = dJ/dtheta|_u + lambda . dR/dtheta|_u. */
+
+/* Pressure drag coefficient of the level-p_max state u_dev on the slip walls:
+ *   C_D = -(1 / (q_inf S_ref)) sum_{wall faces} int p(U) n . dir dsigma,
+ * n the element's outward unit normal (into the body), q_inf = |v_inf|^2 / 2
+ * (rho_inf = 1), U the element's trace, the residual's face quadrature.
+ * dir_host: host [d] direction (normally the free stream's); sref > 0.
+ * cd_host receives C_D; grad_dev (may be NULL) dC_D/du (level p_max, psi
+ * coordinates).  Synchronises. */
+eg_status eg_drag(eg_handle* h, const double* u_dev, const double* dir_host, double sref, double* cd_host,
+                  double* grad_dev);
+
+/* Transposed Jacobian of the residual (Section 3.3, eqs. (jac1), (jac2),
+ * transposed): out_dev = (dR_p/du)(u_dev)^T w_dev at level p >= 1, matrix
+ * free from the pointwise flux Jacobians at u_dev.  All level-p vectors.
+ * Asynchronous. */
+eg_status eg_adjoint_apply(eg_handle* h, int p, const double* u_dev, const double* w_dev, double* out_dev);
+
+/* Adjoint solve (dR/du)(u_dev)^T lambda + g_dev = 0 at level p_max by the
+ * transposed linear V-cycle: transposed PRK smoother (Section 2.3 with
+ * P^T, blocks frozen at u_dev with dtau at cfl_max), truncation / padding
+ * transfers, and on p = 0 one EXP1 step (Sections 2.1-2.2) of the linear
+ * adjoint problem with the transposed p = 0 operator.  lam_dev: initial
+ * guess in, solution out.  Stops when the 2-norm of the adjoint residual
+ * has dropped by drop_tol; hist_host[0..*n_cycles_host] as for
+ * eg_solve_steady.  Element blocks up to 64 x 64 (else EG_ERR_UNSUPPORTED).
+ * Runs in FP64 on every handle.  Synchronises. */
+eg_status eg_adjoint_solve(eg_handle* h, const double* u_dev, const double* g_dev, double* lam_dev, double drop_tol,
+                           int max_cycles, double* hist_host, int* n_cycles_host);
+
 /* Profiling aid: HIP-event timing of the solver's own kernel launches, by
  * kernel class and level, recorded on the handle's stream while enabled.
  * eg_profile(h, 1) clears the records and starts recording, eg_profile(h, 0)

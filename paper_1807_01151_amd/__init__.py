@@ -13,3 +13,4 @@ from .binding import (  # noqa: F401
     library_path,
     EXPORTED_SYMBOLS,
 )
+from . import autograd  # noqa: F401

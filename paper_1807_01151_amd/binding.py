@@ -14,6 +14,7 @@ EXPORTED_SYMBOLS = (
     "eg_init_mesh", "eg_free", "eg_last_error", "eg_sizes", "eg_set_freestream", "eg_residual",
     "eg_timestep", "eg_element_jacobian", "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm",
     "eg_vcycle", "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read",
+    "eg_drag", "eg_adjoint_apply", "eg_adjoint_solve",
 )
 
 KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
@@ -75,6 +76,9 @@ def lib():
         L.eg_solve_resume.argtypes = [vp, vp, d, i, pd, C.POINTER(i)]
         L.eg_profile.argtypes = [vp, i]
         L.eg_profile_read.argtypes = [vp, i, i, pd, C.POINTER(i)]
+        L.eg_drag.argtypes = [vp, vp, pd, d, pd, vp]
+        L.eg_adjoint_apply.argtypes = [vp, i, vp, vp, vp]
+        L.eg_adjoint_solve.argtypes = [vp, vp, vp, vp, d, i, pd, C.POINTER(i)]
         for name in ("eg_sizes", "eg_set_freestream", "eg_residual", "eg_timestep", "eg_element_jacobian",
                      "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm", "eg_vcycle",
                      "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read"):
@@ -123,6 +127,7 @@ class Solver:
             self._h = None
             raise EgError(st, msg)
         self.dim, self.p_max, self.n_elem, self.V = m.dim, p_max, m.n_elem, m.dim + 2
+        self.mach, self.alpha_deg, self.beta_deg = mach, alpha_deg, beta_deg
         self.krylov_m = krylov_m
         self._np = np
 
@@ -221,3 +226,50 @@ class Solver:
         if st not in (0, 5, 6) or (raise_on_fail and st != 0):
             self._chk(st)
         return hist[: nc.value + 1], st
+
+
+def _freestream_direction(dim, alpha_deg, beta_deg):
+    import math
+    a, b = math.radians(alpha_deg), math.radians(beta_deg)
+    v = (math.cos(a) * math.cos(b), math.sin(a) * math.cos(b), math.sin(b))
+    return v[:dim]
+
+
+def _solver_drag(self, u, direction=None, sref: float = 1.0, grad: bool = False):
+    """Pressure drag coefficient C_D of the level-p_max state u (and
+    optionally dC_D/du on the device)."""
+    if direction is None:
+        direction = _freestream_direction(self.dim, self.alpha_deg, self.beta_deg)
+    dv = (C.c_double * 3)(*([float(x) for x in direction] + [0.0] * (3 - len(direction))))
+    cd = C.c_double(0.0)
+    g = self.empty(self.p_max) if grad else None
+    self._chk(lib().eg_drag(self._h, _ptr(u), dv, float(sref), C.byref(cd), _ptr(g)))
+    return (cd.value, g) if grad else cd.value
+
+
+def _solver_adjoint_apply(self, p: int, u, w, out=None):
+    """(dR_p/du)(u)^T w."""
+    o = self.empty(p) if out is None else out
+    self._chk(lib().eg_adjoint_apply(self._h, p, _ptr(u), _ptr(w), _ptr(o)))
+    return o
+
+
+def _solver_adjoint_solve(self, u, g, lam=None, drop_tol: float = 1e-10, max_cycles: int = 500,
+                          raise_on_fail: bool = True):
+    """lambda with (dR/du)(u)^T lambda + g = 0 (adjoint V-cycles); returns
+    (lambda, history of the adjoint residual 2-norm, status)."""
+    import torch
+    np = self._np
+    lam = torch.zeros_like(g) if lam is None else lam
+    hist = np.zeros(max_cycles + 1)
+    nc = C.c_int(0)
+    st = lib().eg_adjoint_solve(self._h, _ptr(u), _ptr(g), _ptr(lam), drop_tol, max_cycles,
+                                hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nc))
+    if st not in (0, 5) or (raise_on_fail and st != 0):
+        self._chk(st)
+    return lam, hist[: nc.value + 1], st
+
+
+Solver.drag = _solver_drag
+Solver.adjoint_apply = _solver_adjoint_apply
+Solver.adjoint_solve = _solver_adjoint_solve

@@ -74,6 +74,24 @@ struct eg_handle {
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
   std::vector<ProfRec> recs;
+  double mach = 0.3;
+  // drag functional
+  double* dpart = nullptr;  // [E] per-element contributions
+  double* spart = nullptr;  // partial sums of the deterministic reductions
+  double* sout = nullptr;
+  // adjoint workspaces (allocated by the first adjoint call), phi coordinates
+  bool adj_ready = false;
+  double* adj_bc[5] = {};    // pointwise flux Jacobians at the linearisation state, per level p >= 1
+  double* adj_F[5] = {};     // FP64 LU factors of the PRK blocks at that state
+  int* adj_perm[5] = {};
+  double* adj_u[5] = {};     // linearisation state restricted to each level
+  double* lam[5] = {};       // adjoint iterate (p_max) and coarse corrections
+  double* lamn[5] = {};
+  double* gq[5] = {};        // adjoint forcing per level
+  double* rho[5] = {};       // adjoint residual per level
+  double* AdT = nullptr;     // transposed p = 0 operator
+  double* AoT = nullptr;
+  double* zero0 = nullptr;   // K0 zeros
 };
 
 namespace {
@@ -552,6 +570,116 @@ eg_status entry_norm(eg_handle* h, double* rn) {
   return EG_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of the steady problem (drag sensitivity): (dR/du)^T lambda + g = 0
+// solved by the transposed linear V-cycle: on p >= 1 the PRK smoother with the
+// transposed blocks Pt^T = G/dtau - Dt^T (same LU factors, transposed
+// solves), the adjoint residual restricted by truncation and the correction
+// prolongated by padding (the transposes of the forward transfers), and on
+// p = 0 one EXP1 step of the linear adjoint problem with the transposed
+// p = 0 operator.  The blocks, dtau (at CFL_max) and the pointwise flux
+// Jacobians are evaluated once at the linearisation state.
+// ---------------------------------------------------------------------------
+eg_status adj_alloc(eg_handle* h) {
+  if (h->adj_ready) return EG_OK;
+  const DevMesh& M = h->M;
+  const int d = M.d, ne = M.ne, V = M.V;
+  for (int p = 0; p <= h->pmax; ++p) {
+    const size_t K = (size_t)ne * V * nmodes_of(d, p);
+    ECHK(dalloc(h, &h->adj_u[p], K));
+    ECHK(dalloc(h, &h->lam[p], K));
+    ECHK(dalloc(h, &h->lamn[p], K));
+    ECHK(dalloc(h, &h->gq[p], K));
+    ECHK(dalloc(h, &h->rho[p], K));
+    if (p >= 1) {
+      const size_t n = (size_t)V * nmodes_of(d, p);
+      ECHK(dalloc(h, &h->adj_bc[p], (size_t)ne * eg::jac_points_size(d, p)));
+      ECHK(dalloc(h, &h->adj_F[p], (size_t)ne * n * n));
+      ECHK(dalloc(h, &h->adj_perm[p], (size_t)ne * n));
+    }
+  }
+  ECHK(dalloc(h, &h->AdT, (size_t)ne * V * V));
+  ECHK(dalloc(h, &h->AoT, (size_t)ne * M.NF * V * V));
+  ECHK(dalloc(h, &h->zero0, (size_t)ne * V));
+  HIPCHK(h, eg::launch_fill0(h->zero0, (size_t)ne * V, h->st));
+  h->adj_ready = true;
+  return EG_OK;
+}
+
+eg_status adj_supported(eg_handle* h) {
+  for (int p = 1; p <= h->pmax; ++p)
+    if (!eg::prk_tr_supported(NB(h, p)))
+      return fail(h, EG_ERR_UNSUPPORTED, "adjoint: element blocks larger than 64 are not supported");
+  return EG_OK;
+}
+
+// Linearisation state u (psi coordinates, level p_max) on every level, the
+// pointwise Jacobians and FP64 block factors for p >= 1, the transposed p = 0
+// operator.
+eg_status adj_setup(eg_handle* h, const double* u_dev) {
+  const DevMesh& M = h->M;
+  const int pm = h->pmax;
+  HIPCHK(h, eg::launch_basis(M, nmodes_of(M.d, pm), u_dev, h->adj_u[pm], 0, h->st));
+  for (int p = pm; p >= 1; --p) HIPCHK(h, eg::launch_restrict(M, p, h->adj_u[p], h->adj_u[p - 1], h->uc0[p - 1], h->st));
+  for (int p = 1; p <= pm; ++p) {
+    DevMesh M2 = M;
+    M2.bc = h->adj_bc[p];
+    HIPCHK(h, eg::launch_timestep(M, p, nmodes_of(M.d, p), h->cfl_max, 1.0, h->adj_u[p], h->dtau, h->st));
+    HIPCHK(h, eg::launch_jac_points(M, h->tabs[p], p, h->adj_u[p], h->adj_bc[p], h->st));
+    HIPCHK(h, eg::launch_jacobian(M2, h->tabs[p], p, h->adj_u[p], h->dtau, h->adj_F[p], h->adj_perm[p], h->dfail,
+                                  true, eg::PREC_FP64, h->st));
+  }
+  HIPCHK(h, eg::launch_p0_setup(M, h->adj_u[0], nullptr, pm, h->cfl_max, 1, h->u0, h->b0, h->Ad, h->Ao, h->dt0, h->st));
+  HIPCHK(h, eg::launch_p0_transpose(M, h->Ad, h->Ao, h->dt0, h->AdT, h->AoT, h->st));
+  return EG_OK;
+}
+
+// One transposed V-cycle below level p on lam[p] with forcing gq[p].
+eg_status adj_vc(eg_handle* h, int p) {
+  const DevMesh& M = h->M;
+  if (p == 0) {
+    HIPCHK(h, eg::launch_adj_p0_rhs(M, h->gq[0], h->dt0, h->b0, h->st));
+    HIPCHK(h, eg::launch_arnoldi(M, h->m, h->nblk_arn, h->AdT, h->AoT, h->b0, h->Vb, h->H, h->part1, h->part2,
+                                 h->info, h->arn_st, h->arn_wn0, h->arn_W, h->H2, h->st));
+    HIPCHK(h, eg::launch_phi1(h->m, h->H, h->H2, h->info, h->y, h->dfail, h->st));
+    HIPCHK(h, eg::launch_exp1_update(M, h->Vb, h->y, h->info, h->zero0, h->lam[0], h->st));
+    return EG_OK;
+  }
+  const int n = NB(h, p), N = nmodes_of(M.d, p), Nc = nmodes_of(M.d, p - 1), rows = M.ne * M.V;
+  const size_t K = (size_t)M.ne * n;
+  HIPCHK(h, eg::launch_copy(h->lam[p], h->lamn[p], K, h->st));
+  for (int k = 1; k <= h->s; ++k) {
+    HIPCHK(h, eg::launch_adj_residual(M, h->tabs[p], p, h->lam[p], h->gq[p], h->adj_bc[p], h->rho[p], h->st));
+    const double beta = 1.0 / (h->s - k + 1.0);
+    HIPCHK(h, eg::launch_prk_stage_tr(M, n, h->adj_F[p], h->adj_perm[p], h->rho[p], h->lamn[p], h->lam[p], beta,
+                                      h->st));
+  }
+  HIPCHK(h, eg::launch_adj_residual(M, h->tabs[p], p, h->lam[p], h->gq[p], h->adj_bc[p], h->rho[p], h->st));
+  HIPCHK(h, eg::launch_trunc(h->rho[p], h->gq[p - 1], N, Nc, rows, h->st));
+  HIPCHK(h, eg::launch_fill0(h->lam[p - 1], (size_t)rows * Nc, h->st));
+  ECHK(adj_vc(h, p - 1));
+  HIPCHK(h, eg::launch_pad_add(h->lam[p], h->lam[p - 1], N, Nc, rows, h->st));
+  return EG_OK;
+}
+
+// ||psi-coordinate adjoint residual at p_max||_2 -> host.
+eg_status adj_norm(eg_handle* h, double* out) {
+  const DevMesh& M = h->M;
+  const int pm = h->pmax, N = nmodes_of(M.d, pm);
+  const size_t K = (size_t)M.ne * M.V * N;
+  HIPCHK(h, eg::launch_adj_residual(M, h->tabs[pm], pm, h->lam[pm], h->gq[pm], h->adj_bc[pm], h->rho[pm], h->st));
+  HIPCHK(h, eg::launch_basis(M, N, h->rho[pm], h->tmp2, 2, h->st));
+  HIPCHK(h, eg::launch_sum(h->tmp2, h->tmp2, K, h->spart, 1, h->sout, h->st));
+  HIPCHK(h, hipMemcpyAsync(h->hpin, h->sout, sizeof(double), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(h, hipMemcpyAsync(h->hpin + 1, h->dfail, sizeof(int), hipMemcpyDeviceToHost, h->st));
+  ECHK(sync_status(h));
+  *out = h->hpin[0];
+  int fl = 0;
+  std::memcpy(&fl, h->hpin + 1, sizeof(int));
+  if (fl) return fail(h, EG_ERR_DIVERGED, "singular pivot in a block factorisation or in phi_1");
+  return EG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -576,6 +704,7 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
   h->s = prm->rk_stages;
   h->m = prm->krylov_m;
   h->relr = prm->relative_ramp;
+  h->mach = prm->mach;
   h->mixed = prm->precision == EG_MIXED;
   h->cfl_max = prm->cfl_max;
   h->st = static_cast<hipStream_t>(hip_stream);
@@ -678,6 +807,9 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
   AL(h->npart, (size_t)(ne + 255) / 256 + 1);
   AL(h->nout, 1);
   AL(h->dfail, 1);
+  AL(h->dpart, ne);
+  AL(h->spart, 256);
+  AL(h->sout, 1);
 #undef AL
   {
     hipError_t e = hipHostMalloc((void**)&h->hpin, 64, hipHostMallocDefault);
@@ -905,6 +1037,72 @@ eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_
   h->sv_nmin = 1;
   h->sv_rmin = HUGE_VAL;
   return solve_loop(h, u_dev, 1, -1.0, drop_tol, max_cycles, hist_host, n_cycles_host);
+}
+
+eg_status eg_drag(eg_handle* h, const double* u_dev, const double* dir_host, double sref, double* cd_host,
+                  double* grad_dev) {
+  if (!h || !u_dev || !dir_host || !cd_host || !(sref > 0.0)) return EG_ERR_ARG;
+  if (!(h->mach > 0.0)) return fail(h, EG_ERR_ARG, "drag needs a free stream with mach > 0");
+  const DevMesh& M = h->M;
+  const int p = h->pmax, N = nmodes_of(M.d, p);
+  double dir[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < M.d; ++a) dir[a] = dir_host[a];
+  const double scale = -1.0 / (0.5 * h->mach * h->mach * sref);
+  HIPCHK(h, eg::launch_basis(M, N, u_dev, h->tmp, 0, h->st));
+  HIPCHK(h, eg::launch_drag(M, h->tabs[p], p, h->tmp, dir, scale, h->dpart, h->tmp2, h->st));
+  HIPCHK(h, eg::launch_sum(h->dpart, nullptr, (size_t)M.ne, h->spart, 0, h->sout, h->st));
+  if (grad_dev) HIPCHK(h, eg::launch_basis(M, N, h->tmp2, grad_dev, 2, h->st));
+  HIPCHK(h, hipMemcpyAsync(h->hpin, h->sout, sizeof(double), hipMemcpyDeviceToHost, h->st));
+  ECHK(sync_status(h));
+  *cd_host = h->hpin[0];
+  return EG_OK;
+}
+
+eg_status eg_adjoint_apply(eg_handle* h, int p, const double* u_dev, const double* w_dev, double* out_dev) {
+  if (!h || !u_dev || !w_dev || !out_dev) return EG_ERR_ARG;
+  if (p < 1 || p > h->pmax) return fail(h, EG_ERR_ARG, "order out of range (p >= 1)");
+  ECHK(adj_alloc(h));
+  const DevMesh& M = h->M;
+  const int N = nmodes_of(M.d, p);
+  HIPCHK(h, eg::launch_basis(M, N, u_dev, h->tmp, 0, h->st));
+  HIPCHK(h, eg::launch_basis(M, N, w_dev, h->tmp2, 0, h->st));
+  HIPCHK(h, eg::launch_jac_points(M, h->tabs[p], p, h->tmp, h->adj_bc[p], h->st));
+  HIPCHK(h, eg::launch_adj_residual(M, h->tabs[p], p, h->tmp2, nullptr, h->adj_bc[p], h->rho[p], h->st));
+  HIPCHK(h, eg::launch_basis(M, N, h->rho[p], out_dev, 2, h->st));
+  return EG_OK;
+}
+
+eg_status eg_adjoint_solve(eg_handle* h, const double* u_dev, const double* g_dev, double* lam_dev, double drop_tol,
+                           int max_cycles, double* hist_host, int* n_cycles_host) {
+  if (!h || !u_dev || !g_dev || !lam_dev || !hist_host || !n_cycles_host || max_cycles < 0) return EG_ERR_ARG;
+  if (h->pmax < 1) return fail(h, EG_ERR_UNSUPPORTED, "adjoint needs p_max >= 1");
+  ECHK(adj_supported(h));
+  ECHK(adj_alloc(h));
+  const DevMesh& M = h->M;
+  const int pm = h->pmax, N = nmodes_of(M.d, pm);
+  ECHK(adj_setup(h, u_dev));
+  HIPCHK(h, eg::launch_basis(M, N, g_dev, h->gq[pm], 3, h->st));
+  HIPCHK(h, eg::launch_basis(M, N, lam_dev, h->lam[pm], 0, h->st));
+  eg_status st = EG_OK;
+  double r1 = 0.0;
+  for (int n = 0;; ++n) {
+    double rn = 0.0;
+    st = adj_norm(h, &rn);
+    if (st != EG_OK) break;
+    hist_host[n] = rn;
+    *n_cycles_host = n;
+    if (n == 0) r1 = rn;
+    if (!std::isfinite(rn)) { st = fail(h, EG_ERR_DIVERGED, "non-finite adjoint residual"); break; }
+    if (rn <= drop_tol * r1) break;
+    if (n == max_cycles) { st = fail(h, EG_ERR_NOT_CONVERGED, "max_cycles reached"); break; }
+    st = adj_vc(h, pm);
+    if (st != EG_OK) break;
+  }
+  hipError_t e = eg::launch_basis(M, N, h->lam[pm], lam_dev, 1, h->st);
+  if (e != hipSuccess && st == EG_OK) st = hipfail(h, e, "basis");
+  hipError_t e2 = hipStreamSynchronize(h->st);
+  if (e2 != hipSuccess && st == EG_OK) st = hipfail(h, e2, "sync");
+  return st;
 }
 
 eg_status eg_solve_resume(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,

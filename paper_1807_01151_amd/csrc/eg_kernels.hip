@@ -25,6 +25,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "eg_common.h"
 #include "eg_launch.h"
 #include "eg_physics.h"
@@ -1832,6 +1834,361 @@ __global__ __launch_bounds__(128) void k_jac_to_psi(double* __restrict__ Dm, con
 }
 
 // ===========================================================================
+// Adjoint (drag sensitivity): the pressure drag functional and its gradient,
+// the transposed-Jacobian residual, the transposed PRK stage and the
+// transposed p = 0 operator of the adjoint V-cycle.
+// ===========================================================================
+
+// Pressure drag on the slip walls (the functional of the adjoint study):
+//   C_D = scale * sum_{wall faces} sum_k w_k |n dsigma| p(U(x_k)) (n^ . dir),
+// scale = -1 / (q_inf S_ref), n^ the element's outward unit normal (into the
+// body).  One thread per element: part[e] = its contribution, gt[e] = dC_D/dut
+// (phi coordinates; zero off the wall), the pressure derivative by dual
+// numbers.
+struct Dir3 {
+  double v[3];
+};
+
+template <int D, int P>
+__global__ __launch_bounds__(128) void k_drag(const double* __restrict__ ut, const double* __restrict__ xv,
+                                              const int* __restrict__ nbr, int ne, Tab<D, P> tab, Gas gas, Dir3 dir,
+                                              double scale, double* __restrict__ part, double* __restrict__ gt) {
+  using C = Cfg<D, P>;
+  constexpr int V = C::V, N = C::N, Q = C::Q, QF = C::QF, NF = C::NF, NC = C::NC;
+  __shared__ Tab<D, P> t;
+  copy_tab(t, tab);
+  __syncthreads();
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double* g = gt + (size_t)e * V * N;  // owned by this thread
+  for (int x = 0; x < V * N; ++x) g[x] = 0.0;
+  double acc = 0.0;
+  const double* ue = ut + (size_t)e * V * N;
+  for (int lf = 0; lf < NF; ++lf) {
+    if (nbr[(size_t)e * NF + lf] != NB_WALL) continue;
+    double X[NC * D];
+#pragma unroll
+    for (int a = 0; a < NC * D; ++a) X[a] = xv[(size_t)e * NC * D + a];
+    int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1];
+    face_axes<D>(lf, ta);
+    for (int k = 0; k < QF; ++k) {
+      double xi[D], wk = 1.0;
+      xi[lf >> 1] = (lf & 1) ? 1.0 : -1.0;
+      int r0 = k;
+#pragma unroll
+      for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; xi[ta[q]] = t.x[ik[q]]; wk *= t.w[ik[q]]; }
+      double c[D][D], det;
+      geom<D>(X, xi, c, det);
+      double nh[D], a2 = 0.0;
+      const double sg = (lf & 1) ? 1.0 : -1.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) { nh[a] = sg * c[lf >> 1][a]; a2 += nh[a] * nh[a]; }
+      const double area = sqrt(a2);
+      double nd = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) nd += nh[a] / area * dir.v[a];
+      Dual<V> U[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) U[v] = Dual<V>(0.0);
+      for (int j = 0; j < N; ++j) {
+        const double ph = phi_face<D, P>(t, j, lf, ta, ik);
+#pragma unroll
+        for (int v = 0; v < V; ++v) U[v].v += ue[v * N + j] * ph;
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) U[v].d[v] = 1.0;
+      const Dual<V> pr = pressure<D>(U, gas.g);
+      const double wt = scale * wk * area * nd;
+      acc += wt * pr.v;
+      for (int j = 0; j < N; ++j) {
+        const double ph = phi_face<D, P>(t, j, lf, ta, ik);
+#pragma unroll
+        for (int v = 0; v < V; ++v) g[v * N + j] += wt * pr.d[v] * ph;
+      }
+    }
+  }
+  part[e] = acc;
+}
+
+// Deterministic sum of n values: per-block partial sums, then one block adds
+// them in a fixed order.
+__global__ __launch_bounds__(256) void k_sum_partial(const double* __restrict__ x, const double* __restrict__ y, size_t n,
+                                                     double* __restrict__ part) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    a += y ? x[i] * y[i] : x[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ part, int nblk, int take_sqrt,
+                                                   double* __restrict__ out) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) a += part[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = take_sqrt ? sqrt(s[0]) : s[0];
+}
+
+// ---------------------------------------------------------------------------
+// Transposed-Jacobian residual (the adjoint residual) in phi coordinates:
+//   out = Dt^T w (+ g),  Dt = dRt/dut at the linearisation state,
+// matrix free from the pointwise flux Jacobians of k_jac_points at that
+// state (per element [QV][D][V][V] volume, [NF*QF][V][V] faces):
+//   out_{(w,j)} = sum_q phi_j(q) sum_r sum_v B_{q,r}[v][w] G_{v,r}(q)
+//               - sum_faces sum_k phi_j(x_k) sum_v C_k[v][w] (W_v(x_k) - W^nb_v(x_k)),
+// G_{v,r}(q) = sum_i w_{v,i} d_r phi_i(q) the reference gradient and W, W^nb
+// the traces of w on the element and on the neighbour (zero on boundary
+// faces).  The neighbour term is the transposed off-diagonal block: the
+// Rusanov flux is antisymmetric under exchanging the sides and flipping the
+// normal, so dF~_nb/dU_own = -dF~_own/dU_own, and the neighbour's residual
+// couples to this element through this element's own face Jacobian C_k.
+// ---------------------------------------------------------------------------
+template <int D, int P, int EB>
+__global__ __launch_bounds__(256) void k_adj_residual(const double* __restrict__ wt, const double* __restrict__ gadd,
+                                                      const double* __restrict__ BC, const int* __restrict__ nbr,
+                                                      const uint8_t* __restrict__ ncode, int ne, Tab<D, P> tab,
+                                                      double* __restrict__ out) {
+  using C = Cfg<D, P>;
+  constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF;
+  constexpr int PER = (QV * D + NF * QF) * V * V;
+  __shared__ double s_w[EB * V * N];
+  __shared__ double s_hv[EB * QV * V];
+  __shared__ double s_hf[EB * NF * QF * V];
+  __shared__ Tab<D, P> t;
+  const int tid = threadIdx.x;
+  const int e0 = blockIdx.x * EB;
+  copy_tab(t, tab);
+  {
+    const int nel = min(EB, ne - e0);
+    stage<(EB * V * N + 255) / 256>(s_w, wt + (size_t)e0 * V * N, nel * V * N, tid, 256);
+  }
+  __syncthreads();
+  for (int it = tid; it < EB * QV; it += blockDim.x) {
+    const int el = it / QV, q = it % QV;
+    const int e = e0 + el;
+    if (e >= ne) continue;
+    int iq[D];
+    {
+      int r0 = q;
+#pragma unroll
+      for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
+    }
+    double G[V][D];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int r = 0; r < D; ++r) G[v][r] = 0.0;
+    const double* sw = &s_w[el * V * N];
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        const double dp = dphi_vol<D, P>(t, i, iq, r);
+#pragma unroll
+        for (int v = 0; v < V; ++v) G[v][r] += sw[v * N + i] * dp;
+      }
+    }
+    const double* B = BC + (size_t)e * PER + (size_t)q * D * V * V;
+    double H[V];
+#pragma unroll
+    for (int w = 0; w < V; ++w) H[w] = 0.0;
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int w = 0; w < V; ++w) H[w] += B[(r * V + v) * V + w] * G[v][r];
+#pragma unroll
+    for (int w = 0; w < V; ++w) s_hv[(el * QV + q) * V + w] = H[w];
+  }
+  for (int it = tid; it < EB * NF * QF; it += blockDim.x) {
+    const int el = it / (NF * QF), lf = (it / QF) % NF, k = it % QF;
+    const int e = e0 + el;
+    if (e >= ne) continue;
+    int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1];
+    face_axes<D>(lf, ta);
+    {
+      int r0 = k;
+#pragma unroll
+      for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
+    }
+    double W[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) W[v] = 0.0;
+    const double* sw = &s_w[el * V * N];
+    for (int j = 0; j < N; ++j) {
+      const double ph = phi_face<D, P>(t, j, lf, ta, ik);
+#pragma unroll
+      for (int v = 0; v < V; ++v) W[v] += sw[v * N + j] * ph;
+    }
+    const int nb = nbr[(size_t)e * NF + lf];
+    if (nb >= 0) {
+      const int code = ncode[(size_t)e * NF + lf];
+      const int lf2 = code & 7;
+      int ta2[D - 1 > 0 ? D - 1 : 1], jk[D - 1 > 0 ? D - 1 : 1];
+      face_axes<D>(lf2, ta2);
+      nb_face_index<D, Q>(code, ik, jk);
+      const double* wn = wt + (size_t)nb * V * N;
+      for (int j = 0; j < N; ++j) {
+        const double ph = phi_face<D, P>(t, j, lf2, ta2, jk);
+#pragma unroll
+        for (int v = 0; v < V; ++v) W[v] -= wn[v * N + j] * ph;
+      }
+    }
+    const double* Cm = BC + (size_t)e * PER + (size_t)QV * D * V * V + (size_t)(lf * QF + k) * V * V;
+    double H[V];
+#pragma unroll
+    for (int w = 0; w < V; ++w) H[w] = 0.0;
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int w = 0; w < V; ++w) H[w] += Cm[v * V + w] * W[v];
+#pragma unroll
+    for (int w = 0; w < V; ++w) s_hf[((el * NF + lf) * QF + k) * V + w] = H[w];
+  }
+  __syncthreads();
+  for (int it = tid; it < EB * V * N; it += blockDim.x) {
+    const int el = it / (V * N), w = (it / N) % V, j = it % N;
+    const int e = e0 + el;
+    if (e >= ne) continue;
+    double acc = 0.0;
+    for (int q = 0; q < QV; ++q) {
+      int iq[D];
+      int r0 = q;
+#pragma unroll
+      for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
+      acc += phi_vol<D, P>(t, j, iq) * s_hv[(el * QV + q) * V + w];
+    }
+    for (int lf = 0; lf < NF; ++lf) {
+      int ta[D - 1 > 0 ? D - 1 : 1];
+      face_axes<D>(lf, ta);
+      for (int k = 0; k < QF; ++k) {
+        int ik[D - 1 > 0 ? D - 1 : 1];
+        int r0 = k;
+#pragma unroll
+        for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
+        acc -= phi_face<D, P>(t, j, lf, ta, ik) * s_hf[((el * NF + lf) * QF + k) * V + w];
+      }
+    }
+    const size_t o = (size_t)e0 * V * N + it;
+    out[o] = gadd ? acc + gadd[o] : acc;
+  }
+}
+
+// Transposed PRK stage: lam = lam_n + beta Pt^{-T} r with the LU factors of
+// Pt (Pi Pt = L U, column-major, row k = k-th pivot row): solve U^T z = r,
+// L^T y = z, x[perm[k]] = y_k.  One wavefront per element, lane l holding
+// column l of the factor (U(k, l) for k <= l, L(k, l) for k > l).
+template <int NB>
+__global__ __launch_bounds__(256) void k_prk_stage_tr(const double* __restrict__ Fm, const int* __restrict__ perm,
+                                                      const double* __restrict__ rt, const double* __restrict__ un,
+                                                      double* __restrict__ ut, double beta, int ne) {
+  static_assert(NB <= 64, "one column per lane");
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (e >= ne) return;
+  const double* F = Fm + (size_t)e * NB * NB;
+  const int l = lane < NB ? lane : NB - 1;
+  double col[NB];
+#pragma unroll
+  for (int m = 0; m < NB; ++m) col[m] = F[(size_t)l * NB + m];
+  double b = rt[(size_t)e * NB + l];
+  // U^T z = r (forward): z_k = b_k / U(k, k); lanes l > k subtract U(k, l) z_k
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const double zk = readlane_d(b, k) / readlane_d(col[k], k);
+    b = (lane == k) ? zk : fma(-((lane > k) ? col[k] : 0.0), zk, b);
+  }
+  // L^T y = z (backward, unit diagonal): lanes l < k subtract L(k, l) y_k
+#pragma unroll
+  for (int k = NB - 1; k >= 0; --k) {
+    const double yk = readlane_d(b, k);
+    b = fma(-((lane < k) ? col[k] : 0.0), yk, b);
+  }
+  if (lane < NB) {
+    const int o = perm[(size_t)e * NB + lane];
+    ut[(size_t)e * NB + o] = un[(size_t)e * NB + o] + beta * b;
+  }
+}
+
+// Transposed p = 0 operator for the adjoint EXP1: A^T-side blocks
+// (T J0^T)_{F,E} = dt_F (J0_{E,F})^T from the forward blocks Ad = T J0 (diag)
+// and Ao[E][lf2] = dt_E J0_{E,F} (lf2: the face of E that touches F).
+template <int V, int NF>
+__global__ __launch_bounds__(256) void k_p0_transpose(const double* __restrict__ Ad, const double* __restrict__ Ao,
+                                                      const double* __restrict__ dt, const int* __restrict__ nbr,
+                                                      const uint8_t* __restrict__ ncode, double* __restrict__ AdT,
+                                                      double* __restrict__ AoT, int ne) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= ne * (1 + NF)) return;
+  const int e = id / (1 + NF), slot = id % (1 + NF);
+  if (slot == 0) {
+#pragma unroll
+    for (int w = 0; w < V; ++w)
+#pragma unroll
+      for (int v = 0; v < V; ++v) AdT[(size_t)e * V * V + w * V + v] = Ad[(size_t)e * V * V + v * V + w];
+    return;
+  }
+  const int lf = slot - 1;
+  const int nb = nbr[(size_t)e * NF + lf];
+  double* o = AoT + ((size_t)e * NF + lf) * V * V;
+  if (nb < 0) {
+#pragma unroll
+    for (int x = 0; x < V * V; ++x) o[x] = 0.0;
+    return;
+  }
+  const int lf2 = ncode[(size_t)e * NF + lf] & 7;
+  const double* a = Ao + ((size_t)nb * NF + lf2) * V * V;
+  const double sc = dt[e] / dt[nb];
+#pragma unroll
+  for (int w = 0; w < V; ++w)
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[w * V + v] = sc * a[v * V + w];
+}
+
+// Adjoint p = 0 right-hand side in psi coordinates: b = dt * gt0 / L00.
+__global__ __launch_bounds__(256) void k_adj_p0_rhs(const double* __restrict__ gt0, const double* __restrict__ Lpk,
+                                                    int NT, const double* __restrict__ dt, int V, int ne,
+                                                    double* __restrict__ b) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= ne * V) return;
+  const int e = id / V;
+  b[id] = dt[e] * gt0[id] / Lpk[(size_t)e * NT];
+}
+
+// Leading-slice truncation y = Trunc(x) (N -> Nc modes per row) and the
+// padded correction x += Pad(y); zero fill.
+__global__ void k_trunc(const double* __restrict__ x, double* __restrict__ y, int N, int Nc, int rows) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= rows * Nc) return;
+  const int r = id / Nc, i = id % Nc;
+  y[id] = x[(size_t)r * N + i];
+}
+
+__global__ void k_pad_add(double* __restrict__ x, const double* __restrict__ y, int N, int Nc, int rows) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= rows * Nc) return;
+  const int r = id / Nc, i = id % Nc;
+  x[(size_t)r * N + i] += y[id];
+}
+
+__global__ void k_fill0(double* __restrict__ x, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+// ===========================================================================
 // launchers
 // ===========================================================================
 namespace {
@@ -2253,6 +2610,175 @@ hipError_t launch_jac_to_psi(const DevMesh& M, int N, double* Dm, hipStream_t st
     case 27: return jac_to_psi_t<27>(M, Dm, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+
+// ---------------------------------------------------------------------------
+// adjoint launchers
+// ---------------------------------------------------------------------------
+size_t jac_points_size(int d, int p) {
+  const int V = d + 2, Q = p + 2;
+  const int QV = (d == 2) ? Q * Q : Q * Q * Q, QF = (d == 2) ? Q : Q * Q;
+  return (size_t)(QV * d + 2 * d * QF) * V * V;
+}
+
+namespace {
+template <int D, int P>
+hipError_t jac_points_only_t(const DevMesh& M, const TabData& td, const double* ut, double* bc, hipStream_t st) {
+  Tab<D, P, double> t;
+  fill_tab(t, td);
+  using C = Cfg<D, P>;
+  constexpr int NPT = C::QV + C::NF * C::QF;
+  const int items = M.ne * NPT;
+  hipLaunchKernelGGL((k_jac_points<D, P, double>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.nbr,
+                     M.ncode, bc, M.ne, t, M.gas);
+  return hipGetLastError();
+}
+
+template <int D, int P>
+constexpr int adj_tile() {
+  using C = Cfg<D, P>;
+  constexpr int per = (C::V * C::N + C::QV * C::V + C::NF * C::QF * C::V) * 8;
+  constexpr int eb = 40 * 1024 / per;
+  return eb < 1 ? 1 : (eb > 32 ? 32 : eb);
+}
+
+template <int D, int P>
+hipError_t adj_residual_t(const DevMesh& M, const TabData& td, const double* wt, const double* gadd,
+                          const double* bc, double* out, hipStream_t st) {
+  Tab<D, P, double> t;
+  fill_tab(t, td);
+  constexpr int EB = adj_tile<D, P>();
+  const int grid = (M.ne + EB - 1) / EB;
+  hipLaunchKernelGGL((k_adj_residual<D, P, EB>), dim3(grid), dim3(256), 0, st, wt, gadd, bc, M.nbr, M.ncode, M.ne, t,
+                     out);
+  return hipGetLastError();
+}
+
+template <int D, int P>
+hipError_t drag_t(const DevMesh& M, const TabData& td, const double* ut, const double* dir, double scale,
+                  double* part, double* gt, hipStream_t st) {
+  Tab<D, P, double> t;
+  fill_tab(t, td);
+  Dir3 dv{{dir[0], dir[1], dir[2]}};
+  hipLaunchKernelGGL((k_drag<D, P>), dim3((M.ne + 127) / 128), dim3(128), 0, st, ut, M.xv, M.nbr, M.ne, t, M.gas, dv,
+                     scale, part, gt);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_jac_points(const DevMesh& M, const TabData& td, int p, const double* ut, double* bc,
+                             hipStream_t st) {
+#define CALL_JP(DD, PP) jac_points_only_t<DD, PP>(M, td, ut, bc, st)
+  if (M.d == 2) {
+    switch (p) {
+      case 1: return CALL_JP(2, 1);
+      case 2: return CALL_JP(2, 2);
+      case 3: return CALL_JP(2, 3);
+      case 4: return CALL_JP(2, 4);
+      default: break;
+    }
+  } else {
+    switch (p) {
+      case 1: return CALL_JP(3, 1);
+      case 2: return CALL_JP(3, 2);
+      default: break;
+    }
+  }
+#undef CALL_JP
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj_residual(const DevMesh& M, const TabData& td, int p, const double* wt, const double* gadd,
+                               const double* bc, double* out, hipStream_t st) {
+#define CALL_AR(DD, PP) adj_residual_t<DD, PP>(M, td, wt, gadd, bc, out, st)
+  if (M.d == 2) {
+    switch (p) {
+      case 1: return CALL_AR(2, 1);
+      case 2: return CALL_AR(2, 2);
+      case 3: return CALL_AR(2, 3);
+      case 4: return CALL_AR(2, 4);
+      default: break;
+    }
+  } else {
+    switch (p) {
+      case 1: return CALL_AR(3, 1);
+      case 2: return CALL_AR(3, 2);
+      default: break;
+    }
+  }
+#undef CALL_AR
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_drag(const DevMesh& M, const TabData& td, int p, const double* ut, const double* dir, double scale,
+                       double* part, double* gt, hipStream_t st) {
+#define CALL_DR(DD, PP) drag_t<DD, PP>(M, td, ut, dir, scale, part, gt, st)
+  if (M.d == 2) { EG_DISPATCH_P(2, p, CALL_DR) }
+  else { EG_DISPATCH_P(3, p, CALL_DR) }
+#undef CALL_DR
+  return hipErrorInvalidValue;
+}
+
+bool prk_tr_supported(int n) { return n == 16 || n == 36 || n == 64 || n == 40; }
+
+hipError_t launch_prk_stage_tr(const DevMesh& M, int n, const double* F, const int* perm, const double* rt,
+                               const double* un, double* ut, double beta, hipStream_t st) {
+  const int grid = (M.ne + 3) / 4;
+  switch (n) {
+    case 16: hipLaunchKernelGGL((k_prk_stage_tr<16>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
+    case 36: hipLaunchKernelGGL((k_prk_stage_tr<36>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
+    case 40: hipLaunchKernelGGL((k_prk_stage_tr<40>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
+    case 64: hipLaunchKernelGGL((k_prk_stage_tr<64>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_p0_transpose(const DevMesh& M, const double* Ad, const double* Ao, const double* dt, double* AdT,
+                               double* AoT, hipStream_t st) {
+  const int cnt = M.ne * (1 + M.NF);
+  if (M.d == 2)
+    hipLaunchKernelGGL((k_p0_transpose<4, 4>), dim3((cnt + 255) / 256), dim3(256), 0, st, Ad, Ao, dt, M.nbr, M.ncode,
+                       AdT, AoT, M.ne);
+  else
+    hipLaunchKernelGGL((k_p0_transpose<5, 6>), dim3((cnt + 255) / 256), dim3(256), 0, st, Ad, Ao, dt, M.nbr, M.ncode,
+                       AdT, AoT, M.ne);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_p0_rhs(const DevMesh& M, const double* gt0, const double* dt, double* b, hipStream_t st) {
+  const int cnt = M.ne * M.V;
+  hipLaunchKernelGGL(k_adj_p0_rhs, dim3((cnt + 255) / 256), dim3(256), 0, st, gt0, M.Lpk, M.NT, dt, M.V, M.ne, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_trunc(const double* x, double* y, int N, int Nc, int rows, hipStream_t st) {
+  const int cnt = rows * Nc;
+  hipLaunchKernelGGL(k_trunc, dim3((cnt + 255) / 256), dim3(256), 0, st, x, y, N, Nc, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_add(double* x, const double* y, int N, int Nc, int rows, hipStream_t st) {
+  const int cnt = rows * Nc;
+  hipLaunchKernelGGL(k_pad_add, dim3((cnt + 255) / 256), dim3(256), 0, st, x, y, N, Nc, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill0(double* x, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill0, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n);
+  return hipGetLastError();
+}
+
+int sum_blocks(size_t n) { return (int)std::min<size_t>(256, (n + 255) / 256); }
+
+hipError_t launch_sum(const double* x, const double* y, size_t n, double* part, int take_sqrt, double* out,
+                      hipStream_t st) {
+  const int nb = sum_blocks(n);
+  hipLaunchKernelGGL(k_sum_partial, dim3(nb), dim3(256), 0, st, x, y, n, part);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, part, nb, take_sqrt, out);
+  return hipGetLastError();
 }
 
 }  // namespace eg

@@ -71,4 +71,24 @@ hipError_t launch_copy(const double* a, double* b, size_t n, hipStream_t st);
 hipError_t launch_freestream(const DevMesh& M, int N, double* u, hipStream_t st);
 hipError_t launch_jac_to_psi(const DevMesh& M, int N, double* Dm, hipStream_t st);
 
+// adjoint (drag sensitivity)
+size_t jac_points_size(int d, int p);  // values per element of the pointwise flux Jacobians
+hipError_t launch_jac_points(const DevMesh& M, const TabData& td, int p, const double* ut, double* bc, hipStream_t st);
+hipError_t launch_adj_residual(const DevMesh& M, const TabData& td, int p, const double* wt, const double* gadd,
+                               const double* bc, double* out, hipStream_t st);
+hipError_t launch_drag(const DevMesh& M, const TabData& td, int p, const double* ut, const double* dir, double scale,
+                       double* part, double* gt, hipStream_t st);
+bool prk_tr_supported(int n);
+hipError_t launch_prk_stage_tr(const DevMesh& M, int n, const double* F, const int* perm, const double* rt,
+                               const double* un, double* ut, double beta, hipStream_t st);
+hipError_t launch_p0_transpose(const DevMesh& M, const double* Ad, const double* Ao, const double* dt, double* AdT,
+                               double* AoT, hipStream_t st);
+hipError_t launch_adj_p0_rhs(const DevMesh& M, const double* gt0, const double* dt, double* b, hipStream_t st);
+hipError_t launch_trunc(const double* x, double* y, int N, int Nc, int rows, hipStream_t st);
+hipError_t launch_pad_add(double* x, const double* y, int N, int Nc, int rows, hipStream_t st);
+hipError_t launch_fill0(double* x, size_t n, hipStream_t st);
+int sum_blocks(size_t n);
+hipError_t launch_sum(const double* x, const double* y, size_t n, double* part, int take_sqrt, double* out,
+                      hipStream_t st);
+
 }  // namespace eg

@@ -1,0 +1,112 @@
+"""Adjoint drag sensitivity on the GPU against the FP64 oracle: the drag
+functional and its gradient, the transposed-Jacobian kernel against the
+oracle's assembled Jacobian, the adjoint V-cycle against the oracle's sparse
+direct adjoint, and the torch.autograd gradient dC_D/dtheta (Mach number and
+wall-bump amplitudes) against central finite differences of converged GPU
+solves (step 1e-6, FP64).
+
+Tolerances: the functional and the matrix-free products are single FP64
+evaluations (1e-12 of the largest entry, as for the residual); the adjoint
+solution is iterated to a 1e-12 drop of its residual, so it matches the
+direct solve to ~1e-12 times the conditioning (1e-8 bound); the FD check is
+limited by the steady solves' 1e-12 drop over a step of 1e-6 (1e-5 bound)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from eg_inputs import ogrid, cubed_sphere_shell, wall_bumps, bump_centers
+from tests.gpu_util import perturbed, to_dev, to_host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("ogrid16x6-p3", ogrid(16, 6), 3, 3.0),
+    ("ogrid12x4-p2", ogrid(12, 4), 2, -2.0),
+    ("sphere6x2x2x2-p1", cubed_sphere_shell(2, 2), 1, 2.0),
+]
+
+
+def _solver(mesh, p, alpha, **kw):
+    import paper_1807_01151_amd as P
+    return P.Solver(mesh, p, alpha_deg=alpha, **kw)
+
+
+@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
+def test_drag_parity(name, mesh, p, alpha):
+    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
+    S = _solver(mesh, p, alpha)
+    u = perturbed(O, p, 300)
+    c_o, g_o = O.drag(p, u, sref=0.7, grad=True)
+    c_g, g_g = S.drag(to_dev(u), sref=0.7, grad=True)
+    print(name, "C_D", c_o, c_g, flush=True)
+    assert abs(c_g - c_o) <= 1e-12 * abs(c_o)
+    assert rel_err(to_host(g_g), g_o) < 1e-12
+
+
+@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
+def test_adjoint_apply_parity(name, mesh, p, alpha):
+    """(dR_p/du)^T w against the oracle's assembled Jacobian (exact blocks,
+    pinned to complex step) at every level p >= 1."""
+    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
+    S = _solver(mesh, p, alpha)
+    rng = np.random.default_rng(301)
+    for lev in range(1, p + 1):
+        u = perturbed(O, lev, 310 + lev)
+        w = rng.standard_normal(u.shape)
+        ref = (O.jacobian_sparse(lev, u).T @ w.ravel()).reshape(u.shape)
+        got = to_host(S.adjoint_apply(lev, to_dev(u), to_dev(w)))
+        e = rel_err(got, ref)
+        print(f"  {name} p={lev} J^T w error {e:.3e}", flush=True)
+        assert e < 1e-12
+
+
+@pytest.fixture(scope="module")
+def c1_steady():
+    mesh = ogrid(24, 12)
+    O = oracle.Oracle(mesh, 1)
+    u, h, st = O.solve(O.freestream(1), s=4, m=30, cfl_max=100.0, drop=1e-12, max_cycles=6000)
+    assert st == 0
+    return mesh, O, u
+
+
+def test_adjoint_solve_parity(c1_steady):
+    """The adjoint V-cycle at the converged c1 state (O-grid 24 x 12, p = 1)
+    against the oracle's sparse direct solve of (dR/du)^T lambda + dC_D/du = 0."""
+    mesh, O, u = c1_steady
+    S = _solver(mesh, 1, 0.0, rk_stages=4, cfl_max=100.0, krylov_m=30)
+    _, g = O.drag(1, u, grad=True)
+    lam_o = O.adjoint(1, u, g)
+    lam_g, hist, st = S.adjoint_solve(to_dev(u), to_dev(g), drop_tol=1e-12, max_cycles=10000)
+    e = rel_err(to_host(lam_g), lam_o)
+    print("adjoint cycles", len(hist) - 1, "drop", hist[-1] / hist[0], "lambda error", e, flush=True)
+    assert st == 0
+    assert e < 1e-8
+
+
+def test_steady_drag_gradient_matches_finite_differences():
+    """dC_D/dtheta by torch.autograd through the adjoint, theta = (Mach, two
+    wall-bump amplitudes), against central differences of converged GPU
+    solves at theta +- 1e-6."""
+    import paper_1807_01151_amd as P
+    base = ogrid(12, 4)
+    prob = P.autograd.SteadyDragProblem(base=base, centers=bump_centers(2, 2, seed=5), sigma=0.4, p_max=1,
+                                        solver_kw=dict(rk_stages=4, cfl_max=100.0, krylov_m=30),
+                                        drop=1e-13, adjoint_drop=1e-12)
+    theta = torch.tensor([0.3, 0.0, 0.0], dtype=torch.float64, requires_grad=True)
+    cd = P.autograd.SteadyDrag.apply(theta, prob)
+    cd.backward()
+    grad = theta.grad.numpy()
+    h = 1e-6
+    fd = np.zeros(3)
+    for i in range(3):
+        tp, tm = theta.detach().clone(), theta.detach().clone()
+        tp[i] += h
+        tm[i] -= h
+        Sp, Sm = prob.solver(tp.tolist()), prob.solver(tm.tolist())
+        cp = Sp.drag(prob.steady(Sp), sref=prob.sref)
+        cm = Sm.drag(prob.steady(Sm), sref=prob.sref)
+        fd[i] = (cp - cm) / (2 * h)
+    print("C_D", float(cd), "adjoint gradient", grad, "FD", fd, flush=True)
+    assert np.all(np.abs(grad - fd) <= 1e-5 * np.abs(fd) + 1e-9)
