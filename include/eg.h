@@ -174,6 +174,33 @@ eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_
 eg_status eg_solve_resume(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
                           int* n_cycles_host);
 
+/* ---- Batched independent solves ----
+ * n_solves steady problems (Section 2.4 eMG each) in one handle: meshes of
+ * any size with the same dim, p_max, rk_stages, krylov_m, cfl_max,
+ * relative_ramp, gamma and precision; mach, alpha_deg and beta_deg may
+ * differ.  The meshes are concatenated into one disconnected mesh, so every
+ * kernel launch covers all solves; the residual norms, the CFL ramp and the
+ * EXP1 Krylov process (Arnoldi, phi_1, breakdown) are per solve.  Level-p
+ * vectors are the solves' vectors one after another (eg_layout gives the
+ * offsets).  On a batch handle eg_vcycle, eg_solve_steady, eg_solve_resume,
+ * eg_rnorm, eg_drag and eg_adjoint_solve return EG_ERR_ARG; the per-element
+ * entries (eg_residual, eg_prk_step, ...) act on all solves with one CFL. */
+eg_status eg_init_batch(const eg_mesh* meshes, const eg_params* params, int n_solves, void* hip_stream,
+                        eg_handle** out);
+
+/* Offset (in doubles) of solve `solve` in a level-p vector, its modes per
+ * variable and its element count (a single-solve handle is solve 0). */
+eg_status eg_layout(const eg_handle* h, int solve, int p, int64_t* offset, int* n_modes, int* n_elem);
+
+/* Batched steady solve: V-cycles of all solves together until every solve
+ * has r_n <= drop_tol r_1 (its own r_1) or max_cycles.  hist_host is
+ * [n_solves][max_cycles + 1]: solve s's norms r_1, r_2, ... up to the cycle
+ * it reached the drop, which n_cycles_host[s] receives.  Converged solves
+ * keep being cycled (they sit at their fixed point) until all are done.
+ * Returns EG_OK when all converged, EG_ERR_NOT_CONVERGED, EG_ERR_DIVERGED. */
+eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
+                         int* n_cycles_host);
+
 /* ---- Adjoint drag sensitivity (discrete adjoint of the steady problem) ----
  * The paper solves R(u) = 0 (Section 2.1, eq. (starteq) at steady state);
  * these entries give d(functional)/d(parameter) for a converged u by the

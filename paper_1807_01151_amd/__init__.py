@@ -7,6 +7,7 @@ implementation: if the library is missing or cannot be loaded, calls raise.
 """
 
 from .binding import (  # noqa: F401
+    BatchSolver,
     EgError,
     Solver,
     lib,

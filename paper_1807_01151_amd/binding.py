@@ -14,7 +14,7 @@ EXPORTED_SYMBOLS = (
     "eg_init_mesh", "eg_free", "eg_last_error", "eg_sizes", "eg_set_freestream", "eg_residual",
     "eg_timestep", "eg_element_jacobian", "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm",
     "eg_vcycle", "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read",
-    "eg_drag", "eg_adjoint_apply", "eg_adjoint_solve",
+    "eg_drag", "eg_adjoint_apply", "eg_adjoint_solve", "eg_init_batch", "eg_layout", "eg_solve_batch",
 )
 
 KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
@@ -77,6 +77,9 @@ def lib():
         L.eg_profile.argtypes = [vp, i]
         L.eg_profile_read.argtypes = [vp, i, i, pd, C.POINTER(i)]
         L.eg_drag.argtypes = [vp, vp, pd, d, pd, vp]
+        L.eg_init_batch.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), i, vp, C.POINTER(vp)]
+        L.eg_layout.argtypes = [vp, i, i, C.POINTER(C.c_int64), C.POINTER(i), C.POINTER(i)]
+        L.eg_solve_batch.argtypes = [vp, vp, d, i, pd, C.POINTER(i)]
         L.eg_adjoint_apply.argtypes = [vp, i, vp, vp, vp]
         L.eg_adjoint_solve.argtypes = [vp, vp, vp, vp, d, i, pd, C.POINTER(i)]
         for name in ("eg_sizes", "eg_set_freestream", "eg_residual", "eg_timestep", "eg_element_jacobian",
@@ -273,3 +276,78 @@ def _solver_adjoint_solve(self, u, g, lam=None, drop_tol: float = 1e-10, max_cyc
 Solver.drag = _solver_drag
 Solver.adjoint_apply = _solver_adjoint_apply
 Solver.adjoint_solve = _solver_adjoint_solve
+
+
+class BatchSolver:
+    """n independent steady solves (same dim, p_max and solver settings; own
+    mesh, Mach number and angles) in one handle of the library: every kernel
+    launch covers all solves, norms, CFL ramps and the EXP1 Krylov process
+    are per solve.  The state is one device tensor of the solves' level-p_max
+    vectors one after another (``views`` splits it)."""
+
+    def __init__(self, meshes, p_max: int, machs, alphas=None, betas=None, rk_stages: int = 4,
+                 cfl_max: float = 100.0, krylov_m: int = 30, relative_ramp: bool = True, gamma: float = 1.4,
+                 precision: str = "fp64", stream=None):
+        import numpy as np
+        import torch
+        L = lib()
+        n = len(meshes)
+        alphas = [0.0] * n if alphas is None else list(alphas)
+        betas = [0.0] * n if betas is None else list(betas)
+        ms = [m.contiguous() for m in meshes]
+        self._keep = [(m.xyz, m.elem_vert, m.bface_tag) for m in ms]
+        cms = (_Mesh * n)(*[_Mesh(m.dim, m.n_vert, m.xyz.ctypes.data_as(C.POINTER(C.c_double)), m.n_elem,
+                                  m.elem_vert.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  m.bface_tag.ctypes.data_as(C.POINTER(C.c_int8))) for m in ms])
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        cps = (_Params * n)(*[_Params(p_max, rk_stages, cfl_max, krylov_m, int(relative_ramp), gamma, float(machs[i]),
+                                      float(alphas[i]), float(betas[i]), PRECISIONS[precision]) for i in range(n)])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        st = L.eg_init_batch(cms, cps, n, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        self._h = h
+        if st != 0:
+            msg = L.eg_last_error(h).decode() if h.value else ""
+            if h.value:
+                L.eg_free(h)
+            self._h = None
+            raise EgError(st, msg)
+        self.n, self.dim, self.p_max, self.V = n, ms[0].dim, p_max, ms[0].dim + 2
+        self.n_elem = sum(m.n_elem for m in ms)
+        self.elems = [m.n_elem for m in ms]
+        self._np = np
+
+    close = Solver.close
+    __del__ = Solver.__del__
+    _chk = Solver._chk
+    N = Solver.N
+    empty = Solver.empty
+    freestream = Solver.freestream
+    residual = Solver.residual
+
+    def layout(self, solve: int, p: int):
+        off = C.c_int64(0)
+        nm, ne = C.c_int(0), C.c_int(0)
+        self._chk(lib().eg_layout(self._h, solve, p, C.byref(off), C.byref(nm), C.byref(ne)))
+        return off.value, nm.value, ne.value
+
+    def views(self, u):
+        """Per-solve [n_elem_s, V, N] views of a batch vector."""
+        out, e0 = [], 0
+        for ne in self.elems:
+            out.append(u[e0:e0 + ne])
+            e0 += ne
+        return out
+
+    def solve(self, u, drop_tol: float = 1e-10, max_cycles: int = 1000):
+        """Returns (list of per-solve residual histories, cycles per solve, status)."""
+        np = self._np
+        hist = np.zeros((self.n, max_cycles + 1))
+        nc = (C.c_int * self.n)()
+        st = lib().eg_solve_batch(self._h, _ptr(u), drop_tol, max_cycles,
+                                  hist.ctypes.data_as(C.POINTER(C.c_double)), nc)
+        if st not in (0, 5, 6):
+            self._chk(st)
+        cyc = [int(nc[i]) for i in range(self.n)]
+        return [hist[i, : cyc[i] + 1] for i in range(self.n)], cyc, st

@@ -92,6 +92,13 @@ struct eg_handle {
   double* AdT = nullptr;     // transposed p = 0 operator
   double* AoT = nullptr;
   double* zero0 = nullptr;   // K0 zeros
+  // batched solves (eg_init_batch): per-solve CFL staging and norms
+  bool batch = false;
+  std::vector<int> seg_e0;   // host copy of the element ranges
+  double* dcfl = nullptr;    // [nseg] device CFL per solve
+  double* cfl_e_buf = nullptr;  // [E] per-element CFL (bound to M.cfl_e only inside eg_solve_batch)
+  double* hcfl = nullptr;    // [nseg] pinned
+  double* hnorm = nullptr;   // [nseg] pinned
 };
 
 namespace {
@@ -277,7 +284,7 @@ hipEvent_t next_event(eg_handle* h) {
 // (exact for the mass matrix of multilinear elements).
 eg_status setup_mesh(eg_handle* h, const eg_mesh* mesh, std::vector<double>& xv, std::vector<int>& nbr,
                      std::vector<uint8_t>& ncode, std::vector<double>& Lpk, std::vector<double>& Gpk,
-                     std::vector<double>& hE, double& omega) {
+                     std::vector<double>& hE, double& omega, std::vector<double>& vol) {
   const int d = mesh->dim, ne = mesh->n_elem, nf = 2 * d, nc = 1 << d, ncf = 1 << (d - 1);
   xv.assign((size_t)ne * nc * d, 0.0);
   for (int e = 0; e < ne; ++e)
@@ -376,7 +383,7 @@ eg_status setup_mesh(eg_handle* h, const eg_mesh* mesh, std::vector<double>& xv,
   Lpk.assign((size_t)ne * NT, 0.0);
   Gpk.assign((size_t)ne * NT, 0.0);
   hE.assign(ne, 0.0);
-  std::vector<double> vol(ne, 0.0);
+  vol.assign(ne, 0.0);
   int nq = 1;
   for (int r = 0; r < d; ++r) nq *= Q;
   // phi at the volume points (element independent)
@@ -493,8 +500,8 @@ eg_status run_exp1(eg_handle* h, double cfl, double* ut0, const double* ft0) {
   PCALL(h, EG_K_P0_SETUP, 0, eg::launch_p0_setup(M, ut0, ft0, h->pmax, cfl, 1, h->u0, h->b0, h->Ad, h->Ao, h->dt0, h->st));
   PCALL(h, EG_K_ARNOLDI, 0, eg::launch_arnoldi(M, h->m, h->nblk_arn, h->Ad, h->Ao, h->b0, h->Vb, h->H, h->part1,
                                                 h->part2, h->info, h->arn_st, h->arn_wn0, h->arn_W, h->H2, h->st));
-  PCALL(h, EG_K_PHI1, 0, eg::launch_phi1(h->m, h->H, h->H2, h->info, h->y, h->dfail, h->st));
-  PCALL(h, EG_K_EXP1_UPDATE, 0, eg::launch_exp1_update(M, h->Vb, h->y, h->info, h->u0, ut0, h->st));
+  PCALL(h, EG_K_PHI1, 0, eg::launch_phi1(h->m, h->M.nseg, h->H, h->H2, h->info, h->y, h->dfail, h->st));
+  PCALL(h, EG_K_EXP1_UPDATE, 0, eg::launch_exp1_update(M, h->m, h->Vb, h->y, h->info, h->u0, ut0, h->st));
   return EG_OK;
 }
 
@@ -641,8 +648,8 @@ eg_status adj_vc(eg_handle* h, int p) {
     HIPCHK(h, eg::launch_adj_p0_rhs(M, h->gq[0], h->dt0, h->b0, h->st));
     HIPCHK(h, eg::launch_arnoldi(M, h->m, h->nblk_arn, h->AdT, h->AoT, h->b0, h->Vb, h->H, h->part1, h->part2,
                                  h->info, h->arn_st, h->arn_wn0, h->arn_W, h->H2, h->st));
-    HIPCHK(h, eg::launch_phi1(h->m, h->H, h->H2, h->info, h->y, h->dfail, h->st));
-    HIPCHK(h, eg::launch_exp1_update(M, h->Vb, h->y, h->info, h->zero0, h->lam[0], h->st));
+    HIPCHK(h, eg::launch_phi1(h->m, h->M.nseg, h->H, h->H2, h->info, h->y, h->dfail, h->st));
+    HIPCHK(h, eg::launch_exp1_update(M, h->m, h->Vb, h->y, h->info, h->zero0, h->lam[0], h->st));
     return EG_OK;
   }
   const int n = NB(h, p), N = nmodes_of(M.d, p), Nc = nmodes_of(M.d, p - 1), rows = M.ne * M.V;
@@ -684,20 +691,38 @@ eg_status adj_norm(eg_handle* h, double* out) {
 
 extern "C" {
 
-eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stream, eg_handle** out) {
-  if (!out) return EG_ERR_ARG;
-  *out = nullptr;
-  if (!mesh || !prm || !mesh->xyz || !mesh->elem_vert || !mesh->bface_tag) return EG_ERR_ARG;
-  if ((mesh->dim != 2 && mesh->dim != 3) || mesh->n_vert <= 0 || mesh->n_elem <= 0) return EG_ERR_ARG;
-  eg_handle* h = new (std::nothrow) eg_handle;
-  if (!h) return EG_ERR_ALLOC;
+}  // extern "C"
+
+namespace {
+
+// Free-stream conserved state of a parameter set (rho = 1, p = 1/gamma).
+void freestream_of(const eg_params* prm, int d, double* U) {
+  const double al = prm->alpha_deg * M_PI / 180.0, be = prm->beta_deg * M_PI / 180.0;
+  double v[3] = {prm->mach * std::cos(al) * std::cos(be), prm->mach * std::sin(al) * std::cos(be),
+                 prm->mach * std::sin(be)};
+  double ke = 0.0;
+  for (int x = 0; x < 5; ++x) U[x] = 0.0;
+  U[0] = 1.0;
+  for (int a = 0; a < d; ++a) { U[1 + a] = v[a]; ke += v[a] * v[a]; }
+  U[d + 1] = 1.0 / (prm->gamma * (prm->gamma - 1.0)) + 0.5 * ke;
+}
+
+// Batch definition: element ranges of the solves in the union mesh and
+// their free-stream states.
+struct BatchDef {
+  int n = 0;
+  std::vector<int> e0;                     // [n + 1]
+  std::vector<std::array<double, 5>> uinf;  // [n]
+};
+
+eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, void* hip_stream,
+                      const BatchDef* bd) {
   const int d = mesh->dim;
   const int pmax_lim = (d == 2) ? 4 : 2;
   if (prm->p_max < 0 || prm->p_max > pmax_lim || prm->rk_stages < 1 || prm->krylov_m < 1 || prm->krylov_m > 48 ||
       !(prm->cfl_max > 0.0) || !(prm->gamma > 1.0) || !(prm->mach >= 0.0) ||
       (prm->precision != EG_FP64 && prm->precision != EG_MIXED)) {
     h->err = "invalid parameters (p_max, rk_stages, krylov_m 1..48, cfl_max, gamma, mach or precision)";
-    *out = h;
     return EG_ERR_ARG;
   }
   h->pmax = prm->p_max;
@@ -727,12 +752,12 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
     for (int a = 0; a < d; ++a) { M.gas.Uinf[1 + a] = v[a]; ke += v[a] * v[a]; }
     M.gas.Uinf[d + 1] = 1.0 / (prm->gamma * (prm->gamma - 1.0)) + 0.5 * ke;
   }
-  std::vector<double> xv, Lpk, Gpk, hE;
+  std::vector<double> xv, Lpk, Gpk, hE, vol;
   std::vector<int> nbr;
   std::vector<uint8_t> ncode;
   double omega = 0.0;
-  eg_status s = setup_mesh(h, mesh, xv, nbr, ncode, Lpk, Gpk, hE, omega);
-  if (s != EG_OK) { *out = h; return s; }
+  eg_status s = setup_mesh(h, mesh, xv, nbr, ncode, Lpk, Gpk, hE, omega, vol);
+  if (s != EG_OK) return s;
   M.omega = omega;
   h->tabs.resize(h->pmax + 1);
   for (int p = 0; p <= h->pmax; ++p) fill_tabdata(h->tabs[p], d, p, h->modes);
@@ -741,7 +766,7 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
 #define AL(ptr, cnt)                                  \
   do {                                                \
     eg_status a_ = dalloc(h, &(ptr), (size_t)(cnt));  \
-    if (a_ != EG_OK) { *out = h; return a_; }         \
+    if (a_ != EG_OK) return a_;                       \
   } while (0)
   AL(M.xv, xv.size());
   AL(M.nbr, nbr.size());
@@ -793,19 +818,60 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
   AL(h->Ad, (size_t)ne * V * V);
   AL(h->Ao, (size_t)ne * M.NF * V * V);
   AL(h->dt0, ne);
+  // batch tables: solve of each element, element ranges, |Omega| per solve,
+  // per-element free stream, and Arnoldi blocks that never straddle solves
+  const int nseg = bd ? bd->n : 1;
+  std::vector<int> brow0, brow1, bseg, sblk0;
+  std::vector<int> sid;
+  std::vector<double> seg_omega, uinf_e;
+  if (bd) {
+    M.nseg = nseg;
+    h->batch = true;
+    h->seg_e0 = bd->e0;
+    sid.assign(ne, 0);
+    seg_omega.assign(nseg, 0.0);
+    uinf_e.assign((size_t)ne * V, 0.0);
+    sblk0.push_back(0);
+    for (int sg = 0; sg < nseg; ++sg) {
+      for (int e = bd->e0[sg]; e < bd->e0[sg + 1]; ++e) {
+        sid[e] = sg;
+        seg_omega[sg] += vol[e];
+        for (int v = 0; v < V; ++v) uinf_e[(size_t)e * V + v] = bd->uinf[sg][v];
+      }
+      const int r0 = bd->e0[sg] * V, r1 = bd->e0[sg + 1] * V;
+      for (int r = r0; r < r1; r += 256) {
+        brow0.push_back(r);
+        brow1.push_back(std::min(r + 256, r1));
+        bseg.push_back(sg);
+      }
+      sblk0.push_back((int)brow0.size());
+    }
+    h->nblk_arn = (int)brow0.size();
+    AL(M.sid, ne);
+    AL(M.seg_e0, nseg + 1);
+    AL(M.seg_omega, nseg);
+    AL(M.uinf_e, (size_t)ne * V);
+    AL(h->cfl_e_buf, ne);
+    AL(M.brow0, brow0.size());
+    AL(M.brow1, brow1.size());
+    AL(M.bseg, bseg.size());
+    AL(M.sblk0, sblk0.size());
+    AL(h->dcfl, nseg);
+  } else {
+    h->nblk_arn = eg::arnoldi_blocks((int)K0);
+  }
   AL(h->Vb, (size_t)(h->m + 1) * K0);
-  AL(h->H, (size_t)(h->m + 1) * h->m);
-  h->nblk_arn = eg::arnoldi_blocks((int)K0);
+  AL(h->H, (size_t)nseg * (h->m + 1) * h->m);
   AL(h->part1, (size_t)h->nblk_arn * (h->m + 2));
   AL(h->part2, (size_t)h->nblk_arn * (h->m + 2));
-  AL(h->info, 2);
-  AL(h->arn_st, 2);
-  AL(h->arn_wn0, 1);
+  AL(h->info, 2 * nseg);
+  AL(h->arn_st, 2 * nseg);
+  AL(h->arn_wn0, nseg);
   AL(h->arn_W, 2 * K0);
-  AL(h->H2, (size_t)(h->m + 1) * h->m);
-  AL(h->y, h->m + 1);
+  AL(h->H2, (size_t)nseg * (h->m + 1) * h->m);
+  AL(h->y, (size_t)nseg * (h->m + 1));
   AL(h->npart, (size_t)(ne + 255) / 256 + 1);
-  AL(h->nout, 1);
+  AL(h->nout, nseg);
   AL(h->dfail, 1);
   AL(h->dpart, ne);
   AL(h->spart, 256);
@@ -813,7 +879,9 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
 #undef AL
   {
     hipError_t e = hipHostMalloc((void**)&h->hpin, 64, hipHostMallocDefault);
-    if (e != hipSuccess) { h->hpin = nullptr; h->err = "hipHostMalloc failed"; *out = h; return EG_ERR_ALLOC; }
+    if (e == hipSuccess && bd) e = hipHostMalloc((void**)&h->hcfl, sizeof(double) * nseg, hipHostMallocDefault);
+    if (e == hipSuccess && bd) e = hipHostMalloc((void**)&h->hnorm, sizeof(double) * nseg, hipHostMallocDefault);
+    if (e != hipSuccess) { h->err = "hipHostMalloc failed"; return EG_ERR_ALLOC; }
   }
   // the p = 0 face rule is the 2-point rule of the order-0 tables
   double g2x[2] = {h->tabs[0].x[0], h->tabs[0].x[1]}, g2w[2] = {h->tabs[0].w[0], h->tabs[0].w[1]};
@@ -827,11 +895,103 @@ eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stre
   if (e == hipSuccess) e = hipMemcpy(M.g2x, g2x, 16, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(M.g2w, g2w, 16, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(h->dfail, 0, sizeof(int));
-  if (e == hipSuccess) e = hipMemset(h->info, 0, 2 * sizeof(double));
-  if (e != hipSuccess) { *out = h; return hipfail(h, e, "upload"); }
-  *out = h;
+  if (e == hipSuccess) e = hipMemset(h->info, 0, 2 * nseg * sizeof(double));
+  if (bd) {
+    if (e == hipSuccess) e = hipMemcpy(M.sid, sid.data(), sid.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M.seg_e0, bd->e0.data(), bd->e0.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M.seg_omega, seg_omega.data(), seg_omega.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M.uinf_e, uinf_e.data(), uinf_e.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M.brow0, brow0.data(), brow0.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M.brow1, brow1.data(), brow1.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M.bseg, bseg.data(), bseg.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(M.sblk0, sblk0.data(), sblk0.size() * 4, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hipfail(h, e, "upload");
   return EG_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stream, eg_handle** out) {
+  if (!out) return EG_ERR_ARG;
+  *out = nullptr;
+  if (!mesh || !prm || !mesh->xyz || !mesh->elem_vert || !mesh->bface_tag) return EG_ERR_ARG;
+  if ((mesh->dim != 2 && mesh->dim != 3) || mesh->n_vert <= 0 || mesh->n_elem <= 0) return EG_ERR_ARG;
+  eg_handle* h = new (std::nothrow) eg_handle;
+  if (!h) return EG_ERR_ALLOC;
+  *out = h;
+  return init_common(h, mesh, prm, hip_stream, nullptr);
+}
+
+eg_status eg_init_batch(const eg_mesh* meshes, const eg_params* params, int n_solves, void* hip_stream,
+                        eg_handle** out) {
+  if (!out) return EG_ERR_ARG;
+  *out = nullptr;
+  if (!meshes || !params || n_solves < 1) return EG_ERR_ARG;
+  const int d = meshes[0].dim;
+  long long nv = 0, ne = 0;
+  for (int i = 0; i < n_solves; ++i) {
+    const eg_mesh& m = meshes[i];
+    const eg_params& q = params[i];
+    if (!m.xyz || !m.elem_vert || !m.bface_tag || m.dim != d || m.n_vert <= 0 || m.n_elem <= 0) return EG_ERR_ARG;
+    if (q.p_max != params[0].p_max || q.rk_stages != params[0].rk_stages || q.krylov_m != params[0].krylov_m ||
+        q.cfl_max != params[0].cfl_max || q.relative_ramp != params[0].relative_ramp ||
+        q.gamma != params[0].gamma || q.precision != params[0].precision || !(q.mach >= 0.0))
+      return EG_ERR_ARG;
+    nv += m.n_vert;
+    ne += m.n_elem;
+  }
+  if (ne > (1LL << 28) || nv > (1LL << 30)) return EG_ERR_ARG;
+  eg_handle* h = new (std::nothrow) eg_handle;
+  if (!h) return EG_ERR_ALLOC;
+  *out = h;
+  // union mesh: vertices and elements of the solves one after another (no
+  // shared vertices, so no face is matched across solves)
+  const int nc = 1 << d, nf = 2 * d;
+  std::vector<double> xyz((size_t)nv * d);
+  std::vector<int32_t> ev((size_t)ne * nc);
+  std::vector<int8_t> tag((size_t)ne * nf);
+  BatchDef bd;
+  bd.n = n_solves;
+  bd.e0.push_back(0);
+  long long ov = 0, oe = 0;
+  for (int i = 0; i < n_solves; ++i) {
+    const eg_mesh& m = meshes[i];
+    std::memcpy(&xyz[(size_t)ov * d], m.xyz, sizeof(double) * (size_t)m.n_vert * d);
+    for (long long k = 0; k < (long long)m.n_elem * nc; ++k) {
+      if (m.elem_vert[k] < 0 || m.elem_vert[k] >= m.n_vert) {
+        h->err = "element vertex index out of range";
+        return EG_ERR_MESH;
+      }
+      ev[(size_t)oe * nc + k] = (int32_t)(m.elem_vert[k] + ov);
+    }
+    std::memcpy(&tag[(size_t)oe * nf], m.bface_tag, (size_t)m.n_elem * nf);
+    ov += m.n_vert;
+    oe += m.n_elem;
+    bd.e0.push_back((int)oe);
+    std::array<double, 5> U{};
+    freestream_of(&params[i], d, U.data());
+    bd.uinf.push_back(U);
+  }
+  eg_mesh um{d, (int)nv, xyz.data(), (int)ne, ev.data(), tag.data()};
+  return init_common(h, &um, &params[0], hip_stream, &bd);
+}
+
+eg_status eg_layout(const eg_handle* h, int solve, int p, int64_t* offset, int* n_modes, int* n_elem) {
+  if (!h || p < 0 || p > h->pmax) return EG_ERR_ARG;
+  const int nseg = h->M.nseg;
+  if (solve < 0 || solve >= nseg) return EG_ERR_ARG;
+  const int e0 = h->batch ? h->seg_e0[solve] : 0, e1 = h->batch ? h->seg_e0[solve + 1] : h->M.ne;
+  const int N = nmodes_of(h->M.d, p);
+  if (offset) *offset = (int64_t)e0 * h->M.V * N;
+  if (n_modes) *n_modes = N;
+  if (n_elem) *n_elem = e1 - e0;
+  return EG_OK;
+}
+
+
 
 void eg_free(eg_handle* h) {
   if (!h) return;
@@ -839,6 +999,8 @@ void eg_free(eg_handle* h) {
   for (void* p : h->allocs) (void)hipFree(p);
   for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->hpin) (void)hipHostFree(h->hpin);
+  if (h->hcfl) (void)hipHostFree(h->hcfl);
+  if (h->hnorm) (void)hipHostFree(h->hnorm);
   delete h;
 }
 
@@ -937,6 +1099,7 @@ eg_status eg_exp1_step(eg_handle* h, double cfl, double* u0_dev, const double* f
 
 eg_status eg_rnorm(eg_handle* h, const double* r_dev, double* rn_host) {
   if (!h || !r_dev || !rn_host) return EG_ERR_ARG;
+  if (h->batch) return fail(h, EG_ERR_ARG, "batch handle: per-solve norms need eg_solve_batch");
   const int N = nmodes_of(h->M.d, h->pmax);
   HIPCHK(h, eg::launch_basis(h->M, N, r_dev, h->tmp, 3, h->st));
   HIPCHK(h, eg::launch_norm(h->M, N, h->tmp, h->npart, h->nout, h->st));
@@ -974,6 +1137,7 @@ eg_status eg_profile_read(eg_handle* h, int kernel_class, int p, double* total_m
 
 eg_status eg_vcycle(eg_handle* h, double* u_dev, int n, double rref, double* rn_host, double* cfl_host) {
   if (!h || !u_dev || !rn_host || n < 1) return EG_ERR_ARG;
+  if (h->batch) return fail(h, EG_ERR_ARG, "batch handle: per-solve norms need eg_solve_batch");
   if (!eg::jacobian_supported(h->M.d, h->pmax) && h->pmax > 0)
     return fail(h, EG_ERR_UNSUPPORTED, "element block too large");
   const int N = nmodes_of(h->M.d, h->pmax);
@@ -1031,6 +1195,7 @@ eg_status solve_loop(eg_handle* h, double* u_dev, int n0, double r1, double drop
 eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
                           int* n_cycles_host) {
   if (!h || !u_dev || !hist_host || !n_cycles_host || max_cycles < 0) return EG_ERR_ARG;
+  if (h->batch) return fail(h, EG_ERR_ARG, "batch handle: per-solve norms need eg_solve_batch");
   if (!eg::jacobian_supported(h->M.d, h->pmax) && h->pmax > 0)
     return fail(h, EG_ERR_UNSUPPORTED, "element block too large");
   h->sv_phase_b = 0;
@@ -1042,6 +1207,7 @@ eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_
 eg_status eg_drag(eg_handle* h, const double* u_dev, const double* dir_host, double sref, double* cd_host,
                   double* grad_dev) {
   if (!h || !u_dev || !dir_host || !cd_host || !(sref > 0.0)) return EG_ERR_ARG;
+  if (h->batch) return fail(h, EG_ERR_ARG, "batch handle: per-solve norms need eg_solve_batch");
   if (!(h->mach > 0.0)) return fail(h, EG_ERR_ARG, "drag needs a free stream with mach > 0");
   const DevMesh& M = h->M;
   const int p = h->pmax, N = nmodes_of(M.d, p);
@@ -1075,6 +1241,7 @@ eg_status eg_adjoint_apply(eg_handle* h, int p, const double* u_dev, const doubl
 eg_status eg_adjoint_solve(eg_handle* h, const double* u_dev, const double* g_dev, double* lam_dev, double drop_tol,
                            int max_cycles, double* hist_host, int* n_cycles_host) {
   if (!h || !u_dev || !g_dev || !lam_dev || !hist_host || !n_cycles_host || max_cycles < 0) return EG_ERR_ARG;
+  if (h->batch) return fail(h, EG_ERR_ARG, "batch handle: per-solve norms need eg_solve_batch");
   if (h->pmax < 1) return fail(h, EG_ERR_UNSUPPORTED, "adjoint needs p_max >= 1");
   ECHK(adj_supported(h));
   ECHK(adj_alloc(h));
@@ -1102,6 +1269,71 @@ eg_status eg_adjoint_solve(eg_handle* h, const double* u_dev, const double* g_de
   if (e != hipSuccess && st == EG_OK) st = hipfail(h, e, "basis");
   hipError_t e2 = hipStreamSynchronize(h->st);
   if (e2 != hipSuccess && st == EG_OK) st = hipfail(h, e2, "sync");
+  return st;
+}
+
+eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
+                         int* n_cycles_host) {
+  if (!h || !u_dev || !hist_host || !n_cycles_host || max_cycles < 0) return EG_ERR_ARG;
+  if (!h->batch) return fail(h, EG_ERR_ARG, "not a batch handle (eg_init_batch)");
+  if (!eg::jacobian_supported(h->M.d, h->pmax) && h->pmax > 0)
+    return fail(h, EG_ERR_UNSUPPORTED, "element block too large");
+  h->M.cfl_e = h->cfl_e_buf;  // per-solve CFL for the duration of the batch solve
+  const DevMesh& M = h->M;
+  const int nseg = M.nseg, pm = h->pmax, N = nmodes_of(M.d, pm);
+  std::vector<double> r1(nseg, -1.0), rmin(nseg, HUGE_VAL);
+  std::vector<int> done(nseg, 0), nmin(nseg, 1);
+  for (int sg = 0; sg < nseg; ++sg) n_cycles_host[sg] = 0;
+  HIPCHK(h, eg::launch_basis(M, N, u_dev, h->ut[pm], 0, h->st));
+  eg_status st = EG_OK;
+  int phase_b = 0;
+  for (int n = 1;; ++n) {
+    // FP64 entry norms of every solve
+    PCALL(h, EG_K_RESIDUAL, pm,
+          eg::launch_residual(M, h->tabs[pm], pm, h->ut[pm], nullptr, h->rt[pm], eg::PREC_FP64, h->st));
+    PCALL(h, EG_K_NORM, pm, eg::launch_norm(M, N, h->rt[pm], h->npart, h->nout, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->hnorm, h->nout, sizeof(double) * nseg, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->hpin + 1, h->dfail, sizeof(int), hipMemcpyDeviceToHost, h->st));
+    st = sync_status(h);
+    if (st != EG_OK) break;
+    int fl = 0;
+    std::memcpy(&fl, h->hpin + 1, sizeof(int));
+    if (fl) { st = fail(h, EG_ERR_DIVERGED, "singular pivot in a block factorisation or in phi_1"); break; }
+    bool all = true, bad = false;
+    double worst = 0.0;
+    for (int sg = 0; sg < nseg; ++sg) {
+      const double rn = h->hnorm[sg];
+      if (r1[sg] < 0.0) r1[sg] = rn;
+      if (!done[sg]) {
+        hist_host[(size_t)sg * (max_cycles + 1) + (n - 1)] = rn;
+        n_cycles_host[sg] = n - 1;
+        if (rn <= drop_tol * r1[sg]) done[sg] = 1;
+      }
+      if (!std::isfinite(rn)) bad = true;
+      all = all && done[sg];
+      worst = std::max(worst, rn / r1[sg]);
+      if (!(rn >= rmin[sg])) { rmin[sg] = rn; nmin[sg] = n; }
+      h->hcfl[sg] = cfl_ramp(h->cfl_max, rn, h->relr ? r1[sg] : 1.0, n, pm);
+    }
+    if (bad) { st = fail(h, EG_ERR_DIVERGED, "non-finite residual norm"); break; }
+    if (all) break;
+    if (n - 1 == max_cycles) { st = fail(h, EG_ERR_NOT_CONVERGED, "max_cycles reached"); break; }
+    if (h->mixed && !phase_b) {
+      bool stall = false;
+      for (int sg = 0; sg < nseg; ++sg) stall = stall || (!done[sg] && n - nmin[sg] >= EG_STALL_CYCLES);
+      if (worst <= EG_PHASE_B_DROP || stall) phase_b = 1;
+    }
+    h->phase_b = phase_b;
+    HIPCHK(h, hipMemcpyAsync(h->dcfl, h->hcfl, sizeof(double) * nseg, hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, eg::launch_expand_cfl(M, h->dcfl, h->st));
+    st = vc_rec(h, pm, h->cfl_max);
+    if (st != EG_OK) break;
+  }
+  hipError_t e = eg::launch_basis(M, N, h->ut[pm], u_dev, 1, h->st);
+  if (e != hipSuccess && st == EG_OK) st = hipfail(h, e, "basis");
+  hipError_t e2 = hipStreamSynchronize(h->st);
+  if (e2 != hipSuccess && st == EG_OK) st = hipfail(h, e2, "sync");
+  h->M.cfl_e = nullptr;
   return st;
 }
 

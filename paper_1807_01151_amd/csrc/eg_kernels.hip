@@ -178,7 +178,8 @@ template <int D, int P, int EB, class R>
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut, const double* __restrict__ fadd,
                                                   double* __restrict__ rt, const double* __restrict__ xv,
                                                   const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
-                                                  int ne, Tab<D, P, R> tab, GasT<R> gas) {
+                                                  int ne, Tab<D, P, R> tab, GasT<R> gas,
+                                                  const double* __restrict__ uinf_e) {
   using C = Cfg<D, P>;
   constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, NC = C::NC;
   __shared__ R s_u[EB * V * N];
@@ -275,7 +276,10 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
     } else if (nb == NB_WALL) {
       ghost_wall<D>(UL, nh, UR);
     } else {
-      ghost_far<D>(UL, nh, UR, gas.Uinf, gas.g);
+      R Ui[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) Ui[v] = uinf_e ? R(uinf_e[(size_t)e * V + v]) : gas.Uinf[v];
+      ghost_far<D>(UL, nh, UR, Ui, gas.g);
     }
     R F[V];
     rusanov<D>(UL, UR, nh, F, gas.g);
@@ -337,7 +341,8 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
                                                   const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
                                                   const double* __restrict__ Gpk, int NT, const double* __restrict__ dtau,
                                                   R* __restrict__ out, int* __restrict__ perm, int* __restrict__ fail,
-                                                  int ne, Tab<D, P, R> tab, GasT<R> gas) {
+                                                  int ne, Tab<D, P, R> tab, GasT<R> gas,
+                                                  const double* __restrict__ uinf_e) {
   using C = Cfg<D, P>;
   constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, NC = C::NC, n = C::NB;
   constexpr int NP = N * N;
@@ -431,7 +436,12 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
     } else {
       Dual<V, R> UG[V];
       if (nb == NB_WALL) ghost_wall<D>(UL, nh, UG);
-      else ghost_far<D>(UL, nh, UG, gas.Uinf, gas.g);
+      else {
+        R Ui[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) Ui[v] = uinf_e ? R(uinf_e[(size_t)e * V + v]) : gas.Uinf[v];
+        ghost_far<D>(UL, nh, UG, Ui, gas.g);
+      }
       rusanov<D>(UL, UG, nh, F, gas.g);
     }
     const R wa = wk * area;
@@ -569,7 +579,8 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
 template <int D, int P, class R>
 __global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ ut, const double* __restrict__ xv,
                                                     const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
-                                                    R* __restrict__ BC, int ne, Tab<D, P, R> tab, GasT<R> gas) {
+                                                    R* __restrict__ BC, int ne, Tab<D, P, R> tab, GasT<R> gas,
+                                                    const double* __restrict__ uinf_e) {
   using C = Cfg<D, P>;
   constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, NC = C::NC;
   constexpr int NPT = QV + NF * QF;
@@ -655,7 +666,12 @@ __global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ u
     } else {
       Dual<V, R> UG[V];
       if (nb == NB_WALL) ghost_wall<D>(UL, nh, UG);
-      else ghost_far<D>(UL, nh, UG, gas.Uinf, gas.g);
+      else {
+        R Ui[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) Ui[v] = uinf_e ? R(uinf_e[(size_t)e * V + v]) : gas.Uinf[v];
+        ghost_far<D>(UL, nh, UG, Ui, gas.g);
+      }
       rusanov<D>(UL, UG, nh, F, gas.g);
     }
     const R wa = wk * area;
@@ -1039,7 +1055,8 @@ __global__ __launch_bounds__(256) void k_prolong(double* __restrict__ ut, const 
 template <int D>
 __global__ __launch_bounds__(256) void k_timestep(const double* __restrict__ ut, int N, const double* __restrict__ Lpk,
                                                   int NT, const double* __restrict__ hE, int p, double cfl, double mult,
-                                                  double* __restrict__ dtau, int ne, double g) {
+                                                  double* __restrict__ dtau, int ne, double g,
+                                                  const double* __restrict__ cfl_e) {
   constexpr int V = D + 2;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
@@ -1068,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_timestep(const double* __restrict__ ut,
 #pragma unroll
   for (int a = 0; a < D; ++a) q2 += (U[1 + a] / U[0]) * (U[1 + a] / U[0]);
   const double c = sqrt(g * pressure<D>(U, g) / U[0]);
-  dtau[e] = mult * cfl * hE[e] / ((2.0 * p + 1.0) * (sqrt(q2) + c));
+  dtau[e] = mult * (cfl_e ? cfl_e[e] : cfl) * hE[e] / ((2.0 * p + 1.0) * (sqrt(q2) + c));
 }
 
 // ---------------------------------------------------------------------------
@@ -1117,6 +1134,36 @@ __global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ p
   if (threadIdx.x == 0) out[0] = sqrt(s_w[0] + s_w[1] + s_w[2] + s_w[3]) / omega;
 }
 
+// Density-residual norm of every solve of a batch: one block per solve sums
+// its element range [seg_e0[s], seg_e0[s + 1]) in a fixed order.
+template <int D, int N>
+__global__ __launch_bounds__(256) void k_norm_seg(const double* __restrict__ rt, const double* __restrict__ Lpk,
+                                                  int NT, const int* __restrict__ seg_e0,
+                                                  const double* __restrict__ seg_omega, double* __restrict__ out) {
+  constexpr int V = D + 2;
+  __shared__ double s_w[4];
+  const int sg = blockIdx.x;
+  const int e0 = seg_e0[sg], e1 = seg_e0[sg + 1];
+  double acc = 0.0;
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const double* L = Lpk + (size_t)e * NT;
+    const double* a = rt + (size_t)e * V * N;
+    double r[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double s = a[i];
+#pragma unroll
+      for (int j = 0; j < i; ++j) s -= L[i * (i + 1) / 2 + j] * r[j];
+      r[i] = s / L[i * (i + 1) / 2 + i];
+      acc += r[i] * r[i];
+    }
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[sg] = sqrt(s_w[0] + s_w[1] + s_w[2] + s_w[3]) / seg_omega[sg];
+}
+
 // ---------------------------------------------------------------------------
 // p = 0 level set-up for EXP1 (Sections 2.1 and 3.3 at p = 0), psi
 // coordinates, one thread per element:
@@ -1132,7 +1179,8 @@ __global__ __launch_bounds__(128) void k_p0_setup(const double* __restrict__ ut0
                                                   int pmax, double cfl, int scale, double* __restrict__ u0,
                                                   double* __restrict__ bvec, double* __restrict__ Ad,
                                                   double* __restrict__ Ao, double* __restrict__ dtout, int ne, Gas gas,
-                                                  const double* __restrict__ gx, const double* __restrict__ gw) {
+                                                  const double* __restrict__ gx, const double* __restrict__ gw,
+                                                  const double* __restrict__ uinf_e, const double* __restrict__ cfl_e) {
   constexpr int V = D + 2, NF = 2 * D, NC = 1 << D, QF = 1 << (D - 1);
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
@@ -1150,7 +1198,8 @@ __global__ __launch_bounds__(128) void k_p0_setup(const double* __restrict__ ut0
 #pragma unroll
     for (int a = 0; a < D; ++a) q2 += (U[1 + a] / U[0]) * (U[1 + a] / U[0]);
     const double c = sqrt(gas.g * pressure<D>(U, gas.g) / U[0]);
-    dt = (pmax + 1.0) * cfl * hE[e] / ((2.0 * pmax + 1.0) * (sqrt(q2) + c));
+    const double ce = cfl_e ? cfl_e[e] : cfl;
+    dt = (pmax + 1.0) * ce * hE[e] / ((2.0 * pmax + 1.0) * (sqrt(q2) + c));
   }
   double R[V], Jd[V * V];
 #pragma unroll
@@ -1203,7 +1252,12 @@ __global__ __launch_bounds__(128) void k_p0_setup(const double* __restrict__ ut0
       } else {
         Dual<V> UG[V];
         if (nb == NB_WALL) ghost_wall<D>(UL, nh, UG);
-        else ghost_far<D>(UL, nh, UG, gas.Uinf, gas.g);
+        else {
+          double Ui[V];
+#pragma unroll
+          for (int v = 0; v < V; ++v) Ui[v] = uinf_e ? uinf_e[(size_t)e * V + v] : gas.Uinf[v];
+          ghost_far<D>(UL, nh, UG, Ui, gas.g);
+        }
         rusanov<D>(UL, UG, nh, F, gas.g);
       }
 #pragma unroll
@@ -1357,23 +1411,24 @@ __device__ __forceinline__ void block_sums_rs(double (&p)[NV], double x, int cnt
   __syncthreads();
 }
 
-// Deterministic sum over the nblk blocks of cnt per-block partials
-// (part[q * P + i]) into s_out[i]: group g of threads sums q = g, g + G, ...
-// with its loads issued sixteen at a time, then the G group sums are added in
-// order.  Every block computes bitwise the same totals.
-__device__ __forceinline__ void grid_partials_sum(const double* __restrict__ part, int nblk, int P, int cnt,
+// Deterministic sum over the blocks [b0, b1) of cnt per-block partials
+// (part[q * P + i]) into s_out[i]: group g of threads sums q = b0 + g,
+// b0 + g + G, ... with its loads issued sixteen at a time, then the G group
+// sums are added in order.  Every block of the range computes bitwise the
+// same totals.
+__device__ __forceinline__ void grid_partials_sum(const double* __restrict__ part, int b0, int b1, int P, int cnt,
                                                   double* s_tmp /*[256]*/, double* s_out) {
   const int G = blockDim.x / cnt;
   const int t = threadIdx.x;
   if (t < G * cnt) {
     const int g = t / cnt, i = t % cnt;
     double s = 0.0;
-    for (int q0 = g; q0 < nblk; q0 += 16 * G) {
+    for (int q0 = b0 + g; q0 < b1; q0 += 16 * G) {
       double a[16];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int q = q0 + u * G;
-        a[u] = q < nblk ? part[(size_t)q * P + i] : 0.0;
+        a[u] = q < b1 ? part[(size_t)q * P + i] : 0.0;
       }
 #pragma unroll
       for (int w = 8; w >= 1; w >>= 1)
@@ -1390,6 +1445,31 @@ __device__ __forceinline__ void grid_partials_sum(const double* __restrict__ par
     s_out[t] = s;
   }
   __syncthreads();
+}
+
+// Solve segments of a batched Arnoldi (all null for a single solve): block b
+// covers rows [brow0[b], brow1[b]) of solve bseg[b]; solve s owns blocks
+// [sblk0[s], sblk0[s + 1]).  Each solve has its own Hessenberg matrix, beta,
+// Krylov dimension and breakdown flag, so batched solves stay independent.
+struct ArnSeg {
+  const int* brow0;
+  const int* brow1;
+  const int* bseg;
+  const int* sblk0;
+};
+
+struct SegPos {
+  int sg, b0, b1, k, kend;
+};
+
+__device__ __forceinline__ SegPos seg_pos(const ArnSeg& S, int K) {
+  SegPos r;
+  r.sg = S.bseg ? S.bseg[blockIdx.x] : 0;
+  r.b0 = S.sblk0 ? S.sblk0[r.sg] : 0;
+  r.b1 = S.sblk0 ? S.sblk0[r.sg + 1] : (int)gridDim.x;
+  r.k = (S.brow0 ? S.brow0[blockIdx.x] : (int)(blockIdx.x * blockDim.x)) + (int)threadIdx.x;
+  r.kend = S.brow1 ? S.brow1[blockIdx.x] : K;
+  return r;
 }
 
 // Arnoldi process of EXP1 as a sequence of full-grid kernels (a kernel
@@ -1412,43 +1492,44 @@ __device__ __forceinline__ void grid_partials_sum(const double* __restrict__ par
 // Happy breakdown (hn <= 1e-12 ||A v_j||) sets st[0], so every later kernel
 // returns; info[0] = Krylov dimension used, info[1] = beta.
 __global__ __launch_bounds__(256) void k_arn_beta(int K, const double* __restrict__ b, double* __restrict__ part,
-                                                  int P, int* __restrict__ st) {
+                                                  int P, int* __restrict__ st, ArnSeg S) {
   __shared__ double s_wave[4 * 64];
   __shared__ double s_h[64];
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const double x = k < K ? b[k] : 0.0;
+  const SegPos sp = seg_pos(S, K);
+  const double x = sp.k < sp.kend ? b[sp.k] : 0.0;
   block_sums<1>(1, [&](int) { return x * x; }, s_wave, s_h);
   if (threadIdx.x == 0) part[blockIdx.x * P] = s_h[0];
-  if (blockIdx.x == 0 && threadIdx.x == 0) { st[0] = 0; st[1] = 0; }
+  if (blockIdx.x == sp.b0 && threadIdx.x == 0) { st[2 * sp.sg] = 0; st[2 * sp.sg + 1] = 0; }
 }
 
 __global__ __launch_bounds__(256) void k_arn_start(int K, int m, const double* __restrict__ b,
                                                    const double* __restrict__ part, int P, double* __restrict__ Vb,
-                                                   double* __restrict__ info, int* __restrict__ st) {
+                                                   double* __restrict__ info, int* __restrict__ st, ArnSeg S) {
   __shared__ double s_tmp[256];
   __shared__ double s_g[64];
-  grid_partials_sum(part, gridDim.x, P, 1, s_tmp, s_g);
+  const SegPos sp = seg_pos(S, K);
+  grid_partials_sum(part, sp.b0, sp.b1, P, 1, s_tmp, s_g);
   const double beta = sqrt(s_g[0]);
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    info[1] = beta;
-    info[0] = (beta == 0.0) ? 0.0 : (double)m;
-    if (beta == 0.0) st[0] = 1;
+  if (blockIdx.x == sp.b0 && threadIdx.x == 0) {
+    info[2 * sp.sg + 1] = beta;
+    info[2 * sp.sg] = (beta == 0.0) ? 0.0 : (double)m;
+    if (beta == 0.0) st[2 * sp.sg] = 1;
   }
   if (beta == 0.0) return;
-  if (k < K) Vb[k] = b[k] / beta;
+  if (sp.k < sp.kend) Vb[sp.k] = b[sp.k] / beta;
 }
 
 template <int V, int NF>
 __global__ __launch_bounds__(256) void k_arn_a(int K, const int* __restrict__ nbr, const double* __restrict__ Ad,
                                                const double* __restrict__ Ao, const double* __restrict__ Vb,
                                                double* __restrict__ W, double* __restrict__ part, int P,
-                                               const int* __restrict__ st) {
-  if (st[0]) return;
+                                               const int* __restrict__ st, ArnSeg S) {
+  const SegPos sp = seg_pos(S, K);
+  if (st[2 * sp.sg]) return;
   __shared__ double s_wave[4 * 64];
   __shared__ double s_h[64];
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool act = k < K;
+  const int k = sp.k;
+  const bool act = k < sp.kend;
   const double v0 = act ? Vb[k] : 0.0;
   const double w = act ? spmv_row<V, NF>(k, nbr, Ad, Ao, Vb) : 0.0;
   if (act) W[k] = w;
@@ -1460,22 +1541,25 @@ template <int NVM>
 __global__ __launch_bounds__(256) void k_arn_b(int K, int m, int j, const double* __restrict__ Vb,
                                                double* __restrict__ W, const double* __restrict__ part1,
                                                double* __restrict__ part2, int P, double* __restrict__ H,
-                                               double* __restrict__ wn0, const int* __restrict__ st) {
-  if (st[0]) return;
+                                               double* __restrict__ wn0, const int* __restrict__ st, ArnSeg S) {
+  const SegPos sp = seg_pos(S, K);
+  if (st[2 * sp.sg]) return;
   __shared__ double s_wave[4 * 64];
   __shared__ double s_h[64];
   __shared__ double s_g[64];
   __shared__ double s_tmp[256];
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool act = k < K;
-  const int kc = act ? k : K - 1;  // clamped row: loads need no divergent branch
+  H += (size_t)sp.sg * (m + 1) * m;
+  wn0 += sp.sg;
+  const int k = sp.k;
+  const bool act = k < sp.kend;
+  const int kc = act ? k : sp.kend - 1;  // clamped row: loads need no divergent branch
   double vr[NVM];
 #pragma unroll
   for (int i = 0; i < NVM; ++i) vr[i] = (i <= j) ? Vb[(size_t)i * K + kc] : 0.0;
   const double w = act ? W[kc] : 0.0;
 #pragma unroll
   for (int i = 0; i < NVM; ++i) vr[i] = act ? vr[i] : 0.0;
-  grid_partials_sum(part1, gridDim.x, P, j + 2, s_tmp, s_g);
+  grid_partials_sum(part1, sp.b0, sp.b1, P, j + 2, s_tmp, s_g);
   double a0 = 0.0, a1 = 0.0;
 #pragma unroll
   for (int i = 0; i < NVM; i += 2) {
@@ -1484,8 +1568,8 @@ __global__ __launch_bounds__(256) void k_arn_b(int K, int m, int j, const double
   }
   const double w1 = w - (a0 + a1);
   if (act) W[k] = w1;
-  if (blockIdx.x == 0 && threadIdx.x <= j) H[threadIdx.x * m + j] = s_g[threadIdx.x];
-  if (blockIdx.x == 0 && threadIdx.x == 0) wn0[0] = sqrt(s_g[j + 1]);
+  if (blockIdx.x == sp.b0 && threadIdx.x <= j) H[threadIdx.x * m + j] = s_g[threadIdx.x];
+  if (blockIdx.x == sp.b0 && threadIdx.x == 0) wn0[0] = sqrt(s_g[j + 1]);
   constexpr int NP = NVM == 48 ? 64 : NVM;
   double pp[NP];
 #pragma unroll
@@ -1505,17 +1589,23 @@ __global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* 
                                                 double* __restrict__ Wn, const double* __restrict__ part2,
                                                 double* __restrict__ part1, int P, double* __restrict__ H,
                                                 double* __restrict__ H2, const double* __restrict__ wn0,
-                                                double* __restrict__ info, int* __restrict__ st) {
-  if (st[0]) return;
+                                                double* __restrict__ info, int* __restrict__ st, ArnSeg S) {
+  const SegPos sp = seg_pos(S, K);
+  if (st[2 * sp.sg]) return;
+  H += (size_t)sp.sg * (m + 1) * m;
+  H2 += (size_t)sp.sg * (m + 1) * m;
+  wn0 += sp.sg;
+  info += 2 * sp.sg;
+  st += 2 * sp.sg;
   __shared__ double s_wave[4 * 64];
   __shared__ double s_h[64];
   __shared__ double s_c[64];
   __shared__ double s_p[64];
   __shared__ double s_tmp[256];
   __shared__ double s_Hf[NEXT ? NVM * NVM : 1];
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool act = k < K;
-  const int kc = act ? k : K - 1;  // clamped row: loads need no divergent branch
+  const int k = sp.k;
+  const bool act = k < sp.kend;
+  const int kc = act ? k : sp.kend - 1;  // clamped row: loads need no divergent branch
   // every global load first: the basis row, w, the product A w and the
   // finished columns of the Hessenberg matrix
   double vr[NVM];
@@ -1547,7 +1637,7 @@ __global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* 
       if (t < nH) s_Hf[kk * NVM + i] = h1v[u] + h2v[u];
     }
   }
-  grid_partials_sum(part2, gridDim.x, P, j + 2, s_tmp, s_h);
+  grid_partials_sum(part2, sp.b0, sp.b1, P, j + 2, s_tmp, s_h);
   double h2sq = 0.0;
   for (int i = 0; i <= j; ++i) h2sq += s_h[i] * s_h[i];
   const double hn = sqrt(fmax(s_h[j + 1] - h2sq, 0.0));
@@ -1567,8 +1657,8 @@ __global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* 
     }
   }
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x <= j) H2[threadIdx.x * m + j] = s_h[threadIdx.x];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blockIdx.x == sp.b0 && threadIdx.x <= j) H2[threadIdx.x * m + j] = s_h[threadIdx.x];
+  if (blockIdx.x == sp.b0 && threadIdx.x == 0) {
     H[(j + 1) * m + j] = hn;
     if (brk) { st[0] = 1; info[0] = (double)(j + 1); }
   }
@@ -1638,6 +1728,11 @@ __global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, cons
   extern __shared__ double sm[];
   __shared__ int s_sq, s_piv;
   __shared__ double s_red[256];
+  // one block per solve of a batch
+  H += (size_t)blockIdx.x * (mstride + 1) * mstride;
+  H2 += (size_t)blockIdx.x * (mstride + 1) * mstride;
+  info += 2 * blockIdx.x;
+  y += (size_t)blockIdx.x * (mstride + 1);
   const int mu = (int)info[0];
   if (mu <= 0) return;
   const int n = mu + 1, nn = n * n;
@@ -1762,17 +1857,21 @@ __global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, cons
   for (int i = threadIdx.x; i < mu; i += blockDim.x) y[i] = E[i * n + mu];
 }
 
-// u0 += beta V_m y ; then back to phi coordinates: ut0 = u0 / L00.
+// u0 += beta V_m y ; then back to phi coordinates: ut0 = u0 / L00 (y and
+// beta of the row's solve).
 __global__ __launch_bounds__(256) void k_exp1_update(int K, int V, const double* __restrict__ Vb,
                                                      const double* __restrict__ y, const double* __restrict__ info,
                                                      const double* __restrict__ u0, const double* __restrict__ Lpk,
-                                                     int NT, double* __restrict__ ut0) {
+                                                     int NT, double* __restrict__ ut0, const int* __restrict__ sid,
+                                                     int ystride) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
-  const int mu = (int)info[0];
-  const double beta = info[1];
+  const int sg = sid ? sid[k / V] : 0;
+  const int mu = (int)info[2 * sg];
+  const double beta = info[2 * sg + 1];
+  const double* ys = y + (size_t)sg * ystride;
   double s = 0.0;
-  for (int j = 0; j < mu; ++j) s += Vb[(size_t)j * K + k] * y[j];
+  for (int j = 0; j < mu; ++j) s += Vb[(size_t)j * K + k] * ys[j];
   const double u = u0[k] + beta * s;
   ut0[k] = u / Lpk[(size_t)(k / V) * NT];
 }
@@ -1797,11 +1896,11 @@ __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, siz
 // Uniform free stream as level-p coefficients in psi coordinates:
 // u_{E,v,0} = U_v / psi_0 = U_v L_00 / phi_0.
 __global__ void k_freestream(double* __restrict__ u, int V, int N, const double* __restrict__ Lpk, int NT, double phi0,
-                             Gas gas, int ne) {
+                             Gas gas, int ne, const double* __restrict__ uinf_e) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= ne * V * N) return;
   const int e = id / (V * N), v = (id / N) % V, i = id % N;
-  u[id] = (i == 0) ? gas.Uinf[v] * Lpk[(size_t)e * NT] / phi0 : 0.0;
+  u[id] = (i == 0) ? (uinf_e ? uinf_e[(size_t)e * V + v] : gas.Uinf[v]) * Lpk[(size_t)e * NT] / phi0 : 0.0;
 }
 
 // D = L^{-1} Dt L^{-T} per (v, w) block (tests of the Jacobian in psi
@@ -2183,6 +2282,13 @@ __global__ void k_pad_add(double* __restrict__ x, const double* __restrict__ y, 
   x[(size_t)r * N + i] += y[id];
 }
 
+// Per-element CFL of a batch from the per-solve values.
+__global__ void k_expand_cfl(const double* __restrict__ cfl_s, const int* __restrict__ sid, double* __restrict__ cfl_e,
+                             int ne) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ne) cfl_e[e] = cfl_s[sid[e]];
+}
+
 __global__ void k_fill0(double* __restrict__ x, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = 0.0;
@@ -2229,7 +2335,7 @@ hipError_t residual_t(const DevMesh& M, const TabData& td, const double* ut, con
   constexpr int EB = res_tile<D, P, R>();
   const int grid = (M.ne + EB - 1) / EB;
   hipLaunchKernelGGL((k_residual<D, P, EB, R>), dim3(grid), dim3(256), 0, st, ut, fadd, rt, M.xv, M.nbr, M.ncode,
-                     M.ne, t, gas_as<R>(M.gas));
+                     M.ne, t, gas_as<R>(M.gas), M.uinf_e);
   return hipGetLastError();
 }
 
@@ -2248,7 +2354,7 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
       const int items = M.ne * NPT;
       R* bc = static_cast<R*>(M.bc);
       hipLaunchKernelGGL((k_jac_points<D, P, R>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.nbr,
-                         M.ncode, bc, M.ne, t, gas);
+                         M.ncode, bc, M.ne, t, gas, M.uinf_e);
       hipLaunchKernelGGL((k_jaclu_wave<D, P, R>), dim3((M.ne + 3) / 4), dim3(256), 0, st, bc, M.Gpk, M.NT, dtau,
                          out, perm, fail, M.ne, t);
       return hipGetLastError();
@@ -2259,13 +2365,13 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
     hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
-                       fail, M.ne, t, gas);
+                       fail, M.ne, t, gas, M.uinf_e);
   } else {
     auto kf = k_jacobian<D, P, false, R>;
     hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
-                       fail, M.ne, t, gas);
+                       fail, M.ne, t, gas, M.uinf_e);
   }
   return hipGetLastError();
 }
@@ -2287,6 +2393,11 @@ hipError_t restrict_t(const DevMesh& M, const double* ut, double* uc, double* uc
 
 template <int D, int N>
 hipError_t norm_t(const DevMesh& M, const double* rt, double* part, double* out, hipStream_t st) {
+  if (M.seg_e0) {
+    hipLaunchKernelGGL((k_norm_seg<D, N>), dim3(M.nseg), dim3(256), 0, st, rt, M.Lpk, M.NT, M.seg_e0, M.seg_omega,
+                       out);
+    return hipGetLastError();
+  }
   const int nblk = (M.ne + 255) / 256;
   hipLaunchKernelGGL((k_norm_partial<D, N>), dim3(nblk), dim3(256), 0, st, rt, M.Lpk, M.NT, M.ne, part);
   hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, st, part, nblk, M.omega, out);
@@ -2450,10 +2561,10 @@ hipError_t launch_timestep(const DevMesh& M, int p, int N, double cfl, double mu
   const int grid = (M.ne + 255) / 256;
   if (M.d == 2)
     hipLaunchKernelGGL((k_timestep<2>), dim3(grid), dim3(256), 0, st, ut, N, M.Lpk, M.NT, M.hE, p, cfl, mult, dtau,
-                       M.ne, M.gas.g);
+                       M.ne, M.gas.g, M.cfl_e);
   else
     hipLaunchKernelGGL((k_timestep<3>), dim3(grid), dim3(256), 0, st, ut, N, M.Lpk, M.NT, M.hE, p, cfl, mult, dtau,
-                       M.ne, M.gas.g);
+                       M.ne, M.gas.g, M.cfl_e);
   return hipGetLastError();
 }
 
@@ -2484,10 +2595,10 @@ hipError_t launch_p0_setup(const DevMesh& M, const double* ut0, const double* ft
   const int grid = (M.ne + 127) / 128;
   if (M.d == 2)
     hipLaunchKernelGGL((k_p0_setup<2>), dim3(grid), dim3(128), 0, st, ut0, ft0, M.xv, M.nbr, M.Lpk, M.NT, M.hE, pmax,
-                       cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w);
+                       cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w, M.uinf_e, M.cfl_e);
   else
     hipLaunchKernelGGL((k_p0_setup<3>), dim3(grid), dim3(128), 0, st, ut0, ft0, M.xv, M.nbr, M.Lpk, M.NT, M.hE, pmax,
-                       cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w);
+                       cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w, M.uinf_e, M.cfl_e);
   return hipGetLastError();
 }
 
@@ -2498,28 +2609,30 @@ static int arn_nvm(int need) { return need <= 8 ? 8 : need <= 16 ? 16 : need <= 
 
 template <int NVM>
 static void launch_arn_b(int nblk, hipStream_t s, int K, int m, int j, const double* Vb, double* W,
-                         const double* part1, double* part2, int P, double* H, double* wn0, const int* st) {
-  hipLaunchKernelGGL(k_arn_b<NVM>, dim3(nblk), dim3(256), 0, s, K, m, j, Vb, W, part1, part2, P, H, wn0, st);
+                         const double* part1, double* part2, int P, double* H, double* wn0, const int* st,
+                         ArnSeg S) {
+  hipLaunchKernelGGL(k_arn_b<NVM>, dim3(nblk), dim3(256), 0, s, K, m, j, Vb, W, part1, part2, P, H, wn0, st, S);
 }
 
 template <int V, int NF, bool NEXT, int NVM>
 static void launch_arn_ca(int nblk, hipStream_t s, int K, int m, int j, const int* nbr, const double* Ad,
                           const double* Ao, double* Vb, const double* W, double* Wn, const double* part2,
-                          double* part1, int P, double* H, double* H2, const double* wn0, double* info, int* st) {
+                          double* part1, int P, double* H, double* H2, const double* wn0, double* info, int* st,
+                          ArnSeg S) {
   hipLaunchKernelGGL((k_arn_ca<V, NF, NEXT, NVM>), dim3(nblk), dim3(256), 0, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn,
-                     part2, part1, P, H, H2, wn0, info, st);
+                     part2, part1, P, H, H2, wn0, info, st, S);
 }
 
 template <int V, int NF, bool NEXT>
 static void dispatch_arn_ca(int nvm, int nblk, hipStream_t s, int K, int m, int j, const int* nbr,
                             const double* Ad, const double* Ao, double* Vb, const double* W, double* Wn,
                             const double* part2, double* part1, int P, double* H, double* H2, const double* wn0,
-                            double* info, int* st) {
+                            double* info, int* st, ArnSeg S) {
   switch (nvm) {
-    case 8: launch_arn_ca<V, NF, NEXT, 8>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st); break;
-    case 16: launch_arn_ca<V, NF, NEXT, 16>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st); break;
-    case 32: launch_arn_ca<V, NF, NEXT, 32>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st); break;
-    default: launch_arn_ca<V, NF, NEXT, 48>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st); break;
+    case 8: launch_arn_ca<V, NF, NEXT, 8>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st, S); break;
+    case 16: launch_arn_ca<V, NF, NEXT, 16>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st, S); break;
+    case 32: launch_arn_ca<V, NF, NEXT, 32>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st, S); break;
+    default: launch_arn_ca<V, NF, NEXT, 48>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st, S); break;
   }
 }
 
@@ -2528,49 +2641,51 @@ hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, c
                           double* wn0, double* W2, double* H2, hipStream_t stream) {
   const int K = M.ne * M.V;
   const int P = m + 2;
-  // one thread per row, at most 48 basis vectors held in registers
-  if (nblk != arnoldi_blocks(K) || m < 1 || m > 48) return hipErrorInvalidValue;
+  // one thread per row, at most 48 basis vectors held in registers; a batch
+  // brings its own block tables (every block inside one solve's rows)
+  if ((!M.brow0 && nblk != arnoldi_blocks(K)) || m < 1 || m > 48) return hipErrorInvalidValue;
+  const ArnSeg S{M.brow0, M.brow1, M.bseg, M.sblk0};
   double* W[2] = {W2, W2 + K};
-  hipLaunchKernelGGL(k_arn_beta, dim3(nblk), dim3(256), 0, stream, K, b, part1, P, st);
-  hipLaunchKernelGGL(k_arn_start, dim3(nblk), dim3(256), 0, stream, K, m, b, part1, P, Vb, info, st);
-  if (M.d == 2) hipLaunchKernelGGL((k_arn_a<4, 4>), dim3(nblk), dim3(256), 0, stream, K, M.nbr, Ad, Ao, Vb, W[0], part1, P, st);
-  else hipLaunchKernelGGL((k_arn_a<5, 6>), dim3(nblk), dim3(256), 0, stream, K, M.nbr, Ad, Ao, Vb, W[0], part1, P, st);
+  hipLaunchKernelGGL(k_arn_beta, dim3(nblk), dim3(256), 0, stream, K, b, part1, P, st, S);
+  hipLaunchKernelGGL(k_arn_start, dim3(nblk), dim3(256), 0, stream, K, m, b, part1, P, Vb, info, st, S);
+  if (M.d == 2) hipLaunchKernelGGL((k_arn_a<4, 4>), dim3(nblk), dim3(256), 0, stream, K, M.nbr, Ad, Ao, Vb, W[0], part1, P, st, S);
+  else hipLaunchKernelGGL((k_arn_a<5, 6>), dim3(nblk), dim3(256), 0, stream, K, M.nbr, Ad, Ao, Vb, W[0], part1, P, st, S);
   for (int j = 0; j < m; ++j) {
     double* Wc = W[j & 1];
     double* Wn = W[(j + 1) & 1];
     switch (arn_nvm(j + 1)) {
-      case 8: launch_arn_b<8>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st); break;
-      case 16: launch_arn_b<16>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st); break;
-      case 32: launch_arn_b<32>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st); break;
-      default: launch_arn_b<48>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st); break;
+      case 8: launch_arn_b<8>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
+      case 16: launch_arn_b<16>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
+      case 32: launch_arn_b<32>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
+      default: launch_arn_b<48>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
     }
     const bool next = (j + 1 < m);
     const int nvm = arn_nvm(next ? j + 2 : j + 1);
     if (M.d == 2) {
-      if (next) dispatch_arn_ca<4, 4, true>(nvm, nblk, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
-      else dispatch_arn_ca<4, 4, false>(nvm, nblk, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
+      if (next) dispatch_arn_ca<4, 4, true>(nvm, nblk, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st, S);
+      else dispatch_arn_ca<4, 4, false>(nvm, nblk, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st, S);
     } else {
-      if (next) dispatch_arn_ca<5, 6, true>(nvm, nblk, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
-      else dispatch_arn_ca<5, 6, false>(nvm, nblk, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st);
+      if (next) dispatch_arn_ca<5, 6, true>(nvm, nblk, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st, S);
+      else dispatch_arn_ca<5, 6, false>(nvm, nblk, stream, K, m, j, M.nbr, Ad, Ao, Vb, Wc, Wn, part2, part1, P, H, H2, wn0, info, st, S);
     }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_phi1(int m, const double* H, const double* H2, const double* info, double* y, int* fail,
+hipError_t launch_phi1(int m, int nseg, const double* H, const double* H2, const double* info, double* y, int* fail,
                        hipStream_t st) {
   const size_t lds = (size_t)8 * (m + 1) * (m + 1) * 8;
   hipError_t e = hipFuncSetAttribute((const void*)k_phi1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_phi1, dim3(1), dim3(256), lds, st, H, H2, m, info, y, fail);
+  hipLaunchKernelGGL(k_phi1, dim3(nseg), dim3(256), lds, st, H, H2, m, info, y, fail);
   return hipGetLastError();
 }
 
-hipError_t launch_exp1_update(const DevMesh& M, const double* Vb, const double* y, const double* info,
+hipError_t launch_exp1_update(const DevMesh& M, int m, const double* Vb, const double* y, const double* info,
                               const double* u0, double* ut0, hipStream_t st) {
   const int K = M.ne * M.V;
   hipLaunchKernelGGL(k_exp1_update, dim3((K + 255) / 256), dim3(256), 0, st, K, M.V, Vb, y, info, u0, M.Lpk, M.NT,
-                     ut0);
+                     ut0, M.sid, m + 1);
   return hipGetLastError();
 }
 
@@ -2596,7 +2711,7 @@ hipError_t launch_freestream(const DevMesh& M, int N, double* u, hipStream_t st)
   const int cnt = M.ne * M.V * N;
   const double phi0 = (M.d == 2) ? 0.5 : 0.35355339059327373;
   hipLaunchKernelGGL(k_freestream, dim3((cnt + 255) / 256), dim3(256), 0, st, u, M.V, N, M.Lpk, M.NT, phi0, M.gas,
-                     M.ne);
+                     M.ne, M.uinf_e);
   return hipGetLastError();
 }
 
@@ -2631,7 +2746,7 @@ hipError_t jac_points_only_t(const DevMesh& M, const TabData& td, const double* 
   constexpr int NPT = C::QV + C::NF * C::QF;
   const int items = M.ne * NPT;
   hipLaunchKernelGGL((k_jac_points<D, P, double>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.nbr,
-                     M.ncode, bc, M.ne, t, M.gas);
+                     M.ncode, bc, M.ne, t, M.gas, M.uinf_e);
   return hipGetLastError();
 }
 
@@ -2762,6 +2877,11 @@ hipError_t launch_trunc(const double* x, double* y, int N, int Nc, int rows, hip
 hipError_t launch_pad_add(double* x, const double* y, int N, int Nc, int rows, hipStream_t st) {
   const int cnt = rows * Nc;
   hipLaunchKernelGGL(k_pad_add, dim3((cnt + 255) / 256), dim3(256), 0, st, x, y, N, Nc, rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_cfl(const DevMesh& M, const double* cfl_s, hipStream_t st) {
+  hipLaunchKernelGGL(k_expand_cfl, dim3((M.ne + 255) / 256), dim3(256), 0, st, cfl_s, M.sid, M.cfl_e, M.ne);
   return hipGetLastError();
 }
 

@@ -24,6 +24,18 @@ struct DevMesh {
   double* g2x = nullptr;   // 2-point Gauss rule (p = 0 faces)
   double* g2w = nullptr;
   void* bc = nullptr;      // pointwise flux-Jacobian scratch of the block assembly (FP64 or FP32)
+  // batched solves (null for a single solve): per-element free stream [E][V]
+  // and CFL [E]; solve segments (element ranges) and Arnoldi block tables
+  double* uinf_e = nullptr;
+  double* cfl_e = nullptr;
+  int nseg = 1;
+  int* sid = nullptr;        // [E] solve of each element
+  int* seg_e0 = nullptr;     // [nseg + 1] first element of each solve
+  double* seg_omega = nullptr;  // [nseg] |Omega| of each solve
+  int* brow0 = nullptr;      // [nblk] first row of each Arnoldi block
+  int* brow1 = nullptr;      // [nblk] end row of each Arnoldi block
+  int* bseg = nullptr;       // [nblk] solve of each Arnoldi block
+  int* sblk0 = nullptr;      // [nseg + 1] first Arnoldi block of each solve
 };
 
 // arithmetic precision of a smoother kernel
@@ -62,9 +74,9 @@ int arnoldi_blocks(int K);
 hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, const double* Ao, const double* b,
                           double* Vb, double* H, double* part1, double* part2, double* info, int* st, double* wn0,
                           double* W2, double* H2, hipStream_t stream);
-hipError_t launch_phi1(int m, const double* H, const double* H2, const double* info, double* y, int* fail,
+hipError_t launch_phi1(int m, int nseg, const double* H, const double* H2, const double* info, double* y, int* fail,
                        hipStream_t st);
-hipError_t launch_exp1_update(const DevMesh& M, const double* Vb, const double* y, const double* info,
+hipError_t launch_exp1_update(const DevMesh& M, int m, const double* Vb, const double* y, const double* info,
                               const double* u0, double* ut0, hipStream_t st);
 hipError_t launch_nbr_export(const DevMesh& M, int* out, hipStream_t st);
 hipError_t launch_copy(const double* a, double* b, size_t n, hipStream_t st);
@@ -87,6 +99,7 @@ hipError_t launch_adj_p0_rhs(const DevMesh& M, const double* gt0, const double* 
 hipError_t launch_trunc(const double* x, double* y, int N, int Nc, int rows, hipStream_t st);
 hipError_t launch_pad_add(double* x, const double* y, int N, int Nc, int rows, hipStream_t st);
 hipError_t launch_fill0(double* x, size_t n, hipStream_t st);
+hipError_t launch_expand_cfl(const DevMesh& M, const double* cfl_s, hipStream_t st);
 int sum_blocks(size_t n);
 hipError_t launch_sum(const double* x, const double* y, size_t n, double* part, int take_sqrt, double* out,
                       hipStream_t st);
