@@ -186,6 +186,70 @@ def mixed_measurements(P, mesh, p, dof, args, fp64_ms):
             "phase_a_speedup_vs_fp64": round(fp64_ms / ms_a, 3), "phase_b_speedup_vs_fp64": round(fp64_ms / ms_b, 3)}
 
 
+def batched_measurements(P, steps, budget_s, precision="mixed"):
+    """The batched workload: 64 independent cylinder solves drawn from seed
+    1807 (N_theta ~ U{16..96}, N_r = N_theta / 2, p ~ U{1..4}, Ma ~ U[0.1,
+    0.4], alpha ~ U[-5, 5] deg), one batch handle per order (every kernel
+    launch covers all solves of that order).  Reports the V-cycle
+    throughput of the whole batch and, within a time budget, how many solves
+    reach the 1e-10 drop."""
+    import torch
+    from eg_inputs import batch_draws, ogrid
+    draws = batch_draws(64, seed=1807)
+    groups = {}
+    for i, d in enumerate(draws):
+        groups.setdefault(d["p"], []).append(i)
+    t_init = time.perf_counter()
+    handles = {}
+    for p, idx in sorted(groups.items()):
+        meshes = [ogrid(draws[i]["n_theta"], draws[i]["n_r"]) for i in idx]
+        B = P.BatchSolver(meshes, p, [draws[i]["mach"] for i in idx], [draws[i]["alpha_deg"] for i in idx],
+                          rk_stages=3, cfl_max=10.0, krylov_m=30, precision=precision)
+        handles[p] = (B, B.freestream(p), idx)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t_init
+    dof = sum(B.n_elem * B.V * B.N(p) for p, (B, _, _) in handles.items())
+    for p, (B, u, _) in handles.items():
+        B.solve(u, drop_tol=0.0, max_cycles=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, (B, u, _) in handles.items():
+        B.solve(u, drop_tol=0.0, max_cycles=steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"solves": 64, "elements": int(sum(B.n_elem for B, _, _ in handles.values())), "dof": int(dof),
+           "groups": {str(p): len(idx) for p, (_, _, idx) in handles.items()}, "precision": precision,
+           "setup_s": round(t_init, 3), "ms_per_batched_cycle": round(wall / steps * 1e3, 3),
+           "dof_updates_per_s": dof * steps / wall}
+    log(f"[bench] batched: {out}")
+    # convergence within the budget: each order group from its free streams
+    import numpy as np
+    conv, div, drops = 0, 0, []
+    t1 = time.perf_counter()
+    for p, (B, _, idx) in sorted(handles.items()):
+        left = budget_s - (time.perf_counter() - t1)
+        if left <= 0:
+            break
+        u = B.freestream(p)
+        # cycle cap from the measured cost so the group fits its share of the budget
+        cap = max(10, int(left / len(handles) / max(wall / steps / len(handles), 1e-4)))
+        hists, cyc, st = B.solve(u, drop_tol=1e-10, max_cycles=cap)
+        ok = sum(1 for h in hists if h[-1] <= 1e-10 * h[0])
+        bad = sum(1 for h in hists if not np.isfinite(h[-1]))
+        conv += ok
+        div += bad
+        drops += [float(h[-1] / h[0]) for h in hists if np.isfinite(h[-1])]
+        log(f"[bench] batched p={p}: {ok}/{len(hists)} converged, {bad} diverged, cap {cap} cycles, "
+            f"{time.perf_counter() - t1:.1f}s")
+    out["converged_to_1e-10"] = conv
+    out["diverged"] = div
+    out["median_drop_reached"] = float(np.median(drops)) if drops else None
+    out["convergence_run_s"] = round(time.perf_counter() - t1, 2)
+    for B, _, _ in handles.values():
+        B.close()
+    return out
+
+
 def c1_time_to_drop(P):
     """Time to a 1e-10 FP64 residual drop on the O-grid 24 x 12, p = 1 solve
     (s = 4, CFL_max = 100, m = 30), which converges, in FP64 and mixed."""
@@ -216,6 +280,8 @@ def main():
     ap.add_argument("--drop-budget", type=float, default=60.0,
                     help="seconds cap of each (FP64, mixed) time-to-1e-10 run on the benchmark mesh")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision measurements")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-solve batched workload")
+    ap.add_argument("--batch-budget", type=float, default=30.0, help="seconds cap of the batched convergence run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-drop", action="store_true", help="skip the time-to-1e-10 run")
     ap.add_argument("--calibrate", action="store_true",
@@ -288,6 +354,8 @@ def main():
             del Sm
         mixed["c1_time_to_1e-10"] = c1_time_to_drop(P)
         extras["mixed"] = mixed
+    if not args.no_batched:
+        extras["batched"] = batched_measurements(P, 10, args.batch_budget)
     if args.calibrate:
         nb = 256 << 20
         x = torch.ones(nb // 8, dtype=torch.float64, device="cuda")

@@ -197,7 +197,10 @@ eg_status eg_layout(const eg_handle* h, int solve, int p, int64_t* offset, int* 
  * [n_solves][max_cycles + 1]: solve s's norms r_1, r_2, ... up to the cycle
  * it reached the drop, which n_cycles_host[s] receives.  Converged solves
  * keep being cycled (they sit at their fixed point) until all are done.
- * Returns EG_OK when all converged, EG_ERR_NOT_CONVERGED, EG_ERR_DIVERGED. */
+ * A solve whose norm becomes non-finite is marked diverged (its history
+ * ends there) and the others continue; its values never reach the other
+ * solves.  Returns EG_OK when all converged, else EG_ERR_DIVERGED if any
+ * diverged, else EG_ERR_NOT_CONVERGED. */
 eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
                          int* n_cycles_host);
 

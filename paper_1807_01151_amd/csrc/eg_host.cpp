@@ -1296,10 +1296,11 @@ eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_c
     HIPCHK(h, hipMemcpyAsync(h->hpin + 1, h->dfail, sizeof(int), hipMemcpyDeviceToHost, h->st));
     st = sync_status(h);
     if (st != EG_OK) break;
-    int fl = 0;
-    std::memcpy(&fl, h->hpin + 1, sizeof(int));
-    if (fl) { st = fail(h, EG_ERR_DIVERGED, "singular pivot in a block factorisation or in phi_1"); break; }
-    bool all = true, bad = false;
+    // A solve whose norm is not finite has diverged: it is recorded and
+    // left alone (its values stay inside its own elements and Krylov
+    // segment); the others go on.  The shared pivot-failure flag is not
+    // decisive here for the same reason.
+    bool all = true;
     double worst = 0.0;
     for (int sg = 0; sg < nseg; ++sg) {
       const double rn = h->hnorm[sg];
@@ -1307,20 +1308,31 @@ eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_c
       if (!done[sg]) {
         hist_host[(size_t)sg * (max_cycles + 1) + (n - 1)] = rn;
         n_cycles_host[sg] = n - 1;
-        if (rn <= drop_tol * r1[sg]) done[sg] = 1;
+        if (!std::isfinite(rn)) done[sg] = 2;
+        else if (rn <= drop_tol * r1[sg]) done[sg] = 1;
       }
-      if (!std::isfinite(rn)) bad = true;
       all = all && done[sg];
-      worst = std::max(worst, rn / r1[sg]);
-      if (!(rn >= rmin[sg])) { rmin[sg] = rn; nmin[sg] = n; }
-      h->hcfl[sg] = cfl_ramp(h->cfl_max, rn, h->relr ? r1[sg] : 1.0, n, pm);
+      if (done[sg] != 2) {
+        worst = std::max(worst, rn / r1[sg]);
+        if (!(rn >= rmin[sg])) { rmin[sg] = rn; nmin[sg] = n; }
+      }
+      h->hcfl[sg] = std::isfinite(rn) ? cfl_ramp(h->cfl_max, rn, h->relr ? r1[sg] : 1.0, n, pm) : 1.0;
     }
-    if (bad) { st = fail(h, EG_ERR_DIVERGED, "non-finite residual norm"); break; }
-    if (all) break;
-    if (n - 1 == max_cycles) { st = fail(h, EG_ERR_NOT_CONVERGED, "max_cycles reached"); break; }
+    if (all) {
+      for (int sg = 0; sg < nseg; ++sg)
+        if (done[sg] == 2) st = fail(h, EG_ERR_DIVERGED, "a solve of the batch diverged (non-finite norm)");
+      break;
+    }
+    if (n - 1 == max_cycles) {
+      bool div = false;
+      for (int sg = 0; sg < nseg; ++sg) div = div || done[sg] == 2;
+      st = fail(h, div ? EG_ERR_DIVERGED : EG_ERR_NOT_CONVERGED,
+                div ? "a solve of the batch diverged (non-finite norm)" : "max_cycles reached");
+      break;
+    }
     if (h->mixed && !phase_b) {
       bool stall = false;
-      for (int sg = 0; sg < nseg; ++sg) stall = stall || (!done[sg] && n - nmin[sg] >= EG_STALL_CYCLES);
+      for (int sg = 0; sg < nseg; ++sg) stall = stall || (done[sg] == 0 && n - nmin[sg] >= EG_STALL_CYCLES);
       if (worst <= EG_PHASE_B_DROP || stall) phase_b = 1;
     }
     h->phase_b = phase_b;

@@ -108,5 +108,5 @@ def test_steady_drag_gradient_matches_finite_differences():
         cp = Sp.drag(prob.steady(Sp), sref=prob.sref)
         cm = Sm.drag(prob.steady(Sm), sref=prob.sref)
         fd[i] = (cp - cm) / (2 * h)
-    print("C_D", float(cd), "adjoint gradient", grad, "FD", fd, flush=True)
+    print("C_D", cd.item(), "adjoint gradient", grad, "FD", fd, flush=True)
     assert np.all(np.abs(grad - fd) <= 1e-5 * np.abs(fd) + 1e-9)
