@@ -719,7 +719,7 @@ __device__ __forceinline__ float readlane_d(float x, int lane) {
 }
 
 template <int D, int P, class R>
-__global__ __launch_bounds__(256) void k_jaclu_wave(const R* __restrict__ BC, const double* __restrict__ Gpk,
+__global__ __launch_bounds__(256, 2) void k_jaclu_wave(const R* __restrict__ BC, const double* __restrict__ Gpk,
                                                     int NT, const double* __restrict__ dtau, R* __restrict__ out,
                                                     int* __restrict__ perm, int* __restrict__ fail, int ne,
                                                     Tab<D, P, R> tab) {
