@@ -174,6 +174,15 @@ eg_status eg_solve_steady(eg_handle* h, double* u_dev, double drop_tol, int max_
 eg_status eg_solve_resume(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
                           int* n_cycles_host);
 
+/* Graph replay (enable != 0): the steady-solve entries (eg_solve_steady,
+ * eg_solve_resume, eg_solve_batch) capture the V-cycle below the entry norm
+ * once (one graph per mixed-precision phase) into a HIP graph on an
+ * internal stream of the handle, ordered after and before the handle's
+ * stream by events, and replay it every cycle; the CFL of each cycle is
+ * read from device memory.  Results are identical to the eager launches.
+ * Off by default; profiling (eg_profile) runs eagerly. */
+eg_status eg_set_graphs(eg_handle* h, int enable);
+
 /* ---- Batched independent solves ----
  * n_solves steady problems (Section 2.4 eMG each) in one handle: meshes of
  * any size with the same dim, p_max, rk_stages, krylov_m, cfl_max,

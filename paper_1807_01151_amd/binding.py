@@ -15,6 +15,7 @@ EXPORTED_SYMBOLS = (
     "eg_timestep", "eg_element_jacobian", "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm",
     "eg_vcycle", "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read",
     "eg_drag", "eg_adjoint_apply", "eg_adjoint_solve", "eg_init_batch", "eg_layout", "eg_solve_batch",
+    "eg_set_graphs",
 )
 
 KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
@@ -77,6 +78,7 @@ def lib():
         L.eg_profile.argtypes = [vp, i]
         L.eg_profile_read.argtypes = [vp, i, i, pd, C.POINTER(i)]
         L.eg_drag.argtypes = [vp, vp, pd, d, pd, vp]
+        L.eg_set_graphs.argtypes = [vp, i]
         L.eg_init_batch.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), i, vp, C.POINTER(vp)]
         L.eg_layout.argtypes = [vp, i, i, C.POINTER(C.c_int64), C.POINTER(i), C.POINTER(i)]
         L.eg_solve_batch.argtypes = [vp, vp, d, i, pd, C.POINTER(i)]
@@ -212,6 +214,10 @@ class Solver:
     def profile(self, enable: bool):
         self._chk(lib().eg_profile(self._h, int(enable)))
 
+    def set_graphs(self, enable: bool):
+        """Replay the V-cycle as a captured HIP graph in the steady solves."""
+        self._chk(lib().eg_set_graphs(self._h, int(enable)))
+
     def profile_read(self, kernel_class: str, p: int = -1):
         """(total milliseconds, launches) of one kernel class at level p (-1: all)."""
         ms = C.c_double(0.0)
@@ -320,6 +326,7 @@ class BatchSolver:
 
     close = Solver.close
     __del__ = Solver.__del__
+    set_graphs = Solver.set_graphs
     _chk = Solver._chk
     N = Solver.N
     empty = Solver.empty

@@ -97,6 +97,14 @@ struct eg_handle {
   std::vector<int> seg_e0;   // host copy of the element ranges
   double* dcfl = nullptr;    // [nseg] device CFL per solve
   double* cfl_e_buf = nullptr;  // [E] per-element CFL (bound to M.cfl_e only inside eg_solve_batch)
+  // graph replay of the V-cycle below the entry norm (eg_set_graphs)
+  bool graphs = false;
+  hipStream_t gst = nullptr;          // internal capture stream (non-default, default priority)
+  hipEvent_t gev = nullptr;
+  hipGraph_t ggraph[2] = {};          // per mixed-precision phase
+  hipGraphExec_t gexec[2] = {};
+  double* dcfl1 = nullptr;            // device CFL scalar read by the captured kernels
+  double* hcfl1 = nullptr;            // pinned
   double* hcfl = nullptr;    // [nseg] pinned
   double* hnorm = nullptr;   // [nseg] pinned
 };
@@ -876,9 +884,11 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
   AL(h->dpart, ne);
   AL(h->spart, 256);
   AL(h->sout, 1);
+  AL(h->dcfl1, 1);
 #undef AL
   {
     hipError_t e = hipHostMalloc((void**)&h->hpin, 64, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&h->hcfl1, sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess && bd) e = hipHostMalloc((void**)&h->hcfl, sizeof(double) * nseg, hipHostMallocDefault);
     if (e == hipSuccess && bd) e = hipHostMalloc((void**)&h->hnorm, sizeof(double) * nseg, hipHostMallocDefault);
     if (e != hipSuccess) { h->err = "hipHostMalloc failed"; return EG_ERR_ALLOC; }
@@ -910,9 +920,88 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
   return EG_OK;
 }
 
+// One V-cycle below the entry norm (rt[p_max] holds the entry residual):
+// eagerly, or by replaying a captured graph of it.  The graph reads the CFL
+// from device memory (per element in a batch, else the scalar dcfl1), so one
+// capture per mixed-precision phase serves every cycle; everything else it
+// touches is handle-owned and fixed.
+eg_status vcycle_run(eg_handle* h, double cfl) {
+  if (!h->graphs || h->prof) return vc_rec(h, h->pmax, cfl);
+  if (!h->batch) {
+    h->hcfl1[0] = cfl;
+    HIPCHK(h, hipMemcpyAsync(h->dcfl1, h->hcfl1, sizeof(double), hipMemcpyHostToDevice, h->st));
+  }
+  const int g = h->mixed && h->phase_b ? 1 : 0;
+  if (!h->gexec[g]) {
+    if (!h->batch) h->M.cfl_one = h->dcfl1;
+    HIPCHK(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+    eg_status st = vc_rec(h, h->pmax, cfl);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(h->st, &graph);
+    h->M.cfl_one = nullptr;
+    if (st != EG_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return hipfail(h, e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hipfail(h, e, "hipGraphInstantiate");
+    }
+    h->ggraph[g] = graph;
+    h->gexec[g] = ex;
+  }
+  HIPCHK(h, hipGraphLaunch(h->gexec[g], h->st));
+  return EG_OK;
+}
+
+// Solve loops in graph mode run on the handle's internal stream, ordered
+// after the caller's stream on entry and before it on exit.
+struct StreamSwap {
+  eg_handle* h;
+  hipStream_t caller;
+  bool on = false;
+  eg_status begin() {
+    caller = h->st;
+    if (!h->graphs || h->prof) return EG_OK;
+    if (!h->gst) {
+      HIPCHK(h, hipStreamCreateWithFlags(&h->gst, hipStreamNonBlocking));
+      HIPCHK(h, hipEventCreateWithFlags(&h->gev, hipEventDisableTiming));
+    }
+    HIPCHK(h, hipEventRecord(h->gev, caller));
+    HIPCHK(h, hipStreamWaitEvent(h->gst, h->gev, 0));
+    h->st = h->gst;
+    on = true;
+    return EG_OK;
+  }
+  void end() {
+    if (!on) return;
+    (void)hipEventRecord(h->gev, h->gst);
+    (void)hipStreamWaitEvent(caller, h->gev, 0);
+    h->st = caller;
+    on = false;
+  }
+  ~StreamSwap() { end(); }
+};
+
+// Binds the batch's per-element CFL array for the duration of a batch solve.
+struct CflBind {
+  eg_handle* h;
+  explicit CflBind(eg_handle* hh) : h(hh) { h->M.cfl_e = h->cfl_e_buf; }
+  ~CflBind() { h->M.cfl_e = nullptr; }
+};
+
 }  // namespace
 
 extern "C" {
+
+eg_status eg_set_graphs(eg_handle* h, int enable) {
+  if (!h) return EG_ERR_ARG;
+  h->graphs = enable != 0;
+  return EG_OK;
+}
 
 eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stream, eg_handle** out) {
   if (!out) return EG_ERR_ARG;
@@ -1000,6 +1089,13 @@ void eg_free(eg_handle* h) {
   for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->hpin) (void)hipHostFree(h->hpin);
   if (h->hcfl) (void)hipHostFree(h->hcfl);
+  if (h->hcfl1) (void)hipHostFree(h->hcfl1);
+  for (int i = 0; i < 2; ++i) {
+    if (h->gexec[i]) (void)hipGraphExecDestroy(h->gexec[i]);
+    if (h->ggraph[i]) (void)hipGraphDestroy(h->ggraph[i]);
+  }
+  if (h->gev) (void)hipEventDestroy(h->gev);
+  if (h->gst) (void)hipStreamDestroy(h->gst);
   if (h->hnorm) (void)hipHostFree(h->hnorm);
   delete h;
 }
@@ -1158,8 +1254,20 @@ eg_status eg_vcycle(eg_handle* h, double* u_dev, int n, double rref, double* rn_
 namespace {
 // Cycles n = n0, n0 + 1, ...: entry norm, stop test, V-cycle.  r1 < 0 means
 // "take r_1 from this call's first norm".
+eg_status solve_loop_body(eg_handle* h, double* u_dev, int n0, double r1, double drop_tol, int max_cycles,
+                          double* hist_host, int* n_cycles_host);
+
 eg_status solve_loop(eg_handle* h, double* u_dev, int n0, double r1, double drop_tol, int max_cycles,
                      double* hist_host, int* n_cycles_host) {
+  StreamSwap sw{h, h->st};
+  ECHK(sw.begin());
+  eg_status st = solve_loop_body(h, u_dev, n0, r1, drop_tol, max_cycles, hist_host, n_cycles_host);
+  sw.end();
+  return st;
+}
+
+eg_status solve_loop_body(eg_handle* h, double* u_dev, int n0, double r1, double drop_tol, int max_cycles,
+                          double* hist_host, int* n_cycles_host) {
   const int N = nmodes_of(h->M.d, h->pmax);
   HIPCHK(h, eg::launch_basis(h->M, N, u_dev, h->ut[h->pmax], 0, h->st));
   eg_status st = EG_OK;
@@ -1181,7 +1289,7 @@ eg_status solve_loop(eg_handle* h, double* u_dev, int n0, double r1, double drop
       if (rn <= EG_PHASE_B_DROP * r1 || n - h->sv_nmin >= EG_STALL_CYCLES) h->sv_phase_b = 1;
     }
     h->phase_b = h->sv_phase_b;
-    st = vc_rec(h, h->pmax, cfl);
+    st = vcycle_run(h, cfl);
     if (st != EG_OK) break;
   }
   hipError_t e = eg::launch_basis(h->M, N, h->ut[h->pmax], u_dev, 1, h->st);
@@ -1278,7 +1386,9 @@ eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_c
   if (!h->batch) return fail(h, EG_ERR_ARG, "not a batch handle (eg_init_batch)");
   if (!eg::jacobian_supported(h->M.d, h->pmax) && h->pmax > 0)
     return fail(h, EG_ERR_UNSUPPORTED, "element block too large");
-  h->M.cfl_e = h->cfl_e_buf;  // per-solve CFL for the duration of the batch solve
+  StreamSwap sw{h, h->st};
+  ECHK(sw.begin());
+  CflBind cb(h);  // per-solve CFL for the duration of the batch solve
   const DevMesh& M = h->M;
   const int nseg = M.nseg, pm = h->pmax, N = nmodes_of(M.d, pm);
   std::vector<double> r1(nseg, -1.0), rmin(nseg, HUGE_VAL);
@@ -1338,14 +1448,13 @@ eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_c
     h->phase_b = phase_b;
     HIPCHK(h, hipMemcpyAsync(h->dcfl, h->hcfl, sizeof(double) * nseg, hipMemcpyHostToDevice, h->st));
     HIPCHK(h, eg::launch_expand_cfl(M, h->dcfl, h->st));
-    st = vc_rec(h, pm, h->cfl_max);
+    st = vcycle_run(h, h->cfl_max);
     if (st != EG_OK) break;
   }
   hipError_t e = eg::launch_basis(M, N, h->ut[pm], u_dev, 1, h->st);
   if (e != hipSuccess && st == EG_OK) st = hipfail(h, e, "basis");
   hipError_t e2 = hipStreamSynchronize(h->st);
   if (e2 != hipSuccess && st == EG_OK) st = hipfail(h, e2, "sync");
-  h->M.cfl_e = nullptr;
   return st;
 }
 

@@ -1056,7 +1056,7 @@ template <int D>
 __global__ __launch_bounds__(256) void k_timestep(const double* __restrict__ ut, int N, const double* __restrict__ Lpk,
                                                   int NT, const double* __restrict__ hE, int p, double cfl, double mult,
                                                   double* __restrict__ dtau, int ne, double g,
-                                                  const double* __restrict__ cfl_e) {
+                                                  const double* __restrict__ cfl_e, int cfl_stride) {
   constexpr int V = D + 2;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
@@ -1085,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_timestep(const double* __restrict__ ut,
 #pragma unroll
   for (int a = 0; a < D; ++a) q2 += (U[1 + a] / U[0]) * (U[1 + a] / U[0]);
   const double c = sqrt(g * pressure<D>(U, g) / U[0]);
-  dtau[e] = mult * (cfl_e ? cfl_e[e] : cfl) * hE[e] / ((2.0 * p + 1.0) * (sqrt(q2) + c));
+  dtau[e] = mult * (cfl_e ? cfl_e[(size_t)cfl_stride * e] : cfl) * hE[e] / ((2.0 * p + 1.0) * (sqrt(q2) + c));
 }
 
 // ---------------------------------------------------------------------------
@@ -1180,7 +1180,8 @@ __global__ __launch_bounds__(128) void k_p0_setup(const double* __restrict__ ut0
                                                   double* __restrict__ bvec, double* __restrict__ Ad,
                                                   double* __restrict__ Ao, double* __restrict__ dtout, int ne, Gas gas,
                                                   const double* __restrict__ gx, const double* __restrict__ gw,
-                                                  const double* __restrict__ uinf_e, const double* __restrict__ cfl_e) {
+                                                  const double* __restrict__ uinf_e, const double* __restrict__ cfl_e,
+                                                  int cfl_stride) {
   constexpr int V = D + 2, NF = 2 * D, NC = 1 << D, QF = 1 << (D - 1);
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
@@ -1198,7 +1199,7 @@ __global__ __launch_bounds__(128) void k_p0_setup(const double* __restrict__ ut0
 #pragma unroll
     for (int a = 0; a < D; ++a) q2 += (U[1 + a] / U[0]) * (U[1 + a] / U[0]);
     const double c = sqrt(gas.g * pressure<D>(U, gas.g) / U[0]);
-    const double ce = cfl_e ? cfl_e[e] : cfl;
+    const double ce = cfl_e ? cfl_e[(size_t)cfl_stride * e] : cfl;
     dt = (pmax + 1.0) * ce * hE[e] / ((2.0 * pmax + 1.0) * (sqrt(q2) + c));
   }
   double R[V], Jd[V * V];
@@ -2362,14 +2363,22 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
   }
   if (factor) {
     auto kf = k_jacobian<D, P, true, R>;
-    hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+    static bool attr = false;  // set once: not a stream operation, so also fine while capturing
+    if (!attr) {
+      hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
     hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
                        fail, M.ne, t, gas, M.uinf_e);
   } else {
     auto kf = k_jacobian<D, P, false, R>;
-    hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+    static bool attr = false;
+    if (!attr) {
+      hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
     hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
                        fail, M.ne, t, gas, M.uinf_e);
   }
@@ -2556,15 +2565,20 @@ hipError_t launch_prolong(int N, int Nc, int rows, double* ut, const double* uc,
   return hipGetLastError();
 }
 
+// CFL source of the time-step kernels: a per-element array (batch), a
+// device scalar (captured V-cycles), or the host value passed by argument.
+static const double* cfl_ptr(const DevMesh& M) { return M.cfl_e ? M.cfl_e : M.cfl_one; }
+static int cfl_stride(const DevMesh& M) { return M.cfl_e ? 1 : 0; }
+
 hipError_t launch_timestep(const DevMesh& M, int p, int N, double cfl, double mult, const double* ut, double* dtau,
                            hipStream_t st) {
   const int grid = (M.ne + 255) / 256;
   if (M.d == 2)
     hipLaunchKernelGGL((k_timestep<2>), dim3(grid), dim3(256), 0, st, ut, N, M.Lpk, M.NT, M.hE, p, cfl, mult, dtau,
-                       M.ne, M.gas.g, M.cfl_e);
+                       M.ne, M.gas.g, cfl_ptr(M), cfl_stride(M));
   else
     hipLaunchKernelGGL((k_timestep<3>), dim3(grid), dim3(256), 0, st, ut, N, M.Lpk, M.NT, M.hE, p, cfl, mult, dtau,
-                       M.ne, M.gas.g, M.cfl_e);
+                       M.ne, M.gas.g, cfl_ptr(M), cfl_stride(M));
   return hipGetLastError();
 }
 
@@ -2595,10 +2609,10 @@ hipError_t launch_p0_setup(const DevMesh& M, const double* ut0, const double* ft
   const int grid = (M.ne + 127) / 128;
   if (M.d == 2)
     hipLaunchKernelGGL((k_p0_setup<2>), dim3(grid), dim3(128), 0, st, ut0, ft0, M.xv, M.nbr, M.Lpk, M.NT, M.hE, pmax,
-                       cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w, M.uinf_e, M.cfl_e);
+                       cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w, M.uinf_e, cfl_ptr(M), cfl_stride(M));
   else
     hipLaunchKernelGGL((k_p0_setup<3>), dim3(grid), dim3(128), 0, st, ut0, ft0, M.xv, M.nbr, M.Lpk, M.NT, M.hE, pmax,
-                       cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w, M.uinf_e, M.cfl_e);
+                       cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w, M.uinf_e, cfl_ptr(M), cfl_stride(M));
   return hipGetLastError();
 }
 
@@ -2675,8 +2689,12 @@ hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, c
 hipError_t launch_phi1(int m, int nseg, const double* H, const double* H2, const double* info, double* y, int* fail,
                        hipStream_t st) {
   const size_t lds = (size_t)8 * (m + 1) * (m + 1) * 8;
-  hipError_t e = hipFuncSetAttribute((const void*)k_phi1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
+  static size_t attr_lds = 0;  // largest size set so far
+  if (lds > attr_lds) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_phi1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_lds = lds;
+  }
   hipLaunchKernelGGL(k_phi1, dim3(nseg), dim3(256), lds, st, H, H2, m, info, y, fail);
   return hipGetLastError();
 }

@@ -28,6 +28,7 @@ struct DevMesh {
   // and CFL [E]; solve segments (element ranges) and Arnoldi block tables
   double* uinf_e = nullptr;
   double* cfl_e = nullptr;
+  double* cfl_one = nullptr;  // device scalar CFL (bound while a V-cycle is captured)
   int nseg = 1;
   int* sid = nullptr;        // [E] solve of each element
   int* seg_e0 = nullptr;     // [nseg + 1] first element of each solve
