@@ -719,7 +719,7 @@ __device__ __forceinline__ float readlane_d(float x, int lane) {
 }
 
 template <int D, int P, class R>
-__global__ __launch_bounds__(256, 2) void k_jaclu_wave(const R* __restrict__ BC, const double* __restrict__ Gpk,
+__global__ __launch_bounds__(256, 3) void k_jaclu_wave(const R* __restrict__ BC, const double* __restrict__ Gpk,
                                                     int NT, const double* __restrict__ dtau, R* __restrict__ out,
                                                     int* __restrict__ perm, int* __restrict__ fail, int ne,
                                                     Tab<D, P, R> tab) {
@@ -733,7 +733,6 @@ __global__ __launch_bounds__(256, 2) void k_jaclu_wave(const R* __restrict__ BC,
   __shared__ R s_dph[QV * D * N];    // d_r phi_i at volume points
   __shared__ R s_phf[NF * QF * N];   // phi_j at face points
   __shared__ R s_BC[W][PER];
-  __shared__ __align__(16) R s_row[W][64];  // pivot row broadcast
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int e = blockIdx.x * W + wv;
   const bool live = e < ne;
@@ -808,11 +807,12 @@ __global__ __launch_bounds__(256, 2) void k_jaclu_wave(const R* __restrict__ BC,
       for (int w = 0; w < V; ++w) acc[w * N + j] = ((w == v) ? gij * idt : R(0)) - acc[w * N + j];
     }
   }
-  // LU with partial pivoting, rows in registers.  The pivot lane writes its
-  // (final) U row to LDS once; every lane reads it back with 128-bit
-  // broadcast loads.  Lanes already used as pivots get a zero multiplier, so
-  // the update below leaves their rows unchanged without a branch.
-  R* srow = s_row[wv];
+  // LU with partial pivoting, rows in registers.  The pivot row is
+  // broadcast from its lane with readlane into scalar registers, which the
+  // FMAs take as operands (an LDS broadcast of the row would deliver 1 KB
+  // per load to the wavefront and bind the factorisation to the LDS
+  // bandwidth).  Lanes already used as pivots get a zero multiplier, so the
+  // update below leaves their rows unchanged without a branch.
   int mystep = (lane < n) ? -1 : n;
 #pragma unroll
   for (int k = 0; k < n; ++k) {
@@ -824,22 +824,13 @@ __global__ __launch_bounds__(256, 2) void k_jaclu_wave(const R* __restrict__ BC,
     const int pl = __builtin_amdgcn_readfirstlane(63 - (int)(kmax & 63u));
     // the winner must be a row not yet used as a pivot
     if (lane == pl && mystep >= 0) atomicOr(fail, 4);
-    if (lane == pl) {
-      mystep = k;
-#pragma unroll
-      for (int j = k; j < n; ++j) srow[j] = acc[j];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const R piv = srow[k];
+    mystep = (lane == pl) ? k : mystep;
+    const R piv = readlane_d(acc[k], pl);
     if (lane == 0 && !(dabs(piv) > R(0))) atomicOr(fail, 1);
     const R l = (mystep < 0) ? acc[k] * (R(1) / piv) : R(0);
     if (mystep < 0) acc[k] = l;
 #pragma unroll
-    for (int j = k + 1; j < n; ++j) acc[j] = fma(-l, srow[j], acc[j]);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    for (int j = k + 1; j < n; ++j) acc[j] = fma(-l, readlane_d(acc[j], pl), acc[j]);
   }
   if (lane < n) {
     R* o = out + (size_t)e * n * n;
