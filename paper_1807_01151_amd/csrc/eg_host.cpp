@@ -502,14 +502,15 @@ double cfl_ramp(double cfl_max, double rn, double rref, int n, int pmax) {
   return std::min(cfl_max, std::max(a, b));
 }
 
-// EXP1 on the phi-coordinate p = 0 state ut0 with optional forcing ft0.
-eg_status run_exp1(eg_handle* h, double cfl, double* ut0, const double* ft0) {
+// EXP1 on the phi-coordinate p = 0 state ut0 with optional forcing ft0; with
+// update = false the final update of ut0 is left to the caller.
+eg_status run_exp1(eg_handle* h, double cfl, double* ut0, const double* ft0, bool update = true) {
   const DevMesh& M = h->M;
   PCALL(h, EG_K_P0_SETUP, 0, eg::launch_p0_setup(M, ut0, ft0, h->pmax, cfl, 1, h->u0, h->b0, h->Ad, h->Ao, h->dt0, h->st));
   PCALL(h, EG_K_ARNOLDI, 0, eg::launch_arnoldi(M, h->m, h->nblk_arn, h->Ad, h->Ao, h->b0, h->Vb, h->H, h->part1,
                                                 h->part2, h->info, h->arn_st, h->arn_wn0, h->arn_W, h->H2, h->st));
   PCALL(h, EG_K_PHI1, 0, eg::launch_phi1(h->m, h->M.nseg, h->H, h->H2, h->info, h->y, h->dfail, h->st));
-  PCALL(h, EG_K_EXP1_UPDATE, 0, eg::launch_exp1_update(M, h->m, h->Vb, h->y, h->info, h->u0, ut0, h->st));
+  if (update) PCALL(h, EG_K_EXP1_UPDATE, 0, eg::launch_exp1_update(M, h->m, h->Vb, h->y, h->info, h->u0, ut0, h->st));
   return EG_OK;
 }
 
@@ -518,28 +519,29 @@ eg_status run_exp1(eg_handle* h, double cfl, double* ut0, const double* ft0) {
 eg_status run_prk(eg_handle* h, int p, double cfl, const double* ft) {
   const DevMesh& M = h->M;
   const int N = nmodes_of(M.d, p), n = NB(h, p);
-  const size_t K = (size_t)M.ne * n;
   PCALL(h, EG_K_TIMESTEP, p, eg::launch_timestep(M, p, N, cfl, 1.0, h->ut[p], h->dtau, h->st));
   const int pb = blk_prec(h, p), pr = res_prec(h, p);
   PCALL(h, EG_K_JACOBIAN_LU, p,
         eg::launch_jacobian(M, h->tabs[p], p, h->ut[p], h->dtau, h->F[p], h->perm[p], h->dfail, true, pb, h->st));
-  PCALL(h, EG_K_TRANSFER, p, eg::launch_copy(h->ut[p], h->un[p], K, h->st));
   for (int k = 1; k <= h->s; ++k) {
     if (k > 1)
       PCALL(h, EG_K_RESIDUAL, p, eg::launch_residual(M, h->tabs[p], p, h->ut[p], ft, h->rt[p], pr, h->st));
     const double beta = 1.0 / (h->s - k + 1.0);
+    // the first stage starts from ut and keeps it in un for the later stages
     PCALL(h, EG_K_PRK_STAGE, p,
-          eg::launch_prk_stage(M, n, h->F[p], h->perm[p], h->rt[p], nullptr, h->un[p], h->ut[p], beta, pb, h->st));
+          eg::launch_prk_stage(M, n, h->F[p], h->perm[p], h->rt[p], nullptr, k == 1 ? nullptr : h->un[p], h->ut[p],
+                               beta, pb, h->st, k == 1 ? h->un[p] : nullptr));
   }
   return EG_OK;
 }
 
-// V-cycle below level p (Section 2.4): PRK, restriction with FAS forcing,
-// recursion, prolongation of the coarse error.  Requires rt[p] = R_p + f_p.
-eg_status vc_rec(eg_handle* h, int p, double cfl) {
+// Descending half of the V-cycle below level p >= 1 (Section 2.4): PRK,
+// restriction with FAS forcing, recursion, down to the EXP1 step on p = 0
+// without its final update.  Requires rt[p] = R_p + f_p.
+eg_status vc_down(eg_handle* h, int p, double cfl) {
   const DevMesh& M = h->M;
   const double* fp = (p == h->pmax) ? nullptr : h->ft[p];
-  if (p == 0) return run_exp1(h, cfl, h->ut[0], fp);
+  if (p == 0) return run_exp1(h, cfl, h->ut[0], fp, false);
   const int pr = res_prec(h, p);
   if (p == h->pmax && pr == eg::PREC_FP32) {
     // phase A: rt holds R64(u^n) (the entry norm's residual); the top level
@@ -551,19 +553,38 @@ eg_status vc_rec(eg_handle* h, int p, double cfl) {
     fp = h->ft[p];
   }
   ECHK(run_prk(h, p, cfl, fp));
-  const int N = nmodes_of(M.d, p), Nc = nmodes_of(M.d, p - 1), rows = M.ne * M.V;
+  const int N = nmodes_of(M.d, p);
   PCALL(h, EG_K_RESIDUAL, p, eg::launch_residual(M, h->tabs[p], p, h->ut[p], fp, h->rt[p], pr, h->st));
   PCALL(h, EG_K_TRANSFER, p, eg::launch_restrict(M, p, h->ut[p], h->ut[p - 1], h->uc0[p - 1], h->st));
   {
     // FAS forcing of level p - 1 with that level's own residual R_{p-1}(v0)
-    // (FP32 on p - 1 >= 1 in mixed mode, FP64 on p = 0)
+    // (FP32 on p - 1 >= 1 in mixed mode, FP64 on p = 0), fused with the
+    // forcing f = trunc(r_p) - R_{p-1} and rt[p - 1] = trunc(r_p)
     const int pc = res_prec(h, p - 1);
+    eg::FasOut fas;
+    fas.rhat = h->rt[p];
+    fas.Nf = N;
+    fas.fc = h->ft[p - 1];
     PCALL(h, EG_K_RESIDUAL, p - 1,
-          eg::launch_residual(M, h->tabs[p - 1], p - 1, h->ut[p - 1], nullptr, h->rt[p - 1], pc, h->st));
-    PCALL(h, EG_K_TRANSFER, p, eg::launch_fas(N, Nc, rows, h->rt[p], h->rt[p - 1], h->ft[p - 1], h->st));
+          eg::launch_residual(M, h->tabs[p - 1], p - 1, h->ut[p - 1], nullptr, h->rt[p - 1], pc, h->st, fas));
   }
-  ECHK(vc_rec(h, p - 1, cfl));
-  PCALL(h, EG_K_TRANSFER, p, eg::launch_prolong(N, Nc, rows, h->ut[p], h->ut[p - 1], h->uc0[p - 1], h->st));
+  return vc_down(h, p - 1, cfl);
+}
+
+// One V-cycle (Section 2.4): the descent, then the EXP1 update on p = 0 and
+// the prolongation of the coarse corrections up to p_max in one kernel (the
+// cycle has no post-smoothing, so nothing runs between them).
+eg_status vc_rec(eg_handle* h, int p, double cfl) {
+  if (p == 0) return run_exp1(h, cfl, h->ut[0], nullptr);
+  ECHK(vc_down(h, p, cfl));
+  eg::UpChain c{};
+  for (int l = 0; l <= p; ++l) {
+    c.ut[l] = h->ut[l];
+    c.uc0[l] = h->uc0[l];
+    c.N[l] = nmodes_of(h->M.d, l);
+  }
+  c.pmax = p;
+  PCALL(h, EG_K_EXP1_UPDATE, 0, eg::launch_exp1_prolong(h->M, h->m, h->Vb, h->y, h->info, h->u0, c, h->st));
   return EG_OK;
 }
 
@@ -878,7 +899,7 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
   AL(h->arn_W, 2 * K0);
   AL(h->H2, (size_t)nseg * (h->m + 1) * h->m);
   AL(h->y, (size_t)nseg * (h->m + 1));
-  AL(h->npart, (size_t)(ne + 255) / 256 + 1);
+  AL(h->npart, (size_t)ne / 4 + 2);  // one partial per block of >= 4 elements
   AL(h->nout, nseg);
   AL(h->dfail, 1);
   AL(h->dpart, ne);
@@ -1122,7 +1143,7 @@ eg_status eg_residual(eg_handle* h, int p, const double* u_dev, double* r_dev) {
   if (p < 0 || p > h->pmax) return fail(h, EG_ERR_ARG, "order out of range");
   const int N = nmodes_of(h->M.d, p);
   HIPCHK(h, eg::launch_basis(h->M, N, u_dev, h->tmp, 0, h->st));
-  HIPCHK(h, eg::launch_residual(h->M, h->tabs[p], p, h->tmp, nullptr, h->tmp2, blk_prec(h, p), h->st));
+  PCALL(h, EG_K_RESIDUAL, p, eg::launch_residual(h->M, h->tabs[p], p, h->tmp, nullptr, h->tmp2, blk_prec(h, p), h->st));
   HIPCHK(h, eg::launch_basis(h->M, N, h->tmp2, r_dev, 2, h->st));
   return EG_OK;
 }

@@ -172,14 +172,30 @@ __device__ __forceinline__ double wave_sum(double v) {
 // (3) one thread per face point evaluates both traces (the neighbour's from
 // global memory at its matching Gauss point) and the Rusanov flux, (4) one
 // thread per output (element, var, mode) projects onto the test functions.
-// Optional: add a forcing vector.
+// Optional: add a forcing vector; or, as the coarse residual of the FAS
+// restriction (Section 2.4, steps 2-3, full approximation form), return the
+// truncated fine residual t in rt and the forcing t - R in fas.fc instead of
+// R (in phi coordinates the truncation of a residual is its leading modes).
 // ---------------------------------------------------------------------------
+template <int D, int P, class R>
+constexpr int res_table_values() {
+  using C = Cfg<D, P>;
+  return C::QV * C::N * (1 + D) + C::NF * C::QF * C::N;
+}
+
+// The basis tables live in LDS when they fit in 32 KiB (every 2D order and
+// 3D p = 1); larger 3D orders evaluate the tensor products on the fly.
+template <int D, int P, class R>
+constexpr bool res_tables() {
+  return res_table_values<D, P, R>() * (int)sizeof(R) <= 32 * 1024;
+}
+
 template <int D, int P, int EB, class R>
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut, const double* __restrict__ fadd,
                                                   double* __restrict__ rt, const double* __restrict__ xv,
                                                   const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
                                                   int ne, Tab<D, P, R> tab, GasT<R> gas,
-                                                  const double* __restrict__ uinf_e) {
+                                                  const double* __restrict__ uinf_e, FasOut fas) {
   using C = Cfg<D, P>;
   constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, NC = C::NC;
   __shared__ R s_u[EB * V * N];
@@ -187,6 +203,12 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
   __shared__ R s_ff[EB * NF * QF * V];
   __shared__ R s_x[EB * NC * D];
   __shared__ Tab<D, P, R> t;
+  // basis tables of the block: phi_k and d_r phi_k at the volume points,
+  // phi_k at the face points ([q][k], [q][r][k], [lf][kf][k])
+  constexpr bool TBL = res_tables<D, P, R>();
+  __shared__ R s_phv[TBL ? QV * N : 1];
+  __shared__ R s_dphv[TBL ? QV * D * N : 1];
+  __shared__ R s_phf[TBL ? NF * QF * N : 1];
   const int tid = threadIdx.x;
   const int e0 = blockIdx.x * EB;
   copy_tab(t, tab);
@@ -196,6 +218,26 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
     stage<(EB * NC * D + 255) / 256>(s_x, xv + (size_t)e0 * NC * D, nel * NC * D, tid, 256);
   }
   __syncthreads();
+  if constexpr (TBL) {
+  for (int it = tid; it < QV * N; it += blockDim.x) {
+    const int q = it / N, kk = it % N;
+    int iq[D], r0 = q;
+#pragma unroll
+    for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
+    s_phv[it] = phi_vol<D, P, R>(t, kk, iq);
+#pragma unroll
+    for (int r = 0; r < D; ++r) s_dphv[(q * D + r) * N + kk] = dphi_vol<D, P, R>(t, kk, iq, r);
+  }
+  for (int it = tid; it < NF * QF * N; it += blockDim.x) {
+    const int lf = it / (QF * N), kf = (it / N) % QF, kk = it % N;
+    int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1], r0 = kf;
+    face_axes<D>(lf, ta);
+#pragma unroll
+    for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
+    s_phf[it] = phi_face<D, P, R>(t, kk, lf, ta, ik);
+  }
+  __syncthreads();
+  }
   // volume points
   for (int it = tid; it < EB * QV; it += blockDim.x) {
     const int el = it / QV, q = it % QV;
@@ -212,7 +254,9 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
     for (int v = 0; v < V; ++v) U[v] = R(0);
     const R* su = &s_u[el * V * N];
     for (int k = 0; k < N; ++k) {
-      R ph = phi_vol<D, P, R>(t, k, iq);
+      R ph;
+      if constexpr (TBL) ph = s_phv[q * N + k];
+      else ph = phi_vol<D, P, R>(t, k, iq);
 #pragma unroll
       for (int v = 0; v < V; ++v) U[v] += su[v * N + k] * ph;
     }
@@ -245,7 +289,9 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
     for (int v = 0; v < V; ++v) UL[v] = R(0);
     const R* su = &s_u[el * V * N];
     for (int j = 0; j < N; ++j) {
-      R ph = phi_face<D, P, R>(t, j, lf, ta, ik);
+      R ph;
+      if constexpr (TBL) ph = s_phf[(lf * QF + k) * N + j];
+      else ph = phi_face<D, P, R>(t, j, lf, ta, ik);
 #pragma unroll
       for (int v = 0; v < V; ++v) UL[v] += su[v * N + j] * ph;
     }
@@ -268,8 +314,13 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
 #pragma unroll
       for (int v = 0; v < V; ++v) UR[v] = R(0);
       const double* un = ut + (size_t)nb * V * N;
+      int kf2 = 0;
+#pragma unroll
+      for (int q = D - 2; q >= 0; --q) kf2 = kf2 * Q + jk[q];
       for (int j = 0; j < N; ++j) {
-        R ph = phi_face<D, P, R>(t, j, lf2, ta2, jk);
+        R ph;
+        if constexpr (TBL) ph = s_phf[(lf2 * QF + kf2) * N + j];
+        else ph = phi_face<D, P, R>(t, j, lf2, ta2, jk);
 #pragma unroll
         for (int v = 0; v < V; ++v) UR[v] += R(un[v * N + j]) * ph;
       }
@@ -293,28 +344,44 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
     const int e = e0 + el;
     if (e >= ne) continue;
     R acc = R(0);
-    for (int q = 0; q < QV; ++q) {
-      int iq[D];
-      int r0 = q;
+    if constexpr (TBL) {
+      for (int q = 0; q < QV; ++q) {
+        const R* fc = &s_fc[((el * QV + q) * V + v) * D];
 #pragma unroll
-      for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
-      const R* fc = &s_fc[((el * QV + q) * V + v) * D];
+        for (int r = 0; r < D; ++r) acc += s_dphv[(q * D + r) * N + i] * fc[r];
+      }
+      for (int fk = 0; fk < NF * QF; ++fk) acc -= s_phf[fk * N + i] * s_ff[(el * NF * QF + fk) * V + v];
+    } else {
+      for (int q = 0; q < QV; ++q) {
+        int iq[D];
+        int r0 = q;
 #pragma unroll
-      for (int r = 0; r < D; ++r) acc += dphi_vol<D, P, R>(t, i, iq, r) * fc[r];
-    }
-    for (int lf = 0; lf < NF; ++lf) {
-      int ta[D - 1 > 0 ? D - 1 : 1];
-      face_axes<D>(lf, ta);
-      for (int k = 0; k < QF; ++k) {
-        int ik[D - 1 > 0 ? D - 1 : 1];
-        int r0 = k;
+        for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
+        const R* fc = &s_fc[((el * QV + q) * V + v) * D];
 #pragma unroll
-        for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
-        acc -= phi_face<D, P, R>(t, i, lf, ta, ik) * s_ff[((el * NF + lf) * QF + k) * V + v];
+        for (int r = 0; r < D; ++r) acc += dphi_vol<D, P, R>(t, i, iq, r) * fc[r];
+      }
+      for (int lf = 0; lf < NF; ++lf) {
+        int ta[D - 1 > 0 ? D - 1 : 1];
+        face_axes<D>(lf, ta);
+        for (int k = 0; k < QF; ++k) {
+          int ik[D - 1 > 0 ? D - 1 : 1];
+          int r0 = k;
+#pragma unroll
+          for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
+          acc -= phi_face<D, P, R>(t, i, lf, ta, ik) * s_ff[((el * NF + lf) * QF + k) * V + v];
+        }
       }
     }
     const size_t o = (size_t)e0 * V * N + it;
-    rt[o] = fadd ? double(acc) + fadd[o] : double(acc);
+    const double r = fadd ? double(acc) + fadd[o] : double(acc);
+    if (fas.rhat) {
+      const double tr = fas.rhat[((size_t)e * V + v) * fas.Nf + i];
+      fas.fc[o] = tr - r;
+      rt[o] = tr;
+    } else {
+      rt[o] = r;
+    }
   }
 }
 
@@ -844,13 +911,15 @@ __global__ __launch_bounds__(256, 3) void k_jaclu_wave(const R* __restrict__ BC,
 // PRK stage (Section 2.3, eq. (prk_scalar)) in phi coordinates:
 //   ut = un + beta Pt^{-1} (rt [+ ft]),
 // one wavefront per element, lane l owning rows l, l+64, ...; forward and
-// back substitution on the column-major LU factors.
+// back substitution on the column-major LU factors.  First stage: un is null,
+// the stage starts from ut itself and stores that state in save (the un of
+// the later stages).
 // ---------------------------------------------------------------------------
 template <int NR, class R>
 __global__ __launch_bounds__(256) void k_prk_stage(const R* __restrict__ Fm, const int* __restrict__ perm,
                                                    const double* __restrict__ rt, const double* __restrict__ ft,
-                                                   const double* __restrict__ un, double* __restrict__ ut, double beta,
-                                                   int n, int ne) {
+                                                   const double* __restrict__ un, double* __restrict__ ut,
+                                                   double* __restrict__ save, double beta, int n, int ne) {
   const int lane = threadIdx.x & 63;
   const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (e >= ne) return;
@@ -900,7 +969,12 @@ __global__ __launch_bounds__(256) void k_prk_stage(const R* __restrict__ Fm, con
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
     const int i = lane + 64 * s;
-    if (i < n) ut[(size_t)e * n + i] = un[(size_t)e * n + i] + beta * double(b[s]);
+    if (i < n) {
+      const size_t o = (size_t)e * n + i;
+      const double u0 = un ? un[o] : ut[o];
+      if (save) save[o] = u0;
+      ut[o] = u0 + beta * double(b[s]);
+    }
   }
 }
 
@@ -908,11 +982,12 @@ __global__ __launch_bounds__(256) void k_prk_stage(const R* __restrict__ Fm, con
 // row (column-major storage, so each column load is coalesced over the lanes
 // and all NB loads are independent and in flight together), then runs the
 // forward and back substitution in registers, broadcasting x_j with readlane
-// at a constant lane.  Same arithmetic as k_prk_stage.
+// at a constant lane.  Same arithmetic and arguments as k_prk_stage.
 template <int NB, class R>
 __global__ __launch_bounds__(256) void k_prk_stage_t(const R* __restrict__ Fm, const int* __restrict__ perm,
                                                      const double* __restrict__ rt, const double* __restrict__ un,
-                                                     double* __restrict__ ut, double beta, int ne) {
+                                                     double* __restrict__ ut, double* __restrict__ save, double beta,
+                                                     int ne) {
   static_assert(NB <= 64, "one row per lane");
   const int lane = threadIdx.x & 63;
   const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -923,6 +998,8 @@ __global__ __launch_bounds__(256) void k_prk_stage_t(const R* __restrict__ Fm, c
 #pragma unroll
   for (int j = 0; j < NB; ++j) row[j] = F[(size_t)j * NB + i];
   R b = R(rt[(size_t)e * NB + perm[(size_t)e * NB + i]]);
+  const size_t o = (size_t)e * NB + i;
+  const double u0 = un ? un[o] : ut[o];
   // L y = b (unit diagonal): rows below j subtract L(i, j) y_j
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -935,7 +1012,10 @@ __global__ __launch_bounds__(256) void k_prk_stage_t(const R* __restrict__ Fm, c
     const R xj = readlane_d(b, j) / readlane_d(row[j], j);
     b = (lane == j) ? xj : fma(-((lane < j) ? row[j] : R(0)), xj, b);
   }
-  if (lane < NB) ut[(size_t)e * NB + lane] = un[(size_t)e * NB + lane] + beta * double(b);
+  if (lane < NB) {
+    if (save) save[o] = u0;
+    ut[o] = u0 + beta * double(b);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1013,30 +1093,6 @@ __global__ __launch_bounds__(256) void k_restrict(const double* __restrict__ ut,
   }
 }
 
-// FAS coarse forcing (Section 2.4, steps 2-3, standard full approximation
-// form): fc = Trunc(rhat_p) - rc; the coarse stage-1 residual becomes
-// Trunc(rhat_p).  In phi coordinates truncation of a residual is the leading
-// slice.
-__global__ __launch_bounds__(256) void k_fas(const double* __restrict__ rhat, double* __restrict__ rc,
-                                             double* __restrict__ fc, int N, int Nc, int rows) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= rows * Nc) return;
-  const int row = id / Nc, k = id % Nc;
-  const double t = rhat[(size_t)row * N + k];
-  fc[id] = t - rc[id];
-  rc[id] = t;
-}
-
-// Prolongation of the coarse error and correction (Section 2.4, steps 5-6):
-// ut[:, :, :Nc] += uc - uc0.
-__global__ __launch_bounds__(256) void k_prolong(double* __restrict__ ut, const double* __restrict__ uc,
-                                                 const double* __restrict__ uc0, int N, int Nc, int rows) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= rows * Nc) return;
-  const int row = id / Nc, k = id % Nc;
-  ut[(size_t)row * N + k] += uc[id] - uc0[id];
-}
-
 // ---------------------------------------------------------------------------
 // Pseudo-time step (Section 4, eq. (x3d)) from the element mean
 //   Ubar = u_0 psi_0,  u_0 = (L^T ut)_0,  psi_0 = phi_0 / L_00,
@@ -1048,28 +1104,31 @@ __global__ __launch_bounds__(256) void k_timestep(const double* __restrict__ ut,
                                                   int NT, const double* __restrict__ hE, int p, double cfl, double mult,
                                                   double* __restrict__ dtau, int ne, double g,
                                                   const double* __restrict__ cfl_e, int cfl_stride) {
-  constexpr int V = D + 2;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
-  const double* L = Lpk + (size_t)e * NT;
-  const double psi0 = (D == 2 ? 0.5 : 0.35355339059327373) / L[0];
+  // G lanes per element: lane t sums the entries t, t + G, ... of the
+  // element's [V][N] block (coalesced loads), then the G partial sums of
+  // every variable are combined by shuffles within the group
+  constexpr int V = D + 2, G = 16;
+  const int e = blockIdx.x * (256 / G) + (int)threadIdx.x / G, t = (int)threadIdx.x % G;
+  const bool act = e < ne;
   double U[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) U[v] = 0.0;
-  for (int j0 = 0; j0 < N; j0 += 8) {
-    double lc[8], uv[8][V];
+  if (act) {
+    const double* L = Lpk + (size_t)e * NT;
+    const double* a = ut + (size_t)e * V * N;
+    for (int idx = t; idx < V * N; idx += G) {
+      const int v = idx / N, j = idx % N;
+      const double x = L[j * (j + 1) / 2] * a[idx];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int j = j0 + u < N ? j0 + u : N - 1;
-      lc[u] = (j0 + u < N) ? L[j * (j + 1) / 2] : 0.0;
-#pragma unroll
-      for (int v = 0; v < V; ++v) uv[u][v] = ut[((size_t)e * V + v) * N + j];
+      for (int w = 0; w < V; ++w) U[w] += (w == v) ? x : 0.0;
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u)
-#pragma unroll
-      for (int v = 0; v < V; ++v) U[v] += lc[u] * uv[u][v];
   }
+#pragma unroll
+  for (int o = G / 2; o >= 1; o >>= 1)
+#pragma unroll
+    for (int v = 0; v < V; ++v) U[v] += __shfl_xor(U[v], o, 64);
+  if (!act || t != 0) return;
+  const double psi0 = (D == 2 ? 0.5 : 0.35355339059327373) / Lpk[(size_t)e * NT];
 #pragma unroll
   for (int v = 0; v < V; ++v) U[v] *= psi0;
   double q2 = 0.0;
@@ -1083,30 +1142,40 @@ __global__ __launch_bounds__(256) void k_timestep(const double* __restrict__ ut,
 // Density-residual norm (Section 4): sum over elements of |L^{-1} rt_rho|^2,
 // block partial sums then one deterministic final sum.
 // ---------------------------------------------------------------------------
+// G lanes per element (G = N rounded up to a power of two, so a group never
+// straddles a wavefront): lane i holds r_i and row i of L and the forward
+// substitution runs by columns, x_j broadcast from lane j, which performs
+// the same operations per row as a sequential solve.
+template <int N>
+constexpr int norm_group() {
+  return N <= 1 ? 1 : N <= 4 ? 4 : N <= 8 ? 8 : N <= 16 ? 16 : N <= 32 ? 32 : 64;
+}
+
 template <int D, int N>
 __global__ __launch_bounds__(256) void k_norm_partial(const double* __restrict__ rt, const double* __restrict__ Lpk,
                                                       int NT, int ne, double* __restrict__ part) {
-  constexpr int V = D + 2;
+  constexpr int V = D + 2, G = norm_group<N>(), EPB = 256 / G;
   __shared__ double s_w[4];
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  double acc = 0.0;
-  if (e < ne) {
-    const double* L = Lpk + (size_t)e * NT;
-    const double* a = rt + (size_t)e * V * N;
-    double r[N], l[N * (N + 1) / 2];
+  const int e = blockIdx.x * EPB + (int)threadIdx.x / G, i = (int)threadIdx.x % G;
+  const int base = (int)(threadIdx.x & 63) - i;  // first lane of the group
+  const bool act = e < ne && i < N;
+  double r = 0.0, l[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) r[i] = a[i];
+  for (int j = 0; j < N; ++j) l[j] = 0.0;
+  if (act) {
+    const double* L = Lpk + (size_t)e * NT + i * (i + 1) / 2;
+    r = rt[(size_t)e * V * N + i];
 #pragma unroll
-    for (int i = 0; i < N * (N + 1) / 2; ++i) l[i] = L[i];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double s = r[i];
-#pragma unroll
-      for (int j = 0; j < i; ++j) s -= l[i * (i + 1) / 2 + j] * r[j];
-      r[i] = s / l[i * (i + 1) / 2 + i];
-      acc += r[i] * r[i];
-    }
+    for (int j = 0; j < N; ++j) l[j] = (j <= i) ? L[j] : 0.0;
   }
+  double x = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const double xj = __shfl(r, base + j, 64) / __shfl(l[j], base + j, 64);
+    if (i == j) x = xj;
+    else if (i > j) r -= l[j] * xj;
+  }
+  double acc = act ? x * x : 0.0;
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
   __syncthreads();
@@ -1164,7 +1233,7 @@ __global__ __launch_bounds__(256) void k_norm_seg(const double* __restrict__ rt,
 // scale = false: dt = 1 (plain J0 and R0 + f0).
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ __launch_bounds__(128) void k_p0_setup(const double* __restrict__ ut0, const double* __restrict__ ft0,
+__global__ __launch_bounds__(256) void k_p0_setup(const double* __restrict__ ut0, const double* __restrict__ ft0,
                                                   const double* __restrict__ xv, const int* __restrict__ nbr,
                                                   const double* __restrict__ Lpk, int NT, const double* __restrict__ hE,
                                                   int pmax, double cfl, int scale, double* __restrict__ u0,
@@ -1173,38 +1242,43 @@ __global__ __launch_bounds__(128) void k_p0_setup(const double* __restrict__ ut0
                                                   const double* __restrict__ gx, const double* __restrict__ gw,
                                                   const double* __restrict__ uinf_e, const double* __restrict__ cfl_e,
                                                   int cfl_stride) {
+  // one lane per (face, face point) of an element, G lanes per element
+  // (padded to a power of two); the contributions are summed over the points
+  // of a face (neighbour block) and over all faces (R0, diagonal block) by
+  // butterfly shuffles, a fixed order
   constexpr int V = D + 2, NF = 2 * D, NC = 1 << D, QF = 1 << (D - 1);
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
+  constexpr int G = (D == 2) ? 8 : 32, EPB = 256 / G;
+  const int e = blockIdx.x * EPB + (int)threadIdx.x / G, t = (int)threadIdx.x % G;
+  const int lf = t / QF, k = t % QF;
+  const bool act = e < ne && lf < NF;
   const double phi0 = (D == 2 ? 0.5 : 0.35355339059327373);
-  const double L00 = Lpk[(size_t)e * NT];
-  double X[NC * D];
-#pragma unroll
-  for (int i = 0; i < NC * D; ++i) X[i] = xv[(size_t)e * NC * D + i];
+  const int ec = e < ne ? e : ne - 1;  // clamped element: every lane loads in bounds
+  const double L00 = Lpk[(size_t)ec * NT];
   double U[V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) U[v] = ut0[(size_t)e * V + v] * phi0;
+  for (int v = 0; v < V; ++v) U[v] = ut0[(size_t)ec * V + v] * phi0;
   double dt = 1.0;
   if (scale) {
     double q2 = 0.0;
 #pragma unroll
     for (int a = 0; a < D; ++a) q2 += (U[1 + a] / U[0]) * (U[1 + a] / U[0]);
     const double c = sqrt(gas.g * pressure<D>(U, gas.g) / U[0]);
-    const double ce = cfl_e ? cfl_e[(size_t)cfl_stride * e] : cfl;
-    dt = (pmax + 1.0) * ce * hE[e] / ((2.0 * pmax + 1.0) * (sqrt(q2) + c));
+    const double ce = cfl_e ? cfl_e[(size_t)cfl_stride * ec] : cfl;
+    dt = (pmax + 1.0) * ce * hE[ec] / ((2.0 * pmax + 1.0) * (sqrt(q2) + c));
   }
-  double R[V], Jd[V * V];
+  double R[V], Jd[V * V], Jo[V * V];
 #pragma unroll
   for (int v = 0; v < V; ++v) R[v] = 0.0;
 #pragma unroll
-  for (int x = 0; x < V * V; ++x) Jd[x] = 0.0;
-  for (int lf = 0; lf < NF; ++lf) {
-    double Jo[V * V];
+  for (int x = 0; x < V * V; ++x) { Jd[x] = 0.0; Jo[x] = 0.0; }
+  int nb = -1;
+  double L00n = 1.0;
+  if (act) {
+    double X[NC * D];
 #pragma unroll
-    for (int x = 0; x < V * V; ++x) Jo[x] = 0.0;
-    const int nb = nbr[(size_t)e * NF + lf];
+    for (int i = 0; i < NC * D; ++i) X[i] = xv[(size_t)e * NC * D + i];
+    nb = nbr[(size_t)e * NF + lf];
     double UN[V];
-    double L00n = 1.0;
     if (nb >= 0) {
       L00n = Lpk[(size_t)nb * NT];
 #pragma unroll
@@ -1212,58 +1286,71 @@ __global__ __launch_bounds__(128) void k_p0_setup(const double* __restrict__ ut0
     }
     int ta[D - 1];
     face_axes<D>(lf, ta);
-    for (int k = 0; k < QF; ++k) {
-      double xi[D], wk = 1.0;
-      xi[lf >> 1] = (lf & 1) ? 1.0 : -1.0;
-      int r0 = k;
+    double xi[D], wk = 1.0;
+    xi[lf >> 1] = (lf & 1) ? 1.0 : -1.0;
+    int r0 = k;
 #pragma unroll
-      for (int q = 0; q < D - 1; ++q) { xi[ta[q]] = gx[r0 & 1]; wk *= gw[r0 & 1]; r0 >>= 1; }
-      double c[D][D], det;
-      geom<D>(X, xi, c, det);
-      double nh[D], a2 = 0.0;
-      const double sg = (lf & 1) ? 1.0 : -1.0;
+    for (int q = 0; q < D - 1; ++q) { xi[ta[q]] = gx[r0 & 1]; wk *= gw[r0 & 1]; r0 >>= 1; }
+    double c[D][D], det;
+    geom<D>(X, xi, c, det);
+    double nh[D], a2 = 0.0;
+    const double sg = (lf & 1) ? 1.0 : -1.0;
 #pragma unroll
-      for (int a = 0; a < D; ++a) { nh[a] = sg * c[lf >> 1][a]; a2 += nh[a] * nh[a]; }
-      const double area = sqrt(a2);
+    for (int a = 0; a < D; ++a) { nh[a] = sg * c[lf >> 1][a]; a2 += nh[a] * nh[a]; }
+    const double area = sqrt(a2);
 #pragma unroll
-      for (int a = 0; a < D; ++a) nh[a] /= area;
-      const double wa = wk * area * phi0;
-      Dual<V> UL[V], F[V];
+    for (int a = 0; a < D; ++a) nh[a] /= area;
+    const double wa = wk * area * phi0;
+    Dual<V> UL[V], F[V];
 #pragma unroll
-      for (int v = 0; v < V; ++v) { UL[v] = Dual<V>(U[v]); UL[v].d[v] = 1.0; }
-      if (nb >= 0) {
-        rusanov<D>(UL, UN, nh, F, gas.g);
-        Dual<V> UR[V], F2[V];
+    for (int v = 0; v < V; ++v) { UL[v] = Dual<V>(U[v]); UL[v].d[v] = 1.0; }
+    if (nb >= 0) {
+      rusanov<D>(UL, UN, nh, F, gas.g);
+      Dual<V> UR[V], F2[V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) { UR[v] = Dual<V>(UN[v]); UR[v].d[v] = 1.0; }
-        rusanov<D>(U, UR, nh, F2, gas.g);
+      for (int v = 0; v < V; ++v) { UR[v] = Dual<V>(UN[v]); UR[v].d[v] = 1.0; }
+      rusanov<D>(U, UR, nh, F2, gas.g);
 #pragma unroll
-        for (int v = 0; v < V; ++v)
+      for (int v = 0; v < V; ++v)
 #pragma unroll
-          for (int w = 0; w < V; ++w) Jo[v * V + w] -= wa * phi0 * F2[v].d[w];
-      } else {
-        Dual<V> UG[V];
-        if (nb == NB_WALL) ghost_wall<D>(UL, nh, UG);
-        else {
-          double Ui[V];
+        for (int w = 0; w < V; ++w) Jo[v * V + w] = -(wa * phi0 * F2[v].d[w]);
+    } else {
+      Dual<V> UG[V];
+      if (nb == NB_WALL) ghost_wall<D>(UL, nh, UG);
+      else {
+        double Ui[V];
 #pragma unroll
-          for (int v = 0; v < V; ++v) Ui[v] = uinf_e ? uinf_e[(size_t)e * V + v] : gas.Uinf[v];
-          ghost_far<D>(UL, nh, UG, Ui, gas.g);
-        }
-        rusanov<D>(UL, UG, nh, F, gas.g);
+        for (int v = 0; v < V; ++v) Ui[v] = uinf_e ? uinf_e[(size_t)e * V + v] : gas.Uinf[v];
+        ghost_far<D>(UL, nh, UG, Ui, gas.g);
       }
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        R[v] -= wa * F[v].v;
-#pragma unroll
-        for (int w = 0; w < V; ++w) Jd[v * V + w] -= wa * phi0 * F[v].d[w];
-      }
+      rusanov<D>(UL, UG, nh, F, gas.g);
     }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      R[v] = -(wa * F[v].v);
+#pragma unroll
+      for (int w = 0; w < V; ++w) Jd[v * V + w] = -(wa * phi0 * F[v].d[w]);
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < QF; o <<= 1)
+#pragma unroll
+    for (int x = 0; x < V * V; ++x) Jo[x] += __shfl_xor(Jo[x], o, 64);
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) R[v] += __shfl_xor(R[v], o, 64);
+#pragma unroll
+    for (int x = 0; x < V * V; ++x) Jd[x] += __shfl_xor(Jd[x], o, 64);
+  }
+  if (!act) return;
+  if (k == 0) {
     // psi coordinates: dR0_E/du0_F = Jt / (L00_E L00_F)
     const double so = dt / (L00 * L00n);
 #pragma unroll
     for (int x = 0; x < V * V; ++x) Ao[((size_t)e * NF + lf) * V * V + x] = (nb >= 0) ? so * Jo[x] : 0.0;
   }
+  if (t != 0) return;
   const double sd = dt / (L00 * L00);
 #pragma unroll
   for (int x = 0; x < V * V; ++x) Ad[(size_t)e * V * V + x] = sd * Jd[x];
@@ -1714,6 +1801,61 @@ __device__ void lds_matmul(int n, const double* A, const double* B, double* Cm) 
   __syncthreads();
 }
 
+// (V - U) E = V + U for n <= 32 by the four wavefronts of the block, with no
+// block barrier inside the elimination: every wave holds the coefficient
+// matrix, one row per lane and zero-padded to order 32 by an identity block,
+// plus eight of the right-hand-side columns.  The waves make the same pivot
+// choices (largest |a| of the unused rows, compared as float keys with ties
+// to the lowest lane), eliminate with the pivot row broadcast by readlane
+// and back-substitute in pivot order.  E overwrites X.
+__device__ void phi1_solve_wave(int n, const double* Pm, double* X, int* fail) {
+  constexpr int NM = 32, NC = 8;
+  const int lane = threadIdx.x & 63, c0 = (threadIdx.x >> 6) * NC;
+  double a[NM], x[NC];
+#pragma unroll
+  for (int j = 0; j < NM; ++j) a[j] = (lane < n && j < n) ? Pm[lane * n + j] : (lane == j ? 1.0 : 0.0);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) x[c] = (lane < n && c0 + c < n) ? X[lane * n + c0 + c] : (lane == c0 + c ? 1.0 : 0.0);
+  __syncthreads();  // X is overwritten below
+  int mystep = (lane < NM) ? -1 : 64;
+#pragma unroll
+  for (int k = 0; k < NM; ++k) {
+    unsigned key = 0u;
+    if (mystep < 0) key = (__float_as_uint((float)fabs(a[k])) & ~63u) | (unsigned)(63 - lane);
+    const unsigned kmax = wave_max_u32(key);
+    const int pl = __builtin_amdgcn_readfirstlane(63 - (int)(kmax & 63u));
+    mystep = (lane == pl) ? k : mystep;
+    const double piv = readlane_d(a[k], pl);
+    if (threadIdx.x == 0 && !(fabs(piv) > 0.0)) atomicOr(fail, 2);
+    const double l = (mystep < 0) ? a[k] * (1.0 / piv) : 0.0;
+#pragma unroll
+    for (int j = k + 1; j < NM; ++j) a[j] = fma(-l, readlane_d(a[j], pl), a[j]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) x[c] = fma(-l, readlane_d(x[c], pl), x[c]);
+  }
+  // back substitution: the row of step k is final once the rows of later
+  // steps are; it is scaled by 1/u_kk and removed from the rows of earlier
+  // steps (u_sk = a[k] of the lane of step s < k)
+#pragma unroll
+  for (int k = NM - 1; k >= 0; --k) {
+    const int q = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(mystep == k)));
+    const double inv = 1.0 / readlane_d(a[k], q);
+    const double coef = (mystep < k) ? a[k] : 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const double xq = readlane_d(x[c], q) * inv;
+      x[c] = (lane == q) ? xq : fma(-coef, xq, x[c]);
+    }
+  }
+  if (mystep < n) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (c0 + c < n) X[mystep * n + c0 + c] = x[c];
+  }
+  __syncthreads();
+}
+
+template <bool WAVE>
 __global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, const double* __restrict__ H2, int mstride,
                                               const double* __restrict__ info, double* __restrict__ y,
                                               int* __restrict__ fail) {
@@ -1790,54 +1932,58 @@ __global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, cons
   double* X = B4;
   for (int it = threadIdx.x; it < nn; it += blockDim.x) { Pm[it] = Vm[it] - U[it]; X[it] = Vm[it] + U[it]; }
   __syncthreads();
-  __shared__ double s_l[64];
-  for (int k = 0; k < n; ++k) {
-    // pivot: wave 0 finds the first row of largest |Pm[i][k]|, i >= k
-    // (n <= 49 rows, one per lane)
-    if (threadIdx.x < 64) {
-      const int i = threadIdx.x;
-      double a = (i >= k && i < n) ? fabs(Pm[i * n + k]) : -1.0;
-      int idx = i;
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        const double a2 = __shfl_xor(a, o, 64);
-        const int i2 = __shfl_xor(idx, o, 64);
-        if (a2 > a || (a2 == a && i2 < idx)) { a = a2; idx = i2; }
+  if constexpr (WAVE) {
+    phi1_solve_wave(n, Pm, X, fail);
+  } else {
+    __shared__ double s_l[64];
+    for (int k = 0; k < n; ++k) {
+      // pivot: wave 0 finds the first row of largest |Pm[i][k]|, i >= k
+      // (n <= 49 rows, one per lane)
+      if (threadIdx.x < 64) {
+        const int i = threadIdx.x;
+        double a = (i >= k && i < n) ? fabs(Pm[i * n + k]) : -1.0;
+        int idx = i;
+  #pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+          const double a2 = __shfl_xor(a, o, 64);
+          const int i2 = __shfl_xor(idx, o, 64);
+          if (a2 > a || (a2 == a && i2 < idx)) { a = a2; idx = i2; }
+        }
+        if (threadIdx.x == 0) {
+          if (!(a > 0.0)) atomicOr(fail, 2);
+          s_piv = idx;
+        }
       }
-      if (threadIdx.x == 0) {
-        if (!(a > 0.0)) atomicOr(fail, 2);
-        s_piv = idx;
+      __syncthreads();
+      const int pv = s_piv;
+      if (pv != k) {
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+          double t1 = Pm[k * n + j]; Pm[k * n + j] = Pm[pv * n + j]; Pm[pv * n + j] = t1;
+          double t2 = X[k * n + j]; X[k * n + j] = X[pv * n + j]; X[pv * n + j] = t2;
+        }
+        __syncthreads();
       }
-    }
-    __syncthreads();
-    const int pv = s_piv;
-    if (pv != k) {
-      for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        double t1 = Pm[k * n + j]; Pm[k * n + j] = Pm[pv * n + j]; Pm[pv * n + j] = t1;
-        double t2 = X[k * n + j]; X[k * n + j] = X[pv * n + j]; X[pv * n + j] = t2;
+      // row multipliers once per row, then the rank-1 update
+      if (threadIdx.x > k && threadIdx.x < n) s_l[threadIdx.x] = Pm[threadIdx.x * n + k] / Pm[k * n + k];
+      __syncthreads();
+      for (int it = threadIdx.x; it < (n - k - 1) * n; it += blockDim.x) {
+        const int i = k + 1 + it / n, j = it % n;
+        const double l = s_l[i];
+        X[i * n + j] -= l * X[k * n + j];
+        if (j > k) Pm[i * n + j] -= l * Pm[k * n + j];
+        else if (j == k) Pm[i * n + j] = 0.0;
       }
       __syncthreads();
     }
-    // row multipliers once per row, then the rank-1 update
-    if (threadIdx.x > k && threadIdx.x < n) s_l[threadIdx.x] = Pm[threadIdx.x * n + k] / Pm[k * n + k];
-    __syncthreads();
-    for (int it = threadIdx.x; it < (n - k - 1) * n; it += blockDim.x) {
-      const int i = k + 1 + it / n, j = it % n;
-      const double l = s_l[i];
-      X[i * n + j] -= l * X[k * n + j];
-      if (j > k) Pm[i * n + j] -= l * Pm[k * n + j];
-      else if (j == k) Pm[i * n + j] = 0.0;
+    for (int k = n - 1; k >= 0; --k) {
+      for (int j = threadIdx.x; j < n; j += blockDim.x) X[k * n + j] /= Pm[k * n + k];
+      __syncthreads();
+      for (int it = threadIdx.x; it < k * n; it += blockDim.x) {
+        const int i = it / n, j = it % n;
+        X[i * n + j] -= Pm[i * n + k] * X[k * n + j];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  for (int k = n - 1; k >= 0; --k) {
-    for (int j = threadIdx.x; j < n; j += blockDim.x) X[k * n + j] /= Pm[k * n + k];
-    __syncthreads();
-    for (int it = threadIdx.x; it < k * n; it += blockDim.x) {
-      const int i = it / n, j = it % n;
-      X[i * n + j] -= Pm[i * n + k] * X[k * n + j];
-    }
-    __syncthreads();
   }
   double* E = X;
   double* Tm = B6;
@@ -1847,6 +1993,26 @@ __global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, cons
     __syncthreads();
   }
   for (int i = threadIdx.x; i < mu; i += blockDim.x) y[i] = E[i * n + mu];
+}
+
+// sum_{i < mu} Vb[i][k] y[i] in order of i, the loads issued sixteen at a
+// time (a loop of single loads would wait for each of them in turn).
+__device__ __forceinline__ double basis_dot(const double* __restrict__ Vb, size_t K, int k,
+                                            const double* __restrict__ ys, int mu) {
+  double s = 0.0;
+  for (int i0 = 0; i0 < mu; i0 += 16) {
+    double a[16], b[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int i = i0 + u < mu ? i0 + u : i0;
+      a[u] = Vb[(size_t)i * K + k];
+      b[u] = ys[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (i0 + u < mu) s += a[u] * b[u];
+  }
+  return s;
 }
 
 // u0 += beta V_m y ; then back to phi coordinates: ut0 = u0 / L00 (y and
@@ -1862,10 +2028,57 @@ __global__ __launch_bounds__(256) void k_exp1_update(int K, int V, const double*
   const int mu = (int)info[2 * sg];
   const double beta = info[2 * sg + 1];
   const double* ys = y + (size_t)sg * ystride;
-  double s = 0.0;
-  for (int j = 0; j < mu; ++j) s += Vb[(size_t)j * K + k] * ys[j];
+  const double s = basis_dot(Vb, K, k, ys, mu);
   const double u = u0[k] + beta * s;
   ut0[k] = u / Lpk[(size_t)(k / V) * NT];
+}
+
+// The EXP1 update of the p = 0 state followed by the whole prolongation
+// chain of the V-cycle (Section 2.4, steps 5-6, from level 1 up to p_max):
+//   ut0 as k_exp1_update computes it, then for l = 1..p_max
+//   ut_l[:N_{l-1}] += ut_{l-1} - uc0_{l-1}.
+// Modes are independent along the chain, so one thread takes one (row, mode)
+// pair, j < N_{p_max - 1}, and carries its corrected value of ut_{l-1} from
+// level to level (thread j = 0 also forms ut0).  Same operations in the same
+// order as k_exp1_update followed by the prolongations one level at a time.
+__global__ __launch_bounds__(256) void k_exp1_prolong(int K, int V, const double* __restrict__ Vb,
+                                                      const double* __restrict__ y, const double* __restrict__ info,
+                                                      const double* __restrict__ u0, const double* __restrict__ Lpk,
+                                                      int NT, const int* __restrict__ sid, int ystride, UpChain c) {
+  const int NJ = c.N[c.pmax - 1];
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= K * NJ) return;
+  const int k = id / NJ, j = id % NJ;
+  // every load of the chain first: ut_l and uc0_{l-1} at (k, j), and
+  // ut_{l-1} where the level below leaves mode j as it is (no thread writes
+  // such an entry, so it can be read ahead of the corrections)
+  double a_ut[4], a_uc0[4], a_prev[4];
+#pragma unroll
+  for (int l = 1; l <= 4; ++l) {
+    const bool on = l <= c.pmax && j < c.N[l - 1];
+    const int Nc = c.N[l - 1];
+    a_ut[l - 1] = on ? c.ut[l][(size_t)k * c.N[l] + j] : 0.0;
+    a_uc0[l - 1] = on ? c.uc0[l - 1][(size_t)k * Nc + j] : 0.0;
+    a_prev[l - 1] = (on && l >= 2 && j >= c.N[l - 2]) ? c.ut[l - 1][(size_t)k * Nc + j] : 0.0;
+  }
+  double cur = 0.0;  // this thread's value of ut_{l-1}[k][j]
+  if (j == 0) {
+    const int sg = sid ? sid[k / V] : 0;
+    const int mu = (int)info[2 * sg];
+    const double beta = info[2 * sg + 1];
+    const double s = basis_dot(Vb, K, k, y + (size_t)sg * ystride, mu);
+    const double u = u0[k] + beta * s;
+    cur = u / Lpk[(size_t)(k / V) * NT];
+    c.ut[0][k] = cur;
+  }
+#pragma unroll
+  for (int l = 1; l <= 4; ++l) {
+    if (l > c.pmax || j >= c.N[l - 1]) continue;  // mode j joins the chain at a higher level
+    // a mode the level below did not correct enters as it stands
+    if (l >= 2 && j >= c.N[l - 2]) cur = a_prev[l - 1];
+    cur = a_ut[l - 1] + (cur - a_uc0[l - 1]);
+    c.ut[l][(size_t)k * c.N[l] + j] = cur;
+  }
 }
 
 // Neighbour table for export: element index, or -1 on any boundary face.
@@ -2295,8 +2508,15 @@ template <int D, int P, class R>
 constexpr int res_tile() {
   using C = Cfg<D, P>;
   constexpr int per = (C::V * C::N + C::QV * C::V * D + C::NF * C::QF * C::V + C::NC * D) * (int)sizeof(R);
-  constexpr int eb = 48 * 1024 / per;
-  return eb < 1 ? 1 : (eb > 32 ? 32 : eb);
+  constexpr int tables = res_tables<D, P, R>() ? res_table_values<D, P, R>() * (int)sizeof(R) : 0;
+  constexpr int budget = 48 * 1024 - tables;
+  constexpr int eb0 = budget / per < 1 ? 1 : (budget / per > 32 ? 32 : budget / per);
+  // with the tables in LDS, at most one pass of the block over the volume
+  // points: smaller tiles put more blocks on every compute unit, which hides
+  // the latency of the three dependent phases better than a larger share of
+  // the table set-up
+  constexpr int eb1 = !res_tables<D, P, R>() ? eb0 : (256 / C::QV < 1 ? 1 : 256 / C::QV);
+  return eb0 < eb1 ? eb0 : eb1;
 }
 
 template <int D, int P, class R>
@@ -2321,13 +2541,13 @@ GasT<R> gas_as(const Gas& g) {
 
 template <int D, int P, class R>
 hipError_t residual_t(const DevMesh& M, const TabData& td, const double* ut, const double* fadd, double* rt,
-                      hipStream_t st) {
+                      const FasOut& fas, hipStream_t st) {
   Tab<D, P, R> t;
   fill_tab(t, td);
   constexpr int EB = res_tile<D, P, R>();
   const int grid = (M.ne + EB - 1) / EB;
   hipLaunchKernelGGL((k_residual<D, P, EB, R>), dim3(grid), dim3(256), 0, st, ut, fadd, rt, M.xv, M.nbr, M.ncode,
-                     M.ne, t, gas_as<R>(M.gas), M.uinf_e);
+                     M.ne, t, gas_as<R>(M.gas), M.uinf_e, fas);
   return hipGetLastError();
 }
 
@@ -2398,7 +2618,8 @@ hipError_t norm_t(const DevMesh& M, const double* rt, double* part, double* out,
                        out);
     return hipGetLastError();
   }
-  const int nblk = (M.ne + 255) / 256;
+  constexpr int EPB = 256 / norm_group<N>();  // elements per block; part holds >= ne / 4 + 1 values
+  const int nblk = (M.ne + EPB - 1) / EPB;
   hipLaunchKernelGGL((k_norm_partial<D, N>), dim3(nblk), dim3(256), 0, st, rt, M.Lpk, M.NT, M.ne, part);
   hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, st, part, nblk, M.omega, out);
   return hipGetLastError();
@@ -2424,14 +2645,14 @@ hipError_t jac_to_psi_t(const DevMesh& M, double* Dm, hipStream_t st) {
   }
 
 hipError_t launch_residual(const DevMesh& M, const TabData& td, int p, const double* ut, const double* fadd,
-                           double* rt, int prec, hipStream_t st) {
+                           double* rt, int prec, hipStream_t st, const FasOut& fas) {
   if (prec == PREC_FP32) {
-#define CALL_RES(DD, PP) residual_t<DD, PP, float>(M, td, ut, fadd, rt, st)
+#define CALL_RES(DD, PP) residual_t<DD, PP, float>(M, td, ut, fadd, rt, fas, st)
     if (M.d == 2) { EG_DISPATCH_P(2, p, CALL_RES) }
     else { EG_DISPATCH_P(3, p, CALL_RES) }
 #undef CALL_RES
   } else {
-#define CALL_RES(DD, PP) residual_t<DD, PP, double>(M, td, ut, fadd, rt, st)
+#define CALL_RES(DD, PP) residual_t<DD, PP, double>(M, td, ut, fadd, rt, fas, st)
     if (M.d == 2) { EG_DISPATCH_P(2, p, CALL_RES) }
     else { EG_DISPATCH_P(3, p, CALL_RES) }
 #undef CALL_RES
@@ -2484,30 +2705,32 @@ hipError_t launch_jacobian(const DevMesh& M, const TabData& td, int p, const dou
 
 template <class R>
 static hipError_t launch_prk_stage_r(const DevMesh& M, int n, const R* F, const int* perm, const double* rt,
-                                     const double* ft, const double* un, double* ut, double beta, hipStream_t st) {
+                                     const double* ft, const double* un, double* ut, double* save, double beta,
+                                     hipStream_t st) {
   const int grid = (M.ne + 3) / 4;
   if (!ft) {
     switch (n) {
-      case 16: hipLaunchKernelGGL((k_prk_stage_t<16, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
-      case 36: hipLaunchKernelGGL((k_prk_stage_t<36, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
-      case 64: hipLaunchKernelGGL((k_prk_stage_t<64, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
-      case 40: hipLaunchKernelGGL((k_prk_stage_t<40, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); return hipGetLastError();
+      case 16: hipLaunchKernelGGL((k_prk_stage_t<16, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
+      case 36: hipLaunchKernelGGL((k_prk_stage_t<36, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
+      case 64: hipLaunchKernelGGL((k_prk_stage_t<64, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
+      case 40: hipLaunchKernelGGL((k_prk_stage_t<40, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
       default: break;
     }
   }
-  if (n <= 64) hipLaunchKernelGGL((k_prk_stage<1, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
-  else if (n <= 128) hipLaunchKernelGGL((k_prk_stage<2, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
-  else if (n <= 192) hipLaunchKernelGGL((k_prk_stage<3, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
-  else if (n <= 320) hipLaunchKernelGGL((k_prk_stage<5, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, beta, n, M.ne);
+  if (n <= 64) hipLaunchKernelGGL((k_prk_stage<1, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, save, beta, n, M.ne);
+  else if (n <= 128) hipLaunchKernelGGL((k_prk_stage<2, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, save, beta, n, M.ne);
+  else if (n <= 192) hipLaunchKernelGGL((k_prk_stage<3, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, save, beta, n, M.ne);
+  else if (n <= 320) hipLaunchKernelGGL((k_prk_stage<5, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, ft, un, ut, save, beta, n, M.ne);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_prk_stage(const DevMesh& M, int n, const void* F, const int* perm, const double* rt,
-                            const double* ft, const double* un, double* ut, double beta, int prec, hipStream_t st) {
+                            const double* ft, const double* un, double* ut, double beta, int prec, hipStream_t st,
+                            double* save) {
   if (prec == PREC_FP32)
-    return launch_prk_stage_r<float>(M, n, static_cast<const float*>(F), perm, rt, ft, un, ut, beta, st);
-  return launch_prk_stage_r<double>(M, n, static_cast<const double*>(F), perm, rt, ft, un, ut, beta, st);
+    return launch_prk_stage_r<float>(M, n, static_cast<const float*>(F), perm, rt, ft, un, ut, save, beta, st);
+  return launch_prk_stage_r<double>(M, n, static_cast<const double*>(F), perm, rt, ft, un, ut, save, beta, st);
 }
 
 hipError_t launch_basis(const DevMesh& M, int N, const double* x, double* y, int mode, hipStream_t st) {
@@ -2544,18 +2767,6 @@ hipError_t launch_restrict(const DevMesh& M, int p, const double* ut, double* uc
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_fas(int N, int Nc, int rows, const double* rhat, double* rc, double* fc, hipStream_t st) {
-  const int cnt = rows * Nc;
-  hipLaunchKernelGGL(k_fas, dim3((cnt + 255) / 256), dim3(256), 0, st, rhat, rc, fc, N, Nc, rows);
-  return hipGetLastError();
-}
-
-hipError_t launch_prolong(int N, int Nc, int rows, double* ut, const double* uc, const double* uc0, hipStream_t st) {
-  const int cnt = rows * Nc;
-  hipLaunchKernelGGL(k_prolong, dim3((cnt + 255) / 256), dim3(256), 0, st, ut, uc, uc0, N, Nc, rows);
-  return hipGetLastError();
-}
-
 // CFL source of the time-step kernels: a per-element array (batch), a
 // device scalar (captured V-cycles), or the host value passed by argument.
 static const double* cfl_ptr(const DevMesh& M) { return M.cfl_e ? M.cfl_e : M.cfl_one; }
@@ -2563,7 +2774,7 @@ static int cfl_stride(const DevMesh& M) { return M.cfl_e ? 1 : 0; }
 
 hipError_t launch_timestep(const DevMesh& M, int p, int N, double cfl, double mult, const double* ut, double* dtau,
                            hipStream_t st) {
-  const int grid = (M.ne + 255) / 256;
+  const int grid = (M.ne + 15) / 16;  // 16 lanes per element
   if (M.d == 2)
     hipLaunchKernelGGL((k_timestep<2>), dim3(grid), dim3(256), 0, st, ut, N, M.Lpk, M.NT, M.hE, p, cfl, mult, dtau,
                        M.ne, M.gas.g, cfl_ptr(M), cfl_stride(M));
@@ -2597,12 +2808,13 @@ hipError_t launch_norm(const DevMesh& M, int N, const double* rt, double* part, 
 
 hipError_t launch_p0_setup(const DevMesh& M, const double* ut0, const double* ft0, int pmax, double cfl, int scale,
                            double* u0, double* b, double* Ad, double* Ao, double* dt, hipStream_t st) {
-  const int grid = (M.ne + 127) / 128;
+  // 8 (2D) or 32 (3D) lanes per element
+  const int grid = M.d == 2 ? (M.ne + 31) / 32 : (M.ne + 7) / 8;
   if (M.d == 2)
-    hipLaunchKernelGGL((k_p0_setup<2>), dim3(grid), dim3(128), 0, st, ut0, ft0, M.xv, M.nbr, M.Lpk, M.NT, M.hE, pmax,
+    hipLaunchKernelGGL((k_p0_setup<2>), dim3(grid), dim3(256), 0, st, ut0, ft0, M.xv, M.nbr, M.Lpk, M.NT, M.hE, pmax,
                        cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w, M.uinf_e, cfl_ptr(M), cfl_stride(M));
   else
-    hipLaunchKernelGGL((k_p0_setup<3>), dim3(grid), dim3(128), 0, st, ut0, ft0, M.xv, M.nbr, M.Lpk, M.NT, M.hE, pmax,
+    hipLaunchKernelGGL((k_p0_setup<3>), dim3(grid), dim3(256), 0, st, ut0, ft0, M.xv, M.nbr, M.Lpk, M.NT, M.hE, pmax,
                        cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w, M.uinf_e, cfl_ptr(M), cfl_stride(M));
   return hipGetLastError();
 }
@@ -2680,13 +2892,18 @@ hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, c
 hipError_t launch_phi1(int m, int nseg, const double* H, const double* H2, const double* info, double* y, int* fail,
                        hipStream_t st) {
   const size_t lds = (size_t)8 * (m + 1) * (m + 1) * 8;
+  if (m + 1 <= 32) {
+    // 8 matrices of order <= 32: 64 KiB, within the default limit
+    hipLaunchKernelGGL(k_phi1<true>, dim3(nseg), dim3(256), lds, st, H, H2, m, info, y, fail);
+    return hipGetLastError();
+  }
   static size_t attr_lds = 0;  // largest size set so far
   if (lds > attr_lds) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_phi1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void*)k_phi1<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_lds = lds;
   }
-  hipLaunchKernelGGL(k_phi1, dim3(nseg), dim3(256), lds, st, H, H2, m, info, y, fail);
+  hipLaunchKernelGGL(k_phi1<false>, dim3(nseg), dim3(256), lds, st, H, H2, m, info, y, fail);
   return hipGetLastError();
 }
 
@@ -2695,6 +2912,16 @@ hipError_t launch_exp1_update(const DevMesh& M, int m, const double* Vb, const d
   const int K = M.ne * M.V;
   hipLaunchKernelGGL(k_exp1_update, dim3((K + 255) / 256), dim3(256), 0, st, K, M.V, Vb, y, info, u0, M.Lpk, M.NT,
                      ut0, M.sid, m + 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_exp1_prolong(const DevMesh& M, int m, const double* Vb, const double* y, const double* info,
+                               const double* u0, const UpChain& c, hipStream_t st) {
+  if (c.pmax < 1 || c.pmax > 4) return hipErrorInvalidValue;
+  const int K = M.ne * M.V;
+  const size_t T = (size_t)K * c.N[c.pmax - 1];
+  hipLaunchKernelGGL(k_exp1_prolong, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st, K, M.V, Vb, y, info, u0,
+                     M.Lpk, M.NT, M.sid, m + 1, c);
   return hipGetLastError();
 }
 

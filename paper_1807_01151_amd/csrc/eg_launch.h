@@ -54,18 +54,26 @@ struct TabData {
   int m[128][3];
 };
 
+// FAS form of the residual output: with rhat set, rt receives the fine
+// residual rhat (Nf modes per row) truncated to the level's modes and fc the
+// forcing rt - R (fc = fine - coarse); fadd must then be null.
+struct FasOut {
+  const double* rhat = nullptr;
+  int Nf = 0;
+  double* fc = nullptr;
+};
 hipError_t launch_residual(const DevMesh& M, const TabData& td, int p, const double* ut, const double* fadd,
-                           double* rt, int prec, hipStream_t st);
+                           double* rt, int prec, hipStream_t st, const FasOut& fas = FasOut{});
 bool jacobian_supported(int d, int p);
 hipError_t launch_jacobian(const DevMesh& M, const TabData& td, int p, const double* ut, const double* dtau,
                            void* out, int* perm, int* fail, bool factor, int prec, hipStream_t st);
+// un null: the stage starts from ut and, if save is set, stores it there
 hipError_t launch_prk_stage(const DevMesh& M, int n, const void* F, const int* perm, const double* rt,
-                            const double* ft, const double* un, double* ut, double beta, int prec, hipStream_t st);
+                            const double* ft, const double* un, double* ut, double beta, int prec, hipStream_t st,
+                            double* save = nullptr);
 hipError_t launch_sub(const double* a, const double* b, double* out, size_t n, hipStream_t st);
 hipError_t launch_basis(const DevMesh& M, int N, const double* x, double* y, int mode, hipStream_t st);
 hipError_t launch_restrict(const DevMesh& M, int p, const double* ut, double* uc, double* uc0, hipStream_t st);
-hipError_t launch_fas(int N, int Nc, int rows, const double* rhat, double* rc, double* fc, hipStream_t st);
-hipError_t launch_prolong(int N, int Nc, int rows, double* ut, const double* uc, const double* uc0, hipStream_t st);
 hipError_t launch_timestep(const DevMesh& M, int p, int N, double cfl, double mult, const double* ut, double* dtau,
                            hipStream_t st);
 hipError_t launch_norm(const DevMesh& M, int N, const double* rt, double* part, double* out, hipStream_t st);
@@ -79,6 +87,17 @@ hipError_t launch_phi1(int m, int nseg, const double* H, const double* H2, const
                        hipStream_t st);
 hipError_t launch_exp1_update(const DevMesh& M, int m, const double* Vb, const double* y, const double* info,
                               const double* u0, double* ut0, hipStream_t st);
+// Levels 0..pmax of the V-cycle state: ut[l] and the restricted copies
+// uc0[l] (N[l] modes per row); pmax <= 4.
+struct UpChain {
+  double* ut[5];
+  const double* uc0[5];
+  int N[5];
+  int pmax;
+};
+// EXP1 update of ut[0] followed by the prolongations to levels 1..pmax.
+hipError_t launch_exp1_prolong(const DevMesh& M, int m, const double* Vb, const double* y, const double* info,
+                               const double* u0, const UpChain& c, hipStream_t st);
 hipError_t launch_nbr_export(const DevMesh& M, int* out, hipStream_t st);
 hipError_t launch_copy(const double* a, double* b, size_t n, hipStream_t st);
 hipError_t launch_freestream(const DevMesh& M, int N, double* u, hipStream_t st);
