@@ -833,21 +833,25 @@ __global__ __launch_bounds__(256, 3) void k_jaclu_wave(const R* __restrict__ BC,
   R acc[n];
 #pragma unroll
   for (int c = 0; c < n; ++c) acc[c] = R(0);
+  // volume points: the D directions are summed per point before the
+  // product with phi_j, so the row update runs once per point
 #pragma unroll 1
   for (int q = 0; q < QV; ++q) {
+    R bw[V];
+#pragma unroll
+    for (int w = 0; w < V; ++w) bw[w] = R(0);
 #pragma unroll
     for (int r = 0; r < D; ++r) {
       const R a = s_dph[(q * D + r) * N + i];
       const R* B = &sB[((q * D + r) * V + v) * V];
-      R bw[V];
 #pragma unroll
-      for (int w = 0; w < V; ++w) bw[w] = a * B[w];
+      for (int w = 0; w < V; ++w) bw[w] += a * B[w];
+    }
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        const R ph = s_phv[q * N + j];
+    for (int j = 0; j < N; ++j) {
+      const R ph = s_phv[q * N + j];
 #pragma unroll
-        for (int w = 0; w < V; ++w) acc[w * N + j] += bw[w] * ph;
-      }
+      for (int w = 0; w < V; ++w) acc[w * N + j] += bw[w] * ph;
     }
   }
 #pragma unroll 1
