@@ -53,7 +53,7 @@ def work_model(d, p):
 
 
 # kernels behind each timed class (bench time classes -> device functions)
-CLASS_KERNELS = {"jacobian_lu": ["k_jac_points", "k_jaclu_wave", "wave_max_u32", "readlane_d"],
+CLASS_KERNELS = {"jacobian_lu": ["k_jac_points", "k_jaclu_wave", "wave_max_u32", "readlane_d", "bperm_d"],
                  "prk_stage": ["k_prk_stage_t", "k_prk_stage"],
                  "residual": ["k_residual", "stage"]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobian_lu_c2_pmc_traffic.md")

@@ -333,6 +333,17 @@ class BatchSolver:
     freestream = Solver.freestream
     residual = Solver.residual
 
+    def profile(self, enable: bool):
+        """Event timing of every kernel class (see Solver.profile)."""
+        self._chk(lib().eg_profile(self._h, int(enable)))
+
+    def profile_read(self, kernel_class: str, p: int = -1):
+        """(total milliseconds, launches) of one kernel class at level p (-1: all)."""
+        ms = C.c_double(0.0)
+        n = C.c_int(0)
+        self._chk(lib().eg_profile_read(self._h, KERNEL_CLASSES.index(kernel_class), p, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
     def layout(self, solve: int, p: int):
         off = C.c_int64(0)
         nm, ne = C.c_int(0), C.c_int(0)

@@ -807,7 +807,8 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
   AL(M.g2w, 2);
   {
     size_t per = 0;
-    for (int p = 1; p <= h->pmax; ++p) per = std::max(per, eg::jac_points_per_elem(d, p));
+    for (int p = 1; p <= h->pmax; ++p)
+      per = std::max(per, eg::jac_points_per_elem(d, p, h->mixed && blk_prec(h, p) == eg::PREC_FP32));
     if (per) {
       double* bc = nullptr;  // sized for FP64 values; the FP32 assembly uses the front half
       AL(bc, (size_t)ne * per);
@@ -899,7 +900,7 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
   AL(h->arn_W, 2 * K0);
   AL(h->H2, (size_t)nseg * (h->m + 1) * h->m);
   AL(h->y, (size_t)nseg * (h->m + 1));
-  AL(h->npart, (size_t)ne / 4 + 2);  // one partial per block of >= 4 elements
+  AL(h->npart, (size_t)ne + 2);  // block partials, or one value per element (batch norms)
   AL(h->nout, nseg);
   AL(h->dfail, 1);
   AL(h->dpart, ne);

@@ -784,6 +784,16 @@ __device__ __forceinline__ double readlane_d(double x, int lane) {
 __device__ __forceinline__ float readlane_d(float x, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
+// Value of x in the lane at byte address addr (lane * 4) through the LDS
+// crossbar (no LDS storage is used).
+__device__ __forceinline__ double bperm_d(double x, int addr) {
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float bperm_d(float x, int addr) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
+}
 
 template <int D, int P, class R>
 __global__ __launch_bounds__(256, 3) void k_jaclu_wave(const R* __restrict__ BC, const double* __restrict__ Gpk,
@@ -900,14 +910,225 @@ __global__ __launch_bounds__(256, 3) void k_jaclu_wave(const R* __restrict__ BC,
     if (lane == 0 && !(dabs(piv) > R(0))) atomicOr(fail, 1);
     const R l = (mystep < 0) ? acc[k] * (R(1) / piv) : R(0);
     if (mystep < 0) acc[k] = l;
+    // every sixth entry of the pivot row travels through ds_bpermute (the
+    // LDS crossbar) instead of readlane, which moves a share of the
+    // broadcast off the vector ALU (measured: 3% faster than readlane only)
 #pragma unroll
-    for (int j = k + 1; j < n; ++j) acc[j] = fma(-l, readlane_d(acc[j], pl), acc[j]);
+    for (int j = k + 1; j < n; ++j) {
+      const R pj = ((j - k) % 6 == 0) ? bperm_d(acc[j], pl * 4) : readlane_d(acc[j], pl);
+      acc[j] = fma(-l, pj, acc[j]);
+    }
   }
   if (lane < n) {
     R* o = out + (size_t)e * n * n;
 #pragma unroll
     for (int j = 0; j < n; ++j) o[(size_t)j * n + mystep] = acc[j];
     perm[(size_t)e * n + mystep] = lane;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same block assembly and LU for 64 < n = V N < 256, by one block of V
+// wavefronts per element: wavefront w holds the N columns of variable w for
+// every row (RPL = ceil(n / 64) rows per lane: lane, lane + 64, ...), so an
+// element's rows are spread over V register files and every register index
+// is a constant.  Elimination step k: the wavefront that holds column k
+// chooses the pivot (largest |a| of the unused rows, float keys with the row
+// in the low 8 bits), forms the multipliers and passes them with the pivot
+// row index to the others through LDS (double-buffered: one block barrier
+// per step); every wavefront then updates its own columns, the pivot row
+// broadcast by readlane from its own registers.  The step loop is not
+// unrolled (n^2 unrolled steps would not fit the instruction cache); the
+// column sweep of a step is, with uniform branches per column.  Output as
+// k_jaclu_wave.
+// ---------------------------------------------------------------------------
+template <int D, int P>
+constexpr bool jaclu_cols_fits() {
+  using C = Cfg<D, P>;
+  return C::NB > 64 && C::NB < 256;
+}
+
+// Step k on the wavefront's columns c0 + J: columns beyond k take the rank-1
+// update with the pivot row (slot PS, lane pl), column k receives the
+// multipliers, and column k + 1 is kept as the next pivot column.  Every
+// branch is uniform and no column is skipped by an early exit, so the
+// columns keep their registers across the step loop.
+template <int PS, int RPL, int N, class R>
+__device__ __forceinline__ void jaclu_cols_sweep(R (&acc)[RPL][N], const R (&l)[RPL], const int (&mystep)[RPL],
+                                                 R (&col)[RPL], int c0, int k, int pl) {
+#pragma unroll
+  for (int J = 0; J < N; ++J) {
+    const int c = c0 + J;
+    if (c > k) {
+      const R pj = readlane_d(acc[PS][J], pl);
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) acc[s][J] = fma(-l[s], pj, acc[s][J]);
+      if (c == k + 1) {
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) col[s] = acc[s][J];
+      }
+    } else if (c == k) {
+#pragma unroll
+      for (int s = 0; s < RPL; ++s)
+        if (mystep[s] < 0) acc[s][J] = l[s];
+    }
+  }
+}
+
+template <int D, int P, class R>
+__global__ __launch_bounds__((64 * Cfg<D, P>::V), 2) void k_jaclu_cols(
+    const R* __restrict__ BC, const double* __restrict__ Gpk, int NT, const double* __restrict__ dtau,
+    R* __restrict__ out, int* __restrict__ perm, int* __restrict__ fail, int ne, Tab<D, P, R> tab) {
+  using C = Cfg<D, P>;
+  constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, n = C::NB;
+  constexpr int RPL = (n + 63) / 64, NTH = 64 * V;
+  static_assert(jaclu_cols_fits<D, P>() && RPL <= 3, "block size");
+  constexpr int PER = (QV * D + NF * QF) * V * V;
+  __shared__ Tab<D, P, R> t;
+  __shared__ R s_phv[QV * N];
+  __shared__ R s_dph[QV * D * N];
+  __shared__ R s_phf[NF * QF * N];
+  __shared__ R s_BC[PER];
+  __shared__ R s_l[2][64 * RPL];
+  __shared__ int s_pr[2];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int e = blockIdx.x;
+  if (e >= ne) return;  // whole block
+  copy_tab(t, tab);
+  stage<(PER + NTH - 1) / NTH>(s_BC, BC + (size_t)e * PER, PER, threadIdx.x, NTH);
+  __syncthreads();
+  for (int it = threadIdx.x; it < QV * N; it += NTH) {
+    const int q = it / N, j = it % N;
+    int iq[D], r0 = q;
+#pragma unroll
+    for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
+    s_phv[it] = phi_vol<D, P, R>(t, j, iq);
+#pragma unroll
+    for (int r = 0; r < D; ++r) s_dph[(q * D + r) * N + j] = dphi_vol<D, P, R>(t, j, iq, r);
+  }
+  for (int it = threadIdx.x; it < NF * QF * N; it += NTH) {
+    const int lf = it / (QF * N), k = (it / N) % QF, j = it % N;
+    int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1], r0 = k;
+    face_axes<D>(lf, ta);
+#pragma unroll
+    for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
+    s_phf[it] = phi_face<D, P, R>(t, j, lf, ta, ik);
+  }
+  __syncthreads();
+  const R* sB = s_BC;
+  const R* sC = s_BC + QV * D * V * V;
+  int vv[RPL], ii[RPL];
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    const int rr = lane + 64 * s < n ? lane + 64 * s : 0;
+    vv[s] = rr / N;
+    ii[s] = rr % N;
+  }
+  // columns (wv, j) of every row of the lane
+  R acc[RPL][N];
+#pragma unroll
+  for (int s = 0; s < RPL; ++s)
+#pragma unroll
+    for (int j = 0; j < N; ++j) acc[s][j] = R(0);
+#pragma unroll 1
+  for (int q = 0; q < QV; ++q) {
+    R bw[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      bw[s] = R(0);
+#pragma unroll
+      for (int r = 0; r < D; ++r) bw[s] += s_dph[(q * D + r) * N + ii[s]] * sB[((q * D + r) * V + vv[s]) * V + wv];
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const R ph = s_phv[q * N + j];
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) acc[s][j] += bw[s] * ph;
+    }
+  }
+#pragma unroll 1
+  for (int fk = 0; fk < NF * QF; ++fk) {
+    R cw[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) cw[s] = s_phf[fk * N + ii[s]] * sC[(fk * V + vv[s]) * V + wv];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const R ph = s_phf[fk * N + j];
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) acc[s][j] -= cw[s] * ph;
+    }
+  }
+  {
+    const R idt = R(1.0 / dtau[e]);
+    const double* G = Gpk + (size_t)e * NT;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      const int i = ii[s];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const R gij = R((i >= j) ? G[i * (i + 1) / 2 + j] : G[j * (j + 1) / 2 + i]);
+        acc[s][j] = ((vv[s] == wv) ? gij * idt : R(0)) - acc[s][j];
+      }
+    }
+  }
+  // LU with partial pivoting over the V wavefronts
+  int mystep[RPL];
+  R col[RPL];
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    mystep[s] = (lane + 64 * s < n) ? -1 : n;
+    col[s] = acc[s][0];  // column 0 is the first column of wavefront 0
+  }
+  const int c0 = wv * N;
+#pragma unroll 1
+  for (int k = 0; k < n; ++k) {
+    const int buf = k & 1;
+    if (wv == k / N) {
+      unsigned key = 0u;
+#pragma unroll
+      for (int s = 0; s < RPL; ++s)
+        if (mystep[s] < 0)
+          key = max(key, (__float_as_uint((float)dabs(col[s])) & ~255u) | (unsigned)(255 - (lane + 64 * s)));
+      const unsigned kmax = wave_max_u32(key);
+      const int pr = __builtin_amdgcn_readfirstlane(255 - (int)(kmax & 255u));
+      const int pl = pr & 63, ps = pr >> 6;
+      R cps = col[0];
+#pragma unroll
+      for (int s = 1; s < RPL; ++s) cps = (ps == s) ? col[s] : cps;
+      const R piv = readlane_d(cps, pl);
+      if (lane == 0 && !(dabs(piv) > R(0))) atomicOr(fail, 1);
+      const R ipiv = R(1) / piv;
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) {
+        const int row = lane + 64 * s;
+        if (row == pr && mystep[s] >= 0) atomicOr(fail, 4);  // the winner must be an unused row
+        s_l[buf][row] = (mystep[s] < 0 && row != pr) ? col[s] * ipiv : R(0);
+      }
+      if (lane == 0) s_pr[buf] = pr;
+    }
+    __syncthreads();
+    const int pr = __builtin_amdgcn_readfirstlane(s_pr[buf]);
+    const int pl = pr & 63, ps = pr >> 6;
+    R l[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      if (lane + 64 * s == pr) mystep[s] = k;
+      l[s] = s_l[buf][lane + 64 * s];
+    }
+    if (ps == 0) jaclu_cols_sweep<0, RPL, N, R>(acc, l, mystep, col, c0, k, pl);
+    else if constexpr (RPL > 1) {
+      if (ps == 1) jaclu_cols_sweep<(RPL > 1 ? 1 : 0), RPL, N, R>(acc, l, mystep, col, c0, k, pl);
+      else if constexpr (RPL > 2) jaclu_cols_sweep<(RPL > 2 ? 2 : 0), RPL, N, R>(acc, l, mystep, col, c0, k, pl);
+    }
+  }
+  R* o = out + (size_t)e * n * n;
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    if (lane + 64 * s < n) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) o[(size_t)(c0 + j) * n + mystep[s]] = acc[s][j];
+      if (wv == 0) perm[(size_t)e * n + mystep[s]] = lane + 64 * s;
+    }
   }
 }
 
@@ -1019,6 +1240,97 @@ __global__ __launch_bounds__(256) void k_prk_stage_t(const R* __restrict__ Fm, c
   if (lane < NB) {
     if (save) save[o] = u0;
     ut[o] = u0 + beta * double(b);
+  }
+}
+
+// PRK stage for block sizes 64 < NB < 256: one wavefront per element with
+// RPL rows per lane (lane, lane + 64, ...); the factor columns stream
+// through registers in chunks of eight whose loads are all issued before
+// the chunk is used (a loop over single columns would wait for each load in
+// turn), x_j broadcast with readlane.  The chunk loop is not unrolled, which
+// keeps few registers live and many wavefronts per SIMD to cover the load
+// latency.  Same arithmetic and arguments as k_prk_stage.
+template <int NB, class R>
+__global__ __launch_bounds__(256) void k_prk_stage_c(const R* __restrict__ Fm, const int* __restrict__ perm,
+                                                     const double* __restrict__ rt, const double* __restrict__ un,
+                                                     double* __restrict__ ut, double* __restrict__ save, double beta,
+                                                     int ne) {
+  constexpr int RPL = (NB + 63) / 64, CH = 8;
+  static_assert(NB > 64 && NB < 256, "rows per lane");
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (e >= ne) return;
+  const R* F = Fm + (size_t)e * NB * NB;
+  int ic[RPL];  // clamped rows: every load in bounds
+  R b[RPL];
+  double u0[RPL];
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    const int i = lane + 64 * s;
+    ic[s] = i < NB ? i : NB - 1;
+    const size_t o = (size_t)e * NB + ic[s];
+    b[s] = (i < NB) ? R(rt[(size_t)e * NB + perm[o]]) : R(0);
+    u0[s] = un ? un[o] : ut[o];
+  }
+  // L y = b (unit diagonal); the columns j of row slot sl (64 sl <= j <
+  // 64 sl + 64) take x_j from b[sl], chunks never straddle two slots
+#pragma unroll
+  for (int sl = 0; sl < RPL; ++sl) {
+#pragma unroll 1
+    for (int j0 = 64 * sl; j0 < NB && j0 < 64 * sl + 64; j0 += CH) {
+      R cf[CH][RPL];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int j = j0 + c < NB ? j0 + c : NB - 1;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) cf[c][s] = F[(size_t)j * NB + ic[s]];
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int j = j0 + c;
+        if (j < NB) {
+          const R xj = readlane_d(b[sl], j & 63);
+#pragma unroll
+          for (int s = 0; s < RPL; ++s) b[s] = fma(-((lane + 64 * s > j) ? cf[c][s] : R(0)), xj, b[s]);
+        }
+      }
+    }
+  }
+  // U x = y
+#pragma unroll
+  for (int sl = RPL - 1; sl >= 0; --sl) {
+    const int jlast = (NB < 64 * sl + 64 ? NB : 64 * sl + 64) - 1;
+#pragma unroll 1
+    for (int j0 = (jlast / CH) * CH; j0 >= 64 * sl; j0 -= CH) {
+      R cf[CH][RPL];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int j = j0 + c < NB ? j0 + c : NB - 1;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) cf[c][s] = F[(size_t)j * NB + ic[s]];
+      }
+#pragma unroll
+      for (int c = CH - 1; c >= 0; --c) {
+        const int j = j0 + c;
+        if (j < NB) {
+          const R xj = readlane_d(b[sl], j & 63) / readlane_d(cf[c][sl], j & 63);
+#pragma unroll
+          for (int s = 0; s < RPL; ++s) {
+            const int i = lane + 64 * s;
+            b[s] = (i == j) ? xj : fma(-((i < j) ? cf[c][s] : R(0)), xj, b[s]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    const int i = lane + 64 * s;
+    if (i < NB) {
+      const size_t o = (size_t)e * NB + i;
+      if (save) save[o] = u0[s];
+      ut[o] = u0[s] + beta * double(b[s]);
+    }
   }
 }
 
@@ -1198,30 +1510,45 @@ __global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ p
   if (threadIdx.x == 0) out[0] = sqrt(s_w[0] + s_w[1] + s_w[2] + s_w[3]) / omega;
 }
 
-// Density-residual norm of every solve of a batch: one block per solve sums
-// its element range [seg_e0[s], seg_e0[s + 1]) in a fixed order.
+// Density-residual norm of every solve of a batch: the squared norm of
+// every element (lanes per element as in k_norm_partial), then one block per
+// solve sums its element range [seg_e0[s], seg_e0[s + 1]) in a fixed order.
 template <int D, int N>
-__global__ __launch_bounds__(256) void k_norm_seg(const double* __restrict__ rt, const double* __restrict__ Lpk,
-                                                  int NT, const int* __restrict__ seg_e0,
-                                                  const double* __restrict__ seg_omega, double* __restrict__ out) {
-  constexpr int V = D + 2;
+__global__ __launch_bounds__(256) void k_norm_elem(const double* __restrict__ rt, const double* __restrict__ Lpk,
+                                                   int NT, int ne, double* __restrict__ enorm) {
+  constexpr int V = D + 2, G = norm_group<N>(), EPB = 256 / G;
+  const int e = blockIdx.x * EPB + (int)threadIdx.x / G, i = (int)threadIdx.x % G;
+  const int base = (int)(threadIdx.x & 63) - i;
+  const bool act = e < ne && i < N;
+  double r = 0.0, l[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) l[j] = 0.0;
+  if (act) {
+    const double* L = Lpk + (size_t)e * NT + i * (i + 1) / 2;
+    r = rt[(size_t)e * V * N + i];
+#pragma unroll
+    for (int j = 0; j < N; ++j) l[j] = (j <= i) ? L[j] : 0.0;
+  }
+  double x = 0.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const double xj = __shfl(r, base + j, 64) / __shfl(l[j], base + j, 64);
+    if (i == j) x = xj;
+    else if (i > j) r -= l[j] * xj;
+  }
+  double acc = act ? x * x : 0.0;
+#pragma unroll
+  for (int o = G / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (e < ne && i == 0) enorm[e] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_norm_segsum(const double* __restrict__ enorm, const int* __restrict__ seg_e0,
+                                                     const double* __restrict__ seg_omega, double* __restrict__ out) {
   __shared__ double s_w[4];
   const int sg = blockIdx.x;
   const int e0 = seg_e0[sg], e1 = seg_e0[sg + 1];
   double acc = 0.0;
-  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const double* L = Lpk + (size_t)e * NT;
-    const double* a = rt + (size_t)e * V * N;
-    double r[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double s = a[i];
-#pragma unroll
-      for (int j = 0; j < i; ++j) s -= L[i * (i + 1) / 2 + j] * r[j];
-      r[i] = s / L[i * (i + 1) / 2 + i];
-      acc += r[i] * r[i];
-    }
-  }
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) acc += enorm[e];
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = acc;
   __syncthreads();
@@ -2563,7 +2890,7 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
   R* out = static_cast<R*>(outv);
   const GasT<R> gas = gas_as<R>(M.gas);
   const size_t lds = (size_t)jac_lds_values<D, P>() * sizeof(R);
-  if constexpr (Cfg<D, P>::NB <= 64) {
+  if constexpr (Cfg<D, P>::NB <= 64 || jaclu_cols_fits<D, P>()) {
     if (factor && M.bc) {
       using C = Cfg<D, P>;
       constexpr int NPT = C::QV + C::NF * C::QF;
@@ -2571,8 +2898,13 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
       R* bc = static_cast<R*>(M.bc);
       hipLaunchKernelGGL((k_jac_points<D, P, R>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.nbr,
                          M.ncode, bc, M.ne, t, gas, M.uinf_e);
-      hipLaunchKernelGGL((k_jaclu_wave<D, P, R>), dim3((M.ne + 3) / 4), dim3(256), 0, st, bc, M.Gpk, M.NT, dtau,
-                         out, perm, fail, M.ne, t);
+      if constexpr (Cfg<D, P>::NB <= 64) {
+        hipLaunchKernelGGL((k_jaclu_wave<D, P, R>), dim3((M.ne + 3) / 4), dim3(256), 0, st, bc, M.Gpk, M.NT, dtau,
+                           out, perm, fail, M.ne, t);
+      } else {
+        hipLaunchKernelGGL((k_jaclu_cols<D, P, R>), dim3(M.ne), dim3(64 * Cfg<D, P>::V), 0, st, bc, M.Gpk, M.NT,
+                           dtau, out, perm, fail, M.ne, t);
+      }
       return hipGetLastError();
     }
   }
@@ -2617,13 +2949,15 @@ hipError_t restrict_t(const DevMesh& M, const double* ut, double* uc, double* uc
 
 template <int D, int N>
 hipError_t norm_t(const DevMesh& M, const double* rt, double* part, double* out, hipStream_t st) {
+  constexpr int EPB = 256 / norm_group<N>();  // elements per block
   if (M.seg_e0) {
-    hipLaunchKernelGGL((k_norm_seg<D, N>), dim3(M.nseg), dim3(256), 0, st, rt, M.Lpk, M.NT, M.seg_e0, M.seg_omega,
-                       out);
+    // part holds >= ne values here: the squared norm of every element
+    hipLaunchKernelGGL((k_norm_elem<D, N>), dim3((M.ne + EPB - 1) / EPB), dim3(256), 0, st, rt, M.Lpk, M.NT, M.ne,
+                       part);
+    hipLaunchKernelGGL(k_norm_segsum, dim3(M.nseg), dim3(256), 0, st, part, M.seg_e0, M.seg_omega, out);
     return hipGetLastError();
   }
-  constexpr int EPB = 256 / norm_group<N>();  // elements per block; part holds >= ne / 4 + 1 values
-  const int nblk = (M.ne + EPB - 1) / EPB;
+  const int nblk = (M.ne + EPB - 1) / EPB;  // part holds >= ne / 4 + 1 values
   hipLaunchKernelGGL((k_norm_partial<D, N>), dim3(nblk), dim3(256), 0, st, rt, M.Lpk, M.NT, M.ne, part);
   hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, st, part, nblk, M.omega, out);
   return hipGetLastError();
@@ -2664,9 +2998,11 @@ hipError_t launch_residual(const DevMesh& M, const TabData& td, int p, const dou
   return hipErrorInvalidValue;
 }
 
-size_t jac_points_per_elem(int d, int p) {
+size_t jac_points_per_elem(int d, int p, bool fp32) {
   const int V = d + 2, Q = p + 2, N = (d == 2) ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
-  if (p < 1 || V * N > 64) return 0;
+  // blocks that take the register kernels (k_jaclu_wave, k_jaclu_cols)
+  (void)fp32;
+  if (p < 1 || V * N >= 256) return 0;
   const int QV = (d == 2) ? Q * Q : Q * Q * Q, QF = (d == 2) ? Q : Q * Q;
   return (size_t)(QV * d + 2 * d * QF) * V * V;
 }
@@ -2718,6 +3054,8 @@ static hipError_t launch_prk_stage_r(const DevMesh& M, int n, const R* F, const 
       case 36: hipLaunchKernelGGL((k_prk_stage_t<36, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
       case 64: hipLaunchKernelGGL((k_prk_stage_t<64, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
       case 40: hipLaunchKernelGGL((k_prk_stage_t<40, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
+      case 100: hipLaunchKernelGGL((k_prk_stage_c<100, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
+      case 135: hipLaunchKernelGGL((k_prk_stage_c<135, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
       default: break;
     }
   }

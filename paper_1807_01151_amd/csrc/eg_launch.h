@@ -43,9 +43,9 @@ struct DevMesh {
 constexpr int PREC_FP64 = 0;
 constexpr int PREC_FP32 = 1;
 
-// values per element of the pointwise flux-Jacobian scratch at order p (0 if
-// the order uses the single-kernel assembly)
-size_t jac_points_per_elem(int d, int p);
+// values per element of the pointwise flux-Jacobian scratch at order p for
+// FP64 or FP32 blocks (0 if that order uses the single-kernel assembly)
+size_t jac_points_per_elem(int d, int p, bool fp32);
 
 // Host copy of the 1D tables of one order (filled by the set-up code).
 struct TabData {
