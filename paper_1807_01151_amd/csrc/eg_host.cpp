@@ -815,6 +815,19 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
       M.bc = bc;
     }
   }
+  // basis tables of the block assembly, both precisions
+  for (int p = 1; p <= h->pmax; ++p) {
+    if (!eg::jacobian_supported(d, p)) continue;
+    const size_t cnt = eg::phitab_values(d, p);
+    double* t64 = nullptr;
+    float* t32 = nullptr;
+    AL(t64, cnt);
+    AL(t32, cnt);
+    HIPCHK(h, eg::launch_fill_phitab(M, h->tabs[p], p, eg::PREC_FP64, t64, h->st));
+    HIPCHK(h, eg::launch_fill_phitab(M, h->tabs[p], p, eg::PREC_FP32, t32, h->st));
+    M.phitab[p][eg::PREC_FP64] = t64;
+    M.phitab[p][eg::PREC_FP32] = t32;
+  }
   for (int p = 0; p <= h->pmax; ++p) {
     const size_t K = (size_t)ne * V * nmodes_of(d, p);
     AL(h->ut[p], K);

@@ -24,6 +24,9 @@ struct DevMesh {
   double* g2x = nullptr;   // 2-point Gauss rule (p = 0 faces)
   double* g2w = nullptr;
   void* bc = nullptr;      // pointwise flux-Jacobian scratch of the block assembly (FP64 or FP32)
+  // per order and precision: phi at the volume points [QV][N], then at the
+  // face points [NF QF][N] (the shared operands of the block assembly)
+  const void* phitab[5][2] = {};
   // batched solves (null for a single solve): per-element free stream [E][V]
   // and CFL [E]; solve segments (element ranges) and Arnoldi block tables
   double* uinf_e = nullptr;
@@ -46,6 +49,7 @@ constexpr int PREC_FP32 = 1;
 // values per element of the pointwise flux-Jacobian scratch at order p for
 // FP64 or FP32 blocks (0 if that order uses the single-kernel assembly)
 size_t jac_points_per_elem(int d, int p, bool fp32);
+size_t phitab_values(int d, int p);
 
 // Host copy of the 1D tables of one order (filled by the set-up code).
 struct TabData {
@@ -106,6 +110,8 @@ hipError_t launch_jac_to_psi(const DevMesh& M, int N, double* Dm, hipStream_t st
 // adjoint (drag sensitivity)
 size_t jac_points_size(int d, int p);  // values per element of the pointwise flux Jacobians
 hipError_t launch_jac_points(const DevMesh& M, const TabData& td, int p, const double* ut, double* bc, hipStream_t st);
+// fills M.phitab[p][prec] (phitab_values(d, p) values of that precision)
+hipError_t launch_fill_phitab(const DevMesh& M, const TabData& td, int p, int prec, void* dst, hipStream_t st);
 hipError_t launch_adj_residual(const DevMesh& M, const TabData& td, int p, const double* wt, const double* gadd,
                                const double* bc, double* out, hipStream_t st);
 hipError_t launch_drag(const DevMesh& M, const TabData& td, int p, const double* ut, const double* dir, double scale,
