@@ -2885,6 +2885,88 @@ __global__ __launch_bounds__(256) void k_prk_stage_tr(const double* __restrict__
   }
 }
 
+// Transposed PRK stage for 64 < NB < 256: lanes hold columns lane, lane +
+// 64, ... of the factor, whose elements stream through registers in chunks
+// of eight (loads of a chunk issued together); x_k broadcast by readlane from
+// the lane of column k.  Same arithmetic as k_prk_stage_tr.
+template <int NB>
+__global__ __launch_bounds__(256) void k_prk_stage_trc(const double* __restrict__ Fm, const int* __restrict__ perm,
+                                                       const double* __restrict__ rt, const double* __restrict__ un,
+                                                       double* __restrict__ ut, double beta, int ne) {
+  constexpr int RPL = (NB + 63) / 64, CH = 8;
+  static_assert(NB > 64 && NB < 256, "columns per lane");
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (e >= ne) return;
+  const double* F = Fm + (size_t)e * NB * NB;
+  int lc[RPL];  // clamped columns: every load in bounds
+  double b[RPL];
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    const int l = lane + 64 * s;
+    lc[s] = l < NB ? l : NB - 1;
+    b[s] = (l < NB) ? rt[(size_t)e * NB + lc[s]] : 0.0;
+  }
+  // U^T z = r (forward): z_k = b_k / U(k, k); columns l > k subtract U(k, l) z_k
+#pragma unroll
+  for (int sl = 0; sl < RPL; ++sl) {
+#pragma unroll 1
+    for (int k0 = 64 * sl; k0 < NB && k0 < 64 * sl + 64; k0 += CH) {
+      double cf[CH][RPL];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int k = k0 + c < NB ? k0 + c : NB - 1;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) cf[c][s] = F[(size_t)lc[s] * NB + k];
+      }
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int k = k0 + c;
+        if (k < NB) {
+          const double zk = readlane_d(b[sl], k & 63) / readlane_d(cf[c][sl], k & 63);
+#pragma unroll
+          for (int s = 0; s < RPL; ++s) {
+            const int l = lane + 64 * s;
+            b[s] = (l == k) ? zk : fma(-((l > k) ? cf[c][s] : 0.0), zk, b[s]);
+          }
+        }
+      }
+    }
+  }
+  // L^T y = z (backward, unit diagonal): columns l < k subtract L(k, l) y_k
+#pragma unroll
+  for (int sl = RPL - 1; sl >= 0; --sl) {
+    const int klast = (NB < 64 * sl + 64 ? NB : 64 * sl + 64) - 1;
+#pragma unroll 1
+    for (int k0 = (klast / CH) * CH; k0 >= 64 * sl; k0 -= CH) {
+      double cf[CH][RPL];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int k = k0 + c < NB ? k0 + c : NB - 1;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) cf[c][s] = F[(size_t)lc[s] * NB + k];
+      }
+#pragma unroll
+      for (int c = CH - 1; c >= 0; --c) {
+        const int k = k0 + c;
+        if (k < NB) {
+          const double yk = readlane_d(b[sl], k & 63);
+#pragma unroll
+          for (int s = 0; s < RPL; ++s) b[s] = fma(-((lane + 64 * s < k) ? cf[c][s] : 0.0), yk, b[s]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    const int l = lane + 64 * s;
+    if (l < NB) {
+      const int o = perm[(size_t)e * NB + l];
+      ut[(size_t)e * NB + o] = un[(size_t)e * NB + o] + beta * b[s];
+    }
+  }
+}
+
 // Transposed p = 0 operator for the adjoint EXP1: A^T-side blocks
 // (T J0^T)_{F,E} = dt_F (J0_{E,F})^T from the forward blocks Ad = T J0 (diag)
 // and Ao[E][lf2] = dt_E J0_{E,F} (lf2: the face of E that touches F).
@@ -3581,7 +3663,11 @@ hipError_t launch_drag(const DevMesh& M, const TabData& td, int p, const double*
   return hipErrorInvalidValue;
 }
 
-bool prk_tr_supported(int n) { return n == 16 || n == 36 || n == 64 || n == 40; }
+// n = 100 (2D p = 4) is left out: its adjoint V-cycle diverged on every
+// state tried, with the transposed kernel checked by a CPU emulation of its
+// loops and (dR/du)^T w equal to the oracle's at every level; the cause is
+// not established.
+bool prk_tr_supported(int n) { return n == 16 || n == 36 || n == 64 || n == 40 || n == 135; }
 
 hipError_t launch_prk_stage_tr(const DevMesh& M, int n, const double* F, const int* perm, const double* rt,
                                const double* un, double* ut, double beta, hipStream_t st) {
@@ -3590,6 +3676,7 @@ hipError_t launch_prk_stage_tr(const DevMesh& M, int n, const double* F, const i
     case 16: hipLaunchKernelGGL((k_prk_stage_tr<16>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
     case 36: hipLaunchKernelGGL((k_prk_stage_tr<36>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
     case 40: hipLaunchKernelGGL((k_prk_stage_tr<40>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
+    case 135: hipLaunchKernelGGL((k_prk_stage_trc<135>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
     case 64: hipLaunchKernelGGL((k_prk_stage_tr<64>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
     default: return hipErrorInvalidValue;
   }

@@ -25,6 +25,8 @@ CASES = [
     ("ogrid16x6-p3", ogrid(16, 6), 3, 3.0),
     ("ogrid12x4-p2", ogrid(12, 4), 2, -2.0),
     ("sphere6x2x2x2-p1", cubed_sphere_shell(2, 2), 1, 2.0),
+    ("ogrid10x3-p4", ogrid(10, 3), 4, 1.0),
+    ("sphere6x2x2x2-p2", cubed_sphere_shell(2, 2), 2, -1.0),
 ]
 
 
@@ -41,7 +43,9 @@ def test_drag_parity(name, mesh, p, alpha):
     c_o, g_o = O.drag(p, u, sref=0.7, grad=True)
     c_g, g_g = S.drag(to_dev(u), sref=0.7, grad=True)
     print(name, "C_D", c_o, c_g, flush=True)
-    assert abs(c_g - c_o) <= 1e-12 * abs(c_o)
+    # C_D is a sum of O(1) wall-pressure terms whose free-stream part cancels
+    # over the closed wall, so its round-off is relative to O(1), not to C_D
+    assert abs(c_g - c_o) <= 1e-12 * max(abs(c_o), 1.0)
     assert rel_err(to_host(g_g), g_o) < 1e-12
 
 
@@ -83,6 +87,39 @@ def test_adjoint_solve_parity(c1_steady):
     print("adjoint cycles", len(hist) - 1, "drop", hist[-1] / hist[0], "lambda error", e, flush=True)
     assert st == 0
     assert e < 1e-8
+
+
+@pytest.mark.parametrize("name,mesh,p,alpha", CASES[4:], ids=[c[0] for c in CASES[4:]])
+def test_adjoint_solve_large_blocks(name, mesh, p, alpha):
+    """Adjoint V-cycles with the 135 x 135 blocks of 3D p = 2 at a perturbed
+    state: the adjoint problem is linear in lambda, so its residual
+    (dR/du)^T lambda + dC_D/du, with the oracle's assembled Jacobian, is
+    checked directly (10^-8 of |g| after a 10^-11 drop of the V-cycle's own
+    residual)."""
+    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
+    S = _solver(mesh, p, alpha, rk_stages=4, cfl_max=20.0, krylov_m=30)
+    u = perturbed(O, p, 320, amp=0.005)
+    _, g = O.drag(p, u, grad=True)
+    lam, hist, st = S.adjoint_solve(to_dev(u), to_dev(g), drop_tol=1e-11, max_cycles=4000)
+    lam = to_host(lam)
+    r = (O.jacobian_sparse(p, u).T @ lam.ravel()).reshape(g.shape) + g
+    e = np.linalg.norm(r) / np.linalg.norm(g)
+    print(f"{name}: adjoint cycles {len(hist) - 1}, drop {hist[-1] / hist[0]:.2e}, equation residual {e:.2e}",
+          flush=True)
+    assert st == 0
+    assert e < 1e-8
+
+
+def test_adjoint_rejects_2d_p4():
+    """2D p = 4 has no transposed block solve: the call reports it."""
+    import paper_1807_01151_amd as P
+    mesh = ogrid(10, 3)
+    O = oracle.Oracle(mesh, 4)
+    S = _solver(mesh, 4, 0.0)
+    u = perturbed(O, 4, 321, amp=0.005)
+    _, g = O.drag(4, u, grad=True)
+    with pytest.raises(P.EgError, match="transposed block solve"):
+        S.adjoint_solve(to_dev(u), to_dev(g), drop_tol=1e-10, max_cycles=10)
 
 
 def test_steady_drag_gradient_matches_finite_differences():
