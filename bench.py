@@ -161,6 +161,7 @@ def mixed_measurements(P, mesh, p, dof, args, fp64_ms):
     switched (r <= 1e-4 r_1)."""
     import torch
     S = P.Solver(mesh, p, rk_stages=3, cfl_max=10.0, krylov_m=30, mach=0.3, alpha_deg=0.0, precision="mixed")
+    S.autotune()
     u = S.freestream(p)
     S.solve_steady(u, drop_tol=0.0, max_cycles=args.warmup)
     torch.cuda.synchronize()
@@ -205,6 +206,7 @@ def batched_measurements(P, steps, budget_s, precision="mixed"):
         meshes = [ogrid(draws[i]["n_theta"], draws[i]["n_r"]) for i in idx]
         B = P.BatchSolver(meshes, p, [draws[i]["mach"] for i in idx], [draws[i]["alpha_deg"] for i in idx],
                           rk_stages=3, cfl_max=10.0, krylov_m=30, precision=precision)
+        B.autotune()  # residual tiles of this order group
         handles[p] = (B, B.freestream(p), idx)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t_init
@@ -301,6 +303,8 @@ def main():
     d, p = 2, 3
     log("[bench] init")
     S = P.Solver(mesh, p, rk_stages=3, cfl_max=10.0, krylov_m=30, mach=0.3, alpha_deg=0.0)
+    tiles = S.autotune()  # residual tiles per order and precision (outside the timed region)
+    log(f"[bench] residual tiles (elements per workgroup): {tiles}")
     dof = mesh.n_elem * 4 * 16
     u = S.freestream(p)
     # warm-up cycles
@@ -333,7 +337,8 @@ def main():
     cls, lev = key.split("@")[0], int(key.split("@p")[1])
     roof = roofline_entry(cls, lev, prof[key][0], prof[key][1], mesh.n_elem, d)
     roof["share_of_kernel_time"] = ms_dom / tot
-    extras = {"kernels_ms_per_cycle": {k: round(v[0] / args.steps, 5) for k, v in prof.items()}}
+    extras = {"kernels_ms_per_cycle": {k: round(v[0] / args.steps, 5) for k, v in prof.items()},
+              "residual_tiles": {f"p{q}/{k}": t for (q, k), t in tiles.items()}}
     for c2 in ("residual", "jacobian_lu", "prk_stage"):
         k2 = f"{c2}@p{p}"
         if k2 in prof:

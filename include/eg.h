@@ -183,6 +183,19 @@ eg_status eg_solve_resume(eg_handle* h, double* u_dev, double drop_tol, int max_
  * Off by default; profiling (eg_profile) runs eagerly. */
 eg_status eg_set_graphs(eg_handle* h, int enable);
 
+/* Tile autotuner (no passage of the paper: a tuning of this implementation).
+ * For every order p <= p_max and both arithmetic precisions, times the
+ * residual kernel (eq. (euler3)) with three element tiles per workgroup
+ * (half, the default and 1.5 x the default) on a free-stream state, reps
+ * launches each with HIP events on the handle's stream, and keeps the
+ * fastest for every later residual of the handle (results do not depend on
+ * the tile: every output is formed by one thread with the same sums).
+ * tiles_host (nullable, host memory, 2 (p_max + 1) ints): the chosen
+ * elements per workgroup, [p][FP64, FP32].  Uses the handle's scratch
+ * buffers and rt; call it before a solve, not between eg_solve_steady and
+ * eg_solve_resume.  Drops captured V-cycle graphs (they are recaptured). */
+eg_status eg_autotune(eg_handle* h, int reps, int* tiles_host);
+
 /* ---- Batched independent solves ----
  * n_solves steady problems (Section 2.4 eMG each) in one handle: meshes of
  * any size with the same dim, p_max, rk_stages, krylov_m, cfl_max,

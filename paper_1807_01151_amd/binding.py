@@ -14,7 +14,7 @@ EXPORTED_SYMBOLS = (
     "eg_init_mesh", "eg_free", "eg_last_error", "eg_sizes", "eg_set_freestream", "eg_residual",
     "eg_timestep", "eg_element_jacobian", "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm",
     "eg_vcycle", "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read",
-    "eg_drag", "eg_adjoint_apply", "eg_adjoint_solve", "eg_init_batch", "eg_layout", "eg_solve_batch",
+    "eg_drag", "eg_adjoint_apply", "eg_adjoint_solve", "eg_init_batch", "eg_layout", "eg_solve_batch", "eg_autotune",
     "eg_set_graphs",
 )
 
@@ -79,6 +79,7 @@ def lib():
         L.eg_profile_read.argtypes = [vp, i, i, pd, C.POINTER(i)]
         L.eg_drag.argtypes = [vp, vp, pd, d, pd, vp]
         L.eg_set_graphs.argtypes = [vp, i]
+        L.eg_autotune.argtypes = [vp, i, C.POINTER(i)]
         L.eg_init_batch.argtypes = [C.POINTER(_Mesh), C.POINTER(_Params), i, vp, C.POINTER(vp)]
         L.eg_layout.argtypes = [vp, i, i, C.POINTER(C.c_int64), C.POINTER(i), C.POINTER(i)]
         L.eg_solve_batch.argtypes = [vp, vp, d, i, pd, C.POINTER(i)]
@@ -218,6 +219,12 @@ class Solver:
         """Replay the V-cycle as a captured HIP graph in the steady solves."""
         self._chk(lib().eg_set_graphs(self._h, int(enable)))
 
+    def autotune(self, reps: int = 5):
+        """Time the residual's element tiles per order and precision and keep
+        the fastest (eg_autotune); returns {(p, "fp64" | "fp32"): elements
+        per workgroup}."""
+        return _autotune(self, reps)
+
     def profile_read(self, kernel_class: str, p: int = -1):
         """(total milliseconds, launches) of one kernel class at level p (-1: all)."""
         ms = C.c_double(0.0)
@@ -235,6 +242,13 @@ class Solver:
         if st not in (0, 5, 6) or (raise_on_fail and st != 0):
             self._chk(st)
         return hist[: nc.value + 1], st
+
+
+def _autotune(obj, reps):
+    pmax = obj.p_max
+    tiles = (C.c_int * (2 * (pmax + 1)))()
+    obj._chk(lib().eg_autotune(obj._h, int(reps), tiles))
+    return {(p, prec): tiles[2 * p + k] for p in range(pmax + 1) for k, prec in enumerate(("fp64", "fp32"))}
 
 
 def _freestream_direction(dim, alpha_deg, beta_deg):
@@ -332,6 +346,10 @@ class BatchSolver:
     empty = Solver.empty
     freestream = Solver.freestream
     residual = Solver.residual
+
+    def autotune(self, reps: int = 5):
+        """Residual tiles per order and precision of the batch (see Solver.autotune)."""
+        return _autotune(self, reps)
 
     def profile(self, enable: bool):
         """Event timing of every kernel class (see Solver.profile)."""

@@ -1038,6 +1038,55 @@ eg_status eg_set_graphs(eg_handle* h, int enable) {
   return EG_OK;
 }
 
+eg_status eg_autotune(eg_handle* h, int reps, int* tiles_host) {
+  if (!h || reps < 1) return EG_ERR_ARG;
+  eg::DevMesh& M = h->M;
+  for (int i = 0; i < 2; ++i) {  // captured graphs hold the old launches
+    if (h->gexec[i]) (void)hipGraphExecDestroy(h->gexec[i]);
+    if (h->ggraph[i]) (void)hipGraphDestroy(h->ggraph[i]);
+    h->gexec[i] = nullptr;
+    h->ggraph[i] = nullptr;
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(h, hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(h, EG_ERR_HIP, "hipEventCreate");
+  }
+  eg_status st = EG_OK;
+  for (int p = 0; p <= h->pmax && st == EG_OK; ++p) {
+    const int N = nmodes_of(M.d, p);
+    // free stream in phi coordinates as the timing state
+    hipError_t e = eg::launch_freestream(M, N, h->tmp, h->st);
+    if (e == hipSuccess) e = eg::launch_basis(M, N, h->tmp, h->tmp2, 0, h->st);
+    for (int prec = 0; prec < 2 && e == hipSuccess; ++prec) {
+      int best = 1;
+      float tbest = 0.0f;
+      for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+        M.res_tile_choice[p][prec] = c;
+        e = eg::launch_residual(M, h->tabs[p], p, h->tmp2, nullptr, h->rt[p], prec, h->st);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(a, h->st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+          e = eg::launch_residual(M, h->tabs[p], p, h->tmp2, nullptr, h->rt[p], prec, h->st);
+        if (e == hipSuccess) e = hipEventRecord(b, h->st);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && (c == 0 || ms < tbest)) {
+          tbest = ms;
+          best = c;
+        }
+      }
+      M.res_tile_choice[p][prec] = best;
+      if (tiles_host) tiles_host[2 * p + prec] = eg::residual_tile(M.d, p, prec, best);
+    }
+    if (e != hipSuccess) st = hipfail(h, e, "autotune");
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return st;
+}
+
 eg_status eg_init_mesh(const eg_mesh* mesh, const eg_params* prm, void* hip_stream, eg_handle** out) {
   if (!out) return EG_ERR_ARG;
   *out = nullptr;

@@ -3080,16 +3080,39 @@ GasT<R> gas_as(const Gas& g) {
   return o;
 }
 
-template <int D, int P, class R>
-hipError_t residual_t(const DevMesh& M, const TabData& td, const double* ut, const double* fadd, double* rt,
-                      const FasOut& fas, hipStream_t st) {
-  Tab<D, P, R> t;
-  fill_tab(t, td);
-  constexpr int EB = res_tile<D, P, R>();
+// Residual tiles (elements per workgroup) the autotuner chooses among: half,
+// the default and one and a half times the default (res_tile).
+template <int D, int P, class R, int C>
+constexpr int res_tile_cand() {
+  constexpr int def = res_tile<D, P, R>();
+  constexpr int half = def / 2 < 1 ? 1 : def / 2, more = (3 * def) / 2 > 32 ? 32 : (3 * def) / 2;
+  return C == 0 ? half : C == 2 ? (more < 1 ? 1 : more) : def;
+}
+
+template <int D, int P, int EB, class R>
+hipError_t residual_launch(const DevMesh& M, const Tab<D, P, R>& t, const double* ut, const double* fadd, double* rt,
+                           const FasOut& fas, hipStream_t st) {
   const int grid = (M.ne + EB - 1) / EB;
   hipLaunchKernelGGL((k_residual<D, P, EB, R>), dim3(grid), dim3(256), 0, st, ut, fadd, rt, M.xv, M.nbr, M.ncode,
                      M.ne, t, gas_as<R>(M.gas), M.uinf_e, fas);
   return hipGetLastError();
+}
+
+template <int D, int P, class R>
+hipError_t residual_t(const DevMesh& M, const TabData& td, const double* ut, const double* fadd, double* rt,
+                      const FasOut& fas, int choice, hipStream_t st) {
+  Tab<D, P, R> t;
+  fill_tab(t, td);
+  switch (choice) {
+    case 0: return residual_launch<D, P, res_tile_cand<D, P, R, 0>(), R>(M, t, ut, fadd, rt, fas, st);
+    case 2: return residual_launch<D, P, res_tile_cand<D, P, R, 2>(), R>(M, t, ut, fadd, rt, fas, st);
+    default: return residual_launch<D, P, res_tile_cand<D, P, R, 1>(), R>(M, t, ut, fadd, rt, fas, st);
+  }
+}
+
+template <int D, int P, class R>
+int res_tile_of(int choice) {
+  return choice == 0 ? res_tile_cand<D, P, R, 0>() : choice == 2 ? res_tile_cand<D, P, R, 2>() : res_tile_cand<D, P, R, 1>();
 }
 
 template <int D, int P, class R>
@@ -3198,13 +3221,14 @@ hipError_t jac_to_psi_t(const DevMesh& M, double* Dm, hipStream_t st) {
 
 hipError_t launch_residual(const DevMesh& M, const TabData& td, int p, const double* ut, const double* fadd,
                            double* rt, int prec, hipStream_t st, const FasOut& fas) {
+  const int choice = (p >= 0 && p < 5) ? M.res_tile_choice[p][prec == PREC_FP32 ? 1 : 0] : 1;
   if (prec == PREC_FP32) {
-#define CALL_RES(DD, PP) residual_t<DD, PP, float>(M, td, ut, fadd, rt, fas, st)
+#define CALL_RES(DD, PP) residual_t<DD, PP, float>(M, td, ut, fadd, rt, fas, choice, st)
     if (M.d == 2) { EG_DISPATCH_P(2, p, CALL_RES) }
     else { EG_DISPATCH_P(3, p, CALL_RES) }
 #undef CALL_RES
   } else {
-#define CALL_RES(DD, PP) residual_t<DD, PP, double>(M, td, ut, fadd, rt, fas, st)
+#define CALL_RES(DD, PP) residual_t<DD, PP, double>(M, td, ut, fadd, rt, fas, choice, st)
     if (M.d == 2) { EG_DISPATCH_P(2, p, CALL_RES) }
     else { EG_DISPATCH_P(3, p, CALL_RES) }
 #undef CALL_RES
@@ -3523,6 +3547,30 @@ hipError_t launch_jac_to_psi(const DevMesh& M, int N, double* Dm, hipStream_t st
 // ---------------------------------------------------------------------------
 // adjoint launchers
 // ---------------------------------------------------------------------------
+int residual_tile(int d, int p, int prec, int choice) {
+#define TILE_OF(DD, PP) (prec == PREC_FP32 ? res_tile_of<DD, PP, float>(choice) : res_tile_of<DD, PP, double>(choice))
+  if (d == 2) {
+    switch (p) {
+      case 0: return TILE_OF(2, 0);
+      case 1: return TILE_OF(2, 1);
+      case 2: return TILE_OF(2, 2);
+      case 3: return TILE_OF(2, 3);
+      case 4: return TILE_OF(2, 4);
+      default: break;
+    }
+  } else {
+    switch (p) {
+      case 0: return TILE_OF(3, 0);
+      case 1: return TILE_OF(3, 1);
+      case 2: return TILE_OF(3, 2);
+      case 3: return TILE_OF(3, 3);
+      default: break;
+    }
+  }
+#undef TILE_OF
+  return 0;
+}
+
 size_t phitab_values(int d, int p) {
   const int Q = p + 2, N = (d == 2) ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
   const int QV = (d == 2) ? Q * Q : Q * Q * Q, QF = (d == 2) ? Q : Q * Q;

@@ -27,6 +27,9 @@ struct DevMesh {
   // per order and precision: phi at the volume points [QV][N], then at the
   // face points [NF QF][N] (the shared operands of the block assembly)
   const void* phitab[5][2] = {};
+  // residual tile per order and precision (FP64, FP32): index of the
+  // candidate (0: half, 1: default, 2: 1.5 x the default), set by eg_autotune
+  int res_tile_choice[5][2] = {{1, 1}, {1, 1}, {1, 1}, {1, 1}, {1, 1}};
   // batched solves (null for a single solve): per-element free stream [E][V]
   // and CFL [E]; solve segments (element ranges) and Arnoldi block tables
   double* uinf_e = nullptr;
@@ -50,6 +53,8 @@ constexpr int PREC_FP32 = 1;
 // FP64 or FP32 blocks (0 if that order uses the single-kernel assembly)
 size_t jac_points_per_elem(int d, int p, bool fp32);
 size_t phitab_values(int d, int p);
+// elements per workgroup of the residual at (d, p, precision) for a tile choice
+int residual_tile(int d, int p, int prec, int choice);
 
 // Host copy of the 1D tables of one order (filled by the set-up code).
 struct TabData {
