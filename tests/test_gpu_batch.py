@@ -91,3 +91,28 @@ def test_batch_solve_matches_single_solves(precision):
             O = oracle.Oracle(MESHES[i], p, mach=MACHS[i], alpha_deg=ALPHAS[i])
             ub = to_host(uv)
             assert O.rnorm(p, O.residual(p, ub)) <= 2e-10 * hists[i][0]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_p4_cycles_match_single(precision):
+    """p = 4 (100 x 100 blocks: the column-split factorisation and the
+    chunked stage kernel) in a batch of two solves against each solve alone:
+    five V-cycles from the free streams agree to 1e-12 r_1 (the batch sums
+    its residual norms per solve in another order) and so do the states."""
+    import paper_1807_01151_amd as P
+    meshes, machs, alphas = MESHES[:2], MACHS[:2], ALPHAS[:2]
+    kw = dict(rk_stages=3, cfl_max=10.0, krylov_m=30, precision=precision)
+    B = P.BatchSolver(meshes, 4, machs, alphas, **kw)
+    u = B.freestream(4)
+    hists, cyc, st = B.solve(u, drop_tol=0.0, max_cycles=5)
+    for i, uv in enumerate(B.views(u)):
+        S = P.Solver(meshes[i], 4, mach=machs[i], alpha_deg=alphas[i], **kw)
+        us = S.freestream(4)
+        h, _ = S.solve_steady(us, drop_tol=0.0, max_cycles=5)
+        n = min(len(h), len(hists[i]))
+        dev = np.max(np.abs(hists[i][:n] - h[:n])) / h[0]
+        e = rel_err(to_host(uv), to_host(us))
+        print(f"  {precision} solve {i}: history dev {dev:.2e}, state {e:.2e}", flush=True)
+        assert n == 6
+        assert dev < 1e-12
+        assert e < 1e-10

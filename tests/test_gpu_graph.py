@@ -70,3 +70,19 @@ def test_graph_replay_equals_eager_batch():
     for x, y in zip(ha, hb):
         assert np.array_equal(x, y)
     assert np.array_equal(to_host(ua), to_host(ub))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_equals_eager_p4(precision):
+    """O-grid 10 x 3, p = 4 (column-split block factorisation, chunked stage
+    kernels): 8 cycles replayed from the graph equal the eager cycles."""
+    import paper_1807_01151_amd as P
+    mesh = ogrid(10, 3)
+    a = P.Solver(mesh, 4, rk_stages=3, cfl_max=10.0, krylov_m=30, precision=precision)
+    b = P.Solver(mesh, 4, rk_stages=3, cfl_max=10.0, krylov_m=30, precision=precision)
+    b.set_graphs(True)
+    ua, ub = a.freestream(4), b.freestream(4)
+    ha, _ = a.solve_steady(ua, drop_tol=0.0, max_cycles=8)
+    hb, _ = b.solve_steady(ub, drop_tol=0.0, max_cycles=8)
+    assert np.array_equal(ha, hb)
+    assert np.array_equal(to_host(ua), to_host(ub))
