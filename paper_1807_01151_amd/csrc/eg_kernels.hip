@@ -1508,6 +1508,13 @@ __global__ __launch_bounds__(256) void k_basis(const double* __restrict__ x, dou
   for (int i = 0; i < N; ++i) o[i] = r[i];
 }
 
+// Lanes per element row of N modes in the lane-group kernels: N rounded up
+// to a power of two, so that a group never straddles a wavefront.
+template <int N>
+constexpr int norm_group() {
+  return N <= 1 ? 1 : N <= 4 ? 4 : N <= 8 ? 8 : N <= 16 ? 16 : N <= 32 ? 32 : 64;
+}
+
 // Restriction of the solution from order p (N modes) to p-1 (Nc modes): the
 // L2 projection, which in psi coordinates is truncation: u = L^T ut, keep
 // the leading Nc entries, ut_c = L_c^{-T} u_c.
@@ -1590,11 +1597,6 @@ __global__ __launch_bounds__(256) void k_timestep(const double* __restrict__ ut,
 // straddles a wavefront): lane i holds r_i and row i of L and the forward
 // substitution runs by columns, x_j broadcast from lane j, which performs
 // the same operations per row as a sequential solve.
-template <int N>
-constexpr int norm_group() {
-  return N <= 1 ? 1 : N <= 4 ? 4 : N <= 8 ? 8 : N <= 16 ? 16 : N <= 32 ? 32 : 64;
-}
-
 template <int D, int N>
 __global__ __launch_bounds__(256) void k_norm_partial(const double* __restrict__ rt, const double* __restrict__ Lpk,
                                                       int NT, int ne, double* __restrict__ part) {
@@ -2498,8 +2500,11 @@ __global__ __launch_bounds__(256) void k_exp1_update(int K, int V, const double*
 //   ut_l[:N_{l-1}] += ut_{l-1} - uc0_{l-1}.
 // Modes are independent along the chain, so one thread takes one (row, mode)
 // pair, j < N_{p_max - 1}, and carries its corrected value of ut_{l-1} from
-// level to level (thread j = 0 also forms ut0).  Same operations in the same
-// order as k_exp1_update followed by the prolongations one level at a time.
+// level to level.  The threads of mode 0, which also form ut0 (a dot
+// product over the Krylov basis), come first, one per row, so that they
+// fill whole wavefronts; the other modes follow.  Same operations in the
+// same order as k_exp1_update followed by the prolongations one level at a
+// time.
 __global__ __launch_bounds__(256) void k_exp1_prolong(int K, int V, const double* __restrict__ Vb,
                                                       const double* __restrict__ y, const double* __restrict__ info,
                                                       const double* __restrict__ u0, const double* __restrict__ Lpk,
@@ -2507,7 +2512,7 @@ __global__ __launch_bounds__(256) void k_exp1_prolong(int K, int V, const double
   const int NJ = c.N[c.pmax - 1];
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= K * NJ) return;
-  const int k = id / NJ, j = id % NJ;
+  const int k = id < K ? id : (id - K) / (NJ - 1), j = id < K ? 0 : 1 + (id - K) % (NJ - 1);
   // every load of the chain first: ut_l and uc0_{l-1} at (k, j), and
   // ut_{l-1} where the level below leaves mode j as it is (no thread writes
   // such an entry, so it can be read ahead of the corrections)
