@@ -2231,25 +2231,33 @@ __global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* 
 // approximation of exp(dt H_m) (end of Section 2.2).  y[i] = E[i][m].
 // ---------------------------------------------------------------------------
 // Cm = A B for n x n row-major matrices in LDS, by a block of 256 threads.
-// For n <= 32 each thread owns a 2 x 2 tile of the output (four FMAs per
-// four LDS reads); larger n takes one output per thread and pass.
+// For n <= 32 on the FP64 matrix cores: the product is padded to 32 x 32
+// and wavefront w computes the 16 x 16 output tile (w / 2, w % 2) with eight
+// 16 x 16 x 4 steps (lane l holds A[i][k] and B[k][j] for i, j = l % 16 and
+// k = l / 16 of the step, and receives rows l / 16 + 4 r, r = 0 .. 3, of
+// column l % 16 of the tile); every fragment is read from LDS before the
+// first step.  Larger n takes one output per thread and pass.
+typedef double dbl4_t __attribute__((ext_vector_type(4)));
+
 __device__ void lds_matmul(int n, const double* A, const double* B, double* Cm) {
   if (n <= 32) {
-    const int r0 = 2 * (threadIdx.x >> 4), c0 = 2 * (threadIdx.x & 15);
-    if (r0 < n && c0 < n) {
-      const int r1 = min(r0 + 1, n - 1), c1 = min(c0 + 1, n - 1);
-      double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
-      for (int k = 0; k < n; ++k) {
-        const double a0 = A[r0 * n + k], a1 = A[r1 * n + k];
-        const double b0 = B[k * n + c0], b1 = B[k * n + c1];
-        s00 += a0 * b0; s01 += a0 * b1; s10 += a1 * b0; s11 += a1 * b1;
-      }
-      Cm[r0 * n + c0] = s00;
-      if (c0 + 1 < n) Cm[r0 * n + c0 + 1] = s01;
-      if (r0 + 1 < n) {
-        Cm[(r0 + 1) * n + c0] = s10;
-        if (c0 + 1 < n) Cm[(r0 + 1) * n + c0 + 1] = s11;
-      }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int ia = 16 * (w >> 1) + li, jb = 16 * (w & 1) + li;
+    double a[8], b[8];
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      const int k = 4 * st + lk;
+      a[st] = (ia < n && k < n) ? A[ia * n + k] : 0.0;
+      b[st] = (k < n && jb < n) ? B[k * n + jb] : 0.0;
+    }
+    dbl4_t c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < 8; ++st) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[st], c, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * (w >> 1) + lk + 4 * r;
+      if (i < n && jb < n) Cm[i * n + jb] = c[r];
     }
   } else {
     for (int it = threadIdx.x; it < n * n; it += blockDim.x) {
