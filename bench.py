@@ -187,6 +187,36 @@ def mixed_measurements(P, mesh, p, dof, args, fp64_ms):
             "phase_a_speedup_vs_fp64": round(fp64_ms / ms_a, 3), "phase_b_speedup_vs_fp64": round(fp64_ms / ms_b, 3)}
 
 
+def sphere_measurements(P, warmup=2, steps=10):
+    """FP64 against mixed precision on the 3D sphere workload (cubed-sphere
+    hex shell 6 x 16 x 16 x 24 = 36864 hexes, p = 2, 135 x 135 blocks): V-cycle
+    cost from the free stream (the mixed solve is in phase A there)."""
+    import torch
+    from eg_inputs import cubed_sphere_shell
+    mesh = cubed_sphere_shell(16, 24)
+    dof = mesh.n_elem * 27 * 5
+    out = {"workload": "3D sphere, cubed-sphere hex shell 6x16x16x24 = 36864 hexes, DG p=2 (27 modes x 5 vars), "
+                       "eMG V-cycle p2->p0, 3-stage PRK, EXP1 m=30, CFL 10, Ma 0.3, free-stream start",
+           "dof": dof}
+    for prec in ("fp64", "mixed"):
+        S = P.Solver(mesh, 2, rk_stages=3, cfl_max=10.0, krylov_m=30, mach=0.3, alpha_deg=0.0, precision=prec)
+        S.autotune()
+        u = S.freestream(2)
+        S.solve_steady(u, drop_tol=0.0, max_cycles=warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.solve_steady(u, drop_tol=0.0, max_cycles=steps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        out[f"{prec}_ms_per_cycle"] = round(ms, 3)
+        out[f"{prec}_dof_updates_per_s"] = dof / ms * 1e3
+        log(f"[bench] sphere {prec}: {ms:.3f} ms/cycle")
+        del S, u
+        torch.cuda.empty_cache()
+    out["mixed_speedup_vs_fp64"] = round(out["fp64_ms_per_cycle"] / out["mixed_ms_per_cycle"], 3)
+    return out
+
+
 def batched_measurements(P, steps, budget_s, precision="mixed"):
     """The batched workload: 64 independent cylinder solves drawn from seed
     1807 (N_theta ~ U{16..96}, N_r = N_theta / 2, p ~ U{1..4}, Ma ~ U[0.1,
@@ -283,6 +313,8 @@ def main():
                     help="seconds cap of each (FP64, mixed) time-to-1e-10 run on the benchmark mesh")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision measurements")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-solve batched workload")
+    ap.add_argument("--no-sphere", action="store_true",
+                    help="skip the FP64 / mixed V-cycle timing on the 3D sphere (also skipped by --no-mixed)")
     ap.add_argument("--batch-budget", type=float, default=30.0, help="seconds cap of the batched convergence run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-drop", action="store_true", help="skip the time-to-1e-10 run")
@@ -359,6 +391,8 @@ def main():
             del Sm
         mixed["c1_time_to_1e-10"] = c1_time_to_drop(P)
         extras["mixed"] = mixed
+        if not args.no_sphere:
+            extras["sphere"] = sphere_measurements(P)
     if not args.no_batched:
         extras["batched"] = batched_measurements(P, 10, args.batch_budget)
     if args.calibrate:
