@@ -322,8 +322,8 @@ def main():
                     help="end with a 256 MiB device-to-device copy (the reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the solver would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the solver has no multi-GPU path "
+              "(its element-domain sharding over several GPUs is a design note, not built).", file=sys.stderr)
         sys.exit(2)
 
     import torch
