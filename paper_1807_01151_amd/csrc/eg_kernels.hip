@@ -2110,7 +2110,7 @@ __global__ __launch_bounds__(256) void k_arn_b(int K, int m, int j, const double
   if (act) W[k] = w1;
   if (blockIdx.x == sp.b0 && threadIdx.x <= j) H[threadIdx.x * m + j] = s_g[threadIdx.x];
   if (blockIdx.x == sp.b0 && threadIdx.x == 0) wn0[0] = sqrt(s_g[j + 1]);
-  constexpr int NP = NVM == 48 ? 64 : NVM;
+  constexpr int NP = NVM > 32 ? 64 : NVM > 16 ? 32 : NVM;  // a power of two
   double pp[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) pp[i] = (i < NVM) ? w1 * vr[i < NVM ? i : 0] : 0.0;
@@ -2215,7 +2215,7 @@ __global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* 
   if constexpr (NEXT) {
     const double wn = (aw - ((c0 + c1) + s_c[j + 1] * v)) * ihn;
     if (act) Wn[k] = wn;
-    constexpr int NP = NVM == 48 ? 64 : NVM;
+    constexpr int NP = NVM > 32 ? 64 : NVM > 16 ? 32 : NVM;  // a power of two
     double pp[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) pp[i] = (i <= j) ? wn * vr[i < NVM ? i : 0] : (i == j + 1 ? wn * v : 0.0);
@@ -3414,8 +3414,9 @@ hipError_t launch_p0_setup(const DevMesh& M, const double* ut0, const double* ft
 
 int arnoldi_blocks(int K) { return (K + 255) / 256; }
 
-// Smallest register-resident basis size covering `need` vectors.
-static int arn_nvm(int need) { return need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 48; }
+// Smallest register-resident basis size covering `need` vectors: 8, 16, 24,
+// 32, then 48 (a kernel issues the loads of its whole size).
+static int arn_nvm(int need) { return need <= 32 ? 8 * ((need + 7) / 8) : 48; }
 
 template <int NVM>
 static void launch_arn_b(int nblk, hipStream_t s, int K, int m, int j, const double* Vb, double* W,
@@ -3441,6 +3442,7 @@ static void dispatch_arn_ca(int nvm, int nblk, hipStream_t s, int K, int m, int 
   switch (nvm) {
     case 8: launch_arn_ca<V, NF, NEXT, 8>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st, S); break;
     case 16: launch_arn_ca<V, NF, NEXT, 16>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st, S); break;
+    case 24: launch_arn_ca<V, NF, NEXT, 24>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st, S); break;
     case 32: launch_arn_ca<V, NF, NEXT, 32>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st, S); break;
     default: launch_arn_ca<V, NF, NEXT, 48>(nblk, s, K, m, j, nbr, Ad, Ao, Vb, W, Wn, part2, part1, P, H, H2, wn0, info, st, S); break;
   }
@@ -3466,6 +3468,7 @@ hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, c
     switch (arn_nvm(j + 1)) {
       case 8: launch_arn_b<8>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
       case 16: launch_arn_b<16>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
+      case 24: launch_arn_b<24>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
       case 32: launch_arn_b<32>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
       default: launch_arn_b<48>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
     }
