@@ -1371,6 +1371,67 @@ __global__ __launch_bounds__(256) void k_prk_stage_t(const R* __restrict__ Fm, c
   }
 }
 
+// Broadcast of lane J of every 16-lane row to the whole row (the DPP row
+// broadcast, row_newbcast), for the 16 x 16 stage below.
+template <int J>
+__device__ __forceinline__ double row_bcast(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x150 + J, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x150 + J, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int J>
+__device__ __forceinline__ float row_bcast(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x150 + J, 0xF, 0xF, false));
+}
+
+template <int J, int NB, class R>
+__device__ __forceinline__ void g16_forward(const R (&row)[NB], R& b, int i) {
+  if constexpr (J < NB) {
+    const R xj = row_bcast<J>(b);
+    b = fma(-((i > J) ? row[J] : R(0)), xj, b);
+    g16_forward<J + 1, NB, R>(row, b, i);
+  }
+}
+template <int J, int NB, class R>
+__device__ __forceinline__ void g16_backward(const R (&row)[NB], R& b, int i) {
+  if constexpr (J >= 0) {
+    const R xj = row_bcast<J>(b) / row_bcast<J>(row[J]);
+    b = (i == J) ? xj : fma(-((i < J) ? row[J] : R(0)), xj, b);
+    g16_backward<J - 1, NB, R>(row, b, i);
+  }
+}
+
+// PRK stage for 16 x 16 blocks (2D p = 1): four elements per wavefront, one
+// per 16-lane row, so that every lane holds a factor row (k_prk_stage_t
+// would leave 48 of 64 lanes idle); x_j goes to the lanes of its element by
+// the DPP row broadcast of lane j.  Lanes of elements past ne work on
+// element ne - 1 and store nothing, so that every row of the wavefront takes
+// part in the broadcasts.  Same arithmetic and arguments as k_prk_stage_t.
+template <class R>
+__global__ __launch_bounds__(256) void k_prk_stage_g16(const R* __restrict__ Fm, const int* __restrict__ perm,
+                                                       const double* __restrict__ rt, const double* __restrict__ un,
+                                                       double* __restrict__ ut, double* __restrict__ save,
+                                                       double beta, int ne) {
+  constexpr int NB = 16;
+  const int lane = threadIdx.x & 63, i = lane & 15;
+  const int e = 4 * (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) + (lane >> 4);
+  const bool act = e < ne;
+  const int ec = act ? e : ne - 1;
+  const R* F = Fm + (size_t)ec * NB * NB;
+  R row[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) row[j] = __builtin_nontemporal_load(&F[(size_t)j * NB + i]);
+  const size_t o = (size_t)ec * NB + i;
+  R b = R(rt[(size_t)ec * NB + perm[o]]);
+  const double u0 = un ? un[o] : ut[o];
+  g16_forward<0, NB, R>(row, b, i);
+  g16_backward<NB - 1, NB, R>(row, b, i);
+  if (act) {
+    if (save) save[o] = u0;
+    ut[o] = u0 + beta * double(b);
+  }
+}
+
 // PRK stage for block sizes 64 < NB < 256: one wavefront per element with
 // RPL rows per lane (lane, lane + 64, ...); the factor columns stream
 // through registers in chunks of eight whose loads are all issued before
@@ -3301,7 +3362,7 @@ static hipError_t launch_prk_stage_r(const DevMesh& M, int n, const R* F, const 
   const int grid = (M.ne + 3) / 4;
   if (!ft) {
     switch (n) {
-      case 16: hipLaunchKernelGGL((k_prk_stage_t<16, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
+      case 16: hipLaunchKernelGGL((k_prk_stage_g16<R>), dim3((M.ne + 15) / 16), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
       case 36: hipLaunchKernelGGL((k_prk_stage_t<36, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
       case 64: hipLaunchKernelGGL((k_prk_stage_t<64, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
       case 40: hipLaunchKernelGGL((k_prk_stage_t<40, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
