@@ -61,8 +61,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobian_lu_c2_pmc_traffic.md")
 
 def kernel_source_digest(cls):
     """sha256 over the shared device headers and the text of the device
-    functions of one kernel class, so that a stored counter reading can be
-    matched to the code it was taken on."""
+    functions of one kernel class (their definitions: lines that declare a
+    __device__ or __global__ function of that name), so that a stored counter
+    reading can be matched to the code it was taken on."""
     csrc = os.path.join(ROOT, "paper_1807_01151_amd", "csrc")
     h = hashlib.sha256()
     for f in ("eg_common.h", "eg_physics.h"):
@@ -71,6 +72,9 @@ def kernel_source_digest(cls):
     for name in CLASS_KERNELS[cls]:
         for m in re.finditer(r"\b" + name + r"\(", src):
             start = src.rfind("\n", 0, m.start())
+            line = src[start + 1:src.find("\n", m.start())]
+            if "__device__" not in line and "__global__" not in line:
+                continue  # a call, not the definition
             end = src.find("\n}\n", m.start())
             h.update(src[start:end].encode())
     return h.hexdigest()
