@@ -958,6 +958,148 @@ __global__ __launch_bounds__(256, 3) void k_jaclu_wave(const R* __restrict__ BC,
   }
 }
 
+// Maximum of an unsigned key within each 16-lane row of the wavefront (the
+// first four DPP steps of wave_max_u32 leave the row maximum in lane 15 of
+// the row), broadcast back to the row with the DPP row broadcast.
+__device__ __forceinline__ unsigned row_max_u32(unsigned x) {
+  int v = (int)x;
+  v = (int)max((unsigned)v, (unsigned)__builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  v = (int)max((unsigned)v, (unsigned)__builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  v = (int)max((unsigned)v, (unsigned)__builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xE, false));  // row_shr:4
+  v = (int)max((unsigned)v, (unsigned)__builtin_amdgcn_update_dpp(v, v, 0x118, 0xF, 0xC, false));  // row_shr:8
+  return (unsigned)__builtin_amdgcn_update_dpp(0, v, 0x150 + 15, 0xF, 0xF, false);                 // row_newbcast:15
+}
+
+// The block assembly and LU of k_jaclu_wave for 16 x 16 blocks (2D p = 1),
+// four elements per wavefront, one per 16-lane row (k_jaclu_wave would
+// leave 48 of 64 lanes idle), sixteen per workgroup.  Same contraction,
+// pivot keys (largest |a| as float, ties to the lowest row) and elimination
+// arithmetic, so the factors are bitwise those of k_jaclu_wave; the pivot
+// row, a different lane in each row, travels through ds_bpermute.  Lanes of
+// elements past ne work on element ne - 1 and store nothing, so that every
+// row takes part in the row-wide DPP steps.
+template <int D, int P, class R>
+__global__ __launch_bounds__(256) void k_jaclu_g16(const R* __restrict__ BC, const double* __restrict__ Gpk, int NT,
+                                                   const double* __restrict__ dtau, R* __restrict__ out,
+                                                   int* __restrict__ perm, int* __restrict__ fail, int ne,
+                                                   Tab<D, P, R> tab, const R* __restrict__ gph) {
+  using C = Cfg<D, P>;
+  constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, n = C::NB;
+  static_assert(n == 16, "one element per 16-lane row");
+  constexpr int W = 16;  // elements per block
+  constexpr int PER = (QV * D + NF * QF) * V * V;
+  __shared__ Tab<D, P, R> t;
+  __shared__ R s_dph[QV * D * N];
+  __shared__ R s_phf[NF * QF * N];
+  __shared__ R s_BC[W * PER];
+  const int lane = threadIdx.x & 63, r = lane & 15;
+  const int el = 4 * (threadIdx.x >> 6) + (lane >> 4);
+  const int e0 = blockIdx.x * W;
+  const int e = e0 + el;
+  const bool live = e < ne;
+  const int elc = live ? el : ne - 1 - e0;  // an element of this block (e0 < ne)
+  const int ec = e0 + elc;
+  copy_tab(t, tab);
+  {
+    const int nel = min(W, ne - e0);
+    stage<(W * PER + 255) / 256>(s_BC, BC + (size_t)e0 * PER, nel * PER, threadIdx.x, 256);
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < QV * N; it += blockDim.x) {
+    const int q = it / N, j = it % N;
+    int iq[D], r0 = q;
+#pragma unroll
+    for (int a = 0; a < D; ++a) { iq[a] = r0 % Q; r0 /= Q; }
+#pragma unroll
+    for (int a = 0; a < D; ++a) s_dph[(q * D + a) * N + j] = dphi_vol<D, P, R>(t, j, iq, a);
+  }
+  for (int it = threadIdx.x; it < NF * QF * N; it += blockDim.x) {
+    const int lf = it / (QF * N), k = (it / N) % QF, j = it % N;
+    int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1], r0 = k;
+    face_axes<D>(lf, ta);
+#pragma unroll
+    for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
+    s_phf[it] = phi_face<D, P, R>(t, j, lf, ta, ik);
+  }
+  __syncthreads();
+  const R* sB = s_BC + elc * PER;
+  const R* sC = sB + QV * D * V * V;
+  const int v = r / N, i = r % N;
+  R acc[n];
+#pragma unroll
+  for (int c = 0; c < n; ++c) acc[c] = R(0);
+#pragma unroll 1
+  for (int q = 0; q < QV; ++q) {
+    R bw[V];
+#pragma unroll
+    for (int w = 0; w < V; ++w) bw[w] = R(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const R ad = s_dph[(q * D + a) * N + i];
+      const R* B = &sB[((q * D + a) * V + v) * V];
+#pragma unroll
+      for (int w = 0; w < V; ++w) bw[w] += ad * B[w];
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const R ph = gph[q * N + j];  // uniform: a scalar load
+#pragma unroll
+      for (int w = 0; w < V; ++w) acc[w * N + j] += bw[w] * ph;
+    }
+  }
+#pragma unroll 1
+  for (int fk = 0; fk < NF * QF; ++fk) {
+    const R a = s_phf[fk * N + i];
+    const R* Cm = &sC[(fk * V + v) * V];
+    R cw[V];
+#pragma unroll
+    for (int w = 0; w < V; ++w) cw[w] = a * Cm[w];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const R ph = gph[(QV + fk) * N + j];
+#pragma unroll
+      for (int w = 0; w < V; ++w) acc[w * N + j] -= cw[w] * ph;
+    }
+  }
+  {
+    const R idt = R(1.0 / dtau[ec]);
+    const double* G = Gpk + (size_t)ec * NT;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const R gij = R((i >= j) ? G[i * (i + 1) / 2 + j] : G[j * (j + 1) / 2 + i]);
+#pragma unroll
+      for (int w = 0; w < V; ++w) acc[w * N + j] = ((w == v) ? gij * idt : R(0)) - acc[w * N + j];
+    }
+  }
+  const int rowbase = lane & ~15;
+  int mystep = -1;
+#pragma unroll
+  for (int k = 0; k < n; ++k) {
+    unsigned key = 0u;
+    if (mystep < 0) key = (__float_as_uint((float)dabs(acc[k])) & ~63u) | (unsigned)(15 - r);
+    const unsigned kmax = row_max_u32(key);
+    const int pr = 15 - (int)(kmax & 63u);  // pivot row of this lane's element
+    const int pa = (rowbase + pr) * 4;       // its lane, as a ds_bpermute address
+    if (r == pr && mystep >= 0) atomicOr(fail, 4);
+    mystep = (r == pr) ? k : mystep;
+    const R piv = bperm_d(acc[k], pa);
+    if (r == 0 && !(dabs(piv) > R(0))) atomicOr(fail, 1);
+    const R l = (mystep < 0) ? acc[k] * (R(1) / piv) : R(0);
+    if (mystep < 0) acc[k] = l;
+#pragma unroll
+    for (int j = k + 1; j < n; ++j) {
+      const R pj = bperm_d(acc[j], pa);
+      acc[j] = fma(-l, pj, acc[j]);
+    }
+  }
+  if (live && mystep >= 0) {  // every row is chosen once: an unused row always has the largest key
+    R* o = out + (size_t)e * n * n;
+#pragma unroll
+    for (int j = 0; j < n; ++j) o[(size_t)j * n + mystep] = acc[j];
+    perm[(size_t)e * n + mystep] = r;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The same block assembly and LU for 64 < n = V N < 256, by one block of
 // n / CPW wavefronts per element: wavefront w holds CPW consecutive columns
@@ -3205,7 +3347,12 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
       R* bc = static_cast<R*>(M.bc);
       hipLaunchKernelGGL((k_jac_points<D, P, R>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.nbr,
                          M.ncode, bc, M.ne, t, gas, M.uinf_e);
-      if constexpr (Cfg<D, P>::NB <= 64) {
+      if constexpr (Cfg<D, P>::NB == 16) {
+        const R* gph = static_cast<const R*>(M.phitab[P][sizeof(R) == 4 ? PREC_FP32 : PREC_FP64]);
+        if (!gph) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_jaclu_g16<D, P, R>), dim3((M.ne + 15) / 16), dim3(256), 0, st, bc, M.Gpk, M.NT, dtau,
+                           out, perm, fail, M.ne, t, gph);
+      } else if constexpr (Cfg<D, P>::NB <= 64) {
         const R* gph = static_cast<const R*>(M.phitab[P][sizeof(R) == 4 ? PREC_FP32 : PREC_FP64]);
         if (!gph) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_jaclu_wave<D, P, R>), dim3((M.ne + 3) / 4), dim3(256), 0, st, bc, M.Gpk, M.NT, dtau,
