@@ -828,6 +828,28 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
     M.phitab[p][eg::PREC_FP64] = t64;
     M.phitab[p][eg::PREC_FP32] = t32;
   }
+  // restriction operators p -> p - 1 of every element, R = L_c^{-T} [I 0] L^T
+  // (Nc x N row-major, L the Cholesky factor of the phi mass matrix, L_c its
+  // leading Nc x Nc block): column j of R solves L_c^T x = (row j of L)_c
+  for (int p = 1; p <= h->pmax; ++p) {
+    const int N = nmodes_of(d, p), Nc = nmodes_of(d, p - 1), NT = M.NT;
+    std::vector<double> R((size_t)ne * Nc * N), y(Nc);
+    for (int e = 0; e < ne; ++e) {
+      const double* L = &Lpk[(size_t)e * NT];
+      double* Re = &R[(size_t)e * Nc * N];
+      for (int j = 0; j < N; ++j) {
+        for (int m = 0; m < Nc; ++m) y[m] = (m <= j) ? L[j * (j + 1) / 2 + m] : 0.0;
+        for (int k = Nc - 1; k >= 0; --k) {
+          double sk = y[k];
+          for (int m = k + 1; m < Nc; ++m) sk -= L[m * (m + 1) / 2 + k] * y[m];
+          y[k] = sk / L[k * (k + 1) / 2 + k];
+        }
+        for (int k = 0; k < Nc; ++k) Re[(size_t)k * N + j] = y[k];
+      }
+    }
+    AL(M.Rop[p], R.size());
+    HIPCHK(h, hipMemcpy(M.Rop[p], R.data(), R.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
   for (int p = 0; p <= h->pmax; ++p) {
     const size_t K = (size_t)ne * V * nmodes_of(d, p);
     AL(h->ut[p], K);

@@ -1720,31 +1720,34 @@ constexpr int norm_group() {
 
 // Restriction of the solution from order p (N modes) to p-1 (Nc modes): the
 // L2 projection, which in psi coordinates is truncation: u = L^T ut, keep
-// the leading Nc entries, ut_c = L_c^{-T} u_c.
+// the leading Nc entries, ut_c = L_c^{-T} u_c.  The composed operator
+// R = L_c^{-T} [I 0] L^T of each element (Nc x N, row-major) is formed at
+// set-up; one thread per coarse coefficient applies its row of R.
 template <int N, int Nc>
 __global__ __launch_bounds__(256) void k_restrict(const double* __restrict__ ut, double* __restrict__ uc,
-                                                  double* __restrict__ uc0, const double* __restrict__ Lpk, int NT, int V,
+                                                  double* __restrict__ uc0, const double* __restrict__ Rop, int V,
                                                   int ne) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= ne * V) return;
-  const int e = id / V;
-  const double* L = Lpk + (size_t)e * NT;
-  const double* a = ut + (size_t)id * N;
-  double u[Nc];
-  for (int k = 0; k < Nc; ++k) {
-    double s = 0.0;
-    for (int j = k; j < N; ++j) s += L[j * (j + 1) / 2 + k] * a[j];
-    u[k] = s;
+  if (id >= ne * V * Nc) return;
+  const int k = id % Nc, row = id / Nc, e = row / V;
+  const double* a = ut + (size_t)row * N;
+  const double* r = Rop + ((size_t)e * Nc + k) * N;
+  double s = 0.0;
+  // sixteen loads of each operand in flight, then their products in order
+  for (int j0 = 0; j0 < N; j0 += 16) {
+    double av[16], rv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int j = j0 + u < N ? j0 + u : N - 1;
+      av[u] = a[j];
+      rv[u] = r[j];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (j0 + u < N) s += rv[u] * av[u];
   }
-  for (int k = Nc - 1; k >= 0; --k) {
-    double s = u[k];
-    for (int j = k + 1; j < Nc; ++j) s -= L[j * (j + 1) / 2 + k] * u[j];
-    u[k] = s / L[k * (k + 1) / 2 + k];
-  }
-  for (int k = 0; k < Nc; ++k) {
-    uc[(size_t)id * Nc + k] = u[k];
-    uc0[(size_t)id * Nc + k] = u[k];
-  }
+  uc[id] = s;
+  uc0[id] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -3398,10 +3401,10 @@ hipError_t basis_t(const DevMesh& M, const double* x, double* y, int mode, hipSt
 }
 
 template <int N, int Nc>
-hipError_t restrict_t(const DevMesh& M, const double* ut, double* uc, double* uc0, hipStream_t st) {
-  const int rows = M.ne * M.V;
-  hipLaunchKernelGGL((k_restrict<N, Nc>), dim3((rows + 255) / 256), dim3(256), 0, st, ut, uc, uc0, M.Lpk, M.NT, M.V,
-                     M.ne);
+hipError_t restrict_t(const DevMesh& M, const double* R, const double* ut, double* uc, double* uc0, hipStream_t st) {
+  if (!R) return hipErrorInvalidValue;
+  const int cnt = M.ne * M.V * Nc;
+  hipLaunchKernelGGL((k_restrict<N, Nc>), dim3((cnt + 255) / 256), dim3(256), 0, st, ut, uc, uc0, R, M.V, M.ne);
   return hipGetLastError();
 }
 
@@ -3551,17 +3554,17 @@ hipError_t launch_basis(const DevMesh& M, int N, const double* x, double* y, int
 hipError_t launch_restrict(const DevMesh& M, int p, const double* ut, double* uc, double* uc0, hipStream_t st) {
   if (M.d == 2) {
     switch (p) {
-      case 1: return restrict_t<4, 1>(M, ut, uc, uc0, st);
-      case 2: return restrict_t<9, 4>(M, ut, uc, uc0, st);
-      case 3: return restrict_t<16, 9>(M, ut, uc, uc0, st);
-      case 4: return restrict_t<25, 16>(M, ut, uc, uc0, st);
+      case 1: return restrict_t<4, 1>(M, M.Rop[p], ut, uc, uc0, st);
+      case 2: return restrict_t<9, 4>(M, M.Rop[p], ut, uc, uc0, st);
+      case 3: return restrict_t<16, 9>(M, M.Rop[p], ut, uc, uc0, st);
+      case 4: return restrict_t<25, 16>(M, M.Rop[p], ut, uc, uc0, st);
       default: break;
     }
   } else {
     switch (p) {
-      case 1: return restrict_t<8, 1>(M, ut, uc, uc0, st);
-      case 2: return restrict_t<27, 8>(M, ut, uc, uc0, st);
-      case 3: return restrict_t<64, 27>(M, ut, uc, uc0, st);
+      case 1: return restrict_t<8, 1>(M, M.Rop[p], ut, uc, uc0, st);
+      case 2: return restrict_t<27, 8>(M, M.Rop[p], ut, uc, uc0, st);
+      case 3: return restrict_t<64, 27>(M, M.Rop[p], ut, uc, uc0, st);
       default: break;
     }
   }
