@@ -829,8 +829,9 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
     M.phitab[p][eg::PREC_FP32] = t32;
   }
   // restriction operators p -> p - 1 of every element, R = L_c^{-T} [I 0] L^T
-  // (Nc x N row-major, L the Cholesky factor of the phi mass matrix, L_c its
-  // leading Nc x Nc block): column j of R solves L_c^T x = (row j of L)_c
+  // (stored by columns, [N][Nc]; L the Cholesky factor of the phi mass
+  // matrix, L_c its leading Nc x Nc block): column j of R solves
+  // L_c^T x = (row j of L)_c
   for (int p = 1; p <= h->pmax; ++p) {
     const int N = nmodes_of(d, p), Nc = nmodes_of(d, p - 1), NT = M.NT;
     std::vector<double> R((size_t)ne * Nc * N), y(Nc);
@@ -844,7 +845,7 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
           for (int m = k + 1; m < Nc; ++m) sk -= L[m * (m + 1) / 2 + k] * y[m];
           y[k] = sk / L[k * (k + 1) / 2 + k];
         }
-        for (int k = 0; k < Nc; ++k) Re[(size_t)k * N + j] = y[k];
+        for (int k = 0; k < Nc; ++k) Re[(size_t)j * Nc + k] = y[k];
       }
     }
     AL(M.Rop[p], R.size());

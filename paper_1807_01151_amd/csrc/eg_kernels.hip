@@ -1721,8 +1721,9 @@ constexpr int norm_group() {
 // Restriction of the solution from order p (N modes) to p-1 (Nc modes): the
 // L2 projection, which in psi coordinates is truncation: u = L^T ut, keep
 // the leading Nc entries, ut_c = L_c^{-T} u_c.  The composed operator
-// R = L_c^{-T} [I 0] L^T of each element (Nc x N, row-major) is formed at
-// set-up; one thread per coarse coefficient applies its row of R.
+// R = L_c^{-T} [I 0] L^T of each element is formed at set-up, stored by
+// columns ([N][Nc]: the Nc threads of a row read consecutive entries); one
+// thread per coarse coefficient applies its row of R.
 template <int N, int Nc>
 __global__ __launch_bounds__(256) void k_restrict(const double* __restrict__ ut, double* __restrict__ uc,
                                                   double* __restrict__ uc0, const double* __restrict__ Rop, int V,
@@ -1731,7 +1732,7 @@ __global__ __launch_bounds__(256) void k_restrict(const double* __restrict__ ut,
   if (id >= ne * V * Nc) return;
   const int k = id % Nc, row = id / Nc, e = row / V;
   const double* a = ut + (size_t)row * N;
-  const double* r = Rop + ((size_t)e * Nc + k) * N;
+  const double* r = Rop + (size_t)e * Nc * N + k;  // R[k][j] at r[j * Nc]
   double s = 0.0;
   // sixteen loads of each operand in flight, then their products in order
   for (int j0 = 0; j0 < N; j0 += 16) {
@@ -1740,7 +1741,7 @@ __global__ __launch_bounds__(256) void k_restrict(const double* __restrict__ ut,
     for (int u = 0; u < 16; ++u) {
       const int j = j0 + u < N ? j0 + u : N - 1;
       av[u] = a[j];
-      rv[u] = r[j];
+      rv[u] = r[(size_t)j * Nc];
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u)

@@ -19,7 +19,7 @@ struct DevMesh {
   int* nbr = nullptr;      // [E][2d]
   uint8_t* ncode = nullptr;
   double* Lpk = nullptr;   // [E][NT] Cholesky factor of the phi mass matrix
-  // restriction p -> p - 1 per element, R = L_c^{-T} [I 0] L^T: [E][N(p-1)][N(p)]
+  // restriction p -> p - 1 per element, R = L_c^{-T} [I 0] L^T by columns: [E][N(p)][N(p-1)]
   double* Rop[5] = {};
   double* Gpk = nullptr;   // [E][NT] phi mass matrix
   double* hE = nullptr;    // [E] 2 d |E| / |dE|
