@@ -642,7 +642,9 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
 // each: volume point q writes Bq[r][v][w] = w_q d(F_v . c_r)/dU_w (r < D),
 // face point (lf, k) writes Cf[v][w] = w_k |n dsigma| dF~_v/dU_own_w (with the
 // ghost chain rule on boundary faces), all by dual numbers.  Layout per
-// element: [QV][D][V][V] then [NF*QF][V][V].
+// element: [QV][D][V][V] then [NF*QF][V][V].  The thread index runs over
+// all volume points first, then all face points, so that a wavefront takes
+// one of the two paths.
 template <int D, int P, class R>
 __global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ ut, const double* __restrict__ xv,
                                                     const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
@@ -657,7 +659,9 @@ __global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ u
   __syncthreads();
   const int it = blockIdx.x * blockDim.x + threadIdx.x;
   if (it >= ne * NPT) return;
-  const int e = it / NPT, pt = it % NPT;
+  const int nv = ne * QV;
+  const int e = it < nv ? it / QV : (it - nv) / (NF * QF);
+  const int pt = it < nv ? it % QV : QV + (it - nv) % (NF * QF);
   const double* ue = ut + (size_t)e * V * N;
   R X[NC * D];
 #pragma unroll
