@@ -18,5 +18,6 @@ from .meshes import (  # noqa: F401
     box,
     radial_map,
     wall_bumps,
+    reorient,
 )
 from .draws import batch_draws, bump_centers, seeded_array  # noqa: F401

@@ -244,3 +244,45 @@ def wall_bumps(mesh: Mesh, amps, centers, sigma: float, r_in: float = 0.5,
         delta += a * np.exp(-th * th / (2.0 * sigma * sigma))
     xyz = xh * (r + delta * w)[:, None]
     return Mesh(mesh.dim, xyz, mesh.elem_vert.copy(), mesh.bface_tag.copy(), mesh.name + "+bumps")
+
+
+def _rotations(dim: int):
+    """The orientation-preserving symmetries of the reference square / cube
+    (signed permutation matrices with determinant +1): 4 in 2D, 24 in 3D."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(dim)):
+        for signs in itertools.product((1, -1), repeat=dim):
+            S = np.zeros((dim, dim), dtype=np.int64)
+            for r in range(dim):
+                S[r, perm[r]] = signs[r]
+            if round(np.linalg.det(S)) == 1:
+                out.append(S)
+    return out
+
+
+def reorient(mesh: Mesh, seed: int) -> Mesh:
+    """Same elements and geometry, new local reference frames: each element's
+    local vertex list is re-labelled by a seeded random rotation S of the
+    reference square / cube (xi_old = S xi_new), and its boundary tags follow
+    the faces they belong to.  Shared faces then meet with every combination
+    of axis swap and flips, which the structured generators never produce."""
+    dim = mesh.dim
+    rots = _rotations(dim)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pick = rng.integers(0, len(rots), size=mesh.n_elem)
+    nc = 2 ** dim
+    corners = np.array([[2 * ((k >> r) & 1) - 1 for r in range(dim)] for k in range(nc)], dtype=np.int64)
+    index_of = {tuple(c): k for k, c in enumerate(corners)}
+    ev = np.empty_like(mesh.elem_vert)
+    tg = np.empty_like(mesh.bface_tag)
+    for e in range(mesh.n_elem):
+        S = rots[pick[e]]
+        for k in range(nc):
+            ev[e, k] = mesh.elem_vert[e, index_of[tuple(S @ corners[k])]]
+        for rn in range(dim):
+            r = int(np.nonzero(S[:, rn])[0][0])
+            for s in (-1, 1):
+                so = S[r, rn] * s
+                tg[e, 2 * rn + (s > 0)] = mesh.bface_tag[e, 2 * r + (so > 0)]
+    return Mesh(dim, mesh.xyz.copy(), ev, tg, mesh.name + f"+reoriented{seed}")

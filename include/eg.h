@@ -217,12 +217,13 @@ eg_status eg_layout(const eg_handle* h, int solve, int p, int64_t* offset, int* 
 /* Batched steady solve: V-cycles of all solves together until every solve
  * has r_n <= drop_tol r_1 (its own r_1) or max_cycles.  hist_host is
  * [n_solves][max_cycles + 1]: solve s's norms r_1, r_2, ... up to the cycle
- * it reached the drop, which n_cycles_host[s] receives.  Converged solves
- * keep being cycled (they sit at their fixed point) until all are done.
- * A solve whose norm becomes non-finite is marked diverged (its history
- * ends there) and the others continue; its values never reach the other
- * solves.  Returns EG_OK when all converged, else EG_ERR_DIVERGED if any
- * diverged, else EG_ERR_NOT_CONVERGED. */
+ * it reached the drop, which n_cycles_host[s] receives.  The kernels keep
+ * covering converged solves until all are done, but each converged solve's
+ * state is saved at the cycle whose norm reached the drop and is what u_dev
+ * returns for it.  A solve whose norm becomes non-finite is marked diverged
+ * (its history ends there) and the others continue; its values never reach
+ * the other solves.  Returns EG_OK when all converged, else EG_ERR_DIVERGED
+ * if any diverged, else EG_ERR_NOT_CONVERGED. */
 eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
                          int* n_cycles_host);
 
@@ -255,7 +256,8 @@ eg_status eg_adjoint_apply(eg_handle* h, int p, const double* u_dev, const doubl
  * adjoint problem with the transposed p = 0 operator.  lam_dev: initial
  * guess in, solution out.  Stops when the 2-norm of the adjoint residual
  * has dropped by drop_tol; hist_host[0..*n_cycles_host] as for
- * eg_solve_steady.  Element blocks up to 64 x 64 (else EG_ERR_UNSUPPORTED).
+ * eg_solve_steady.  Orders with a transposed block solve: 2D p <= 3 and 3D
+ * p <= 2 (else EG_ERR_UNSUPPORTED).
  * Runs in FP64 on every handle.  Synchronises. */
 eg_status eg_adjoint_solve(eg_handle* h, const double* u_dev, const double* g_dev, double* lam_dev, double drop_tol,
                            int max_cycles, double* hist_host, int* n_cycles_host);
@@ -272,7 +274,7 @@ enum {
   EG_K_TRANSFER = 3,     /* restriction, FAS forcing, prolongation, state copies */
   EG_K_TIMESTEP = 4,     /* pseudo-time step */
   EG_K_P0_SETUP = 5,     /* p = 0 residual, Jacobian blocks and right-hand side */
-  EG_K_ARNOLDI = 6,      /* Arnoldi process (cooperative) */
+  EG_K_ARNOLDI = 6,      /* Arnoldi process (two grid-wide kernels per step) */
   EG_K_PHI1 = 7,         /* phi_1 of the Hessenberg matrix */
   EG_K_EXP1_UPDATE = 8,  /* Krylov combination of the EXP1 update */
   EG_K_NORM = 9,         /* residual norm */

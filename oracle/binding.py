@@ -59,6 +59,7 @@ def lib():
         L.orc_flux_jac.argtypes = [C.c_int, C.c_double, _d, _d, _d]
         L.orc_rusanov.argtypes = [C.c_int, C.c_double, _d, _d, _d, _d]
         L.orc_ghost.argtypes = [C.c_void_p, C.c_int, _d, _d, _d, _d]
+        L.orc_rusanov_jac.argtypes = [C.c_int, C.c_double, _d, _d, _d, _d, _d]
         L.orc_timestep.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, _d, _d]
         L.orc_rnorm.restype = C.c_double
         L.orc_rnorm.argtypes = [C.c_void_p, C.c_int, _d]
@@ -148,6 +149,15 @@ def rusanov(dim, gamma, UL, UR, nh):
     F = np.zeros(dim + 2)
     lib().orc_rusanov(dim, gamma, _p(UL), _p(UR), _p(nh), _p(F))
     return F
+
+
+def rusanov_jac(dim, gamma, UL, UR, nh):
+    """(dF/dUL, dF/dUR) of the Rusanov flux by complex step."""
+    UL, UR, nh = (np.ascontiguousarray(a, dtype=np.float64) for a in (UL, UR, nh))
+    JL = np.zeros((dim + 2, dim + 2))
+    JR = np.zeros((dim + 2, dim + 2))
+    lib().orc_rusanov_jac(dim, gamma, _p(UL), _p(UR), _p(nh), _p(JL), _p(JR))
+    return JL, JR
 
 
 def flux_jac(dim, gamma, U, g):

@@ -1356,6 +1356,24 @@ void orc_rusanov(int dim, double gamma, const double* UL, const double* UR, cons
   rusanov<double>(dim, gamma, UL, UR, nh, F);
 }
 
+// Jacobians of the Rusanov flux with respect to each trace, by complex step
+// through the same templated flux the element Jacobians use (tests of the
+// derivative tie semantics).  JL[v][w] = dF_v/dUL_w, JR likewise.
+void orc_rusanov_jac(int dim, double gamma, const double* UL, const double* UR, const double* nh, double* JL,
+                     double* JR) {
+  const int V = dim + 2;
+  cs_jac(V, UL, [&](const cd* Uc, cd* Fc) {
+    cd Ur[MAXV];
+    for (int v = 0; v < V; ++v) Ur[v] = cd(UR[v], 0.0);
+    rusanov<cd>(dim, gamma, Uc, Ur, nh, Fc);
+  }, JL);
+  cs_jac(V, UR, [&](const cd* Uc, cd* Fc) {
+    cd Ul[MAXV];
+    for (int v = 0; v < V; ++v) Ul[v] = cd(UL[v], 0.0);
+    rusanov<cd>(dim, gamma, Ul, Uc, nh, Fc);
+  }, JR);
+}
+
 void orc_ghost(void* h, int tg, const double* U, const double* nh, const double* x, double* Ug) {
   ghost_any<double>(*static_cast<Oracle*>(h), tg, U, nh, x, Ug);
 }

@@ -93,12 +93,26 @@ def lib():
     return _lib
 
 
-def _ptr(t):
-    if t is None:
-        return None
+def check_tensor(t, numel=None, dtype="float64", device=None, name="tensor"):
+    """Checks a caller tensor before its pointer crosses the C ABI: a torch
+    tensor of the given dtype and element count, contiguous, on the handle's
+    device.  The kernels read and write exactly numel values, so a mismatch
+    is refused here rather than left to the device.  Raises TypeError
+    (type, dtype, device) or ValueError (size)."""
     import torch
-    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or not t.is_contiguous():
-        raise TypeError("expected a contiguous device tensor")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    want = getattr(torch, dtype)
+    if t.dtype != want:
+        raise TypeError(f"{name}: expected dtype {want}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()} (shape {tuple(t.shape)})")
+    if not t.is_contiguous():
+        raise TypeError(f"{name}: expected a contiguous tensor")
+    if t.device.type != "cuda":
+        raise TypeError(f"{name}: expected a device tensor, got one on {t.device}")
+    if device is not None and t.device.index != device:
+        raise TypeError(f"{name}: tensor on cuda:{t.device.index}, handle on cuda:{device}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -135,6 +149,7 @@ class Solver:
         self.dim, self.p_max, self.n_elem, self.V = m.dim, p_max, m.n_elem, m.dim + 2
         self.mach, self.alpha_deg, self.beta_deg = mach, alpha_deg, beta_deg
         self.krylov_m = krylov_m
+        self.device = torch.cuda.current_device()
         self._np = np
 
     def close(self):
@@ -155,61 +170,87 @@ class Solver:
     def N(self, p: int) -> int:
         return (p + 1) ** self.dim
 
+    def _vec(self, t, p: int, name: str = "u"):
+        """Pointer of a level-p coefficient vector (n_elem * V * N_p FP64
+        values on the handle's device); None passes through."""
+        if t is None:
+            return None
+        if not 0 <= p <= self.p_max:
+            raise ValueError(f"order p = {p} outside 0..{self.p_max}")
+        return check_tensor(t, self.n_elem * self.V * self.N(p), "float64", self.device, name)
+
+    def _arr(self, t, numel: int, name: str, dtype: str = "float64"):
+        return check_tensor(t, numel, dtype, self.device, name)
+
     def empty(self, p: int):
         import torch
         return torch.empty((self.n_elem, self.V, self.N(p)), dtype=torch.float64, device="cuda")
 
     def freestream(self, p: int):
         u = self.empty(p)
-        self._chk(lib().eg_set_freestream(self._h, p, _ptr(u)))
+        pu = self._vec(u, p)
+        self._chk(lib().eg_set_freestream(self._h, p, pu))
         return u
 
     def residual(self, p: int, u, out=None):
+        pu = self._vec(u, p, "u")
         r = self.empty(p) if out is None else out
-        self._chk(lib().eg_residual(self._h, p, _ptr(u), _ptr(r)))
+        pr = self._vec(r, p, "out")
+        self._chk(lib().eg_residual(self._h, p, pu, pr))
         return r
 
     def timestep(self, p: int, cfl: float, u):
         import torch
-        dt = torch.empty(self.n_elem, dtype=torch.float64, device="cuda")
+        if u.dim() != 3:
+            raise ValueError("u: expected a [n_elem, V, N_p] tensor")
         p_level = round(u.shape[2] ** (1.0 / self.dim)) - 1
-        self._chk(lib().eg_timestep(self._h, p, p_level, cfl, _ptr(u), _ptr(dt)))
+        pu = self._vec(u, p_level, "u")
+        dt = torch.empty(self.n_elem, dtype=torch.float64, device="cuda")
+        self._chk(lib().eg_timestep(self._h, p, p_level, cfl, pu, self._arr(dt, self.n_elem, "dtau")))
         return dt
 
     def element_jacobian(self, p: int, u):
         import torch
+        pu = self._vec(u, p, "u")
         n = self.V * self.N(p)
         D = torch.empty((self.n_elem, n, n), dtype=torch.float64, device="cuda")
-        self._chk(lib().eg_element_jacobian(self._h, p, _ptr(u), _ptr(D)))
+        self._chk(lib().eg_element_jacobian(self._h, p, pu, self._arr(D, self.n_elem * n * n, "D")))
         return D
 
     def prk_step(self, p: int, cfl: float, u, f=None):
-        self._chk(lib().eg_prk_step(self._h, p, cfl, _ptr(u), _ptr(f)))
+        pu, pf = self._vec(u, p, "u"), self._vec(f, p, "f")
+        self._chk(lib().eg_prk_step(self._h, p, cfl, pu, pf))
         return u
 
     def jacobian_p0(self, u0):
         import torch
+        pu = self._vec(u0, 0, "u0")
         V, nf = self.V, 2 * self.dim
         Dg = torch.empty((self.n_elem, V, V), dtype=torch.float64, device="cuda")
         Off = torch.empty((self.n_elem, nf, V, V), dtype=torch.float64, device="cuda")
         nb = torch.empty((self.n_elem, nf), dtype=torch.int32, device="cuda")
-        self._chk(lib().eg_jacobian_p0(self._h, _ptr(u0), _ptr(Dg), _ptr(Off), _ptr(nb)))
+        self._chk(lib().eg_jacobian_p0(self._h, pu, self._arr(Dg, Dg.numel(), "diag"),
+                                       self._arr(Off, Off.numel(), "off"),
+                                       self._arr(nb, nb.numel(), "nbr", "int32")))
         return Dg, Off, nb
 
     def exp1_step(self, cfl: float, u0, f0=None):
+        pu, pf = self._vec(u0, 0, "u0"), self._vec(f0, 0, "f0")
         mu = C.c_int(0)
-        self._chk(lib().eg_exp1_step(self._h, cfl, _ptr(u0), _ptr(f0), C.byref(mu)))
+        self._chk(lib().eg_exp1_step(self._h, cfl, pu, pf, C.byref(mu)))
         return u0, mu.value
 
     def rnorm(self, r) -> float:
+        pr = self._vec(r, self.p_max, "r")
         v = C.c_double(0.0)
-        self._chk(lib().eg_rnorm(self._h, _ptr(r), C.byref(v)))
+        self._chk(lib().eg_rnorm(self._h, pr, C.byref(v)))
         return v.value
 
     def vcycle(self, u, n: int, rref: float = 0.0):
+        pu = self._vec(u, self.p_max, "u")
         rn = C.c_double(0.0)
         cfl = C.c_double(0.0)
-        self._chk(lib().eg_vcycle(self._h, _ptr(u), n, rref, C.byref(rn), C.byref(cfl)))
+        self._chk(lib().eg_vcycle(self._h, pu, n, rref, C.byref(rn), C.byref(cfl)))
         return rn.value, cfl.value
 
     def profile(self, enable: bool):
@@ -235,10 +276,11 @@ class Solver:
     def solve_steady(self, u, drop_tol: float = 1e-10, max_cycles: int = 1000, raise_on_fail: bool = False,
                      resume: bool = False):
         np = self._np
+        pu = self._vec(u, self.p_max, "u")
         hist = np.zeros(max_cycles + 1)
         nc = C.c_int(0)
         fn = lib().eg_solve_resume if resume else lib().eg_solve_steady
-        st = fn(self._h, _ptr(u), drop_tol, max_cycles, hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nc))
+        st = fn(self._h, pu, drop_tol, max_cycles, hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nc))
         if st not in (0, 5, 6) or (raise_on_fail and st != 0):
             self._chk(st)
         return hist[: nc.value + 1], st
@@ -265,15 +307,17 @@ def _solver_drag(self, u, direction=None, sref: float = 1.0, grad: bool = False)
         direction = _freestream_direction(self.dim, self.alpha_deg, self.beta_deg)
     dv = (C.c_double * 3)(*([float(x) for x in direction] + [0.0] * (3 - len(direction))))
     cd = C.c_double(0.0)
+    pu = self._vec(u, self.p_max, "u")
     g = self.empty(self.p_max) if grad else None
-    self._chk(lib().eg_drag(self._h, _ptr(u), dv, float(sref), C.byref(cd), _ptr(g)))
+    self._chk(lib().eg_drag(self._h, pu, dv, float(sref), C.byref(cd), self._vec(g, self.p_max, "grad")))
     return (cd.value, g) if grad else cd.value
 
 
 def _solver_adjoint_apply(self, p: int, u, w, out=None):
     """(dR_p/du)(u)^T w."""
+    pu, pw = self._vec(u, p, "u"), self._vec(w, p, "w")
     o = self.empty(p) if out is None else out
-    self._chk(lib().eg_adjoint_apply(self._h, p, _ptr(u), _ptr(w), _ptr(o)))
+    self._chk(lib().eg_adjoint_apply(self._h, p, pu, pw, self._vec(o, p, "out")))
     return o
 
 
@@ -283,10 +327,12 @@ def _solver_adjoint_solve(self, u, g, lam=None, drop_tol: float = 1e-10, max_cyc
     (lambda, history of the adjoint residual 2-norm, status)."""
     import torch
     np = self._np
+    pu, pg = self._vec(u, self.p_max, "u"), self._vec(g, self.p_max, "g")
     lam = torch.zeros_like(g) if lam is None else lam
+    pl = self._vec(lam, self.p_max, "lam")
     hist = np.zeros(max_cycles + 1)
     nc = C.c_int(0)
-    st = lib().eg_adjoint_solve(self._h, _ptr(u), _ptr(g), _ptr(lam), drop_tol, max_cycles,
+    st = lib().eg_adjoint_solve(self._h, pu, pg, pl, drop_tol, max_cycles,
                                 hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nc))
     if st not in (0, 5) or (raise_on_fail and st != 0):
         self._chk(st)
@@ -336,6 +382,7 @@ class BatchSolver:
         self.n, self.dim, self.p_max, self.V = n, ms[0].dim, p_max, ms[0].dim + 2
         self.n_elem = sum(m.n_elem for m in ms)
         self.elems = [m.n_elem for m in ms]
+        self.device = torch.cuda.current_device()
         self._np = np
 
     close = Solver.close
@@ -343,6 +390,8 @@ class BatchSolver:
     set_graphs = Solver.set_graphs
     _chk = Solver._chk
     N = Solver.N
+    _vec = Solver._vec
+    _arr = Solver._arr
     empty = Solver.empty
     freestream = Solver.freestream
     residual = Solver.residual
@@ -379,9 +428,10 @@ class BatchSolver:
     def solve(self, u, drop_tol: float = 1e-10, max_cycles: int = 1000):
         """Returns (list of per-solve residual histories, cycles per solve, status)."""
         np = self._np
+        pu = self._vec(u, self.p_max, "u")
         hist = np.zeros((self.n, max_cycles + 1))
         nc = (C.c_int * self.n)()
-        st = lib().eg_solve_batch(self._h, _ptr(u), drop_tol, max_cycles,
+        st = lib().eg_solve_batch(self._h, pu, drop_tol, max_cycles,
                                   hist.ctypes.data_as(C.POINTER(C.c_double)), nc)
         if st not in (0, 5, 6):
             self._chk(st)

@@ -96,6 +96,7 @@ struct eg_handle {
   bool batch = false;
   std::vector<int> seg_e0;   // host copy of the element ranges
   double* dcfl = nullptr;    // [nseg] device CFL per solve
+  double* bsave = nullptr;   // [K at p_max] states of converged solves, saved at their last norm
   double* cfl_e_buf = nullptr;  // [E] per-element CFL (bound to M.cfl_e only inside eg_solve_batch)
   // graph replay of the V-cycle below the entry norm (eg_set_graphs)
   bool graphs = false;
@@ -1498,6 +1499,8 @@ eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_c
   CflBind cb(h);  // per-solve CFL for the duration of the batch solve
   const DevMesh& M = h->M;
   const int nseg = M.nseg, pm = h->pmax, N = nmodes_of(M.d, pm);
+  const size_t per_elem = (size_t)M.V * N;
+  if (!h->bsave) ECHK(dalloc(h, &h->bsave, (size_t)M.ne * per_elem));
   std::vector<double> r1(nseg, -1.0), rmin(nseg, HUGE_VAL);
   std::vector<int> done(nseg, 0), nmin(nseg, 1);
   for (int sg = 0; sg < nseg; ++sg) n_cycles_host[sg] = 0;
@@ -1526,7 +1529,15 @@ eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_c
         hist_host[(size_t)sg * (max_cycles + 1) + (n - 1)] = rn;
         n_cycles_host[sg] = n - 1;
         if (!std::isfinite(rn)) done[sg] = 2;
-        else if (rn <= drop_tol * r1[sg]) done[sg] = 1;
+        else if (rn <= drop_tol * r1[sg]) {
+          // keep the state whose norm reached the drop: later cycles of the
+          // batch still run over this solve's elements
+          done[sg] = 1;
+          const size_t o = (size_t)h->seg_e0[sg] * per_elem;
+          const size_t cnt = (size_t)(h->seg_e0[sg + 1] - h->seg_e0[sg]) * per_elem;
+          HIPCHK(h, hipMemcpyAsync(h->bsave + o, h->ut[pm] + o, cnt * sizeof(double), hipMemcpyDeviceToDevice,
+                                   h->st));
+        }
       }
       all = all && done[sg];
       if (done[sg] != 2) {
@@ -1557,6 +1568,13 @@ eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_c
     HIPCHK(h, eg::launch_expand_cfl(M, h->dcfl, h->st));
     st = vcycle_run(h, h->cfl_max);
     if (st != EG_OK) break;
+  }
+  for (int sg = 0; sg < nseg; ++sg) {
+    if (done[sg] != 1) continue;
+    const size_t o = (size_t)h->seg_e0[sg] * per_elem;
+    const size_t cnt = (size_t)(h->seg_e0[sg + 1] - h->seg_e0[sg]) * per_elem;
+    hipError_t ec = hipMemcpyAsync(h->ut[pm] + o, h->bsave + o, cnt * sizeof(double), hipMemcpyDeviceToDevice, h->st);
+    if (ec != hipSuccess && st == EG_OK) st = hipfail(h, ec, "restore converged states");
   }
   hipError_t e = eg::launch_basis(M, N, h->ut[pm], u_dev, 1, h->st);
   if (e != hipSuccess && st == EG_OK) st = hipfail(h, e, "basis");

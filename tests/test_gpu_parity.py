@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
-from eg_inputs import ogrid, cubed_sphere_shell, box, TAG_FARFIELD
+from eg_inputs import ogrid, cubed_sphere_shell, box, reorient, TAG_FARFIELD
 from tests.gpu_util import perturbed, to_dev, to_host, rel_err
 
 pytestmark = pytest.mark.gpu
@@ -26,6 +26,9 @@ CASES = [
     ("box2d-skew-p2", box(2, 5, skew=0.2, seed=2, tag=TAG_FARFIELD), 2, 7.0),
     ("sphere6x2x2x2-p1", cubed_sphere_shell(2, 2), 1, 2.0),
     ("sphere6x2x2x2-p2", cubed_sphere_shell(2, 2), 2, 2.0),
+    # random local frames: neighbours meet with every swap / flip combination
+    ("ogrid16x6-p3-reoriented", reorient(ogrid(16, 6), 11), 3, 3.0),
+    ("sphere6x2x2x2-p2-reoriented", reorient(cubed_sphere_shell(2, 2), 12), 2, 2.0),
 ]
 
 
