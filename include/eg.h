@@ -75,7 +75,21 @@ typedef struct {
   double alpha_deg;   /* free-stream angle in the x-y plane */
   double beta_deg;    /* 3D only: angle out of the x-y plane */
   int precision;      /* EG_FP64 or EG_MIXED (see below) */
+  int flux;           /* numerical flux of the face integrals: EG_FLUX_RUSANOV or EG_FLUX_ROE */
 } eg_params;
+
+/* Numerical flux (eg_params.flux), Section 3.1 after eq. (euler3) and
+ * Section 3.3 (the same flux with a ghost state on boundary faces):
+ *  EG_FLUX_RUSANOV  local Lax-Friedrichs, dissipation max over both sides of
+ *                   |v . n| + c;
+ *  EG_FLUX_ROE      the paper's Roe solver: Roe-averaged (sqrt(rho)-weighted)
+ *                   velocity and total enthalpy, wave decomposition of the
+ *                   jump, Harten's entropy fix on the two acoustic waves for
+ *                   |lambda| < c / 10 (the paper names no fix).
+ * Every kernel (residual, element blocks, p = 0 operator, J v, J^T w, drag)
+ * uses the handle's flux; its Jacobians come from the same dual-number
+ * evaluation. */
+enum { EG_FLUX_RUSANOV = 0, EG_FLUX_ROE = 1 };
 
 /* Arithmetic of the smoother (eg_params.precision).
  *  EG_FP64:  every kernel in FP64.
@@ -86,8 +100,9 @@ typedef struct {
  *            phase A also evaluates the residuals of the levels p >= 1 in
  *            FP32, with an FP64 defect at p_max (d = R64(u^n) - R32(u^n) is
  *            that level's forcing for the cycle); it ends for good once the
- *            FP64 norm r_n <= 1e-4 r_1 or has not reached a new minimum for
- *            100 cycles.  Phase B evaluates every residual in FP64, so the
+ *            FP64 norm r_n <= 1e-4 r_1, has not reached a new minimum for
+ *            100 cycles, or r_n > 0.9 r_{n-50} (less than 10% progress in
+ *            50 cycles).  Phase B evaluates every residual in FP64, so the
  *            FP32 blocks only precondition an FP64 defect correction
  *            (Section 2.3, eq. (prk_scalar) with P in FP32) and the
  *            converged state is the FP64 steady state.  eg_vcycle runs
@@ -112,7 +127,8 @@ eg_status eg_set_freestream(eg_handle* h, int p, double* u_dev);
 
 /* DG residual R_p(u) of Section 3.1, eq. (euler3) (no source term):
  *   R_{E,i} = -sum_faces int psi_i F~.n dsigma + int_E F . grad psi_i dx,
- * Rusanov flux, (p+2)^d Gauss points per element and (p+2)^(d-1) per face.
+ * the handle's numerical flux (eg_params.flux), (p+2)^d Gauss points per
+ * element and (p+2)^(d-1) per face.
  * u_dev, r_dev: level-p vectors.  Evaluated in the smoother's arithmetic:
  * FP32 for p >= 1 on an EG_MIXED handle (FP64 inputs and outputs), else FP64.
  * Asynchronous. */
@@ -243,6 +259,17 @@ eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_c
 eg_status eg_drag(eg_handle* h, const double* u_dev, const double* dir_host, double sref, double* cd_host,
                   double* grad_dev);
 
+/* Jacobian of the residual applied to a vector (Section 3.3, eqs. (jac1)
+ * and (jac2): element-diagonal and neighbour blocks together), matrix free:
+ * out_dev = (dR_p/du)(u_dev) v_dev at any level 0 <= p <= p_max, by
+ * forward-mode differentiation of the residual (dual numbers with one
+ * tangent at every quadrature point; the flux, ghost-state and Rusanov
+ * derivatives are exact, with the tie rules of the block Jacobians).  All
+ * level-p vectors in the ABI's psi coordinates.  Uses the handle's residual
+ * workspace of level p (not while a solve runs on the handle).
+ * Asynchronous. */
+eg_status eg_jacobian_apply(eg_handle* h, int p, const double* u_dev, const double* v_dev, double* out_dev);
+
 /* Transposed Jacobian of the residual (Section 3.3, eqs. (jac1), (jac2),
  * transposed): out_dev = (dR_p/du)(u_dev)^T w_dev at level p >= 1, matrix
  * free from the pointwise flux Jacobians at u_dev.  All level-p vectors.
@@ -282,6 +309,16 @@ enum {
 };
 eg_status eg_profile(eg_handle* h, int enable);
 eg_status eg_profile_read(eg_handle* h, int kernel_class, int p, double* total_ms, int* launches);
+
+/* Achievable peaks of the current device, for roofline fractions (a
+ * measurement aid, no passage of the paper): kind 0 = HBM bandwidth in GB/s
+ * (1 GiB streaming copy, bytes read + written), 1 = FP64 matrix-core
+ * TFLOP/s (16 x 16 x 4 FP64 products, eight independent chains per
+ * wavefront), 2 = FP64 vector FMA TFLOP/s (sixteen independent chains per
+ * lane).  Allocates and frees its own device buffers; runs on hip_stream
+ * (NULL: default stream) and synchronises it.  EG_ERR_ARG for another kind,
+ * EG_ERR_HIP if a HIP call fails. */
+eg_status eg_measure_peak(int kind, void* hip_stream, double* value_host);
 
 #ifdef __cplusplus
 }

@@ -60,6 +60,9 @@ def lib():
         L.orc_rusanov.argtypes = [C.c_int, C.c_double, _d, _d, _d, _d]
         L.orc_ghost.argtypes = [C.c_void_p, C.c_int, _d, _d, _d, _d]
         L.orc_rusanov_jac.argtypes = [C.c_int, C.c_double, _d, _d, _d, _d, _d]
+        L.orc_roe_jac.argtypes = [C.c_int, C.c_double, _d, _d, _d, _d, _d]
+        L.orc_roe.argtypes = [C.c_int, C.c_double, _d, _d, _d, _d]
+        L.orc_set_flux.argtypes = [C.c_void_p, C.c_int]
         L.orc_timestep.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, _d, _d]
         L.orc_rnorm.restype = C.c_double
         L.orc_rnorm.argtypes = [C.c_void_p, C.c_int, _d]
@@ -160,6 +163,22 @@ def rusanov_jac(dim, gamma, UL, UR, nh):
     return JL, JR
 
 
+def roe(dim, gamma, UL, UR, nh):
+    UL, UR, nh = (np.ascontiguousarray(a, dtype=np.float64) for a in (UL, UR, nh))
+    F = np.zeros(dim + 2)
+    lib().orc_roe(dim, gamma, _p(UL), _p(UR), _p(nh), _p(F))
+    return F
+
+
+def roe_jac(dim, gamma, UL, UR, nh):
+    """(dF/dUL, dF/dUR) of the Roe flux by complex step."""
+    UL, UR, nh = (np.ascontiguousarray(a, dtype=np.float64) for a in (UL, UR, nh))
+    JL = np.zeros((dim + 2, dim + 2))
+    JR = np.zeros((dim + 2, dim + 2))
+    lib().orc_roe_jac(dim, gamma, _p(UL), _p(UR), _p(nh), _p(JL), _p(JR))
+    return JL, JR
+
+
 def flux_jac(dim, gamma, U, g):
     U, g = (np.ascontiguousarray(a, dtype=np.float64) for a in (U, g))
     K = np.zeros((dim + 2, dim + 2))
@@ -171,7 +190,7 @@ class Oracle:
     """One mesh + free stream + p_max.  Level-p vectors are float64[E, V, N_p]."""
 
     def __init__(self, mesh, pmax: int, gamma: float = 1.4, mach: float = 0.3,
-                 alpha_deg: float = 0.0, beta_deg: float = 0.0):
+                 alpha_deg: float = 0.0, beta_deg: float = 0.0, flux: str = "rusanov"):
         m = mesh.contiguous()
         self.mesh = m
         self.dim = m.dim
@@ -187,6 +206,10 @@ class Oracle:
         if not h:
             raise ValueError("oracle mesh set-up failed: " + err.value.decode())
         self._h = C.c_void_p(h)
+        if flux not in ("rusanov", "roe"):
+            raise ValueError("flux must be 'rusanov' or 'roe'")
+        self.flux = flux
+        lib().orc_set_flux(self._h, 1 if flux == "roe" else 0)
 
     def __del__(self):
         h = getattr(self, "_h", None)

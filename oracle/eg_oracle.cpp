@@ -178,6 +178,7 @@ struct Oracle {
   std::vector<std::array<int, 3>> modes;  // at pmax
   int Nmax = 0;
   double Uinf[MAXV];
+  int flux = 0;  // numerical flux: 0 Rusanov, 1 Roe
   std::string err;
 };
 
@@ -354,6 +355,73 @@ template <class S> void rusanov(int d, double g, const S* UL, const S* UR, const
   S cR = cs_sqrt(g * pressure(d, g, UR) / UR[0]);
   S lam = cs_max(S(cs_abs(vnL) + cL), S(cs_abs(vnR) + cR));
   for (int v = 0; v < d + 2; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * (UR[v] - UL[v]);
+}
+
+// Roe's approximate Riemann solver (Roe 1981; the paper's flux, Section 3.1
+// after eq. (euler3) and Section 3.3): F~ = 1/2 (F(UL) + F(UR)) . n
+// - 1/2 sum_k |lambda_k| alpha_k r_k over the waves of the Jacobian at the
+// Roe-averaged state (sqrt(rho)-weighted velocity and total enthalpy), n a
+// unit vector: acoustic waves v_n -+ c with strengths
+// (dp -+ rho c dv_n) / (2 c^2), the entropy wave v_n with strength
+// drho - dp / c^2, and the shear waves v_n carrying rho (dv - dv_n n).  The
+// paper names no entropy fix; the reading taken is Harten's on the two
+// acoustic waves, |lambda| -> (lambda^2 + delta^2) / (2 delta) for
+// |lambda| < delta = 0.1 c (inactive in subsonic flow away from sonic
+// points); the entropy and shear waves keep |v_n| (zero slope at v_n = 0 by
+// the tie rule of cs_abs).
+template <class S> S harten_abs(const S& lam, const S& delta) {
+  if (std::fabs(re(lam)) < re(delta)) return (lam * lam + delta * delta) / (2.0 * delta);
+  return cs_abs(lam);
+}
+
+template <class S> void roe(int d, double g, const S* UL, const S* UR, const double* nh, S* F) {
+  const int V = d + 2;
+  S FL[MAXV], FR[MAXV];
+  flux_n(d, g, UL, nh, FL);
+  flux_n(d, g, UR, nh, FR);
+  S rl = UL[0], rr = UR[0];
+  S pl = pressure(d, g, UL), pr = pressure(d, g, UR);
+  S vl[MAXD], vr[MAXD];
+  for (int a = 0; a < d; ++a) { vl[a] = UL[1 + a] / rl; vr[a] = UR[1 + a] / rr; }
+  S hl = (UL[d + 1] + pl) / rl, hr = (UR[d + 1] + pr) / rr;
+  // Roe averages
+  S sl = cs_sqrt(rl), sr = cs_sqrt(rr);
+  S wsum = sl + sr;
+  S v[MAXD], q2 = 0.0, vn = 0.0;
+  for (int a = 0; a < d; ++a) {
+    v[a] = (sl * vl[a] + sr * vr[a]) / wsum;
+    q2 += v[a] * v[a];
+    vn += v[a] * nh[a];
+  }
+  S H = (sl * hl + sr * hr) / wsum;
+  S c2 = (g - 1.0) * (H - 0.5 * q2);
+  S c = cs_sqrt(c2);
+  S rho = sl * sr;
+  // jumps and wave strengths
+  S drho = rr - rl, dp = pr - pl, dv[MAXD], dvn = 0.0;
+  for (int a = 0; a < d; ++a) { dv[a] = vr[a] - vl[a]; dvn += dv[a] * nh[a]; }
+  S a1 = (dp - rho * c * dvn) / (2.0 * c2);
+  S a5 = (dp + rho * c * dvn) / (2.0 * c2);
+  S a2 = drho - dp / c2;
+  S delta = 0.1 * c;
+  S l1 = harten_abs(S(vn - c), delta), l5 = harten_abs(S(vn + c), delta), l2 = cs_abs(vn);
+  // dissipation sum_k |lambda_k| alpha_k r_k
+  S Dd[MAXV];
+  Dd[0] = l1 * a1 + l5 * a5 + l2 * a2;
+  S vdt = 0.0;
+  for (int a = 0; a < d; ++a) {
+    S dvt = dv[a] - dvn * nh[a];
+    vdt += v[a] * dvt;
+    Dd[1 + a] = l1 * a1 * (v[a] - c * nh[a]) + l5 * a5 * (v[a] + c * nh[a]) + l2 * (a2 * v[a] + rho * dvt);
+  }
+  Dd[d + 1] = l1 * a1 * (H - c * vn) + l5 * a5 * (H + c * vn) + l2 * (a2 * 0.5 * q2 + rho * vdt);
+  for (int w = 0; w < V; ++w) F[w] = 0.5 * (FL[w] + FR[w]) - 0.5 * Dd[w];
+}
+
+// The numerical flux of the oracle (Rusanov unless the Roe flux is selected).
+template <class S> void num_flux(const Oracle& O, const S* UL, const S* UR, const double* nh, S* F) {
+  if (O.flux == 1) roe(O.d, O.gam, UL, UR, nh, F);
+  else rusanov(O.d, O.gam, UL, UR, nh, F);
 }
 
 // Manufactured smooth state (tests of the convergence rate only).
@@ -713,7 +781,7 @@ template <class S> void residual_t(const Oracle& O, int p, const S* u, S* r) {
       } else {
         ghost_any(O, F.tag, UL, nh, x, UR);
       }
-      rusanov(d, O.gam, UL, UR, nh, Fl);
+      num_flux(O, UL, UR, nh, Fl);
       for (int v = 0; v < V; ++v) flux[((size_t)fc * nqf + k) * V + v] = (w * area) * Fl[v];
     }
   }
@@ -801,12 +869,12 @@ void jacobian_blocks(const Oracle& O, int p, const double* u, double* D, double*
           cs_jac(V, UL, [&](const cd* Uc, cd* Fc) {
             cd URc[MAXV];
             for (int v = 0; v < V; ++v) URc[v] = UR[v];
-            rusanov(d, O.gam, Uc, URc, nh, Fc);
+            num_flux(O, Uc, URc, nh, Fc);
           }, JL);
           cs_jac(V, UR, [&](const cd* Uc, cd* Fc) {
             cd ULc[MAXV];
             for (int v = 0; v < V; ++v) ULc[v] = UL[v];
-            rusanov(d, O.gam, ULc, Uc, nh, Fc);
+            num_flux(O, ULc, Uc, nh, Fc);
           }, JR);
           if (side == 0) { std::memcpy(Jown, JL, sizeof JL); std::memcpy(Joth, JR, sizeof JR); other = F.eR; for (int i = 0; i < N; ++i) psiE[i] = psiL[i], psiO[i] = psiR[i]; }
           else { std::memcpy(Jown, JR, sizeof JR); std::memcpy(Joth, JL, sizeof JL); other = F.eL; for (int i = 0; i < N; ++i) psiE[i] = psiR[i], psiO[i] = psiL[i]; }
@@ -817,12 +885,12 @@ void jacobian_blocks(const Oracle& O, int p, const double* u, double* D, double*
           cs_jac(V, UL, [&](const cd* Uc, cd* Fc) {
             cd Ugc[MAXV];
             for (int v = 0; v < V; ++v) Ugc[v] = Ug[v];
-            rusanov(d, O.gam, Uc, Ugc, nh, Fc);
+            num_flux(O, Uc, Ugc, nh, Fc);
           }, JL);
           cs_jac(V, Ug, [&](const cd* Uc, cd* Fc) {
             cd ULc[MAXV];
             for (int v = 0; v < V; ++v) ULc[v] = UL[v];
-            rusanov(d, O.gam, ULc, Uc, nh, Fc);
+            num_flux(O, ULc, Uc, nh, Fc);
           }, Jg);
           cs_jac(V, UL, [&](const cd* Uc, cd* Fc) { ghost_any(O, F.tag, Uc, nh, x, Fc); }, Gg);
           for (int v = 0; v < V; ++v)
@@ -1371,6 +1439,28 @@ void orc_rusanov_jac(int dim, double gamma, const double* UL, const double* UR, 
     cd Ul[MAXV];
     for (int v = 0; v < V; ++v) Ul[v] = cd(UL[v], 0.0);
     rusanov<cd>(dim, gamma, Ul, Uc, nh, Fc);
+  }, JR);
+}
+
+void orc_set_flux(void* h, int flux) { static_cast<Oracle*>(h)->flux = flux; }
+
+void orc_roe(int dim, double gamma, const double* UL, const double* UR, const double* nh, double* F) {
+  roe<double>(dim, gamma, UL, UR, nh, F);
+}
+
+// Jacobians of the Roe flux with respect to each trace by complex step.
+void orc_roe_jac(int dim, double gamma, const double* UL, const double* UR, const double* nh, double* JL,
+                 double* JR) {
+  const int V = dim + 2;
+  cs_jac(V, UL, [&](const cd* Uc, cd* Fc) {
+    cd Ur[MAXV];
+    for (int v = 0; v < V; ++v) Ur[v] = cd(UR[v], 0.0);
+    roe<cd>(dim, gamma, Uc, Ur, nh, Fc);
+  }, JL);
+  cs_jac(V, UR, [&](const cd* Uc, cd* Fc) {
+    cd Ul[MAXV];
+    for (int v = 0; v < V; ++v) Ul[v] = cd(UL[v], 0.0);
+    roe<cd>(dim, gamma, Ul, Uc, nh, Fc);
   }, JR);
 }
 

@@ -15,7 +15,7 @@ EXPORTED_SYMBOLS = (
     "eg_timestep", "eg_element_jacobian", "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm",
     "eg_vcycle", "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read",
     "eg_drag", "eg_adjoint_apply", "eg_adjoint_solve", "eg_init_batch", "eg_layout", "eg_solve_batch", "eg_autotune",
-    "eg_set_graphs",
+    "eg_set_graphs", "eg_measure_peak", "eg_jacobian_apply",
 )
 
 KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
@@ -39,9 +39,11 @@ class _Mesh(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("p_max", C.c_int), ("rk_stages", C.c_int), ("cfl_max", C.c_double), ("krylov_m", C.c_int),
                 ("relative_ramp", C.c_int), ("gamma", C.c_double), ("mach", C.c_double),
-                ("alpha_deg", C.c_double), ("beta_deg", C.c_double), ("precision", C.c_int)]
+                ("alpha_deg", C.c_double), ("beta_deg", C.c_double), ("precision", C.c_int),
+                ("flux", C.c_int)]
 
 PRECISIONS = {"fp64": 0, "mixed": 1}
+FLUXES = {"rusanov": 0, "roe": 1}
 
 
 def library_path() -> str:
@@ -72,6 +74,8 @@ def lib():
         L.eg_jacobian_p0.argtypes = [vp, vp, vp, vp, vp]
         L.eg_exp1_step.argtypes = [vp, d, vp, vp, C.POINTER(i)]
         L.eg_rnorm.argtypes = [vp, vp, pd]
+        L.eg_measure_peak.argtypes = [i, vp, pd]
+        L.eg_measure_peak.restype = i
         L.eg_vcycle.argtypes = [vp, vp, i, d, pd, pd]
         L.eg_solve_steady.argtypes = [vp, vp, d, i, pd, C.POINTER(i)]
         L.eg_solve_resume.argtypes = [vp, vp, d, i, pd, C.POINTER(i)]
@@ -84,6 +88,7 @@ def lib():
         L.eg_layout.argtypes = [vp, i, i, C.POINTER(C.c_int64), C.POINTER(i), C.POINTER(i)]
         L.eg_solve_batch.argtypes = [vp, vp, d, i, pd, C.POINTER(i)]
         L.eg_adjoint_apply.argtypes = [vp, i, vp, vp, vp]
+        L.eg_jacobian_apply.argtypes = [vp, i, vp, vp, vp]
         L.eg_adjoint_solve.argtypes = [vp, vp, vp, vp, d, i, pd, C.POINTER(i)]
         for name in ("eg_sizes", "eg_set_freestream", "eg_residual", "eg_timestep", "eg_element_jacobian",
                      "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm", "eg_vcycle",
@@ -122,7 +127,7 @@ class Solver:
 
     def __init__(self, mesh, p_max: int, rk_stages: int = 4, cfl_max: float = 100.0, krylov_m: int = 30,
                  relative_ramp: bool = True, gamma: float = 1.4, mach: float = 0.3, alpha_deg: float = 0.0,
-                 beta_deg: float = 0.0, precision: str = "fp64", stream=None):
+                 beta_deg: float = 0.0, precision: str = "fp64", flux: str = "rusanov", stream=None):
         import numpy as np
         import torch
         L = lib()
@@ -133,9 +138,11 @@ class Solver:
                    m.bface_tag.ctypes.data_as(C.POINTER(C.c_int8)))
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
-        self.precision = precision
+        if flux not in FLUXES:
+            raise ValueError(f"flux must be one of {sorted(FLUXES)}")
+        self.precision, self.flux = precision, flux
         cp = _Params(p_max, rk_stages, cfl_max, krylov_m, int(relative_ramp), gamma, mach, alpha_deg, beta_deg,
-                     PRECISIONS[precision])
+                     PRECISIONS[precision], FLUXES[flux])
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         st = L.eg_init_mesh(C.byref(cm), C.byref(cp), C.c_void_p(self.stream.cuda_stream), C.byref(h))
@@ -286,6 +293,19 @@ class Solver:
         return hist[: nc.value + 1], st
 
 
+def measure_peak(kind: str, stream=None) -> float:
+    """Achievable peak of the current device: "hbm" (GB/s, streaming copy),
+    "fp64_mfma" or "fp64_fma" (TFLOP/s)."""
+    import torch
+    kinds = {"hbm": 0, "fp64_mfma": 1, "fp64_fma": 2}
+    st = stream if stream is not None else torch.cuda.current_stream()
+    v = C.c_double(0.0)
+    s = lib().eg_measure_peak(kinds[kind], C.c_void_p(st.cuda_stream), C.byref(v))
+    if s != 0:
+        raise EgError(s, "eg_measure_peak failed")
+    return v.value
+
+
 def _autotune(obj, reps):
     pmax = obj.p_max
     tiles = (C.c_int * (2 * (pmax + 1)))()
@@ -311,6 +331,14 @@ def _solver_drag(self, u, direction=None, sref: float = 1.0, grad: bool = False)
     g = self.empty(self.p_max) if grad else None
     self._chk(lib().eg_drag(self._h, pu, dv, float(sref), C.byref(cd), self._vec(g, self.p_max, "grad")))
     return (cd.value, g) if grad else cd.value
+
+
+def _solver_jacobian_apply(self, p: int, u, v, out=None):
+    """(dR_p/du)(u) v (matrix free, forward-mode dual numbers)."""
+    pu, pv = self._vec(u, p, "u"), self._vec(v, p, "v")
+    o = self.empty(p) if out is None else out
+    self._chk(lib().eg_jacobian_apply(self._h, p, pu, pv, self._vec(o, p, "out")))
+    return o
 
 
 def _solver_adjoint_apply(self, p: int, u, w, out=None):
@@ -341,6 +369,7 @@ def _solver_adjoint_solve(self, u, g, lam=None, drop_tol: float = 1e-10, max_cyc
 
 Solver.drag = _solver_drag
 Solver.adjoint_apply = _solver_adjoint_apply
+Solver.jacobian_apply = _solver_jacobian_apply
 Solver.adjoint_solve = _solver_adjoint_solve
 
 
@@ -353,7 +382,7 @@ class BatchSolver:
 
     def __init__(self, meshes, p_max: int, machs, alphas=None, betas=None, rk_stages: int = 4,
                  cfl_max: float = 100.0, krylov_m: int = 30, relative_ramp: bool = True, gamma: float = 1.4,
-                 precision: str = "fp64", stream=None):
+                 precision: str = "fp64", flux: str = "rusanov", stream=None):
         import numpy as np
         import torch
         L = lib()
@@ -367,8 +396,11 @@ class BatchSolver:
                                   m.bface_tag.ctypes.data_as(C.POINTER(C.c_int8))) for m in ms])
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        if flux not in FLUXES:
+            raise ValueError(f"flux must be one of {sorted(FLUXES)}")
         cps = (_Params * n)(*[_Params(p_max, rk_stages, cfl_max, krylov_m, int(relative_ramp), gamma, float(machs[i]),
-                                      float(alphas[i]), float(betas[i]), PRECISIONS[precision]) for i in range(n)])
+                                      float(alphas[i]), float(betas[i]), PRECISIONS[precision], FLUXES[flux])
+                              for i in range(n)])
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         st = L.eg_init_batch(cms, cps, n, C.c_void_p(self.stream.cuda_stream), C.byref(h))

@@ -37,11 +37,16 @@ struct Tab {
   int8_t m[Cfg<D, P>::N][3];
 };
 
-// Free stream and gas constant passed to kernels by value.
+// Numerical flux of the face integrals (Section 3.1 after eq. (euler3)).
+constexpr int FLUX_RUSANOV = 0;
+constexpr int FLUX_ROE = 1;
+
+// Free stream, gas constant and numerical flux passed to kernels by value.
 template <class R = double>
 struct GasT {
   R g;
   R Uinf[5];
+  int flux;  // FLUX_RUSANOV or FLUX_ROE
 };
 using Gas = GasT<double>;
 

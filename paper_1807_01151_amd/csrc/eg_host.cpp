@@ -71,6 +71,7 @@ struct eg_handle {
   double sv_r1 = 0.0;
   int sv_phase_b = 0, sv_nmin = 0;  // mixed mode: phase B reached; cycle of the smallest norm
   double sv_rmin = 0.0;
+  double sv_ring[64] = {};  // mixed mode: entry norms of the last cycles (index n mod 64)
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
   std::vector<ProfRec> recs;
@@ -492,10 +493,20 @@ int res_prec(const eg_handle* h, int p) {
 }
 
 // Mixed mode switches to phase B for good once the FP64 residual norm has
-// dropped below this fraction of r_1, or has not reached a new minimum for
-// EG_STALL_CYCLES cycles (the FP32 noise floor of phase A is ~1e-5 r_1).
+// dropped below this fraction of r_1, has not reached a new minimum for
+// EG_STALL_CYCLES cycles, or has fallen by less than 10% over the last
+// EG_SLOW_CYCLES cycles (the FP32 noise floor of phase A is ~1e-5 r_1 in
+// 2D; in 3D the norm creeps along a plateau near 1e-4 r_1 instead).
 constexpr double EG_PHASE_B_DROP = 1e-4;
 constexpr int EG_STALL_CYCLES = 100;
+constexpr int EG_SLOW_CYCLES = 50;
+constexpr double EG_SLOW_FACTOR = 0.9;
+static_assert(EG_SLOW_CYCLES < 64, "ring of past norms");
+
+bool phase_a_over(double rn, double r1, int n, int nmin, const double* ring) {
+  if (rn <= EG_PHASE_B_DROP * r1 || n - nmin >= EG_STALL_CYCLES) return true;
+  return n > EG_SLOW_CYCLES && rn > EG_SLOW_FACTOR * ring[(n - EG_SLOW_CYCLES) % 64];
+}
 
 double cfl_ramp(double cfl_max, double rn, double rref, int n, int pmax) {
   double a = (rn > 0.0) ? rref / rn : HUGE_VAL;
@@ -751,8 +762,9 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
   const int pmax_lim = (d == 2) ? 4 : 2;
   if (prm->p_max < 0 || prm->p_max > pmax_lim || prm->rk_stages < 1 || prm->krylov_m < 1 || prm->krylov_m > 48 ||
       !(prm->cfl_max > 0.0) || !(prm->gamma > 1.0) || !(prm->mach >= 0.0) ||
-      (prm->precision != EG_FP64 && prm->precision != EG_MIXED)) {
-    h->err = "invalid parameters (p_max, rk_stages, krylov_m 1..48, cfl_max, gamma, mach or precision)";
+      (prm->precision != EG_FP64 && prm->precision != EG_MIXED) ||
+      (prm->flux != EG_FLUX_RUSANOV && prm->flux != EG_FLUX_ROE)) {
+    h->err = "invalid parameters (p_max, rk_stages, krylov_m 1..48, cfl_max, gamma, mach, precision or flux)";
     return EG_ERR_ARG;
   }
   h->pmax = prm->p_max;
@@ -773,6 +785,7 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
   const int N = nmodes_of(d, h->pmax);
   M.NT = N * (N + 1) / 2;
   M.gas.g = prm->gamma;
+  M.gas.flux = prm->flux == EG_FLUX_ROE ? eg::FLUX_ROE : eg::FLUX_RUSANOV;
   {
     const double al = prm->alpha_deg * M_PI / 180.0, be = prm->beta_deg * M_PI / 180.0;
     double v[3] = {prm->mach * std::cos(al) * std::cos(be), prm->mach * std::sin(al) * std::cos(be),
@@ -1135,7 +1148,8 @@ eg_status eg_init_batch(const eg_mesh* meshes, const eg_params* params, int n_so
     if (!m.xyz || !m.elem_vert || !m.bface_tag || m.dim != d || m.n_vert <= 0 || m.n_elem <= 0) return EG_ERR_ARG;
     if (q.p_max != params[0].p_max || q.rk_stages != params[0].rk_stages || q.krylov_m != params[0].krylov_m ||
         q.cfl_max != params[0].cfl_max || q.relative_ramp != params[0].relative_ramp ||
-        q.gamma != params[0].gamma || q.precision != params[0].precision || !(q.mach >= 0.0))
+        q.gamma != params[0].gamma || q.precision != params[0].precision || q.flux != params[0].flux ||
+        !(q.mach >= 0.0))
       return EG_ERR_ARG;
     nv += m.n_vert;
     ne += m.n_elem;
@@ -1313,6 +1327,12 @@ eg_status eg_rnorm(eg_handle* h, const double* r_dev, double* rn_host) {
   return EG_OK;
 }
 
+eg_status eg_measure_peak(int kind, void* hip_stream, double* value_host) {
+  if (kind < 0 || kind > 2 || !value_host) return EG_ERR_ARG;
+  return eg::measure_peak(kind, static_cast<hipStream_t>(hip_stream), value_host) == hipSuccess ? EG_OK
+                                                                                                 : EG_ERR_HIP;
+}
+
 eg_status eg_profile(eg_handle* h, int enable) {
   if (!h) return EG_ERR_ARG;
   HIPCHK(h, hipStreamSynchronize(h->st));
@@ -1394,8 +1414,9 @@ eg_status solve_loop_body(eg_handle* h, double* u_dev, int n0, double r1, double
     const double cfl = cfl_ramp(h->cfl_max, rn, h->relr ? r1 : 1.0, n, h->pmax);
     if (h->mixed && !h->sv_phase_b) {
       if (!(rn >= h->sv_rmin)) { h->sv_rmin = rn; h->sv_nmin = n; }
-      if (rn <= EG_PHASE_B_DROP * r1 || n - h->sv_nmin >= EG_STALL_CYCLES) h->sv_phase_b = 1;
+      if (phase_a_over(rn, r1, n, h->sv_nmin, h->sv_ring)) h->sv_phase_b = 1;
     }
+    h->sv_ring[n % 64] = rn;
     h->phase_b = h->sv_phase_b;
     st = vcycle_run(h, cfl);
     if (st != EG_OK) break;
@@ -1437,6 +1458,18 @@ eg_status eg_drag(eg_handle* h, const double* u_dev, const double* dir_host, dou
   HIPCHK(h, hipMemcpyAsync(h->hpin, h->sout, sizeof(double), hipMemcpyDeviceToHost, h->st));
   ECHK(sync_status(h));
   *cd_host = h->hpin[0];
+  return EG_OK;
+}
+
+eg_status eg_jacobian_apply(eg_handle* h, int p, const double* u_dev, const double* v_dev, double* out_dev) {
+  if (!h || !u_dev || !v_dev || !out_dev) return EG_ERR_ARG;
+  if (p < 0 || p > h->pmax) return fail(h, EG_ERR_ARG, "order out of range");
+  const DevMesh& M = h->M;
+  const int N = nmodes_of(M.d, p);
+  HIPCHK(h, eg::launch_basis(M, N, u_dev, h->tmp, 0, h->st));
+  HIPCHK(h, eg::launch_basis(M, N, v_dev, h->tmp2, 0, h->st));
+  HIPCHK(h, eg::launch_tangent(M, h->tabs[p], p, h->tmp, h->tmp2, h->rt[p], h->st));
+  HIPCHK(h, eg::launch_basis(M, N, h->rt[p], out_dev, 2, h->st));
   return EG_OK;
 }
 
@@ -1503,6 +1536,7 @@ eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_c
   if (!h->bsave) ECHK(dalloc(h, &h->bsave, (size_t)M.ne * per_elem));
   std::vector<double> r1(nseg, -1.0), rmin(nseg, HUGE_VAL);
   std::vector<int> done(nseg, 0), nmin(nseg, 1);
+  std::vector<double> ring((size_t)nseg * 64, 0.0);  // past entry norms per solve (mixed-mode switch)
   for (int sg = 0; sg < nseg; ++sg) n_cycles_host[sg] = 0;
   HIPCHK(h, eg::launch_basis(M, N, u_dev, h->ut[pm], 0, h->st));
   eg_status st = EG_OK;
@@ -1560,9 +1594,11 @@ eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_c
     }
     if (h->mixed && !phase_b) {
       bool stall = false;
-      for (int sg = 0; sg < nseg; ++sg) stall = stall || (done[sg] == 0 && n - nmin[sg] >= EG_STALL_CYCLES);
+      for (int sg = 0; sg < nseg; ++sg)
+        stall = stall || (done[sg] == 0 && phase_a_over(h->hnorm[sg], 0.0, n, nmin[sg], &ring[(size_t)sg * 64]));
       if (worst <= EG_PHASE_B_DROP || stall) phase_b = 1;
     }
+    for (int sg = 0; sg < nseg; ++sg) ring[(size_t)sg * 64 + n % 64] = h->hnorm[sg];
     h->phase_b = phase_b;
     HIPCHK(h, hipMemcpyAsync(h->dcfl, h->hcfl, sizeof(double) * nseg, hipMemcpyHostToDevice, h->st));
     HIPCHK(h, eg::launch_expand_cfl(M, h->dcfl, h->st));

@@ -76,6 +76,11 @@ struct FasOut {
 hipError_t launch_residual(const DevMesh& M, const TabData& td, int p, const double* ut, const double* fadd,
                            double* rt, int prec, hipStream_t st, const FasOut& fas = FasOut{});
 bool jacobian_supported(int d, int p);
+// FP64 block assembly on the matrix cores and LDS-resident blocked LU
+// (eg_jaclu_lds.hip) for 2D p = 4 and 3D p = 2; bc from k_jac_points.
+bool jaclu_lds_supported(int d, int p);
+hipError_t launch_jaclu_lds(const DevMesh& M, const TabData& td, int p, const double* bc, const double* dtau,
+                            double* out, int* perm, int* fail, hipStream_t st);
 hipError_t launch_jacobian(const DevMesh& M, const TabData& td, int p, const double* ut, const double* dtau,
                            void* out, int* perm, int* fail, bool factor, int prec, hipStream_t st);
 // un null: the stage starts from ut and, if save is set, stores it there
@@ -114,6 +119,10 @@ hipError_t launch_copy(const double* a, double* b, size_t n, hipStream_t st);
 hipError_t launch_freestream(const DevMesh& M, int N, double* u, hipStream_t st);
 hipError_t launch_jac_to_psi(const DevMesh& M, int N, double* Dm, hipStream_t st);
 
+// (dRt_p/dut)(ut) vt by forward-mode dual numbers (eg_tangent.hip), p >= 0
+hipError_t launch_tangent(const DevMesh& M, const TabData& td, int p, const double* ut, const double* vt, double* jv,
+                          hipStream_t st);
+
 // adjoint (drag sensitivity)
 size_t jac_points_size(int d, int p);  // values per element of the pointwise flux Jacobians
 hipError_t launch_jac_points(const DevMesh& M, const TabData& td, int p, const double* ut, double* bc, hipStream_t st);
@@ -133,6 +142,9 @@ hipError_t launch_trunc(const double* x, double* y, int N, int Nc, int rows, hip
 hipError_t launch_pad_add(double* x, const double* y, int N, int Nc, int rows, hipStream_t st);
 hipError_t launch_fill0(double* x, size_t n, hipStream_t st);
 hipError_t launch_expand_cfl(const DevMesh& M, const double* cfl_s, hipStream_t st);
+// Achievable peaks (eg_peak.hip): kind 0 HBM copy GB/s, 1 FP64 matrix-core
+// TFLOP/s, 2 FP64 vector FMA TFLOP/s; allocates its own buffers.
+hipError_t measure_peak(int kind, hipStream_t st, double* value);
 int sum_blocks(size_t n);
 hipError_t launch_sum(const double* x, const double* y, size_t n, double* part, int take_sqrt, double* out,
                       hipStream_t st);

@@ -181,6 +181,76 @@ __device__ __forceinline__ void rusanov(const SL* UL, const SR* UR, const real_t
   for (int v = 0; v < D + 2; ++v) F[v] = R(0.5) * (FL[v] + FR[v]) - R(0.5) * lam * (ur[v] - ul[v]);
 }
 
+// Roe's approximate Riemann solver (the paper's flux, Section 3.1 after
+// eq. (euler3), Section 3.3): 1/2 (F(UL) + F(UR)) . n minus half the sum
+// over the waves of the Jacobian at the Roe-averaged state (sqrt(rho)
+// weights for velocity and total enthalpy) of |lambda| x strength x
+// eigenvector: acoustic waves v_n -+ c with strengths (dp -+ rho c dv_n) /
+// (2 c^2), the entropy wave v_n with drho - dp / c^2, the shear waves v_n
+// carrying rho (dv - dv_n n).  Entropy fix (the paper names none; the
+// reading taken): Harten's on the acoustic waves, |lambda| ->
+// (lambda^2 + delta^2) / (2 delta) for |lambda| < delta = c / 10.
+template <class S>
+__device__ __forceinline__ S harten_abs(const S& lam, const S& delta) {
+  using R = real_t<S>;
+  if (dabs(val(lam)) < val(delta)) return (lam * lam + delta * delta) / (R(2) * delta);
+  return dabs(lam);
+}
+
+template <int D, class SL, class SR, class S>
+__device__ __forceinline__ void roe(const SL* UL, const SR* UR, const real_t<S>* nh, S* F, real_t<S> g) {
+  using R = real_t<S>;
+  S ul[D + 2], ur[D + 2];
+#pragma unroll
+  for (int v = 0; v < D + 2; ++v) { ul[v] = S(UL[v]); ur[v] = S(UR[v]); }
+  S FL[D + 2], FR[D + 2];
+  flux_n<D>(ul, nh, FL, g);
+  flux_n<D>(ur, nh, FR, g);
+  const S rl = ul[0], rr = ur[0];
+  const S pl = pressure<D>(ul, g), pr = pressure<D>(ur, g);
+  S vl[D], vr[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) { vl[a] = ul[1 + a] / rl; vr[a] = ur[1 + a] / rr; }
+  const S hl = (ul[D + 1] + pl) / rl, hr = (ur[D + 1] + pr) / rr;
+  const S sl = dsqrt(rl), sr = dsqrt(rr);
+  const S wsum = sl + sr;
+  S v[D];
+  S q2 = S(R(0)), vn = S(R(0));
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    v[a] = (sl * vl[a] + sr * vr[a]) / wsum;
+    q2 = q2 + v[a] * v[a];
+    vn = vn + v[a] * nh[a];
+  }
+  const S H = (sl * hl + sr * hr) / wsum;
+  const S c2 = (g - R(1)) * (H - R(0.5) * q2);
+  const S c = dsqrt(c2);
+  const S rho = sl * sr;
+  const S drho = rr - rl, dp = pr - pl;
+  S dv[D];
+  S dvn = S(R(0));
+#pragma unroll
+  for (int a = 0; a < D; ++a) { dv[a] = vr[a] - vl[a]; dvn = dvn + dv[a] * nh[a]; }
+  const S a1 = (dp - rho * c * dvn) / (R(2) * c2);
+  const S a5 = (dp + rho * c * dvn) / (R(2) * c2);
+  const S a2 = drho - dp / c2;
+  const S delta = R(0.1) * c;
+  const S l1 = harten_abs(S(vn - c), delta), l5 = harten_abs(S(vn + c), delta), l2 = dabs(vn);
+  const S w1 = l1 * a1, w5 = l5 * a5;
+  S Dd[D + 2];
+  Dd[0] = w1 + w5 + l2 * a2;
+  S vdt = S(R(0));
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const S dvt = dv[a] - dvn * nh[a];
+    vdt = vdt + v[a] * dvt;
+    Dd[1 + a] = w1 * (v[a] - c * nh[a]) + w5 * (v[a] + c * nh[a]) + l2 * (a2 * v[a] + rho * dvt);
+  }
+  Dd[D + 1] = w1 * (H - c * vn) + w5 * (H + c * vn) + l2 * (a2 * (R(0.5) * q2) + rho * vdt);
+#pragma unroll
+  for (int k = 0; k < D + 2; ++k) F[k] = R(0.5) * (FL[k] + FR[k]) - R(0.5) * Dd[k];
+}
+
 // Slip wall: mirror the momentum about the face, rho v_g = rho v - 2 (rho v . n) n.
 template <int D, class S> __device__ __forceinline__ void ghost_wall(const S* U, const real_t<S>* nh, S* G) {
   using R = real_t<S>;

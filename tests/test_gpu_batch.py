@@ -89,10 +89,13 @@ def test_batch_solve_matches_single_solves(precision):
         assert hists[i][-1] <= 1e-10 * hists[i][0]
         # the returned state is the one whose norm the history ends with,
         # although the batch kept cycling until its slowest solve converged
+        # (near the drop the norm is round-off dominated, so the two
+        # evaluations agree to 1e-12 r_1, not relative to r_n; further
+        # cycles would move it by O(1e-10) r_1)
         S64 = _single(i, p)
         rn_ret = S64.rnorm(S64.residual(p, uv.contiguous()))
         print(f"  solve {i}: norm of the returned state {rn_ret:.6e}, recorded {hists[i][-1]:.6e}", flush=True)
-        assert abs(rn_ret - hists[i][-1]) <= 1e-8 * hists[i][-1]
+        assert abs(rn_ret - hists[i][-1]) <= 1e-12 * hists[i][0]
         if precision == "fp64":
             O = oracle.Oracle(MESHES[i], p, mach=MACHS[i], alpha_deg=ALPHAS[i])
             ub = to_host(uv)

@@ -20,28 +20,38 @@ from tests.gpu_util import perturbed, to_dev, to_host, rel_err
 pytestmark = pytest.mark.gpu
 
 CASES = [
-    ("c1-ogrid24x12-p1", ogrid(24, 12), 1, 0.0),
-    ("ogrid16x6-p3", ogrid(16, 6), 3, 3.0),
-    ("ogrid10x3-p4", ogrid(10, 3), 4, -2.0),
-    ("box2d-skew-p2", box(2, 5, skew=0.2, seed=2, tag=TAG_FARFIELD), 2, 7.0),
-    ("sphere6x2x2x2-p1", cubed_sphere_shell(2, 2), 1, 2.0),
-    ("sphere6x2x2x2-p2", cubed_sphere_shell(2, 2), 2, 2.0),
+    ("c1-ogrid24x12-p1", ogrid(24, 12), 1, 0.0, "rusanov"),
+    ("ogrid16x6-p3", ogrid(16, 6), 3, 3.0, "rusanov"),
+    ("ogrid10x3-p4", ogrid(10, 3), 4, -2.0, "rusanov"),
+    ("box2d-skew-p2", box(2, 5, skew=0.2, seed=2, tag=TAG_FARFIELD), 2, 7.0, "rusanov"),
+    ("sphere6x2x2x2-p1", cubed_sphere_shell(2, 2), 1, 2.0, "rusanov"),
+    ("sphere6x2x2x2-p2", cubed_sphere_shell(2, 2), 2, 2.0, "rusanov"),
+    # the paper's Roe flux (with the entropy-fix reading)
+    ("c1-ogrid24x12-p1-roe", ogrid(24, 12), 1, 0.0, "roe"),
+    ("ogrid16x6-p3-roe", ogrid(16, 6), 3, 3.0, "roe"),
+    ("ogrid10x3-p4-roe", ogrid(10, 3), 4, -2.0, "roe"),
+    ("sphere6x2x2x2-p2-roe", cubed_sphere_shell(2, 2), 2, 2.0, "roe"),
     # random local frames: neighbours meet with every swap / flip combination
-    ("ogrid16x6-p3-reoriented", reorient(ogrid(16, 6), 11), 3, 3.0),
-    ("sphere6x2x2x2-p2-reoriented", reorient(cubed_sphere_shell(2, 2), 12), 2, 2.0),
+    ("ogrid16x6-p3-reoriented", reorient(ogrid(16, 6), 11), 3, 3.0, "rusanov"),
+    ("sphere6x2x2x2-p2-reoriented", reorient(cubed_sphere_shell(2, 2), 12), 2, 2.0, "roe"),
 ]
+IDS = [c[0] for c in CASES]
 
 
-def _solver(mesh, p, alpha, **kw):
+def _solver(mesh, p, alpha, flux="rusanov", **kw):
     import paper_1807_01151_amd as P
-    return P.Solver(mesh, p, alpha_deg=alpha, **kw)
+    return P.Solver(mesh, p, alpha_deg=alpha, flux=flux, **kw)
 
 
-@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
-def test_residual_parity(name, mesh, p, alpha):
+def _oracle(mesh, p, alpha, flux="rusanov"):
+    return oracle.Oracle(mesh, p, alpha_deg=alpha, flux=flux)
+
+
+@pytest.mark.parametrize("name,mesh,p,alpha,flux", CASES, ids=IDS)
+def test_residual_parity(name, mesh, p, alpha, flux):
     print("case", name, flush=True)
-    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
-    S = _solver(mesh, p, alpha)
+    O = _oracle(mesh, p, alpha, flux)
+    S = _solver(mesh, p, alpha, flux)
     for lev in range(p + 1):
         u = perturbed(O, lev, 100 + lev)
         r_o = O.residual(lev, u)
@@ -59,10 +69,10 @@ def test_freestream_preservation_gpu():
     assert np.max(np.abs(r)) < 1e-13
 
 
-@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
-def test_timestep_parity(name, mesh, p, alpha):
-    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
-    S = _solver(mesh, p, alpha)
+@pytest.mark.parametrize("name,mesh,p,alpha,flux", CASES, ids=IDS)
+def test_timestep_parity(name, mesh, p, alpha, flux):
+    O = _oracle(mesh, p, alpha, flux)
+    S = _solver(mesh, p, alpha, flux)
     for lev in (0, p):
         u = perturbed(O, lev, 200 + lev)
         dt_o = O.timestep(p, 37.0, u)
@@ -70,10 +80,10 @@ def test_timestep_parity(name, mesh, p, alpha):
         assert rel_err(dt_g, dt_o) < 1e-13
 
 
-@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
-def test_element_jacobian_parity(name, mesh, p, alpha):
-    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
-    S = _solver(mesh, p, alpha)
+@pytest.mark.parametrize("name,mesh,p,alpha,flux", CASES, ids=IDS)
+def test_element_jacobian_parity(name, mesh, p, alpha, flux):
+    O = _oracle(mesh, p, alpha, flux)
+    S = _solver(mesh, p, alpha, flux)
     for lev in range(1, p + 1):
         u = perturbed(O, lev, 300 + lev)
         D_o = O.jacobian_blocks(lev, u)
@@ -81,10 +91,10 @@ def test_element_jacobian_parity(name, mesh, p, alpha):
         assert rel_err(D_g, D_o) < 1e-12, (lev, rel_err(D_g, D_o))
 
 
-@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
-def test_prk_step_parity(name, mesh, p, alpha):
-    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
-    S = _solver(mesh, p, alpha, rk_stages=3)
+@pytest.mark.parametrize("name,mesh,p,alpha,flux", CASES, ids=IDS)
+def test_prk_step_parity(name, mesh, p, alpha, flux):
+    O = _oracle(mesh, p, alpha, flux)
+    S = _solver(mesh, p, alpha, flux, rk_stages=3)
     for lev in range(1, p + 1):
         u = perturbed(O, lev, 400 + lev)
         f = 1e-3 * np.random.default_rng(401 + lev).standard_normal(u.shape)
@@ -95,10 +105,10 @@ def test_prk_step_parity(name, mesh, p, alpha):
         assert rel_err(out_g - u, out_o - u) < 1e-11, (lev, rel_err(out_g - u, out_o - u))
 
 
-@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
-def test_jacobian_p0_parity(name, mesh, p, alpha):
-    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
-    S = _solver(mesh, p, alpha)
+@pytest.mark.parametrize("name,mesh,p,alpha,flux", CASES, ids=IDS)
+def test_jacobian_p0_parity(name, mesh, p, alpha, flux):
+    O = _oracle(mesh, p, alpha, flux)
+    S = _solver(mesh, p, alpha, flux)
     u = perturbed(O, 0, 500)
     D_o, Off_o = O.jacobian_blocks(0, u, offdiag=True)
     Dg, Og, nb = S.jacobian_p0(to_dev(u))
@@ -107,10 +117,10 @@ def test_jacobian_p0_parity(name, mesh, p, alpha):
     assert np.array_equal(to_host(nb), O.neighbours())
 
 
-@pytest.mark.parametrize("name,mesh,p,alpha", CASES, ids=[c[0] for c in CASES])
-def test_exp1_step_parity(name, mesh, p, alpha):
-    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
-    S = _solver(mesh, p, alpha, krylov_m=30)
+@pytest.mark.parametrize("name,mesh,p,alpha,flux", CASES, ids=IDS)
+def test_exp1_step_parity(name, mesh, p, alpha, flux):
+    O = _oracle(mesh, p, alpha, flux)
+    S = _solver(mesh, p, alpha, flux, krylov_m=30)
     u = perturbed(O, 0, 600)
     f = 1e-3 * np.random.default_rng(601).standard_normal(u.shape)
     out_o, mu_o, beta_o = O.exp1(30, 20.0, u, f)
@@ -134,10 +144,10 @@ def test_exp1_happy_breakdown_parity():
     assert rel_err(to_host(ud) - u, out_o - u) < 1e-9
 
 
-@pytest.mark.parametrize("name,mesh,p,alpha", CASES[:5], ids=[c[0] for c in CASES[:5]])
-def test_vcycle_parity(name, mesh, p, alpha):
-    O = oracle.Oracle(mesh, p, alpha_deg=alpha)
-    S = _solver(mesh, p, alpha, rk_stages=4, cfl_max=100.0, krylov_m=30)
+@pytest.mark.parametrize("name,mesh,p,alpha,flux", CASES[:5] + CASES[6:10], ids=IDS[:5] + IDS[6:10])
+def test_vcycle_parity(name, mesh, p, alpha, flux):
+    O = _oracle(mesh, p, alpha, flux)
+    S = _solver(mesh, p, alpha, flux, rk_stages=4, cfl_max=100.0, krylov_m=30)
     u = perturbed(O, p, 700, amp=0.005)
     r1 = O.rnorm(p, O.residual(p, u))
     out_o, rn_o, cfl_o = O.vcycle(u, 3, s=4, m=30, cfl_max=100.0, rref=r1 * 0.5)
@@ -201,3 +211,21 @@ def test_c1_history_and_fixed_point():
     assert rel_err(ug, u_o) < 1e-8
     # the oracle's residual of the GPU's converged state
     assert O.rnorm(1, O.residual(1, ug)) <= 2e-10 * h_o[0]
+
+
+def test_c1_roe_history_and_fixed_point():
+    """The c1 solve with the Roe flux: the first 12 cycles of the free-running
+    history agree with the oracle's to 1e-12 r_1, the GPU solve reaches the
+    1e-10 drop, and the oracle's Roe residual of the GPU's converged state is
+    at the drop (the fixed point R(u) = 0 of the Roe discretisation)."""
+    mesh = ogrid(24, 12)
+    O = _oracle(mesh, 1, 0.0, "roe")
+    S = _solver(mesh, 1, 0.0, "roe", rk_stages=4, cfl_max=100.0, krylov_m=30)
+    _, h_o, _ = O.solve(O.freestream(1), s=4, m=30, cfl_max=100.0, drop=1e-10, max_cycles=12)
+    ud = S.freestream(1)
+    h_g, st_g = S.solve_steady(ud, drop_tol=1e-10, max_cycles=8000)
+    print("roe c1 cycles", len(h_g) - 1, "status", st_g, flush=True)
+    assert st_g == 0
+    dev = np.abs(h_g[:13] - h_o[:13]) / h_o[0]
+    assert dev.max() < 1e-12, dev.max()
+    assert O.rnorm(1, O.residual(1, to_host(ud))) <= 2e-10 * h_o[0]
