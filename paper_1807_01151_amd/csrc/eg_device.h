@@ -86,12 +86,13 @@ __device__ __forceinline__ void geom(const R* X, const R* xi, R c[D][D], R& det)
   }
 }
 
+// Tangential axes of face lf (ascending, skipping the normal axis lf / 2);
+// every index is static, so the caller's array stays in registers.
 template <int D>
 __device__ __forceinline__ void face_axes(int lf, int* ta) {
-  int r = lf >> 1, k = 0;
+  const int r = lf >> 1;
 #pragma unroll
-  for (int a = 0; a < D; ++a)
-    if (a != r) ta[k++] = a;
+  for (int q = 0; q < D - 1; ++q) ta[q] = q + (q >= r ? 1 : 0);
 }
 
 // Point index on the neighbour's face seen from this element's face point

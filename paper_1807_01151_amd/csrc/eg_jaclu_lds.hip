@@ -241,8 +241,11 @@ __global__ __launch_bounds__(512, 1) void k_jaclu_lds(const double* __restrict__
             } else if (used[s] < 0) {
               const double l = pv[s][tt] * ip;
               pv[s][tt] = l;
+              // fixed trip count (the bound is constant only once the step
+              // loop is unrolled), so that pv stays in registers
 #pragma unroll
-              for (int c = tt + 1; c < 16; ++c) pv[s][c] = fma(-l, pr[c], pv[s][c]);
+              for (int c = 0; c < 16; ++c)
+                if (c > tt) pv[s][c] = fma(-l, pr[c], pv[s][c]);
             }
           }
         }
@@ -280,7 +283,8 @@ __global__ __launch_bounds__(512, 1) void k_jaclu_lds(const double* __restrict__
         if (tt < nbk) {
           const int pr = s_prow[kb + tt];
 #pragma unroll
-          for (int t2 = 0; t2 < tt; ++t2) y[tt] = fma(-A[(kb + t2) * LDA + pr], y[t2], y[tt]);
+          for (int t2 = 0; t2 < 16; ++t2)
+            if (t2 < tt) y[tt] = fma(-A[(kb + t2) * LDA + pr], y[t2], y[tt]);
         }
       }
 #pragma unroll
