@@ -168,6 +168,19 @@ eg_status eg_exp1_step(eg_handle* h, double cfl, double* u0_dev, const double* f
  * of a level-p_max residual vector.  Synchronises. */
 eg_status eg_rnorm(eg_handle* h, const double* r_dev, double* rn_host);
 
+/* The norm of eg_rnorm without allocation or synchronisation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  r_dev: level-p_max
+ * residual (psi coordinates, as eg_rnorm); rn_dev: device pointer to one
+ * double that receives the norm.  Enqueued on the handle's stream; calls
+ * no allocating routine.  Its only workspace is a static per-device array
+ * of 4096 partial sums (32 KiB, held by each GPU the library runs on until
+ * the process ends), so the handle may have at most 1,048,576 elements
+ * (else EG_ERR_ARG with a message).  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (other streams or threads) race.
+ * Batch handles: EG_ERR_ARG. */
+eg_status eg_rnorm_noalloc(eg_handle* h, const double* r_dev, double* rn_dev);
+
 /* One eMG V-cycle (Section 2.4) on the level-p_max state u_dev, cycle index
  * n >= 1 (enters the CFL ramp).  rref is the reference norm of the ramp
  * (r_1 for the relative ramp, 1 for the absolute one; 0 = use the state's

@@ -15,7 +15,8 @@ EXPORTED_SYMBOLS = (
     "eg_timestep", "eg_element_jacobian", "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm",
     "eg_vcycle", "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read",
     "eg_drag", "eg_adjoint_apply", "eg_adjoint_solve", "eg_init_batch", "eg_layout", "eg_solve_batch", "eg_autotune",
-    "eg_set_graphs", "eg_measure_peak", "eg_jacobian_apply",
+    "eg_set_graphs", "eg_measure_peak", "eg_rnorm_noalloc",
+    "eg_jacobian_apply",
 )
 
 KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
@@ -74,6 +75,8 @@ def lib():
         L.eg_jacobian_p0.argtypes = [vp, vp, vp, vp, vp]
         L.eg_exp1_step.argtypes = [vp, d, vp, vp, C.POINTER(i)]
         L.eg_rnorm.argtypes = [vp, vp, pd]
+        L.eg_rnorm_noalloc.argtypes = [vp, vp, vp]
+        L.eg_rnorm_noalloc.restype = i
         L.eg_measure_peak.argtypes = [i, vp, pd]
         L.eg_measure_peak.restype = i
         L.eg_vcycle.argtypes = [vp, vp, i, d, pd, pd]
@@ -252,6 +255,15 @@ class Solver:
         v = C.c_double(0.0)
         self._chk(lib().eg_rnorm(self._h, pr, C.byref(v)))
         return v.value
+
+    def rnorm_noalloc(self, r, out=None):
+        """eg_rnorm's norm written into a one-element device tensor, with no
+        allocation inside the library and no synchronisation."""
+        import torch
+        pr = self._vec(r, self.p_max, "r")
+        o = torch.empty(1, dtype=torch.float64, device="cuda") if out is None else out
+        self._chk(lib().eg_rnorm_noalloc(self._h, pr, self._arr(o, 1, "out")))
+        return o
 
     def vcycle(self, u, n: int, rref: float = 0.0):
         pu = self._vec(u, self.p_max, "u")

@@ -24,6 +24,7 @@ using eg::TabData;
 
 struct eg_handle {
   DevMesh M;
+  int dev = 0;  // device current at eg_init_mesh / eg_init_batch
   int pmax = 1, s = 4, m = 30, relr = 1;
   int mixed = 0;  // EG_MIXED: FP32 smoother on p >= 1 (phase A), then FP64 residuals (phase B)
   int phase_b = 0;  // mixed mode: the current V-cycle is a defect-correction (phase B) cycle
@@ -776,6 +777,13 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
   h->cfl_max = prm->cfl_max;
   h->st = static_cast<hipStream_t>(hip_stream);
   h->modes = hier_modes(d, h->pmax);
+  {
+    // the handle's device; the no-allocation norm's static workspace is
+    // resolved here, once per device, with that device current
+    hipError_t e = hipGetDevice(&h->dev);
+    if (e == hipSuccess) e = eg::noalloc_resolve(h->dev);
+    if (e != hipSuccess) return hipfail(h, e, "device set-up");
+  }
   DevMesh& M = h->M;
   M.d = d;
   M.V = d + 2;
@@ -1324,6 +1332,17 @@ eg_status eg_rnorm(eg_handle* h, const double* r_dev, double* rn_host) {
   HIPCHK(h, hipMemcpyAsync(h->hpin, h->nout, sizeof(double), hipMemcpyDeviceToHost, h->st));
   ECHK(sync_status(h));
   *rn_host = h->hpin[0];
+  return EG_OK;
+}
+
+eg_status eg_rnorm_noalloc(eg_handle* h, const double* r_dev, double* rn_dev) {
+  if (!h || !r_dev || !rn_dev) return EG_ERR_ARG;
+  if (h->batch) return fail(h, EG_ERR_ARG, "batch handle: per-solve norms need eg_solve_batch");
+  if (h->M.ne > eg::noalloc_max_elems())
+    return fail(h, EG_ERR_ARG, "eg_rnorm_noalloc: " + std::to_string(h->M.ne) + " elements exceed the static workspace (" +
+                                   std::to_string(eg::noalloc_max_elems()) + " elements)");
+  HIPCHK(h, eg::launch_dnorm_noalloc(h->dev, h->M.ne, h->M.V, nmodes_of(h->M.d, h->pmax), h->M.omega, r_dev, rn_dev,
+                                     h->st));
   return EG_OK;
 }
 

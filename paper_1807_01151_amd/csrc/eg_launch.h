@@ -142,6 +142,13 @@ hipError_t launch_trunc(const double* x, double* y, int N, int Nc, int rows, hip
 hipError_t launch_pad_add(double* x, const double* y, int N, int Nc, int rows, hipStream_t st);
 hipError_t launch_fill0(double* x, size_t n, hipStream_t st);
 hipError_t launch_expand_cfl(const DevMesh& M, const double* cfl_s, hipStream_t st);
+// No-allocation density norm (eg_noalloc.hip): the file-scope workspace's
+// address on `device` is resolved once, with that device current; the launch
+// then needs no allocation.  ne <= noalloc_max_elems().
+int noalloc_max_elems();
+hipError_t noalloc_resolve(int device);
+hipError_t launch_dnorm_noalloc(int device, int ne, int V, int N, double omega, const double* r, double* out,
+                                hipStream_t st);
 // Achievable peaks (eg_peak.hip): kind 0 HBM copy GB/s, 1 FP64 matrix-core
 // TFLOP/s, 2 FP64 vector FMA TFLOP/s; allocates its own buffers.
 hipError_t measure_peak(int kind, hipStream_t st, double* value);
