@@ -11,6 +11,16 @@
 
 namespace eg {
 
+// Orders LDS accesses between the lanes of one wavefront: a store by one
+// lane before the call is seen by a load of another lane after it.  Without
+// it the per-thread memory model lets the compiler hoist a load above
+// another lane's (conditional) store to the same address.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The numerical flux selected for the handle (uniform over a launch).
 template <int D, class SL, class SR, class S, class R>
 __device__ __forceinline__ void num_flux(const SL* UL, const SR* UR, const real_t<S>* nh, S* F,

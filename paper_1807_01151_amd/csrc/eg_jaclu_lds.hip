@@ -1,5 +1,6 @@
 // PRK element block assembly and LU for 64 < n = V N < 256 (2D p = 4:
-// n = 100; 3D p = 2: n = 135) in FP64 on the matrix cores.
+// n = 100; 3D p = 2: n = 135) on the matrix cores: FP64 for the FP64
+// smoother, FP32 with FP32 accumulation for the mixed-precision one.
 //
 // The block (Section 2.3, end; Section 3.3, eq. (jac1), phi coordinates) is
 //   Pt[(v,i),(w,j)] = delta_vw G_ij / dtau - Dt[(v,i),(w,j)],
@@ -19,12 +20,14 @@
 // p = 2), then the assembled block, column-major (phase 2: 146 KB), on
 // which the LU with partial pivoting runs in panels of 16 columns:
 //   (a) wavefront 0 factorises the panel in registers (rows in lanes,
-//       largest |a| as the pivot, ties to the lowest row slot), writes it
-//       back and records the new logical row order: pivot rows first, in
-//       pivot order, then the others;
-//   (b) U12 = L11^{-1} A12 by forward substitution, one column per thread;
-//   (c) A22 -= L21 U12 on the matrix cores, one 16 x 16 tile per
-//       wavefront at a time.
+//       largest |a| as the pivot, ties to the lowest row slot, the pivot
+//       row broadcast through LDS), writes it back, records the new logical
+//       row order (pivot rows first, in pivot order, then the others) and
+//       forms L11^{-1};
+//   (b, c) every wavefront takes a 16-column tile of the trailing part:
+//       U12 = L11^{-1} A12 on the matrix cores, whose accumulators are in
+//       the B-operand layout of the next product, then A22 -= L21 U12 tile
+//       by tile (waves sharing a column tile split its row tiles).
 // Rows are never moved: the logical order lives in s_prow and the factors
 // are written out in it, column-major with perm[k] = the block row of the
 // k-th pivot, the format of the other factorisation kernels (read by the
@@ -40,7 +43,7 @@ namespace eg {
 
 namespace {
 
-template <int D, int P>
+template <int D, int P, class R>
 struct LdsLu {
   using C = Cfg<D, P>;
   static constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, n = C::NB;
@@ -62,30 +65,61 @@ struct LdsLu {
   static_assert(n > 64 && n < 192 && RPL <= 3, "block size");
 };
 
-template <int D, int P>
+template <int D, int P, class R>
 constexpr size_t jaclu_lds_bytes() {
-  return (size_t)LdsLu<D, P>::VALUES * sizeof(double);
+  return (size_t)LdsLu<D, P, R>::VALUES * sizeof(R);
 }
 
-template <int D, int P>
-__global__ __launch_bounds__(512, 1) void k_jaclu_lds(const double* __restrict__ BC, const double* __restrict__ Gpk,
-                                                      int NT, const double* __restrict__ dtau, double* __restrict__ out,
+// The 16 x 16 x 4 matrix-core product of the arithmetic type: FP64 for the
+// FP64 smoother, FP32 (FP32 accumulation) for the mixed-precision one.  The
+// accumulator layouts differ: lane l holds rows (l >> 4) + 4 r (FP64) or
+// 4 (l >> 4) + r (FP32) of column l & 15; the A operand is A[l & 15][l >> 4]
+// and the B operand B[l >> 4][l & 15] in both (checked on the GPU by
+// in-bounds probes).
+typedef float flt4_t __attribute__((ext_vector_type(4)));
+template <class R> struct Mfma;
+template <> struct Mfma<double> {
+  using acc = dbl4_t;
+  static __device__ __forceinline__ acc run(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int r) { return kq + 4 * r; }
+};
+template <> struct Mfma<float> {
+  using acc = flt4_t;
+  static __device__ __forceinline__ acc run(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
+};
+
+// FP32 blocks take half the LDS, so two workgroups share a compute unit
+// (the serial panel steps of one overlap the other's matrix-core work):
+// four waves per SIMD, 128 registers per lane; FP64: two waves per SIMD.
+template <int D, int P, class R>
+__global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 2) void k_jaclu_lds(const R* __restrict__ BC, const double* __restrict__ Gpk,
+                                                      int NT, const double* __restrict__ dtau, R* __restrict__ out,
                                                       int* __restrict__ perm, int* __restrict__ fail, int ne,
                                                       Tab<D, P, double> tab) {
-  using L = LdsLu<D, P>;
+  using L = LdsLu<D, P, R>;
+  using MF = Mfma<R>;
+  using acc_t = typename MF::acc;
   constexpr int V = L::V, N = L::N, Q = L::Q, QV = L::QV, QF = L::QF, NF = L::NF, n = L::n, NW = L::NW;
   constexpr int NPF = L::NPF, NT16 = L::NT16, JPW = L::JPW, JOBS = L::JOBS, RPL = L::RPL, LDA = L::LDA;
-  extern __shared__ double s_mem[];
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  R* s_mem = reinterpret_cast<R*>(s_raw);
   __shared__ Tab<D, P, double> t;
   __shared__ int s_prow[n];
+  __shared__ R s_piv[16];         // pivot-row broadcast of the panel step
+  __shared__ R s_linv[16 * 16];   // L11^{-1} of the current panel, row-major
   const int e = blockIdx.x;
   if (e >= ne) return;  // whole workgroup
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int il = lane & 15, kq = lane >> 4;
-  double* s_dph = s_mem;               // [QV][D][N]
-  double* s_ph = s_mem + L::OFF_PH;    // [QV + NPF][N]: phi at the volume, then the face points
-  double* s_B = s_mem + L::OFF_B;      // [QV][D][V][V] then [NPF][V][V]
-  const double* s_C = s_B + QV * D * V * V;
+  R* s_dph = s_mem;               // [QV][D][N]
+  R* s_ph = s_mem + L::OFF_PH;    // [QV + NPF][N]: phi at the volume, then the face points
+  R* s_B = s_mem + L::OFF_B;      // [QV][D][V][V] then [NPF][V][V]
+  const R* s_C = s_B + QV * D * V * V;
 
   // ---- phase 1: tables and the element's pointwise Jacobians into LDS
   copy_tab(t, tab);
@@ -97,8 +131,8 @@ __global__ __launch_bounds__(512, 1) void k_jaclu_lds(const double* __restrict__
 #pragma unroll
     for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
 #pragma unroll
-    for (int r = 0; r < D; ++r) s_dph[(q * D + r) * N + j] = dphi_vol<D, P, double>(t, j, iq, r);
-    s_ph[q * N + j] = phi_vol<D, P, double>(t, j, iq);
+    for (int r = 0; r < D; ++r) s_dph[(q * D + r) * N + j] = R(dphi_vol<D, P, double>(t, j, iq, r));
+    s_ph[q * N + j] = R(phi_vol<D, P, double>(t, j, iq));
   }
   for (int it = tid; it < NPF * N; it += 512) {
     const int lf = it / (QF * N), k = (it / N) % QF, j = it % N;
@@ -106,7 +140,7 @@ __global__ __launch_bounds__(512, 1) void k_jaclu_lds(const double* __restrict__
     face_axes<D>(lf, ta);
 #pragma unroll
     for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
-    s_ph[(QV + lf * QF + k) * N + j] = phi_face<D, P, double>(t, j, lf, ta, ik);
+    s_ph[(QV + lf * QF + k) * N + j] = R(phi_face<D, P, double>(t, j, lf, ta, ik));
   }
   for (int k = tid; k < n; k += 512) s_prow[k] = k;
   __syncthreads();
@@ -121,59 +155,59 @@ __global__ __launch_bounds__(512, 1) void k_jaclu_lds(const double* __restrict__
     jv[jj] = (jb / NT16) / V;
     jw[jj] = (jb / NT16) % V;
   }
-  dbl4_t acc[JPW][NT16];
+  acc_t acc[JPW][NT16];
 #pragma unroll
   for (int jj = 0; jj < JPW; ++jj)
 #pragma unroll
-    for (int c = 0; c < NT16; ++c) acc[jj][c] = dbl4_t{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < NT16; ++c) acc[jj][c] = acc_t{R(0), R(0), R(0), R(0)};
 #pragma unroll 1
   for (int ks = 0; ks < L::KSV; ++ks) {
     const int q = 4 * ks + kq;
-    double bf[NT16], dp[NT16][D];
+    R bf[NT16], dp[NT16][D];
 #pragma unroll
     for (int c = 0; c < NT16; ++c) {
       const int j = 16 * c + il;
-      bf[c] = j < N ? s_ph[q * N + j] : 0.0;
+      bf[c] = j < N ? s_ph[q * N + j] : R(0);
 #pragma unroll
-      for (int r = 0; r < D; ++r) dp[c][r] = j < N ? s_dph[(q * D + r) * N + j] : 0.0;
+      for (int r = 0; r < D; ++r) dp[c][r] = j < N ? s_dph[(q * D + r) * N + j] : R(0);
     }
 #pragma unroll
     for (int jj = 0; jj < JPW; ++jj) {
       if (wv + NW * jj < JOBS) {
-        double a = 0.0;
+        R a = R(0);
 #pragma unroll
         for (int r = 0; r < D; ++r) {
-          const double d = NT16 == 1 ? dp[0][r] : (jt[jj] == 0 ? dp[0][r] : dp[NT16 - 1][r]);
+          const R d = NT16 == 1 ? dp[0][r] : (jt[jj] == 0 ? dp[0][r] : dp[NT16 - 1][r]);
           a = fma(d, s_B[((q * D + r) * V + jv[jj]) * V + jw[jj]], a);
         }
 #pragma unroll
-        for (int c = 0; c < NT16; ++c) acc[jj][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[c], acc[jj][c], 0, 0, 0);
+        for (int c = 0; c < NT16; ++c) acc[jj][c] = MF::run(a, bf[c], acc[jj][c]);
       }
     }
   }
 #pragma unroll 1
   for (int ks = 0; ks < L::KSF; ++ks) {
     const int fk = 4 * ks + kq;
-    double bf[NT16];
+    R bf[NT16];
 #pragma unroll
     for (int c = 0; c < NT16; ++c) {
       const int j = 16 * c + il;
-      bf[c] = j < N ? s_ph[(QV + fk) * N + j] : 0.0;
+      bf[c] = j < N ? s_ph[(QV + fk) * N + j] : R(0);
     }
 #pragma unroll
     for (int jj = 0; jj < JPW; ++jj) {
       if (wv + NW * jj < JOBS) {
-        const double fa = NT16 == 1 ? bf[0] : (jt[jj] == 0 ? bf[0] : bf[NT16 - 1]);
-        const double a = -fa * s_C[(fk * V + jv[jj]) * V + jw[jj]];
+        const R fa = NT16 == 1 ? bf[0] : (jt[jj] == 0 ? bf[0] : bf[NT16 - 1]);
+        const R a = -fa * s_C[(fk * V + jv[jj]) * V + jw[jj]];
 #pragma unroll
-        for (int c = 0; c < NT16; ++c) acc[jj][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[c], acc[jj][c], 0, 0, 0);
+        for (int c = 0; c < NT16; ++c) acc[jj][c] = MF::run(a, bf[c], acc[jj][c]);
       }
     }
   }
   __syncthreads();  // phase-1 LDS is overwritten by the block below
 
   // ---- the block Pt = G/dtau - Dt, column-major in LDS
-  double* A = s_mem;
+  R* A = s_mem;
   {
     const double idt = 1.0 / dtau[e];
     const double* G = Gpk + (size_t)e * NT;
@@ -184,10 +218,10 @@ __global__ __launch_bounds__(512, 1) void k_jaclu_lds(const double* __restrict__
       for (int c = 0; c < NT16; ++c) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = 16 * jt[jj] + kq + 4 * r, j = 16 * c + il;
+          const int i = 16 * jt[jj] + MF::row(kq, r), j = 16 * c + il;
           if (i < N && j < N) {
-            double g = 0.0;
-            if (jv[jj] == jw[jj]) g = ((i >= j) ? G[i * (i + 1) / 2 + j] : G[j * (j + 1) / 2 + i]) * idt;
+            R g = R(0);
+            if (jv[jj] == jw[jj]) g = R(((i >= j) ? G[i * (i + 1) / 2 + j] : G[j * (j + 1) / 2 + i]) * idt);
             A[(jw[jj] * N + j) * LDA + jv[jj] * N + i] = g - acc[jj][c][r];
           }
         }
@@ -200,9 +234,9 @@ __global__ __launch_bounds__(512, 1) void k_jaclu_lds(const double* __restrict__
 #pragma unroll 1
   for (int kb = 0; kb < n; kb += 16) {
     const int nbk = min(16, n - kb);
-    // (a) panel factorisation by wavefront 0
+    // (a) panel factorisation by wavefront 0, then L11^{-1}
     if (wv == 0) {
-      double pv[RPL][16];
+      R pv[RPL][16];
       int prw[RPL], used[RPL];
 #pragma unroll
       for (int s = 0; s < RPL; ++s) {
@@ -210,11 +244,13 @@ __global__ __launch_bounds__(512, 1) void k_jaclu_lds(const double* __restrict__
         prw[s] = lr < n ? s_prow[lr] : 0;
         used[s] = lr < n ? -1 : 16;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) pv[s][c] = (lr < n && c < nbk) ? A[(kb + c) * LDA + prw[s]] : 0.0;
+        for (int c = 0; c < 16; ++c) pv[s][c] = (lr < n && c < nbk) ? A[(kb + c) * LDA + prw[s]] : R(0);
       }
 #pragma unroll
       for (int tt = 0; tt < 16; ++tt) {
         if (tt < nbk) {
+          // pivot: largest |a| of the unused rows (float keys, ties to the
+          // lowest row slot; used rows and rows past n have key 0)
           unsigned key = 0u;
 #pragma unroll
           for (int s = 0; s < RPL; ++s)
@@ -223,30 +259,37 @@ __global__ __launch_bounds__(512, 1) void k_jaclu_lds(const double* __restrict__
           const unsigned kmax = wave_max_u32(key);
           const int ws = __builtin_amdgcn_readfirstlane(255 - (int)(kmax & 255u));
           const int wl = ws & 63, wsl = ws >> 6;
-          double pr[16];
+          // the pivot row goes through LDS once (the winning lane writes it,
+          // every lane reads it back as a broadcast), ordered between the
+          // lanes by wave-scope fences (the previous step's reads before the
+          // write, the write before this step's reads)
+          wave_lds_sync();
+          if (lane == wl) {
 #pragma unroll
-          for (int c = 0; c < 16; ++c) {
-            double x = pv[0][c];
+            for (int s = 0; s < RPL; ++s)
+              if (wsl == s) {
 #pragma unroll
-            for (int s = 1; s < RPL; ++s) x = (wsl == s) ? pv[s][c] : x;
-            pr[c] = readlane_d(x, wl);
+                for (int c = 0; c < 16; ++c)
+                  if (c >= tt) s_piv[c] = pv[s][c];
+              }
           }
-          if (lane == 0 && !(fabs(pr[tt]) > 0.0)) atomicOr(fail, 1);
-          const double ip = 1.0 / pr[tt];
+          wave_lds_sync();
+          R pr[16];
+#pragma unroll
+          for (int c = 0; c < 16; ++c) pr[c] = (c >= tt) ? s_piv[c] : R(0);
+          if (lane == 0 && !(fabs(pr[tt]) > R(0))) atomicOr(fail, 1);
+          const R ip = R(1) / pr[tt];
+          // rows not used as pivots take multiplier l, the others l = 0
+          // (their values are then left unchanged by the update)
 #pragma unroll
           for (int s = 0; s < RPL; ++s) {
-            if (lane + 64 * s == ws) {
-              if (used[s] >= 0) atomicOr(fail, 4);  // the winner must be an unused row
-              used[s] = tt;
-            } else if (used[s] < 0) {
-              const double l = pv[s][tt] * ip;
-              pv[s][tt] = l;
-              // fixed trip count (the bound is constant only once the step
-              // loop is unrolled), so that pv stays in registers
+            if (lane + 64 * s == ws) used[s] = tt;
+            const bool act = used[s] < 0;
+            const R l = act ? pv[s][tt] * ip : R(0);
+            pv[s][tt] = act ? l : pv[s][tt];
 #pragma unroll
-              for (int c = 0; c < 16; ++c)
-                if (c > tt) pv[s][c] = fma(-l, pr[c], pv[s][c]);
-            }
+            for (int c = 0; c < 16; ++c)
+              if (c > tt) pv[s][c] = fma(-l, pr[c], pv[s][c]);
           }
         }
       }
@@ -268,64 +311,93 @@ __global__ __launch_bounds__(512, 1) void k_jaclu_lds(const double* __restrict__
         }
         before += __popcll(bal);
       }
+      // L11^{-1} (unit lower triangular; identity past nbk), lane j < 16
+      // forms column j by forward substitution from the panel and row order
+      // the other lanes have just written
+      wave_lds_sync();
+      if (lane < 16) {
+        R x[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          R v = (t == lane) ? R(1) : R(0);
+          if (t < nbk) {
+            const int pr = s_prow[kb + t];
+#pragma unroll
+            for (int t2 = 0; t2 < 16; ++t2)
+              if (t2 < t) v = fma(-A[(kb + t2) * LDA + pr], x[t2], v);
+          }
+          x[t] = v;
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) s_linv[t * 16 + lane] = x[t];
+      }
     }
     __syncthreads();
     const int k1 = kb + nbk, m = n - k1;
     if (m <= 0) break;
-    // (b) U12 = L11^{-1} A12, one column per thread
-    if (tid < m) {
-      const int col = k1 + tid;
-      double y[16];
-#pragma unroll
-      for (int tt = 0; tt < 16; ++tt) y[tt] = tt < nbk ? A[col * LDA + s_prow[kb + tt]] : 0.0;
-#pragma unroll
-      for (int tt = 1; tt < 16; ++tt) {
-        if (tt < nbk) {
-          const int pr = s_prow[kb + tt];
-#pragma unroll
-          for (int t2 = 0; t2 < 16; ++t2)
-            if (t2 < tt) y[tt] = fma(-A[(kb + t2) * LDA + pr], y[t2], y[tt]);
-        }
-      }
-#pragma unroll
-      for (int tt = 1; tt < 16; ++tt)
-        if (tt < nbk) A[col * LDA + s_prow[kb + tt]] = y[tt];
-    }
-    __syncthreads();
-    // (c) A22 -= L21 U12 on the matrix cores
+    // (b, c) column tile tj of wavefront wv: U12 = L11^{-1} A12 on the matrix
+    // cores (its accumulator register r is the B operand of k-step r), then
+    // A22 -= L21 U12 for the row tiles of this wavefront; waves sharing a
+    // column tile split its row tiles and each forms the U12 tile
     const int T = (m + 15) / 16;
-#pragma unroll 1
-    for (int tile = wv; tile < T * T; tile += NW) {
-      const int ti = tile / T, tj = tile % T;
-      const int cc = k1 + 16 * tj + il;
-      const bool cok = cc < n;
-      int crow[4];
-      dbl4_t c;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int lr = k1 + 16 * ti + kq + 4 * r;
-        crow[r] = lr < n ? s_prow[lr] : -1;
-        c[r] = (crow[r] >= 0 && cok) ? A[cc * LDA + crow[r]] : 0.0;
-      }
-      const int alr = k1 + 16 * ti + il;
-      const int arow = alr < n ? s_prow[alr] : -1;
+    const int per = NW / T > 0 ? NW / T : 1;   // wavefronts per column tile
+    const int tj = wv % T, sub = wv / T;
+    const bool act = wv < T * per;
+    const int cc = k1 + 16 * tj + il;
+    const bool cok = act && cc < n;
+    acc_t u = acc_t{R(0), R(0), R(0), R(0)};
+    if (act) {
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4) {
         const int k = 4 * s4 + kq;
-        const bool kok = k < nbk;
-        const double a = (arow >= 0 && kok) ? -A[(kb + k) * LDA + arow] : 0.0;
-        const double b = (kok && cok) ? A[cc * LDA + s_prow[kb + k]] : 0.0;
-        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+        const R a = s_linv[il * 16 + k];
+        const R b = (k < nbk && cok) ? A[cc * LDA + s_prow[kb + k]] : R(0);
+        u = MF::run(a, b, u);
       }
+    }
+    __syncthreads();  // every wave sharing the tile has read A12 before U12 replaces it
+    if (act && sub == 0 && cok) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (crow[r] >= 0 && cok) A[cc * LDA + crow[r]] = c[r];
+      for (int r = 0; r < 4; ++r) {
+        const int k = MF::row(kq, r);
+        if (k < nbk) A[cc * LDA + s_prow[kb + k]] = u[r];
+      }
+    }
+    // FP32: the accumulator layout is not the B-operand layout, so U12 is
+    // read back from LDS once it is complete
+    if constexpr (sizeof(R) == 4) __syncthreads();
+    if (act) {
+#pragma unroll 2
+      for (int ti = sub; ti < T; ti += per) {
+        int crow[4];
+        acc_t c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int lr = k1 + 16 * ti + MF::row(kq, r);
+          crow[r] = lr < n ? s_prow[lr] : -1;
+          c[r] = (crow[r] >= 0 && cok) ? A[cc * LDA + crow[r]] : R(0);
+        }
+        const int alr = k1 + 16 * ti + il;
+        const int arow = alr < n ? s_prow[alr] : -1;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int k = 4 * s4 + kq;
+          const R a = (arow >= 0 && k < nbk) ? -A[(kb + k) * LDA + arow] : R(0);
+          R b;
+          if constexpr (sizeof(R) == 8) b = u[s4];
+          else b = (k < nbk && cok) ? A[cc * LDA + s_prow[kb + k]] : R(0);
+          c = MF::run(a, b, c);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (crow[r] >= 0 && cok) A[cc * LDA + crow[r]] = c[r];
+      }
     }
     __syncthreads();
   }
 
   // ---- factors in pivot order, column-major, and the permutation
-  double* o = out + (size_t)e * n * n;
+  R* o = out + (size_t)e * n * n;
   for (int it = tid; it < n * n; it += 512) {
     const int col = it / n, k = it % n;
     o[it] = A[col * LDA + s_prow[k]];
@@ -333,21 +405,21 @@ __global__ __launch_bounds__(512, 1) void k_jaclu_lds(const double* __restrict__
   for (int k = tid; k < n; k += 512) perm[(size_t)e * n + k] = s_prow[k];
 }
 
-template <int D, int P>
-hipError_t jaclu_lds_t(const DevMesh& M, const TabData& td, const double* bc, const double* dtau, double* out,
+template <int D, int P, class R>
+hipError_t jaclu_lds_t(const DevMesh& M, const TabData& td, const void* bc, const double* dtau, void* out,
                        int* perm, int* fail, hipStream_t st) {
   Tab<D, P, double> t;
   fill_tab(t, td);
-  const size_t lds = jaclu_lds_bytes<D, P>();
+  const size_t lds = jaclu_lds_bytes<D, P, R>();
   static bool attr = false;  // set once: not a stream operation, so also fine while capturing
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_jaclu_lds<D, P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)k_jaclu_lds<D, P, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((k_jaclu_lds<D, P>), dim3(M.ne), dim3(512), lds, st, bc, M.Gpk, M.NT, dtau, out, perm, fail,
-                     M.ne, t);
+  hipLaunchKernelGGL((k_jaclu_lds<D, P, R>), dim3(M.ne), dim3(512), lds, st, static_cast<const R*>(bc), M.Gpk, M.NT,
+                     dtau, static_cast<R*>(out), perm, fail, M.ne, t);
   return hipGetLastError();
 }
 
@@ -355,10 +427,15 @@ hipError_t jaclu_lds_t(const DevMesh& M, const TabData& td, const double* bc, co
 
 bool jaclu_lds_supported(int d, int p) { return (d == 2 && p == 4) || (d == 3 && p == 2); }
 
-hipError_t launch_jaclu_lds(const DevMesh& M, const TabData& td, int p, const double* bc, const double* dtau,
-                            double* out, int* perm, int* fail, hipStream_t st) {
-  if (M.d == 2 && p == 4) return jaclu_lds_t<2, 4>(M, td, bc, dtau, out, perm, fail, st);
-  if (M.d == 3 && p == 2) return jaclu_lds_t<3, 2>(M, td, bc, dtau, out, perm, fail, st);
+hipError_t launch_jaclu_lds(const DevMesh& M, const TabData& td, int p, int prec, const void* bc, const double* dtau,
+                            void* out, int* perm, int* fail, hipStream_t st) {
+  const bool f32 = prec == PREC_FP32;
+  if (M.d == 2 && p == 4)
+    return f32 ? jaclu_lds_t<2, 4, float>(M, td, bc, dtau, out, perm, fail, st)
+               : jaclu_lds_t<2, 4, double>(M, td, bc, dtau, out, perm, fail, st);
+  if (M.d == 3 && p == 2)
+    return f32 ? jaclu_lds_t<3, 2, float>(M, td, bc, dtau, out, perm, fail, st)
+               : jaclu_lds_t<3, 2, double>(M, td, bc, dtau, out, perm, fail, st);
   return hipErrorInvalidValue;
 }
 

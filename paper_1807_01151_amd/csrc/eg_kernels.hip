@@ -3193,9 +3193,8 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
         if (!gph) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_jaclu_wave<D, P, R>), dim3((M.ne + 3) / 4), dim3(256), 0, st, bc, M.Gpk, M.NT, dtau,
                            out, perm, fail, M.ne, t, gph);
-      } else if (sizeof(R) == 8 && jaclu_lds_supported(D, P)) {
-        return launch_jaclu_lds(M, td, P, reinterpret_cast<const double*>(bc), dtau,
-                                reinterpret_cast<double*>(out), perm, fail, st);
+      } else if (jaclu_lds_supported(D, P)) {
+        return launch_jaclu_lds(M, td, P, sizeof(R) == 4 ? PREC_FP32 : PREC_FP64, bc, dtau, out, perm, fail, st);
       } else {
         const R* gph = static_cast<const R*>(M.phitab[P][sizeof(R) == 4 ? PREC_FP32 : PREC_FP64]);
         if (!gph) return hipErrorInvalidValue;

@@ -76,11 +76,12 @@ struct FasOut {
 hipError_t launch_residual(const DevMesh& M, const TabData& td, int p, const double* ut, const double* fadd,
                            double* rt, int prec, hipStream_t st, const FasOut& fas = FasOut{});
 bool jacobian_supported(int d, int p);
-// FP64 block assembly on the matrix cores and LDS-resident blocked LU
-// (eg_jaclu_lds.hip) for 2D p = 4 and 3D p = 2; bc from k_jac_points.
+// Block assembly on the matrix cores and LDS-resident blocked LU
+// (eg_jaclu_lds.hip) for 2D p = 4 and 3D p = 2, FP64 or FP32 (prec); bc
+// from k_jac_points in the same precision, out FP64 or FP32 factors.
 bool jaclu_lds_supported(int d, int p);
-hipError_t launch_jaclu_lds(const DevMesh& M, const TabData& td, int p, const double* bc, const double* dtau,
-                            double* out, int* perm, int* fail, hipStream_t st);
+hipError_t launch_jaclu_lds(const DevMesh& M, const TabData& td, int p, int prec, const void* bc, const double* dtau,
+                            void* out, int* perm, int* fail, hipStream_t st);
 hipError_t launch_jacobian(const DevMesh& M, const TabData& td, int p, const double* ut, const double* dtau,
                            void* out, int* perm, int* fail, bool factor, int prec, hipStream_t st);
 // un null: the stage starts from ut and, if save is set, stores it there
