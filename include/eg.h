@@ -302,6 +302,22 @@ eg_status eg_adjoint_apply(eg_handle* h, int p, const double* u_dev, const doubl
 eg_status eg_adjoint_solve(eg_handle* h, const double* u_dev, const double* g_dev, double* lam_dev, double drop_tol,
                            int max_cycles, double* hist_host, int* n_cycles_host);
 
+/* One component of the adjoint gradient of the drag coefficient with
+ * respect to a parameter theta of the problem (free-stream Mach number, a
+ * wall-bump amplitude, ...): with lambda the adjoint solution at the
+ * converged state u (eg_adjoint_solve with g = dC_D/du),
+ *   dC_D/dtheta = dC_D/dtheta|_u + lambda . dR/dtheta|_u,
+ * both partial derivatives at fixed coefficients u taken as central
+ * differences over the handles hp and hm, built at theta + step and
+ * theta - step (same mesh topology, element count, order and device; their
+ * own geometry and free stream).  u_dev, lam_dev: level-p_max vectors
+ * (psi coordinates); dir_host, sref: as eg_drag.  The residuals, their
+ * difference and the dot product with lambda run in the library's kernels
+ * (FP64, deterministic sums); uses both handles' residual workspaces.
+ * dj_host receives dC_D/dtheta.  Synchronises both streams. */
+eg_status eg_param_sensitivity(eg_handle* hp, eg_handle* hm, double step, const double* u_dev, const double* lam_dev,
+                               const double* dir_host, double sref, double* dj_host);
+
 /* Profiling aid: HIP-event timing of the solver's own kernel launches, by
  * kernel class and level, recorded on the handle's stream while enabled.
  * eg_profile(h, 1) clears the records and starts recording, eg_profile(h, 0)

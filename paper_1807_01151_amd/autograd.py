@@ -4,9 +4,10 @@ Each Function only marshals tensors to the C ABI: the forward passes run the
 library's residual, drag and steady-solve kernels, the backward passes its
 transposed-Jacobian kernel and adjoint V-cycle.  The parameter derivatives
 of the residual and of the drag at a fixed state (dR/dtheta|_u,
-dC_D/dtheta|_u) are central differences of residual and drag evaluations on
-handles built at theta +- h; everything else is the discrete adjoint
-(dR/du)^T lambda + dC_D/du = 0, dC_D/dtheta = dC_D/dtheta|_u + lambda . dR/dtheta|_u.
+dC_D/dtheta|_u) are central differences over handles built at theta +- h,
+formed inside the library (eg_param_sensitivity); everything else is the
+discrete adjoint (dR/du)^T lambda + dC_D/du = 0,
+dC_D/dtheta = dC_D/dtheta|_u + lambda . dR/dtheta|_u.
 """
 
 from __future__ import annotations
@@ -99,14 +100,16 @@ class SteadyDrag(torch.autograd.Function):
         lam, _, _ = S.adjoint_solve(u, g, drop_tol=prob.adjoint_drop, max_cycles=prob.adjoint_max_cycles)
         h = prob.fd_step
         out = torch.zeros(len(th), dtype=torch.float64)
+        direction = None
         for i in range(len(th)):
             tp, tm = list(th), list(th)
             tp[i] += h
             tm[i] -= h
             Sp, Sm = prob.solver(tp), prob.solver(tm)
-            dR = (Sp.residual(prob.p_max, u) - Sm.residual(prob.p_max, u)) / (2 * h)
-            dC = (Sp.drag(u, sref=prob.sref) - Sm.drag(u, sref=prob.sref)) / (2 * h)
-            out[i] = dC + float(torch.sum(lam * dR))
+            if direction is None:
+                from .binding import _freestream_direction
+                direction = _freestream_direction(S.dim, S.alpha_deg, S.beta_deg)
+            out[i] = Sp.param_sensitivity(Sm, h, u, lam, direction=direction, sref=prob.sref)
             Sp.close()
             Sm.close()
         return grad * out, None

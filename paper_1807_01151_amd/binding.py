@@ -16,7 +16,7 @@ EXPORTED_SYMBOLS = (
     "eg_vcycle", "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read",
     "eg_drag", "eg_adjoint_apply", "eg_adjoint_solve", "eg_init_batch", "eg_layout", "eg_solve_batch", "eg_autotune",
     "eg_set_graphs", "eg_measure_peak", "eg_rnorm_noalloc",
-    "eg_jacobian_apply",
+    "eg_param_sensitivity", "eg_jacobian_apply",
 )
 
 KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
@@ -92,6 +92,8 @@ def lib():
         L.eg_solve_batch.argtypes = [vp, vp, d, i, pd, C.POINTER(i)]
         L.eg_adjoint_apply.argtypes = [vp, i, vp, vp, vp]
         L.eg_jacobian_apply.argtypes = [vp, i, vp, vp, vp]
+        L.eg_param_sensitivity.argtypes = [vp, vp, d, vp, vp, pd, d, pd]
+        L.eg_param_sensitivity.restype = i
         L.eg_adjoint_solve.argtypes = [vp, vp, vp, vp, d, i, pd, C.POINTER(i)]
         for name in ("eg_sizes", "eg_set_freestream", "eg_residual", "eg_timestep", "eg_element_jacobian",
                      "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm", "eg_vcycle",
@@ -379,9 +381,23 @@ def _solver_adjoint_solve(self, u, g, lam=None, drop_tol: float = 1e-10, max_cyc
     return lam, hist[: nc.value + 1], st
 
 
+def _solver_param_sensitivity(self, minus, step: float, u, lam, direction=None, sref: float = 1.0):
+    """dC_D/dtheta = dC_D/dtheta|_u + lambda . dR/dtheta|_u by central
+    differences over this handle (built at theta + step) and ``minus``
+    (theta - step), evaluated inside the library (eg_param_sensitivity)."""
+    if direction is None:
+        direction = _freestream_direction(self.dim, self.alpha_deg, self.beta_deg)
+    dv = (C.c_double * 3)(*([float(x) for x in direction] + [0.0] * (3 - len(direction))))
+    pu, pl = self._vec(u, self.p_max, "u"), self._vec(lam, self.p_max, "lam")
+    out = C.c_double(0.0)
+    self._chk(lib().eg_param_sensitivity(self._h, minus._h, float(step), pu, pl, dv, float(sref), C.byref(out)))
+    return out.value
+
+
 Solver.drag = _solver_drag
 Solver.adjoint_apply = _solver_adjoint_apply
 Solver.jacobian_apply = _solver_jacobian_apply
+Solver.param_sensitivity = _solver_param_sensitivity
 Solver.adjoint_solve = _solver_adjoint_solve
 
 

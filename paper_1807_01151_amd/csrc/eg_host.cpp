@@ -1506,6 +1506,38 @@ eg_status eg_adjoint_apply(eg_handle* h, int p, const double* u_dev, const doubl
   return EG_OK;
 }
 
+eg_status eg_param_sensitivity(eg_handle* hp, eg_handle* hm, double step, const double* u_dev, const double* lam_dev,
+                               const double* dir_host, double sref, double* dj_host) {
+  if (!hp || !hm || hp == hm || !u_dev || !lam_dev || !dir_host || !dj_host || !(step > 0.0) || !(sref > 0.0))
+    return EG_ERR_ARG;
+  if (hp->batch || hm->batch) return fail(hp, EG_ERR_ARG, "batch handle: per-solve sensitivities are not supported");
+  if (hp->M.d != hm->M.d || hp->M.ne != hm->M.ne || hp->pmax != hm->pmax || hp->dev != hm->dev)
+    return fail(hp, EG_ERR_ARG, "the two handles must have the same dimension, elements, order and device");
+  const int p = hp->pmax, N = nmodes_of(hp->M.d, p);
+  const size_t K = (size_t)hp->M.ne * hp->M.V * N;
+  // R_p(u) on both handles (psi coordinates), each on its own stream
+  eg_handle* hh[2] = {hp, hm};
+  for (eg_handle* x : hh) {
+    HIPCHK(hp, eg::launch_basis(x->M, N, u_dev, x->tmp, 0, x->st));
+    HIPCHK(hp, eg::launch_residual(x->M, x->tabs[p], p, x->tmp, nullptr, x->tmp2, eg::PREC_FP64, x->st));
+    HIPCHK(hp, eg::launch_basis(x->M, N, x->tmp2, x->un[p], 2, x->st));
+  }
+  HIPCHK(hp, hipStreamSynchronize(hm->st));
+  // lambda . (R(theta + h) - R(theta - h)) on hp's stream, deterministic sums
+  HIPCHK(hp, eg::launch_sub(hp->un[p], hm->un[p], hp->tmp2, K, hp->st));
+  HIPCHK(hp, eg::launch_sum(hp->tmp2, lam_dev, K, hp->spart, 0, hp->sout, hp->st));
+  HIPCHK(hp, hipMemcpyAsync(hp->hpin + 2, hp->sout, sizeof(double), hipMemcpyDeviceToHost, hp->st));
+  ECHK(sync_status(hp));
+  const double dr = hp->hpin[2];
+  double cdp = 0.0, cdm = 0.0;
+  eg_status st = eg_drag(hp, u_dev, dir_host, sref, &cdp, nullptr);
+  if (st != EG_OK) return st;
+  st = eg_drag(hm, u_dev, dir_host, sref, &cdm, nullptr);
+  if (st != EG_OK) return fail(hp, st, std::string("drag on the theta - h handle: ") + hm->err);
+  *dj_host = (cdp - cdm) / (2.0 * step) + dr / (2.0 * step);
+  return EG_OK;
+}
+
 eg_status eg_adjoint_solve(eg_handle* h, const double* u_dev, const double* g_dev, double* lam_dev, double drop_tol,
                            int max_cycles, double* hist_host, int* n_cycles_host) {
   if (!h || !u_dev || !g_dev || !lam_dev || !hist_host || !n_cycles_host || max_cycles < 0) return EG_ERR_ARG;

@@ -147,3 +147,29 @@ def test_steady_drag_gradient_matches_finite_differences():
         fd[i] = (cp - cm) / (2 * h)
     print("C_D", cd.item(), "adjoint gradient", grad, "FD", fd, flush=True)
     assert np.all(np.abs(grad - fd) <= 1e-5 * np.abs(fd) + 1e-9)
+
+
+def test_param_sensitivity_matches_separate_evaluations():
+    """eg_param_sensitivity (central differences over the theta +- h handles,
+    formed in the library) against the same formula assembled from the
+    library's residual and drag calls, and from the oracle's: the theta
+    derivative at a fixed state of C_D plus lambda . R, theta = Mach."""
+    import paper_1807_01151_amd as P
+    import torch
+    mesh, p, mach, h = ogrid(12, 4), 2, 0.3, 1e-6
+    O = oracle.Oracle(mesh, p, mach=mach)
+    u = perturbed(O, p, 930)
+    lam = np.random.default_rng(931).standard_normal(u.shape)
+    Sp = P.Solver(mesh, p, mach=mach + h)
+    Sm = P.Solver(mesh, p, mach=mach - h)
+    ud, ld = to_dev(u), to_dev(lam)
+    got = Sp.param_sensitivity(Sm, h, ud, ld, direction=(1.0, 0.0))
+    dR = (Sp.residual(p, ud) - Sm.residual(p, ud)) / (2 * h)
+    ref = (Sp.drag(ud, direction=(1.0, 0.0)) - Sm.drag(ud, direction=(1.0, 0.0))) / (2 * h) + float(torch.sum(ld * dR))
+    Op, Om = oracle.Oracle(mesh, p, mach=mach + h), oracle.Oracle(mesh, p, mach=mach - h)
+    orc = ((Op.drag(p, u, (1.0, 0.0)) - Om.drag(p, u, (1.0, 0.0))) / (2 * h)
+           + float(np.sum(lam * (Op.residual(p, u) - Om.residual(p, u)))) / (2 * h))
+    print(f"param sensitivity: library {got:.12e}, separate calls {ref:.12e}, oracle {orc:.12e}", flush=True)
+    assert abs(got - ref) <= 1e-12 * max(abs(ref), 1.0)
+    # central differences of O(1) sums over 2h = 2e-6: rounding of 1e-16 becomes ~1e-10
+    assert abs(got - orc) <= 1e-8 * max(abs(orc), 1.0)
