@@ -21,7 +21,7 @@
 // which the LU with partial pivoting runs in panels of 16 columns:
 //   (a) wavefront 0 factorises the panel in registers (rows in lanes,
 //       largest |a| as the pivot, ties to the lowest row slot, the pivot
-//       row broadcast through LDS), writes it back, records the new logical
+//       row broadcast by lane reads), writes it back, records the new logical
 //       row order (pivot rows first, in pivot order, then the others) and
 //       forms L11^{-1};
 //   (b, c) every wavefront takes a 16-column tile of the trailing part:
@@ -93,6 +93,104 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int kq, int r) { return 4 * kq + r; }
 };
 
+// Panel factorisation of columns kb .. kb + nbk - 1 of the LDS block by one
+// wavefront: the rows of logical positions kb .. n - 1 in its lanes (NS
+// slots of 64, as many as rows remain), the panel in registers.  Pivot: the
+// largest |a| among the unused rows (float keys, ties to the lowest row
+// slot); the pivot row is read out of the winning lane's registers into
+// scalar registers (the slot index is uniform: a scalar branch).  Then the
+// panel is written back, the new logical row order recorded (pivot rows
+// first, in pivot order, then the others in their previous order) and
+// L11^{-1} formed in s_linv (row-major, unit lower triangular, identity past
+// nbk).
+template <int NS, int n, int LDA, class R>
+__device__ __noinline__ void panel_wave(R* A, int* s_prow, R* s_linv, int* fail, int kb, int nbk, int lane) {
+  R pv[NS][16];
+  int prw[NS], used[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int lr = kb + lane + 64 * s;
+    prw[s] = lr < n ? s_prow[lr] : 0;
+    used[s] = lr < n ? -1 : 16;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) pv[s][c] = (lr < n && c < nbk) ? A[(kb + c) * LDA + prw[s]] : R(0);
+  }
+#pragma unroll
+  for (int tt = 0; tt < 16; ++tt) {
+    if (tt < nbk) {
+      unsigned key = 0u;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const unsigned ks = (__float_as_uint((float)fabs(pv[s][tt])) & ~255u) | (unsigned)(255 - (lane + 64 * s));
+        key = max(key, used[s] < 0 ? ks : 0u);
+      }
+      const unsigned kmax = wave_max_u32(key);
+      const int ws = __builtin_amdgcn_readfirstlane(255 - (int)(kmax & 255u));
+      const int wl = ws & 63, wsl = ws >> 6;
+      R pr[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) pr[c] = R(0);
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        if (wsl == s) {
+#pragma unroll
+          for (int c = 0; c < 16; ++c)
+            if (c >= tt) pr[c] = readlane_d(pv[s][c], wl);
+        }
+      if (lane == 0 && !(fabs(pr[tt]) > R(0))) atomicOr(fail, 1);
+      const R ip = R(1) / pr[tt];
+      // rows not used as pivots take multiplier l, the others l = 0 (their
+      // values are then left unchanged by the update)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        if (lane + 64 * s == ws) used[s] = tt;
+        const bool act = used[s] < 0;
+        const R l = act ? pv[s][tt] * ip : R(0);
+        pv[s][tt] = act ? l : pv[s][tt];
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c > tt) pv[s][c] = fma(-l, pr[c], pv[s][c]);
+      }
+    }
+  }
+  int before = 0;  // unused rows in the slots before this one
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int lr = kb + lane + 64 * s;
+    const bool live = lr < n;
+    const bool rest = live && used[s] < 0;
+    const unsigned long long bal = __ballot(rest);
+    const int below = __popcll(bal & ((1ull << lane) - 1ull));
+    if (live) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < nbk) A[(kb + c) * LDA + prw[s]] = pv[s][c];
+      const int pos = rest ? kb + nbk + before + below : kb + used[s];
+      s_prow[pos] = prw[s];
+    }
+    before += __popcll(bal);
+  }
+  // lane j < 16 forms column j of L11^{-1} by forward substitution from the
+  // panel and the row order the other lanes have just written
+  wave_lds_sync();
+  if (lane < 16) {
+    R x[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      R v = (t == lane) ? R(1) : R(0);
+      if (t < nbk) {
+        const int pr = s_prow[kb + t];
+#pragma unroll
+        for (int t2 = 0; t2 < 16; ++t2)
+          if (t2 < t) v = fma(-A[(kb + t2) * LDA + pr], x[t2], v);
+      }
+      x[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) s_linv[t * 16 + lane] = x[t];
+  }
+}
+
 // FP32 blocks take half the LDS, so two workgroups share a compute unit
 // (the serial panel steps of one overlap the other's matrix-core work):
 // four waves per SIMD, 128 registers per lane; FP64: two waves per SIMD.
@@ -110,7 +208,6 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 2) void k_jaclu_lds(const
   R* s_mem = reinterpret_cast<R*>(s_raw);
   __shared__ Tab<D, P, double> t;
   __shared__ int s_prow[n];
-  __shared__ R s_piv[16];         // pivot-row broadcast of the panel step
   __shared__ R s_linv[16 * 16];   // L11^{-1} of the current panel, row-major
   const int e = blockIdx.x;
   if (e >= ne) return;  // whole workgroup
@@ -234,102 +331,17 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 2) void k_jaclu_lds(const
 #pragma unroll 1
   for (int kb = 0; kb < n; kb += 16) {
     const int nbk = min(16, n - kb);
-    // (a) panel factorisation by wavefront 0, then L11^{-1}
+    // (a) panel factorisation by wavefront 0 (with as many row slots as
+    // rows remain), then L11^{-1}
     if (wv == 0) {
-      R pv[RPL][16];
-      int prw[RPL], used[RPL];
-#pragma unroll
-      for (int s = 0; s < RPL; ++s) {
-        const int lr = kb + lane + 64 * s;
-        prw[s] = lr < n ? s_prow[lr] : 0;
-        used[s] = lr < n ? -1 : 16;
-#pragma unroll
-        for (int c = 0; c < 16; ++c) pv[s][c] = (lr < n && c < nbk) ? A[(kb + c) * LDA + prw[s]] : R(0);
-      }
-#pragma unroll
-      for (int tt = 0; tt < 16; ++tt) {
-        if (tt < nbk) {
-          // pivot: largest |a| of the unused rows (float keys, ties to the
-          // lowest row slot; used rows and rows past n have key 0)
-          unsigned key = 0u;
-#pragma unroll
-          for (int s = 0; s < RPL; ++s)
-            if (used[s] < 0)
-              key = max(key, (__float_as_uint((float)fabs(pv[s][tt])) & ~255u) | (unsigned)(255 - (lane + 64 * s)));
-          const unsigned kmax = wave_max_u32(key);
-          const int ws = __builtin_amdgcn_readfirstlane(255 - (int)(kmax & 255u));
-          const int wl = ws & 63, wsl = ws >> 6;
-          // the pivot row goes through LDS once (the winning lane writes it,
-          // every lane reads it back as a broadcast), ordered between the
-          // lanes by wave-scope fences (the previous step's reads before the
-          // write, the write before this step's reads)
-          wave_lds_sync();
-          if (lane == wl) {
-#pragma unroll
-            for (int s = 0; s < RPL; ++s)
-              if (wsl == s) {
-#pragma unroll
-                for (int c = 0; c < 16; ++c)
-                  if (c >= tt) s_piv[c] = pv[s][c];
-              }
-          }
-          wave_lds_sync();
-          R pr[16];
-#pragma unroll
-          for (int c = 0; c < 16; ++c) pr[c] = (c >= tt) ? s_piv[c] : R(0);
-          if (lane == 0 && !(fabs(pr[tt]) > R(0))) atomicOr(fail, 1);
-          const R ip = R(1) / pr[tt];
-          // rows not used as pivots take multiplier l, the others l = 0
-          // (their values are then left unchanged by the update)
-#pragma unroll
-          for (int s = 0; s < RPL; ++s) {
-            if (lane + 64 * s == ws) used[s] = tt;
-            const bool act = used[s] < 0;
-            const R l = act ? pv[s][tt] * ip : R(0);
-            pv[s][tt] = act ? l : pv[s][tt];
-#pragma unroll
-            for (int c = 0; c < 16; ++c)
-              if (c > tt) pv[s][c] = fma(-l, pr[c], pv[s][c]);
-          }
-        }
-      }
-      // write the panel back and the new logical order of rows kb..n-1
-      int before = 0;  // unused rows in the slots before this one
-#pragma unroll
-      for (int s = 0; s < RPL; ++s) {
-        const int lr = kb + lane + 64 * s;
-        const bool live = lr < n;
-        const bool rest = live && used[s] < 0;
-        const unsigned long long bal = __ballot(rest);
-        const int below = __popcll(bal & ((1ull << lane) - 1ull));
-        if (live) {
-#pragma unroll
-          for (int c = 0; c < 16; ++c)
-            if (c < nbk) A[(kb + c) * LDA + prw[s]] = pv[s][c];
-          const int pos = rest ? kb + nbk + before + below : kb + used[s];
-          s_prow[pos] = prw[s];
-        }
-        before += __popcll(bal);
-      }
-      // L11^{-1} (unit lower triangular; identity past nbk), lane j < 16
-      // forms column j by forward substitution from the panel and row order
-      // the other lanes have just written
-      wave_lds_sync();
-      if (lane < 16) {
-        R x[16];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-          R v = (t == lane) ? R(1) : R(0);
-          if (t < nbk) {
-            const int pr = s_prow[kb + t];
-#pragma unroll
-            for (int t2 = 0; t2 < 16; ++t2)
-              if (t2 < t) v = fma(-A[(kb + t2) * LDA + pr], x[t2], v);
-          }
-          x[t] = v;
-        }
-#pragma unroll
-        for (int t = 0; t < 16; ++t) s_linv[t * 16 + lane] = x[t];
+      const int rows = n - kb;
+      if constexpr (RPL >= 3) {
+        if (rows > 128) panel_wave<3, n, LDA>(A, s_prow, s_linv, fail, kb, nbk, lane);
+        else if (rows > 64) panel_wave<2, n, LDA>(A, s_prow, s_linv, fail, kb, nbk, lane);
+        else panel_wave<1, n, LDA>(A, s_prow, s_linv, fail, kb, nbk, lane);
+      } else {
+        if (rows > 64) panel_wave<2, n, LDA>(A, s_prow, s_linv, fail, kb, nbk, lane);
+        else panel_wave<1, n, LDA>(A, s_prow, s_linv, fail, kb, nbk, lane);
       }
     }
     __syncthreads();
