@@ -65,7 +65,7 @@ def work_model(d, p, fp32_blocks=False):
 # device functions behind each timed class, by source file (for the digest
 # that ties a stored counter reading to the code it was taken on)
 CLASS_SOURCES = {
-    "jacobian_lu": [("eg_kernels.hip", ["k_jac_points"]), ("eg_jaclu_lds.hip", ["k_jaclu_lds"])],
+    "jacobian_lu": [("eg_kernels.hip", ["k_jac_points"]), ("eg_jaclu_lds.hip", ["panel_wave", "k_jaclu_lds"])],
     "prk_stage": [("eg_kernels.hip", ["k_prk_stage_c", "k_prk_stage_t", "k_prk_stage"])],
     "residual": [("eg_kernels.hip", ["k_residual"])],
 }

@@ -945,307 +945,6 @@ __global__ __launch_bounds__(256) void k_jaclu_g16(const R* __restrict__ BC, con
 }
 
 // ---------------------------------------------------------------------------
-// The same block assembly and LU for 64 < n = V N < 256, by one block of
-// n / CPW wavefronts per element: wavefront w holds CPW consecutive columns
-// (all of one variable, or a block of its modes) for every row (RPL =
-// ceil(n / 64) rows per lane: lane, lane + 64, ...), so an element's rows
-// are spread over several register files and every register index is a
-// constant.  Elimination step k: the wavefront that holds column k
-// chooses the pivot (largest |a| of the unused rows, float keys with the row
-// in the low 8 bits), forms the multipliers and passes them with the pivot
-// row index to the others through LDS (double-buffered, one block barrier
-// per panel of B steps, below); every wavefront then updates its own
-// columns, the pivot row broadcast by readlane from its own registers.  The
-// step loop is not unrolled (n^2 unrolled steps would not fit the
-// instruction cache); the column sweep of a step is, with uniform branches
-// per column.  Output as k_jaclu_wave.
-// ---------------------------------------------------------------------------
-template <int D, int P>
-constexpr bool jaclu_cols_fits() {
-  using C = Cfg<D, P>;
-  return C::NB > 64 && C::NB < 256;
-}
-
-// Panel width of the column-split LU: the wavefront that holds columns
-// k0 .. k0 + B - 1 eliminates all B of them before the block barrier (B
-// divides N, so a panel never straddles two wavefronts), and the others then
-// apply the B rank-1 updates in the same order: the arithmetic of the
-// unblocked elimination with one barrier per B steps.
-template <int D, int P>
-constexpr int jaclu_cols_panel() {
-  constexpr int N = Cfg<D, P>::N;
-  return (D == 2 && N % 5 == 0) ? 5 : 1;
-}
-
-// Columns per wavefront: the smallest block of one variable's columns (a
-// divisor of N) that keeps the element within 16 wavefronts; more
-// wavefronts per element shorten the elimination's critical path (3D p = 2:
-// 9 columns, 15 wavefronts, measured 1.5x faster than 27 columns in FP32 and
-// free of register spills in FP64; 2D p = 4: all 25 columns, 4 wavefronts).
-template <int D, int P, class R>
-constexpr int jaclu_cols_cpw() {
-  using C = Cfg<D, P>;
-  for (int c = 1; c <= C::N; ++c)
-    if (C::N % c == 0 && C::NB / c <= 16) return c;
-  return C::N;
-}
-
-template <int D, int P, class R>
-constexpr int jaclu_cols_threads() {
-  return 64 * (Cfg<D, P>::NB / jaclu_cols_cpw<D, P, R>());
-}
-
-template <int RPL, class R>
-__device__ __forceinline__ R slot_sel(const R (&x)[RPL], int slot) {
-  R v = x[0];
-#pragma unroll
-  for (int s = 1; s < RPL; ++s) v = (slot == s) ? x[s] : v;
-  return v;
-}
-template <int RPL, int N, class R>
-__device__ __forceinline__ R slot_sel(const R (&x)[RPL][N], int J, int slot) {
-  R v = x[0][J];
-#pragma unroll
-  for (int s = 1; s < RPL; ++s) v = (slot == s) ? x[s][J] : v;
-  return v;
-}
-
-// Apply phase on the wavefront's columns c0 + J >= kb (the columns beyond the
-// panel): the rank-1 update with pivot row slot PS, lane pl; after the last
-// update of the panel (capture) column kb becomes the next pivot column.
-// A wavefront whose columns all lie beyond kb sweeps them without a test
-// per column (the common case); only the one holding column kb tests.
-// Every branch is uniform, so the columns keep their registers.
-template <int PS, int RPL, int N, class R>
-__device__ __forceinline__ void jaclu_cols_apply(R (&acc)[RPL][N], const R (&l)[RPL], R (&col)[RPL], int c0, int kb,
-                                                 int pl, bool capture) {
-  if (c0 >= kb) {
-#pragma unroll
-    for (int J = 0; J < N; ++J) {
-      const R pj = readlane_d(acc[PS][J], pl);
-#pragma unroll
-      for (int s = 0; s < RPL; ++s) acc[s][J] = fma(-l[s], pj, acc[s][J]);
-    }
-    if (capture && c0 == kb) {
-#pragma unroll
-      for (int s = 0; s < RPL; ++s) col[s] = acc[s][0];
-    }
-  } else if (c0 + N > kb) {
-#pragma unroll
-    for (int J = 0; J < N; ++J) {
-      const int c = c0 + J;
-      if (c >= kb) {
-        const R pj = readlane_d(acc[PS][J], pl);
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) acc[s][J] = fma(-l[s], pj, acc[s][J]);
-        if (capture && c == kb) {
-#pragma unroll
-          for (int s = 0; s < RPL; ++s) col[s] = acc[s][J];
-        }
-      }
-    }
-  }
-}
-
-// Panel PI of the owning wavefront (its columns J0 = PI B .. J0 + B - 1,
-// global k0 ..): pivot, multipliers to LDS and to column k, update of the
-// panel's remaining columns, next column as pivot column.
-template <int PI, int B, int RPL, int N, class R>
-__device__ __forceinline__ void jaclu_cols_panel_run(R (&acc)[RPL][N], int (&mystep)[RPL], R (&col)[RPL], int k0,
-                                                     int lane, R* s_lb, int* s_prb, int* fail) {
-  constexpr int J0 = PI * B;
-#pragma unroll
-  for (int t = 0; t < B; ++t) {
-    const int J = J0 + t, k = k0 + t;
-    unsigned key = 0u;
-#pragma unroll
-    for (int s = 0; s < RPL; ++s)
-      if (mystep[s] < 0)
-        key = max(key, (__float_as_uint((float)dabs(col[s])) & ~255u) | (unsigned)(255 - (lane + 64 * s)));
-    const unsigned kmax = wave_max_u32(key);
-    const int pr = __builtin_amdgcn_readfirstlane(255 - (int)(kmax & 255u));
-    const int pl = pr & 63, ps = pr >> 6;
-    const R piv = readlane_d(slot_sel(col, ps), pl);
-    if (lane == 0 && !(dabs(piv) > R(0))) atomicOr(fail, 1);
-    const R ipiv = R(1) / piv;
-    R l[RPL];
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-      const int row = lane + 64 * s;
-      if (row == pr && mystep[s] >= 0) atomicOr(fail, 4);  // the winner must be an unused row
-      l[s] = (mystep[s] < 0 && row != pr) ? col[s] * ipiv : R(0);
-      s_lb[t * 64 * RPL + row] = l[s];
-      if (row == pr) mystep[s] = k;
-      if (mystep[s] < 0) acc[s][J] = l[s];
-    }
-    if (lane == 0) s_prb[t] = pr;
-#pragma unroll
-    for (int J2 = J + 1; J2 < J0 + B; ++J2) {
-      const R pj = readlane_d(slot_sel(acc, J2, ps), pl);
-#pragma unroll
-      for (int s = 0; s < RPL; ++s) acc[s][J2] = fma(-l[s], pj, acc[s][J2]);
-    }
-    if (t + 1 < B) {
-#pragma unroll
-      for (int s = 0; s < RPL; ++s) col[s] = acc[s][J + 1 < N ? J + 1 : J];
-    }
-  }
-}
-
-template <int PI, int B, int RPL, int N, class R>
-__device__ __forceinline__ void jaclu_cols_panel_dispatch(int pi, R (&acc)[RPL][N], int (&mystep)[RPL],
-                                                          R (&col)[RPL], int k0, int lane, R* s_lb, int* s_prb,
-                                                          int* fail) {
-  if constexpr (PI * B < N) {
-    if (pi == PI) jaclu_cols_panel_run<PI, B, RPL, N, R>(acc, mystep, col, k0, lane, s_lb, s_prb, fail);
-    else jaclu_cols_panel_dispatch<PI + 1, B, RPL, N, R>(pi, acc, mystep, col, k0, lane, s_lb, s_prb, fail);
-  }
-}
-
-template <int D, int P, class R>
-__global__ __launch_bounds__((jaclu_cols_threads<D, P, R>()), 2) void k_jaclu_cols(
-    const R* __restrict__ BC, const double* __restrict__ Gpk, int NT, const double* __restrict__ dtau,
-    R* __restrict__ out, int* __restrict__ perm, int* __restrict__ fail, int ne, Tab<D, P, R> tab,
-    const R* __restrict__ gph) {
-  using C = Cfg<D, P>;
-  constexpr int V = C::V, N = C::N, Q = C::Q, QV = C::QV, QF = C::QF, NF = C::NF, n = C::NB;
-  constexpr int RPL = (n + 63) / 64, CPW = jaclu_cols_cpw<D, P, R>(), NTH = jaclu_cols_threads<D, P, R>();
-  static_assert(jaclu_cols_fits<D, P>() && RPL <= 3 && NTH <= 1024, "block size");
-  static_assert(CPW % jaclu_cols_panel<D, P>() == 0, "panels within a wavefront");
-  constexpr int PER = (QV * D + NF * QF) * V * V;
-  __shared__ Tab<D, P, R> t;
-  __shared__ R s_dph[QV * D * N];
-  __shared__ R s_phf[NF * QF * N];
-  __shared__ R s_BC[PER];
-  __shared__ R s_l[2][jaclu_cols_panel<D, P>() * 64 * RPL];
-  __shared__ int s_pr[2][jaclu_cols_panel<D, P>()];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int e = blockIdx.x;
-  if (e >= ne) return;  // whole block
-  copy_tab(t, tab);
-  stage<(PER + NTH - 1) / NTH>(s_BC, BC + (size_t)e * PER, PER, threadIdx.x, NTH);
-  __syncthreads();
-  for (int it = threadIdx.x; it < QV * N; it += NTH) {
-    const int q = it / N, j = it % N;
-    int iq[D], r0 = q;
-#pragma unroll
-    for (int r = 0; r < D; ++r) { iq[r] = r0 % Q; r0 /= Q; }
-#pragma unroll
-    for (int r = 0; r < D; ++r) s_dph[(q * D + r) * N + j] = dphi_vol<D, P, R>(t, j, iq, r);
-  }
-  for (int it = threadIdx.x; it < NF * QF * N; it += NTH) {
-    const int lf = it / (QF * N), k = (it / N) % QF, j = it % N;
-    int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1], r0 = k;
-    face_axes<D>(lf, ta);
-#pragma unroll
-    for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
-    s_phf[it] = phi_face<D, P, R>(t, j, lf, ta, ik);
-  }
-  __syncthreads();
-  const R* sB = s_BC;
-  const R* sC = s_BC + QV * D * V * V;
-  int vv[RPL], ii[RPL];
-#pragma unroll
-  for (int s = 0; s < RPL; ++s) {
-    const int rr = lane + 64 * s < n ? lane + 64 * s : 0;
-    vv[s] = rr / N;
-    ii[s] = rr % N;
-  }
-  // columns c0 + j (variable wvar, modes m0 + j) of every row of the lane
-  const int c0 = wv * CPW, wvar = c0 / N, m0 = c0 % N;
-  R acc[RPL][CPW];
-#pragma unroll
-  for (int s = 0; s < RPL; ++s)
-#pragma unroll
-    for (int j = 0; j < CPW; ++j) acc[s][j] = R(0);
-#pragma unroll 1
-  for (int q = 0; q < QV; ++q) {
-    R bw[RPL];
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-      bw[s] = R(0);
-#pragma unroll
-      for (int r = 0; r < D; ++r) bw[s] += s_dph[(q * D + r) * N + ii[s]] * sB[((q * D + r) * V + vv[s]) * V + wvar];
-    }
-#pragma unroll
-    for (int j = 0; j < CPW; ++j) {
-      const R ph = gph[q * N + m0 + j];  // uniform: a scalar load
-#pragma unroll
-      for (int s = 0; s < RPL; ++s) acc[s][j] += bw[s] * ph;
-    }
-  }
-#pragma unroll 1
-  for (int fk = 0; fk < NF * QF; ++fk) {
-    R cw[RPL];
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) cw[s] = s_phf[fk * N + ii[s]] * sC[(fk * V + vv[s]) * V + wvar];
-#pragma unroll
-    for (int j = 0; j < CPW; ++j) {
-      const R ph = gph[(QV + fk) * N + m0 + j];
-#pragma unroll
-      for (int s = 0; s < RPL; ++s) acc[s][j] -= cw[s] * ph;
-    }
-  }
-  {
-    const R idt = R(1.0 / dtau[e]);
-    const double* G = Gpk + (size_t)e * NT;
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-      const int i = ii[s];
-#pragma unroll
-      for (int j = 0; j < CPW; ++j) {
-        const int jj = m0 + j;
-        const R gij = R((i >= jj) ? G[i * (i + 1) / 2 + jj] : G[jj * (jj + 1) / 2 + i]);
-        acc[s][j] = ((vv[s] == wvar) ? gij * idt : R(0)) - acc[s][j];
-      }
-    }
-  }
-  // LU with partial pivoting over the wavefronts, B columns per barrier
-  constexpr int B = jaclu_cols_panel<D, P>();
-  int mystep[RPL];
-  R col[RPL];
-#pragma unroll
-  for (int s = 0; s < RPL; ++s) {
-    mystep[s] = (lane + 64 * s < n) ? -1 : n;
-    col[s] = acc[s][0];  // column 0 is the first column of wavefront 0
-  }
-#pragma unroll 1
-  for (int k0 = 0; k0 < n; k0 += B) {
-    const int buf = (k0 / B) & 1;
-    if (wv == k0 / CPW)
-      jaclu_cols_panel_dispatch<0, B, RPL, CPW, R>((k0 - c0) / B, acc, mystep, col, k0, lane, &s_l[buf][0],
-                                                   &s_pr[buf][0], fail);
-    __syncthreads();
-#pragma unroll 1
-    for (int t = 0; t < B; ++t) {
-      const int pr = __builtin_amdgcn_readfirstlane(s_pr[buf][t]);
-      const int pl = pr & 63, ps = pr >> 6;
-      R l[RPL];
-#pragma unroll
-      for (int s = 0; s < RPL; ++s) {
-        if (lane + 64 * s == pr) mystep[s] = k0 + t;
-        l[s] = s_l[buf][t * 64 * RPL + lane + 64 * s];
-      }
-      const bool cap = (t == B - 1);
-      if (ps == 0) jaclu_cols_apply<0, RPL, CPW, R>(acc, l, col, c0, k0 + B, pl, cap);
-      else if constexpr (RPL > 1) {
-        if (ps == 1) jaclu_cols_apply<(RPL > 1 ? 1 : 0), RPL, CPW, R>(acc, l, col, c0, k0 + B, pl, cap);
-        else if constexpr (RPL > 2) jaclu_cols_apply<(RPL > 2 ? 2 : 0), RPL, CPW, R>(acc, l, col, c0, k0 + B, pl, cap);
-      }
-    }
-  }
-  R* o = out + (size_t)e * n * n;
-#pragma unroll
-  for (int s = 0; s < RPL; ++s) {
-    if (lane + 64 * s < n) {
-#pragma unroll
-      for (int j = 0; j < CPW; ++j) o[(size_t)(c0 + j) * n + mystep[s]] = acc[s][j];
-      if (wv == 0) perm[(size_t)e * n + mystep[s]] = lane + 64 * s;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // PRK stage (Section 2.3, eq. (prk_scalar)) in phi coordinates:
 //   ut = un + beta Pt^{-1} (rt [+ ft]),
 // one wavefront per element, lane l owning rows l, l+64, ...; forward and
@@ -1422,7 +1121,9 @@ __global__ __launch_bounds__(256) void k_prk_stage_g16(const R* __restrict__ Fm,
 // RPL rows per lane (lane, lane + 64, ...); the factor columns stream
 // through registers in chunks of eight whose loads are all issued before
 // the chunk is used (a loop over single columns would wait for each load in
-// turn), x_j broadcast with readlane.  The chunk loop is not unrolled, which
+// turn), x_j broadcast with readlane.  A column j in row slot sl is read
+// only in the slots the substitution touches (rows >= 64 sl forward,
+// rows < 64 sl + 64 backward).  The chunk loop is not unrolled, which
 // keeps few registers live and many wavefronts per SIMD to cover the load
 // latency.  Same arithmetic and arguments as k_prk_stage.
 template <int NB, class R>
@@ -1458,7 +1159,7 @@ __global__ __launch_bounds__(256) void k_prk_stage_c(const R* __restrict__ Fm, c
       for (int c = 0; c < CH; ++c) {
         const int j = j0 + c < NB ? j0 + c : NB - 1;
 #pragma unroll
-        for (int s = 0; s < RPL; ++s) cf[c][s] = F[(size_t)j * NB + ic[s]];
+        for (int s = sl; s < RPL; ++s) cf[c][s] = F[(size_t)j * NB + ic[s]];
       }
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
@@ -1466,7 +1167,7 @@ __global__ __launch_bounds__(256) void k_prk_stage_c(const R* __restrict__ Fm, c
         if (j < NB) {
           const R xj = readlane_d(b[sl], j & 63);
 #pragma unroll
-          for (int s = 0; s < RPL; ++s) b[s] = fma(-((lane + 64 * s > j) ? cf[c][s] : R(0)), xj, b[s]);
+          for (int s = sl; s < RPL; ++s) b[s] = fma(-((lane + 64 * s > j) ? cf[c][s] : R(0)), xj, b[s]);
         }
       }
     }
@@ -1482,7 +1183,7 @@ __global__ __launch_bounds__(256) void k_prk_stage_c(const R* __restrict__ Fm, c
       for (int c = 0; c < CH; ++c) {
         const int j = j0 + c < NB ? j0 + c : NB - 1;
 #pragma unroll
-        for (int s = 0; s < RPL; ++s) cf[c][s] = F[(size_t)j * NB + ic[s]];
+        for (int s = 0; s <= sl; ++s) cf[c][s] = F[(size_t)j * NB + ic[s]];
       }
 #pragma unroll
       for (int c = CH - 1; c >= 0; --c) {
@@ -1490,7 +1191,7 @@ __global__ __launch_bounds__(256) void k_prk_stage_c(const R* __restrict__ Fm, c
         if (j < NB) {
           const R xj = readlane_d(b[sl], j & 63) / readlane_d(cf[c][sl], j & 63);
 #pragma unroll
-          for (int s = 0; s < RPL; ++s) {
+          for (int s = 0; s <= sl; ++s) {
             const int i = lane + 64 * s;
             b[s] = (i == j) ? xj : fma(-((i < j) ? cf[c][s] : R(0)), xj, b[s]);
           }
@@ -3175,7 +2876,7 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
   R* out = static_cast<R*>(outv);
   const GasT<R> gas = gas_as<R>(M.gas);
   const size_t lds = (size_t)jac_lds_values<D, P>() * sizeof(R);
-  if constexpr (Cfg<D, P>::NB <= 64 || jaclu_cols_fits<D, P>()) {
+  if constexpr (Cfg<D, P>::NB < 256) {
     if (factor && M.bc) {
       using C = Cfg<D, P>;
       constexpr int NPT = C::QV + C::NF * C::QF;
@@ -3193,13 +2894,11 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
         if (!gph) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_jaclu_wave<D, P, R>), dim3((M.ne + 3) / 4), dim3(256), 0, st, bc, M.Gpk, M.NT, dtau,
                            out, perm, fail, M.ne, t, gph);
-      } else if (jaclu_lds_supported(D, P)) {
-        return launch_jaclu_lds(M, td, P, sizeof(R) == 4 ? PREC_FP32 : PREC_FP64, bc, dtau, out, perm, fail, st);
       } else {
-        const R* gph = static_cast<const R*>(M.phitab[P][sizeof(R) == 4 ? PREC_FP32 : PREC_FP64]);
-        if (!gph) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_jaclu_cols<D, P, R>), dim3(M.ne), dim3(jaclu_cols_threads<D, P, R>()), 0, st, bc,
-                           M.Gpk, M.NT, dtau, out, perm, fail, M.ne, t, gph);
+        // 64 < n < 256: the LDS-resident kernel (every such block size that
+        // the residual supports)
+        if (!jaclu_lds_supported(D, P)) return hipErrorInvalidValue;
+        return launch_jaclu_lds(M, td, P, sizeof(R) == 4 ? PREC_FP32 : PREC_FP64, bc, dtau, out, perm, fail, st);
       }
       return hipGetLastError();
     }
@@ -3297,7 +2996,7 @@ hipError_t launch_residual(const DevMesh& M, const TabData& td, int p, const dou
 
 size_t jac_points_per_elem(int d, int p, bool fp32) {
   const int V = d + 2, Q = p + 2, N = (d == 2) ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
-  // blocks that take the register kernels (k_jaclu_wave, k_jaclu_cols)
+  // blocks that take the point-Jacobian kernels (k_jaclu_g16, k_jaclu_wave, k_jaclu_lds)
   (void)fp32;
   if (p < 1 || V * N >= 256) return 0;
   const int QV = (d == 2) ? Q * Q : Q * Q * Q, QF = (d == 2) ? Q : Q * Q;

@@ -12,10 +12,20 @@ namespace eg {
 
 namespace {
 
-// y = x over n double2 values, grid-stride, 16-byte loads and stores.
-__global__ __launch_bounds__(256) void k_peak_copy(const double2* __restrict__ x, double2* __restrict__ y, size_t n) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    y[i] = x[i];
+// y = x over n double2 values, grid-stride, 16-byte non-temporal loads and
+// stores, four loads in flight per thread before the stores.
+typedef double dv2_t __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(256) void k_peak_copy(const dv2_t* __restrict__ x, dv2_t* __restrict__ y, size_t n) {
+  const size_t st = (size_t)gridDim.x * blockDim.x;
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  for (; i + 3 * st < n; i += 4 * st) {
+    dv2_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = __builtin_nontemporal_load(x + i + k * st);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(v[k], y + i + k * st);
+  }
+  for (; i < n; i += st) __builtin_nontemporal_store(__builtin_nontemporal_load(x + i), y + i);
 }
 
 // Eight independent accumulator chains of 16 x 16 x 4 FP64 matrix-core
@@ -81,8 +91,8 @@ hipError_t measure_peak(int kind, hipStream_t st, double* value) {
     if ((e = hipEventRecord(a, st)) != hipSuccess) break;
     for (int r = 0; r < reps; ++r) {
       if (kind == 0)
-        hipLaunchKernelGGL(k_peak_copy, dim3(4 * grid), dim3(256), 0, st, static_cast<const double2*>(x),
-                           static_cast<double2*>(y), bytes / sizeof(double2));
+        hipLaunchKernelGGL(k_peak_copy, dim3(4 * grid), dim3(256), 0, st, static_cast<const dv2_t*>(x),
+                           static_cast<dv2_t*>(y), bytes / sizeof(dv2_t));
       else if (kind == 1)
         hipLaunchKernelGGL(k_peak_mfma64, dim3(grid), dim3(256), 0, st, iters, 1.0, static_cast<double*>(x));
       else
