@@ -65,7 +65,7 @@ typedef struct {
 } eg_mesh;
 
 typedef struct {
-  int p_max;          /* highest order, 0..4 (2D) or 0..2 (3D) */
+  int p_max;          /* highest order, 0..4 (2D) or 0..3 (3D) */
   int rk_stages;      /* s of the PRK smoother (Section 2.3); paper: 4 */
   double cfl_max;     /* upper bound of the CFL ramp (Section 4, eq. (cfl)); paper: 100 */
   int krylov_m;       /* Krylov dimension of EXP1 (Section 5: m = 30), 1..48 */
@@ -297,7 +297,7 @@ eg_status eg_adjoint_apply(eg_handle* h, int p, const double* u_dev, const doubl
  * guess in, solution out.  Stops when the 2-norm of the adjoint residual
  * has dropped by drop_tol; hist_host[0..*n_cycles_host] as for
  * eg_solve_steady.  Orders with a transposed block solve: 2D p <= 3 and 3D
- * p <= 2 (else EG_ERR_UNSUPPORTED).
+ * p <= 3 (else EG_ERR_UNSUPPORTED).
  * Runs in FP64 on every handle.  Synchronises. */
 eg_status eg_adjoint_solve(eg_handle* h, const double* u_dev, const double* g_dev, double* lam_dev, double drop_tol,
                            int max_cycles, double* hist_host, int* n_cycles_host);

@@ -20,6 +20,13 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+// The same for data that may live in global memory: workgroup-scope fences
+// (every earlier store of the wavefront complete before its later loads).
+__device__ __forceinline__ void wave_mem_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 // The numerical flux selected for the handle (uniform over a launch).
 template <int D, class SL, class SR, class S, class R>

@@ -658,7 +658,7 @@ eg_status adj_alloc(eg_handle* h) {
 eg_status adj_supported(eg_handle* h) {
   for (int p = 1; p <= h->pmax; ++p)
     if (!eg::prk_tr_supported(NB(h, p)))
-      return fail(h, EG_ERR_UNSUPPORTED, "adjoint: no transposed block solve for this order (2D p <= 3, 3D p <= 2)");
+      return fail(h, EG_ERR_UNSUPPORTED, "adjoint: no transposed block solve for this order (2D p <= 3, 3D p <= 3)");
   return EG_OK;
 }
 
@@ -760,7 +760,7 @@ struct BatchDef {
 eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, void* hip_stream,
                       const BatchDef* bd) {
   const int d = mesh->dim;
-  const int pmax_lim = (d == 2) ? 4 : 2;
+  const int pmax_lim = (d == 2) ? 4 : 3;
   if (prm->p_max < 0 || prm->p_max > pmax_lim || prm->rk_stages < 1 || prm->krylov_m < 1 || prm->krylov_m > 48 ||
       !(prm->cfl_max > 0.0) || !(prm->gamma > 1.0) || !(prm->mach >= 0.0) ||
       (prm->precision != EG_FP64 && prm->precision != EG_MIXED) ||
@@ -840,13 +840,19 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
   // basis tables of the block assembly, both precisions
   for (int p = 1; p <= h->pmax; ++p) {
     if (!eg::jacobian_supported(d, p)) continue;
-    const size_t cnt = eg::phitab_values(d, p);
+    const bool big = eg::jaclu_big_supported(d, p);  // the global-memory kernel's table
+    const size_t cnt = big ? eg::bigtab_values(d, p) : eg::phitab_values(d, p);
     double* t64 = nullptr;
     float* t32 = nullptr;
     AL(t64, cnt);
     AL(t32, cnt);
-    HIPCHK(h, eg::launch_fill_phitab(M, h->tabs[p], p, eg::PREC_FP64, t64, h->st));
-    HIPCHK(h, eg::launch_fill_phitab(M, h->tabs[p], p, eg::PREC_FP32, t32, h->st));
+    if (big) {
+      HIPCHK(h, eg::launch_fill_bigtab(M, h->tabs[p], p, eg::PREC_FP64, t64, h->st));
+      HIPCHK(h, eg::launch_fill_bigtab(M, h->tabs[p], p, eg::PREC_FP32, t32, h->st));
+    } else {
+      HIPCHK(h, eg::launch_fill_phitab(M, h->tabs[p], p, eg::PREC_FP64, t64, h->st));
+      HIPCHK(h, eg::launch_fill_phitab(M, h->tabs[p], p, eg::PREC_FP32, t32, h->st));
+    }
     M.phitab[p][eg::PREC_FP64] = t64;
     M.phitab[p][eg::PREC_FP32] = t32;
   }

@@ -95,16 +95,21 @@ template <> struct Mfma<float> {
 
 // Panel factorisation of columns kb .. kb + nbk - 1 of the LDS block by one
 // wavefront: the rows of logical positions kb .. n - 1 in its lanes (NS
-// slots of 64, as many as rows remain), the panel in registers.  Pivot: the
-// largest |a| among the unused rows (float keys, ties to the lowest row
-// slot); the pivot row is read out of the winning lane's registers into
+// slots of 64, as many as rows remain), the panel in registers.  A holds
+// the columns from cb on (column c at A + (c - cb) LDA).  Pivot: the largest |a| among the unused rows
+// (float keys with the row slot in the low bits, ties to the lowest slot);
+// the pivot row is read out of the winning lane's registers into
 // scalar registers (the slot index is uniform: a scalar branch).  Then the
 // panel is written back, the new logical row order recorded (pivot rows
 // first, in pivot order, then the others in their previous order) and
 // L11^{-1} formed in s_linv (row-major, unit lower triangular, identity past
 // nbk).
 template <int NS, int n, int LDA, class R>
-__device__ __noinline__ void panel_wave(R* A, int* s_prow, R* s_linv, int* fail, int kb, int nbk, int lane) {
+__device__ __forceinline__ void panel_body(R* A, int cb, int* s_prow, R* s_linv, int* fail, int kb, int nbk,
+                                           int lane) {
+  // the row slot index in the low bits of the key: 8 bits up to n = 256, 9 up to 512
+  constexpr unsigned KM = n <= 256 ? 255u : 511u;
+  static_assert(n <= 512, "row index bits of the pivot key");
   R pv[NS][16];
   int prw[NS], used[NS];
 #pragma unroll
@@ -113,7 +118,7 @@ __device__ __noinline__ void panel_wave(R* A, int* s_prow, R* s_linv, int* fail,
     prw[s] = lr < n ? s_prow[lr] : 0;
     used[s] = lr < n ? -1 : 16;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) pv[s][c] = (lr < n && c < nbk) ? A[(kb + c) * LDA + prw[s]] : R(0);
+    for (int c = 0; c < 16; ++c) pv[s][c] = (lr < n && c < nbk) ? A[(kb + c - cb) * LDA + prw[s]] : R(0);
   }
 #pragma unroll
   for (int tt = 0; tt < 16; ++tt) {
@@ -121,11 +126,11 @@ __device__ __noinline__ void panel_wave(R* A, int* s_prow, R* s_linv, int* fail,
       unsigned key = 0u;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const unsigned ks = (__float_as_uint((float)fabs(pv[s][tt])) & ~255u) | (unsigned)(255 - (lane + 64 * s));
+        const unsigned ks = (__float_as_uint((float)fabs(pv[s][tt])) & ~KM) | (KM - (unsigned)(lane + 64 * s));
         key = max(key, used[s] < 0 ? ks : 0u);
       }
       const unsigned kmax = wave_max_u32(key);
-      const int ws = __builtin_amdgcn_readfirstlane(255 - (int)(kmax & 255u));
+      const int ws = __builtin_amdgcn_readfirstlane((int)(KM - (kmax & KM)));
       const int wl = ws & 63, wsl = ws >> 6;
       R pr[16];
 #pragma unroll
@@ -164,7 +169,7 @@ __device__ __noinline__ void panel_wave(R* A, int* s_prow, R* s_linv, int* fail,
     if (live) {
 #pragma unroll
       for (int c = 0; c < 16; ++c)
-        if (c < nbk) A[(kb + c) * LDA + prw[s]] = pv[s][c];
+        if (c < nbk) A[(kb + c - cb) * LDA + prw[s]] = pv[s][c];
       const int pos = rest ? kb + nbk + before + below : kb + used[s];
       s_prow[pos] = prw[s];
     }
@@ -172,7 +177,7 @@ __device__ __noinline__ void panel_wave(R* A, int* s_prow, R* s_linv, int* fail,
   }
   // lane j < 16 forms column j of L11^{-1} by forward substitution from the
   // panel and the row order the other lanes have just written
-  wave_lds_sync();
+  wave_mem_sync();
   if (lane < 16) {
     R x[16];
 #pragma unroll
@@ -182,13 +187,21 @@ __device__ __noinline__ void panel_wave(R* A, int* s_prow, R* s_linv, int* fail,
         const int pr = s_prow[kb + t];
 #pragma unroll
         for (int t2 = 0; t2 < 16; ++t2)
-          if (t2 < t) v = fma(-A[(kb + t2) * LDA + pr], x[t2], v);
+          if (t2 < t) v = fma(-A[(kb + t2 - cb) * LDA + pr], x[t2], v);
       }
       x[t] = v;
     }
 #pragma unroll
     for (int t = 0; t < 16; ++t) s_linv[t * 16 + lane] = x[t];
   }
+}
+
+// The panel as a called function (one copy per slot count, so that the
+// kernel holds only the live variant's registers).
+template <int NS, int n, int LDA, class R>
+__device__ __noinline__ void panel_wave(R* A, int cb, int* s_prow, R* s_linv, int* fail, int kb, int nbk,
+                                        int lane) {
+  panel_body<NS, n, LDA>(A, cb, s_prow, s_linv, fail, kb, nbk, lane);
 }
 
 // FP32 blocks take half the LDS, so two workgroups share a compute unit
@@ -336,12 +349,12 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 2) void k_jaclu_lds(const
     if (wv == 0) {
       const int rows = n - kb;
       if constexpr (RPL >= 3) {
-        if (rows > 128) panel_wave<3, n, LDA>(A, s_prow, s_linv, fail, kb, nbk, lane);
-        else if (rows > 64) panel_wave<2, n, LDA>(A, s_prow, s_linv, fail, kb, nbk, lane);
-        else panel_wave<1, n, LDA>(A, s_prow, s_linv, fail, kb, nbk, lane);
+        if (rows > 128) panel_wave<3, n, LDA>(A, 0, s_prow, s_linv, fail, kb, nbk, lane);
+        else if (rows > 64) panel_wave<2, n, LDA>(A, 0, s_prow, s_linv, fail, kb, nbk, lane);
+        else panel_wave<1, n, LDA>(A, 0, s_prow, s_linv, fail, kb, nbk, lane);
       } else {
-        if (rows > 64) panel_wave<2, n, LDA>(A, s_prow, s_linv, fail, kb, nbk, lane);
-        else panel_wave<1, n, LDA>(A, s_prow, s_linv, fail, kb, nbk, lane);
+        if (rows > 64) panel_wave<2, n, LDA>(A, 0, s_prow, s_linv, fail, kb, nbk, lane);
+        else panel_wave<1, n, LDA>(A, 0, s_prow, s_linv, fail, kb, nbk, lane);
       }
     }
     __syncthreads();
@@ -435,6 +448,320 @@ hipError_t jaclu_lds_t(const DevMesh& M, const TabData& td, const void* bc, cons
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Element blocks too large for LDS (3D p = 3: n = 320, 819 KB in FP64): the
+// same assembly and LU with the block in global memory (the factor output
+// buffer itself, column-major, rows in their original order until the end).
+//
+// Basis tables of the order (one copy per device, read through the caches
+// by every workgroup; filled once at set-up by k_fill_bigtab with the
+// kernels' own basis formulas):
+//   [QV][D][N] d_r phi_j at the volume points, [QV][N] phi_j there,
+//   [NF QF][N] phi_j at the face points.
+// ---------------------------------------------------------------------------
+template <int D, int P>
+struct BigLu {
+  using C = Cfg<D, P>;
+  static constexpr int V = C::V, N = C::N, QV = C::QV, QF = C::QF, NF = C::NF, n = C::NB;
+  static constexpr int NPF = NF * QF;
+  static constexpr int KSV = (QV + 3) / 4, KSF = (NPF + 3) / 4;  // k-steps of four points (last one padded)
+  static constexpr int NT16 = N / 16;
+  static constexpr int NW = 8, JR = 2;                            // wavefronts; jobs per wavefront and round
+  static constexpr int JOBS = V * V * NT16;
+  static constexpr int ROUNDS = (JOBS + NW * JR - 1) / (NW * JR);
+  static constexpr int PER = (QV * D + NPF) * V * V;              // pointwise Jacobian values per element
+  static constexpr int TAB_D = 0, TAB_V = QV * D * N, TAB_F = TAB_V + QV * N, TAB = TAB_F + NPF * N;
+  static constexpr int RPL = (n + 63) / 64;
+  static_assert(N % 16 == 0 && n % 16 == 0 && n <= 320, "tiles of 16; at most five row slots");
+};
+
+template <int D, int P, class R>
+constexpr size_t jaclu_big_lds_values() {
+  using L = BigLu<D, P>;
+  return (size_t)(L::PER > L::NW * L::n ? L::PER : L::NW * L::n);
+}
+
+template <int D, int P, class R>
+__global__ __launch_bounds__(256) void k_fill_bigtab(R* __restrict__ out, Tab<D, P, double> tab) {
+  using L = BigLu<D, P>;
+  constexpr int N = L::N, Q = Cfg<D, P>::Q, QV = L::QV, QF = L::QF;
+  __shared__ Tab<D, P, double> t;
+  copy_tab(t, tab);
+  __syncthreads();
+  for (int it = threadIdx.x + blockIdx.x * blockDim.x; it < L::TAB; it += blockDim.x * gridDim.x) {
+    if (it < L::TAB_V) {
+      const int q = it / (D * N), r = (it / N) % D, j = it % N;
+      int iq[D], r0 = q;
+#pragma unroll
+      for (int a = 0; a < D; ++a) { iq[a] = r0 % Q; r0 /= Q; }
+      out[it] = R(dphi_vol<D, P, double>(t, j, iq, r));
+    } else if (it < L::TAB_F) {
+      const int q = (it - L::TAB_V) / N, j = it % N;
+      int iq[D], r0 = q;
+#pragma unroll
+      for (int a = 0; a < D; ++a) { iq[a] = r0 % Q; r0 /= Q; }
+      out[it] = R(phi_vol<D, P, double>(t, j, iq));
+    } else {
+      const int f = it - L::TAB_F;
+      const int lf = f / (QF * N), k = (f / N) % QF, j = f % N;
+      int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1], r0 = k;
+      face_axes<D>(lf, ta);
+#pragma unroll
+      for (int a = 0; a < D - 1; ++a) { ik[a] = r0 % Q; r0 /= Q; }
+      out[it] = R(phi_face<D, P, double>(t, j, lf, ta, ik));
+    }
+  }
+}
+
+template <int NT, class R>
+__device__ __forceinline__ R sel_tile(const R (&x)[NT], int i) {
+  R v = x[0];
+#pragma unroll
+  for (int c = 1; c < NT; ++c) v = (i == c) ? x[c] : v;
+  return v;
+}
+
+// One workgroup (eight wavefronts) per element.
+// Assembly: the element's pointwise Jacobians in LDS; jobs (v, w, 16-row
+// tile) in rounds of two per wavefront, each accumulating its N/16 output
+// tiles over the volume and face points on the 16 x 16 x 4 matrix-core
+// instruction (operands as in k_jaclu_lds, basis values from the device
+// table), then written to global memory: Pt = G/dtau - Dt (factor) or Dt
+// itself (row-major, the unfactored element block).
+// LU with partial pivoting in panels of 16 columns, as k_jaclu_lds: (a) the
+// panel is copied to LDS, wavefront 0 factorises it there (panel_wave) and
+// it is copied back, (b) U12 = L11^{-1} A12 per 16-column tile on the
+// matrix cores, (c) A22 -= L21 U12 per 16 x 16 tile (L21 from the LDS
+// panel), the tiles spread over the wavefronts.  Finally every column is permuted
+// into pivot order through LDS.
+template <int D, int P, class R>
+__global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 2) void k_jaclu_big(
+    const R* __restrict__ BC, const R* __restrict__ gtab, const double* __restrict__ Gpk, int NT,
+    const double* __restrict__ dtau, R* __restrict__ out, int* __restrict__ perm, int* __restrict__ fail, int ne,
+    int factor) {
+  using L = BigLu<D, P>;
+  using MF = Mfma<R>;
+  using acc_t = typename MF::acc;
+  constexpr int V = L::V, N = L::N, QV = L::QV, NPF = L::NPF, n = L::n, NW = L::NW, JR = L::JR, NT16 = L::NT16;
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  R* s_mem = reinterpret_cast<R*>(s_raw);
+  __shared__ int s_prow[n];
+  __shared__ R s_linv[16 * 16];
+  const int e = blockIdx.x;
+  if (e >= ne) return;  // whole workgroup
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int il = lane & 15, kq = lane >> 4;
+  R* A = out + (size_t)e * n * n;
+  const R* s_B = s_mem;                       // [QV][D][V][V]
+  const R* s_C = s_mem + QV * D * V * V;      // [NPF][V][V]
+  const R* tdp = gtab + L::TAB_D;
+  const R* tph = gtab + L::TAB_V;
+  const R* tpf = gtab + L::TAB_F;
+
+  stage<(L::PER + 511) / 512>(s_mem, BC + (size_t)e * L::PER, L::PER, tid, 512);
+  for (int k = tid; k < n; k += 512) s_prow[k] = k;
+  __syncthreads();
+
+  // ---- assembly
+  const double idt = 1.0 / dtau[e];
+  const double* G = Gpk + (size_t)e * NT;
+#pragma unroll 1
+  for (int rd = 0; rd < L::ROUNDS; ++rd) {
+    int jv[JR], jw[JR], jt[JR];
+    bool jon[JR];
+#pragma unroll
+    for (int jj = 0; jj < JR; ++jj) {
+      const int job = (rd * NW + wv) * JR + jj;
+      jon[jj] = job < L::JOBS;
+      const int jb = jon[jj] ? job : 0;
+      jt[jj] = jb % NT16;
+      jv[jj] = (jb / NT16) / V;
+      jw[jj] = (jb / NT16) % V;
+    }
+    if (!jon[0]) continue;  // uniform over the wavefront
+    acc_t acc[JR][NT16];
+#pragma unroll
+    for (int jj = 0; jj < JR; ++jj)
+#pragma unroll
+      for (int c = 0; c < NT16; ++c) acc[jj][c] = acc_t{R(0), R(0), R(0), R(0)};
+#pragma unroll 2
+    for (int ks = 0; ks < L::KSV; ++ks) {
+      const int q = 4 * ks + kq;
+      const bool qv = q < QV;
+      const int qc = qv ? q : QV - 1;
+      R bf[NT16];
+#pragma unroll
+      for (int c = 0; c < NT16; ++c) bf[c] = qv ? tph[qc * N + 16 * c + il] : R(0);
+#pragma unroll
+      for (int jj = 0; jj < JR; ++jj) {
+        if (jon[jj]) {
+          R a = R(0);
+#pragma unroll
+          for (int r = 0; r < D; ++r)
+            a = fma(tdp[(qc * D + r) * N + 16 * jt[jj] + il], s_B[((qc * D + r) * V + jv[jj]) * V + jw[jj]], a);
+          a = qv ? a : R(0);
+#pragma unroll
+          for (int c = 0; c < NT16; ++c) acc[jj][c] = MF::run(a, bf[c], acc[jj][c]);
+        }
+      }
+    }
+#pragma unroll 2
+    for (int ks = 0; ks < L::KSF; ++ks) {
+      const int fk = 4 * ks + kq;
+      const bool fv = fk < NPF;
+      const int fc = fv ? fk : NPF - 1;
+      R bf[NT16];
+#pragma unroll
+      for (int c = 0; c < NT16; ++c) bf[c] = fv ? tpf[fc * N + 16 * c + il] : R(0);
+#pragma unroll
+      for (int jj = 0; jj < JR; ++jj) {
+        if (jon[jj]) {
+          const R a = -sel_tile(bf, jt[jj]) * s_C[(fc * V + jv[jj]) * V + jw[jj]];
+#pragma unroll
+          for (int c = 0; c < NT16; ++c) acc[jj][c] = MF::run(a, bf[c], acc[jj][c]);
+        }
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < JR; ++jj) {
+      if (!jon[jj]) continue;
+#pragma unroll
+      for (int c = 0; c < NT16; ++c) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * jt[jj] + MF::row(kq, r), j = 16 * c + il;
+          if (factor) {
+            R g = R(0);
+            if (jv[jj] == jw[jj]) g = R(((i >= j) ? G[i * (i + 1) / 2 + j] : G[j * (j + 1) / 2 + i]) * idt);
+            A[(size_t)(jw[jj] * N + j) * n + jv[jj] * N + i] = g - acc[jj][c][r];
+          } else {
+            A[(size_t)(jv[jj] * N + i) * n + jw[jj] * N + j] = acc[jj][c][r];
+          }
+        }
+      }
+    }
+  }
+  if (!factor) return;  // uniform
+  __syncthreads();  // the block is complete (global memory, one workgroup)
+
+  // ---- LU with partial pivoting, panels of 16 columns
+  R* s_pan = s_mem;  // the current panel, [16][n] (rows in their original order)
+#pragma unroll 1
+  for (int kb = 0; kb < n; kb += 16) {
+    for (int it = tid; it < 16 * n; it += 512) s_pan[it] = A[(size_t)kb * n + it];
+    __syncthreads();
+    if (wv == 0) {
+      const int rows = n - kb;
+      if (rows > 256) panel_wave<5, n, n>(s_pan, kb, s_prow, s_linv, fail, kb, 16, lane);
+      else if (rows > 192) panel_wave<4, n, n>(s_pan, kb, s_prow, s_linv, fail, kb, 16, lane);
+      else if (rows > 128) panel_wave<3, n, n>(s_pan, kb, s_prow, s_linv, fail, kb, 16, lane);
+      else if (rows > 64) panel_wave<2, n, n>(s_pan, kb, s_prow, s_linv, fail, kb, 16, lane);
+      else panel_wave<1, n, n>(s_pan, kb, s_prow, s_linv, fail, kb, 16, lane);
+    }
+    __syncthreads();
+    for (int it = tid; it < 16 * n; it += 512) A[(size_t)kb * n + it] = s_pan[it];
+    const int k1 = kb + 16, m = n - k1;
+    if (m <= 0) break;
+    const int T = m / 16;
+    // (b) U12 = L11^{-1} A12, one 16-column tile per wavefront at a time
+#pragma unroll 1
+    for (int tj = wv; tj < T; tj += NW) {
+      const int cc = k1 + 16 * tj + il;
+      acc_t u = acc_t{R(0), R(0), R(0), R(0)};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = 4 * s4 + kq;
+        u = MF::run(s_linv[il * 16 + k], A[(size_t)cc * n + s_prow[kb + k]], u);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) A[(size_t)cc * n + s_prow[kb + MF::row(kq, r)]] = u[r];
+    }
+    __syncthreads();
+    // (c) A22 -= L21 U12 over the T x T tiles, two per wavefront at a time
+    // with every load issued before the products
+#pragma unroll 1
+    for (int it0 = 2 * wv; it0 < T * T; it0 += 2 * NW) {
+      acc_t c2[2];
+      R a2[2][4], b2[2][4];
+      int crow[2][4], ccol[2];
+      bool on[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int it = it0 + h;
+        on[h] = it < T * T;
+        const int ti = on[h] ? it / T : 0, tj = on[h] ? it % T : 0;
+        ccol[h] = k1 + 16 * tj + il;
+        const int arow = s_prow[k1 + 16 * ti + il];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          crow[h][r] = s_prow[k1 + 16 * ti + MF::row(kq, r)];
+          c2[h][r] = A[(size_t)ccol[h] * n + crow[h][r]];
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int k = 4 * s4 + kq;
+          a2[h][s4] = -s_pan[k * n + arow];
+          b2[h][s4] = A[(size_t)ccol[h] * n + s_prow[kb + k]];
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) c2[h] = MF::run(a2[h][s4], b2[h][s4], c2[h]);
+        if (on[h]) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) A[(size_t)ccol[h] * n + crow[h][r]] = c2[h][r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  __syncthreads();  // the last panel's copy-back is complete; LDS is reused below
+
+  // ---- factors in pivot order: each column through LDS (one wavefront per
+  // column; its reads of the column complete before its writes)
+  R* s_col = s_mem + wv * n;
+#pragma unroll 1
+  for (int col = wv; col < n; col += NW) {
+    R* cp = A + (size_t)col * n;
+#pragma unroll
+    for (int s = 0; s < L::RPL; ++s)
+      if (lane + 64 * s < n) s_col[lane + 64 * s] = cp[lane + 64 * s];
+    wave_lds_sync();
+#pragma unroll
+    for (int s = 0; s < L::RPL; ++s)
+      if (lane + 64 * s < n) cp[lane + 64 * s] = s_col[s_prow[lane + 64 * s]];
+    wave_lds_sync();
+  }
+  for (int k = tid; k < n; k += 512) perm[(size_t)e * n + k] = s_prow[k];
+}
+
+template <int D, int P, class R>
+hipError_t jaclu_big_t(const DevMesh& M, const void* bc, const void* tab, const double* dtau, void* out, int* perm,
+                       int* fail, bool factor, hipStream_t st) {
+  const size_t lds = jaclu_big_lds_values<D, P, R>() * sizeof(R);
+  static bool attr = false;  // set once: not a stream operation, so also fine while capturing
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_jaclu_big<D, P, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_jaclu_big<D, P, R>), dim3(M.ne), dim3(512), lds, st, static_cast<const R*>(bc),
+                     static_cast<const R*>(tab), M.Gpk, M.NT, dtau, static_cast<R*>(out), perm, fail, M.ne,
+                     factor ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int D, int P, class R>
+hipError_t fill_bigtab_t(const TabData& td, void* dst, hipStream_t st) {
+  Tab<D, P, double> t;
+  fill_tab(t, td);
+  hipLaunchKernelGGL((k_fill_bigtab<D, P, R>), dim3(64), dim3(256), 0, st, static_cast<R*>(dst), t);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 bool jaclu_lds_supported(int d, int p) { return (d == 2 && p == 4) || (d == 3 && p == 2); }
@@ -448,6 +775,28 @@ hipError_t launch_jaclu_lds(const DevMesh& M, const TabData& td, int p, int prec
   if (M.d == 3 && p == 2)
     return f32 ? jaclu_lds_t<3, 2, float>(M, td, bc, dtau, out, perm, fail, st)
                : jaclu_lds_t<3, 2, double>(M, td, bc, dtau, out, perm, fail, st);
+  return hipErrorInvalidValue;
+}
+
+bool jaclu_big_supported(int d, int p) { return d == 3 && p == 3; }
+
+size_t bigtab_values(int d, int p) {
+  if (d == 3 && p == 3) return (size_t)BigLu<3, 3>::TAB;
+  return 0;
+}
+
+hipError_t launch_fill_bigtab(const DevMesh& M, const TabData& td, int p, int prec, void* dst, hipStream_t st) {
+  if (M.d == 3 && p == 3)
+    return prec == PREC_FP32 ? fill_bigtab_t<3, 3, float>(td, dst, st) : fill_bigtab_t<3, 3, double>(td, dst, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_jaclu_big(const DevMesh& M, int p, int prec, const void* bc, const void* tab, const double* dtau,
+                            void* out, int* perm, int* fail, bool factor, hipStream_t st) {
+  if (!tab) return hipErrorInvalidValue;
+  if (M.d == 3 && p == 3)
+    return prec == PREC_FP32 ? jaclu_big_t<3, 3, float>(M, bc, tab, dtau, out, perm, fail, factor, st)
+                             : jaclu_big_t<3, 3, double>(M, bc, tab, dtau, out, perm, fail, factor, st);
   return hipErrorInvalidValue;
 }
 

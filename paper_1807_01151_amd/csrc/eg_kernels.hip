@@ -1117,7 +1117,7 @@ __global__ __launch_bounds__(256) void k_prk_stage_g16(const R* __restrict__ Fm,
   }
 }
 
-// PRK stage for block sizes 64 < NB < 256: one wavefront per element with
+// PRK stage for block sizes 64 < NB <= 320: one wavefront per element with
 // RPL rows per lane (lane, lane + 64, ...); the factor columns stream
 // through registers in chunks of eight whose loads are all issued before
 // the chunk is used (a loop over single columns would wait for each load in
@@ -1132,7 +1132,7 @@ __global__ __launch_bounds__(256) void k_prk_stage_c(const R* __restrict__ Fm, c
                                                      double* __restrict__ ut, double* __restrict__ save, double beta,
                                                      int ne) {
   constexpr int RPL = (NB + 63) / 64, CH = 8;
-  static_assert(NB > 64 && NB < 256, "rows per lane");
+  static_assert(NB > 64 && NB <= 320, "rows per lane");
   const int lane = threadIdx.x & 63;
   const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (e >= ne) return;
@@ -2649,16 +2649,17 @@ __global__ __launch_bounds__(256) void k_prk_stage_tr(const double* __restrict__
   }
 }
 
-// Transposed PRK stage for 64 < NB < 256: lanes hold columns lane, lane +
+// Transposed PRK stage for 64 < NB <= 320: lanes hold columns lane, lane +
 // 64, ... of the factor, whose elements stream through registers in chunks
-// of eight (loads of a chunk issued together); x_k broadcast by readlane from
-// the lane of column k.  Same arithmetic as k_prk_stage_tr.
+// of eight (loads of a chunk issued together; only the column slots the
+// substitution touches); x_k broadcast by readlane from the lane of column
+// k.  Same arithmetic as k_prk_stage_tr.
 template <int NB>
 __global__ __launch_bounds__(256) void k_prk_stage_trc(const double* __restrict__ Fm, const int* __restrict__ perm,
                                                        const double* __restrict__ rt, const double* __restrict__ un,
                                                        double* __restrict__ ut, double beta, int ne) {
   constexpr int RPL = (NB + 63) / 64, CH = 8;
-  static_assert(NB > 64 && NB < 256, "columns per lane");
+  static_assert(NB > 64 && NB <= 320, "columns per lane");
   const int lane = threadIdx.x & 63;
   const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (e >= ne) return;
@@ -2681,7 +2682,7 @@ __global__ __launch_bounds__(256) void k_prk_stage_trc(const double* __restrict_
       for (int c = 0; c < CH; ++c) {
         const int k = k0 + c < NB ? k0 + c : NB - 1;
 #pragma unroll
-        for (int s = 0; s < RPL; ++s) cf[c][s] = F[(size_t)lc[s] * NB + k];
+        for (int s = sl; s < RPL; ++s) cf[c][s] = F[(size_t)lc[s] * NB + k];
       }
 #pragma unroll
       for (int c = 0; c < CH; ++c) {
@@ -2689,7 +2690,7 @@ __global__ __launch_bounds__(256) void k_prk_stage_trc(const double* __restrict_
         if (k < NB) {
           const double zk = readlane_d(b[sl], k & 63) / readlane_d(cf[c][sl], k & 63);
 #pragma unroll
-          for (int s = 0; s < RPL; ++s) {
+          for (int s = sl; s < RPL; ++s) {
             const int l = lane + 64 * s;
             b[s] = (l == k) ? zk : fma(-((l > k) ? cf[c][s] : 0.0), zk, b[s]);
           }
@@ -2708,7 +2709,7 @@ __global__ __launch_bounds__(256) void k_prk_stage_trc(const double* __restrict_
       for (int c = 0; c < CH; ++c) {
         const int k = k0 + c < NB ? k0 + c : NB - 1;
 #pragma unroll
-        for (int s = 0; s < RPL; ++s) cf[c][s] = F[(size_t)lc[s] * NB + k];
+        for (int s = 0; s <= sl; ++s) cf[c][s] = F[(size_t)lc[s] * NB + k];
       }
 #pragma unroll
       for (int c = CH - 1; c >= 0; --c) {
@@ -2716,7 +2717,7 @@ __global__ __launch_bounds__(256) void k_prk_stage_trc(const double* __restrict_
         if (k < NB) {
           const double yk = readlane_d(b[sl], k & 63);
 #pragma unroll
-          for (int s = 0; s < RPL; ++s) b[s] = fma(-((lane + 64 * s < k) ? cf[c][s] : 0.0), yk, b[s]);
+          for (int s = 0; s <= sl; ++s) b[s] = fma(-((lane + 64 * s < k) ? cf[c][s] : 0.0), yk, b[s]);
         }
       }
     }
@@ -2875,7 +2876,6 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
   fill_tab(t, td);
   R* out = static_cast<R*>(outv);
   const GasT<R> gas = gas_as<R>(M.gas);
-  const size_t lds = (size_t)jac_lds_values<D, P>() * sizeof(R);
   if constexpr (Cfg<D, P>::NB < 256) {
     if (factor && M.bc) {
       using C = Cfg<D, P>;
@@ -2902,29 +2902,46 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
       }
       return hipGetLastError();
     }
-  }
-  if (factor) {
-    auto kf = k_jacobian<D, P, true, R>;
-    static bool attr = false;  // set once: not a stream operation, so also fine while capturing
-    if (!attr) {
-      hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-      attr = true;
-    }
-    hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
-                       fail, M.ne, t, gas, M.uinf_e);
   } else {
-    auto kf = k_jacobian<D, P, false, R>;
-    static bool attr = false;
-    if (!attr) {
-      hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-      attr = true;
-    }
-    hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
-                       fail, M.ne, t, gas, M.uinf_e);
+    // n >= 256 (3D p = 3): point Jacobians, then assembly (and LU) with the
+    // block in global memory, factored or not
+    if (!M.bc || !jaclu_big_supported(D, P)) return hipErrorInvalidValue;
+    using C = Cfg<D, P>;
+    constexpr int NPT = C::QV + C::NF * C::QF;
+    const int items = M.ne * NPT;
+    R* bc = static_cast<R*>(M.bc);
+    hipLaunchKernelGGL((k_jac_points<D, P, R>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.nbr,
+                       M.ncode, bc, M.ne, t, gas, M.uinf_e);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_jaclu_big(M, P, sizeof(R) == 4 ? PREC_FP32 : PREC_FP64, bc,
+                            M.phitab[P][sizeof(R) == 4 ? PREC_FP32 : PREC_FP64], dtau, out, perm, fail, factor, st);
   }
-  return hipGetLastError();
+  if constexpr (Cfg<D, P>::NB < 256) {
+    const size_t lds = (size_t)jac_lds_values<D, P>() * sizeof(R);
+    if (factor) {
+      auto kf = k_jacobian<D, P, true, R>;
+      static bool attr = false;  // set once: not a stream operation, so also fine while capturing
+      if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+      }
+      hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
+                         fail, M.ne, t, gas, M.uinf_e);
+    } else {
+      auto kf = k_jacobian<D, P, false, R>;
+      static bool attr = false;
+      if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+      }
+      hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
+                         fail, M.ne, t, gas, M.uinf_e);
+    }
+    return hipGetLastError();
+  }
 }
 
 template <int N>
@@ -2996,9 +3013,10 @@ hipError_t launch_residual(const DevMesh& M, const TabData& td, int p, const dou
 
 size_t jac_points_per_elem(int d, int p, bool fp32) {
   const int V = d + 2, Q = p + 2, N = (d == 2) ? (p + 1) * (p + 1) : (p + 1) * (p + 1) * (p + 1);
-  // blocks that take the point-Jacobian kernels (k_jaclu_g16, k_jaclu_wave, k_jaclu_lds)
+  // blocks that take the point-Jacobian kernels (k_jaclu_g16, k_jaclu_wave,
+  // k_jaclu_lds, k_jaclu_big)
   (void)fp32;
-  if (p < 1 || V * N >= 256) return 0;
+  if (p < 1 || V * N > 320) return 0;
   const int QV = (d == 2) ? Q * Q : Q * Q * Q, QF = (d == 2) ? Q : Q * Q;
   return (size_t)(QV * d + 2 * d * QF) * V * V;
 }
@@ -3006,7 +3024,7 @@ size_t jac_points_per_elem(int d, int p, bool fp32) {
 bool jacobian_supported(int d, int p) {
   if (p < 1) return false;
   if (d == 2) return p <= 4;
-  return p <= 2;
+  return p <= 3;
 }
 
 template <class R>
@@ -3025,6 +3043,7 @@ static hipError_t launch_jacobian_r(const DevMesh& M, const TabData& td, int p, 
     switch (p) {
       case 1: return CALL_JAC(3, 1);
       case 2: return CALL_JAC(3, 2);
+      case 3: return CALL_JAC(3, 3);
       default: break;
     }
   }
@@ -3052,6 +3071,7 @@ static hipError_t launch_prk_stage_r(const DevMesh& M, int n, const R* F, const 
       case 40: hipLaunchKernelGGL((k_prk_stage_t<40, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
       case 100: hipLaunchKernelGGL((k_prk_stage_c<100, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
       case 135: hipLaunchKernelGGL((k_prk_stage_c<135, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
+      case 320: hipLaunchKernelGGL((k_prk_stage_c<320, R>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, save, beta, M.ne); return hipGetLastError();
       default: break;
     }
   }
@@ -3300,6 +3320,7 @@ hipError_t launch_jac_to_psi(const DevMesh& M, int N, double* Dm, hipStream_t st
     case 16: return jac_to_psi_t<16>(M, Dm, st);
     case 25: return jac_to_psi_t<25>(M, Dm, st);
     case 27: return jac_to_psi_t<27>(M, Dm, st);
+    case 64: return jac_to_psi_t<64>(M, Dm, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -3434,6 +3455,7 @@ hipError_t launch_jac_points(const DevMesh& M, const TabData& td, int p, const d
     switch (p) {
       case 1: return CALL_JP(3, 1);
       case 2: return CALL_JP(3, 2);
+      case 3: return CALL_JP(3, 3);
       default: break;
     }
   }
@@ -3456,6 +3478,7 @@ hipError_t launch_adj_residual(const DevMesh& M, const TabData& td, int p, const
     switch (p) {
       case 1: return CALL_AR(3, 1);
       case 2: return CALL_AR(3, 2);
+      case 3: return CALL_AR(3, 3);
       default: break;
     }
   }
@@ -3476,7 +3499,7 @@ hipError_t launch_drag(const DevMesh& M, const TabData& td, int p, const double*
 // state tried, with the transposed kernel checked by a CPU emulation of its
 // loops and (dR/du)^T w equal to the oracle's at every level; the cause is
 // not established.
-bool prk_tr_supported(int n) { return n == 16 || n == 36 || n == 64 || n == 40 || n == 135; }
+bool prk_tr_supported(int n) { return n == 16 || n == 36 || n == 64 || n == 40 || n == 135 || n == 320; }
 
 hipError_t launch_prk_stage_tr(const DevMesh& M, int n, const double* F, const int* perm, const double* rt,
                                const double* un, double* ut, double beta, hipStream_t st) {
@@ -3486,6 +3509,7 @@ hipError_t launch_prk_stage_tr(const DevMesh& M, int n, const double* F, const i
     case 36: hipLaunchKernelGGL((k_prk_stage_tr<36>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
     case 40: hipLaunchKernelGGL((k_prk_stage_tr<40>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
     case 135: hipLaunchKernelGGL((k_prk_stage_trc<135>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
+    case 320: hipLaunchKernelGGL((k_prk_stage_trc<320>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
     case 64: hipLaunchKernelGGL((k_prk_stage_tr<64>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
     default: return hipErrorInvalidValue;
   }

@@ -27,7 +27,9 @@ struct DevMesh {
   double* g2w = nullptr;
   void* bc = nullptr;      // pointwise flux-Jacobian scratch of the block assembly (FP64 or FP32)
   // per order and precision: phi at the volume points [QV][N], then at the
-  // face points [NF QF][N] (the shared operands of the block assembly)
+  // face points [NF QF][N] (the shared operands of the block assembly); for
+  // 3D p = 3 the global-memory kernel's table (bigtab_values(3, 3) values:
+  // d phi and phi at the volume points, phi at the face points)
   const void* phitab[5][2] = {};
   // residual tile per order and precision (FP64, FP32): index of the
   // candidate (0: half, 1: default, 2: 1.5 x the default), set by eg_autotune
@@ -80,6 +82,15 @@ bool jacobian_supported(int d, int p);
 // (eg_jaclu_lds.hip) for 2D p = 4 and 3D p = 2, FP64 or FP32 (prec); bc
 // from k_jac_points in the same precision, out FP64 or FP32 factors.
 bool jaclu_lds_supported(int d, int p);
+// Block assembly and LU with the block in global memory (eg_jaclu_lds.hip)
+// for 3D p = 3 (n = 320), FP64 or FP32 (prec); bc the point Jacobians of
+// k_jac_points, tab the order's basis table (launch_fill_bigtab); factor =
+// false writes the unfactored element block Dt row-major instead.
+bool jaclu_big_supported(int d, int p);
+size_t bigtab_values(int d, int p);
+hipError_t launch_fill_bigtab(const DevMesh& M, const TabData& td, int p, int prec, void* dst, hipStream_t st);
+hipError_t launch_jaclu_big(const DevMesh& M, int p, int prec, const void* bc, const void* tab, const double* dtau,
+                            void* out, int* perm, int* fail, bool factor, hipStream_t st);
 hipError_t launch_jaclu_lds(const DevMesh& M, const TabData& td, int p, int prec, const void* bc, const double* dtau,
                             void* out, int* perm, int* fail, hipStream_t st);
 hipError_t launch_jacobian(const DevMesh& M, const TabData& td, int p, const double* ut, const double* dtau,

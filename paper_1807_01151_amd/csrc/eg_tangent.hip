@@ -193,6 +193,7 @@ hipError_t launch_tangent(const DevMesh& M, const TabData& td, int p, const doub
       case 0: return tangent_t<3, 0>(M, td, ut, vt, jv, st);
       case 1: return tangent_t<3, 1>(M, td, ut, vt, jv, st);
       case 2: return tangent_t<3, 2>(M, td, ut, vt, jv, st);
+      case 3: return tangent_t<3, 3>(M, td, ut, vt, jv, st);
       default: break;
     }
   }

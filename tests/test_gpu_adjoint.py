@@ -27,6 +27,7 @@ CASES = [
     ("sphere6x2x2x2-p1", cubed_sphere_shell(2, 2), 1, 2.0),
     ("ogrid10x3-p4", ogrid(10, 3), 4, 1.0),
     ("sphere6x2x2x2-p2", cubed_sphere_shell(2, 2), 2, -1.0),
+    ("sphere6x2x2x2-p3", cubed_sphere_shell(2, 2), 3, 1.0),
 ]
 
 
@@ -91,8 +92,8 @@ def test_adjoint_solve_parity(c1_steady):
 
 @pytest.mark.parametrize("name,mesh,p,alpha", CASES[4:], ids=[c[0] for c in CASES[4:]])
 def test_adjoint_solve_large_blocks(name, mesh, p, alpha):
-    """Adjoint V-cycles with the 135 x 135 blocks of 3D p = 2 at a perturbed
-    state: the adjoint problem is linear in lambda, so its residual
+    """Adjoint V-cycles with the 135 x 135 and 320 x 320 blocks of 3D p = 2
+    and 3 at a perturbed state: the adjoint problem is linear in lambda, so its residual
     (dR/du)^T lambda + dC_D/du, with the oracle's assembled Jacobian, is
     checked directly (10^-8 of |g| after a 10^-11 drop of the V-cycle's own
     residual)."""

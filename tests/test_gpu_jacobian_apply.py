@@ -21,6 +21,7 @@ CASES = [
     ("sphere6x2x2x2-p2-reoriented", reorient(cubed_sphere_shell(2, 2), 9), 2, 2.0, "rusanov"),
     ("ogrid12x4-p3-roe", ogrid(12, 4), 3, 3.0, "roe"),
     ("sphere6x2x2x2-p2-roe", cubed_sphere_shell(2, 2), 2, 2.0, "roe"),
+    ("sphere6x2x2x2-p3", cubed_sphere_shell(2, 2), 3, 2.0, "rusanov"),
 ]
 
 

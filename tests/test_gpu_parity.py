@@ -34,6 +34,9 @@ CASES = [
     # random local frames: neighbours meet with every swap / flip combination
     ("ogrid16x6-p3-reoriented", reorient(ogrid(16, 6), 11), 3, 3.0, "rusanov"),
     ("sphere6x2x2x2-p2-reoriented", reorient(cubed_sphere_shell(2, 2), 12), 2, 2.0, "roe"),
+    # 3D p = 3: 320 x 320 element blocks (assembly and LU in global memory)
+    ("sphere6x2x2x2-p3", cubed_sphere_shell(2, 2), 3, 2.0, "rusanov"),
+    ("sphere6x2x2x2-p3-reoriented", reorient(cubed_sphere_shell(2, 2), 13), 3, -1.0, "roe"),
 ]
 IDS = [c[0] for c in CASES]
 
@@ -144,7 +147,8 @@ def test_exp1_happy_breakdown_parity():
     assert rel_err(to_host(ud) - u, out_o - u) < 1e-9
 
 
-@pytest.mark.parametrize("name,mesh,p,alpha,flux", CASES[:5] + CASES[6:10], ids=IDS[:5] + IDS[6:10])
+@pytest.mark.parametrize("name,mesh,p,alpha,flux", CASES[:5] + CASES[6:10] + CASES[12:13],
+                         ids=IDS[:5] + IDS[6:10] + IDS[12:13])
 def test_vcycle_parity(name, mesh, p, alpha, flux):
     O = _oracle(mesh, p, alpha, flux)
     S = _solver(mesh, p, alpha, flux, rk_stages=4, cfl_max=100.0, krylov_m=30)
