@@ -287,6 +287,58 @@ def c1_time_to_drop(P):
     return out
 
 
+def c5_adjoint(P, budget):
+    """The adjoint workload: cubed-sphere shell 6 x 12 x 12 x 16 = 13824 hexes
+    at p = 3 (320 x 320 blocks), Ma 0.3, s = 4, CFL_max = 100: the mixed-
+    precision solve from the free stream to the 1e-10 drop, then the adjoint
+    solve (FP64) and dC_D/dtheta for theta = (Mach, two seeded 1e-3-scale
+    Gaussian wall-bump amplitudes) from one paired residual and drag
+    evaluation per parameter (eg_param_sensitivity, h = 1e-6)."""
+    import math
+    import torch
+    from eg_inputs import cubed_sphere_shell, wall_bumps, bump_centers
+    from paper_1807_01151_amd.binding import _freestream_direction
+    mesh = cubed_sphere_shell(12, 16)
+    centers = bump_centers(3, 2, seed=1807)
+    sref = math.pi * 0.25  # the unit-diameter sphere's frontal area
+    kw = dict(rk_stages=4, cfl_max=100.0, krylov_m=30)
+    S = P.Solver(mesh, 3, mach=0.3, precision="mixed", **kw)
+    S.autotune()
+    out = {"workload": "3D sphere shell 6x12x12x16 = 13824 hexes, DG p=3 (64 modes x 5 vars, 320 x 320 blocks), "
+                       "mixed-precision steady state, FP64 adjoint, theta = (Ma, 2 wall bumps)"}
+    out["steady"], u = drop_run(S, 3, 100000, budget, "c5 mixed", chunk=500)
+    if not out["steady"]["converged"]:
+        return out
+    cd, g = S.drag(u, sref=sref, grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam, hist, st = S.adjoint_solve(u, g, drop_tol=1e-10, max_cycles=6000, raise_on_fail=False)
+    torch.cuda.synchronize()
+    out["adjoint"] = {"cycles": len(hist) - 1, "drop": float(hist[-1] / hist[0]), "status": int(st),
+                      "time_s": round(time.perf_counter() - t0, 3)}
+    log(f"[bench] c5 adjoint: {out['adjoint']}")
+    h = 1e-6
+    theta = [0.3, 0.0, 0.0]
+    direction = _freestream_direction(3, 0.0, 0.0)
+    grad = []
+    t0 = time.perf_counter()
+    for i in range(3):
+        tp, tm = list(theta), list(theta)
+        tp[i] += h
+        tm[i] -= h
+        Sp = P.Solver(wall_bumps(mesh, tp[1:], centers, 0.4), 3, mach=tp[0], **kw)
+        Sm = P.Solver(wall_bumps(mesh, tm[1:], centers, 0.4), 3, mach=tm[0], **kw)
+        grad.append(Sp.param_sensitivity(Sm, h, u, lam, direction=direction, sref=sref))
+        Sp.close()
+        Sm.close()
+    out["C_D"] = cd
+    out["dCD_dtheta"] = grad
+    out["sensitivity_s"] = round(time.perf_counter() - t0, 3)
+    log(f"[bench] c5: C_D {cd:.8e} gradient {grad}")
+    S.close()
+    return out
+
+
 def cpu_baseline(mesh, p):
     """The FP64 oracle on the host cores (all of them): one V-cycle of the
     benchmark workload from the free stream (a bounded sample, ~20 s)."""
@@ -318,6 +370,9 @@ def main():
     ap.add_argument("--batch-budget", type=float, default=30.0, help="seconds cap of the batched convergence run")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured-peak kernels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--c5", action="store_true",
+                    help="also run the 3D p = 3 adjoint workload (minutes: a converged 13824-hex p = 3 solve)")
+    ap.add_argument("--c5-budget", type=float, default=600.0, help="seconds cap of the c5 steady solve")
     ap.add_argument("--calibrate", action="store_true",
                     help="end with a 256 MiB device-to-device copy (the reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -423,6 +478,8 @@ def main():
         extras["c1_time_to_1e-10"] = c1_time_to_drop(P)
     if not args.no_batched:
         extras["batched"] = batched_measurements(P, 10, args.batch_budget)
+    if args.c5:
+        extras["c5_adjoint"] = c5_adjoint(P, args.c5_budget)
     if args.calibrate:
         nb = 256 << 20
         x = torch.ones(nb // 8, dtype=torch.float64, device="cuda")

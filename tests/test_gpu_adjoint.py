@@ -150,6 +150,36 @@ def test_steady_drag_gradient_matches_finite_differences():
     assert np.all(np.abs(grad - fd) <= 1e-5 * np.abs(fd) + 1e-9)
 
 
+@pytest.mark.timeout(900)
+def test_steady_drag_gradient_3d_p3_matches_finite_differences():
+    """The adjoint workload's check at 3D p = 3 (320 x 320 blocks): dC_D/dtheta
+    by torch.autograd through the adjoint, theta = (Mach, one seeded
+    Gaussian wall-bump amplitude), on the shell 6 x 3 x 3 x 4, against
+    central differences (h = 1e-6) of converged FP64 GPU solves."""
+    import paper_1807_01151_amd as P
+    base = cubed_sphere_shell(3, 4)
+    prob = P.autograd.SteadyDragProblem(base=base, centers=bump_centers(3, 1, seed=5), sigma=0.4, p_max=3,
+                                        solver_kw=dict(rk_stages=4, cfl_max=100.0, krylov_m=30),
+                                        drop=1e-12, max_cycles=10000, adjoint_drop=1e-11,
+                                        adjoint_max_cycles=10000)
+    theta = torch.tensor([0.3, 0.0], dtype=torch.float64, requires_grad=True)
+    cd = P.autograd.SteadyDrag.apply(theta, prob)
+    cd.backward()
+    grad = theta.grad.numpy()
+    h = 1e-6
+    fd = np.zeros(2)
+    for i in range(2):
+        tp, tm = theta.detach().clone(), theta.detach().clone()
+        tp[i] += h
+        tm[i] -= h
+        Sp, Sm = prob.solver(tp.tolist()), prob.solver(tm.tolist())
+        cp = Sp.drag(prob.steady(Sp), sref=prob.sref)
+        cm = Sm.drag(prob.steady(Sm), sref=prob.sref)
+        fd[i] = (cp - cm) / (2 * h)
+    print("3D p=3 C_D", cd.item(), "adjoint gradient", grad, "FD", fd, flush=True)
+    assert np.all(np.abs(grad - fd) <= 1e-4 * np.abs(fd) + 1e-9)
+
+
 def test_param_sensitivity_matches_separate_evaluations():
     """eg_param_sensitivity (central differences over the theta +- h handles,
     formed in the library) against the same formula assembled from the
