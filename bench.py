@@ -207,9 +207,10 @@ def batched_measurements(P, steps, budget_s, precision="mixed"):
     """The batched workload: 64 independent cylinder solves drawn from seed
     1807 (N_theta ~ U{16..96}, N_r = N_theta / 2, p ~ U{1..4}, Ma ~ U[0.1,
     0.4], alpha ~ U[-5, 5] deg), s = 4, CFL_max = 100, one batch handle per
-    order (every kernel launch covers all solves of that order).  Reports the
-    V-cycle throughput of the whole batch and, within a time budget, how many
-    solves reach the 1e-10 drop."""
+    order, all four advanced together (eg_solve_multi: per V-cycle one
+    synchronisation and one graph launch holding every order group's
+    V-cycle).  Reports the V-cycle throughput of the whole batch and, within
+    a time budget, how many solves reach the 1e-10 drop, diverge or stall."""
     import numpy as np
     import torch
     from eg_inputs import batch_draws, ogrid
@@ -224,44 +225,54 @@ def batched_measurements(P, steps, budget_s, precision="mixed"):
         B = P.BatchSolver(meshes, p, [draws[i]["mach"] for i in idx], [draws[i]["alpha_deg"] for i in idx],
                           rk_stages=4, cfl_max=100.0, krylov_m=30, precision=precision)
         B.autotune()
-        handles[p] = (B, B.freestream(p), idx)
+        B.set_graphs(True)
+        handles[p] = (B, idx)
     torch.cuda.synchronize()
     t_init = time.perf_counter() - t_init
-    dof = sum(B.n_elem * B.V * B.N(p) for p, (B, _, _) in handles.items())
-    for p, (B, u, _) in handles.items():
-        B.solve(u, drop_tol=0.0, max_cycles=2)
+    order = sorted(handles)
+    Bs = [handles[p][0] for p in order]
+    dof = sum(B.n_elem * B.V * B.N(B.p_max) for B in Bs)
+    us = [B.freestream(B.p_max) for B in Bs]
+    P.solve_multi(Bs, us, drop_tol=0.0, max_cycles=2)  # graph capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for p, (B, u, _) in handles.items():
-        B.solve(u, drop_tol=0.0, max_cycles=steps)
+    P.solve_multi(Bs, us, drop_tol=0.0, max_cycles=steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    out = {"solves": 64, "elements": int(sum(B.n_elem for B, _, _ in handles.values())), "dof": int(dof),
-           "groups": {str(p): len(idx) for p, (_, _, idx) in handles.items()}, "precision": precision,
-           "rk_stages": 4, "cfl_max": 100.0, "setup_s": round(t_init, 3),
-           "ms_per_batched_cycle": round(wall / steps * 1e3, 3), "dof_updates_per_s": dof * steps / wall}
+    ms_cycle = wall / steps * 1e3
+    out = {"solves": 64, "elements": int(sum(B.n_elem for B in Bs)), "dof": int(dof),
+           "groups": {str(p): len(handles[p][1]) for p in order}, "precision": precision,
+           "rk_stages": 4, "cfl_max": 100.0, "setup_s": round(t_init, 3), "launch": "eg_solve_multi, one graph per cycle",
+           "ms_per_batched_cycle": round(ms_cycle, 3), "dof_updates_per_s": dof * steps / wall}
     log(f"[bench] batched: {out}")
-    conv, div, drops = 0, 0, []
+    us = [B.freestream(B.p_max) for B in Bs]
+    cap = max(10, int(budget_s / (ms_cycle * 1e-3)))
     t1 = time.perf_counter()
-    for p, (B, _, idx) in sorted(handles.items()):
-        left = budget_s - (time.perf_counter() - t1)
-        if left <= 0:
-            break
-        u = B.freestream(p)
-        cap = max(10, int(left / len(handles) / max(wall / steps / len(handles), 1e-4)))
-        hists, cyc, st = B.solve(u, drop_tol=1e-10, max_cycles=cap)
+    res = P.solve_multi(Bs, us, drop_tol=1e-10, max_cycles=cap)
+    drops, conv, div, stall = [], 0, 0, 0
+    per_group = {}
+    for p, (hists, cyc, st) in zip(order, res):
         ok = sum(1 for h in hists if h[-1] <= 1e-10 * h[0])
         bad = sum(1 for h in hists if not np.isfinite(h[-1]))
         conv += ok
         div += bad
-        drops += [float(h[-1] / h[0]) for h in hists if np.isfinite(h[-1])]
-        log(f"[bench] batched p={p}: {ok}/{len(hists)} converged, {bad} diverged, cap {cap} cycles, "
-            f"{time.perf_counter() - t1:.1f}s")
+        stall += len(hists) - ok - bad
+        per_group[str(p)] = {"converged": ok, "diverged": bad, "stalled": len(hists) - ok - bad,
+                             "cycles_max": int(max(cyc))}
+        drops += [float(h[-1] / h[0]) if np.isfinite(h[-1]) else float("inf") for h in hists]
+    out["convergence_cap_cycles"] = cap
     out["converged_to_1e-10"] = conv
     out["diverged"] = div
-    out["median_drop_reached"] = float(np.median(drops)) if drops else None
+    out["stalled"] = stall
+    out["per_order"] = per_group
+    fin = [d for d in drops if np.isfinite(d)]
+    out["median_drop_reached"] = float(np.median(fin)) if fin else None
+    out["per_solve_drop"] = [float(f"{d:.3g}") for d in drops]
     out["convergence_run_s"] = round(time.perf_counter() - t1, 2)
-    for B, _, _ in handles.values():
+    out["ms_per_cycle_convergence_run"] = round(out["convergence_run_s"] * 1e3 / max(1, max(
+        max(c) for _, c, _ in res)), 3)
+    log(f"[bench] batched convergence: {per_group}, {out['convergence_run_s']} s")
+    for B in Bs:
         B.close()
     return out
 

@@ -256,6 +256,26 @@ eg_status eg_layout(const eg_handle* h, int solve, int p, int64_t* offset, int* 
 eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
                          int* n_cycles_host);
 
+/* Several batch handles (typically one per polynomial order of a
+ * heterogeneous set of solves) advanced together, V-cycle by V-cycle, each
+ * with the arithmetic and bookkeeping of eg_solve_batch (Section 2.4; the
+ * CFL ramp of eq. (cfl) per solve).  Per cycle: the entry residual norms
+ * of every running handle, one synchronisation, then one launch of the
+ * cycle: when every handle has graph replay enabled (eg_set_graphs) a
+ * single graph whose children are the handles' captured V-cycles (no
+ * ordering between them, so the groups may overlap on the GPU), else the
+ * handles' V-cycles one after another, eagerly.  A handle whose solves
+ * have all converged or diverged stops running.  hs[nh]: distinct batch
+ * handles on one device (all their work runs on hs[0]'s stream; the others'
+ * streams must have no work the call depends on after it starts, and the
+ * call synchronises before it returns); u_devs[k], hist_hosts[k] and
+ * n_cycles_hosts[k] as the arguments of eg_solve_batch for handle k;
+ * status_host[nh] (host): each handle's eg_solve_batch status.  Returns
+ * the first error, else EG_ERR_DIVERGED if a solve diverged, else
+ * EG_ERR_NOT_CONVERGED if a handle reached max_cycles, else EG_OK. */
+eg_status eg_solve_multi(eg_handle* const* hs, int nh, double* const* u_devs, double drop_tol, int max_cycles,
+                         double* const* hist_hosts, int* const* n_cycles_hosts, int* status_host);
+
 /* ---- Adjoint drag sensitivity (discrete adjoint of the steady problem) ----
  * The paper solves R(u) = 0 (Section 2.1, eq. (starteq) at steady state);
  * these entries give d(functional)/d(parameter) for a converged u by the

@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     Solver,
     lib,
     library_path,
+    solve_multi,
     EXPORTED_SYMBOLS,
 )
 from . import autograd  # noqa: F401

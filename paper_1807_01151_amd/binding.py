@@ -16,7 +16,7 @@ EXPORTED_SYMBOLS = (
     "eg_vcycle", "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read",
     "eg_drag", "eg_adjoint_apply", "eg_adjoint_solve", "eg_init_batch", "eg_layout", "eg_solve_batch", "eg_autotune",
     "eg_set_graphs", "eg_measure_peak", "eg_rnorm_noalloc",
-    "eg_param_sensitivity", "eg_jacobian_apply",
+    "eg_param_sensitivity", "eg_jacobian_apply", "eg_solve_multi",
 )
 
 KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
@@ -95,6 +95,9 @@ def lib():
         L.eg_param_sensitivity.argtypes = [vp, vp, d, vp, vp, pd, d, pd]
         L.eg_param_sensitivity.restype = i
         L.eg_adjoint_solve.argtypes = [vp, vp, vp, vp, d, i, pd, C.POINTER(i)]
+        L.eg_solve_multi.argtypes = [C.POINTER(vp), i, C.POINTER(vp), d, i, C.POINTER(vp), C.POINTER(vp),
+                                     C.POINTER(i)]
+        L.eg_solve_multi.restype = i
         for name in ("eg_sizes", "eg_set_freestream", "eg_residual", "eg_timestep", "eg_element_jacobian",
                      "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm", "eg_vcycle",
                      "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read"):
@@ -497,3 +500,33 @@ class BatchSolver:
             self._chk(st)
         cyc = [int(nc[i]) for i in range(self.n)]
         return [hist[i, : cyc[i] + 1] for i in range(self.n)], cyc, st
+
+
+def solve_multi(batches, us, drop_tol: float = 1e-10, max_cycles: int = 1000):
+    """Several BatchSolvers (e.g. one per polynomial order) advanced together
+    by eg_solve_multi: per V-cycle one synchronisation and one launch (a
+    single graph of every handle's V-cycle when all have graph replay
+    enabled).  Returns, per handle, (per-solve histories, cycles per solve,
+    status) as BatchSolver.solve."""
+    import numpy as np
+    batches, us = list(batches), list(us)
+    if not batches or len(batches) != len(us):
+        raise ValueError("solve_multi: one state per batch handle")
+    if len({id(b) for b in batches}) != len(batches):
+        raise ValueError("solve_multi: a handle appears twice")
+    nh = len(batches)
+    hs = (C.c_void_p * nh)(*[b._h for b in batches])
+    pu = (C.c_void_p * nh)(*[b._vec(u, b.p_max, "u") for b, u in zip(batches, us)])
+    hists = [np.zeros((b.n, max_cycles + 1)) for b in batches]
+    ncs = [(C.c_int * b.n)() for b in batches]
+    ph = (C.c_void_p * nh)(*[h.ctypes.data for h in hists])
+    pn = (C.c_void_p * nh)(*[C.cast(nc, C.c_void_p).value for nc in ncs])
+    status = (C.c_int * nh)()
+    st = lib().eg_solve_multi(hs, nh, pu, drop_tol, max_cycles, ph, pn, status)
+    if st not in (0, 5, 6):
+        batches[0]._chk(st)
+    out = []
+    for k, b in enumerate(batches):
+        cyc = [int(ncs[k][i]) for i in range(b.n)]
+        out.append(([hists[k][i, : cyc[i] + 1] for i in range(b.n)], cyc, int(status[k])))
+    return out

@@ -1011,35 +1011,41 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
 // from device memory (per element in a batch, else the scalar dcfl1), so one
 // capture per mixed-precision phase serves every cycle; everything else it
 // touches is handle-owned and fixed.
+// Captures (once per mixed-precision phase) the V-cycle below the entry
+// norm on the handle's stream into h->ggraph[g] / h->gexec[g].
+eg_status ensure_graph(eg_handle* h, double cfl) {
+  const int g = h->mixed && h->phase_b ? 1 : 0;
+  if (h->gexec[g]) return EG_OK;
+  if (!h->batch) h->M.cfl_one = h->dcfl1;
+  HIPCHK(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+  eg_status st = vc_rec(h, h->pmax, cfl);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(h->st, &graph);
+  h->M.cfl_one = nullptr;
+  if (st != EG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hipfail(h, e, "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hipfail(h, e, "hipGraphInstantiate");
+  }
+  h->ggraph[g] = graph;
+  h->gexec[g] = ex;
+  return EG_OK;
+}
+
 eg_status vcycle_run(eg_handle* h, double cfl) {
   if (!h->graphs || h->prof) return vc_rec(h, h->pmax, cfl);
   if (!h->batch) {
     h->hcfl1[0] = cfl;
     HIPCHK(h, hipMemcpyAsync(h->dcfl1, h->hcfl1, sizeof(double), hipMemcpyHostToDevice, h->st));
   }
-  const int g = h->mixed && h->phase_b ? 1 : 0;
-  if (!h->gexec[g]) {
-    if (!h->batch) h->M.cfl_one = h->dcfl1;
-    HIPCHK(h, hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
-    eg_status st = vc_rec(h, h->pmax, cfl);
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(h->st, &graph);
-    h->M.cfl_one = nullptr;
-    if (st != EG_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return st;
-    }
-    if (e != hipSuccess) return hipfail(h, e, "hipStreamEndCapture");
-    hipGraphExec_t ex = nullptr;
-    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      (void)hipGraphDestroy(graph);
-      return hipfail(h, e, "hipGraphInstantiate");
-    }
-    h->ggraph[g] = graph;
-    h->gexec[g] = ex;
-  }
-  HIPCHK(h, hipGraphLaunch(h->gexec[g], h->st));
+  ECHK(ensure_graph(h, cfl));
+  HIPCHK(h, hipGraphLaunch(h->gexec[h->mixed && h->phase_b ? 1 : 0], h->st));
   return EG_OK;
 }
 
@@ -1077,6 +1083,131 @@ struct CflBind {
   eg_handle* h;
   explicit CflBind(eg_handle* hh) : h(hh) { h->M.cfl_e = h->cfl_e_buf; }
   ~CflBind() { h->M.cfl_e = nullptr; }
+};
+
+// The bookkeeping of one batch handle's steady solve across V-cycles (shared
+// by eg_solve_batch and eg_solve_multi): per-solve first norms, minima,
+// convergence and divergence flags, the norm ring of the mixed-precision
+// switch.  A solve whose norm is not finite has diverged: it is recorded
+// and left alone (its values stay inside its own elements and Krylov
+// segment) while the others go on; a converged solve's state is saved at
+// the norm that reached the drop (later cycles of the batch still run over
+// its elements) and restored at the end.
+struct BatchRun {
+  eg_handle* h = nullptr;
+  double* u_dev = nullptr;
+  double drop_tol = 0.0;
+  int max_cycles = 0;
+  double* hist = nullptr;
+  int* ncyc = nullptr;
+  int nseg = 0, pm = 0, N = 0;
+  size_t per_elem = 0;
+  std::vector<double> r1, rmin, ring;
+  std::vector<int> done, nmin;
+  int phase_b = 0;
+  bool over = false;  // the solve has ended; its status is `result`
+  eg_status result = EG_OK;
+
+  eg_status begin() {
+    const DevMesh& M = h->M;
+    nseg = M.nseg;
+    pm = h->pmax;
+    N = nmodes_of(M.d, pm);
+    per_elem = (size_t)M.V * N;
+    if (!h->bsave) ECHK(dalloc(h, &h->bsave, (size_t)M.ne * per_elem));
+    r1.assign(nseg, -1.0);
+    rmin.assign(nseg, HUGE_VAL);
+    ring.assign((size_t)nseg * 64, 0.0);
+    done.assign(nseg, 0);
+    nmin.assign(nseg, 1);
+    for (int sg = 0; sg < nseg; ++sg) ncyc[sg] = 0;
+    HIPCHK(h, eg::launch_basis(M, N, u_dev, h->ut[pm], 0, h->st));
+    return EG_OK;
+  }
+  // FP64 entry norms of every solve and the pivot-failure flag, copied to
+  // the host (asynchronous; read after the stream's synchronisation)
+  eg_status launch_entry() {
+    const DevMesh& M = h->M;
+    PCALL(h, EG_K_RESIDUAL, pm,
+          eg::launch_residual(M, h->tabs[pm], pm, h->ut[pm], nullptr, h->rt[pm], eg::PREC_FP64, h->st));
+    PCALL(h, EG_K_NORM, pm, eg::launch_norm(M, N, h->rt[pm], h->npart, h->nout, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->hnorm, h->nout, sizeof(double) * nseg, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(h, hipMemcpyAsync(h->hpin + 1, h->dfail, sizeof(int), hipMemcpyDeviceToHost, h->st));
+    return EG_OK;
+  }
+  // Cycle n's entry norms (after the synchronisation): records them, and
+  // either ends the solve (over, result) or sets the next cycle's CFL
+  // numbers and arithmetic phase.
+  eg_status update(int n) {
+    bool all = true;
+    double worst = 0.0;
+    for (int sg = 0; sg < nseg; ++sg) {
+      const double rn = h->hnorm[sg];
+      if (r1[sg] < 0.0) r1[sg] = rn;
+      if (!done[sg]) {
+        hist[(size_t)sg * (max_cycles + 1) + (n - 1)] = rn;
+        ncyc[sg] = n - 1;
+        if (!std::isfinite(rn)) done[sg] = 2;
+        else if (rn <= drop_tol * r1[sg]) {
+          done[sg] = 1;
+          const size_t o = (size_t)h->seg_e0[sg] * per_elem;
+          const size_t cnt = (size_t)(h->seg_e0[sg + 1] - h->seg_e0[sg]) * per_elem;
+          HIPCHK(h, hipMemcpyAsync(h->bsave + o, h->ut[pm] + o, cnt * sizeof(double), hipMemcpyDeviceToDevice,
+                                   h->st));
+        }
+      }
+      all = all && done[sg];
+      if (done[sg] != 2) {
+        worst = std::max(worst, rn / r1[sg]);
+        if (!(rn >= rmin[sg])) { rmin[sg] = rn; nmin[sg] = n; }
+      }
+      h->hcfl[sg] = std::isfinite(rn) ? cfl_ramp(h->cfl_max, rn, h->relr ? r1[sg] : 1.0, n, pm) : 1.0;
+    }
+    if (all) {
+      over = true;
+      for (int sg = 0; sg < nseg; ++sg)
+        if (done[sg] == 2) result = fail(h, EG_ERR_DIVERGED, "a solve of the batch diverged (non-finite norm)");
+      return EG_OK;
+    }
+    if (n - 1 == max_cycles) {
+      bool div = false;
+      for (int sg = 0; sg < nseg; ++sg) div = div || done[sg] == 2;
+      over = true;
+      result = fail(h, div ? EG_ERR_DIVERGED : EG_ERR_NOT_CONVERGED,
+                    div ? "a solve of the batch diverged (non-finite norm)" : "max_cycles reached");
+      return EG_OK;
+    }
+    if (h->mixed && !phase_b) {
+      bool stall = false;
+      for (int sg = 0; sg < nseg; ++sg)
+        stall = stall || (done[sg] == 0 && phase_a_over(h->hnorm[sg], 0.0, n, nmin[sg], &ring[(size_t)sg * 64]));
+      if (worst <= EG_PHASE_B_DROP || stall) phase_b = 1;
+    }
+    for (int sg = 0; sg < nseg; ++sg) ring[(size_t)sg * 64 + n % 64] = h->hnorm[sg];
+    h->phase_b = phase_b;
+    return EG_OK;
+  }
+  // the next cycle's per-solve CFL numbers to the device, per element
+  eg_status launch_cfl() {
+    HIPCHK(h, hipMemcpyAsync(h->dcfl, h->hcfl, sizeof(double) * nseg, hipMemcpyHostToDevice, h->st));
+    HIPCHK(h, eg::launch_expand_cfl(h->M, h->dcfl, h->st));
+    return EG_OK;
+  }
+  // converged solves back to their saved states; the state to u_dev
+  eg_status finish() {
+    eg_status st = EG_OK;
+    for (int sg = 0; sg < nseg; ++sg) {
+      if (done[sg] != 1) continue;
+      const size_t o = (size_t)h->seg_e0[sg] * per_elem;
+      const size_t cnt = (size_t)(h->seg_e0[sg + 1] - h->seg_e0[sg]) * per_elem;
+      hipError_t ec =
+          hipMemcpyAsync(h->ut[pm] + o, h->bsave + o, cnt * sizeof(double), hipMemcpyDeviceToDevice, h->st);
+      if (ec != hipSuccess && st == EG_OK) st = hipfail(h, ec, "restore converged states");
+    }
+    hipError_t e = eg::launch_basis(h->M, N, h->ut[pm], u_dev, 1, h->st);
+    if (e != hipSuccess && st == EG_OK) st = hipfail(h, e, "basis");
+    return st;
+  }
 };
 
 }  // namespace
@@ -1587,93 +1718,152 @@ eg_status eg_solve_batch(eg_handle* h, double* u_dev, double drop_tol, int max_c
   StreamSwap sw{h, h->st};
   ECHK(sw.begin());
   CflBind cb(h);  // per-solve CFL for the duration of the batch solve
-  const DevMesh& M = h->M;
-  const int nseg = M.nseg, pm = h->pmax, N = nmodes_of(M.d, pm);
-  const size_t per_elem = (size_t)M.V * N;
-  if (!h->bsave) ECHK(dalloc(h, &h->bsave, (size_t)M.ne * per_elem));
-  std::vector<double> r1(nseg, -1.0), rmin(nseg, HUGE_VAL);
-  std::vector<int> done(nseg, 0), nmin(nseg, 1);
-  std::vector<double> ring((size_t)nseg * 64, 0.0);  // past entry norms per solve (mixed-mode switch)
-  for (int sg = 0; sg < nseg; ++sg) n_cycles_host[sg] = 0;
-  HIPCHK(h, eg::launch_basis(M, N, u_dev, h->ut[pm], 0, h->st));
+  BatchRun br;
+  br.h = h;
+  br.u_dev = u_dev;
+  br.drop_tol = drop_tol;
+  br.max_cycles = max_cycles;
+  br.hist = hist_host;
+  br.ncyc = n_cycles_host;
+  ECHK(br.begin());
   eg_status st = EG_OK;
-  int phase_b = 0;
   for (int n = 1;; ++n) {
-    // FP64 entry norms of every solve
-    PCALL(h, EG_K_RESIDUAL, pm,
-          eg::launch_residual(M, h->tabs[pm], pm, h->ut[pm], nullptr, h->rt[pm], eg::PREC_FP64, h->st));
-    PCALL(h, EG_K_NORM, pm, eg::launch_norm(M, N, h->rt[pm], h->npart, h->nout, h->st));
-    HIPCHK(h, hipMemcpyAsync(h->hnorm, h->nout, sizeof(double) * nseg, hipMemcpyDeviceToHost, h->st));
-    HIPCHK(h, hipMemcpyAsync(h->hpin + 1, h->dfail, sizeof(int), hipMemcpyDeviceToHost, h->st));
-    st = sync_status(h);
-    if (st != EG_OK) break;
-    // A solve whose norm is not finite has diverged: it is recorded and
-    // left alone (its values stay inside its own elements and Krylov
-    // segment); the others go on.  The shared pivot-failure flag is not
-    // decisive here for the same reason.
-    bool all = true;
-    double worst = 0.0;
-    for (int sg = 0; sg < nseg; ++sg) {
-      const double rn = h->hnorm[sg];
-      if (r1[sg] < 0.0) r1[sg] = rn;
-      if (!done[sg]) {
-        hist_host[(size_t)sg * (max_cycles + 1) + (n - 1)] = rn;
-        n_cycles_host[sg] = n - 1;
-        if (!std::isfinite(rn)) done[sg] = 2;
-        else if (rn <= drop_tol * r1[sg]) {
-          // keep the state whose norm reached the drop: later cycles of the
-          // batch still run over this solve's elements
-          done[sg] = 1;
-          const size_t o = (size_t)h->seg_e0[sg] * per_elem;
-          const size_t cnt = (size_t)(h->seg_e0[sg + 1] - h->seg_e0[sg]) * per_elem;
-          HIPCHK(h, hipMemcpyAsync(h->bsave + o, h->ut[pm] + o, cnt * sizeof(double), hipMemcpyDeviceToDevice,
-                                   h->st));
-        }
-      }
-      all = all && done[sg];
-      if (done[sg] != 2) {
-        worst = std::max(worst, rn / r1[sg]);
-        if (!(rn >= rmin[sg])) { rmin[sg] = rn; nmin[sg] = n; }
-      }
-      h->hcfl[sg] = std::isfinite(rn) ? cfl_ramp(h->cfl_max, rn, h->relr ? r1[sg] : 1.0, n, pm) : 1.0;
-    }
-    if (all) {
-      for (int sg = 0; sg < nseg; ++sg)
-        if (done[sg] == 2) st = fail(h, EG_ERR_DIVERGED, "a solve of the batch diverged (non-finite norm)");
+    if ((st = br.launch_entry()) != EG_OK) break;
+    if ((st = sync_status(h)) != EG_OK) break;
+    if ((st = br.update(n)) != EG_OK) break;
+    if (br.over) {
+      st = br.result;
       break;
     }
-    if (n - 1 == max_cycles) {
-      bool div = false;
-      for (int sg = 0; sg < nseg; ++sg) div = div || done[sg] == 2;
-      st = fail(h, div ? EG_ERR_DIVERGED : EG_ERR_NOT_CONVERGED,
-                div ? "a solve of the batch diverged (non-finite norm)" : "max_cycles reached");
-      break;
-    }
-    if (h->mixed && !phase_b) {
-      bool stall = false;
-      for (int sg = 0; sg < nseg; ++sg)
-        stall = stall || (done[sg] == 0 && phase_a_over(h->hnorm[sg], 0.0, n, nmin[sg], &ring[(size_t)sg * 64]));
-      if (worst <= EG_PHASE_B_DROP || stall) phase_b = 1;
-    }
-    for (int sg = 0; sg < nseg; ++sg) ring[(size_t)sg * 64 + n % 64] = h->hnorm[sg];
-    h->phase_b = phase_b;
-    HIPCHK(h, hipMemcpyAsync(h->dcfl, h->hcfl, sizeof(double) * nseg, hipMemcpyHostToDevice, h->st));
-    HIPCHK(h, eg::launch_expand_cfl(M, h->dcfl, h->st));
-    st = vcycle_run(h, h->cfl_max);
-    if (st != EG_OK) break;
+    if ((st = br.launch_cfl()) != EG_OK) break;
+    if ((st = vcycle_run(h, h->cfl_max)) != EG_OK) break;
   }
-  for (int sg = 0; sg < nseg; ++sg) {
-    if (done[sg] != 1) continue;
-    const size_t o = (size_t)h->seg_e0[sg] * per_elem;
-    const size_t cnt = (size_t)(h->seg_e0[sg + 1] - h->seg_e0[sg]) * per_elem;
-    hipError_t ec = hipMemcpyAsync(h->ut[pm] + o, h->bsave + o, cnt * sizeof(double), hipMemcpyDeviceToDevice, h->st);
-    if (ec != hipSuccess && st == EG_OK) st = hipfail(h, ec, "restore converged states");
-  }
-  hipError_t e = eg::launch_basis(M, N, h->ut[pm], u_dev, 1, h->st);
-  if (e != hipSuccess && st == EG_OK) st = hipfail(h, e, "basis");
+  const eg_status sf = br.finish();
+  if (st == EG_OK) st = sf;
   hipError_t e2 = hipStreamSynchronize(h->st);
   if (e2 != hipSuccess && st == EG_OK) st = hipfail(h, e2, "sync");
   return st;
+}
+
+eg_status eg_solve_multi(eg_handle* const* hs, int nh, double* const* u_devs, double drop_tol, int max_cycles,
+                         double* const* hist_hosts, int* const* n_cycles_hosts, int* status_host) {
+  if (!hs || nh < 1 || !u_devs || !hist_hosts || !n_cycles_hosts || !status_host || max_cycles < 0)
+    return EG_ERR_ARG;
+  for (int k = 0; k < nh; ++k) {
+    if (!hs[k] || !u_devs[k] || !hist_hosts[k] || !n_cycles_hosts[k]) return EG_ERR_ARG;
+    if (!hs[k]->batch) return fail(hs[k], EG_ERR_ARG, "not a batch handle (eg_init_batch)");
+    if (hs[k]->dev != hs[0]->dev) return fail(hs[0], EG_ERR_ARG, "handles on different devices");
+    if (!eg::jacobian_supported(hs[k]->M.d, hs[k]->pmax) && hs[k]->pmax > 0)
+      return fail(hs[k], EG_ERR_UNSUPPORTED, "element block too large");
+    for (int j = 0; j < k; ++j)
+      if (hs[j] == hs[k]) return fail(hs[0], EG_ERR_ARG, "a handle appears twice");
+  }
+  eg_handle* h0 = hs[0];
+  bool graphs = true;
+  for (int k = 0; k < nh; ++k) graphs = graphs && hs[k]->graphs && !hs[k]->prof;
+  // every handle's work on one stream: h0's (its internal stream in graph
+  // mode); the others' callers' work is complete on entry, and the call
+  // synchronises before it returns
+  StreamSwap sw{h0, h0->st};
+  ECHK(sw.begin());
+  std::vector<hipStream_t> caller(nh);
+  for (int k = 1; k < nh; ++k) {
+    caller[k] = hs[k]->st;
+    HIPCHK(hs[k], hipStreamSynchronize(caller[k]));
+  }
+  for (int k = 1; k < nh; ++k) hs[k]->st = h0->st;
+  std::vector<BatchRun> br(nh);
+  std::vector<hipGraph_t> parents;
+  std::vector<hipGraphExec_t> pexec;
+  std::vector<unsigned> pkey;
+  eg_status st = EG_OK;
+  for (int k = 0; k < nh; ++k) {
+    hs[k]->M.cfl_e = hs[k]->cfl_e_buf;  // per-solve CFL for the duration of the solve
+    br[k].h = hs[k];
+    br[k].u_dev = u_devs[k];
+    br[k].drop_tol = drop_tol;
+    br[k].max_cycles = max_cycles;
+    br[k].hist = hist_hosts[k];
+    br[k].ncyc = n_cycles_hosts[k];
+    if (st == EG_OK) st = br[k].begin();
+  }
+  for (int n = 1; st == EG_OK; ++n) {
+    for (int k = 0; k < nh && st == EG_OK; ++k)
+      if (!br[k].over) st = br[k].launch_entry();
+    if (st != EG_OK) break;
+    if ((st = sync_status(h0)) != EG_OK) break;
+    bool any = false;
+    for (int k = 0; k < nh && st == EG_OK; ++k) {
+      if (br[k].over) continue;
+      st = br[k].update(n);
+      any = any || !br[k].over;
+    }
+    if (st != EG_OK || !any) break;
+    for (int k = 0; k < nh && st == EG_OK; ++k)
+      if (!br[k].over) st = br[k].launch_cfl();
+    if (st != EG_OK) break;
+    if (!graphs) {
+      for (int k = 0; k < nh && st == EG_OK; ++k)
+        if (!br[k].over) st = vc_rec(hs[k], hs[k]->pmax, hs[k]->cfl_max);
+      continue;
+    }
+    // one graph launch for the cycle: the running handles' captured
+    // V-cycles as independent child graphs of one parent graph (one parent
+    // per set of running handles and arithmetic phases)
+    unsigned key = 0;
+    for (int k = 0; k < nh; ++k)
+      if (!br[k].over) key |= (1u << (2 * k)) | ((hs[k]->mixed && hs[k]->phase_b ? 1u : 0u) << (2 * k + 1));
+    int slot = -1;
+    for (size_t i = 0; i < pkey.size(); ++i)
+      if (pkey[i] == key) slot = (int)i;
+    if (slot < 0) {
+      hipGraph_t parent = nullptr;
+      const hipError_t ec = hipGraphCreate(&parent, 0);
+      if (ec != hipSuccess) {
+        st = hipfail(h0, ec, "hipGraphCreate");
+        break;
+      }
+      parents.push_back(parent);
+      for (int k = 0; k < nh && st == EG_OK; ++k) {
+        if (br[k].over) continue;
+        st = ensure_graph(hs[k], hs[k]->cfl_max);
+        if (st != EG_OK) break;
+        hipGraphNode_t node = nullptr;
+        const hipError_t e =
+            hipGraphAddChildGraphNode(&node, parent, nullptr, 0, hs[k]->ggraph[hs[k]->mixed && hs[k]->phase_b ? 1 : 0]);
+        if (e != hipSuccess) st = hipfail(h0, e, "hipGraphAddChildGraphNode");
+      }
+      if (st != EG_OK) break;
+      hipGraphExec_t ex = nullptr;
+      const hipError_t e = hipGraphInstantiate(&ex, parent, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        st = hipfail(h0, e, "hipGraphInstantiate");
+        break;
+      }
+      pexec.push_back(ex);
+      pkey.push_back(key);
+      slot = (int)pkey.size() - 1;
+    }
+    const hipError_t e = hipGraphLaunch(pexec[slot], h0->st);
+    if (e != hipSuccess) st = hipfail(h0, e, "hipGraphLaunch");
+  }
+  for (int k = 0; k < nh; ++k) {
+    const eg_status sf = br[k].finish();
+    if (st == EG_OK) st = sf;
+  }
+  hipError_t e2 = hipStreamSynchronize(h0->st);
+  if (e2 != hipSuccess && st == EG_OK) st = hipfail(h0, e2, "sync");
+  for (auto ex : pexec) (void)hipGraphExecDestroy(ex);
+  for (auto g : parents) (void)hipGraphDestroy(g);
+  eg_status worst = EG_OK;
+  for (int k = 0; k < nh; ++k) {
+    hs[k]->M.cfl_e = nullptr;
+    if (k > 0) hs[k]->st = caller[k];
+    status_host[k] = (int)(st != EG_OK ? st : br[k].result);
+    if (worst == EG_OK || (worst == EG_ERR_NOT_CONVERGED && br[k].result == EG_ERR_DIVERGED))
+      worst = br[k].result;
+  }
+  return st != EG_OK ? st : worst;
 }
 
 eg_status eg_solve_resume(eg_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,

@@ -112,6 +112,7 @@ __device__ __forceinline__ void panel_body(R* A, int cb, int* s_prow, R* s_linv,
   static_assert(n <= 512, "row index bits of the pivot key");
   R pv[NS][16];
   int prw[NS], used[NS];
+  int bad = 0;  // a zero or non-finite pivot, reported once per panel
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int lr = kb + lane + 64 * s;
@@ -142,7 +143,7 @@ __device__ __forceinline__ void panel_body(R* A, int cb, int* s_prow, R* s_linv,
           for (int c = 0; c < 16; ++c)
             if (c >= tt) pr[c] = readlane_d(pv[s][c], wl);
         }
-      if (lane == 0 && !(fabs(pr[tt]) > R(0))) atomicOr(fail, 1);
+      if (!(fabs(pr[tt]) > R(0))) bad = 1;
       const R ip = R(1) / pr[tt];
       // rows not used as pivots take multiplier l, the others l = 0 (their
       // values are then left unchanged by the update)
@@ -158,6 +159,7 @@ __device__ __forceinline__ void panel_body(R* A, int cb, int* s_prow, R* s_linv,
       }
     }
   }
+  if (lane == 0 && bad) atomicOr(fail, 1);
   int before = 0;  // unused rows in the slots before this one
 #pragma unroll
   for (int s = 0; s < NS; ++s) {

@@ -770,6 +770,7 @@ __global__ __launch_bounds__(256, 3) void k_jaclu_wave(const R* __restrict__ BC,
   // bandwidth).  Lanes already used as pivots get a zero multiplier, so the
   // update below leaves their rows unchanged without a branch.
   int mystep = (lane < n) ? -1 : n;
+  int bad = 0;  // failure flags of this element, reported once after the elimination
 #pragma unroll
   for (int k = 0; k < n; ++k) {
     // key: |a| as float with its 6 low mantissa bits replaced by 63 - lane
@@ -779,10 +780,10 @@ __global__ __launch_bounds__(256, 3) void k_jaclu_wave(const R* __restrict__ BC,
     const unsigned kmax = wave_max_u32(key);
     const int pl = __builtin_amdgcn_readfirstlane(63 - (int)(kmax & 63u));
     // the winner must be a row not yet used as a pivot
-    if (lane == pl && mystep >= 0) atomicOr(fail, 4);
+    if (lane == pl && mystep >= 0) bad |= 4;
     mystep = (lane == pl) ? k : mystep;
     const R piv = readlane_d(acc[k], pl);
-    if (lane == 0 && !(dabs(piv) > R(0))) atomicOr(fail, 1);
+    if (!(dabs(piv) > R(0))) bad |= 1;
     const R l = (mystep < 0) ? acc[k] * (R(1) / piv) : R(0);
     if (mystep < 0) acc[k] = l;
     // every sixth entry of the pivot row travels through ds_bpermute (the
@@ -794,6 +795,8 @@ __global__ __launch_bounds__(256, 3) void k_jaclu_wave(const R* __restrict__ BC,
       acc[j] = fma(-l, pj, acc[j]);
     }
   }
+  if (bad & 4) atomicOr(fail, 4);
+  if (lane == 0 && (bad & 1)) atomicOr(fail, 1);
   if (lane < n) {
     R* o = out + (size_t)e * n * n;
 #pragma unroll
@@ -917,6 +920,7 @@ __global__ __launch_bounds__(256) void k_jaclu_g16(const R* __restrict__ BC, con
   }
   const int rowbase = lane & ~15;
   int mystep = -1;
+  int bad = 0;  // failure flags of this lane's element, reported after the elimination
 #pragma unroll
   for (int k = 0; k < n; ++k) {
     unsigned key = 0u;
@@ -924,10 +928,10 @@ __global__ __launch_bounds__(256) void k_jaclu_g16(const R* __restrict__ BC, con
     const unsigned kmax = row_max_u32(key);
     const int pr = 15 - (int)(kmax & 63u);  // pivot row of this lane's element
     const int pa = (rowbase + pr) * 4;       // its lane, as a ds_bpermute address
-    if (r == pr && mystep >= 0) atomicOr(fail, 4);
+    if (r == pr && mystep >= 0) bad |= 4;
     mystep = (r == pr) ? k : mystep;
     const R piv = bperm_d(acc[k], pa);
-    if (r == 0 && !(dabs(piv) > R(0))) atomicOr(fail, 1);
+    if (!(dabs(piv) > R(0))) bad |= 1;
     const R l = (mystep < 0) ? acc[k] * (R(1) / piv) : R(0);
     if (mystep < 0) acc[k] = l;
 #pragma unroll
@@ -936,6 +940,8 @@ __global__ __launch_bounds__(256) void k_jaclu_g16(const R* __restrict__ BC, con
       acc[j] = fma(-l, pj, acc[j]);
     }
   }
+  if (live && (bad & 4)) atomicOr(fail, 4);
+  if (live && r == 0 && (bad & 1)) atomicOr(fail, 1);
   if (live && mystep >= 0) {  // every row is chosen once: an unused row always has the largest key
     R* o = out + (size_t)e * n * n;
 #pragma unroll
@@ -2121,7 +2127,9 @@ __global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, cons
     for (int i = 0; i < n; ++i) nrm = fmax(nrm, s_red[i]);
     const double theta13 = 5.371920351148152;
     int sq = 0;
-    if (nrm > theta13) sq = max(0, (int)ceil(log2(nrm / theta13)));
+    // a non-finite H (a diverged solve) takes no squarings: its result is
+    // non-finite either way, and the exponent must stay bounded
+    if (nrm > theta13 && nrm <= 1.0e300) sq = min(1000, (int)ceil(log2(nrm / theta13)));
     s_sq = sq;
   }
   __syncthreads();

@@ -104,7 +104,7 @@ def test_batch_solve_matches_single_solves(precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_p4_cycles_match_single(precision):
-    """p = 4 (100 x 100 blocks: the column-split factorisation and the
+    """p = 4 (100 x 100 blocks: the LDS-resident assembly and LU and the
     chunked stage kernel) in a batch of two solves against each solve alone:
     five V-cycles from the free streams agree to 1e-12 r_1 (the batch sums
     its residual norms per solve in another order) and so do the states."""
@@ -125,3 +125,32 @@ def test_batch_p4_cycles_match_single(precision):
         assert n == 6
         assert dev < 1e-12
         assert e < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("graphs", [False, True])
+def test_solve_multi_matches_separate_batch_solves(precision, graphs):
+    """Three batch handles of different orders (p = 1, 2, 3 over the same
+    three meshes) advanced together by eg_solve_multi, eagerly and as one
+    graph launch per cycle, against each handle's own eg_solve_batch: every
+    handle runs the same arithmetic either way, so the histories, cycle
+    counts, statuses and final states are bitwise equal (some solves reach
+    the drop within the cap, others do not)."""
+    import paper_1807_01151_amd as P
+    orders = (1, 2, 3)
+    Bs = [_batch(p, precision=precision) for p in orders]
+    for B in Bs:
+        B.set_graphs(graphs)
+    us = [B.freestream(p) for B, p in zip(Bs, orders)]
+    res = P.solve_multi(Bs, us, drop_tol=1e-5, max_cycles=400)
+    for k, p in enumerate(orders):
+        B = _batch(p, precision=precision)
+        B.set_graphs(graphs)
+        u = B.freestream(p)
+        hists, cyc, st = B.solve(u, drop_tol=1e-5, max_cycles=400)
+        hm, cm, sm = res[k]
+        print(f"  {precision} graphs={graphs} p={p}: cycles {cm} status {sm}", flush=True)
+        assert cm == cyc and sm == st
+        for a, b in zip(hm, hists):
+            assert np.array_equal(a, b)
+        assert np.array_equal(to_host(us[k]), to_host(u))
