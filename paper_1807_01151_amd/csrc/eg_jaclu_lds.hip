@@ -104,9 +104,14 @@ template <> struct Mfma<float> {
 // first, in pivot order, then the others in their previous order) and
 // L11^{-1} formed in s_linv (row-major, unit lower triangular, identity past
 // nbk).
+// Pointers into LDS, typed as such so that a called function addresses
+// them with LDS instructions (a generic pointer would take flat accesses).
+template <class T>
+using lds_p = __attribute__((address_space(3))) T*;
+
 template <int NS, int n, int LDA, class R>
-__device__ __forceinline__ void panel_body(R* A, int cb, int* s_prow, R* s_linv, int* fail, int kb, int nbk,
-                                           int lane) {
+__device__ __forceinline__ void panel_body(lds_p<R> A, int cb, lds_p<const int> s_in, lds_p<int> s_prow,
+                                           lds_p<R> s_linv, int* fail, int kb, int nbk, int lane) {
   // the row slot index in the low bits of the key: 8 bits up to n = 256, 9 up to 512
   constexpr unsigned KM = n <= 256 ? 255u : 511u;
   static_assert(n <= 512, "row index bits of the pivot key");
@@ -116,7 +121,7 @@ __device__ __forceinline__ void panel_body(R* A, int cb, int* s_prow, R* s_linv,
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int lr = kb + lane + 64 * s;
-    prw[s] = lr < n ? s_prow[lr] : 0;
+    prw[s] = lr < n ? s_in[lr] : 0;
     used[s] = lr < n ? -1 : 16;
 #pragma unroll
     for (int c = 0; c < 16; ++c) pv[s][c] = (lr < n && c < nbk) ? A[(kb + c - cb) * LDA + prw[s]] : R(0);
@@ -160,6 +165,8 @@ __device__ __forceinline__ void panel_body(R* A, int cb, int* s_prow, R* s_linv,
     }
   }
   if (lane == 0 && bad) atomicOr(fail, 1);
+  if (s_in != s_prow)
+    for (int i = lane; i < kb; i += 64) s_prow[i] = s_in[i];  // the rows already pivoted keep their places
   int before = 0;  // unused rows in the slots before this one
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
@@ -201,9 +208,17 @@ __device__ __forceinline__ void panel_body(R* A, int cb, int* s_prow, R* s_linv,
 // The panel as a called function (one copy per slot count, so that the
 // kernel holds only the live variant's registers).
 template <int NS, int n, int LDA, class R>
-__device__ __noinline__ void panel_wave(R* A, int cb, int* s_prow, R* s_linv, int* fail, int kb, int nbk,
-                                        int lane) {
-  panel_body<NS, n, LDA>(A, cb, s_prow, s_linv, fail, kb, nbk, lane);
+__device__ __noinline__ void panel_wave(lds_p<R> A, int cb, lds_p<const int> s_in, lds_p<int> s_prow,
+                                        lds_p<R> s_linv, int* fail, int kb, int nbk, int lane) {
+  panel_body<NS, n, LDA, R>(A, cb, s_in, s_prow, s_linv, fail, kb, nbk, lane);
+}
+
+// The same with the kernels' LDS arrays (generic pointers into LDS).
+template <int NS, int n, int LDA, class R>
+__device__ __forceinline__ void panel_lds(R* A, int cb, const int* s_in, int* s_prow, R* s_linv, int* fail, int kb,
+                                          int nbk, int lane) {
+  panel_wave<NS, n, LDA, R>((lds_p<R>)A, cb, (lds_p<const int>)s_in, (lds_p<int>)s_prow, (lds_p<R>)s_linv, fail, kb,
+                            nbk, lane);
 }
 
 // FP32 blocks take half the LDS, so two workgroups share a compute unit
@@ -222,8 +237,8 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 2) void k_jaclu_lds(const
   extern __shared__ __align__(16) unsigned char s_raw[];
   R* s_mem = reinterpret_cast<R*>(s_raw);
   __shared__ Tab<D, P, double> t;
-  __shared__ int s_prow[n];
-  __shared__ R s_linv[16 * 16];   // L11^{-1} of the current panel, row-major
+  __shared__ int s_prow2[2][n];   // logical row order (two buffers: look-ahead)
+  __shared__ R s_linv2[2][16 * 16];  // L11^{-1} of the current panel, row-major (two buffers: look-ahead)
   const int e = blockIdx.x;
   if (e >= ne) return;  // whole workgroup
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
@@ -254,7 +269,7 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 2) void k_jaclu_lds(const
     for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; }
     s_ph[(QV + lf * QF + k) * N + j] = R(phi_face<D, P, double>(t, j, lf, ta, ik));
   }
-  for (int k = tid; k < n; k += 512) s_prow[k] = k;
+  for (int k = tid; k < n; k += 512) s_prow2[0][k] = k;
   __syncthreads();
 
   // ---- assembly: job = (v, w, row tile it), two column tiles each
@@ -342,86 +357,178 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 2) void k_jaclu_lds(const
   }
   __syncthreads();
 
-  // ---- LU with partial pivoting, panels of 16 columns
-#pragma unroll 1
-  for (int kb = 0; kb < n; kb += 16) {
-    const int nbk = min(16, n - kb);
-    // (a) panel factorisation by wavefront 0 (with as many row slots as
-    // rows remain), then L11^{-1}
-    if (wv == 0) {
-      const int rows = n - kb;
-      if constexpr (RPL >= 3) {
-        if (rows > 128) panel_wave<3, n, LDA>(A, 0, s_prow, s_linv, fail, kb, nbk, lane);
-        else if (rows > 64) panel_wave<2, n, LDA>(A, 0, s_prow, s_linv, fail, kb, nbk, lane);
-        else panel_wave<1, n, LDA>(A, 0, s_prow, s_linv, fail, kb, nbk, lane);
-      } else {
-        if (rows > 64) panel_wave<2, n, LDA>(A, 0, s_prow, s_linv, fail, kb, nbk, lane);
-        else panel_wave<1, n, LDA>(A, 0, s_prow, s_linv, fail, kb, nbk, lane);
-      }
+  // ---- LU with partial pivoting, panels of 16 columns, with look-ahead:
+  // while wavefront 0 factorises panel k + 1, the others apply panel k's
+  // update to the columns beyond it.  The row order is double-buffered: the
+  // panel writes the new order into the other buffer while the update still
+  // reads the old one (the set of rows below the panel is the same in both).
+  auto panel = [&](int kb, int nbk, const int* pin, int* pout, R* s_linv) {
+    const int rows = n - kb;
+    if constexpr (RPL >= 3) {
+      if (rows > 128) panel_lds<3, n, LDA>(A, 0, pin, pout, s_linv, fail, kb, nbk, lane);
+      else if (rows > 64) panel_lds<2, n, LDA>(A, 0, pin, pout, s_linv, fail, kb, nbk, lane);
+      else panel_lds<1, n, LDA>(A, 0, pin, pout, s_linv, fail, kb, nbk, lane);
+    } else {
+      if (rows > 64) panel_lds<2, n, LDA>(A, 0, pin, pout, s_linv, fail, kb, nbk, lane);
+      else panel_lds<1, n, LDA>(A, 0, pin, pout, s_linv, fail, kb, nbk, lane);
     }
-    __syncthreads();
-    const int k1 = kb + nbk, m = n - k1;
-    if (m <= 0) break;
-    // (b, c) column tile tj of wavefront wv: U12 = L11^{-1} A12 on the matrix
-    // cores (its accumulator register r is the B operand of k-step r), then
-    // A22 -= L21 U12 for the row tiles of this wavefront; waves sharing a
-    // column tile split its row tiles and each forms the U12 tile
-    const int T = (m + 15) / 16;
-    const int per = NW / T > 0 ? NW / T : 1;   // wavefronts per column tile
-    const int tj = wv % T, sub = wv / T;
-    const bool act = wv < T * per;
+  };
+  // A22 tile (ti, tj) below and right of panel kb (nbk columns) -= L21 U12,
+  // rows in the order ord; one wavefront, every load issued before the products
+  auto tile = [&](const int* ord, int kb, int nbk, int k1, int ti, int tj) {
     const int cc = k1 + 16 * tj + il;
-    const bool cok = act && cc < n;
-    acc_t u = acc_t{R(0), R(0), R(0), R(0)};
-    if (act) {
+    const bool cok = cc < n;
+    int crow[4];
+    acc_t c;
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) {
-        const int k = 4 * s4 + kq;
-        const R a = s_linv[il * 16 + k];
-        const R b = (k < nbk && cok) ? A[cc * LDA + s_prow[kb + k]] : R(0);
-        u = MF::run(a, b, u);
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int lr = k1 + 16 * ti + MF::row(kq, r);
+      crow[r] = lr < n ? ord[lr] : -1;
+      c[r] = (crow[r] >= 0 && cok) ? A[cc * LDA + crow[r]] : R(0);
     }
-    __syncthreads();  // every wave sharing the tile has read A12 before U12 replaces it
-    if (act && sub == 0 && cok) {
+    const int alr = k1 + 16 * ti + il;
+    const int arow = alr < n ? ord[alr] : -1;
+    R a[4], b[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = MF::row(kq, r);
-        if (k < nbk) A[cc * LDA + s_prow[kb + k]] = u[r];
-      }
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int k = 4 * s4 + kq;
+      a[s4] = (arow >= 0 && k < nbk) ? -A[(kb + k) * LDA + arow] : R(0);
+      b[s4] = (k < nbk && cok) ? A[cc * LDA + ord[kb + k]] : R(0);
     }
-    // FP32: the accumulator layout is not the B-operand layout, so U12 is
-    // read back from LDS once it is complete
-    if constexpr (sizeof(R) == 4) __syncthreads();
-    if (act) {
-#pragma unroll 2
-      for (int ti = sub; ti < T; ti += per) {
-        int crow[4];
-        acc_t c;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int lr = k1 + 16 * ti + MF::row(kq, r);
-          crow[r] = lr < n ? s_prow[lr] : -1;
-          c[r] = (crow[r] >= 0 && cok) ? A[cc * LDA + crow[r]] : R(0);
-        }
-        const int alr = k1 + 16 * ti + il;
-        const int arow = alr < n ? s_prow[alr] : -1;
+    for (int s4 = 0; s4 < 4; ++s4) c = MF::run(a[s4], b[s4], c);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (crow[r] >= 0 && cok) A[cc * LDA + crow[r]] = c[r];
+  };
+  int cur = 1;
+  if constexpr (sizeof(R) == 4) {
+    // FP32: two workgroups share a compute unit, so the other one's work
+    // overlaps a panel; no look-ahead (its extra phases cost more than
+    // they hide here), one row-order buffer
+    cur = 0;
+#pragma unroll 1
+    for (int kb = 0; kb < n; kb += 16) {
+      const int nbk = min(16, n - kb);
+      if (wv == 0) panel(kb, nbk, s_prow2[0], s_prow2[0], s_linv2[0]);
+      __syncthreads();
+      const int k1 = kb + nbk, m = n - k1;
+      if (m <= 0) break;
+      const int* ord = s_prow2[0];
+      const R* s_linv = s_linv2[0];
+      const int T = (m + 15) / 16;
+#pragma unroll 1
+      for (int tj = wv; tj < T; tj += NW) {
+        const int cc = k1 + 16 * tj + il;
+        const bool cok = cc < n;
+        acc_t u = acc_t{R(0), R(0), R(0), R(0)};
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
           const int k = 4 * s4 + kq;
-          const R a = (arow >= 0 && k < nbk) ? -A[(kb + k) * LDA + arow] : R(0);
-          R b;
-          if constexpr (sizeof(R) == 8) b = u[s4];
-          else b = (k < nbk && cok) ? A[cc * LDA + s_prow[kb + k]] : R(0);
-          c = MF::run(a, b, c);
+          u = MF::run(s_linv[il * 16 + k], (k < nbk && cok) ? A[cc * LDA + ord[kb + k]] : R(0), u);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (crow[r] >= 0 && cok) A[cc * LDA + crow[r]] = c[r];
+        for (int r = 0; r < 4; ++r) {
+          const int k = MF::row(kq, r);
+          if (k < nbk && cok) A[cc * LDA + ord[kb + k]] = u[r];
+        }
       }
+      __syncthreads();
+#pragma unroll 2
+      for (int it = wv; it < T * T; it += NW) tile(ord, kb, nbk, k1, it % T, it / T);
+      __syncthreads();
     }
+  } else {
+    if (wv == 0) panel(0, min(16, n), s_prow2[0], s_prow2[1], s_linv2[1]);
     __syncthreads();
+    // FP64 (one workgroup per compute unit): per panel kb
+    //   phase 1: U12 of the column tiles beyond the next panel (in place),
+    //            and the next panel's columns (tile 0) updated with their
+    //            U12 tile formed in registers (the FP64 accumulator layout
+    //            is the B-operand layout), A12 of tile 0 left unchanged;
+    //   phase 2: wavefront 0 factorises the next panel (its L11^{-1} into
+    //            the other buffer); wavefront 1 stores U12 of tile 0 (pivot
+    //            rows, which the panel does not touch);
+    //            the wavefronts of the other SIMDs update the tiles beyond.
+#pragma unroll 1
+    for (int kb = 0;;) {
+      const int nbk = min(16, n - kb), k1 = kb + nbk, m = n - k1;
+      if (m <= 0) break;
+      const int* ord = s_prow2[cur];
+      const R* s_linv = s_linv2[cur];
+      const int T = (m + 15) / 16;
+      auto u12 = [&](int tj) {
+        const int cc = k1 + 16 * tj + il;
+        const bool cok = cc < n;
+        acc_t u = acc_t{R(0), R(0), R(0), R(0)};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int k = 4 * s4 + kq;
+          u = MF::run(s_linv[il * 16 + k], (k < nbk && cok) ? A[cc * LDA + ord[kb + k]] : R(0), u);
+        }
+        return u;
+      };
+#pragma unroll 1
+      for (int it = wv; it < 2 * T - 1; it += NW) {
+        if (it < T - 1) {
+          const int tj = 1 + it;
+          const acc_t u = u12(tj);
+          const int cc = k1 + 16 * tj + il;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int k = MF::row(kq, r);
+            if (k < nbk && cc < n) A[cc * LDA + ord[kb + k]] = u[r];
+          }
+        } else {
+          const int ti = it - (T - 1);
+          const acc_t u = u12(0);
+          const int cc = k1 + il;
+          const bool cok = cc < n;
+          int crow[4];
+          acc_t c;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int lr = k1 + 16 * ti + MF::row(kq, r);
+            crow[r] = lr < n ? ord[lr] : -1;
+            c[r] = (crow[r] >= 0 && cok) ? A[cc * LDA + crow[r]] : R(0);
+          }
+          const int alr = k1 + 16 * ti + il;
+          const int arow = alr < n ? ord[alr] : -1;
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int k = 4 * s4 + kq;
+            const R a = (arow >= 0 && k < nbk) ? -A[(kb + k) * LDA + arow] : R(0);
+            c = MF::run(a, u[s4], c);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (crow[r] >= 0 && cok) A[cc * LDA + crow[r]] = c[r];
+        }
+      }
+      __syncthreads();
+      if (wv == 0) {
+        panel(k1, min(16, n - k1), ord, s_prow2[cur ^ 1], s_linv2[cur ^ 1]);
+      } else if (wv == 1) {
+        const acc_t u = u12(0);
+        const int cc = k1 + il;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = MF::row(kq, r);
+          if (k < nbk && cc < n) A[cc * LDA + ord[kb + k]] = u[r];
+        }
+      }
+      if (wv % 4 != 0) {
+        // the SIMDs other than wavefront 0's (wavefront w runs on SIMD w mod 4)
+        const int slot = wv - 1 - wv / 4;  // 0 .. NW - NW / 4 - 1
+#pragma unroll 1
+        for (int it = slot; it < T * (T - 1); it += NW - NW / 4) tile(ord, kb, nbk, k1, it % T, 1 + it / T);
+      }
+      __syncthreads();
+      cur ^= 1;
+      kb = k1;
+    }
   }
+  const int* s_prow = s_prow2[cur];
 
   // ---- factors in pivot order, column-major, and the permutation
   R* o = out + (size_t)e * n * n;
@@ -654,11 +761,11 @@ __global__ __launch_bounds__(512, sizeof(R) == 4 ? 4 : 2) void k_jaclu_big(
     __syncthreads();
     if (wv == 0) {
       const int rows = n - kb;
-      if (rows > 256) panel_wave<5, n, n>(s_pan, kb, s_prow, s_linv, fail, kb, 16, lane);
-      else if (rows > 192) panel_wave<4, n, n>(s_pan, kb, s_prow, s_linv, fail, kb, 16, lane);
-      else if (rows > 128) panel_wave<3, n, n>(s_pan, kb, s_prow, s_linv, fail, kb, 16, lane);
-      else if (rows > 64) panel_wave<2, n, n>(s_pan, kb, s_prow, s_linv, fail, kb, 16, lane);
-      else panel_wave<1, n, n>(s_pan, kb, s_prow, s_linv, fail, kb, 16, lane);
+      if (rows > 256) panel_lds<5, n, n>(s_pan, kb, s_prow, s_prow, s_linv, fail, kb, 16, lane);
+      else if (rows > 192) panel_lds<4, n, n>(s_pan, kb, s_prow, s_prow, s_linv, fail, kb, 16, lane);
+      else if (rows > 128) panel_lds<3, n, n>(s_pan, kb, s_prow, s_prow, s_linv, fail, kb, 16, lane);
+      else if (rows > 64) panel_lds<2, n, n>(s_pan, kb, s_prow, s_prow, s_linv, fail, kb, 16, lane);
+      else panel_lds<1, n, n>(s_pan, kb, s_prow, s_prow, s_linv, fail, kb, 16, lane);
     }
     __syncthreads();
     for (int it = tid; it < 16 * n; it += 512) A[(size_t)kb * n + it] = s_pan[it];
