@@ -501,6 +501,13 @@ def main():
         extras["calibration_copy_bytes"] = nb
         log(f"[bench] calibration copy of {nb} bytes done")
     cpu = None if args.no_cpu_baseline else cpu_baseline(mesh, p)
+    fd = config.get("fp64_drop") or {}
+    if cpu and fd.get("converged"):
+        # labelled extrapolation: the GPU FP64 solve's cycle count times the
+        # oracle's measured seconds per cycle (the oracle is not run to the drop)
+        per_cycle = mesh.n_elem * 5 * 27 / cpu["value"]
+        cpu["time_to_1e-10_extrapolated_s"] = round(fd["cycles_to_1e-10"] * per_cycle, 1)
+        cpu["extrapolation"] = "cycles_to_1e-10 of the FP64 GPU solve x the oracle's seconds per V-cycle"
     line = {
         "metric": "V-cycle DOF-updates/s & time to 1e-10 residual drop, FP64 vs mixed precision",
         "value": dof * args.steps / wall,
