@@ -19,5 +19,9 @@ from .meshes import (  # noqa: F401
     radial_map,
     wall_bumps,
     reorient,
+    mapped,
+    straight_nodes,
+    QUAD9_REF,
+    QUAD9_CORNER,
 )
 from .draws import batch_draws, bump_centers, seeded_array  # noqa: F401

@@ -1,5 +1,5 @@
-"""Synthetic straight-sided quad / hex meshes standing in for the paper's
-cylinder (Section 5.1) and sphere (Section 5.2) grids.
+"""Synthetic quad / hex meshes standing in for the paper's cylinder
+(Section 5.1, quadratic curved elements) and sphere (Section 5.2) grids.
 
 Conventions shared by every consumer (they are the input format, not method
 arithmetic):
@@ -12,6 +12,11 @@ arithmetic):
   ``xi_r = -1`` (s = 0) or ``xi_r = +1`` (s = 1).  Tags: 0 interior (matched
   to a neighbour through its shared vertices), 1 slip wall, 2 far-field,
   3 exact-state ghost (manufactured-solution tests of the oracle only).
+* ``elem_geo`` (2D only, optional) is ``float64[n_elem, 9, 2]``: the nodes of a
+  biquadratic element map; node ``a + 3 b`` sits at reference point
+  ``(a - 1, b - 1)``, so nodes 0, 2, 6, 8 are the vertices ``elem_vert[:, 0..3]``
+  and nodes 1, 3, 5, 7 the edge midpoints.  ``None`` means straight-sided
+  (bilinear) elements.
 """
 
 from __future__ import annotations
@@ -34,6 +39,7 @@ class Mesh:
     elem_vert: np.ndarray  # int32 [n_elem, 2**dim]
     bface_tag: np.ndarray  # int8 [n_elem, 2*dim]
     name: str = ""
+    elem_geo: np.ndarray | None = None  # float64 [n_elem, 9, 2] (2D curved) or None
 
     @property
     def n_elem(self) -> int:
@@ -48,7 +54,45 @@ class Mesh:
                     np.ascontiguousarray(self.xyz, dtype=np.float64),
                     np.ascontiguousarray(self.elem_vert, dtype=np.int32),
                     np.ascontiguousarray(self.bface_tag, dtype=np.int8),
-                    self.name)
+                    self.name,
+                    None if self.elem_geo is None else np.ascontiguousarray(self.elem_geo, dtype=np.float64))
+
+
+# Reference positions (a - 1, b - 1) of the nine nodes a + 3 b of a biquadratic quad.
+QUAD9_REF = np.array([[a - 1, b - 1] for b in range(3) for a in range(3)], dtype=np.int64)
+# node index of each bilinear corner a + 2 b
+QUAD9_CORNER = (0, 2, 6, 8)
+
+
+def straight_nodes(mesh: Mesh) -> np.ndarray:
+    """float64[n_elem, 9, 2]: the nine nodes of each element's bilinear map
+    (corners at the vertices, edge nodes at edge midpoints, the centre node at
+    the mean of the corners), i.e. the straight-sided element written as a
+    biquadratic one."""
+    if mesh.dim != 2:
+        raise ValueError("nine-node elements are 2D only")
+    X = mesh.xyz[mesh.elem_vert]  # [E, 4, 2], corner a + 2 b
+    geo = np.empty((mesh.n_elem, 9, 2))
+    for k, (a, b) in enumerate(QUAD9_REF + 1):
+        wa = (1.0 - 0.5 * a, 0.5 * a)
+        wb = (1.0 - 0.5 * b, 0.5 * b)
+        geo[:, k] = sum(wa[i] * wb[j] * X[:, i + 2 * j] for i in range(2) for j in range(2))
+    return geo
+
+
+def mapped(mesh: Mesh, fn, name: str = "") -> Mesh:
+    """Curved 2D mesh: every node of the straight mesh (vertices and the nine
+    bilinear nodes of each element) moved through the smooth map
+    ``fn(float64[n, 2]) -> float64[n, 2]``.  Shared edges keep shared nodes
+    because both neighbours evaluate ``fn`` at the same straight-edge point."""
+    if mesh.dim != 2:
+        raise ValueError("curved elements are 2D only")
+    base = straight_nodes(mesh) if mesh.elem_geo is None else mesh.elem_geo
+    geo = fn(base.reshape(-1, 2)).reshape(base.shape)
+    xyz = fn(np.array(mesh.xyz, dtype=np.float64))
+    for i, k in enumerate(QUAD9_CORNER):
+        geo[:, k] = xyz[mesh.elem_vert[:, i]]
+    return Mesh(2, xyz, mesh.elem_vert.copy(), mesh.bface_tag.copy(), name or mesh.name + "+mapped", geo)
 
 
 def radial_map(n_r: int, r_in: float = 0.5, r_out: float = 20.0,
@@ -69,7 +113,7 @@ def radial_map(n_r: int, r_in: float = 0.5, r_out: float = 20.0,
 
 def ogrid(n_theta: int, n_r: int, r_in: float = 0.5, r_out: float = 20.0,
           stretch: float = 1.2, n_ref: int = 12, inner: int = TAG_WALL,
-          outer: int = TAG_FARFIELD) -> Mesh:
+          outer: int = TAG_FARFIELD, curved: bool = False) -> Mesh:
     """Structured O-grid of quads around a circle of radius ``r_in``.
 
     Element (i, j), i circumferential (periodic), j radial (j = 0 touches the
@@ -77,6 +121,10 @@ def ogrid(n_theta: int, n_r: int, r_in: float = 0.5, r_out: float = 20.0,
     counter-clockwise in theta, so the map is positively oriented; face 0 is
     the inner arc (``inner`` tag at j = 0), face 1 the outer arc (``outer`` tag
     at j = n_r - 1), faces 2/3 the two radial edges.
+
+    ``curved`` adds biquadratic element nodes: the mid-arc nodes sit on the
+    circles (angle halfway between the two vertices), the radial edges stay
+    straight with their midpoints halfway in r.
     """
     if n_theta < 3 or n_r < 1:
         raise ValueError("ogrid needs n_theta >= 3 and n_r >= 1")
@@ -109,7 +157,33 @@ def ogrid(n_theta: int, n_r: int, r_in: float = 0.5, r_out: float = 20.0,
                 tag[e, 0] = inner
             if j == n_r - 1:
                 tag[e, 1] = outer
-    return Mesh(2, xyz, ev, tag, f"ogrid{n_theta}x{n_r}")
+    if not curved:
+        return Mesh(2, xyz, ev, tag, f"ogrid{n_theta}x{n_r}")
+    # node grid: 2 n_theta angles (vertex angles, then the mid angles) by
+    # 2 n_r + 1 radii; every element reads its nine nodes from it, so shared
+    # edges share bit-identical nodes
+    thm = 2.0 * math.pi * (np.arange(n_theta, dtype=np.float64) + 0.5) / n_theta
+    cm, sm = np.cos(thm), np.sin(thm)
+    for i in range(n_theta):  # exact axis points, as for the vertices
+        if 2 * (2 * i + 1) == n_theta:
+            cm[i], sm[i] = 0.0, 1.0
+        elif 2 * i + 1 == n_theta:
+            cm[i], sm[i] = -1.0, 0.0
+        elif 2 * (2 * i + 1) == 3 * n_theta:
+            cm[i], sm[i] = 0.0, -1.0
+    rr = np.empty(2 * n_r + 1)
+    rr[0::2] = r
+    rr[1::2] = 0.5 * (r[:-1] + r[1:])
+    geo = np.empty((n_r * n_theta, 9, 2))
+    for j in range(n_r):
+        for i in range(n_theta):
+            e = j * n_theta + i
+            ip = (i + 1) % n_theta
+            for k, (a, b) in enumerate(QUAD9_REF + 1):
+                rad = rr[2 * j + a]
+                cc, ss = ((c[i], s[i]), (cm[i], sm[i]), (c[ip], s[ip]))[b]
+                geo[e, k] = (rad * cc, rad * ss)
+    return Mesh(2, xyz, ev, tag, f"ogrid{n_theta}x{n_r}c", geo)
 
 
 _PANELS = (
@@ -233,17 +307,26 @@ def wall_bumps(mesh: Mesh, amps, centers, sigma: float, r_in: float = 0.5,
     """
     amps = np.asarray(amps, dtype=np.float64)
     centers = np.asarray(centers, dtype=np.float64).reshape(len(amps), mesh.dim)
-    x = np.array(mesh.xyz, dtype=np.float64)
-    r = np.sqrt(np.sum(x * x, axis=1))
-    xh = x / r[:, None]
-    w = np.clip((r_out - r) / (r_out - r_in), 0.0, 1.0)
-    delta = np.zeros_like(r)
-    for a, c in zip(amps, centers):
-        c = c / np.sqrt(float(c @ c))
-        th = np.arccos(np.clip(xh @ c, -1.0, 1.0))
-        delta += a * np.exp(-th * th / (2.0 * sigma * sigma))
-    xyz = xh * (r + delta * w)[:, None]
-    return Mesh(mesh.dim, xyz, mesh.elem_vert.copy(), mesh.bface_tag.copy(), mesh.name + "+bumps")
+
+    def move(x):
+        x = np.array(x, dtype=np.float64)
+        r = np.sqrt(np.sum(x * x, axis=1))
+        xh = x / r[:, None]
+        w = np.clip((r_out - r) / (r_out - r_in), 0.0, 1.0)
+        delta = np.zeros_like(r)
+        for a, c in zip(amps, centers):
+            c = c / np.sqrt(float(c @ c))
+            th = np.arccos(np.clip(xh @ c, -1.0, 1.0))
+            delta += a * np.exp(-th * th / (2.0 * sigma * sigma))
+        return xh * (r + delta * w)[:, None]
+
+    xyz = move(mesh.xyz)
+    geo = None
+    if mesh.elem_geo is not None:  # curved nodes move with the same field
+        geo = move(mesh.elem_geo.reshape(-1, 2)).reshape(mesh.elem_geo.shape)
+        for i, k in enumerate(QUAD9_CORNER):
+            geo[:, k] = xyz[mesh.elem_vert[:, i]]
+    return Mesh(mesh.dim, xyz, mesh.elem_vert.copy(), mesh.bface_tag.copy(), mesh.name + "+bumps", geo)
 
 
 def _rotations(dim: int):
@@ -276,13 +359,18 @@ def reorient(mesh: Mesh, seed: int) -> Mesh:
     index_of = {tuple(c): k for k, c in enumerate(corners)}
     ev = np.empty_like(mesh.elem_vert)
     tg = np.empty_like(mesh.bface_tag)
+    geo = None if mesh.elem_geo is None else np.empty_like(mesh.elem_geo)
+    node_of = {tuple(c): k for k, c in enumerate(QUAD9_REF)}
     for e in range(mesh.n_elem):
         S = rots[pick[e]]
         for k in range(nc):
             ev[e, k] = mesh.elem_vert[e, index_of[tuple(S @ corners[k])]]
+        if geo is not None:
+            for k in range(9):
+                geo[e, k] = mesh.elem_geo[e, node_of[tuple(S @ QUAD9_REF[k])]]
         for rn in range(dim):
             r = int(np.nonzero(S[:, rn])[0][0])
             for s in (-1, 1):
                 so = S[r, rn] * s
                 tg[e, 2 * rn + (s > 0)] = mesh.bface_tag[e, 2 * r + (so > 0)]
-    return Mesh(dim, mesh.xyz.copy(), ev, tg, mesh.name + f"+reoriented{seed}")
+    return Mesh(dim, mesh.xyz.copy(), ev, tg, mesh.name + f"+reoriented{seed}", geo)

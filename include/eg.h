@@ -62,6 +62,13 @@ typedef struct {
   const int8_t* bface_tag;  /* host, [n_elem][2 dim]; local face 2r+s is xi_r = -1 (s=0)
                                or +1 (s=1).  0 interior (matched to the neighbour
                                that shares its vertices), 1 slip wall, 2 far-field */
+  const double* elem_geo;   /* host, optional (null = straight-sided elements); 2D only:
+                               [n_elem][9][2] nodes of a biquadratic (quadratic curved)
+                               element map, node a+3b at reference point (a-1, b-1)
+                               (Section 5.1 meshes).  Nodes 0, 2, 6, 8 must equal the
+                               vertices 0..3 and the edge node of every interior face
+                               the neighbour's (within 1e-12 relative), else
+                               EG_ERR_MESH; with a 3D mesh, EG_ERR_UNSUPPORTED.  Copied */
 } eg_mesh;
 
 typedef struct {

@@ -36,7 +36,7 @@ def lib():
             build(force=False)
         L = C.CDLL(_LIB)
         L.orc_create.restype = C.c_void_p
-        L.orc_create.argtypes = [C.c_int, C.c_int, _d, C.c_int, _i32, C.POINTER(C.c_int8), C.c_int,
+        L.orc_create.argtypes = [C.c_int, C.c_int, _d, C.c_int, _i32, C.POINTER(C.c_int8), _d, C.c_int,
                                  C.c_double, C.c_double, C.c_double, C.c_double, C.c_char_p, C.c_int]
         L.orc_free.argtypes = [C.c_void_p]
         L.orc_set_threads.argtypes = [C.c_int]
@@ -201,8 +201,8 @@ class Oracle:
         self.mach = mach
         self.alpha_deg, self.beta_deg = alpha_deg, beta_deg
         err = C.create_string_buffer(256)
-        h = lib().orc_create(m.dim, m.n_vert, _p(m.xyz), m.n_elem, _p(m.elem_vert), _p(m.bface_tag), pmax,
-                             gamma, mach, alpha_deg, beta_deg, err, 256)
+        h = lib().orc_create(m.dim, m.n_vert, _p(m.xyz), m.n_elem, _p(m.elem_vert), _p(m.bface_tag),
+                             _p(getattr(m, "elem_geo", None)), pmax, gamma, mach, alpha_deg, beta_deg, err, 256)
         if not h:
             raise ValueError("oracle mesh set-up failed: " + err.value.decode())
         self._h = C.c_void_p(h)

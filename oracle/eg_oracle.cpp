@@ -21,6 +21,9 @@
 //     s_i [chi_i + sum_{j<i} c_ij chi_j], i.e. a lower-triangular transform).
 //   * Numerical flux: Rusanov (local Lax-Friedrichs); boundary fluxes use the
 //     same flux with a ghost state (Section 3.3, boundary flux equation).
+//   * Element map: multilinear through the 2^d vertices, or in 2D, when the
+//     mesh carries nine nodes per element, the biquadratic Lagrange map
+//     through them (quadratic curved elements, Section 5.1).
 //
 // Build: g++ -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC.
 
@@ -170,6 +173,7 @@ struct Oracle {
   std::vector<double> xyz;
   std::vector<int> ev;
   std::vector<signed char> tag;
+  std::vector<double> geo;  // 2D curved: [E][9][2], node a + 3b at (a-1, b-1); empty = straight
   std::vector<Face> faces;
   std::vector<int> efc, eside;  // [E][2d] face id and side (0 = L, 1 = R)
   std::vector<double> T;        // [E][N][N], N = N_pmax, lower triangular
@@ -200,10 +204,49 @@ void embed(int d, int f, const double* s, double* xi) {
 // Multilinear map x(xi), tangents t[r] = dx/dxi_r, det and the vectors
 // c[r] with c[r] . t[r'] = det delta_{r r'} (det * grad_x = sum_r c[r] d/dxi_r;
 // the scaled outward normal of face (r, s) is (2s - 1) c[r]).
+// One-dimensional Lagrange polynomial of node a over the nodes -1, 0, 1, and
+// its derivative (product rule over the factors).
+double lagrange3(int a, double z) {
+  const double zn[3] = {-1.0, 0.0, 1.0};
+  double v = 1.0;
+  for (int m = 0; m < 3; ++m) if (m != a) v *= (z - zn[m]) / (zn[a] - zn[m]);
+  return v;
+}
+double lagrange3_deriv(int a, double z) {
+  const double zn[3] = {-1.0, 0.0, 1.0};
+  double sum = 0.0;
+  for (int j = 0; j < 3; ++j) {
+    if (j == a) continue;
+    double v = 1.0 / (zn[a] - zn[j]);
+    for (int m = 0; m < 3; ++m) if (m != a && m != j) v *= (z - zn[m]) / (zn[a] - zn[m]);
+    sum += v;
+  }
+  return sum;
+}
+
 void geom(const Oracle& O, int e, const double* xi, double* x, double t[MAXD][MAXD],
           double& det, double c[MAXD][MAXD]) {
   const int d = O.d, nc = 1 << d;
   for (int a = 0; a < d; ++a) { x[a] = 0.0; for (int r = 0; r < d; ++r) t[r][a] = 0.0; }
+  if (!O.geo.empty()) {
+    // x(xi, eta) = sum over nodes of l_a(xi) l_b(eta) X_{a+3b}
+    for (int b = 0; b < 3; ++b)
+      for (int a = 0; a < 3; ++a) {
+        const double* X = &O.geo[((size_t)e * 9 + a + 3 * b) * 2];
+        const double N = lagrange3(a, xi[0]) * lagrange3(b, xi[1]);
+        const double dN0 = lagrange3_deriv(a, xi[0]) * lagrange3(b, xi[1]);
+        const double dN1 = lagrange3(a, xi[0]) * lagrange3_deriv(b, xi[1]);
+        for (int q = 0; q < 2; ++q) {
+          x[q] += N * X[q];
+          t[0][q] += dN0 * X[q];
+          t[1][q] += dN1 * X[q];
+        }
+      }
+    det = t[0][0] * t[1][1] - t[0][1] * t[1][0];
+    c[0][0] = t[1][1]; c[0][1] = -t[1][0];
+    c[1][0] = -t[0][1]; c[1][1] = t[0][0];
+    return;
+  }
   for (int k = 0; k < nc; ++k) {
     const double* X = &O.xyz[(size_t)O.ev[(size_t)e * nc + k] * d];
     double N = 1.0, dN[MAXD];
@@ -626,6 +669,31 @@ bool setup(Oracle& O) {
     }
   }
   if (!open.empty()) { O.err = "unmatched interior face"; return false; }
+  if (!O.geo.empty()) {
+    // curved quads: corner nodes are the vertices, and the two sides of an
+    // interior edge share its middle node
+    auto same = [](const double* a, const double* b) {
+      for (int q = 0; q < 2; ++q)
+        if (std::fabs(a[q] - b[q]) > 1e-12 * std::max(1.0, std::fabs(a[q]))) return false;
+      return true;
+    };
+    const int corner_node[4] = {0, 2, 6, 8};
+    for (int e = 0; e < O.ne; ++e)
+      for (int k = 0; k < 4; ++k)
+        if (!same(&O.geo[((size_t)e * 9 + corner_node[k]) * 2], &O.xyz[(size_t)O.ev[(size_t)e * 4 + k] * 2])) {
+          O.err = "curved element node at a corner differs from its vertex";
+          return false;
+        }
+    auto mid = [&](int e, int f) {
+      const int a = f / 2 == 0 ? 2 * (f % 2) : 1, b = f / 2 == 0 ? 1 : 2 * (f % 2);
+      return &O.geo[((size_t)e * 9 + a + 3 * b) * 2];
+    };
+    for (const Face& F : O.faces)
+      if (F.eR >= 0 && !same(mid(F.eL, F.fL), mid(F.eR, F.fR))) {
+        O.err = "non-conforming curved face";
+        return false;
+      }
+  }
 
   // Geometry and per-element orthonormalisation with the (pmax+2)-point rule,
   // which integrates phi_i phi_j det exactly on multilinear elements.
@@ -1305,8 +1373,9 @@ double cfl_ramp(double cfl_max, double rn, double rref, int n, int pmax) {
 // ===========================================================================
 extern "C" {
 
-void* orc_create(int dim, int n_vert, const double* xyz, int n_elem, const int32_t* ev, const int8_t* tag, int pmax,
-                 double gamma, double mach, double alpha_deg, double beta_deg, char* errbuf, int errlen) {
+void* orc_create(int dim, int n_vert, const double* xyz, int n_elem, const int32_t* ev, const int8_t* tag,
+                 const double* geo, int pmax, double gamma, double mach, double alpha_deg, double beta_deg,
+                 char* errbuf, int errlen) {
   Oracle* O = new Oracle;
   O->d = dim;
   O->nv = n_vert;
@@ -1319,7 +1388,9 @@ void* orc_create(int dim, int n_vert, const double* xyz, int n_elem, const int32
   O->xyz.assign(xyz, xyz + (size_t)n_vert * dim);
   O->ev.assign(ev, ev + (size_t)n_elem * (1 << dim));
   O->tag.assign(tag, tag + (size_t)n_elem * 2 * dim);
-  if ((dim != 2 && dim != 3) || pmax < 0 || pmax > 6 || !setup(*O)) {
+  if (geo && dim == 2) O->geo.assign(geo, geo + (size_t)n_elem * 18);
+  if (geo && dim != 2) O->err = "curved elements are 2D only";
+  if ((dim != 2 && dim != 3) || pmax < 0 || pmax > 6 || (geo && dim != 2) || !setup(*O)) {
     if (errbuf && errlen > 0) std::snprintf(errbuf, errlen, "%s", O->err.c_str());
     delete O;
     return nullptr;

@@ -34,7 +34,17 @@ class EgError(RuntimeError):
 
 class _Mesh(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_vert", C.c_int), ("xyz", C.POINTER(C.c_double)), ("n_elem", C.c_int),
-                ("elem_vert", C.POINTER(C.c_int32)), ("bface_tag", C.POINTER(C.c_int8))]
+                ("elem_vert", C.POINTER(C.c_int32)), ("bface_tag", C.POINTER(C.c_int8)),
+                ("elem_geo", C.POINTER(C.c_double))]
+
+
+def _c_mesh(m) -> _Mesh:
+    """eg_mesh view of a contiguous mesh (the arrays must outlive the call)."""
+    geo = getattr(m, "elem_geo", None)
+    return _Mesh(m.dim, m.n_vert, m.xyz.ctypes.data_as(C.POINTER(C.c_double)), m.n_elem,
+                 m.elem_vert.ctypes.data_as(C.POINTER(C.c_int32)),
+                 m.bface_tag.ctypes.data_as(C.POINTER(C.c_int8)),
+                 None if geo is None else geo.ctypes.data_as(C.POINTER(C.c_double)))
 
 
 class _Params(C.Structure):
@@ -140,10 +150,8 @@ class Solver:
         import torch
         L = lib()
         m = mesh.contiguous()
-        self._keep = (m.xyz, m.elem_vert, m.bface_tag)
-        cm = _Mesh(m.dim, m.n_vert, m.xyz.ctypes.data_as(C.POINTER(C.c_double)), m.n_elem,
-                   m.elem_vert.ctypes.data_as(C.POINTER(C.c_int32)),
-                   m.bface_tag.ctypes.data_as(C.POINTER(C.c_int8)))
+        self._keep = (m.xyz, m.elem_vert, m.bface_tag, m.elem_geo)
+        cm = _c_mesh(m)
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         if flux not in FLUXES:
@@ -421,10 +429,8 @@ class BatchSolver:
         alphas = [0.0] * n if alphas is None else list(alphas)
         betas = [0.0] * n if betas is None else list(betas)
         ms = [m.contiguous() for m in meshes]
-        self._keep = [(m.xyz, m.elem_vert, m.bface_tag) for m in ms]
-        cms = (_Mesh * n)(*[_Mesh(m.dim, m.n_vert, m.xyz.ctypes.data_as(C.POINTER(C.c_double)), m.n_elem,
-                                  m.elem_vert.ctypes.data_as(C.POINTER(C.c_int32)),
-                                  m.bface_tag.ctypes.data_as(C.POINTER(C.c_int8))) for m in ms])
+        self._keep = [(m.xyz, m.elem_vert, m.bface_tag, m.elem_geo) for m in ms]
+        cms = (_Mesh * n)(*[_c_mesh(m) for m in ms])
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         if flux not in FLUXES:

@@ -8,8 +8,14 @@ namespace eg {
 
 constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
+// Geometry nodes per element: quads carry the nine nodes of a biquadratic
+// map (quadratic curved elements, Section 5.1; straight ones have their edge
+// and centre nodes at the bilinear positions), hexes their eight vertices.
+constexpr int geo_nodes(int D) { return D == 2 ? 9 : 8; }
+
 // Sizes of order P in dimension D: V variables, Q Gauss points per axis,
-// N = (P+1)^D modes, QV volume points, QF points per face, NF faces, NC corners.
+// N = (P+1)^D modes, QV volume points, QF points per face, NF faces, NC
+// geometry nodes.
 template <int D, int P>
 struct Cfg {
   static constexpr int V = D + 2;
@@ -18,7 +24,7 @@ struct Cfg {
   static constexpr int QV = ipow(Q, D);
   static constexpr int QF = ipow(Q, D - 1);
   static constexpr int NF = 2 * D;
-  static constexpr int NC = 1 << D;
+  static constexpr int NC = geo_nodes(D);
   static constexpr int NB = V * N;  // block size of the element operator
 };
 

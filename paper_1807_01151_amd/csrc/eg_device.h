@@ -57,9 +57,10 @@ inline void fill_tab(Tab<D, P, R>& t, const TabData& td) {
 // helpers
 // ---------------------------------------------------------------------------
 
-// Multilinear element map: the vectors c[r] with c[r] . (dx/dxi_r') = det
-// delta_rr', i.e. det * grad_x = sum_r c[r] d/dxi_r; (2s-1) c[r] is the scaled
-// outward normal of face (r, s).
+// Element map (biquadratic through nine nodes in 2D, trilinear in 3D): the
+// vectors c[r] with c[r] . (dx/dxi_r') = det delta_rr', i.e.
+// det * grad_x = sum_r c[r] d/dxi_r; (2s-1) c[r] is the scaled outward
+// normal of face (r, s).
 template <int D, class R>
 __device__ __forceinline__ void geom(const R* X, const R* xi, R c[D][D], R& det) {
   R t[D][D];
@@ -67,29 +68,51 @@ __device__ __forceinline__ void geom(const R* X, const R* xi, R c[D][D], R& det)
   for (int r = 0; r < D; ++r)
 #pragma unroll
     for (int a = 0; a < D; ++a) t[r][a] = R(0);
-#pragma unroll
-  for (int k = 0; k < (1 << D); ++k) {
-    R g[D];
-#pragma unroll
-    for (int r = 0; r < D; ++r) {
-      R v = R(1);
-#pragma unroll
-      for (int q = 0; q < D; ++q) {
-        R s = ((k >> q) & 1) ? R(1) : R(-1);
-        v *= (q == r) ? R(0.5) * s : R(0.5) * (R(1) + s * xi[q]);
-      }
-      g[r] = v;
-    }
-#pragma unroll
-    for (int r = 0; r < D; ++r)
-#pragma unroll
-      for (int a = 0; a < D; ++a) t[r][a] += g[r] * X[k * D + a];
-  }
   if constexpr (D == 2) {
+    // quadratic Lagrange factors through -1, 0, 1 and their derivatives
+    const R x = xi[0], y = xi[1];
+    const R lx[3] = {R(0.5) * x * (x - R(1)), R(1) - x * x, R(0.5) * x * (x + R(1))};
+    const R dx[3] = {x - R(0.5), R(-2) * x, x + R(0.5)};
+    const R ly[3] = {R(0.5) * y * (y - R(1)), R(1) - y * y, R(0.5) * y * (y + R(1))};
+    const R dy[3] = {y - R(0.5), R(-2) * y, y + R(0.5)};
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      R s0[2] = {R(0), R(0)}, s1[2] = {R(0), R(0)};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          s0[q] += dx[a] * X[(a + 3 * b) * 2 + q];
+          s1[q] += lx[a] * X[(a + 3 * b) * 2 + q];
+        }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        t[0][q] += ly[b] * s0[q];
+        t[1][q] += dy[b] * s1[q];
+      }
+    }
     c[0][0] = t[1][1]; c[0][1] = -t[1][0];
     c[1][0] = -t[0][1]; c[1][1] = t[0][0];
     det = t[0][0] * t[1][1] - t[0][1] * t[1][0];
   } else {
+#pragma unroll
+    for (int k = 0; k < (1 << D); ++k) {
+      R g[D];
+#pragma unroll
+      for (int r = 0; r < D; ++r) {
+        R v = R(1);
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          R s = ((k >> q) & 1) ? R(1) : R(-1);
+          v *= (q == r) ? R(0.5) * s : R(0.5) * (R(1) + s * xi[q]);
+        }
+        g[r] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < D; ++r)
+#pragma unroll
+        for (int a = 0; a < D; ++a) t[r][a] += g[r] * X[k * D + a];
+    }
     c[0][0] = t[1][1] * t[2][2] - t[1][2] * t[2][1];
     c[0][1] = t[1][2] * t[2][0] - t[1][0] * t[2][2];
     c[0][2] = t[1][0] * t[2][1] - t[1][1] * t[2][0];

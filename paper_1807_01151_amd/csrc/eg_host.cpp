@@ -204,10 +204,23 @@ void fill_tabdata(TabData& t, int d, int p, const std::vector<std::array<int, 3>
     for (int r = 0; r < 3; ++r) t.m[k][r] = modes[k][r];
 }
 
-// Tangents of the multilinear map at xi; returns det and c[r] (see geom in
-// the kernels).
+// Tangents of the element map at xi (biquadratic through nine nodes in 2D,
+// trilinear in 3D); returns det and c[r] (see geom in the kernels).
 double host_geom(int d, const double* X, const double* xi, double c[3][3]) {
   double t[3][3] = {};
+  if (d == 2) {
+    auto l = [](int a, double z) { return a == 0 ? 0.5 * z * (z - 1.0) : a == 1 ? 1.0 - z * z : 0.5 * z * (z + 1.0); };
+    auto dl = [](int a, double z) { return a == 0 ? z - 0.5 : a == 1 ? -2.0 * z : z + 0.5; };
+    for (int b = 0; b < 3; ++b)
+      for (int a = 0; a < 3; ++a)
+        for (int q = 0; q < 2; ++q) {
+          t[0][q] += dl(a, xi[0]) * l(b, xi[1]) * X[(a + 3 * b) * 2 + q];
+          t[1][q] += l(a, xi[0]) * dl(b, xi[1]) * X[(a + 3 * b) * 2 + q];
+        }
+    c[0][0] = t[1][1]; c[0][1] = -t[1][0];
+    c[1][0] = -t[0][1]; c[1][1] = t[0][0];
+    return t[0][0] * t[1][1] - t[0][1] * t[1][0];
+  }
   for (int k = 0; k < (1 << d); ++k)
     for (int r = 0; r < d; ++r) {
       double g = 1.0;
@@ -293,17 +306,51 @@ hipEvent_t next_event(eg_handle* h) {
 // the neighbour's face points, element geometry (|E|, |dE|, h_E) and the
 // Cholesky factor of the phi mass matrix, all with the (p_max+2)-point rule
 // (exact for the mass matrix of multilinear elements).
+// The nine nodes of a straight-sided quad (corners Xc[a + 2b]): the bilinear
+// map written as a biquadratic one.
+void straight_nodes9(const double Xc[][3], double* X) {
+  for (int b = 0; b < 3; ++b)
+    for (int a = 0; a < 3; ++a)
+      for (int q = 0; q < 2; ++q) {
+        const double wa[2] = {1.0 - 0.5 * a, 0.5 * a}, wb[2] = {1.0 - 0.5 * b, 0.5 * b};
+        double v = 0.0;
+        for (int j = 0; j < 2; ++j)
+          for (int i = 0; i < 2; ++i) v += wa[i] * wb[j] * Xc[i + 2 * j][q];
+        X[(a + 3 * b) * 2 + q] = v;
+      }
+}
+
 eg_status setup_mesh(eg_handle* h, const eg_mesh* mesh, std::vector<double>& xv, std::vector<int>& nbr,
                      std::vector<uint8_t>& ncode, std::vector<double>& Lpk, std::vector<double>& Gpk,
                      std::vector<double>& hE, double& omega, std::vector<double>& vol) {
   const int d = mesh->dim, ne = mesh->n_elem, nf = 2 * d, nc = 1 << d, ncf = 1 << (d - 1);
-  xv.assign((size_t)ne * nc * d, 0.0);
-  for (int e = 0; e < ne; ++e)
+  const int ng = eg::geo_nodes(d);  // geometry nodes per element
+  if (mesh->elem_geo && d != 2) return fail(h, EG_ERR_UNSUPPORTED, "curved elements are 2D only");
+  auto near = [](double a, double b) { return std::fabs(a - b) <= 1e-12 * std::max(1.0, std::fabs(a)); };
+  xv.assign((size_t)ne * ng * d, 0.0);
+  for (int e = 0; e < ne; ++e) {
+    double Xc[8][3];
     for (int k = 0; k < nc; ++k) {
       int vid = mesh->elem_vert[(size_t)e * nc + k];
       if (vid < 0 || vid >= mesh->n_vert) return fail(h, EG_ERR_MESH, "vertex index out of range");
-      for (int a = 0; a < d; ++a) xv[((size_t)e * nc + k) * d + a] = mesh->xyz[(size_t)vid * d + a];
+      for (int a = 0; a < d; ++a) Xc[k][a] = mesh->xyz[(size_t)vid * d + a];
     }
+    double* X = &xv[(size_t)e * ng * d];
+    if (d == 3) {
+      for (int k = 0; k < nc; ++k)
+        for (int a = 0; a < d; ++a) X[k * d + a] = Xc[k][a];
+    } else if (mesh->elem_geo) {
+      const double* G = &mesh->elem_geo[(size_t)e * 18];
+      for (int k = 0; k < 18; ++k) X[k] = G[k];
+      static const int corner_node[4] = {0, 2, 6, 8};
+      for (int k = 0; k < 4; ++k)
+        for (int a = 0; a < 2; ++a)
+          if (!near(Xc[k][a], X[corner_node[k] * 2 + a]))
+            return fail(h, EG_ERR_MESH, "curved element node at a corner differs from its vertex");
+    } else {
+      straight_nodes9(Xc, X);
+    }
+  }
   nbr.assign((size_t)ne * nf, 0);
   ncode.assign((size_t)ne * nf, 0);
   auto face_corners = [&](int e, int lf, int* vv) {
@@ -382,6 +429,16 @@ eg_status setup_mesh(eg_handle* h, const eg_mesh* mesh, std::vector<double>& xv,
     uint8_t c12, c21;
     if (!code_of(e1, l1, e2, l2, c12) || !code_of(e2, l2, e1, l1, c21))
       return fail(h, EG_ERR_MESH, "non-conforming face");
+    if (d == 2 && mesh->elem_geo) {
+      // a curved edge is shared only if both sides put its middle node at
+      // the same point (the end nodes are the shared vertices)
+      auto mid = [&](int e, int lf) {
+        const int r = lf / 2, s2 = 2 * (lf % 2);
+        return &xv[((size_t)e * 9 + (r == 0 ? s2 + 3 : 1 + 3 * s2)) * 2];
+      };
+      const double *m1 = mid(e1, l1), *m2 = mid(e2, l2);
+      if (!near(m1[0], m2[0]) || !near(m1[1], m2[1])) return fail(h, EG_ERR_MESH, "non-conforming curved face");
+    }
     nbr[(size_t)e1 * nf + l1] = e2;
     ncode[(size_t)e1 * nf + l1] = c12;
     nbr[(size_t)e2 * nf + l2] = e1;
@@ -414,7 +471,7 @@ eg_status setup_mesh(eg_handle* h, const eg_mesh* mesh, std::vector<double>& xv,
   }
   int bad = 0;
   for (int e = 0; e < ne; ++e) {
-    const double* X = &xv[(size_t)e * nc * d];
+    const double* X = &xv[(size_t)e * ng * d];
     std::vector<double> G((size_t)N * N, 0.0), L((size_t)N * N, 0.0);
     double V = 0.0, S = 0.0;
     for (int q = 0; q < nq; ++q) {
@@ -789,7 +846,7 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
   M.V = d + 2;
   M.ne = mesh->n_elem;
   M.NF = 2 * d;
-  M.NC = 1 << d;
+  M.NC = eg::geo_nodes(d);
   const int N = nmodes_of(d, h->pmax);
   M.NT = N * (N + 1) / 2;
   M.gas.g = prm->gamma;
@@ -1309,6 +1366,13 @@ eg_status eg_init_batch(const eg_mesh* meshes, const eg_params* params, int n_so
   std::vector<double> xyz((size_t)nv * d);
   std::vector<int32_t> ev((size_t)ne * nc);
   std::vector<int8_t> tag((size_t)ne * nf);
+  bool curved = false;
+  for (int i = 0; i < n_solves; ++i) curved = curved || meshes[i].elem_geo;
+  if (curved && d != 2) {
+    h->err = "curved elements are 2D only";
+    return EG_ERR_UNSUPPORTED;
+  }
+  std::vector<double> geo(curved ? (size_t)ne * 18 : 0);
   BatchDef bd;
   bd.n = n_solves;
   bd.e0.push_back(0);
@@ -1324,6 +1388,16 @@ eg_status eg_init_batch(const eg_mesh* meshes, const eg_params* params, int n_so
       ev[(size_t)oe * nc + k] = (int32_t)(m.elem_vert[k] + ov);
     }
     std::memcpy(&tag[(size_t)oe * nf], m.bface_tag, (size_t)m.n_elem * nf);
+    if (curved && m.elem_geo) {
+      std::memcpy(&geo[(size_t)oe * 18], m.elem_geo, sizeof(double) * 18 * (size_t)m.n_elem);
+    } else if (curved) {  // a straight mesh among curved ones: its bilinear nodes
+      for (int e = 0; e < m.n_elem; ++e) {
+        double Xc[4][3];
+        for (int k = 0; k < 4; ++k)
+          for (int a = 0; a < 2; ++a) Xc[k][a] = m.xyz[(size_t)m.elem_vert[(size_t)e * 4 + k] * 2 + a];
+        straight_nodes9(Xc, &geo[((size_t)oe + e) * 18]);
+      }
+    }
     ov += m.n_vert;
     oe += m.n_elem;
     bd.e0.push_back((int)oe);
@@ -1331,7 +1405,7 @@ eg_status eg_init_batch(const eg_mesh* meshes, const eg_params* params, int n_so
     freestream_of(&params[i], d, U.data());
     bd.uinf.push_back(U);
   }
-  eg_mesh um{d, (int)nv, xyz.data(), (int)ne, ev.data(), tag.data()};
+  eg_mesh um{d, (int)nv, xyz.data(), (int)ne, ev.data(), tag.data(), curved ? geo.data() : nullptr};
   return init_common(h, &um, &params[0], hip_stream, &bd);
 }
 

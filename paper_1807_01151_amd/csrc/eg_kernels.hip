@@ -1465,7 +1465,7 @@ __global__ __launch_bounds__(256) void k_p0_setup(const double* __restrict__ ut0
   // (padded to a power of two); the contributions are summed over the points
   // of a face (neighbour block) and over all faces (R0, diagonal block) by
   // butterfly shuffles, a fixed order
-  constexpr int V = D + 2, NF = 2 * D, NC = 1 << D, QF = 1 << (D - 1);
+  constexpr int V = D + 2, NF = 2 * D, NC = geo_nodes(D), QF = 1 << (D - 1);
   constexpr int G = (D == 2) ? 8 : 32, EPB = 256 / G;
   const int e = blockIdx.x * EPB + (int)threadIdx.x / G, t = (int)threadIdx.x % G;
   const int lf = t / QF, k = t % QF;

@@ -11,11 +11,11 @@ namespace eg {
 
 // Device-resident mesh data and constants (owned by the handle).
 struct DevMesh {
-  int d = 2, V = 4, ne = 0, NF = 4, NC = 4;
+  int d = 2, V = 4, ne = 0, NF = 4, NC = 9;
   int NT = 0;              // packed triangle size of the p_max basis
   double omega = 0.0;      // |Omega|
   Gas gas{};
-  double* xv = nullptr;    // [E][2^d][d]
+  double* xv = nullptr;    // [E][NC][d] geometry nodes (9 per quad, 8 per hex)
   int* nbr = nullptr;      // [E][2d]
   uint8_t* ncode = nullptr;
   double* Lpk = nullptr;   // [E][NT] Cholesky factor of the phi mass matrix

@@ -28,6 +28,7 @@ CASES = [
     ("ogrid10x3-p4", ogrid(10, 3), 4, 1.0),
     ("sphere6x2x2x2-p2", cubed_sphere_shell(2, 2), 2, -1.0),
     ("sphere6x2x2x2-p3", cubed_sphere_shell(2, 2), 3, 1.0),
+    ("ogrid12x4c-p3-curved", ogrid(12, 4, curved=True), 3, 2.0),
 ]
 
 
@@ -90,7 +91,7 @@ def test_adjoint_solve_parity(c1_steady):
     assert e < 1e-8
 
 
-@pytest.mark.parametrize("name,mesh,p,alpha", CASES[4:], ids=[c[0] for c in CASES[4:]])
+@pytest.mark.parametrize("name,mesh,p,alpha", CASES[4:6], ids=[c[0] for c in CASES[4:6]])
 def test_adjoint_solve_large_blocks(name, mesh, p, alpha):
     """Adjoint V-cycles with the 135 x 135 and 320 x 320 blocks of 3D p = 2
     and 3 at a perturbed state: the adjoint problem is linear in lambda, so its residual

@@ -23,6 +23,7 @@ CASES = [
     ("ogrid10x3-p4", ogrid(10, 3), 4, -2.0),
     ("sphere6x2x2x2-p2", cubed_sphere_shell(2, 2), 2, 2.0),
     ("sphere6x2x2x2-p3", cubed_sphere_shell(2, 2), 3, 2.0),
+    ("ogrid10x3c-p4-curved", ogrid(10, 3, curved=True), 4, -2.0),
 ]
 
 
