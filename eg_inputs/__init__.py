@@ -12,6 +12,7 @@ from .meshes import (  # noqa: F401
     TAG_WALL,
     TAG_FARFIELD,
     TAG_EXACT,
+    TAG_SYMMETRY,
     Mesh,
     ogrid,
     cubed_sphere_shell,
@@ -20,6 +21,7 @@ from .meshes import (  # noqa: F401
     wall_bumps,
     reorient,
     mapped,
+    clip,
     straight_nodes,
     QUAD9_REF,
     QUAD9_CORNER,

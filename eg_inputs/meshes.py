@@ -11,7 +11,8 @@ arithmetic):
 * ``bface_tag`` is ``int8[n_elem, 2*dim]``; local face ``2 r + s`` is the face
   ``xi_r = -1`` (s = 0) or ``xi_r = +1`` (s = 1).  Tags: 0 interior (matched
   to a neighbour through its shared vertices), 1 slip wall, 2 far-field,
-  3 exact-state ghost (manufactured-solution tests of the oracle only).
+  3 exact-state ghost (manufactured-solution tests of the oracle only),
+  4 symmetry plane.
 * ``elem_geo`` (2D only, optional) is ``float64[n_elem, 9, 2]``: the nodes of a
   biquadratic element map; node ``a + 3 b`` sits at reference point
   ``(a - 1, b - 1)``, so nodes 0, 2, 6, 8 are the vertices ``elem_vert[:, 0..3]``
@@ -30,6 +31,7 @@ TAG_INTERIOR = 0
 TAG_WALL = 1
 TAG_FARFIELD = 2
 TAG_EXACT = 3
+TAG_SYMMETRY = 4
 
 
 @dataclasses.dataclass
@@ -374,3 +376,37 @@ def reorient(mesh: Mesh, seed: int) -> Mesh:
                 so = S[r, rn] * s
                 tg[e, 2 * rn + (s > 0)] = mesh.bface_tag[e, 2 * r + (so > 0)]
     return Mesh(dim, mesh.xyz.copy(), ev, tg, mesh.name + f"+reoriented{seed}", geo)
+
+
+def clip(mesh: Mesh, keep, tag: int = TAG_SYMMETRY) -> Mesh:
+    """The elements with ``keep[e]`` true, in their order, with unused
+    vertices dropped; every interior face whose neighbour is dropped becomes
+    a boundary face tagged ``tag``.  Cutting a mirror-symmetric mesh along
+    its plane of symmetry gives the half (or, cut twice, the quarter) domain
+    of Section 5.2's sphere, whose cut faces are symmetry planes."""
+    keep = np.asarray(keep, dtype=bool)
+    dim, nf = mesh.dim, 2 * mesh.dim
+    nc = 2 ** dim
+    owners: dict = {}
+    for e in range(mesh.n_elem):
+        for lf in range(nf):
+            if mesh.bface_tag[e, lf] != TAG_INTERIOR:
+                continue
+            r, s = divmod(lf, 2)
+            key = frozenset(int(mesh.elem_vert[e, k]) for k in range(nc) if (k >> r) & 1 == s)
+            owners.setdefault(key, []).append((e, lf))
+    tg = mesh.bface_tag.copy()
+    for pair in owners.values():
+        if len(pair) != 2:
+            raise ValueError("interior face without exactly one neighbour")
+        (e1, l1), (e2, l2) = pair
+        if keep[e1] and not keep[e2]:
+            tg[e1, l1] = tag
+        elif keep[e2] and not keep[e1]:
+            tg[e2, l2] = tag
+    ev = mesh.elem_vert[keep]
+    used = np.unique(ev)
+    new_id = np.full(mesh.n_vert, -1, dtype=np.int64)
+    new_id[used] = np.arange(len(used))
+    geo = None if mesh.elem_geo is None else mesh.elem_geo[keep].copy()
+    return Mesh(dim, mesh.xyz[used].copy(), new_id[ev].astype(np.int32), tg[keep], mesh.name + "+clip", geo)

@@ -49,8 +49,10 @@ typedef enum {
   EG_ERR_UNSUPPORTED = 7     /* valid request this build does not implement */
 } eg_status;
 
-/* Boundary tags of eg_mesh.bface_tag. */
-enum { EG_FACE_INTERIOR = 0, EG_FACE_WALL = 1, EG_FACE_FARFIELD = 2 };
+/* Boundary tags of eg_mesh.bface_tag.  A symmetry plane (Section 5.2) takes
+   the slip-wall ghost state (the mirror image of the inside state) but is not
+   part of the body surface the drag integrates.  Other values: EG_ERR_MESH. */
+enum { EG_FACE_INTERIOR = 0, EG_FACE_WALL = 1, EG_FACE_FARFIELD = 2, EG_FACE_SYMMETRY = 4 };
 
 typedef struct {
   int dim;                  /* 2 or 3 */
@@ -61,7 +63,8 @@ typedef struct {
                                reference corner (2a-1, 2b-1[, 2c-1]); copied */
   const int8_t* bface_tag;  /* host, [n_elem][2 dim]; local face 2r+s is xi_r = -1 (s=0)
                                or +1 (s=1).  0 interior (matched to the neighbour
-                               that shares its vertices), 1 slip wall, 2 far-field */
+                               that shares its vertices), 1 slip wall, 2 far-field,
+                               4 symmetry plane */
   const double* elem_geo;   /* host, optional (null = straight-sided elements); 2D only:
                                [n_elem][9][2] nodes of a biquadratic (quadratic curved)
                                element map, node a+3b at reference point (a-1, b-1)

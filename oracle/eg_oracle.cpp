@@ -488,6 +488,8 @@ template <class S> void mms_state(int d, double g, const S* x, S* U) {
 
 // Ghost state for boundary faces (Section 3.3: U_ghost is a function of U_L).
 //  tag 1 slip wall: mirror state, rho v_g = rho v - 2 (rho v . n^) n^.
+//  tag 4 symmetry plane (Section 5.2): the same mirror state; only the drag
+//        integral tells it from a wall.
 //  tag 2 far-field: Riemann invariants R+ = v_n + 2c/(g-1) from inside,
 //        R- = v_n,inf - 2 c_inf/(g-1) from the free stream; outflow iff the
 //        boundary normal velocity is > 0, taking tangential velocity and
@@ -496,7 +498,7 @@ template <class S> void mms_state(int d, double g, const S* x, S* U) {
 template <class S> void ghost(const Oracle& O, int tg, const S* U, const double* nh, const double* x, S* Ug) {
   const int d = O.d;
   const double g = O.gam;
-  if (tg == 1) {
+  if (tg == 1 || tg == 4) {
     S mn = 0.0;
     for (int a = 0; a < d; ++a) mn += U[1 + a] * nh[a];
     Ug[0] = U[0];

@@ -59,5 +59,8 @@ using Gas = GasT<double>;
 // Boundary codes stored in the neighbour array for faces without neighbour.
 constexpr int NB_WALL = -1;
 constexpr int NB_FAR = -2;
+// Neighbour code of a slip face that is a symmetry plane rather than the
+// body: same ghost state, left out of the drag integral.
+constexpr uint8_t NCODE_SYMMETRY = 1;
 
 }  // namespace eg

@@ -368,6 +368,11 @@ eg_status setup_mesh(eg_handle* h, const eg_mesh* mesh, std::vector<double>& xv,
     for (int lf = 0; lf < nf; ++lf) {
       int tag = mesh->bface_tag[(size_t)e * nf + lf];
       if (tag == EG_FACE_WALL) { nbr[(size_t)e * nf + lf] = eg::NB_WALL; continue; }
+      if (tag == EG_FACE_SYMMETRY) {
+        nbr[(size_t)e * nf + lf] = eg::NB_WALL;
+        ncode[(size_t)e * nf + lf] = eg::NCODE_SYMMETRY;
+        continue;
+      }
       if (tag == EG_FACE_FARFIELD) { nbr[(size_t)e * nf + lf] = eg::NB_FAR; continue; }
       if (tag != EG_FACE_INTERIOR) return fail(h, EG_ERR_MESH, "unknown boundary tag");
       int vv[4] = {-1, -1, -1, -1};

@@ -2386,7 +2386,8 @@ struct Dir3 {
 
 template <int D, int P>
 __global__ __launch_bounds__(128) void k_drag(const double* __restrict__ ut, const double* __restrict__ xv,
-                                              const int* __restrict__ nbr, int ne, Tab<D, P> tab, Gas gas, Dir3 dir,
+                                              const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
+                                              int ne, Tab<D, P> tab, Gas gas, Dir3 dir,
                                               double scale, double* __restrict__ part, double* __restrict__ gt) {
   using C = Cfg<D, P>;
   constexpr int V = C::V, N = C::N, Q = C::Q, QF = C::QF, NF = C::NF, NC = C::NC;
@@ -2400,7 +2401,7 @@ __global__ __launch_bounds__(128) void k_drag(const double* __restrict__ ut, con
   double acc = 0.0;
   const double* ue = ut + (size_t)e * V * N;
   for (int lf = 0; lf < NF; ++lf) {
-    if (nbr[(size_t)e * NF + lf] != NB_WALL) continue;
+    if (nbr[(size_t)e * NF + lf] != NB_WALL || ncode[(size_t)e * NF + lf] == NCODE_SYMMETRY) continue;
     double X[NC * D];
 #pragma unroll
     for (int a = 0; a < NC * D; ++a) X[a] = xv[(size_t)e * NC * D + a];
@@ -3442,8 +3443,8 @@ hipError_t drag_t(const DevMesh& M, const TabData& td, const double* ut, const d
   Tab<D, P, double> t;
   fill_tab(t, td);
   Dir3 dv{{dir[0], dir[1], dir[2]}};
-  hipLaunchKernelGGL((k_drag<D, P>), dim3((M.ne + 127) / 128), dim3(128), 0, st, ut, M.xv, M.nbr, M.ne, t, M.gas, dv,
-                     scale, part, gt);
+  hipLaunchKernelGGL((k_drag<D, P>), dim3((M.ne + 127) / 128), dim3(128), 0, st, ut, M.xv, M.nbr, M.ncode, M.ne, t,
+                     M.gas, dv, scale, part, gt);
   return hipGetLastError();
 }
 }  // namespace

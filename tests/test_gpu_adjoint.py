@@ -16,10 +16,16 @@ import pytest
 import torch
 
 import oracle
-from eg_inputs import ogrid, cubed_sphere_shell, wall_bumps, bump_centers
+from eg_inputs import ogrid, cubed_sphere_shell, wall_bumps, bump_centers, clip
 from tests.gpu_util import perturbed, to_dev, to_host, rel_err
 
 pytestmark = pytest.mark.gpu
+
+
+def _quarter(mesh):
+    """y > 0, z > 0 part of the shell; the cut faces are symmetry planes."""
+    return clip(mesh, np.all(mesh.xyz[mesh.elem_vert].mean(axis=1)[:, 1:] > 0.0, axis=1))
+
 
 CASES = [
     ("ogrid16x6-p3", ogrid(16, 6), 3, 3.0),
@@ -29,6 +35,7 @@ CASES = [
     ("sphere6x2x2x2-p2", cubed_sphere_shell(2, 2), 2, -1.0),
     ("sphere6x2x2x2-p3", cubed_sphere_shell(2, 2), 3, 1.0),
     ("ogrid12x4c-p3-curved", ogrid(12, 4, curved=True), 3, 2.0),
+    ("sphere6x4x4x2-quarter-p2-symmetry", _quarter(cubed_sphere_shell(4, 2)), 2, 0.0),
 ]
 
 

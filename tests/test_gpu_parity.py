@@ -14,10 +14,18 @@ import numpy as np
 import pytest
 
 import oracle
-from eg_inputs import ogrid, cubed_sphere_shell, box, reorient, wall_bumps, TAG_FARFIELD
+from eg_inputs import ogrid, cubed_sphere_shell, box, reorient, wall_bumps, clip, TAG_FARFIELD
 from tests.gpu_util import perturbed, to_dev, to_host, rel_err
 
 pytestmark = pytest.mark.gpu
+
+
+def _half(mesh, axes):
+    """The part of a mirror-symmetric mesh on the positive side of the
+    coordinate planes ``axes``, cut faces tagged as symmetry planes."""
+    c = mesh.xyz[mesh.elem_vert].mean(axis=1)
+    return clip(mesh, np.all(c[:, list(axes)] > 0.0, axis=1))
+
 
 CASES = [
     ("c1-ogrid24x12-p1", ogrid(24, 12), 1, 0.0, "rusanov"),
@@ -42,6 +50,9 @@ CASES = [
     ("ogrid16x6c-p3-curved-bumps-reoriented",
      reorient(wall_bumps(ogrid(16, 6, curved=True), [0.04], [[0.6, 0.8]], 0.5), 15), 3, 3.0, "rusanov"),
     ("ogrid10x3c-p4-curved-roe", ogrid(10, 3, curved=True), 4, -2.0, "roe"),
+    # symmetry planes: half O-grid (y > 0) and quarter sphere (y > 0, z > 0)
+    ("ogrid16x6c-half-p3-symmetry", _half(ogrid(16, 6, curved=True), (1,)), 3, 0.0, "roe"),
+    ("sphere6x4x4x2-quarter-p2-symmetry", _half(cubed_sphere_shell(4, 2), (1, 2)), 2, 0.0, "rusanov"),
 ]
 IDS = [c[0] for c in CASES]
 
@@ -228,11 +239,14 @@ def test_c1_roe_history_and_fixed_point():
     the oracle's state reproduces the oracle's next state at every one of the
     first 16 cycles, the GPU solve reaches the 1e-10 drop, and the oracle's
     Roe residual of the GPU's converged state is at the drop (the fixed point
-    R(u) = 0 of the Roe discretisation).  From cycle 12 on the Roe trajectory
+    R(u) = 0 of the Roe discretisation).  From cycle 10 on the Roe cycle map
     amplifies rounding: the oracle against itself, with the same mesh given
     as vertices and as nine straight nodes (geometry equal up to rounding),
-    deviates 1.3e-12 r_1 at cycle 12 and 1.3e-8 r_1 at cycle 13, so later
-    cycles are compared one at a time."""
+    gives one-cycle updates from the same state that differ by up to
+    3.7e-10 of the update at cycles 10-13 (1e-13 before), and its
+    free-running histories deviate 1.3e-12 r_1 at cycle 12 and 1.3e-8 r_1 at
+    cycle 13.  So the history is compared over 11 cycles and the one-cycle
+    updates within 2e-9."""
     mesh = ogrid(24, 12)
     O = _oracle(mesh, 1, 0.0, "roe")
     S = _solver(mesh, 1, 0.0, "roe", rk_stages=4, cfl_max=100.0, krylov_m=30)
@@ -245,7 +259,7 @@ def test_c1_roe_history_and_fixed_point():
         rn_g, _ = S.vcycle(ud, n, rref=r1)
         assert abs(rn_g - rn_o) <= 1e-13 * rn_o, n
         e = rel_err(to_host(ud) - u, un - u)
-        assert e < 1e-10, (n, e)
+        assert e < 2e-9, (n, e)
         u = un
     ud = S.freestream(1)
     h_g, st_g = S.solve_steady(ud, drop_tol=1e-10, max_cycles=8000)
