@@ -170,12 +170,12 @@ def drop_run(S, p, max_cycles, budget, tag, chunk=200):
 
 
 def c2_measurements(P, steps, warmup, drop_budget):
-    """The 2D cylinder workload: O-grid 128 x 64 quads, p = 3, s = 3,
-    CFL_max = 10, FP64: V-cycle throughput, dominant kernels, and the drop run
-    (this discrete problem settles into a limit cycle near 1e-4 .. 1e-3 r_1)."""
+    """The 2D cylinder workload: O-grid 128 x 64 quadratic curved quads (the
+    paper's cylinder grid is curved), p = 3, s = 3, CFL_max = 10, FP64:
+    V-cycle throughput, dominant kernels, and the drop run to 1e-10."""
     import torch
     from eg_inputs import ogrid
-    mesh = ogrid(128, 64)
+    mesh = ogrid(128, 64, curved=True)
     S = P.Solver(mesh, 3, rk_stages=3, cfl_max=10.0, krylov_m=30, mach=0.3, alpha_deg=0.0)
     S.autotune()
     dof = mesh.n_elem * 4 * 16
@@ -187,7 +187,8 @@ def c2_measurements(P, steps, warmup, drop_budget):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / steps * 1e3
     prof = profile_cycles(S, u, 3, steps)
-    out = {"workload": "2D cylinder O-grid 128x64 quads, DG p=3 (16 modes x 4 vars), eMG V-cycle p3->p0, "
+    out = {"workload": "2D cylinder O-grid 128x64 quadratic curved quads, DG p=3 (16 modes x 4 vars), "
+                       "eMG V-cycle p3->p0, "
                        "3-stage PRK, EXP1 m=30, CFL_max 10, Ma 0.3, free-stream start, FP64",
            "dof": dof, "ms_per_cycle": round(ms, 4), "dof_updates_per_s": dof / ms * 1e3,
            "kernels_ms_per_cycle": {k: round(v[0] / steps, 5) for k, v in prof.items()}}
@@ -204,7 +205,7 @@ def c2_measurements(P, steps, warmup, drop_budget):
 
 
 def batched_measurements(P, steps, budget_s, precision="mixed"):
-    """The batched workload: 64 independent cylinder solves drawn from seed
+    """The batched workload: 64 independent cylinder solves (curved O-grids) drawn from seed
     1807 (N_theta ~ U{16..96}, N_r = N_theta / 2, p ~ U{1..4}, Ma ~ U[0.1,
     0.4], alpha ~ U[-5, 5] deg), s = 4, CFL_max = 100, one batch handle per
     order, all four advanced together (eg_solve_multi: per V-cycle one
@@ -221,7 +222,7 @@ def batched_measurements(P, steps, budget_s, precision="mixed"):
     t_init = time.perf_counter()
     handles = {}
     for p, idx in sorted(groups.items()):
-        meshes = [ogrid(draws[i]["n_theta"], draws[i]["n_r"]) for i in idx]
+        meshes = [ogrid(draws[i]["n_theta"], draws[i]["n_r"], curved=True) for i in idx]
         B = P.BatchSolver(meshes, p, [draws[i]["mach"] for i in idx], [draws[i]["alpha_deg"] for i in idx],
                           rk_stages=4, cfl_max=100.0, krylov_m=30, precision=precision)
         B.autotune()
@@ -376,7 +377,7 @@ def main():
     ap.add_argument("--no-drop", action="store_true", help="skip the time-to-1e-10 runs")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision measurements")
     ap.add_argument("--no-c2", action="store_true", help="skip the 2D cylinder workload")
-    ap.add_argument("--c2-drop-budget", type=float, default=0.0, help="seconds of the c2 drop run (0: none)")
+    ap.add_argument("--c2-drop-budget", type=float, default=60.0, help="seconds of the c2 drop run (0: none)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-solve batched workload")
     ap.add_argument("--batch-budget", type=float, default=30.0, help="seconds cap of the batched convergence run")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured-peak kernels")

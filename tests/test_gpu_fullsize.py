@@ -1,7 +1,7 @@
-"""Parity at the full size of the benchmarked workload (O-grid 128 x 64, p = 3,
-8192 quads, s = 3, CFL 10, m = 30) in the launch configuration bench.py
-times: the residual and the PRK step on every element, and the first
-V-cycles from the free stream."""
+"""Parity at the full size of the benchmarked workload (O-grid 128 x 64 of
+quadratic curved quads, p = 3, 8192 elements, s = 3, CFL 10, m = 30) in the
+launch configuration bench.py times: the residual and the PRK step on every
+element, the first V-cycles from the free stream, and the converged state."""
 
 import numpy as np
 import pytest
@@ -12,7 +12,7 @@ from tests.gpu_util import perturbed, to_dev, to_host, rel_err
 
 pytestmark = pytest.mark.gpu
 
-MESH = ogrid(128, 64)
+MESH = ogrid(128, 64, curved=True)  # the cylinder grid is quadratic curved (Section 5.1)
 
 
 @pytest.fixture(scope="module")
@@ -76,12 +76,16 @@ def test_c2_deep_iterate_residual(pair):
     assert h_g[-1] < 1e-2 * h_g[0]
 
 
-@pytest.mark.skip(reason="the c2 workload (s = 3, CFL_max 10) stalls between 2e-4 and 2e-3 r_1 after falling to "
-                         "1e-7 r_1: its V-cycle map is unstable at the steady state (spectral radius 1.0097 on the "
-                         "32 x 16 O-grid at p = 3, oracle; cycle-map parity holds at the stalled state); the 1e-10 "
-                         "drop is shown on the c1 and c3 workloads")
 def test_c2_reaches_the_1e10_drop(pair):
+    """The GPU solve reaches the 1e-10 drop (2676 cycles measured), and the
+    oracle's residual norm of the converged state is at the drop.  (On the
+    straight-sided 128 x 64 grid the same solve falls to 1e-7 r_1 and then
+    settles into a limit cycle between 2e-4 and 2e-3 r_1: its V-cycle map is
+    unstable at that grid's steady state.)"""
     O, S = pair
     ud = S.freestream(3)
-    h_g, st = S.solve_steady(ud, drop_tol=1e-10, max_cycles=40000)
+    h_g, st = S.solve_steady(ud, drop_tol=1e-10, max_cycles=20000)
+    print("c2 cycles to 1e-10:", len(h_g) - 1, "status", st, flush=True)
     assert st == 0
+    r = O.rnorm(3, O.residual(3, to_host(ud)))
+    assert r <= 2e-10 * h_g[0]
