@@ -25,5 +25,7 @@ from .meshes import (  # noqa: F401
     straight_nodes,
     QUAD9_REF,
     QUAD9_CORNER,
+    node_ref,
+    node_of_vertex,
 )
 from .draws import batch_draws, bump_centers, seeded_array  # noqa: F401

@@ -13,11 +13,11 @@ arithmetic):
   to a neighbour through its shared vertices), 1 slip wall, 2 far-field,
   3 exact-state ghost (manufactured-solution tests of the oracle only),
   4 symmetry plane.
-* ``elem_geo`` (2D only, optional) is ``float64[n_elem, 9, 2]``: the nodes of a
-  biquadratic element map; node ``a + 3 b`` sits at reference point
-  ``(a - 1, b - 1)``, so nodes 0, 2, 6, 8 are the vertices ``elem_vert[:, 0..3]``
-  and nodes 1, 3, 5, 7 the edge midpoints.  ``None`` means straight-sided
-  (bilinear) elements.
+* ``elem_geo`` (optional) is ``float64[n_elem, 3**dim, dim]``: the nodes of a
+  tensor quadratic element map; node ``a + 3 b (+ 9 c)`` sits at reference
+  point ``(a - 1, b - 1[, c - 1])``, so the nodes whose digits are all 0 or 2
+  are the vertices (``node_of_vertex``).  ``None`` means straight-sided
+  (multilinear) elements.
 """
 
 from __future__ import annotations
@@ -41,7 +41,7 @@ class Mesh:
     elem_vert: np.ndarray  # int32 [n_elem, 2**dim]
     bface_tag: np.ndarray  # int8 [n_elem, 2*dim]
     name: str = ""
-    elem_geo: np.ndarray | None = None  # float64 [n_elem, 9, 2] (2D curved) or None
+    elem_geo: np.ndarray | None = None  # float64 [n_elem, 3**dim, dim] (curved) or None
 
     @property
     def n_elem(self) -> int:
@@ -60,41 +60,52 @@ class Mesh:
                     None if self.elem_geo is None else np.ascontiguousarray(self.elem_geo, dtype=np.float64))
 
 
-# Reference positions (a - 1, b - 1) of the nine nodes a + 3 b of a biquadratic quad.
-QUAD9_REF = np.array([[a - 1, b - 1] for b in range(3) for a in range(3)], dtype=np.int64)
-# node index of each bilinear corner a + 2 b
-QUAD9_CORNER = (0, 2, 6, 8)
+def node_ref(dim: int) -> np.ndarray:
+    """int64[3**dim, dim]: reference position (digits - 1) of every node
+    a + 3 b (+ 9 c) of a tensor quadratic element."""
+    return np.array([[(k // 3 ** r) % 3 - 1 for r in range(dim)] for k in range(3 ** dim)], dtype=np.int64)
+
+
+def node_of_vertex(dim: int) -> list:
+    """Node index of every vertex a + 2 b (+ 4 c) (the node with digits 2a, 2b, 2c)."""
+    return [sum(2 * ((k >> r) & 1) * 3 ** r for r in range(dim)) for k in range(2 ** dim)]
+
+
+QUAD9_REF = node_ref(2)
+QUAD9_CORNER = tuple(node_of_vertex(2))
 
 
 def straight_nodes(mesh: Mesh) -> np.ndarray:
-    """float64[n_elem, 9, 2]: the nine nodes of each element's bilinear map
-    (corners at the vertices, edge nodes at edge midpoints, the centre node at
-    the mean of the corners), i.e. the straight-sided element written as a
-    biquadratic one."""
-    if mesh.dim != 2:
-        raise ValueError("nine-node elements are 2D only")
-    X = mesh.xyz[mesh.elem_vert]  # [E, 4, 2], corner a + 2 b
-    geo = np.empty((mesh.n_elem, 9, 2))
-    for k, (a, b) in enumerate(QUAD9_REF + 1):
-        wa = (1.0 - 0.5 * a, 0.5 * a)
-        wb = (1.0 - 0.5 * b, 0.5 * b)
-        geo[:, k] = sum(wa[i] * wb[j] * X[:, i + 2 * j] for i in range(2) for j in range(2))
+    """float64[n_elem, 3**dim, dim]: the nodes of each element's multilinear
+    map (vertices at the corners, the other nodes at the multilinear
+    positions of their reference points), i.e. the straight-sided element
+    written as a quadratic one."""
+    dim = mesh.dim
+    X = mesh.xyz[mesh.elem_vert]  # [E, 2^dim, dim], vertex a + 2 b + 4 c
+    ref = node_ref(dim) + 1
+    geo = np.zeros((mesh.n_elem, 3 ** dim, dim))
+    for k in range(3 ** dim):
+        for v in range(2 ** dim):
+            w = 1.0
+            for r in range(dim):
+                w *= 0.5 * ref[k, r] if (v >> r) & 1 else 1.0 - 0.5 * ref[k, r]
+            if w != 0.0:
+                geo[:, k] += w * X[:, v]
     return geo
 
 
 def mapped(mesh: Mesh, fn, name: str = "") -> Mesh:
-    """Curved 2D mesh: every node of the straight mesh (vertices and the nine
-    bilinear nodes of each element) moved through the smooth map
-    ``fn(float64[n, 2]) -> float64[n, 2]``.  Shared edges keep shared nodes
-    because both neighbours evaluate ``fn`` at the same straight-edge point."""
-    if mesh.dim != 2:
-        raise ValueError("curved elements are 2D only")
+    """Curved mesh: every node of the mesh (vertices and the 3**dim nodes of
+    each element, multilinear ones for a straight mesh) moved through the
+    smooth map ``fn(float64[n, dim]) -> float64[n, dim]``.  Shared faces keep
+    shared nodes because both neighbours evaluate ``fn`` at the same point."""
+    dim = mesh.dim
     base = straight_nodes(mesh) if mesh.elem_geo is None else mesh.elem_geo
-    geo = fn(base.reshape(-1, 2)).reshape(base.shape)
+    geo = fn(base.reshape(-1, dim)).reshape(base.shape)
     xyz = fn(np.array(mesh.xyz, dtype=np.float64))
-    for i, k in enumerate(QUAD9_CORNER):
+    for i, k in enumerate(node_of_vertex(dim)):
         geo[:, k] = xyz[mesh.elem_vert[:, i]]
-    return Mesh(2, xyz, mesh.elem_vert.copy(), mesh.bface_tag.copy(), name or mesh.name + "+mapped", geo)
+    return Mesh(dim, xyz, mesh.elem_vert.copy(), mesh.bface_tag.copy(), name or mesh.name + "+mapped", geo)
 
 
 def radial_map(n_r: int, r_in: float = 0.5, r_out: float = 20.0,
@@ -201,11 +212,15 @@ _PANELS = (
 
 def cubed_sphere_shell(n: int, n_r: int, r_in: float = 0.5, r_out: float = 20.0,
                        stretch: float = 1.2, n_ref: int = 12,
-                       inner: int = TAG_WALL, outer: int = TAG_FARFIELD) -> Mesh:
+                       inner: int = TAG_WALL, outer: int = TAG_FARFIELD, curved: bool = False) -> Mesh:
     """Equiangular gnomonic cubed-sphere hex shell: 6 panels of n x n columns
     and ``n_r`` radial layers (6 n^2 n_r hexes).  Vertices on panel seams are
     shared.  xi runs outward in r; face 0 is on the body (``inner`` tag),
-    face 1 on the outer sphere (``outer`` tag)."""
+    face 1 on the outer sphere (``outer`` tag).
+
+    ``curved`` adds triquadratic element nodes: the panel grid refined to
+    half steps of the equiangular parameter, projected to the spheres of
+    radius r_j, r_{j+1} and their mean (radial edges stay straight)."""
     if n < 1 or n_r < 1:
         raise ValueError("cubed_sphere_shell needs n >= 1 and n_r >= 1")
     r = radial_map(n_r, r_in, r_out, stretch, n_ref)
@@ -251,7 +266,43 @@ def cubed_sphere_shell(n: int, n_r: int, r_in: float = 0.5, r_out: float = 20.0,
                     if j == n_r - 1:
                         tag[e, 1] = outer
                     e += 1
-    return Mesh(3, xyz, ev, tag, f"cubedsphere6x{n}x{n}x{n_r}")
+    if not curved:
+        return Mesh(3, xyz, ev, tag, f"cubedsphere6x{n}x{n}x{n_r}")
+    # unit directions on the half-step panel grids, deduplicated across seams
+    # so that neighbours on two panels read bit-identical nodes
+    th = np.tan(-math.pi / 4 + (math.pi / 2) * np.arange(2 * n + 1) / (2 * n))
+    th[0], th[-1], th[n] = -1.0, 1.0, 0.0
+    hdirs: dict = {}
+    hid = np.empty((6, 2 * n + 1, 2 * n + 1), dtype=np.int64)
+    hlist = []
+    for P, (nv, t1, t2) in enumerate(_PANELS):
+        nv, t1, t2 = (np.array(a, dtype=np.float64) for a in (nv, t1, t2))
+        for a in range(2 * n + 1):
+            for b in range(2 * n + 1):
+                v = nv + th[a] * t1 + th[b] * t2
+                v = v / math.sqrt(float(v @ v))
+                k = tuple(np.round(v * 1e9).astype(np.int64))
+                if k not in hdirs:
+                    hdirs[k] = len(hlist)
+                    hlist.append(v)
+                hid[P, a, b] = hdirs[k]
+    hlist = np.array(hlist)
+    rr = np.empty(2 * n_r + 1)
+    rr[0::2] = r
+    rr[1::2] = 0.5 * (r[:-1] + r[1:])
+    geo = np.empty((ne, 27, 3))
+    e = 0
+    for j in range(n_r):
+        for P in range(6):
+            for b in range(n):
+                for a in range(n):
+                    for k, (dx, dy, dz) in enumerate(node_ref(3) + 1):
+                        geo[e, k] = rr[2 * j + dx] * hlist[hid[P, 2 * a + dy, 2 * b + dz]]
+                    e += 1
+    # the corner nodes are the vertices themselves
+    for i, k in enumerate(node_of_vertex(3)):
+        geo[:, k] = xyz[ev[:, i]]
+    return Mesh(3, xyz, ev, tag, f"cubedsphere6x{n}x{n}x{n_r}c", geo)
 
 
 def box(dim: int, n: int, lo: float = 0.0, hi: float = 1.0, tag: int = TAG_EXACT,
@@ -325,8 +376,8 @@ def wall_bumps(mesh: Mesh, amps, centers, sigma: float, r_in: float = 0.5,
     xyz = move(mesh.xyz)
     geo = None
     if mesh.elem_geo is not None:  # curved nodes move with the same field
-        geo = move(mesh.elem_geo.reshape(-1, 2)).reshape(mesh.elem_geo.shape)
-        for i, k in enumerate(QUAD9_CORNER):
+        geo = move(mesh.elem_geo.reshape(-1, mesh.dim)).reshape(mesh.elem_geo.shape)
+        for i, k in enumerate(node_of_vertex(mesh.dim)):
             geo[:, k] = xyz[mesh.elem_vert[:, i]]
     return Mesh(mesh.dim, xyz, mesh.elem_vert.copy(), mesh.bface_tag.copy(), mesh.name + "+bumps", geo)
 
@@ -362,14 +413,15 @@ def reorient(mesh: Mesh, seed: int) -> Mesh:
     ev = np.empty_like(mesh.elem_vert)
     tg = np.empty_like(mesh.bface_tag)
     geo = None if mesh.elem_geo is None else np.empty_like(mesh.elem_geo)
-    node_of = {tuple(c): k for k, c in enumerate(QUAD9_REF)}
+    refs = node_ref(dim)
+    node_of = {tuple(c): k for k, c in enumerate(refs)}
     for e in range(mesh.n_elem):
         S = rots[pick[e]]
         for k in range(nc):
             ev[e, k] = mesh.elem_vert[e, index_of[tuple(S @ corners[k])]]
         if geo is not None:
-            for k in range(9):
-                geo[e, k] = mesh.elem_geo[e, node_of[tuple(S @ QUAD9_REF[k])]]
+            for k in range(3 ** dim):
+                geo[e, k] = mesh.elem_geo[e, node_of[tuple(S @ refs[k])]]
         for rn in range(dim):
             r = int(np.nonzero(S[:, rn])[0][0])
             for s in (-1, 1):

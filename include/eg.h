@@ -65,13 +65,15 @@ typedef struct {
                                or +1 (s=1).  0 interior (matched to the neighbour
                                that shares its vertices), 1 slip wall, 2 far-field,
                                4 symmetry plane */
-  const double* elem_geo;   /* host, optional (null = straight-sided elements); 2D only:
-                               [n_elem][9][2] nodes of a biquadratic (quadratic curved)
-                               element map, node a+3b at reference point (a-1, b-1)
-                               (Section 5.1 meshes).  Nodes 0, 2, 6, 8 must equal the
-                               vertices 0..3 and the edge node of every interior face
-                               the neighbour's (within 1e-12 relative), else
-                               EG_ERR_MESH; with a 3D mesh, EG_ERR_UNSUPPORTED.  Copied */
+  const double* elem_geo;   /* host, optional (null = straight-sided elements): nodes of
+                               a quadratic curved element map (Sections 5.1, 5.2 meshes).
+                               2D: [n_elem][9][2], biquadratic, node a+3b at reference
+                               point (a-1, b-1); 3D: [n_elem][27][3], triquadratic, node
+                               a+3b+9c at (a-1, b-1, c-1).  The nodes at the corners
+                               (every digit 0 or 2) must equal the vertices, and both
+                               sides of an interior face must place its nodes (3 per
+                               edge, 9 per quadrilateral) at the same points (within
+                               1e-12 relative), else EG_ERR_MESH.  Copied */
 } eg_mesh;
 
 typedef struct {

@@ -21,9 +21,9 @@
 //     s_i [chi_i + sum_{j<i} c_ij chi_j], i.e. a lower-triangular transform).
 //   * Numerical flux: Rusanov (local Lax-Friedrichs); boundary fluxes use the
 //     same flux with a ghost state (Section 3.3, boundary flux equation).
-//   * Element map: multilinear through the 2^d vertices, or in 2D, when the
-//     mesh carries nine nodes per element, the biquadratic Lagrange map
-//     through them (quadratic curved elements, Section 5.1).
+//   * Element map: multilinear through the 2^d vertices, or, when the mesh
+//     carries 3^d nodes per element, the tensor quadratic Lagrange map through
+//     them (quadratic curved elements, Sections 5.1 and 5.2).
 //
 // Build: g++ -O2 -fno-fast-math -ffp-contract=off -fopenmp -shared -fPIC.
 
@@ -173,7 +173,7 @@ struct Oracle {
   std::vector<double> xyz;
   std::vector<int> ev;
   std::vector<signed char> tag;
-  std::vector<double> geo;  // 2D curved: [E][9][2], node a + 3b at (a-1, b-1); empty = straight
+  std::vector<double> geo;  // curved: [E][3^d][d], node digits (a, b[, c]) at (a-1, b-1[, c-1]); empty = straight
   std::vector<Face> faces;
   std::vector<int> efc, eside;  // [E][2d] face id and side (0 = L, 1 = R)
   std::vector<double> T;        // [E][N][N], N = N_pmax, lower triangular
@@ -229,42 +229,42 @@ void geom(const Oracle& O, int e, const double* xi, double* x, double t[MAXD][MA
   const int d = O.d, nc = 1 << d;
   for (int a = 0; a < d; ++a) { x[a] = 0.0; for (int r = 0; r < d; ++r) t[r][a] = 0.0; }
   if (!O.geo.empty()) {
-    // x(xi, eta) = sum over nodes of l_a(xi) l_b(eta) X_{a+3b}
-    for (int b = 0; b < 3; ++b)
-      for (int a = 0; a < 3; ++a) {
-        const double* X = &O.geo[((size_t)e * 9 + a + 3 * b) * 2];
-        const double N = lagrange3(a, xi[0]) * lagrange3(b, xi[1]);
-        const double dN0 = lagrange3_deriv(a, xi[0]) * lagrange3(b, xi[1]);
-        const double dN1 = lagrange3(a, xi[0]) * lagrange3_deriv(b, xi[1]);
-        for (int q = 0; q < 2; ++q) {
-          x[q] += N * X[q];
-          t[0][q] += dN0 * X[q];
-          t[1][q] += dN1 * X[q];
+    // x(xi) = sum over the 3^d nodes n (digits n_r in 0..2) of
+    // prod_r l_{n_r}(xi_r) X_n, and dx/dxi_r with l' in factor r
+    const int ng = d == 2 ? 9 : 27;
+    for (int k = 0; k < ng; ++k) {
+      int dig[MAXD];
+      for (int r = 0, kk = k; r < d; ++r, kk /= 3) dig[r] = kk % 3;
+      const double* X = &O.geo[((size_t)e * ng + k) * d];
+      double N = 1.0;
+      for (int r = 0; r < d; ++r) N *= lagrange3(dig[r], xi[r]);
+      for (int r = 0; r < d; ++r) {
+        double dN = 1.0;
+        for (int q = 0; q < d; ++q) dN *= (q == r) ? lagrange3_deriv(dig[q], xi[q]) : lagrange3(dig[q], xi[q]);
+        for (int a = 0; a < d; ++a) t[r][a] += dN * X[a];
+      }
+      for (int a = 0; a < d; ++a) x[a] += N * X[a];
+    }
+  } else {
+    for (int k = 0; k < nc; ++k) {
+      const double* X = &O.xyz[(size_t)O.ev[(size_t)e * nc + k] * d];
+      double N = 1.0, dN[MAXD];
+      for (int r = 0; r < d; ++r) {
+        double sg = ((k >> r) & 1) ? 1.0 : -1.0;
+        N *= 0.5 * (1.0 + sg * xi[r]);
+      }
+      for (int r = 0; r < d; ++r) {
+        double v = 1.0;
+        for (int q = 0; q < d; ++q) {
+          double sg = ((k >> q) & 1) ? 1.0 : -1.0;
+          v *= (q == r) ? 0.5 * sg : 0.5 * (1.0 + sg * xi[q]);
         }
+        dN[r] = v;
       }
-    det = t[0][0] * t[1][1] - t[0][1] * t[1][0];
-    c[0][0] = t[1][1]; c[0][1] = -t[1][0];
-    c[1][0] = -t[0][1]; c[1][1] = t[0][0];
-    return;
-  }
-  for (int k = 0; k < nc; ++k) {
-    const double* X = &O.xyz[(size_t)O.ev[(size_t)e * nc + k] * d];
-    double N = 1.0, dN[MAXD];
-    for (int r = 0; r < d; ++r) {
-      double sg = ((k >> r) & 1) ? 1.0 : -1.0;
-      N *= 0.5 * (1.0 + sg * xi[r]);
-    }
-    for (int r = 0; r < d; ++r) {
-      double v = 1.0;
-      for (int q = 0; q < d; ++q) {
-        double sg = ((k >> q) & 1) ? 1.0 : -1.0;
-        v *= (q == r) ? 0.5 * sg : 0.5 * (1.0 + sg * xi[q]);
+      for (int a = 0; a < d; ++a) {
+        x[a] += N * X[a];
+        for (int r = 0; r < d; ++r) t[r][a] += dN[r] * X[a];
       }
-      dN[r] = v;
-    }
-    for (int a = 0; a < d; ++a) {
-      x[a] += N * X[a];
-      for (int r = 0; r < d; ++r) t[r][a] += dN[r] * X[a];
     }
   }
   if (d == 2) {
@@ -672,29 +672,38 @@ bool setup(Oracle& O) {
   }
   if (!open.empty()) { O.err = "unmatched interior face"; return false; }
   if (!O.geo.empty()) {
-    // curved quads: corner nodes are the vertices, and the two sides of an
-    // interior edge share its middle node
-    auto same = [](const double* a, const double* b) {
-      for (int q = 0; q < 2; ++q)
+    // curved elements: the nodes at the corners are the vertices, and the two
+    // sides of an interior face place its 3^(d-1) nodes at the same points
+    const int ng = d == 2 ? 9 : 27;
+    auto same = [&](const double* a, const double* b) {
+      for (int q = 0; q < d; ++q)
         if (std::fabs(a[q] - b[q]) > 1e-12 * std::max(1.0, std::fabs(a[q]))) return false;
       return true;
     };
-    const int corner_node[4] = {0, 2, 6, 8};
+    auto node = [&](int e, int k) { return &O.geo[((size_t)e * ng + k) * d]; };
+    auto digit = [](int k, int r) { for (int q = 0; q < r; ++q) k /= 3; return k % 3; };
     for (int e = 0; e < O.ne; ++e)
-      for (int k = 0; k < 4; ++k)
-        if (!same(&O.geo[((size_t)e * 9 + corner_node[k]) * 2], &O.xyz[(size_t)O.ev[(size_t)e * 4 + k] * 2])) {
+      for (int v = 0; v < nc; ++v) {
+        int k = 0;
+        for (int r = 0, p3 = 1; r < d; ++r, p3 *= 3) k += 2 * ((v >> r) & 1) * p3;
+        if (!same(node(e, k), &O.xyz[(size_t)O.ev[(size_t)e * nc + v] * d])) {
           O.err = "curved element node at a corner differs from its vertex";
           return false;
         }
-    auto mid = [&](int e, int f) {
-      const int a = f / 2 == 0 ? 2 * (f % 2) : 1, b = f / 2 == 0 ? 1 : 2 * (f % 2);
-      return &O.geo[((size_t)e * 9 + a + 3 * b) * 2];
-    };
-    for (const Face& F : O.faces)
-      if (F.eR >= 0 && !same(mid(F.eL, F.fL), mid(F.eR, F.fR))) {
-        O.err = "non-conforming curved face";
-        return false;
       }
+    for (const Face& F : O.faces) {
+      if (F.eR < 0) continue;
+      for (int k = 0; k < ng; ++k) {
+        if (digit(k, F.fL / 2) != 2 * (F.fL % 2)) continue;
+        bool found = false;
+        for (int k2 = 0; k2 < ng; ++k2)
+          if (digit(k2, F.fR / 2) == 2 * (F.fR % 2) && same(node(F.eL, k), node(F.eR, k2))) found = true;
+        if (!found) {
+          O.err = "non-conforming curved face";
+          return false;
+        }
+      }
+    }
   }
 
   // Geometry and per-element orthonormalisation with the (pmax+2)-point rule,
@@ -1390,9 +1399,8 @@ void* orc_create(int dim, int n_vert, const double* xyz, int n_elem, const int32
   O->xyz.assign(xyz, xyz + (size_t)n_vert * dim);
   O->ev.assign(ev, ev + (size_t)n_elem * (1 << dim));
   O->tag.assign(tag, tag + (size_t)n_elem * 2 * dim);
-  if (geo && dim == 2) O->geo.assign(geo, geo + (size_t)n_elem * 18);
-  if (geo && dim != 2) O->err = "curved elements are 2D only";
-  if ((dim != 2 && dim != 3) || pmax < 0 || pmax > 6 || (geo && dim != 2) || !setup(*O)) {
+  if (geo && (dim == 2 || dim == 3)) O->geo.assign(geo, geo + (size_t)n_elem * (dim == 2 ? 18 : 81));
+  if ((dim != 2 && dim != 3) || pmax < 0 || pmax > 6 || !setup(*O)) {
     if (errbuf && errlen > 0) std::snprintf(errbuf, errlen, "%s", O->err.c_str());
     delete O;
     return nullptr;

@@ -41,6 +41,8 @@ class _Mesh(C.Structure):
 def _c_mesh(m) -> _Mesh:
     """eg_mesh view of a contiguous mesh (the arrays must outlive the call)."""
     geo = getattr(m, "elem_geo", None)
+    if geo is not None and geo.shape != (m.n_elem, 3 ** m.dim, m.dim):
+        raise ValueError(f"elem_geo must have shape {(m.n_elem, 3 ** m.dim, m.dim)}, got {geo.shape}")
     return _Mesh(m.dim, m.n_vert, m.xyz.ctypes.data_as(C.POINTER(C.c_double)), m.n_elem,
                  m.elem_vert.ctypes.data_as(C.POINTER(C.c_int32)),
                  m.bface_tag.ctypes.data_as(C.POINTER(C.c_int8)),

@@ -126,6 +126,73 @@ __device__ __forceinline__ void geom(const R* X, const R* xi, R c[D][D], R& det)
   }
 }
 
+// Triquadratic map through 27 nodes (node a + 3b + 9c at reference point
+// (a-1, b-1, c-1); curved hexes, read from global memory): the same c[r] and
+// det as geom<3>.  X holds the element's 81 FP64 node coordinates.
+template <class R>
+__device__ __forceinline__ void geom_q3(const double* __restrict__ X, const R* xi, R c[3][3], R& det) {
+  R l[3][3], dl[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const R z = xi[r];
+    l[r][0] = R(0.5) * z * (z - R(1));
+    l[r][1] = R(1) - z * z;
+    l[r][2] = R(0.5) * z * (z + R(1));
+    dl[r][0] = z - R(0.5);
+    dl[r][1] = R(-2) * z;
+    dl[r][2] = z + R(0.5);
+  }
+  R t[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) t[r][a] = R(0);
+  for (int cc = 0; cc < 3; ++cc)
+    for (int b = 0; b < 3; ++b) {
+      // nodes (0..2, b, cc): partial sums over a of l and dl
+      R sl[3] = {R(0), R(0), R(0)}, sd[3] = {R(0), R(0), R(0)};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double* x = X + (a + 3 * b + 9 * cc) * 3;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const R v = R(x[q]);
+          sl[q] += l[0][a] * v;
+          sd[q] += dl[0][a] * v;
+        }
+      }
+      const R w0 = l[1][b] * l[2][cc], w1 = dl[1][b] * l[2][cc], w2 = l[1][b] * dl[2][cc];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        t[0][q] += w0 * sd[q];
+        t[1][q] += w1 * sl[q];
+        t[2][q] += w2 * sl[q];
+      }
+    }
+  c[0][0] = t[1][1] * t[2][2] - t[1][2] * t[2][1];
+  c[0][1] = t[1][2] * t[2][0] - t[1][0] * t[2][2];
+  c[0][2] = t[1][0] * t[2][1] - t[1][1] * t[2][0];
+  c[1][0] = t[2][1] * t[0][2] - t[2][2] * t[0][1];
+  c[1][1] = t[2][2] * t[0][0] - t[2][0] * t[0][2];
+  c[1][2] = t[2][0] * t[0][1] - t[2][1] * t[0][0];
+  c[2][0] = t[0][1] * t[1][2] - t[0][2] * t[1][1];
+  c[2][1] = t[0][2] * t[1][0] - t[0][0] * t[1][2];
+  c[2][2] = t[0][0] * t[1][1] - t[0][1] * t[1][0];
+  det = t[0][0] * c[0][0] + t[0][1] * c[0][1] + t[0][2] * c[0][2];
+}
+
+// Element map at xi: the nine-node quad map or the trilinear hex map from the
+// staged nodes Xs, or, in the instantiations for curved hexes (CQ), the
+// triquadratic map from the element's 27 nodes Xg in global memory.  A
+// compile-time choice: a run-time branch would give the straight-hex kernels
+// the register footprint of both paths.
+template <int D, bool CQ, class R>
+__device__ __forceinline__ void geom_any(const R* Xs, const double* __restrict__ Xg, const R* xi, R c[D][D],
+                                         R& det) {
+  if constexpr (D == 3 && CQ) geom_q3<R>(Xg, xi, c, det);
+  else geom<D>(Xs, xi, c, det);
+}
+
 // Tangential axes of face lf (ascending, skipping the normal axis lf / 2);
 // every index is static, so the caller's array stays in registers.
 template <int D>

@@ -205,23 +205,33 @@ void fill_tabdata(TabData& t, int d, int p, const std::vector<std::array<int, 3>
 }
 
 // Tangents of the element map at xi (biquadratic through nine nodes in 2D,
-// trilinear in 3D); returns det and c[r] (see geom in the kernels).
-double host_geom(int d, const double* X, const double* xi, double c[3][3]) {
+// trilinear, or triquadratic through 27 nodes, in 3D); returns det and c[r]
+// (see geom in the kernels).
+double host_geom(int d, int ng, const double* X, const double* xi, double c[3][3]) {
   double t[3][3] = {};
-  if (d == 2) {
-    auto l = [](int a, double z) { return a == 0 ? 0.5 * z * (z - 1.0) : a == 1 ? 1.0 - z * z : 0.5 * z * (z + 1.0); };
-    auto dl = [](int a, double z) { return a == 0 ? z - 0.5 : a == 1 ? -2.0 * z : z + 0.5; };
+  auto lq = [](int a, double z) { return a == 0 ? 0.5 * z * (z - 1.0) : a == 1 ? 1.0 - z * z : 0.5 * z * (z + 1.0); };
+  auto dlq = [](int a, double z) { return a == 0 ? z - 0.5 : a == 1 ? -2.0 * z : z + 0.5; };
+  if (d == 3 && ng == 27) {
+    for (int k = 0; k < 27; ++k) {
+      const int a[3] = {k % 3, (k / 3) % 3, k / 9};
+      for (int r = 0; r < 3; ++r) {
+        double g = 1.0;
+        for (int q = 0; q < 3; ++q) g *= (q == r) ? dlq(a[q], xi[q]) : lq(a[q], xi[q]);
+        for (int b = 0; b < 3; ++b) t[r][b] += g * X[k * 3 + b];
+      }
+    }
+  } else if (d == 2) {
     for (int b = 0; b < 3; ++b)
       for (int a = 0; a < 3; ++a)
         for (int q = 0; q < 2; ++q) {
-          t[0][q] += dl(a, xi[0]) * l(b, xi[1]) * X[(a + 3 * b) * 2 + q];
-          t[1][q] += l(a, xi[0]) * dl(b, xi[1]) * X[(a + 3 * b) * 2 + q];
+          t[0][q] += dlq(a, xi[0]) * lq(b, xi[1]) * X[(a + 3 * b) * 2 + q];
+          t[1][q] += lq(a, xi[0]) * dlq(b, xi[1]) * X[(a + 3 * b) * 2 + q];
         }
     c[0][0] = t[1][1]; c[0][1] = -t[1][0];
     c[1][0] = -t[0][1]; c[1][1] = t[0][0];
     return t[0][0] * t[1][1] - t[0][1] * t[1][0];
   }
-  for (int k = 0; k < (1 << d); ++k)
+  for (int k = 0; k < (ng == 27 ? 0 : 1 << d); ++k)
     for (int r = 0; r < d; ++r) {
       double g = 1.0;
       for (int q = 0; q < d; ++q) {
@@ -320,12 +330,29 @@ void straight_nodes9(const double Xc[][3], double* X) {
       }
 }
 
+// The 27 nodes of a straight-sided hex (corners Xc[a + 2b + 4c]): the
+// trilinear map written as a triquadratic one.
+void straight_nodes27(const double Xc[][3], double* X) {
+  for (int k = 0; k < 27; ++k) {
+    const int n[3] = {k % 3, (k / 3) % 3, k / 9};
+    for (int q = 0; q < 3; ++q) {
+      double v = 0.0;
+      for (int j = 0; j < 8; ++j) {
+        double w = 1.0;
+        for (int r = 0; r < 3; ++r) w *= ((j >> r) & 1) ? 0.5 * n[r] : 1.0 - 0.5 * n[r];
+        v += w * Xc[j][q];
+      }
+      X[k * 3 + q] = v;
+    }
+  }
+}
+
 eg_status setup_mesh(eg_handle* h, const eg_mesh* mesh, std::vector<double>& xv, std::vector<int>& nbr,
                      std::vector<uint8_t>& ncode, std::vector<double>& Lpk, std::vector<double>& Gpk,
                      std::vector<double>& hE, double& omega, std::vector<double>& vol) {
   const int d = mesh->dim, ne = mesh->n_elem, nf = 2 * d, nc = 1 << d, ncf = 1 << (d - 1);
-  const int ng = eg::geo_nodes(d);  // geometry nodes per element
-  if (mesh->elem_geo && d != 2) return fail(h, EG_ERR_UNSUPPORTED, "curved elements are 2D only");
+  // geometry nodes per element: 9 per quad, 8 per straight hex, 27 per curved hex
+  const int ng = (mesh->elem_geo && d == 3) ? 27 : eg::geo_nodes(d);
   auto near = [](double a, double b) { return std::fabs(a - b) <= 1e-12 * std::max(1.0, std::fabs(a)); };
   xv.assign((size_t)ne * ng * d, 0.0);
   for (int e = 0; e < ne; ++e) {
@@ -336,17 +363,19 @@ eg_status setup_mesh(eg_handle* h, const eg_mesh* mesh, std::vector<double>& xv,
       for (int a = 0; a < d; ++a) Xc[k][a] = mesh->xyz[(size_t)vid * d + a];
     }
     double* X = &xv[(size_t)e * ng * d];
-    if (d == 3) {
+    if (mesh->elem_geo) {
+      const double* G = &mesh->elem_geo[(size_t)e * ng * d];
+      for (int k = 0; k < ng * d; ++k) X[k] = G[k];
+      for (int k = 0; k < nc; ++k) {
+        int node = 0;  // the node at vertex k: digits 2 * bit_r in base 3
+        for (int r = 0, p3 = 1; r < d; ++r, p3 *= 3) node += 2 * ((k >> r) & 1) * p3;
+        for (int a = 0; a < d; ++a)
+          if (!near(Xc[k][a], X[node * d + a]))
+            return fail(h, EG_ERR_MESH, "curved element node at a corner differs from its vertex");
+      }
+    } else if (d == 3) {
       for (int k = 0; k < nc; ++k)
         for (int a = 0; a < d; ++a) X[k * d + a] = Xc[k][a];
-    } else if (mesh->elem_geo) {
-      const double* G = &mesh->elem_geo[(size_t)e * 18];
-      for (int k = 0; k < 18; ++k) X[k] = G[k];
-      static const int corner_node[4] = {0, 2, 6, 8};
-      for (int k = 0; k < 4; ++k)
-        for (int a = 0; a < 2; ++a)
-          if (!near(Xc[k][a], X[corner_node[k] * 2 + a]))
-            return fail(h, EG_ERR_MESH, "curved element node at a corner differs from its vertex");
     } else {
       straight_nodes9(Xc, X);
     }
@@ -434,15 +463,30 @@ eg_status setup_mesh(eg_handle* h, const eg_mesh* mesh, std::vector<double>& xv,
     uint8_t c12, c21;
     if (!code_of(e1, l1, e2, l2, c12) || !code_of(e2, l2, e1, l1, c21))
       return fail(h, EG_ERR_MESH, "non-conforming face");
-    if (d == 2 && mesh->elem_geo) {
-      // a curved edge is shared only if both sides put its middle node at
-      // the same point (the end nodes are the shared vertices)
-      auto mid = [&](int e, int lf) {
+    if (mesh->elem_geo) {
+      // a curved face is shared only if both sides put its nodes (3 per
+      // edge, 9 per quadrilateral face) at the same points
+      auto face_nodes = [&](int e, int lf, std::vector<const double*>& out) {
         const int r = lf / 2, s2 = 2 * (lf % 2);
-        return &xv[((size_t)e * 9 + (r == 0 ? s2 + 3 : 1 + 3 * s2)) * 2];
+        out.clear();
+        for (int k = 0; k < ng; ++k) {
+          int dig = k;
+          for (int q = 0; q < r; ++q) dig /= 3;
+          if (dig % 3 == s2) out.push_back(&xv[((size_t)e * ng + k) * d]);
+        }
       };
-      const double *m1 = mid(e1, l1), *m2 = mid(e2, l2);
-      if (!near(m1[0], m2[0]) || !near(m1[1], m2[1])) return fail(h, EG_ERR_MESH, "non-conforming curved face");
+      std::vector<const double*> f1, f2;
+      face_nodes(e1, l1, f1);
+      face_nodes(e2, l2, f2);
+      for (const double* a : f1) {
+        bool found = false;
+        for (const double* b : f2) {
+          bool same = true;
+          for (int q = 0; q < d; ++q) same = same && near(a[q], b[q]);
+          found = found || same;
+        }
+        if (!found) return fail(h, EG_ERR_MESH, "non-conforming curved face");
+      }
     }
     nbr[(size_t)e1 * nf + l1] = e2;
     ncode[(size_t)e1 * nf + l1] = c12;
@@ -484,7 +528,7 @@ eg_status setup_mesh(eg_handle* h, const eg_mesh* mesh, std::vector<double>& xv,
       double xi[3], wq = 1.0;
       for (int r = 0; r < d; ++r) { iq[r] = t % Q; t /= Q; xi[r] = gx[iq[r]]; wq *= gw[iq[r]]; }
       double c[3][3];
-      double det = host_geom(d, X, xi, c);
+      double det = host_geom(d, ng, X, xi, c);
       if (!(det > 0.0)) bad++;
       V += wq * det;
       const double* ph = &phi[(size_t)q * N];
@@ -495,7 +539,7 @@ eg_status setup_mesh(eg_handle* h, const eg_mesh* mesh, std::vector<double>& xv,
       double xi[3];
       for (int r = 0; r < d; ++r) xi[r] = ((k >> r) & 1) ? 1.0 : -1.0;
       double c[3][3];
-      if (!(host_geom(d, X, xi, c) > 0.0)) bad++;
+      if (!(host_geom(d, ng, X, xi, c) > 0.0)) bad++;
     }
     for (int lf = 0; lf < nf; ++lf) {
       int r = lf / 2, ta[2], kk = 0;
@@ -507,7 +551,7 @@ eg_status setup_mesh(eg_handle* h, const eg_mesh* mesh, std::vector<double>& xv,
         int t = k;
         for (int q2 = 0; q2 < d - 1; ++q2) { xi[ta[q2]] = gx[t % Q]; wk *= gw[t % Q]; t /= Q; }
         double c[3][3];
-        host_geom(d, X, xi, c);
+        host_geom(d, ng, X, xi, c);
         double a2 = 0.0;
         for (int a = 0; a < d; ++a) a2 += c[r][a] * c[r][a];
         S += wk * std::sqrt(a2);
@@ -851,7 +895,7 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
   M.V = d + 2;
   M.ne = mesh->n_elem;
   M.NF = 2 * d;
-  M.NC = eg::geo_nodes(d);
+  M.NC = (mesh->elem_geo && d == 3) ? 27 : eg::geo_nodes(d);
   const int N = nmodes_of(d, h->pmax);
   M.NT = N * (N + 1) / 2;
   M.gas.g = prm->gamma;
@@ -1373,11 +1417,8 @@ eg_status eg_init_batch(const eg_mesh* meshes, const eg_params* params, int n_so
   std::vector<int8_t> tag((size_t)ne * nf);
   bool curved = false;
   for (int i = 0; i < n_solves; ++i) curved = curved || meshes[i].elem_geo;
-  if (curved && d != 2) {
-    h->err = "curved elements are 2D only";
-    return EG_ERR_UNSUPPORTED;
-  }
-  std::vector<double> geo(curved ? (size_t)ne * 18 : 0);
+  const int gn = d == 2 ? 18 : 81;  // node coordinates per curved element
+  std::vector<double> geo(curved ? (size_t)ne * gn : 0);
   BatchDef bd;
   bd.n = n_solves;
   bd.e0.push_back(0);
@@ -1394,13 +1435,14 @@ eg_status eg_init_batch(const eg_mesh* meshes, const eg_params* params, int n_so
     }
     std::memcpy(&tag[(size_t)oe * nf], m.bface_tag, (size_t)m.n_elem * nf);
     if (curved && m.elem_geo) {
-      std::memcpy(&geo[(size_t)oe * 18], m.elem_geo, sizeof(double) * 18 * (size_t)m.n_elem);
-    } else if (curved) {  // a straight mesh among curved ones: its bilinear nodes
+      std::memcpy(&geo[(size_t)oe * gn], m.elem_geo, sizeof(double) * gn * (size_t)m.n_elem);
+    } else if (curved) {  // a straight mesh among curved ones: its multilinear nodes
       for (int e = 0; e < m.n_elem; ++e) {
-        double Xc[4][3];
-        for (int k = 0; k < 4; ++k)
-          for (int a = 0; a < 2; ++a) Xc[k][a] = m.xyz[(size_t)m.elem_vert[(size_t)e * 4 + k] * 2 + a];
-        straight_nodes9(Xc, &geo[((size_t)oe + e) * 18]);
+        double Xc[8][3];
+        for (int k = 0; k < nc; ++k)
+          for (int a = 0; a < d; ++a) Xc[k][a] = m.xyz[(size_t)m.elem_vert[(size_t)e * nc + k] * d + a];
+        if (d == 2) straight_nodes9(Xc, &geo[((size_t)oe + e) * gn]);
+        else straight_nodes27(Xc, &geo[((size_t)oe + e) * gn]);
       }
     }
     ov += m.n_vert;

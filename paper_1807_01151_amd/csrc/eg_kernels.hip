@@ -63,9 +63,9 @@ constexpr bool res_tables() {
   return res_table_values<D, P, R>() * (int)sizeof(R) <= 32 * 1024;
 }
 
-template <int D, int P, int EB, class R>
+template <int D, int P, int EB, class R, bool CQ = false>
 __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut, const double* __restrict__ fadd,
-                                                  double* __restrict__ rt, const double* __restrict__ xv,
+                                                  double* __restrict__ rt, const double* __restrict__ xv, int nc,
                                                   const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
                                                   int ne, Tab<D, P, R> tab, GasT<R> gas,
                                                   const double* __restrict__ uinf_e, FasOut fas) {
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
   {
     const int nel = min(EB, ne - e0);
     stage<(EB * V * N + 255) / 256>(s_u, ut + (size_t)e0 * V * N, nel * V * N, tid, 256);
-    stage<(EB * NC * D + 255) / 256>(s_x, xv + (size_t)e0 * NC * D, nel * NC * D, tid, 256);
+    if (!CQ) stage<(EB * NC * D + 255) / 256>(s_x, xv + (size_t)e0 * NC * D, nel * NC * D, tid, 256);
   }
   __syncthreads();
   if constexpr (TBL) {
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
       for (int v = 0; v < V; ++v) U[v] += su[v * N + k] * ph;
     }
     R c[D][D], det;
-    geom<D>(&s_x[el * NC * D], xi, c, det);
+    geom_any<D, CQ>(&s_x[el * NC * D], xv + (size_t)(e0 + el) * nc * D, xi, c, det);
 #pragma unroll
     for (int r = 0; r < D; ++r) {
       R F[V];
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void k_residual(const double* __restrict__ ut,
       for (int v = 0; v < V; ++v) UL[v] += su[v * N + j] * ph;
     }
     R c[D][D], det;
-    geom<D>(&s_x[el * NC * D], xi, c, det);
+    geom_any<D, CQ>(&s_x[el * NC * D], xv + (size_t)(e0 + el) * nc * D, xi, c, det);
     R nh[D], a2 = R(0);
     const R sg = (lf & 1) ? R(1) : R(-1);
 #pragma unroll
@@ -276,8 +276,8 @@ constexpr int jac_lds_values() {
   return (ph1 > ph2 ? ph1 : ph2);
 }
 
-template <int D, int P, bool FACTOR, class R>
-__global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut, const double* __restrict__ xv,
+template <int D, int P, bool FACTOR, class R, bool CQ = false>
+__global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut, const double* __restrict__ xv, int nc,
                                                   const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
                                                   const double* __restrict__ Gpk, int NT, const double* __restrict__ dtau,
                                                   R* __restrict__ out, int* __restrict__ perm, int* __restrict__ fail,
@@ -302,7 +302,8 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
   if (e >= ne) return;
   copy_tab(t, tab);
   for (int i = tid; i < V * N; i += blockDim.x) s_u[i] = ut[(size_t)e * V * N + i];
-  for (int i = tid; i < NC * D; i += blockDim.x) s_x[i] = xv[(size_t)e * NC * D + i];
+  if (!CQ)
+    for (int i = tid; i < NC * D; i += blockDim.x) s_x[i] = xv[(size_t)e * NC * D + i];
   __syncthreads();
   for (int q = tid; q < QV; q += blockDim.x) {
     int iq[D];
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
       U[v].d[v] = R(1);
     }
     R c[D][D], det;
-    geom<D>(s_x, xi, c, det);
+    geom_any<D, CQ>(s_x, xv + (size_t)e * nc * D, xi, c, det);
 #pragma unroll
     for (int r = 0; r < D; ++r) {
       Dual<V, R> F[V];
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
       UL[v].d[v] = R(1);
     }
     R c[D][D], det;
-    geom<D>(s_x, xi, c, det);
+    geom_any<D, CQ>(s_x, xv + (size_t)e * nc * D, xi, c, det);
     R nh[D], a2 = R(0);
     const R sg = (lf & 1) ? R(1) : R(-1);
 #pragma unroll
@@ -518,8 +519,8 @@ __global__ __launch_bounds__(256) void k_jacobian(const double* __restrict__ ut,
 // element: [QV][D][V][V] then [NF*QF][V][V].  The thread index runs over
 // all volume points first, then all face points, so that a wavefront takes
 // one of the two paths.
-template <int D, int P, class R>
-__global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ ut, const double* __restrict__ xv,
+template <int D, int P, class R, bool CQ = false>
+__global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ ut, const double* __restrict__ xv, int nc,
                                                     const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
                                                     R* __restrict__ BC, int ne, Tab<D, P, R> tab, GasT<R> gas,
                                                     const double* __restrict__ uinf_e) {
@@ -538,7 +539,7 @@ __global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ u
   const double* ue = ut + (size_t)e * V * N;
   R X[NC * D];
 #pragma unroll
-  for (int a = 0; a < NC * D; ++a) X[a] = R(xv[(size_t)e * NC * D + a]);
+  for (int a = 0; a < NC * D; ++a) X[a] = R(xv[(size_t)e * nc * D + a]);  // unused when nc == 27
   R* out = BC + (size_t)e * PER;
   if (pt < QV) {
     const int q = pt;
@@ -555,7 +556,7 @@ __global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ u
       U[v].d[v] = R(1);
     }
     R c[D][D], det;
-    geom<D>(X, xi, c, det);
+    geom_any<D, CQ>(X, xv + (size_t)e * nc * D, xi, c, det);
 #pragma unroll
     for (int r = 0; r < D; ++r) {
       Dual<V, R> F[V];
@@ -582,7 +583,7 @@ __global__ __launch_bounds__(256) void k_jac_points(const double* __restrict__ u
       UL[v].d[v] = R(1);
     }
     R c[D][D], det;
-    geom<D>(X, xi, c, det);
+    geom_any<D, CQ>(X, xv + (size_t)e * nc * D, xi, c, det);
     R nh[D], a2 = R(0);
     const R sg = (lf & 1) ? R(1) : R(-1);
 #pragma unroll
@@ -1451,9 +1452,9 @@ __global__ __launch_bounds__(256) void k_norm_segsum(const double* __restrict__ 
 //   dt = (p_max+1) dtau(p_max),  b = dt (R0 + f0),  A = dt J0 (row scaling).
 // scale = false: dt = 1 (plain J0 and R0 + f0).
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, bool CQ = false>
 __global__ __launch_bounds__(256) void k_p0_setup(const double* __restrict__ ut0, const double* __restrict__ ft0,
-                                                  const double* __restrict__ xv, const int* __restrict__ nbr,
+                                                  const double* __restrict__ xv, int nc, const int* __restrict__ nbr,
                                                   const double* __restrict__ Lpk, int NT, const double* __restrict__ hE,
                                                   int pmax, double cfl, int scale, double* __restrict__ u0,
                                                   double* __restrict__ bvec, double* __restrict__ Ad,
@@ -1495,7 +1496,7 @@ __global__ __launch_bounds__(256) void k_p0_setup(const double* __restrict__ ut0
   if (act) {
     double X[NC * D];
 #pragma unroll
-    for (int i = 0; i < NC * D; ++i) X[i] = xv[(size_t)e * NC * D + i];
+    for (int i = 0; i < NC * D; ++i) X[i] = xv[(size_t)e * nc * D + i];  // unused when nc == 27
     nb = nbr[(size_t)e * NF + lf];
     double UN[V];
     if (nb >= 0) {
@@ -1511,7 +1512,7 @@ __global__ __launch_bounds__(256) void k_p0_setup(const double* __restrict__ ut0
 #pragma unroll
     for (int q = 0; q < D - 1; ++q) { xi[ta[q]] = gx[r0 & 1]; wk *= gw[r0 & 1]; r0 >>= 1; }
     double c[D][D], det;
-    geom<D>(X, xi, c, det);
+    geom_any<D, CQ>(X, xv + (size_t)e * nc * D, xi, c, det);
     double nh[D], a2 = 0.0;
     const double sg = (lf & 1) ? 1.0 : -1.0;
 #pragma unroll
@@ -2384,8 +2385,8 @@ struct Dir3 {
   double v[3];
 };
 
-template <int D, int P>
-__global__ __launch_bounds__(128) void k_drag(const double* __restrict__ ut, const double* __restrict__ xv,
+template <int D, int P, bool CQ = false>
+__global__ __launch_bounds__(128) void k_drag(const double* __restrict__ ut, const double* __restrict__ xv, int nc,
                                               const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
                                               int ne, Tab<D, P> tab, Gas gas, Dir3 dir,
                                               double scale, double* __restrict__ part, double* __restrict__ gt) {
@@ -2404,7 +2405,7 @@ __global__ __launch_bounds__(128) void k_drag(const double* __restrict__ ut, con
     if (nbr[(size_t)e * NF + lf] != NB_WALL || ncode[(size_t)e * NF + lf] == NCODE_SYMMETRY) continue;
     double X[NC * D];
 #pragma unroll
-    for (int a = 0; a < NC * D; ++a) X[a] = xv[(size_t)e * NC * D + a];
+    for (int a = 0; a < NC * D; ++a) X[a] = xv[(size_t)e * nc * D + a];  // unused when nc == 27
     int ta[D - 1 > 0 ? D - 1 : 1], ik[D - 1 > 0 ? D - 1 : 1];
     face_axes<D>(lf, ta);
     for (int k = 0; k < QF; ++k) {
@@ -2414,7 +2415,7 @@ __global__ __launch_bounds__(128) void k_drag(const double* __restrict__ ut, con
 #pragma unroll
       for (int q = 0; q < D - 1; ++q) { ik[q] = r0 % Q; r0 /= Q; xi[ta[q]] = t.x[ik[q]]; wk *= t.w[ik[q]]; }
       double c[D][D], det;
-      geom<D>(X, xi, c, det);
+      geom_any<D, CQ>(X, xv + (size_t)e * nc * D, xi, c, det);
       double nh[D], a2 = 0.0;
       const double sg = (lf & 1) ? 1.0 : -1.0;
 #pragma unroll
@@ -2852,12 +2853,12 @@ constexpr int res_tile_cand() {
   return C == 0 ? half : C == 2 ? (more < 1 ? 1 : more) : def;
 }
 
-template <int D, int P, int EB, class R>
+template <int D, int P, int EB, class R, bool CQ = false>
 hipError_t residual_launch(const DevMesh& M, const Tab<D, P, R>& t, const double* ut, const double* fadd, double* rt,
                            const FasOut& fas, hipStream_t st) {
   const int grid = (M.ne + EB - 1) / EB;
-  hipLaunchKernelGGL((k_residual<D, P, EB, R>), dim3(grid), dim3(256), 0, st, ut, fadd, rt, M.xv, M.nbr, M.ncode,
-                     M.ne, t, gas_as<R>(M.gas), M.uinf_e, fas);
+  hipLaunchKernelGGL((k_residual<D, P, EB, R, CQ>), dim3(grid), dim3(256), 0, st, ut, fadd, rt, M.xv, M.NC, M.nbr,
+                     M.ncode, M.ne, t, gas_as<R>(M.gas), M.uinf_e, fas);
   return hipGetLastError();
 }
 
@@ -2866,6 +2867,10 @@ hipError_t residual_t(const DevMesh& M, const TabData& td, const double* ut, con
                       const FasOut& fas, int choice, hipStream_t st) {
   Tab<D, P, R> t;
   fill_tab(t, td);
+  if constexpr (D == 3) {
+    // curved hexes: one tile (the default) of the triquadratic instantiation
+    if (M.NC == 27) return residual_launch<D, P, res_tile_cand<D, P, R, 1>(), R, true>(M, t, ut, fadd, rt, fas, st);
+  }
   switch (choice) {
     case 0: return residual_launch<D, P, res_tile_cand<D, P, R, 0>(), R>(M, t, ut, fadd, rt, fas, st);
     case 2: return residual_launch<D, P, res_tile_cand<D, P, R, 2>(), R>(M, t, ut, fadd, rt, fas, st);
@@ -2878,6 +2883,42 @@ int res_tile_of(int choice) {
   return choice == 0 ? res_tile_cand<D, P, R, 0>() : choice == 2 ? res_tile_cand<D, P, R, 2>() : res_tile_cand<D, P, R, 1>();
 }
 
+// Point Jacobians of every element (k_jac_points, the triquadratic
+// instantiation on curved hexes).
+template <int D, int P, class R>
+void launch_jac_points_t(const DevMesh& M, const Tab<D, P, R>& t, const GasT<R>& gas, const double* ut, R* bc,
+                         hipStream_t st) {
+  using C = Cfg<D, P>;
+  constexpr int NPT = C::QV + C::NF * C::QF;
+  const int items = M.ne * NPT;
+  if constexpr (D == 3) {
+    if (M.NC == 27) {
+      hipLaunchKernelGGL((k_jac_points<D, P, R, true>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.NC,
+                         M.nbr, M.ncode, bc, M.ne, t, gas, M.uinf_e);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_jac_points<D, P, R>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.NC, M.nbr,
+                     M.ncode, bc, M.ne, t, gas, M.uinf_e);
+}
+
+// The generic one-workgroup-per-element assembly (and LU), straight or curved.
+template <int D, int P, bool FACTOR, class R, bool CQ>
+hipError_t launch_jacobian_generic(const DevMesh& M, const Tab<D, P, R>& t, const GasT<R>& gas, const double* ut,
+                                   const double* dtau, R* out, int* perm, int* fail, hipStream_t st) {
+  const size_t lds = (size_t)jac_lds_values<D, P>() * sizeof(R);
+  auto kf = k_jacobian<D, P, FACTOR, R, CQ>;
+  static bool attr = false;  // set once: not a stream operation, so also fine while capturing
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.NC, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
+                     fail, M.ne, t, gas, M.uinf_e);
+  return hipGetLastError();
+}
+
 template <int D, int P, class R>
 hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, const double* dtau, void* outv,
                       int* perm, int* fail, bool factor, hipStream_t st) {
@@ -2887,12 +2928,8 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
   const GasT<R> gas = gas_as<R>(M.gas);
   if constexpr (Cfg<D, P>::NB < 256) {
     if (factor && M.bc) {
-      using C = Cfg<D, P>;
-      constexpr int NPT = C::QV + C::NF * C::QF;
-      const int items = M.ne * NPT;
       R* bc = static_cast<R*>(M.bc);
-      hipLaunchKernelGGL((k_jac_points<D, P, R>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.nbr,
-                         M.ncode, bc, M.ne, t, gas, M.uinf_e);
+      launch_jac_points_t<D, P, R>(M, t, gas, ut, bc, st);
       if constexpr (Cfg<D, P>::NB == 16) {
         const R* gph = static_cast<const R*>(M.phitab[P][sizeof(R) == 4 ? PREC_FP32 : PREC_FP64]);
         if (!gph) return hipErrorInvalidValue;
@@ -2915,41 +2952,21 @@ hipError_t jacobian_t(const DevMesh& M, const TabData& td, const double* ut, con
     // n >= 256 (3D p = 3): point Jacobians, then assembly (and LU) with the
     // block in global memory, factored or not
     if (!M.bc || !jaclu_big_supported(D, P)) return hipErrorInvalidValue;
-    using C = Cfg<D, P>;
-    constexpr int NPT = C::QV + C::NF * C::QF;
-    const int items = M.ne * NPT;
     R* bc = static_cast<R*>(M.bc);
-    hipLaunchKernelGGL((k_jac_points<D, P, R>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.nbr,
-                       M.ncode, bc, M.ne, t, gas, M.uinf_e);
+    launch_jac_points_t<D, P, R>(M, t, gas, ut, bc, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_jaclu_big(M, P, sizeof(R) == 4 ? PREC_FP32 : PREC_FP64, bc,
                             M.phitab[P][sizeof(R) == 4 ? PREC_FP32 : PREC_FP64], dtau, out, perm, fail, factor, st);
   }
   if constexpr (Cfg<D, P>::NB < 256) {
-    const size_t lds = (size_t)jac_lds_values<D, P>() * sizeof(R);
-    if (factor) {
-      auto kf = k_jacobian<D, P, true, R>;
-      static bool attr = false;  // set once: not a stream operation, so also fine while capturing
-      if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr = true;
-      }
-      hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
-                         fail, M.ne, t, gas, M.uinf_e);
-    } else {
-      auto kf = k_jacobian<D, P, false, R>;
-      static bool attr = false;
-      if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr = true;
-      }
-      hipLaunchKernelGGL(kf, dim3(M.ne), dim3(256), lds, st, ut, M.xv, M.nbr, M.ncode, M.Gpk, M.NT, dtau, out, perm,
-                         fail, M.ne, t, gas, M.uinf_e);
+    if constexpr (D == 3) {
+      if (M.NC == 27)
+        return factor ? launch_jacobian_generic<D, P, true, R, true>(M, t, gas, ut, dtau, out, perm, fail, st)
+                      : launch_jacobian_generic<D, P, false, R, true>(M, t, gas, ut, dtau, out, perm, fail, st);
     }
-    return hipGetLastError();
+    return factor ? launch_jacobian_generic<D, P, true, R, false>(M, t, gas, ut, dtau, out, perm, fail, st)
+                  : launch_jacobian_generic<D, P, false, R, false>(M, t, gas, ut, dtau, out, perm, fail, st);
   }
 }
 
@@ -3178,10 +3195,14 @@ hipError_t launch_p0_setup(const DevMesh& M, const double* ut0, const double* ft
   // 8 (2D) or 32 (3D) lanes per element
   const int grid = M.d == 2 ? (M.ne + 31) / 32 : (M.ne + 7) / 8;
   if (M.d == 2)
-    hipLaunchKernelGGL((k_p0_setup<2>), dim3(grid), dim3(256), 0, st, ut0, ft0, M.xv, M.nbr, M.Lpk, M.NT, M.hE, pmax,
+    hipLaunchKernelGGL((k_p0_setup<2>), dim3(grid), dim3(256), 0, st, ut0, ft0, M.xv, M.NC, M.nbr, M.Lpk, M.NT, M.hE, pmax,
                        cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w, M.uinf_e, cfl_ptr(M), cfl_stride(M));
+  else if (M.NC == 27)
+    hipLaunchKernelGGL((k_p0_setup<3, true>), dim3(grid), dim3(256), 0, st, ut0, ft0, M.xv, M.NC, M.nbr, M.Lpk, M.NT,
+                       M.hE, pmax, cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w, M.uinf_e, cfl_ptr(M),
+                       cfl_stride(M));
   else
-    hipLaunchKernelGGL((k_p0_setup<3>), dim3(grid), dim3(256), 0, st, ut0, ft0, M.xv, M.nbr, M.Lpk, M.NT, M.hE, pmax,
+    hipLaunchKernelGGL((k_p0_setup<3>), dim3(grid), dim3(256), 0, st, ut0, ft0, M.xv, M.NC, M.nbr, M.Lpk, M.NT, M.hE, pmax,
                        cfl, scale, u0, b, Ad, Ao, dt, M.ne, M.gas, M.g2x, M.g2w, M.uinf_e, cfl_ptr(M), cfl_stride(M));
   return hipGetLastError();
 }
@@ -3409,11 +3430,7 @@ template <int D, int P>
 hipError_t jac_points_only_t(const DevMesh& M, const TabData& td, const double* ut, double* bc, hipStream_t st) {
   Tab<D, P, double> t;
   fill_tab(t, td);
-  using C = Cfg<D, P>;
-  constexpr int NPT = C::QV + C::NF * C::QF;
-  const int items = M.ne * NPT;
-  hipLaunchKernelGGL((k_jac_points<D, P, double>), dim3((items + 255) / 256), dim3(256), 0, st, ut, M.xv, M.nbr,
-                     M.ncode, bc, M.ne, t, M.gas, M.uinf_e);
+  launch_jac_points_t<D, P, double>(M, t, M.gas, ut, bc, st);
   return hipGetLastError();
 }
 
@@ -3443,8 +3460,12 @@ hipError_t drag_t(const DevMesh& M, const TabData& td, const double* ut, const d
   Tab<D, P, double> t;
   fill_tab(t, td);
   Dir3 dv{{dir[0], dir[1], dir[2]}};
-  hipLaunchKernelGGL((k_drag<D, P>), dim3((M.ne + 127) / 128), dim3(128), 0, st, ut, M.xv, M.nbr, M.ncode, M.ne, t,
-                     M.gas, dv, scale, part, gt);
+  if (D == 3 && M.NC == 27)
+    hipLaunchKernelGGL((k_drag<D, P, true>), dim3((M.ne + 127) / 128), dim3(128), 0, st, ut, M.xv, M.NC, M.nbr,
+                       M.ncode, M.ne, t, M.gas, dv, scale, part, gt);
+  else
+    hipLaunchKernelGGL((k_drag<D, P>), dim3((M.ne + 127) / 128), dim3(128), 0, st, ut, M.xv, M.NC, M.nbr, M.ncode,
+                       M.ne, t, M.gas, dv, scale, part, gt);
   return hipGetLastError();
 }
 }  // namespace

@@ -26,9 +26,9 @@ namespace eg {
 
 namespace {
 
-template <int D, int P>
+template <int D, int P, bool CQ = false>
 __global__ __launch_bounds__(256) void k_tangent(const double* __restrict__ ut, const double* __restrict__ vt,
-                                                 double* __restrict__ jv, const double* __restrict__ xv,
+                                                 double* __restrict__ jv, const double* __restrict__ xv, int nc,
                                                  const int* __restrict__ nbr, const uint8_t* __restrict__ ncode,
                                                  int ne, Tab<D, P, double> tab, Gas gas,
                                                  const double* __restrict__ uinf_e) {
@@ -46,7 +46,8 @@ __global__ __launch_bounds__(256) void k_tangent(const double* __restrict__ ut, 
     s_u[i] = ut[(size_t)e * V * N + i];
     s_v[i] = vt[(size_t)e * V * N + i];
   }
-  for (int i = tid; i < NC * D; i += blockDim.x) s_x[i] = xv[(size_t)e * NC * D + i];
+  if (!CQ)
+    for (int i = tid; i < NC * D; i += blockDim.x) s_x[i] = xv[(size_t)e * NC * D + i];
   __syncthreads();
   // volume points
   for (int q = tid; q < QV; q += blockDim.x) {
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(256) void k_tangent(const double* __restrict__ ut, 
       U[v].d[0] = b;
     }
     double c[D][D], det;
-    geom<D>(s_x, xi, c, det);
+    geom_any<D, CQ>(s_x, xv + (size_t)e * nc * D, xi, c, det);
 #pragma unroll
     for (int r = 0; r < D; ++r) {
       T1 F[V];
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(256) void k_tangent(const double* __restrict__ ut, 
       UL[v].d[0] = b;
     }
     double c[D][D], det;
-    geom<D>(s_x, xi, c, det);
+    geom_any<D, CQ>(s_x, xv + (size_t)e * nc * D, xi, c, det);
     double nh[D], a2 = 0.0;
     const double sg = (lf & 1) ? 1.0 : -1.0;
 #pragma unroll
@@ -170,8 +171,12 @@ hipError_t tangent_t(const DevMesh& M, const TabData& td, const double* ut, cons
                      hipStream_t st) {
   Tab<D, P, double> t;
   fill_tab(t, td);
-  hipLaunchKernelGGL((k_tangent<D, P>), dim3(M.ne), dim3(128), 0, st, ut, vt, jv, M.xv, M.nbr, M.ncode, M.ne, t,
-                     M.gas, M.uinf_e);
+  if (D == 3 && M.NC == 27)
+    hipLaunchKernelGGL((k_tangent<D, P, true>), dim3(M.ne), dim3(128), 0, st, ut, vt, jv, M.xv, M.NC, M.nbr, M.ncode,
+                       M.ne, t, M.gas, M.uinf_e);
+  else
+    hipLaunchKernelGGL((k_tangent<D, P>), dim3(M.ne), dim3(128), 0, st, ut, vt, jv, M.xv, M.NC, M.nbr, M.ncode, M.ne,
+                       t, M.gas, M.uinf_e);
   return hipGetLastError();
 }
 

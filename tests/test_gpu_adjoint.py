@@ -36,6 +36,7 @@ CASES = [
     ("sphere6x2x2x2-p3", cubed_sphere_shell(2, 2), 3, 1.0),
     ("ogrid12x4c-p3-curved", ogrid(12, 4, curved=True), 3, 2.0),
     ("sphere6x4x4x2-quarter-p2-symmetry", _quarter(cubed_sphere_shell(4, 2)), 2, 0.0),
+    ("sphere6x2x2x2c-p3-curved", cubed_sphere_shell(2, 2, curved=True), 3, 1.0),
 ]
 
 

@@ -23,6 +23,7 @@ CASES = [
     ("sphere6x2x2x2-p2-roe", cubed_sphere_shell(2, 2), 2, 2.0, "roe"),
     ("sphere6x2x2x2-p3", cubed_sphere_shell(2, 2), 3, 2.0, "rusanov"),
     ("ogrid12x4c-p3-curved-reoriented", reorient(ogrid(12, 4, curved=True), 6), 3, 3.0, "roe"),
+    ("sphere6x2x2x2c-p2-curved-reoriented", reorient(cubed_sphere_shell(2, 2, curved=True), 7), 2, 2.0, "rusanov"),
 ]
 
 

@@ -24,6 +24,8 @@ CASES = [
     ("sphere6x2x2x2-p2", cubed_sphere_shell(2, 2), 2, 2.0),
     ("sphere6x2x2x2-p3", cubed_sphere_shell(2, 2), 3, 2.0),
     ("ogrid10x3c-p4-curved", ogrid(10, 3, curved=True), 4, -2.0),
+    ("sphere6x2x2x2c-p2-curved", cubed_sphere_shell(2, 2, curved=True), 2, 2.0),
+    ("sphere6x2x2x2c-p3-curved", cubed_sphere_shell(2, 2, curved=True), 3, 2.0),
 ]
 
 

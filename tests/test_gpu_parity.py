@@ -53,6 +53,12 @@ CASES = [
     # symmetry planes: half O-grid (y > 0) and quarter sphere (y > 0, z > 0)
     ("ogrid16x6c-half-p3-symmetry", _half(ogrid(16, 6, curved=True), (1,)), 3, 0.0, "roe"),
     ("sphere6x4x4x2-quarter-p2-symmetry", _half(cubed_sphere_shell(4, 2), (1, 2)), 2, 0.0, "rusanov"),
+    # quadratic curved hexes (27-node triquadratic maps, nodes on the spheres)
+    ("sphere6x2x2x2c-p1-curved", cubed_sphere_shell(2, 2, curved=True), 1, 2.0, "rusanov"),
+    ("sphere6x2x2x2c-p2-curved-reoriented-roe", reorient(cubed_sphere_shell(2, 2, curved=True), 16), 2, 2.0, "roe"),
+    ("sphere6x2x2x2c-p3-curved", cubed_sphere_shell(2, 2, curved=True), 3, -1.0, "rusanov"),
+    ("sphere6x4x4x2c-quarter-p2-curved-symmetry", _half(cubed_sphere_shell(4, 2, curved=True), (1, 2)), 2, 0.0,
+     "rusanov"),
 ]
 IDS = [c[0] for c in CASES]
 

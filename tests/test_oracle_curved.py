@@ -1,9 +1,10 @@
-"""Pins of the oracle's quadratic curved quads (biquadratic nine-node element
-map; the cylinder grid of Section 5.1 is built from quadratic curved
-elements): the straight special case, closed-form areas, the h^4 geometric
-error of curved circles against h^2 of straight chords, free-stream
-preservation, local-frame invariance, mirror symmetry and the consistency
-rate of the residual on a curved annulus."""
+"""Pins of the oracle's quadratic curved elements (biquadratic nine-node quads
+and triquadratic 27-node hexes; the cylinder grid of Section 5.1 and the
+sphere grid of Section 5.2 are curved): the straight special case,
+closed-form areas and volumes, the h^4 geometric error of curved circles
+and spheres against h^2 of straight facets, free-stream preservation,
+local-frame invariance, mirror symmetry and the consistency rate of the
+residual on curved annuli and shells."""
 
 import math
 
@@ -11,8 +12,8 @@ import numpy as np
 import pytest
 
 import oracle
-from eg_inputs import (ogrid, box, mapped, straight_nodes, reorient, wall_bumps, Mesh,
-                       TAG_FARFIELD, TAG_EXACT)
+from eg_inputs import (ogrid, box, cubed_sphere_shell, mapped, straight_nodes, reorient, wall_bumps, Mesh,
+                       node_of_vertex, TAG_FARFIELD, TAG_EXACT)
 from tests.test_oracle_norm_ties_orientation import truncation
 from tests.test_oracle_residual import perturbed
 
@@ -163,3 +164,120 @@ def test_curved_mesh_checks():
     bad[3, 7, 1] += 1e-6  # middle node of face 3 (eta = +1), shared with element 4
     with pytest.raises(ValueError, match="non-conforming curved"):
         oracle.Oracle(Mesh(2, m.xyz, m.elem_vert, m.bface_tag, "", bad), 1)
+
+
+# ------------------------------------------------------------------ 3D hexes
+@pytest.mark.parametrize("p", [1, 2])
+def test_straight_nodes_reduce_to_trilinear(p):
+    """27 nodes at the trilinear positions describe the same hex map."""
+    m = reorient(wall_bumps(cubed_sphere_shell(2, 2, r_in=0.5, r_out=1.5), [0.05], [[0.3, 0.5, 0.8]], 0.5,
+                            r_out=1.5), 3)
+    O1 = oracle.Oracle(m, p, alpha_deg=2.0)
+    O2 = oracle.Oracle(Mesh(3, m.xyz, m.elem_vert, m.bface_tag, "", straight_nodes(m)), p, alpha_deg=2.0)
+    for a, b in zip(O1.geometry()[:3], O2.geometry()[:3]):
+        assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(a))
+    u = perturbed(O1, p, 5)
+    r1, r2 = O1.residual(p, u), O2.residual(p, u)
+    assert np.max(np.abs(r1 - r2)) <= 1e-13 * np.max(np.abs(r1))
+    b1, b2 = O1.jacobian_blocks(p, u), O2.jacobian_blocks(p, u)
+    assert np.max(np.abs(b1 - b2)) <= 1e-13 * np.max(np.abs(b1))
+
+
+# a triquadratic map of the unit cube (each component of degree <= 2 in every
+# variable) and its Jacobian matrix
+_TQ = (0.2, 0.15, 0.25, 0.1, -0.12, 0.08)
+
+
+def _triquad(x):
+    s, t, u = x[:, 0], x[:, 1], x[:, 2]
+    a, b, c, d, e, f = _TQ
+    return np.stack([s + a * t * t + d * t * u, t + b * u * u + e * s * u, u + c * s * s + f * s * t], axis=1)
+
+
+def _triquad_det(s, t, u):
+    a, b, c, d, e, f = _TQ
+    J = np.array([[1.0, 2 * a * t + d * u, d * t],
+                  [e * u, 1.0, 2 * b * u + e * s],
+                  [2 * c * s + f * t, f * s, 1.0]])
+    return np.linalg.det(J)
+
+
+def test_exact_volume_of_triquadratic_map():
+    """Element volumes of a box under a global triquadratic map equal the
+    integral of its Jacobian determinant (a polynomial of degree <= 6 per
+    variable, integrated here with numpy's 8-point Gauss-Legendre rule per
+    axis); the straight-sided version of the same mesh misses them."""
+    base = box(3, 3, tag=TAG_FARFIELD)
+    m = mapped(base, _triquad)
+    vol, *_ = oracle.Oracle(m, 1).geometry()
+    gx, gw = np.polynomial.legendre.leggauss(8)
+    want = np.zeros(m.n_elem)
+    for e in range(m.n_elem):
+        lo, hi = base.xyz[base.elem_vert[e, 0]], base.xyz[base.elem_vert[e, 7]]
+        h = 0.5 * (hi - lo)
+        for i, wi in zip(gx, gw):
+            for j, wj in zip(gx, gw):
+                for k, wk in zip(gx, gw):
+                    pt = lo + h * (1.0 + np.array([i, j, k]))
+                    want[e] += wi * wj * wk * _triquad_det(*pt) * h.prod()
+    assert np.max(np.abs(vol - want)) <= 1e-14
+    vol_s, *_ = oracle.Oracle(Mesh(3, m.xyz, m.elem_vert, m.bface_tag), 1).geometry()
+    assert np.max(np.abs(vol_s - want)) > 1e-6
+
+
+def test_shell_volume_rate():
+    """Volume of a cubed-sphere shell against 4/3 pi (r_out^3 - r_in^3): rate
+    4 with curved hexes, 2 with straight ones (3.99 / 4.00 and 1.84 / 1.96
+    measured from 2 to 4 to 8 cells per panel side)."""
+    exact = 4.0 / 3.0 * math.pi * (1.0 - 0.5 ** 3)
+    for curved, lo, hi in ((True, 3.9, 4.1), (False, 1.8, 2.1)):
+        err = []
+        for n in (4, 8):
+            m = cubed_sphere_shell(n, 2, r_in=0.5, r_out=1.0, stretch=1.0001, curved=curved)
+            vol, *_ = oracle.Oracle(m, 1).geometry()
+            err.append(abs(vol.sum() - exact))
+        rate = math.log2(err[0] / err[1])
+        assert lo <= rate <= hi, (curved, err, rate)
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_freestream_preservation_curved_shell(p):
+    """The triquadratic map's cofactor metric terms satisfy the metric
+    identities exactly and the rule integrates them exactly: zero residual
+    of a uniform state."""
+    m = reorient(cubed_sphere_shell(2, 2, inner=TAG_FARFIELD, curved=True), 4)
+    O = oracle.Oracle(m, p, alpha_deg=3.0, beta_deg=-2.0)
+    r = O.residual(p, O.freestream(p))
+    vol, *_ = O.geometry()
+    assert np.max(np.abs(r) / (2.0 * np.sqrt(vol)[:, None, None])) < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_curved_shell_local_frames_and_truncation_rate(p):
+    """Random local frames leave the per-element residual norms unchanged,
+    and the truncation error of the projected manufactured state falls like
+    h^p on curved shells (1.08 and 1.97 measured from 4 to 8 cells)."""
+    m4 = cubed_sphere_shell(4, 4, r_in=0.5, r_out=1.0, inner=TAG_EXACT, outer=TAG_EXACT, curved=True)
+    t1, s1 = truncation(oracle.Oracle(m4, p), p)
+    t2, s2 = truncation(oracle.Oracle(reorient(m4, 8), p), p)
+    assert np.max(np.abs(t1 - t2)) <= 1e-12 * np.max(s1)
+    assert np.max(np.abs(s1 - s2)) <= 1e-12 * np.max(s1)
+    m8 = cubed_sphere_shell(8, 8, r_in=0.5, r_out=1.0, inner=TAG_EXACT, outer=TAG_EXACT, curved=True)
+    t8, _ = truncation(oracle.Oracle(m8, p), p)
+    rate = math.log2(math.sqrt(float(np.mean(t1 ** 2))) / math.sqrt(float(np.mean(t8 ** 2))))
+    assert rate >= p - 0.3, rate
+
+
+def test_curved_hex_checks():
+    m = cubed_sphere_shell(2, 1, curved=True)
+    bad = m.elem_geo.copy()
+    bad[5, node_of_vertex(3)[6], 2] += 1e-6
+    with pytest.raises(ValueError, match="corner"):
+        oracle.Oracle(Mesh(3, m.xyz, m.elem_vert, m.bface_tag, "", bad), 1)
+    bad = m.elem_geo.copy()
+    bad[5, 4 + 9 * 2, 1] += 1e-6  # centre node of face 5 (zeta = +1), an interior face
+    with pytest.raises(ValueError, match="non-conforming curved"):
+        oracle.Oracle(Mesh(3, m.xyz, m.elem_vert, m.bface_tag, "", bad), 1)
+    bad = m.elem_geo.copy()
+    bad[5, 13, 0] += 1e-6  # the centre node belongs to no face
+    oracle.Oracle(Mesh(3, m.xyz, m.elem_vert, m.bface_tag, "", bad), 1)
