@@ -38,7 +38,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def work_model(d, p, fp32_blocks=False):
+def work_model(d, p, fp32_blocks=False, nodes=None):
     """Algorithmic work per element of the three main kernel classes at order
     p, counted as the kernels execute it (no credit for avoided work):
     residual: the dense modal contractions (state at the volume points, the
@@ -47,9 +47,11 @@ def work_model(d, p, fp32_blocks=False):
     summed per volume point before the product with the basis (direction
     sums, volume products, face scalings, face products) plus the LU (2/3 n^3);
     prk_stage: bytes of one stage (factors, permutation, residual, base
-    state, new state)."""
+    state, new state).  ``nodes``: geometry nodes per element (default 9 per
+    quad, 8 per straight hex; 27 per curved hex)."""
     V, N, Q = d + 2, (p + 1) ** d, p + 2
-    QV, QF, NF, NC = Q ** d, Q ** (d - 1), 2 * d, 2 ** d
+    QV, QF, NF = Q ** d, Q ** (d - 1), 2 * d
+    NC = nodes if nodes else (9 if d == 2 else 8)
     n = V * N
     NT = N * (N + 1) // 2
     fb = 4 if fp32_blocks else 8
@@ -107,8 +109,8 @@ def stored_traffic(cls, p):
     return float(v) if v else None
 
 
-def roofline_entry(cls, p, ms, launches, ne, d, peaks=None):
-    w = work_model(d, p)[cls]
+def roofline_entry(cls, p, ms, launches, ne, d, peaks=None, nodes=None):
+    w = work_model(d, p, nodes=nodes)[cls]
     avg_s = ms / launches / 1e3
     if cls == "prk_stage":
         ach = w["bytes"] * ne / avg_s / 1e9
@@ -300,8 +302,8 @@ def c1_time_to_drop(P):
 
 
 def c5_adjoint(P, budget):
-    """The adjoint workload: cubed-sphere shell 6 x 12 x 12 x 16 = 13824 hexes
-    at p = 3 (320 x 320 blocks), Ma 0.3, s = 4, CFL_max = 100: the mixed-
+    """The adjoint workload: cubed-sphere shell 6 x 12 x 12 x 16 = 13824 curved
+    hexes at p = 3 (320 x 320 blocks), Ma 0.3, s = 4, CFL_max = 100: the mixed-
     precision solve from the free stream to the 1e-10 drop, then the adjoint
     solve (FP64) and dC_D/dtheta for theta = (Mach, two seeded 1e-3-scale
     Gaussian wall-bump amplitudes) from one paired residual and drag
@@ -310,13 +312,14 @@ def c5_adjoint(P, budget):
     import torch
     from eg_inputs import cubed_sphere_shell, wall_bumps, bump_centers
     from paper_1807_01151_amd.binding import _freestream_direction
-    mesh = cubed_sphere_shell(12, 16)
+    mesh = cubed_sphere_shell(12, 16, curved=True)  # on straight hexes this solve stalls
     centers = bump_centers(3, 2, seed=1807)
     sref = math.pi * 0.25  # the unit-diameter sphere's frontal area
     kw = dict(rk_stages=4, cfl_max=100.0, krylov_m=30)
     S = P.Solver(mesh, 3, mach=0.3, precision="mixed", **kw)
     S.autotune()
-    out = {"workload": "3D sphere shell 6x12x12x16 = 13824 hexes, DG p=3 (64 modes x 5 vars, 320 x 320 blocks), "
+    out = {"workload": "3D sphere shell 6x12x12x16 = 13824 curved hexes, DG p=3 (64 modes x 5 vars, "
+                       "320 x 320 blocks), "
                        "mixed-precision steady state, FP64 adjoint, theta = (Ma, 2 wall bumps)"}
     out["steady"], u = drop_run(S, 3, 100000, budget, "c5 mixed", chunk=500)
     if not out["steady"]["converged"]:
@@ -378,6 +381,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision measurements")
     ap.add_argument("--no-c2", action="store_true", help="skip the 2D cylinder workload")
     ap.add_argument("--c2-drop-budget", type=float, default=60.0, help="seconds of the c2 drop run (0: none)")
+    ap.add_argument("--no-c1", action="store_true", help="skip the c1 time-to-1e-10 runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-solve batched workload")
     ap.add_argument("--batch-budget", type=float, default=30.0, help="seconds cap of the batched convergence run")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured-peak kernels")
@@ -385,6 +389,8 @@ def main():
     ap.add_argument("--c5", action="store_true",
                     help="also run the 3D p = 3 adjoint workload (minutes: a converged 13824-hex p = 3 solve)")
     ap.add_argument("--c5-budget", type=float, default=600.0, help="seconds cap of the c5 steady solve")
+    ap.add_argument("--straight", action="store_true",
+                    help="straight-sided (trilinear) hexes instead of the curved (triquadratic) sphere shell")
     ap.add_argument("--calibrate", action="store_true",
                     help="end with a 256 MiB device-to-device copy (the reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -398,7 +404,9 @@ def main():
     from eg_inputs import cubed_sphere_shell
 
     torch.cuda.set_device(0)
-    mesh = cubed_sphere_shell(16, 24)
+    # the sphere grid is built from quadratic curved elements (Section 5.2)
+    mesh = cubed_sphere_shell(16, 24, curved=not args.straight)
+    nodes = 8 if args.straight else 27
     d, p = 3, 2
     dof = mesh.n_elem * 5 * 27
     kw = dict(rk_stages=4, cfl_max=100.0, krylov_m=30, mach=0.3, alpha_deg=0.0)
@@ -430,7 +438,7 @@ def main():
     cands = [(v[0], k) for k, v in prof.items() if k.split("@")[0] in ("residual", "jacobian_lu", "prk_stage")]
     ms_dom, key = max(cands)
     cls, lev = key.split("@")[0], int(key.split("@p")[1])
-    roof = roofline_entry(cls, lev, prof[key][0], prof[key][1], mesh.n_elem, d, peaks)
+    roof = roofline_entry(cls, lev, prof[key][0], prof[key][1], mesh.n_elem, d, peaks, nodes)
     roof["share_of_kernel_time"] = ms_dom / tot
     extras = {"kernels_ms_per_cycle": {k: round(v[0] / args.steps, 5) for k, v in prof.items()},
               "kernel_time_per_cycle_ms": round(tot / args.steps, 4),
@@ -438,7 +446,7 @@ def main():
     for c2 in ("residual", "jacobian_lu", "prk_stage"):
         k2 = f"{c2}@p{p}"
         if k2 in prof:
-            e2 = roofline_entry(c2, p, prof[k2][0], prof[k2][1], mesh.n_elem, d, peaks)
+            e2 = roofline_entry(c2, p, prof[k2][0], prof[k2][1], mesh.n_elem, d, peaks, nodes)
             extras[f"roofline_{c2}_p{p}"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in e2.items()}
     arn = prof.get("arnoldi@p0")
     if arn:
@@ -450,7 +458,9 @@ def main():
         byts = m * (K0 * 5 * (1 + 6) * 8 + K0 * 8 * 7) + sum(4 * (j + 1) * K0 * 8 for j in range(m))
         extras["arnoldi"] = {"ms_per_cycle": round(arn[0] / args.steps, 4), "model_bytes_per_exp1": byts,
                              "model_GBps": byts / (arn[0] / args.steps * 1e-3) / 1e9}
-    config = {"workload": "3D sphere, cubed-sphere hex shell 6x16x16x24 = 36864 hexes, DG p=2 (27 modes x 5 vars), "
+    config = {"workload": "3D sphere, cubed-sphere hex shell 6x16x16x24 = 36864 "
+                          + ("straight-sided (trilinear)" if args.straight else "quadratic curved (27-node)")
+                          + " hexes, DG p=2 (27 modes x 5 vars), "
                           "eMG V-cycle p2->p1->p0, 4-stage PRK, EXP1 Krylov m=30, CFL_max 100, Ma 0.3, "
                           "free-stream start, FP64",
               "n_elem": mesh.n_elem, "dof": dof, "p_max": p, "rk_stages": 4, "krylov_m": 30, "cfl_max": 100.0}
@@ -459,6 +469,21 @@ def main():
         config["fp64_drop"], u64 = drop_run(S, p, args.drop_cycles, args.drop_budget, "c3 fp64")
     del S
     torch.cuda.empty_cache()
+    if not args.straight:
+        # the same shell with straight-sided hexes: per-cycle cost of the
+        # triquadratic geometry (the trilinear kernel instantiations)
+        Ss = P.Solver(cubed_sphere_shell(16, 24), p, **kw)
+        Ss.autotune()
+        us = Ss.freestream(p)
+        Ss.solve_steady(us, drop_tol=0.0, max_cycles=args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Ss.solve_steady(us, drop_tol=0.0, max_cycles=args.steps, resume=True)
+        torch.cuda.synchronize()
+        extras["straight_sided_hexes_ms_per_cycle"] = round((time.perf_counter() - t0) / args.steps * 1e3, 4)
+        log(f"[bench] straight-sided hexes: {extras['straight_sided_hexes_ms_per_cycle']} ms/cycle")
+        del Ss, us
+        torch.cuda.empty_cache()
     if not args.no_mixed:
         Sm = P.Solver(mesh, p, precision="mixed", **kw)
         Sm.autotune()
@@ -487,7 +512,8 @@ def main():
     del u64
     if not args.no_c2:
         extras["c2"] = c2_measurements(P, args.steps, args.warmup, args.c2_drop_budget)
-        extras["c1_time_to_1e-10"] = c1_time_to_drop(P)
+        if not args.no_c1:
+            extras["c1_time_to_1e-10"] = c1_time_to_drop(P)
     if not args.no_batched:
         extras["batched"] = batched_measurements(P, 10, args.batch_budget)
     if args.c5:

@@ -1,5 +1,5 @@
 """Parity at the full size of the 3D sphere workload (cubed-sphere hex shell
-6 x 16 x 16 x 24 = 36864 hexes, p = 2: 27 modes x 5 variables, 135 x 135
+6 x 16 x 16 x 24 = 36864 quadratic curved hexes, p = 2: 27 modes x 5 variables, 135 x 135
 element blocks, Ma 0.3) in FP64 and in mixed precision: the residual and the
 PRK step on every element, and the first V-cycle from the free stream
 applied to the oracle's state."""
@@ -13,7 +13,7 @@ from tests.gpu_util import perturbed, to_dev, to_host, rel_err
 
 pytestmark = pytest.mark.gpu
 
-MESH = cubed_sphere_shell(16, 24)
+MESH = cubed_sphere_shell(16, 24, curved=True)  # the sphere grid is curved (Section 5.2)
 KW = dict(rk_stages=4, cfl_max=100.0, krylov_m=30)  # the workload's smoother
 
 
