@@ -1066,7 +1066,7 @@ eg_status init_common(eg_handle* h, const eg_mesh* mesh, const eg_params* prm, v
   AL(h->part2, (size_t)h->nblk_arn * (h->m + 2));
   AL(h->info, 2 * nseg);
   AL(h->arn_st, 2 * nseg);
-  AL(h->arn_wn0, nseg);
+  AL(h->arn_wn0, 2 * nseg);  // ||A v_j|| in two slots per solve
   AL(h->arn_W, 2 * K0);
   AL(h->H2, (size_t)nseg * (h->m + 1) * h->m);
   AL(h->y, (size_t)nseg * (h->m + 1));

@@ -1779,17 +1779,24 @@ __device__ __forceinline__ SegPos seg_pos(const ArnSeg& S, int K) {
 // touches), so every global load of a kernel is issued before the first
 // wait.  The product w = A v_j lives in scratch vector W[j % 2]; v_{j+1}
 // goes to Vb[j + 1].  Kernels:
-//   a  (j = 0 only): W0 = A v_0, partials of <W0, v_0> and ||W0||^2
+//   a  (j = 0 only): W0 = A v_0, partials of <W0, v_0>, ||W0||^2, ||v_0||^2
 //   b  (step j): h1 = sum of partials, W -= V_j h1 (first Gram-Schmidt
-//      pass), partials of the second pass
+//      pass), partials of the second pass; first it normalises v_j by the
+//      norm the previous kernel measured (below)
 //   ca (step j, then j + 1): h2 and hn = sqrt(||W||^2 - ||h2||^2) finish
 //      column j of H; v_{j+1} = (W - V_j h2)/hn; and, fused, the next
 //      product A v_{j+1} = (A W - V_{j+1} (H~_j h2)) / hn (Arnoldi relation
 //      A V_j = V_{j+1} H~_j), which needs W only at neighbour rows, all final
-//      since the previous kernel; partials of the next first pass.  On the
-//      last step only v_{j+1} is formed.
-// Happy breakdown (hn <= 1e-12 ||A v_j||) sets st[0], so every later kernel
-// returns; info[0] = Krylov dimension used, info[1] = beta.
+//      since the previous kernel; partials of the next first pass and of
+//      ||v_{j+1}||^2.  On the last step only v_{j+1} is formed.
+// hn from Pythagoras resolves the true norm only down to ~1e-8 ||W||, so
+// the next b kernel measures s = ||v_{j+1}|| of the vector actually formed
+// and rescales: v_{j+1} /= s, A v_{j+1} /= s, h_{j+2,j+1} = s hn (exact:
+// the Arnoldi relation holds for any scaling of v_{j+1}), and the breakdown
+// test is repeated on s hn.  Happy breakdown (h <= 1e-12 ||A v_j||) sets
+// st[0], so every later kernel returns; info[0] = Krylov dimension used,
+// info[1] = beta.  ||A v_j|| is kept in two slots per solve (step j writes
+// slot j % 2), so no kernel reads a slot one of its own blocks writes.
 __global__ __launch_bounds__(256) void k_arn_beta(int K, const double* __restrict__ b, double* __restrict__ part,
                                                   int P, int* __restrict__ st, ArnSeg S) {
   __shared__ double s_wave[4 * 64];
@@ -1832,15 +1839,16 @@ __global__ __launch_bounds__(256) void k_arn_a(int K, const int* __restrict__ nb
   const double v0 = act ? Vb[k] : 0.0;
   const double w = act ? spmv_row<V, NF>(k, nbr, Ad, Ao, Vb) : 0.0;
   if (act) W[k] = w;
-  block_sums<2>(2, [&](int i) { return i == 0 ? w * v0 : w * w; }, s_wave, s_h);
-  if (threadIdx.x < 2) part[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
+  block_sums<3>(3, [&](int i) { return i == 0 ? w * v0 : i == 1 ? w * w : v0 * v0; }, s_wave, s_h);
+  if (threadIdx.x < 3) part[blockIdx.x * P + threadIdx.x] = s_h[threadIdx.x];
 }
 
 template <int NVM>
-__global__ __launch_bounds__(256) void k_arn_b(int K, int m, int j, const double* __restrict__ Vb,
+__global__ __launch_bounds__(256) void k_arn_b(int K, int m, int j, double* __restrict__ Vb,
                                                double* __restrict__ W, const double* __restrict__ part1,
                                                double* __restrict__ part2, int P, double* __restrict__ H,
-                                               double* __restrict__ wn0, const int* __restrict__ st, ArnSeg S) {
+                                               double* __restrict__ H2, double* __restrict__ wn0,
+                                               double* __restrict__ info, int* __restrict__ st, ArnSeg S) {
   const SegPos sp = seg_pos(S, K);
   if (st[2 * sp.sg]) return;
   __shared__ double s_wave[4 * 64];
@@ -1848,17 +1856,46 @@ __global__ __launch_bounds__(256) void k_arn_b(int K, int m, int j, const double
   __shared__ double s_g[64];
   __shared__ double s_tmp[256];
   H += (size_t)sp.sg * (m + 1) * m;
-  wn0 += sp.sg;
+  H2 += (size_t)sp.sg * (m + 1) * m;
+  wn0 += 2 * sp.sg;
   const int k = sp.k;
   const bool act = k < sp.kend;
   const int kc = act ? k : sp.kend - 1;  // clamped row: loads need no divergent branch
   double vr[NVM];
 #pragma unroll
   for (int i = 0; i < NVM; ++i) vr[i] = (i <= j) ? Vb[(size_t)i * K + kc] : 0.0;
-  const double w = act ? W[kc] : 0.0;
+  double w = act ? W[kc] : 0.0;
 #pragma unroll
   for (int i = 0; i < NVM; ++i) vr[i] = act ? vr[i] : 0.0;
-  grid_partials_sum(part1, sp.b0, sp.b1, P, j + 2, s_tmp, s_g);
+  // h_{j,j-1} from the previous step (H is not written by this kernel, so
+  // every block reads the same value)
+  const double hprev = j > 0 ? H[j * m + j - 1] : 0.0;
+  const double wprev = wn0[(j + 1) & 1];  // ||A v_{j-1}||, written by the previous step
+  grid_partials_sum(part1, sp.b0, sp.b1, P, j + 3, s_tmp, s_g);
+  // normalise v_j by its measured norm s (every block computes the same s);
+  // the subdiagonal's correction s hn - hn goes to H2 (the Hessenberg
+  // matrix is H + H2)
+  const double sn = sqrt(s_g[j + 2]);
+  if (j > 0 && blockIdx.x == sp.b0 && threadIdx.x == 0) H2[j * m + j - 1] = hprev * sn - hprev;
+  if (j > 0 && !(hprev * sn > 1e-12 * wprev)) {
+    // the true subdiagonal is at the breakdown level: dimension j
+    if (blockIdx.x == sp.b0 && threadIdx.x == 0) {
+      st[2 * sp.sg] = 1;
+      info[2 * sp.sg] = (double)j;
+    }
+    return;
+  }
+  const double isc = 1.0 / sn;
+  __syncthreads();  // every thread has read s_g[j + 2] before it is rescaled
+  if (threadIdx.x <= j + 1) s_g[threadIdx.x] *= (threadIdx.x < j) ? isc : isc * isc;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NVM; ++i)
+    if (i == j) {
+      vr[i] *= isc;
+      if (act) Vb[(size_t)i * K + k] = vr[i];
+    }
+  w *= isc;
   double a0 = 0.0, a1 = 0.0;
 #pragma unroll
   for (int i = 0; i < NVM; i += 2) {
@@ -1868,7 +1905,7 @@ __global__ __launch_bounds__(256) void k_arn_b(int K, int m, int j, const double
   const double w1 = w - (a0 + a1);
   if (act) W[k] = w1;
   if (blockIdx.x == sp.b0 && threadIdx.x <= j) H[threadIdx.x * m + j] = s_g[threadIdx.x];
-  if (blockIdx.x == sp.b0 && threadIdx.x == 0) wn0[0] = sqrt(s_g[j + 1]);
+  if (blockIdx.x == sp.b0 && threadIdx.x == 0) wn0[j & 1] = sqrt(s_g[j + 1]);
   constexpr int NP = NVM > 32 ? 64 : NVM > 16 ? 32 : NVM;  // a power of two
   double pp[NP];
 #pragma unroll
@@ -1893,7 +1930,7 @@ __global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* 
   if (st[2 * sp.sg]) return;
   H += (size_t)sp.sg * (m + 1) * m;
   H2 += (size_t)sp.sg * (m + 1) * m;
-  wn0 += sp.sg;
+  wn0 += 2 * sp.sg;
   info += 2 * sp.sg;
   st += 2 * sp.sg;
   __shared__ double s_wave[4 * 64];
@@ -1926,7 +1963,7 @@ __global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* 
       const int kk = t / (j + 1), i = t % (j + 1);
       const bool in = t < nH && kk <= i + 1;
       h1v[u] = in ? H[kk * m + i] : 0.0;
-      h2v[u] = (in && i < j && kk <= i) ? H2[kk * m + i] : 0.0;
+      h2v[u] = (in && i < j && kk <= i + 1) ? H2[kk * m + i] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < IT; ++u) {
@@ -1940,7 +1977,7 @@ __global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* 
   double h2sq = 0.0;
   for (int i = 0; i <= j; ++i) h2sq += s_h[i] * s_h[i];
   const double hn = sqrt(fmax(s_h[j + 1] - h2sq, 0.0));
-  const bool brk = !(hn > 1e-12 * wn0[0]);
+  const bool brk = !(hn > 1e-12 * wn0[j & 1]);
   if (NEXT && !brk) {
     // c = H~_j h2: columns < j split over the four waves (s_tmp is free
     // again), column j from this kernel's own values
@@ -1979,7 +2016,8 @@ __global__ __launch_bounds__(256) void k_arn_ca(int K, int m, int j, const int* 
 #pragma unroll
     for (int i = 0; i < NP; ++i) pp[i] = (i <= j) ? wn * vr[i < NVM ? i : 0] : (i == j + 1 ? wn * v : 0.0);
     block_sums_rs<NP>(pp, wn * wn, j + 2, s_wave, s_p);
-    if (threadIdx.x < j + 3) part1[blockIdx.x * P + threadIdx.x] = s_p[threadIdx.x];
+    block_sums<1>(1, [&](int) { return v * v; }, s_wave, s_p + j + 3);
+    if (threadIdx.x < j + 4) part1[blockIdx.x * P + threadIdx.x] = s_p[threadIdx.x];
   }
 }
 
@@ -2113,7 +2151,7 @@ __global__ __launch_bounds__(256) void k_phi1(const double* __restrict__ H, cons
     const int i = it / n, j = it % n;
     double v = 0.0;
     // only the Hessenberg part (i <= j + 1) is written by the Arnoldi kernel
-    if (i < mu && j < mu && i <= j + 1) v = H[i * mstride + j] + (i <= j ? H2[i * mstride + j] : 0.0);
+    if (i < mu && j < mu && i <= j + 1) v = H[i * mstride + j] + H2[i * mstride + j];
     if (i == 0 && j == mu) v = 1.0;
     B[it] = v;
   }
@@ -3214,10 +3252,11 @@ int arnoldi_blocks(int K) { return (K + 255) / 256; }
 static int arn_nvm(int need) { return need <= 32 ? 8 * ((need + 7) / 8) : 48; }
 
 template <int NVM>
-static void launch_arn_b(int nblk, hipStream_t s, int K, int m, int j, const double* Vb, double* W,
-                         const double* part1, double* part2, int P, double* H, double* wn0, const int* st,
-                         ArnSeg S) {
-  hipLaunchKernelGGL(k_arn_b<NVM>, dim3(nblk), dim3(256), 0, s, K, m, j, Vb, W, part1, part2, P, H, wn0, st, S);
+static void launch_arn_b(int nblk, hipStream_t s, int K, int m, int j, double* Vb, double* W,
+                         const double* part1, double* part2, int P, double* H, double* H2, double* wn0,
+                         double* info, int* st, ArnSeg S) {
+  hipLaunchKernelGGL(k_arn_b<NVM>, dim3(nblk), dim3(256), 0, s, K, m, j, Vb, W, part1, part2, P, H, H2, wn0, info,
+                     st, S);
 }
 
 template <int V, int NF, bool NEXT, int NVM>
@@ -3261,11 +3300,11 @@ hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, c
     double* Wc = W[j & 1];
     double* Wn = W[(j + 1) & 1];
     switch (arn_nvm(j + 1)) {
-      case 8: launch_arn_b<8>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
-      case 16: launch_arn_b<16>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
-      case 24: launch_arn_b<24>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
-      case 32: launch_arn_b<32>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
-      default: launch_arn_b<48>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, wn0, st, S); break;
+      case 8: launch_arn_b<8>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, H2, wn0, info, st, S); break;
+      case 16: launch_arn_b<16>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, H2, wn0, info, st, S); break;
+      case 24: launch_arn_b<24>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, H2, wn0, info, st, S); break;
+      case 32: launch_arn_b<32>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, H2, wn0, info, st, S); break;
+      default: launch_arn_b<48>(nblk, stream, K, m, j, Vb, Wc, part1, part2, P, H, H2, wn0, info, st, S); break;
     }
     const bool next = (j + 1 < m);
     const int nvm = arn_nvm(next ? j + 2 : j + 1);

@@ -108,6 +108,7 @@ hipError_t launch_norm(const DevMesh& M, int N, const double* rt, double* part, 
 hipError_t launch_p0_setup(const DevMesh& M, const double* ut0, const double* ft0, int pmax, double cfl, int scale,
                            double* u0, double* b, double* Ad, double* Ao, double* dt, hipStream_t st);
 int arnoldi_blocks(int K);
+// wn0: two slots per solve (the norm of A v_j of the last two steps).
 hipError_t launch_arnoldi(const DevMesh& M, int m, int nblk, const double* Ad, const double* Ao, const double* b,
                           double* Vb, double* H, double* part1, double* part2, double* info, int* st, double* wn0,
                           double* W2, double* H2, hipStream_t stream);

@@ -40,6 +40,22 @@ def test_c2_prk_full(pair):
     assert rel_err(to_host(ud) - u, out_o - u) < 1e-11
 
 
+def test_c2_exp1_full(pair):
+    """One EXP1 step (m = 30) on all 8192 elements at p = 0: Krylov
+    dimension and update equal the oracle's (modified Gram-Schmidt twice,
+    norms formed directly) to 1e-10 of the update."""
+    O, S = pair
+    u = perturbed(O, 0, 902, amp=0.01)
+    f = 1e-4 * np.random.default_rng(903).standard_normal(u.shape)
+    out_o, mu_o, _ = O.exp1(30, 10.0, u, f)
+    ud = to_dev(u)
+    _, mu_g = S.exp1_step(10.0, ud, to_dev(f))
+    e = rel_err(to_host(ud) - u, out_o - u)
+    print(f"c2 EXP1: mu {mu_g} (oracle {mu_o}), update error {e:.2e}", flush=True)
+    assert mu_g == mu_o
+    assert e < 1e-10
+
+
 def test_c2_cycle_map_and_history(pair):
     """From the free stream: the free-running histories agree to 1e-12 r_1
     over the first cycles, and the GPU cycle applied to the oracle's state

@@ -169,6 +169,26 @@ def test_exp1_happy_breakdown_parity():
     assert rel_err(to_host(ud) - u, out_o - u) < 1e-9
 
 
+@pytest.mark.parametrize("m", [33, 34, 35])
+def test_exp1_near_breakdown_parity(m):
+    """One to three Arnoldi steps short of exhausting K_0 = 36: the last
+    subdiagonal entries are small, where a norm formed by Pythagoras from the
+    Gram-Schmidt coefficients loses its digits; the GPU measures the norm of
+    each new basis vector and rescales, and the update matches the oracle's
+    (modified Gram-Schmidt twice, norms formed directly)."""
+    mesh = ogrid(3, 3, inner=TAG_FARFIELD)
+    O = oracle.Oracle(mesh, 1)
+    S = _solver(mesh, 1, 0.0, krylov_m=m)
+    u = perturbed(O, 0, 660)
+    out_o, mu_o, _ = O.exp1(m, 5.0, u)
+    ud = to_dev(u)
+    _, mu_g = S.exp1_step(5.0, ud)
+    print(f"m = {m}: mu oracle {mu_o}, GPU {mu_g}, update error {rel_err(to_host(ud) - u, out_o - u):.2e}",
+          flush=True)
+    assert mu_g == mu_o
+    assert rel_err(to_host(ud) - u, out_o - u) < 1e-9
+
+
 @pytest.mark.parametrize("name,mesh,p,alpha,flux", CASES[:5] + CASES[6:10] + CASES[12:13] + CASES[14:],
                          ids=IDS[:5] + IDS[6:10] + IDS[12:13] + IDS[14:])
 def test_vcycle_parity(name, mesh, p, alpha, flux):
