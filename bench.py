@@ -330,7 +330,7 @@ def c5_adjoint(P, budget):
     # in chunks of 250 cycles from the previous lambda, reporting progress;
     # the drop is relative to the first chunk's initial adjoint residual
     lam, r0, done, last, st = None, None, 0, None, 5
-    while st == 5 and done < 3000:
+    while st == 5 and done < 4000:
         tol = 1e-10 if r0 is None else 1e-10 * r0 / last
         lam, hist, st = S.adjoint_solve(u, g, lam=lam, drop_tol=min(tol, 1.0), max_cycles=250, raise_on_fail=False)
         r0 = hist[0] if r0 is None else r0
