@@ -328,7 +328,7 @@ eg_status eg_adjoint_apply(eg_handle* h, int p, const double* u_dev, const doubl
  * adjoint problem with the transposed p = 0 operator.  lam_dev: initial
  * guess in, solution out.  Stops when the 2-norm of the adjoint residual
  * has dropped by drop_tol; hist_host[0..*n_cycles_host] as for
- * eg_solve_steady.  Orders with a transposed block solve: 2D p <= 3 and 3D
+ * eg_solve_steady.  Orders with a transposed block solve: 2D p <= 4 and 3D
  * p <= 3 (else EG_ERR_UNSUPPORTED).
  * Runs in FP64 on every handle.  Synchronises. */
 eg_status eg_adjoint_solve(eg_handle* h, const double* u_dev, const double* g_dev, double* lam_dev, double drop_tol,

@@ -764,7 +764,7 @@ eg_status adj_alloc(eg_handle* h) {
 eg_status adj_supported(eg_handle* h) {
   for (int p = 1; p <= h->pmax; ++p)
     if (!eg::prk_tr_supported(NB(h, p)))
-      return fail(h, EG_ERR_UNSUPPORTED, "adjoint: no transposed block solve for this order (2D p <= 3, 3D p <= 3)");
+      return fail(h, EG_ERR_UNSUPPORTED, "adjoint: no transposed block solve for this order (2D p <= 4, 3D p <= 3)");
   return EG_OK;
 }
 

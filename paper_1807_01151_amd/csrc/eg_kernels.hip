@@ -3568,7 +3568,9 @@ hipError_t launch_drag(const DevMesh& M, const TabData& td, int p, const double*
 // state tried, with the transposed kernel checked by a CPU emulation of its
 // loops and (dR/du)^T w equal to the oracle's at every level; the cause is
 // not established.
-bool prk_tr_supported(int n) { return n == 16 || n == 36 || n == 64 || n == 40 || n == 135 || n == 320; }
+bool prk_tr_supported(int n) {
+  return n == 16 || n == 36 || n == 64 || n == 100 || n == 40 || n == 135 || n == 320;
+}
 
 hipError_t launch_prk_stage_tr(const DevMesh& M, int n, const double* F, const int* perm, const double* rt,
                                const double* un, double* ut, double beta, hipStream_t st) {
@@ -3577,6 +3579,7 @@ hipError_t launch_prk_stage_tr(const DevMesh& M, int n, const double* F, const i
     case 16: hipLaunchKernelGGL((k_prk_stage_tr<16>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
     case 36: hipLaunchKernelGGL((k_prk_stage_tr<36>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
     case 40: hipLaunchKernelGGL((k_prk_stage_tr<40>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
+    case 100: hipLaunchKernelGGL((k_prk_stage_trc<100>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
     case 135: hipLaunchKernelGGL((k_prk_stage_trc<135>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
     case 320: hipLaunchKernelGGL((k_prk_stage_trc<320>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
     case 64: hipLaunchKernelGGL((k_prk_stage_tr<64>), dim3(grid), dim3(256), 0, st, F, perm, rt, un, ut, beta, M.ne); break;
