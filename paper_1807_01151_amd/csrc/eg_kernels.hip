@@ -2906,8 +2906,14 @@ hipError_t residual_t(const DevMesh& M, const TabData& td, const double* ut, con
   Tab<D, P, R> t;
   fill_tab(t, td);
   if constexpr (D == 3) {
-    // curved hexes: one tile (the default) of the triquadratic instantiation
-    if (M.NC == 27) return residual_launch<D, P, res_tile_cand<D, P, R, 1>(), R, true>(M, t, ut, fadd, rt, fas, st);
+    // curved hexes: the triquadratic instantiations, same tile candidates
+    if (M.NC == 27) {
+      switch (choice) {
+        case 0: return residual_launch<D, P, res_tile_cand<D, P, R, 0>(), R, true>(M, t, ut, fadd, rt, fas, st);
+        case 2: return residual_launch<D, P, res_tile_cand<D, P, R, 2>(), R, true>(M, t, ut, fadd, rt, fas, st);
+        default: return residual_launch<D, P, res_tile_cand<D, P, R, 1>(), R, true>(M, t, ut, fadd, rt, fas, st);
+      }
+    }
   }
   switch (choice) {
     case 0: return residual_launch<D, P, res_tile_cand<D, P, R, 0>(), R>(M, t, ut, fadd, rt, fas, st);
