@@ -29,3 +29,4 @@ from .meshes import (  # noqa: F401
     node_of_vertex,
 )
 from .draws import batch_draws, bump_centers, seeded_array  # noqa: F401
+from .polymesh import PolyMesh, box_poly, sphere_poly, from_hexes, TET, PRISM, TET_FACES, PRISM_FACES  # noqa: F401

@@ -89,6 +89,27 @@ def lib():
         L.orc_mms_forcing.argtypes = [C.c_void_p, C.c_int, _d]
         L.orc_mms_error.restype = C.c_double
         L.orc_mms_error.argtypes = [C.c_void_p, C.c_int, _d]
+        L.porc_create.restype = C.c_void_p
+        L.porc_create.argtypes = [C.c_int, _d, C.c_int, C.POINTER(C.c_int8), _i32, C.POINTER(C.c_int8), C.c_int,
+                                  C.c_double, C.c_double, C.c_double, C.c_double, C.c_char_p, C.c_int]
+        L.porc_free.argtypes = [C.c_void_p]
+        L.porc_set_flux.argtypes = [C.c_void_p, C.c_int]
+        L.porc_nmodes.restype = C.c_int
+        L.porc_nmodes.argtypes = [C.c_int]
+        L.porc_nfaces.restype = C.c_int
+        L.porc_nfaces.argtypes = [C.c_void_p]
+        L.porc_monomials.argtypes = [C.c_int, _i32]
+        L.porc_geometry.argtypes = [C.c_void_p, _d, _d, _d]
+        L.porc_basis_S.argtypes = [C.c_void_p, _d]
+        L.porc_vol_rule.argtypes = [C.c_void_p, C.c_int, C.c_int, _d, _d]
+        L.porc_faces.argtypes = [C.c_void_p, _i32, _i32, _d]
+        L.porc_face_rule.argtypes = [C.c_void_p, C.c_int, C.c_int, _d, _d, _d]
+        L.porc_psi.argtypes = [C.c_void_p, C.c_int, C.c_int, _d, _d, _d]
+        L.porc_freestream.argtypes = [C.c_void_p, C.c_int, _d]
+        L.porc_residual.argtypes = [C.c_void_p, C.c_int, _d, _d]
+        L.porc_residual_complex.argtypes = [C.c_void_p, C.c_int, _d, _d, _d, _d]
+        L.porc_mms_project.argtypes = [C.c_void_p, C.c_int, _d]
+        L.porc_mms_forcing.argtypes = [C.c_void_p, C.c_int, _d]
         _lib = L
     return _lib
 
@@ -384,3 +405,118 @@ class Oracle:
 
     def mms_error(self, p, u):
         return lib().orc_mms_error(self._h, p, _p(np.ascontiguousarray(u)))
+
+
+def poly_nmodes(p: int) -> int:
+    """N = (p+1)(p+2)(p+3)/6 Cartesian monomials of total degree <= p."""
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def poly_monomials(p: int) -> np.ndarray:
+    """int32[N, 3]: exponents (a_x, a_y, a_z) of chi_j in the oracle's order."""
+    a = np.zeros((poly_nmodes(p), 3), dtype=np.int32)
+    lib().porc_monomials(p, _p(a))
+    return a
+
+
+class PolyOracle:
+    """Tetrahedra and prisms with the Cartesian P_p basis orthonormalised by
+    MGS (Section 3.2).  Level-p vectors are float64[E, 5, N_p]."""
+
+    def __init__(self, mesh, pmax: int, gamma: float = 1.4, mach: float = 0.3,
+                 alpha_deg: float = 0.0, beta_deg: float = 0.0, flux: str = "rusanov"):
+        m = mesh.contiguous()
+        self.mesh = m
+        self.V = 5
+        self.ne = m.n_elem
+        self.pmax = pmax
+        self.gamma = gamma
+        err = C.create_string_buffer(256)
+        h = lib().porc_create(m.n_vert, _p(m.xyz), m.n_elem, _p(m.elem_type), _p(m.elem_vert), _p(m.bface_tag),
+                              pmax, gamma, mach, alpha_deg, beta_deg, err, 256)
+        if not h:
+            raise ValueError("oracle mesh set-up failed: " + err.value.decode())
+        self._h = C.c_void_p(h)
+        if flux not in ("rusanov", "roe"):
+            raise ValueError("flux must be 'rusanov' or 'roe'")
+        self.flux = flux
+        lib().porc_set_flux(self._h, 1 if flux == "roe" else 0)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.porc_free(h)
+            self._h = None
+
+    def N(self, p: int) -> int:
+        return poly_nmodes(p)
+
+    def zeros(self, p: int) -> np.ndarray:
+        return np.zeros((self.ne, 5, self.N(p)))
+
+    def geometry(self):
+        """(volume [E], centroid xc [E, 3], half extents L [E, 3])."""
+        vol = np.zeros(self.ne)
+        xc, L = np.zeros((self.ne, 3)), np.zeros((self.ne, 3))
+        lib().porc_geometry(self._h, _p(vol), _p(xc), _p(L))
+        return vol, xc, L
+
+    def basis_S(self) -> np.ndarray:
+        n = self.N(self.pmax)
+        S = np.zeros((self.ne, n, n))
+        lib().porc_basis_S(self._h, _p(S))
+        return S
+
+    def vol_rule(self, e: int, Q: int):
+        X, W = np.zeros((Q ** 3, 3)), np.zeros(Q ** 3)
+        lib().porc_vol_rule(self._h, e, Q, _p(X), _p(W))
+        return X, W
+
+    def faces(self):
+        nf = lib().porc_nfaces(self._h)
+        info = np.zeros((nf, 6), dtype=np.int32)
+        cv = np.zeros((nf, 4), dtype=np.int32)
+        sgn = np.zeros(nf)
+        lib().porc_faces(self._h, _p(info), _p(cv), _p(sgn))
+        return info, cv, sgn
+
+    def face_rule(self, f: int, Q: int):
+        X, W, Nh = np.zeros((Q * Q, 3)), np.zeros(Q * Q), np.zeros((Q * Q, 3))
+        lib().porc_face_rule(self._h, f, Q, _p(X), _p(W), _p(Nh))
+        return X, W, Nh
+
+    def psi(self, e: int, p: int, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        n = self.N(p)
+        psi, g = np.zeros(n), np.zeros((n, 3))
+        lib().porc_psi(self._h, e, n, _p(x), _p(psi), _p(g))
+        return psi, g
+
+    def freestream(self, p: int) -> np.ndarray:
+        u = self.zeros(p)
+        lib().porc_freestream(self._h, p, _p(u))
+        return u
+
+    def residual(self, p: int, u: np.ndarray) -> np.ndarray:
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        assert u.shape == (self.ne, 5, self.N(p))
+        r = np.zeros_like(u)
+        lib().porc_residual(self._h, p, _p(u), _p(r))
+        return r
+
+    def residual_complex(self, p: int, u: np.ndarray) -> np.ndarray:
+        ure = np.ascontiguousarray(u.real, dtype=np.float64)
+        uim = np.ascontiguousarray(u.imag, dtype=np.float64)
+        rre, rim = np.zeros_like(ure), np.zeros_like(ure)
+        lib().porc_residual_complex(self._h, p, _p(ure), _p(uim), _p(rre), _p(rim))
+        return rre + 1j * rim
+
+    def mms_project(self, p):
+        u = self.zeros(p)
+        lib().porc_mms_project(self._h, p, _p(u))
+        return u
+
+    def mms_forcing(self, p):
+        f = self.zeros(p)
+        lib().porc_mms_forcing(self._h, p, _p(f))
+        return f

@@ -1694,3 +1694,576 @@ double orc_mms_error(void* h, int p, const double* u) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Unstructured tetrahedra and prisms with the paper's basis (Section 3.2):
+// normalised Cartesian monomials chi_j(x) = prod_k ((x_k - xc_k) / L_k)^a_k
+// of total degree <= p (eq. (basis2)), orthonormalised per element by modified
+// Gram-Schmidt in the element's L2 inner product (eq. (basis)).  xc is the
+// element centroid (the integral of x over |E|), L_k half the element's extent
+// along axis k.  Straight-sided elements; the residual follows eq. (euler3)
+// exactly as for the tensor elements above.
+//
+// Readings (the paper is silent on them):
+//  * Monomial order: total degree, then a_x descending, then a_y descending,
+//    so the level-(p-1) space is a leading slice and MGS makes the basis
+//    hierarchical.
+//  * Quadrature: collapsed (Duffy) products of the (p+2)-point Gauss-Legendre
+//    rule on [0, 1].  Tetrahedron: barycentric l1 = t1 (1-t2)(1-t3),
+//    l2 = t2 (1-t3), l3 = t3, weight factor (1-t2)(1-t3)^2; prism: the
+//    triangle l1 = t1 (1-t2), l2 = t2 times zeta = t3, weight (1-t2) |det|;
+//    triangular face: l1 = t1 (1-t2), l2 = t2 over its vertices sorted by
+//    global id; quadrilateral face: tensor rule on the bilinear patch of its
+//    corners (cyclic, starting at the lowest id, towards the lower-id
+//    neighbour).  The volume rule is exact to degree 2p+1 on tetrahedra.
+//  * MGS, xc, and the basis of every level use the volume rule of p_max.
+// ===========================================================================
+
+namespace {
+
+struct PFace {
+  int eL, fL, eR, fR, tag, nv;
+  int cv[4];   // canonical vertex ids
+  double sgn;  // +1 if the canonical normal points out of eL, else -1
+};
+
+struct Poly {
+  Oracle base;  // parameters, free stream, flux selection (d = 3, V = 5)
+  int nv = 0, ne = 0, pmax = 0, Nmax = 0;
+  std::vector<double> xyz;
+  std::vector<int> typ, ev;          // [E], [E][6]
+  std::vector<signed char> tag;      // [E][5]
+  std::vector<PFace> faces;
+  std::vector<int> efc, eside;       // [E][5]
+  std::vector<double> xc, Ls, vol;   // [E][3], [E][3], [E]
+  std::vector<double> S;             // [E][Nmax][Nmax], lower triangular
+  std::vector<std::array<int, 3>> mono;
+  std::string err;
+};
+
+const int TETF[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+const int PRIF[5][4] = {{0, 1, 2, -1}, {3, 4, 5, -1}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}};
+
+int pnmodes(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+int pnfaces(int t) { return t == 0 ? 4 : 5; }
+int pnverts(int t) { return t == 0 ? 4 : 6; }
+
+std::vector<std::array<int, 3>> poly_monomials(int p) {
+  std::vector<std::array<int, 3>> m;
+  for (int k = 0; k <= p; ++k)
+    for (int a = k; a >= 0; --a)
+      for (int b = k - a; b >= 0; --b) m.push_back({a, b, k - a - b});
+  return m;
+}
+
+void face_vertices(const Poly& P, int e, int lf, int* vv, int* n) {
+  const int t = P.typ[e];
+  if (t == 0) {
+    *n = 3;
+    for (int k = 0; k < 3; ++k) vv[k] = P.ev[(size_t)e * 6 + TETF[lf][k]];
+  } else {
+    *n = lf < 2 ? 3 : 4;
+    for (int k = 0; k < *n; ++k) vv[k] = P.ev[(size_t)e * 6 + PRIF[lf][k]];
+  }
+}
+
+// Canonical order of a face's vertices (see the readings above).
+void canonical(int n, const int* vv, int* cv) {
+  if (n == 3) {
+    for (int k = 0; k < 3; ++k) cv[k] = vv[k];
+    std::sort(cv, cv + 3);
+    return;
+  }
+  int k0 = 0;
+  for (int k = 1; k < 4; ++k) if (vv[k] < vv[k0]) k0 = k;
+  int nxt = vv[(k0 + 1) % 4], prv = vv[(k0 + 3) % 4];
+  int dir = nxt < prv ? 1 : 3;
+  for (int k = 0; k < 4; ++k) cv[k] = vv[(k0 + dir * k) % 4];
+}
+
+const double* pvx(const Poly& P, int v) { return &P.xyz[(size_t)v * 3]; }
+
+// Volume rule of element e with Q points per direction: points and weights.
+void poly_vol_rule(const Poly& P, int e, int Q, std::vector<double>& X, std::vector<double>& W) {
+  std::vector<double> xg, wg;
+  gauss_legendre(Q, xg, wg);
+  for (int k = 0; k < Q; ++k) { xg[k] = 0.5 * (1.0 + xg[k]); wg[k] *= 0.5; }
+  X.clear();
+  W.clear();
+  const int* v = &P.ev[(size_t)e * 6];
+  if (P.typ[e] == 0) {
+    const double *A = pvx(P, v[0]), *B = pvx(P, v[1]), *C = pvx(P, v[2]), *D = pvx(P, v[3]);
+    double J[3][3];
+    for (int k = 0; k < 3; ++k) { J[k][0] = B[k] - A[k]; J[k][1] = C[k] - A[k]; J[k][2] = D[k] - A[k]; }
+    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                 J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    for (int i3 = 0; i3 < Q; ++i3)
+      for (int i2 = 0; i2 < Q; ++i2)
+        for (int i1 = 0; i1 < Q; ++i1) {
+          double t1 = xg[i1], t2 = xg[i2], t3 = xg[i3];
+          double l1 = t1 * (1.0 - t2) * (1.0 - t3), l2 = t2 * (1.0 - t3), l3 = t3;
+          for (int k = 0; k < 3; ++k) X.push_back(A[k] + l1 * J[k][0] + l2 * J[k][1] + l3 * J[k][2]);
+          W.push_back(wg[i1] * wg[i2] * wg[i3] * (1.0 - t2) * (1.0 - t3) * (1.0 - t3) * std::fabs(det));
+        }
+  } else {
+    const double* Vx[6];
+    for (int a = 0; a < 6; ++a) Vx[a] = pvx(P, v[a]);
+    for (int i3 = 0; i3 < Q; ++i3)
+      for (int i2 = 0; i2 < Q; ++i2)
+        for (int i1 = 0; i1 < Q; ++i1) {
+          double t1 = xg[i1], t2 = xg[i2], z = xg[i3];
+          double l1 = t1 * (1.0 - t2), l2 = t2, l0 = 1.0 - l1 - l2;
+          double lam[3] = {l0, l1, l2};
+          double J[3][3];
+          for (int k = 0; k < 3; ++k) {
+            double x = 0.0;
+            for (int a = 0; a < 3; ++a) x += lam[a] * ((1.0 - z) * Vx[a][k] + z * Vx[a + 3][k]);
+            X.push_back(x);
+            J[k][0] = (1.0 - z) * (Vx[1][k] - Vx[0][k]) + z * (Vx[4][k] - Vx[3][k]);
+            J[k][1] = (1.0 - z) * (Vx[2][k] - Vx[0][k]) + z * (Vx[5][k] - Vx[3][k]);
+            J[k][2] = 0.0;
+            for (int a = 0; a < 3; ++a) J[k][2] += lam[a] * (Vx[a + 3][k] - Vx[a][k]);
+          }
+          double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+          W.push_back(wg[i1] * wg[i2] * wg[i3] * (1.0 - t2) * std::fabs(det));
+        }
+  }
+}
+
+// Face rule over the canonical vertices: points, weights times |n dsigma|
+// factor (so sum W = area) and unit normals (canonical orientation).
+void poly_face_rule(const Poly& P, const PFace& F, int Q, std::vector<double>& X, std::vector<double>& W,
+                    std::vector<double>& Nh) {
+  std::vector<double> xg, wg;
+  gauss_legendre(Q, xg, wg);
+  for (int k = 0; k < Q; ++k) { xg[k] = 0.5 * (1.0 + xg[k]); wg[k] *= 0.5; }
+  X.clear();
+  W.clear();
+  Nh.clear();
+  const double *C0 = pvx(P, F.cv[0]), *C1 = pvx(P, F.cv[1]), *C2 = pvx(P, F.cv[2]);
+  auto cross = [](const double* a, const double* b, double* c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+  };
+  if (F.nv == 3) {
+    double e1[3], e2[3], nv[3];
+    for (int k = 0; k < 3; ++k) { e1[k] = C1[k] - C0[k]; e2[k] = C2[k] - C0[k]; }
+    cross(e1, e2, nv);
+    double a = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    for (int i2 = 0; i2 < Q; ++i2)
+      for (int i1 = 0; i1 < Q; ++i1) {
+        double t1 = xg[i1], t2 = xg[i2], l1 = t1 * (1.0 - t2), l2 = t2;
+        for (int k = 0; k < 3; ++k) X.push_back(C0[k] + l1 * e1[k] + l2 * e2[k]);
+        W.push_back(wg[i1] * wg[i2] * (1.0 - t2) * a);
+        for (int k = 0; k < 3; ++k) Nh.push_back(nv[k] / a);
+      }
+  } else {
+    const double* C3 = pvx(P, F.cv[3]);
+    for (int i2 = 0; i2 < Q; ++i2)
+      for (int i1 = 0; i1 < Q; ++i1) {
+        double s = xg[i1], t = xg[i2];
+        double xs[3], xt[3], nv[3];
+        for (int k = 0; k < 3; ++k) {
+          X.push_back((1 - s) * (1 - t) * C0[k] + s * (1 - t) * C1[k] + s * t * C2[k] + (1 - s) * t * C3[k]);
+          xs[k] = (1 - t) * (C1[k] - C0[k]) + t * (C2[k] - C3[k]);
+          xt[k] = (1 - s) * (C3[k] - C0[k]) + s * (C2[k] - C1[k]);
+        }
+        cross(xs, xt, nv);
+        double a = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        W.push_back(wg[i1] * wg[i2] * a);
+        for (int k = 0; k < 3; ++k) Nh.push_back(nv[k] / a);
+      }
+  }
+}
+
+// Monomials chi_j and their x-gradients at x for element e (N of them).
+void poly_chi(const Poly& P, int e, int N, const double* x, double* chi, double* gchi /*[N][3] or null*/) {
+  double X[3];
+  for (int k = 0; k < 3; ++k) X[k] = (x[k] - P.xc[(size_t)e * 3 + k]) / P.Ls[(size_t)e * 3 + k];
+  for (int j = 0; j < N; ++j) {
+    const auto& a = P.mono[j];
+    double pw[3], dp[3];
+    for (int k = 0; k < 3; ++k) {
+      pw[k] = 1.0;
+      for (int r = 0; r < a[k]; ++r) pw[k] *= X[k];
+      dp[k] = 0.0;
+      if (a[k] > 0) {
+        double t = 1.0;
+        for (int r = 0; r < a[k] - 1; ++r) t *= X[k];
+        dp[k] = a[k] * t;
+      }
+    }
+    chi[j] = pw[0] * pw[1] * pw[2];
+    if (gchi) {
+      gchi[j * 3 + 0] = dp[0] * pw[1] * pw[2] / P.Ls[(size_t)e * 3 + 0];
+      gchi[j * 3 + 1] = pw[0] * dp[1] * pw[2] / P.Ls[(size_t)e * 3 + 1];
+      gchi[j * 3 + 2] = pw[0] * pw[1] * dp[2] / P.Ls[(size_t)e * 3 + 2];
+    }
+  }
+}
+
+// psi_i = sum_j S_ij chi_j (and gradients).
+void poly_psi(const Poly& P, int e, int N, const double* x, double* psi, double* gpsi) {
+  double chi[64], gchi[64 * 3];
+  poly_chi(P, e, N, x, chi, gpsi ? gchi : nullptr);
+  const double* S = &P.S[(size_t)e * P.Nmax * P.Nmax];
+  for (int i = 0; i < N; ++i) {
+    double s = 0.0, g[3] = {0, 0, 0};
+    for (int j = 0; j <= i; ++j) {
+      s += S[i * P.Nmax + j] * chi[j];
+      if (gpsi) for (int k = 0; k < 3; ++k) g[k] += S[i * P.Nmax + j] * gchi[j * 3 + k];
+    }
+    psi[i] = s;
+    if (gpsi) for (int k = 0; k < 3; ++k) gpsi[i * 3 + k] = g[k];
+  }
+}
+
+bool poly_setup(Poly& P) {
+  Oracle& O = P.base;
+  O.d = 3;
+  O.V = 5;
+  P.mono = poly_monomials(P.pmax);
+  P.Nmax = pnmodes(P.pmax);
+  P.efc.assign((size_t)P.ne * 5, -1);
+  P.eside.assign((size_t)P.ne * 5, 0);
+  std::map<std::vector<int>, int> open;
+  for (int e = 0; e < P.ne; ++e) {
+    if (P.typ[e] != 0 && P.typ[e] != 1) { P.err = "unknown element type"; return false; }
+    for (int lf = 0; lf < pnfaces(P.typ[e]); ++lf) {
+      int vv[4], n;
+      face_vertices(P, e, lf, vv, &n);
+      int tg = P.tag[(size_t)e * 5 + lf];
+      if (tg != 0) {
+        PFace F{e, lf, -1, -1, tg, n, {0, 0, 0, 0}, 1.0};
+        canonical(n, vv, F.cv);
+        P.efc[(size_t)e * 5 + lf] = (int)P.faces.size();
+        P.faces.push_back(F);
+        continue;
+      }
+      std::vector<int> key(vv, vv + n);
+      std::sort(key.begin(), key.end());
+      auto it = open.find(key);
+      if (it == open.end()) {
+        PFace F{e, lf, -1, -1, 0, n, {0, 0, 0, 0}, 1.0};
+        canonical(n, vv, F.cv);
+        open[key] = (int)P.faces.size();
+        P.efc[(size_t)e * 5 + lf] = (int)P.faces.size();
+        P.faces.push_back(F);
+      } else {
+        PFace& F = P.faces[it->second];
+        F.eR = e;
+        F.fR = lf;
+        P.efc[(size_t)e * 5 + lf] = it->second;
+        P.eside[(size_t)e * 5 + lf] = 1;
+        open.erase(it);
+      }
+    }
+  }
+  if (!open.empty()) { P.err = "unmatched interior face"; return false; }
+  // element extents, centroids and the MGS basis
+  const int N = P.Nmax, Q = P.pmax + 2;
+  P.xc.assign((size_t)P.ne * 3, 0.0);
+  P.Ls.assign((size_t)P.ne * 3, 0.0);
+  P.vol.assign(P.ne, 0.0);
+  P.S.assign((size_t)P.ne * N * N, 0.0);
+  bool ok = true;
+  for (int e = 0; e < P.ne; ++e) {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int a = 0; a < pnverts(P.typ[e]); ++a)
+      for (int k = 0; k < 3; ++k) {
+        double c = pvx(P, P.ev[(size_t)e * 6 + a])[k];
+        lo[k] = std::min(lo[k], c);
+        hi[k] = std::max(hi[k], c);
+      }
+    for (int k = 0; k < 3; ++k) P.Ls[(size_t)e * 3 + k] = 0.5 * (hi[k] - lo[k]);
+    std::vector<double> X, W;
+    poly_vol_rule(P, e, Q, X, W);
+    const int nq = (int)W.size();
+    double v = 0.0, m[3] = {0, 0, 0};
+    for (int q = 0; q < nq; ++q) {
+      v += W[q];
+      for (int k = 0; k < 3; ++k) m[k] += W[q] * X[q * 3 + k];
+    }
+    P.vol[e] = v;
+    for (int k = 0; k < 3; ++k) P.xc[(size_t)e * 3 + k] = m[k] / v;
+    // modified Gram-Schmidt on the monomial values at the points, applying
+    // the same operations to the coefficient rows
+    std::vector<double> chi((size_t)nq * N), psiv((size_t)nq * N);
+    for (int q = 0; q < nq; ++q) poly_chi(P, e, N, &X[q * 3], &chi[(size_t)q * N], nullptr);
+    double* S = &P.S[(size_t)e * N * N];
+    for (int i = 0; i < N; ++i) {
+      std::vector<double> w(nq), c(N, 0.0);
+      for (int q = 0; q < nq; ++q) w[q] = chi[(size_t)q * N + i];
+      c[i] = 1.0;
+      for (int j = 0; j < i; ++j) {
+        double h = 0.0;
+        for (int q = 0; q < nq; ++q) h += W[q] * w[q] * psiv[(size_t)q * N + j];
+        for (int q = 0; q < nq; ++q) w[q] -= h * psiv[(size_t)q * N + j];
+        for (int k = 0; k <= j; ++k) c[k] -= h * S[j * N + k];
+      }
+      double nn = 0.0;
+      for (int q = 0; q < nq; ++q) nn += W[q] * w[q] * w[q];
+      if (!(nn > 0.0)) { ok = false; break; }
+      double s = 1.0 / std::sqrt(nn);
+      for (int q = 0; q < nq; ++q) psiv[(size_t)q * N + i] = s * w[q];
+      for (int k = 0; k <= i; ++k) S[i * N + k] = s * c[k];
+    }
+  }
+  if (!ok) { P.err = "degenerate element (MGS)"; return false; }
+  // outward orientation of the canonical face normal for the L element
+  for (auto& F : P.faces) {
+    double cE[3] = {0, 0, 0}, cF[3] = {0, 0, 0};
+    int nve = pnverts(P.typ[F.eL]);
+    for (int a = 0; a < nve; ++a)
+      for (int k = 0; k < 3; ++k) cE[k] += pvx(P, P.ev[(size_t)F.eL * 6 + a])[k] / nve;
+    for (int a = 0; a < F.nv; ++a)
+      for (int k = 0; k < 3; ++k) cF[k] += pvx(P, F.cv[a])[k] / F.nv;
+    std::vector<double> X, W, Nh;
+    poly_face_rule(P, F, 2, X, W, Nh);
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) s += Nh[k] * (cF[k] - cE[k]);
+    F.sgn = s < 0.0 ? -1.0 : 1.0;
+  }
+  double vinf[3] = {O.mach * std::cos(O.alpha) * std::cos(O.beta), O.mach * std::sin(O.alpha) * std::cos(O.beta),
+                    O.mach * std::sin(O.beta)};
+  O.Uinf[0] = 1.0;
+  double ke = 0.0;
+  for (int a = 0; a < 3; ++a) { O.Uinf[1 + a] = vinf[a]; ke += vinf[a] * vinf[a]; }
+  O.Uinf[4] = (1.0 / O.gam) / (O.gam - 1.0) + 0.5 * ke;
+  return true;
+}
+
+template <class S> void poly_state(const Poly& P, int e, int N, const S* u, const double* psi, S* U) {
+  for (int v = 0; v < 5; ++v) {
+    S s = 0.0;
+    for (int i = 0; i < N; ++i) s += u[((size_t)e * 5 + v) * N + i] * psi[i];
+    U[v] = s;
+  }
+  (void)P;
+}
+
+// DG residual R_p(u) of eq. (euler3) on the tetrahedra and prisms:
+//   R_{E,i} = - sum_faces int psi_i F~ . n^ dsigma + int_E F . grad psi_i dx,
+// (p+2)-point collapsed rules in the volume and on every face; each face flux
+// computed once with eL's outward normal and lifted to both sides.
+template <class S> void poly_residual_t(const Poly& P, int p, const S* u, S* r) {
+  const Oracle& O = P.base;
+  const int V = 5, N = pnmodes(p), Q = p + 2;
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < P.ne; ++e) {
+    S* re_ = r + (size_t)e * V * N;
+    for (int i = 0; i < V * N; ++i) re_[i] = 0.0;
+    std::vector<double> X, W;
+    poly_vol_rule(P, e, Q, X, W);
+    double psi[64], gpsi[64 * 3];
+    for (size_t q = 0; q < W.size(); ++q) {
+      poly_psi(P, e, N, &X[q * 3], psi, gpsi);
+      S U[MAXV], F[3][MAXV];
+      poly_state(P, e, N, u, psi, U);
+      for (int a = 0; a < 3; ++a) {
+        double ea[3] = {0, 0, 0};
+        ea[a] = 1.0;
+        flux_n(3, O.gam, U, ea, F[a]);
+      }
+      for (int v = 0; v < V; ++v)
+        for (int i = 0; i < N; ++i) {
+          S s = 0.0;
+          for (int a = 0; a < 3; ++a) s += F[a][v] * gpsi[i * 3 + a];
+          re_[v * N + i] += W[q] * s;
+        }
+    }
+  }
+  const int nf = (int)P.faces.size(), nqf = Q * Q;
+  std::vector<S> flux((size_t)nf * nqf * V);
+#pragma omp parallel for schedule(static)
+  for (int fc = 0; fc < nf; ++fc) {
+    const PFace& F = P.faces[fc];
+    std::vector<double> X, W, Nh;
+    poly_face_rule(P, F, Q, X, W, Nh);
+    double psiL[64], psiR[64];
+    for (int k = 0; k < nqf; ++k) {
+      double nh[3];
+      for (int a = 0; a < 3; ++a) nh[a] = F.sgn * Nh[k * 3 + a];
+      S UL[MAXV], UR[MAXV], Fl[MAXV];
+      poly_psi(P, F.eL, N, &X[k * 3], psiL, nullptr);
+      poly_state(P, F.eL, N, u, psiL, UL);
+      if (F.eR >= 0) {
+        poly_psi(P, F.eR, N, &X[k * 3], psiR, nullptr);
+        poly_state(P, F.eR, N, u, psiR, UR);
+      } else {
+        ghost_any(O, F.tag, UL, nh, &X[k * 3], UR);
+      }
+      num_flux(O, UL, UR, nh, Fl);
+      for (int v = 0; v < V; ++v) flux[((size_t)fc * nqf + k) * V + v] = W[k] * Fl[v];
+    }
+  }
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < P.ne; ++e) {
+    S* re_ = r + (size_t)e * V * N;
+    double psi[64];
+    for (int lf = 0; lf < pnfaces(P.typ[e]); ++lf) {
+      int fc = P.efc[(size_t)e * 5 + lf], side = P.eside[(size_t)e * 5 + lf];
+      std::vector<double> X, W, Nh;
+      poly_face_rule(P, P.faces[fc], Q, X, W, Nh);
+      double sg = side == 0 ? -1.0 : 1.0;
+      for (int k = 0; k < nqf; ++k) {
+        poly_psi(P, e, N, &X[k * 3], psi, nullptr);
+        for (int v = 0; v < V; ++v)
+          for (int i = 0; i < N; ++i) re_[v * N + i] += sg * psi[i] * flux[((size_t)fc * nqf + k) * V + v];
+      }
+    }
+  }
+}
+
+// Manufactured solution on the tetrahedra and prisms: L2 projection (mode 0)
+// and the source f_i = int psi_i div F(U_m) dx (mode 1, divergence by complex
+// step in x), with the (p+4)-point volume rule.
+void poly_mms(const Poly& P, int p, int mode, double* out) {
+  const int V = 5, N = pnmodes(p), Q = p + 4;
+  const double g = P.base.gam;
+  for (int e = 0; e < P.ne; ++e) {
+    for (int i = 0; i < V * N; ++i) out[(size_t)e * V * N + i] = 0.0;
+    std::vector<double> X, W;
+    poly_vol_rule(P, e, Q, X, W);
+    double psi[64];
+    for (size_t q = 0; q < W.size(); ++q) {
+      const double* x = &X[q * 3];
+      poly_psi(P, e, N, x, psi, nullptr);
+      double val[MAXV];
+      if (mode == 0) {
+        mms_state<double>(3, g, x, val);
+      } else {
+        for (int v = 0; v < V; ++v) val[v] = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          cd xcx[3], Uc[MAXV], Fc[MAXV];
+          for (int b = 0; b < 3; ++b) xcx[b] = x[b];
+          xcx[a] = cd(x[a], 1e-30);
+          mms_state<cd>(3, g, xcx, Uc);
+          double ea[3] = {0, 0, 0};
+          ea[a] = 1.0;
+          flux_n<cd>(3, g, Uc, ea, Fc);
+          for (int v = 0; v < V; ++v) val[v] += Fc[v].imag() / 1e-30;
+        }
+      }
+      for (int v = 0; v < V; ++v)
+        for (int i = 0; i < N; ++i) out[((size_t)e * V + v) * N + i] += W[q] * psi[i] * val[v];
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void* porc_create(int n_vert, const double* xyz, int n_elem, const int8_t* typ, const int32_t* ev,
+                  const int8_t* tag, int pmax, double gamma, double mach, double alpha_deg, double beta_deg,
+                  char* errbuf, int errlen) {
+  Poly* P = new Poly;
+  P->nv = n_vert;
+  P->ne = n_elem;
+  P->pmax = pmax;
+  P->base.gam = gamma;
+  P->base.mach = mach;
+  P->base.alpha = alpha_deg * M_PI / 180.0;
+  P->base.beta = beta_deg * M_PI / 180.0;
+  P->xyz.assign(xyz, xyz + (size_t)n_vert * 3);
+  P->typ.assign(typ, typ + n_elem);
+  P->ev.assign(ev, ev + (size_t)n_elem * 6);
+  P->tag.assign(tag, tag + (size_t)n_elem * 5);
+  if (pmax < 0 || pmax > 4 || !poly_setup(*P)) {
+    if (pmax < 0 || pmax > 4) P->err = "pmax out of range";
+    if (errbuf && errlen > 0) std::snprintf(errbuf, errlen, "%s", P->err.c_str());
+    delete P;
+    return nullptr;
+  }
+  return P;
+}
+
+void porc_free(void* h) { delete static_cast<Poly*>(h); }
+void porc_set_flux(void* h, int flux) { static_cast<Poly*>(h)->base.flux = flux; }
+int porc_nmodes(int p) { return pnmodes(p); }
+int porc_nfaces(void* h) { return (int)static_cast<Poly*>(h)->faces.size(); }
+
+void porc_monomials(int p, int32_t* a /*[N][3]*/) {
+  auto m = poly_monomials(p);
+  for (size_t j = 0; j < m.size(); ++j)
+    for (int k = 0; k < 3; ++k) a[j * 3 + k] = m[j][k];
+}
+
+void porc_geometry(void* h, double* vol, double* xc, double* L) {
+  const Poly& P = *static_cast<Poly*>(h);
+  for (int e = 0; e < P.ne; ++e) {
+    vol[e] = P.vol[e];
+    for (int k = 0; k < 3; ++k) { xc[e * 3 + k] = P.xc[e * 3 + k]; L[e * 3 + k] = P.Ls[e * 3 + k]; }
+  }
+}
+
+void porc_basis_S(void* h, double* S) {
+  const Poly& P = *static_cast<Poly*>(h);
+  std::memcpy(S, P.S.data(), P.S.size() * sizeof(double));
+}
+
+// Volume rule of element e with Q points per direction (Q^3 points).
+void porc_vol_rule(void* h, int e, int Q, double* X, double* W) {
+  std::vector<double> x, w;
+  poly_vol_rule(*static_cast<Poly*>(h), e, Q, x, w);
+  std::memcpy(X, x.data(), x.size() * sizeof(double));
+  std::memcpy(W, w.data(), w.size() * sizeof(double));
+}
+
+// Faces: info[f] = (eL, fL, eR, fR, tag, nv), cv[f] canonical vertices, sgn[f].
+void porc_faces(void* h, int32_t* info, int32_t* cv, double* sgn) {
+  const Poly& P = *static_cast<Poly*>(h);
+  for (size_t f = 0; f < P.faces.size(); ++f) {
+    const PFace& F = P.faces[f];
+    int32_t r[6] = {F.eL, F.fL, F.eR, F.fR, F.tag, F.nv};
+    for (int k = 0; k < 6; ++k) info[f * 6 + k] = r[k];
+    for (int k = 0; k < 4; ++k) cv[f * 4 + k] = k < F.nv ? F.cv[k] : -1;
+    sgn[f] = F.sgn;
+  }
+}
+
+// Face rule of face f with Q points per direction (Q^2 points), unit normals
+// out of the face's L element.
+void porc_face_rule(void* h, int f, int Q, double* X, double* W, double* Nh) {
+  const Poly& P = *static_cast<Poly*>(h);
+  std::vector<double> x, w, n;
+  poly_face_rule(P, P.faces[f], Q, x, w, n);
+  for (auto& c : n) c *= P.faces[f].sgn;
+  std::memcpy(X, x.data(), x.size() * sizeof(double));
+  std::memcpy(W, w.data(), w.size() * sizeof(double));
+  std::memcpy(Nh, n.data(), n.size() * sizeof(double));
+}
+
+void porc_psi(void* h, int e, int N, const double* x, double* psi, double* gpsi) {
+  poly_psi(*static_cast<Poly*>(h), e, N, x, psi, gpsi);
+}
+
+void porc_freestream(void* h, int p, double* u) {
+  const Poly& P = *static_cast<Poly*>(h);
+  const int N = pnmodes(p);
+  for (int e = 0; e < P.ne; ++e) {
+    double s00 = P.S[(size_t)e * P.Nmax * P.Nmax];
+    for (int v = 0; v < 5; ++v)
+      for (int i = 0; i < N; ++i) u[((size_t)e * 5 + v) * N + i] = i == 0 ? P.base.Uinf[v] / s00 : 0.0;
+  }
+}
+
+void porc_residual(void* h, int p, const double* u, double* r) { poly_residual_t(*static_cast<Poly*>(h), p, u, r); }
+
+void porc_residual_complex(void* h, int p, const double* ure, const double* uim, double* rre, double* rim) {
+  const Poly& P = *static_cast<Poly*>(h);
+  size_t n = (size_t)P.ne * 5 * pnmodes(p);
+  std::vector<cd> u(n), r(n);
+  for (size_t i = 0; i < n; ++i) u[i] = cd(ure[i], uim[i]);
+  poly_residual_t(P, p, u.data(), r.data());
+  for (size_t i = 0; i < n; ++i) { rre[i] = r[i].real(); rim[i] = r[i].imag(); }
+}
+
+void porc_mms_project(void* h, int p, double* u) { poly_mms(*static_cast<Poly*>(h), p, 0, u); }
+void porc_mms_forcing(void* h, int p, double* f) { poly_mms(*static_cast<Poly*>(h), p, 1, f); }
+
+}  // extern "C"
