@@ -363,6 +363,58 @@ def c5_adjoint(P, budget):
     return out
 
 
+def poly_work(p, n_tet, n_prism):
+    """Algorithmic FP64 flops of one tetrahedron / prism residual at order p
+    (the contractions only; the pointwise flux arithmetic is not counted):
+    monomial coefficients S^T u and R = S m (V N (N+1) each), the state at
+    every volume point (2 V N) and face point (own and neighbour: 4 V N), the
+    flux moments (2 * 15 N_{p-1} per volume point) and the face moments
+    (2 V N per face point).  Bytes: state in, coefficients written and read,
+    the lower triangle of S, residual out."""
+    V, N, NL, Q = 5, (p + 1) * (p + 2) * (p + 3) // 6, p * (p + 1) * (p + 2) // 6, p + 2
+    def one(nf):
+        nfp = nf * Q * Q
+        return 2 * V * N * (N + 1) + Q ** 3 * (2 * V * N + 30 * NL) + nfp * (4 * V * N + 2 * V * N)
+    flops = n_tet * one(4) + n_prism * one(5)
+    byts = (n_tet + n_prism) * 8 * (4 * V * N + N * (N + 1) // 2)
+    return flops, byts
+
+
+def poly_measurements(P, steps):
+    """The DG residual with the paper's Cartesian P_p basis on the
+    tetrahedron / prism sphere shell (9216 tetrahedra, 4608 prisms; Section
+    3.2, Section 5.2's element types), p = 1..3, Roe flux: event-timed
+    launches on the solver's stream."""
+    import torch
+    from eg_inputs import sphere_poly
+    m = sphere_poly(8, 6, 4)
+    n_tet, n_pr = m.counts()
+    S = P.PolySolver(m, 3, mach=0.3, flux="roe")
+    out = {"mesh": f"sphere shell r 0.5..20, {n_tet} tetrahedra + {n_pr} prisms (straight-sided)", "levels": {}}
+    for p in (1, 2, 3):
+        u = S.freestream(p)
+        u.mul_(1.0 + 0.01 * torch.rand_like(u))
+        r = S.residual(p, u)
+        for _ in range(3):
+            S.residual(p, u, out=r)
+        st = S.stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        n = max(steps, 10)
+        e0.record(st)
+        for _ in range(n):
+            S.residual(p, u, out=r)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n
+        fl, by = poly_work(p, n_tet, n_pr)
+        out["levels"][f"p{p}"] = {"ms_per_residual": round(ms, 4), "dof": m.n_elem * 5 * P.PolySolver.N(p),
+                                  "algorithmic_gflop": round(fl / 1e9, 4), "achieved_tflops": round(fl / ms / 1e9, 3),
+                                  "frac_fp64_vector_peak": round(fl / ms / 1e9 / 78.6, 4),
+                                  "algorithmic_bytes": by, "achieved_GBps": round(by / ms / 1e6, 1)}
+        log(f"[bench] tet/prism residual p={p}: {ms * 1e3:.1f} us, {fl / ms / 1e9:.2f} TFLOP/s")
+    return out
+
+
 def cpu_baseline(mesh, p):
     """The FP64 oracle on the host cores (all of them): one V-cycle of the
     benchmark workload from the free stream (a bounded sample, ~20 s)."""
@@ -394,6 +446,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-solve batched workload")
     ap.add_argument("--batch-budget", type=float, default=30.0, help="seconds cap of the batched convergence run")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured-peak kernels")
+    ap.add_argument("--no-poly", action="store_true", help="skip the tetrahedron / prism residual timing")
+    ap.add_argument("--poly-only", action="store_true",
+                    help="only the tetrahedron / prism residual timing (profiling runs); prints its JSON")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--c5", action="store_true",
                     help="also run the 3D p = 3 adjoint workload (minutes: a converged 13824-hex p = 3 solve)")
@@ -413,6 +468,18 @@ def main():
     from eg_inputs import cubed_sphere_shell
 
     torch.cuda.set_device(0)
+    if args.poly_only:
+        res = poly_measurements(P, args.steps)
+        if args.calibrate:
+            nb = 256 << 20
+            x = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+            y = torch.empty_like(x)
+            torch.cuda.synchronize()
+            y.copy_(x)
+            torch.cuda.synchronize()
+            res["calibration_copy_bytes"] = nb
+        print(json.dumps({"tet_prism_residual": res}), flush=True)
+        return
     # the sphere grid is built from quadratic curved elements (Section 5.2)
     mesh = cubed_sphere_shell(16, 24, curved=not args.straight)
     nodes = 8 if args.straight else 27
@@ -525,6 +592,8 @@ def main():
             extras["c1_time_to_1e-10"] = c1_time_to_drop(P)
     if not args.no_batched:
         extras["batched"] = batched_measurements(P, 10, args.batch_budget)
+    if not args.no_poly:
+        extras["tet_prism_residual"] = poly_measurements(P, args.steps)
     if args.c5:
         extras["c5_adjoint"] = c5_adjoint(P, args.c5_budget)
     if args.calibrate:

@@ -381,6 +381,76 @@ eg_status eg_profile_read(eg_handle* h, int kernel_class, int p, double* total_m
  * EG_ERR_HIP if a HIP call fails. */
 eg_status eg_measure_peak(int kind, void* hip_stream, double* value_host);
 
+/* ------------------------------------------------------------------------
+ * Tetrahedra and prisms with the Cartesian basis (Section 3.2).
+ *
+ * The paper's basis: on every element the normalised monomials
+ * chi_j(x) = prod_k ((x_k - xc_k) / L_k)^{a_k} of total degree <= p
+ * (eq. (basis2); xc the element centroid, L_k half the element's extent
+ * along axis k), orthonormalised by modified Gram-Schmidt in the element's
+ * L2 inner product (eq. (basis)): psi_i = sum_{j<=i} S_ij chi_j, S lower
+ * triangular.  N_p = (p+1)(p+2)(p+3)/6 modes, ordered by total degree, then
+ * a_x descending, then a_y descending, so level p-1 is the leading slice.
+ * Coefficient vectors are [elem][var][mode] FP64, V = 5 variables.
+ *
+ * Mesh (eg_poly_mesh, host arrays, copied): elem_type 0 = tetrahedron
+ * (first four vertices, det(v1-v0, v2-v0, v3-v0) > 0), 1 = prism (bottom
+ * v0 v1 v2, top v3 v4 v5, v_{a+3} above v_a, det(v1-v0, v2-v0, v3-v0) > 0);
+ * elem_vert [n_elem][6] (tetrahedra pad with -1); bface_tag [n_elem][5]
+ * with the tags of eg_mesh.  Local faces: tetrahedron face k omits v_k;
+ * prism faces (v0 v1 v2), (v3 v4 v5), (v0 v1 v4 v3), (v1 v2 v5 v4),
+ * (v2 v0 v3 v5).  Interior faces are matched through their vertex sets.
+ * Straight-sided elements only.
+ *
+ * Quadrature with Q = p+2 Gauss-Legendre points per direction on [0, 1],
+ * collapsed on simplices: tetrahedron barycentrics l1 = t1(1-t2)(1-t3),
+ * l2 = t2(1-t3), l3 = t3 (weight factor (1-t2)(1-t3)^2); prism triangle
+ * l1 = t1(1-t2), l2 = t2 (factor 1-t2) times zeta = t3 with the pointwise
+ * Jacobian of the map; triangular faces l1 = t1(1-t2), l2 = t2 over the
+ * face's vertices in ascending global id; quadrilateral faces the tensor
+ * rule on the bilinear patch of the corners, cyclic from the lowest id
+ * towards its lower-id neighbour.  The basis of every level comes from the
+ * volume rule of p_max.
+ * ------------------------------------------------------------------------ */
+typedef struct eg_poly_handle eg_poly_handle;
+
+typedef struct {
+  int n_vert;
+  const double* xyz;         /* host, [n_vert][3] */
+  int n_elem;
+  const int8_t* elem_type;   /* host, [n_elem]: 0 tetrahedron, 1 prism */
+  const int32_t* elem_vert;  /* host, [n_elem][6] */
+  const int8_t* bface_tag;   /* host, [n_elem][5]: 0 interior, 1 wall, 2 far-field, 4 symmetry */
+} eg_poly_mesh;
+
+/* Set-up on the current device: face matching, centroids, extents and the
+ * per-element MGS basis (on the host), device copies.  Uses p_max (0..3),
+ * gamma, mach, alpha_deg, beta_deg and flux of prm; the other fields are
+ * ignored.  EG_ERR_ARG for bad sizes or parameters, EG_ERR_MESH for an
+ * unmatched face, a bad tag or vertex id, a non-positive element or a
+ * degenerate basis; EG_ERR_ALLOC / EG_ERR_HIP for device failures.  *out is
+ * set (and must be freed) whenever the status is not EG_ERR_ARG from a null
+ * out pointer. */
+eg_status eg_poly_init(const eg_poly_mesh* mesh, const eg_params* prm, void* hip_stream, eg_poly_handle** out);
+void eg_poly_free(eg_poly_handle* h);
+const char* eg_poly_last_error(const eg_poly_handle* h);
+
+/* Uniform free stream at level p: u_{E,v,0} = U_inf,v / S_00, other modes 0
+ * (u_dev: n_elem * 5 * N_p doubles, device). */
+eg_status eg_poly_freestream(eg_poly_handle* h, int p, double* u_dev);
+
+/* DG residual R_p(u) of eq. (euler3) on the tetrahedra and prisms:
+ * R_{E,i} = -sum_faces int psi_i F~ . n dsigma + int_E F . grad psi_i dx,
+ * with the handle's numerical flux and the ghost states of eg_mesh tags
+ * (Section 3.3).  u_dev, r_dev: n_elem * 5 * N_p doubles, device, distinct.
+ * Enqueued on the handle's stream, no synchronisation. */
+eg_status eg_poly_residual(eg_poly_handle* h, int p, const double* u_dev, double* r_dev);
+
+/* Copies of the set-up (host buffers): S [n_elem][N_pmax][N_pmax] (row i
+ * holds S_ij, j <= i), xc [n_elem][3], L [n_elem][3], vol [n_elem]; any
+ * pointer may be NULL. */
+eg_status eg_poly_basis(const eg_poly_handle* h, double* S_host, double* xc_host, double* L_host, double* vol_host);
+
 #ifdef __cplusplus
 }
 #endif

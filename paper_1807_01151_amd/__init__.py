@@ -8,6 +8,7 @@ implementation: if the library is missing or cannot be loaded, calls raise.
 
 from .binding import (  # noqa: F401
     BatchSolver,
+    PolySolver,
     EgError,
     Solver,
     lib,

@@ -17,6 +17,8 @@ EXPORTED_SYMBOLS = (
     "eg_drag", "eg_adjoint_apply", "eg_adjoint_solve", "eg_init_batch", "eg_layout", "eg_solve_batch", "eg_autotune",
     "eg_set_graphs", "eg_measure_peak", "eg_rnorm_noalloc",
     "eg_param_sensitivity", "eg_jacobian_apply", "eg_solve_multi",
+    "eg_poly_init", "eg_poly_free", "eg_poly_last_error", "eg_poly_freestream", "eg_poly_residual",
+    "eg_poly_basis",
 )
 
 KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
@@ -47,6 +49,12 @@ def _c_mesh(m) -> _Mesh:
                  m.elem_vert.ctypes.data_as(C.POINTER(C.c_int32)),
                  m.bface_tag.ctypes.data_as(C.POINTER(C.c_int8)),
                  None if geo is None else geo.ctypes.data_as(C.POINTER(C.c_double)))
+
+
+class _PolyMesh(C.Structure):
+    _fields_ = [("n_vert", C.c_int), ("xyz", C.POINTER(C.c_double)), ("n_elem", C.c_int),
+                ("elem_type", C.POINTER(C.c_int8)), ("elem_vert", C.POINTER(C.c_int32)),
+                ("bface_tag", C.POINTER(C.c_int8))]
 
 
 class _Params(C.Structure):
@@ -110,6 +118,18 @@ def lib():
         L.eg_solve_multi.argtypes = [C.POINTER(vp), i, C.POINTER(vp), d, i, C.POINTER(vp), C.POINTER(vp),
                                      C.POINTER(i)]
         L.eg_solve_multi.restype = i
+        L.eg_poly_init.argtypes = [C.POINTER(_PolyMesh), C.POINTER(_Params), vp, C.POINTER(vp)]
+        L.eg_poly_init.restype = i
+        L.eg_poly_free.argtypes = [vp]
+        L.eg_poly_free.restype = None
+        L.eg_poly_last_error.argtypes = [vp]
+        L.eg_poly_last_error.restype = C.c_char_p
+        L.eg_poly_freestream.argtypes = [vp, i, vp]
+        L.eg_poly_freestream.restype = i
+        L.eg_poly_residual.argtypes = [vp, i, vp, vp]
+        L.eg_poly_residual.restype = i
+        L.eg_poly_basis.argtypes = [vp, pd, pd, pd, pd]
+        L.eg_poly_basis.restype = i
         for name in ("eg_sizes", "eg_set_freestream", "eg_residual", "eg_timestep", "eg_element_jacobian",
                      "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm", "eg_vcycle",
                      "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read"):
@@ -538,3 +558,90 @@ def solve_multi(batches, us, drop_tol: float = 1e-10, max_cycles: int = 1000):
         cyc = [int(ncs[k][i]) for i in range(b.n)]
         out.append(([hists[k][i, : cyc[i] + 1] for i in range(b.n)], cyc, int(status[k])))
     return out
+
+
+class PolySolver:
+    """Tetrahedra and prisms with the Cartesian basis (eg_poly_* entry
+    points).  Level-p tensors are float64 [n_elem, 5, N_p] on the device,
+    N_p = (p+1)(p+2)(p+3)/6."""
+
+    def __init__(self, mesh, p_max: int, gamma: float = 1.4, mach: float = 0.3, alpha_deg: float = 0.0,
+                 beta_deg: float = 0.0, flux: str = "rusanov", stream=None):
+        import torch
+        L = lib()
+        m = mesh.contiguous()
+        self._keep = (m.xyz, m.elem_type, m.elem_vert, m.bface_tag)
+        if m.elem_vert.shape != (m.n_elem, 6) or m.bface_tag.shape != (m.n_elem, 5) or m.xyz.shape[1:] != (3,):
+            raise ValueError("poly mesh arrays must be xyz [n_vert, 3], elem_vert [n_elem, 6], bface_tag [n_elem, 5]")
+        if flux not in FLUXES:
+            raise ValueError(f"flux must be one of {sorted(FLUXES)}")
+        cm = _PolyMesh(m.n_vert, m.xyz.ctypes.data_as(C.POINTER(C.c_double)), m.n_elem,
+                       m.elem_type.ctypes.data_as(C.POINTER(C.c_int8)),
+                       m.elem_vert.ctypes.data_as(C.POINTER(C.c_int32)),
+                       m.bface_tag.ctypes.data_as(C.POINTER(C.c_int8)))
+        cp = _Params(p_max, 1, 1.0, 1, 1, gamma, mach, alpha_deg, beta_deg, 0, FLUXES[flux])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        st = L.eg_poly_init(C.byref(cm), C.byref(cp), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        self._h = h
+        if st != 0:
+            msg = L.eg_poly_last_error(h).decode() if h.value else ""
+            if h.value:
+                L.eg_poly_free(h)
+            self._h = None
+            raise EgError(st, msg)
+        self.p_max, self.n_elem, self.V = p_max, m.n_elem, 5
+        self.device = torch.cuda.current_device()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().eg_poly_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        if st != 0:
+            raise EgError(st, lib().eg_poly_last_error(self._h).decode())
+
+    @staticmethod
+    def N(p: int) -> int:
+        return (p + 1) * (p + 2) * (p + 3) // 6
+
+    def _vec(self, t, p: int, name: str):
+        if not 0 <= p <= self.p_max:
+            raise ValueError(f"order p = {p} outside 0..{self.p_max}")
+        return check_tensor(t, self.n_elem * 5 * self.N(p), "float64", self.device, name)
+
+    def empty(self, p: int):
+        import torch
+        return torch.empty((self.n_elem, 5, self.N(p)), dtype=torch.float64, device="cuda")
+
+    def freestream(self, p: int):
+        u = self.empty(p)
+        self._chk(lib().eg_poly_freestream(self._h, p, self._vec(u, p, "u")))
+        return u
+
+    def residual(self, p: int, u, out=None):
+        pu = self._vec(u, p, "u")
+        r = self.empty(p) if out is None else out
+        pr = self._vec(r, p, "out")
+        if pr.value == pu.value:
+            raise ValueError("out must not alias u")
+        self._chk(lib().eg_poly_residual(self._h, p, pu, pr))
+        return r
+
+    def basis(self):
+        """(S [n_elem, N_pmax, N_pmax], xc [n_elem, 3], L [n_elem, 3], vol [n_elem]) of the set-up."""
+        import numpy as np
+        n = self.N(self.p_max)
+        S = np.zeros((self.n_elem, n, n))
+        xc, Lh, vol = np.zeros((self.n_elem, 3)), np.zeros((self.n_elem, 3)), np.zeros(self.n_elem)
+        pd = C.POINTER(C.c_double)
+        self._chk(lib().eg_poly_basis(self._h, S.ctypes.data_as(pd), xc.ctypes.data_as(pd), Lh.ctypes.data_as(pd),
+                                      vol.ctypes.data_as(pd)))
+        return S, xc, Lh, vol

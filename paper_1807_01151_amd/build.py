@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeg.so")
-SOURCES = ["eg_kernels.hip", "eg_jaclu_lds.hip", "eg_noalloc.hip", "eg_peak.hip", "eg_tangent.hip", "eg_host.cpp"]
+SOURCES = ["eg_kernels.hip", "eg_jaclu_lds.hip", "eg_noalloc.hip", "eg_peak.hip", "eg_tangent.hip", "eg_poly.hip", "eg_host.cpp"]
 FLAGS_COMPILE = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC",
                  "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                  "-Wno-unused-result", "-Wno-unknown-pragmas"]

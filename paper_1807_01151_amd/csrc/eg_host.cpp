@@ -837,9 +837,17 @@ eg_status adj_norm(eg_handle* h, double* out) {
 
 }  // namespace
 
-extern "C" {
-
-}  // extern "C"
+namespace eg {
+// The Gauss-Legendre rule mapped to [0, 1] (points ascending, weights summing
+// to 1), for the tetrahedron / prism set-up.
+void gauss_rule01(int Q, double* x, double* w) {
+  gauss_rule(Q, x, w);
+  for (int k = 0; k < Q; ++k) {
+    x[k] = 0.5 * (1.0 + x[k]);
+    w[k] *= 0.5;
+  }
+}
+}  // namespace eg
 
 namespace {
 

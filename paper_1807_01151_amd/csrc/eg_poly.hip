@@ -1,0 +1,833 @@
+// Tetrahedra and prisms with the paper's Cartesian basis (arXiv:1807.01151,
+// Section 3.2): set-up (face matching, centroids, extents, the per-element
+// modified Gram-Schmidt basis, quadrature tables) and the DG residual of
+// eq. (euler3) on the device.
+//
+// Design.  Because the basis is a polynomial in the global coordinates, the
+// residual never needs a reference map at face points: a state is evaluated
+// from its monomial coefficients a = S^T u (U_v(x) = sum_j a_vj chi_j(x)),
+// and the residual is formed in monomial moments
+//   m_vj = int_E F_v . grad chi_j dx - sum_faces int chi_j F~_v dsigma,
+// then R = S m.  k_poly_mono writes a for every element (one FP64 vector per
+// element, read back by the element and its face neighbours); k_poly_residual
+// runs one wavefront per element: the lanes first take the quadrature points
+// (state, flux, weight into LDS), then the outputs (v, j), which contract the
+// staged values with the monomial derivatives recomputed from the scaled
+// coordinates.  Face points are generated on the fly from the face's
+// canonically ordered vertices, so both sides of a face evaluate bit-identical
+// points; a per-face sign turns the canonical normal outward.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/eg.h"
+#include "eg_common.h"
+#include "eg_physics.h"
+
+namespace eg {
+void gauss_rule01(int Q, double* x, double* w);
+}
+
+namespace {
+
+constexpr int PV = 5;         // conserved variables in 3D
+constexpr int PMAX_POLY = 3;  // highest order (N = 20)
+constexpr int NMAX_POLY = 20;
+// boundary codes in the neighbour table
+constexpr int PB_WALL = -1, PB_FAR = -2, PB_SYM = -4;
+
+__host__ __device__ constexpr int pn(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+// Exponents of monomial j: total degree, then a_x descending, then a_y
+// descending.
+__host__ __device__ inline void mono_exp(int j, int& ax, int& ay, int& az) {
+  int idx = 0;
+  for (int k = 0; k <= PMAX_POLY; ++k)
+    for (int a = k; a >= 0; --a)
+      for (int b = k - a; b >= 0; --b) {
+        if (idx == j) { ax = a; ay = b; az = k - a - b; return; }
+        ++idx;
+      }
+  ax = ay = az = 0;
+}
+
+struct PolyDev {
+  const double* xyz;     // [nv][3]
+  const int32_t* ev;     // [E][6]
+  const int8_t* typ;     // [E]
+  const int32_t* nbr;    // [E][5] neighbour or PB_* code
+  const int32_t* fcv;    // [E][5][4] canonical face vertices (-1 pads a triangle)
+  const int8_t* fsg;     // [E][5] +1 / -1: orientation of the canonical normal
+  const double* geo;     // [E][6]: xc, L
+  const double* S;       // [E][nmax][nmax]
+  int ne, nmax;
+};
+
+// Reference tables of one order: tetrahedron and prism volume points
+// (l1, l2, l3 or zeta, weight factor), triangle and quad face points
+// (coordinates 1, 2, weight factor).
+struct PolyRule {
+  const double* tet;   // [Q^3][4]
+  const double* pri;   // [Q^3][4]
+  const double* tri;   // [Q^2][3]
+  const double* quad;  // [Q^2][3]
+};
+
+__device__ __forceinline__ double det3(const double* c0, const double* c1, const double* c2) {
+  return c0[0] * (c1[1] * c2[2] - c1[2] * c2[1]) - c1[0] * (c0[1] * c2[2] - c0[2] * c2[1]) +
+         c2[0] * (c0[1] * c1[2] - c0[2] * c1[1]);
+}
+
+// a[e][v][j] = sum_{i >= j} S[e][i][j] u[e][v][i] (monomial coefficients);
+// one thread per (e, j), so each column of S is read once for all five
+// variables (consecutive threads read consecutive entries of a row of S).
+template <int P>
+__global__ __launch_bounds__(256) void k_poly_mono(PolyDev M, const double* __restrict__ u, double* __restrict__ a) {
+  constexpr int N = pn(P);
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)M.ne * N) return;
+  const int j = (int)(idx % N);
+  const long long e = idx / N;
+  const double* Se = M.S + (size_t)e * M.nmax * M.nmax;
+  const double* ue = u + (size_t)e * PV * N;
+  double s[PV];
+#pragma unroll
+  for (int v = 0; v < PV; ++v) s[v] = 0.0;
+  for (int i = j; i < N; ++i) {
+    const double c = Se[(size_t)i * M.nmax + j];
+#pragma unroll
+    for (int v = 0; v < PV; ++v) s[v] += c * ue[v * N + i];
+  }
+#pragma unroll
+  for (int v = 0; v < PV; ++v) a[((size_t)e * PV + v) * N + j] = s[v];
+}
+
+// Scaled coordinates and monomial powers at a point.
+template <int P>
+__device__ __forceinline__ void powers(const double* x, const double* g, double pw[3][P + 1]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double X = (x[k] - g[k]) / g[3 + k];
+    pw[k][0] = 1.0;
+#pragma unroll
+    for (int r = 1; r <= P; ++r) pw[k][r] = pw[k][r - 1] * X;
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void state_at(const double (*pw)[P + 1], const double* a, double* U) {
+  constexpr int N = pn(P);
+#pragma unroll
+  for (int v = 0; v < PV; ++v) U[v] = 0.0;
+  int j = 0;
+#pragma unroll
+  for (int k = 0; k <= P; ++k)
+#pragma unroll
+    for (int ax = k; ax >= 0; --ax)
+#pragma unroll
+      for (int ay = k - ax; ay >= 0; --ay) {
+        const double c = pw[0][ax] * pw[1][ay] * pw[2][k - ax - ay];
+#pragma unroll
+        for (int v = 0; v < PV; ++v) U[v] += a[v * N + j] * c;
+        ++j;
+      }
+}
+
+// Exponents of monomial j and the index of chi_{j - e_d} (the monomial whose
+// x_d-derivative is a_d chi_{j - e_d} up to 1/L_d; -1 when a_d = 0).
+struct MonoTab {
+  int8_t ex[NMAX_POLY][3];
+  int8_t lo[NMAX_POLY][3];
+};
+constexpr MonoTab make_mono_tab() {
+  MonoTab t{};
+  int idx = 0;
+  for (int k = 0; k <= PMAX_POLY; ++k)
+    for (int a = k; a >= 0; --a)
+      for (int b = k - a; b >= 0; --b) {
+        t.ex[idx][0] = (int8_t)a;
+        t.ex[idx][1] = (int8_t)b;
+        t.ex[idx][2] = (int8_t)(k - a - b);
+        ++idx;
+      }
+  for (int j = 0; j < NMAX_POLY; ++j)
+    for (int d = 0; d < 3; ++d) {
+      t.lo[j][d] = -1;
+      if (t.ex[j][d] == 0) continue;
+      for (int i = 0; i < NMAX_POLY; ++i) {
+        bool same = true;
+        for (int c = 0; c < 3; ++c) same = same && t.ex[i][c] == t.ex[j][c] - (c == d ? 1 : 0);
+        if (same) t.lo[j][d] = (int8_t)i;
+      }
+    }
+  return t;
+}
+__constant__ MonoTab kMono = make_mono_tab();
+
+// The monomials of total degree <= K at a point, in basis order, from the
+// powers table of order P >= K (indices fixed at compile time).
+template <int P, int K>
+__device__ __forceinline__ void mono_values(const double (*pw)[P + 1], double* out) {
+  int j = 0;
+#pragma unroll
+  for (int k = 0; k <= K; ++k)
+#pragma unroll
+    for (int ax = k; ax >= 0; --ax)
+#pragma unroll
+      for (int ay = k - ax; ay >= 0; --ay) out[j++] = pw[0][ax] * pw[1][ay] * pw[2][k - ax - ay];
+}
+
+// One wavefront per element, in five phases:
+//  1. volume points, in chunks of 64 (one per lane): state from the monomial
+//     coefficients, Euler fluxes; LDS gets G[q][d*5+v] = w F_dv / L_d and the
+//     monomials of degree < p at the point;
+//  2. after each chunk, flux moments M[d*5+v][k] += sum_q G[q][.] chi_k(q)
+//     (lanes over (d*5+v, k), accumulated in registers) -- since
+//     grad chi_j = (a_d chi_{j-e_d} / L_d)_d, they carry the whole volume term;
+//  3. face points of every face, in chunks of 64: own and neighbour (or
+//     ghost) traces, the numerical flux; LDS gets w F~_v and all monomials at
+//     the point, in the space phase 1 used;
+//  4. after each chunk, m_vj -= sum_q w F~_v chi_j (lanes over (v, j)); then
+//     m_vj += sum_d a_d M[d*5+v][j-e_d];
+//  5. R = S m.
+// Blocks are mapped to elements so that each XCD (blocks b, b+8, ...) gets a
+// contiguous range of elements, whose neighbours' coefficients then share
+// that XCD's L2.
+template <int P>
+__global__ __launch_bounds__(64) void k_poly_residual(PolyDev M, PolyRule R, eg::Gas gas,
+                                                     const double* __restrict__ a_all, double* __restrict__ r) {
+  constexpr int N = pn(P), NL = pn(P - 1), NL1 = NL > 0 ? NL : 1, Q = P + 2, QV = Q * Q * Q, QF = Q * Q;
+  constexpr int NO = PV * N, NM = 15 * NL;
+  constexpr int CH = 64;  // points per chunk: one per lane
+  constexpr int W1 = 15 + NL, W3 = PV + N;
+  constexpr int MPL = (NM + 63) / 64 > 0 ? (NM + 63) / 64 : 1, OPL = (NO + 63) / 64;
+  __shared__ double sbuf[CH * (W1 > W3 ? W1 : W3)];
+  __shared__ double sa[NO], sm[NO], sM[15 * NL1];
+  __shared__ double sn[5][NO];
+  __shared__ double sg[6], sgn[5][6];
+  __shared__ int snb[5];
+  const int t = threadIdx.x;
+  const int per = (M.ne + 7) / 8;
+  const int e = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (e >= M.ne) return;
+  const int typ = M.typ[e];
+  const int nf = typ == 0 ? 4 : 5;
+  for (int o = t; o < NO; o += 64) sa[o] = a_all[(size_t)e * NO + o];
+  if (t < 6) sg[t] = M.geo[(size_t)e * 6 + t];
+  if (t < 5) snb[t] = t < nf ? M.nbr[(size_t)e * 5 + t] : PB_WALL;
+  __syncthreads();
+  for (int f = 0; f < nf; ++f) {
+    const int nb = snb[f];
+    if (nb < 0) continue;
+    for (int o = t; o < NO; o += 64) sn[f][o] = a_all[(size_t)nb * NO + o];
+    if (t < 6) sgn[f][t] = M.geo[(size_t)nb * 6 + t];
+  }
+  double Xv[6][3];
+  const int nvt = typ == 0 ? 4 : 6;
+  for (int k = 0; k < 6; ++k)
+    for (int c = 0; c < 3; ++c) Xv[k][c] = k < nvt ? M.xyz[(size_t)M.ev[(size_t)e * 6 + k] * 3 + c] : 0.0;
+  // ---- 1 + 2. volume points and flux moments
+  double* sG = sbuf;               // [CH][15]
+  double* sC = sbuf + CH * 15;     // [CH][NL]
+  double accM[MPL];
+#pragma unroll
+  for (int m = 0; m < MPL; ++m) accM[m] = 0.0;
+  for (int q0 = 0; NL > 0 && q0 < QV; q0 += CH) {
+    // keeps the coefficient reads from LDS inside the loop (hoisted, they
+    // would hold V N registers for the whole loop)
+    asm volatile("" ::: "memory");
+    __syncthreads();
+    const int q = q0 + t;
+    if (q < QV) {
+      double x[3], w;
+      if (typ == 0) {
+        const double* rq = R.tet + q * 4;
+        double J[3][3];
+        for (int c = 0; c < 3; ++c) {
+          J[0][c] = Xv[1][c] - Xv[0][c];
+          J[1][c] = Xv[2][c] - Xv[0][c];
+          J[2][c] = Xv[3][c] - Xv[0][c];
+          x[c] = Xv[0][c] + rq[0] * J[0][c] + rq[1] * J[1][c] + rq[2] * J[2][c];
+        }
+        w = rq[3] * fabs(det3(J[0], J[1], J[2]));
+      } else {
+        const double* rq = R.pri + q * 4;
+        const double l1 = rq[0], l2 = rq[1], z = rq[2], l0 = 1.0 - l1 - l2;
+        const double lam[3] = {l0, l1, l2};
+        double J[3][3];
+        for (int c = 0; c < 3; ++c) {
+          double xs = 0.0, dz = 0.0;
+          for (int k = 0; k < 3; ++k) {
+            xs += lam[k] * ((1.0 - z) * Xv[k][c] + z * Xv[k + 3][c]);
+            dz += lam[k] * (Xv[k + 3][c] - Xv[k][c]);
+          }
+          x[c] = xs;
+          J[0][c] = (1.0 - z) * (Xv[1][c] - Xv[0][c]) + z * (Xv[4][c] - Xv[3][c]);
+          J[1][c] = (1.0 - z) * (Xv[2][c] - Xv[0][c]) + z * (Xv[5][c] - Xv[3][c]);
+          J[2][c] = dz;
+        }
+        w = rq[3] * fabs(det3(J[0], J[1], J[2]));
+      }
+      double pw[3][P + 1];
+      powers<P>(x, sg, pw);
+      double U[PV];
+      state_at<P>(pw, sa, U);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double nd[3] = {0.0, 0.0, 0.0};
+        nd[d] = 1.0;
+        double F[PV];
+        eg::flux_n<3>(U, nd, F, gas.g);
+        const double s = w / sg[3 + d];
+#pragma unroll
+        for (int v = 0; v < PV; ++v) sG[t * 15 + d * 5 + v] = s * F[v];
+      }
+      double cv_[NL1];
+      mono_values<P, (P > 0 ? P - 1 : 0)>(pw, cv_);
+#pragma unroll
+      for (int k = 0; k < NL; ++k) sC[t * NL1 + k] = cv_[k];
+    }
+    __syncthreads();
+    const int nq = QV - q0 < CH ? QV - q0 : CH;
+#pragma unroll
+    for (int m = 0; m < MPL; ++m) {
+      const int o = t + 64 * m;
+      if (o < NM) {
+        const int c = o / NL1, k = o % NL1;
+        double acc = accM[m];
+        for (int qq = 0; qq < nq; ++qq) acc += sG[qq * 15 + c] * sC[qq * NL1 + k];
+        accM[m] = acc;
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < MPL; ++m)
+    if (t + 64 * m < NM) sM[t + 64 * m] = accM[m];
+  // ---- 3 + 4. face points of all faces and their moments
+  double* sH = sbuf;               // [CH][5]
+  double* sX = sbuf + CH * PV;     // [CH][N]
+  double accF[OPL];
+#pragma unroll
+  for (int m = 0; m < OPL; ++m) accF[m] = 0.0;
+  const int nfq = nf * QF;
+  for (int q0 = 0; q0 < nfq; q0 += CH) {
+    asm volatile("" ::: "memory");
+    __syncthreads();
+    const int fq = q0 + t;
+    if (fq < nfq) {
+    const int f = fq / QF, q = fq % QF;
+    const int nb = snb[f];
+    const int32_t* cv = M.fcv + ((size_t)e * 5 + f) * 4;
+    const double sgnf = (double)M.fsg[(size_t)e * 5 + f];
+    const int ncv = cv[3] < 0 ? 3 : 4;
+    double C[4][3];
+    for (int k = 0; k < 4; ++k)
+      for (int c = 0; c < 3; ++c) C[k][c] = k < ncv ? M.xyz[(size_t)cv[k] * 3 + c] : 0.0;
+    double x[3], nv[3], w;
+    if (ncv == 3) {
+      const double* rq = R.tri + q * 3;
+      double e1[3], e2[3];
+      for (int c = 0; c < 3; ++c) {
+        e1[c] = C[1][c] - C[0][c];
+        e2[c] = C[2][c] - C[0][c];
+        x[c] = C[0][c] + rq[0] * e1[c] + rq[1] * e2[c];
+      }
+      nv[0] = e1[1] * e2[2] - e1[2] * e2[1];
+      nv[1] = e1[2] * e2[0] - e1[0] * e2[2];
+      nv[2] = e1[0] * e2[1] - e1[1] * e2[0];
+      w = rq[2];
+    } else {
+      const double* rq = R.quad + q * 3;
+      const double s = rq[0], tt = rq[1];
+      double xs[3], xt[3];
+      for (int c = 0; c < 3; ++c) {
+        x[c] = (1 - s) * (1 - tt) * C[0][c] + s * (1 - tt) * C[1][c] + s * tt * C[2][c] + (1 - s) * tt * C[3][c];
+        xs[c] = (1 - tt) * (C[1][c] - C[0][c]) + tt * (C[2][c] - C[3][c]);
+        xt[c] = (1 - s) * (C[3][c] - C[0][c]) + s * (C[2][c] - C[1][c]);
+      }
+      nv[0] = xs[1] * xt[2] - xs[2] * xt[1];
+      nv[1] = xs[2] * xt[0] - xs[0] * xt[2];
+      nv[2] = xs[0] * xt[1] - xs[1] * xt[0];
+      w = rq[2];
+    }
+    const double area = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    double nh[3];
+    for (int c = 0; c < 3; ++c) nh[c] = sgnf * (nv[c] / area);
+    w *= area;
+    double pw[3][P + 1];
+    powers<P>(x, sg, pw);
+    double UL[PV], UR[PV], Fl[PV];
+    state_at<P>(pw, sa, UL);
+    if (nb >= 0) {
+      double pn_[3][P + 1];
+      powers<P>(x, sgn[f], pn_);
+      state_at<P>(pn_, sn[f], UR);
+    } else if (nb == PB_FAR) {
+      eg::ghost_far<3>(UL, nh, UR, gas.Uinf, gas.g);
+    } else {
+      eg::ghost_wall<3>(UL, nh, UR);
+    }
+    if (gas.flux == eg::FLUX_ROE) eg::roe<3>(UL, UR, nh, Fl, gas.g);
+    else eg::rusanov<3>(UL, UR, nh, Fl, gas.g);
+#pragma unroll
+    for (int v = 0; v < PV; ++v) sH[t * PV + v] = w * Fl[v];
+    double xv_[N];
+    mono_values<P, P>(pw, xv_);
+#pragma unroll
+    for (int j = 0; j < N; ++j) sX[t * N + j] = xv_[j];
+    }
+    __syncthreads();
+    const int nq = nfq - q0 < CH ? nfq - q0 : CH;
+#pragma unroll
+    for (int m = 0; m < OPL; ++m) {
+      const int o = t + 64 * m;
+      if (o < NO) {
+        const int v = o / N, j = o % N;
+        double acc = accF[m];
+        for (int qq = 0; qq < nq; ++qq) acc -= sH[qq * PV + v] * sX[qq * N + j];
+        accF[m] = acc;
+      }
+    }
+  }
+  __syncthreads();  // sM complete (written before the face loop)
+#pragma unroll
+  for (int m = 0; m < OPL; ++m) {
+    const int o = t + 64 * m;
+    if (o < NO) {
+      const int v = o / N, j = o % N;
+      double acc = accF[m];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int lo = kMono.lo[j][d];
+        if (lo >= 0) acc += (double)kMono.ex[j][d] * sM[(d * 5 + v) * NL1 + lo];
+      }
+      sm[o] = acc;
+    }
+  }
+  __syncthreads();
+  // ---- 5. R = S m
+  const double* Se = M.S + (size_t)e * M.nmax * M.nmax;
+  for (int o = t; o < NO; o += 64) {
+    const int v = o / N, i = o % N;
+    double s = 0.0;
+    for (int j = 0; j <= i; ++j) s += Se[(size_t)i * M.nmax + j] * sm[v * N + j];
+    r[(size_t)e * NO + o] = s;
+  }
+}
+
+__global__ void k_poly_freestream(int ne, int N, int nmax, const double* __restrict__ S, eg::Gas gas,
+                                  double* __restrict__ u) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)ne * PV * N) return;
+  const int i = (int)(idx % N);
+  const long long ev = idx / N;
+  const int v = (int)(ev % PV);
+  const long long e = ev / PV;
+  u[idx] = i == 0 ? gas.Uinf[v] / S[(size_t)e * nmax * nmax] : 0.0;
+}
+
+}  // namespace
+
+struct eg_poly_handle {
+  int dev = 0, pmax = 0, ne = 0, nv = 0, nmax = 1;
+  hipStream_t st = nullptr;
+  eg::Gas gas{};
+  std::string err;
+  // host copies of the set-up
+  std::vector<double> S, geo, vol;
+  // device
+  double* d_xyz = nullptr;
+  int32_t* d_ev = nullptr;
+  int8_t* d_typ = nullptr;
+  int32_t* d_nbr = nullptr;
+  int32_t* d_fcv = nullptr;
+  int8_t* d_fsg = nullptr;
+  double* d_geo = nullptr;
+  double* d_S = nullptr;
+  double* d_a = nullptr;  // [E][5][nmax] monomial coefficients
+  double* d_rule[PMAX_POLY + 1] = {};
+  PolyRule rule[PMAX_POLY + 1] = {};
+};
+
+namespace {
+
+const int TF[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+const int PF[5][4] = {{0, 1, 2, -1}, {3, 4, 5, -1}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}};
+
+void host_face(const int8_t typ, const int32_t* ev, int lf, int* vv, int* n) {
+  if (typ == 0) {
+    *n = 3;
+    for (int k = 0; k < 3; ++k) vv[k] = ev[TF[lf][k]];
+  } else {
+    *n = lf < 2 ? 3 : 4;
+    for (int k = 0; k < *n; ++k) vv[k] = ev[PF[lf][k]];
+  }
+}
+
+// Canonical order: triangle ascending; quad cyclic from its lowest vertex
+// towards the lower of that vertex's two neighbours.
+void host_canonical(int n, const int* vv, int* cv) {
+  if (n == 3) {
+    int a = vv[0], b = vv[1], c = vv[2];
+    if (a > b) std::swap(a, b);
+    if (b > c) std::swap(b, c);
+    if (a > b) std::swap(a, b);
+    cv[0] = a; cv[1] = b; cv[2] = c; cv[3] = -1;
+    return;
+  }
+  int lo = 0;
+  for (int k = 1; k < 4; ++k) if (vv[k] < vv[lo]) lo = k;
+  const int step = vv[(lo + 1) & 3] < vv[(lo + 3) & 3] ? 1 : 3;
+  for (int k = 0; k < 4; ++k) cv[k] = vv[(lo + step * k) & 3];
+}
+
+// Volume points (x, weight) of element e for Q points per direction.
+void host_vol_points(int typ, const double (*X)[3], int Q, const double* g01, const double* w01,
+                     std::vector<double>& pts, std::vector<double>& wts) {
+  pts.clear();
+  wts.clear();
+  for (int i3 = 0; i3 < Q; ++i3)
+    for (int i2 = 0; i2 < Q; ++i2)
+      for (int i1 = 0; i1 < Q; ++i1) {
+        const double t1 = g01[i1], t2 = g01[i2], t3 = g01[i3];
+        double J[3][3], x[3], wf;
+        if (typ == 0) {
+          const double l1 = t1 * (1 - t2) * (1 - t3), l2 = t2 * (1 - t3), l3 = t3;
+          for (int c = 0; c < 3; ++c) {
+            J[0][c] = X[1][c] - X[0][c];
+            J[1][c] = X[2][c] - X[0][c];
+            J[2][c] = X[3][c] - X[0][c];
+            x[c] = X[0][c] + l1 * J[0][c] + l2 * J[1][c] + l3 * J[2][c];
+          }
+          wf = w01[i1] * w01[i2] * w01[i3] * (1 - t2) * (1 - t3) * (1 - t3);
+        } else {
+          const double l1 = t1 * (1 - t2), l2 = t2, l0 = 1 - l1 - l2, z = t3;
+          const double lam[3] = {l0, l1, l2};
+          for (int c = 0; c < 3; ++c) {
+            double xs = 0, dz = 0;
+            for (int k = 0; k < 3; ++k) {
+              xs += lam[k] * ((1 - z) * X[k][c] + z * X[k + 3][c]);
+              dz += lam[k] * (X[k + 3][c] - X[k][c]);
+            }
+            x[c] = xs;
+            J[0][c] = (1 - z) * (X[1][c] - X[0][c]) + z * (X[4][c] - X[3][c]);
+            J[1][c] = (1 - z) * (X[2][c] - X[0][c]) + z * (X[5][c] - X[3][c]);
+            J[2][c] = dz;
+          }
+          wf = w01[i1] * w01[i2] * w01[i3] * (1 - t2);
+        }
+        const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                           J[1][0] * (J[0][1] * J[2][2] - J[0][2] * J[2][1]) +
+                           J[2][0] * (J[0][1] * J[1][2] - J[0][2] * J[1][1]);
+        for (int c = 0; c < 3; ++c) pts.push_back(x[c]);
+        wts.push_back(wf * std::fabs(det));
+      }
+}
+
+template <class T> hipError_t dev_copy(T** d, const T* h, size_t n) {
+  hipError_t e = hipMalloc((void**)d, n * sizeof(T) + 16);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*d, h, n * sizeof(T), hipMemcpyHostToDevice);
+}
+
+eg_status poly_setup(eg_poly_handle* h, const eg_poly_mesh* m) {
+  const int ne = m->n_elem, nv = m->n_vert;
+  std::vector<int32_t> nbr((size_t)ne * 5, 0), fcv((size_t)ne * 5 * 4, -1);
+  std::vector<int8_t> fsg((size_t)ne * 5, 1);
+  for (int e = 0; e < ne; ++e) {
+    const int typ = m->elem_type[e];
+    if (typ != 0 && typ != 1) { h->err = "element type must be 0 (tetrahedron) or 1 (prism)"; return EG_ERR_MESH; }
+    for (int k = 0; k < (typ == 0 ? 4 : 6); ++k) {
+      const int32_t v = m->elem_vert[(size_t)e * 6 + k];
+      if (v < 0 || v >= nv) { h->err = "element vertex index out of range"; return EG_ERR_MESH; }
+    }
+  }
+  // face matching through sorted vertex sets
+  std::map<std::array<int, 4>, std::pair<int, int>> open;
+  for (int e = 0; e < ne; ++e) {
+    const int typ = m->elem_type[e];
+    for (int lf = 0; lf < (typ == 0 ? 4 : 5); ++lf) {
+      int vv[4], n;
+      host_face(typ, &m->elem_vert[(size_t)e * 6], lf, vv, &n);
+      host_canonical(n, vv, &fcv[((size_t)e * 5 + lf) * 4]);
+      const int tg = m->bface_tag[(size_t)e * 5 + lf];
+      if (tg == 1) { nbr[(size_t)e * 5 + lf] = PB_WALL; continue; }
+      if (tg == 2) { nbr[(size_t)e * 5 + lf] = PB_FAR; continue; }
+      if (tg == 4) { nbr[(size_t)e * 5 + lf] = PB_SYM; continue; }
+      if (tg != 0) { h->err = "boundary tag must be 0, 1, 2 or 4"; return EG_ERR_MESH; }
+      std::array<int, 4> key{vv[0], vv[1], vv[2], n == 4 ? vv[3] : -1};
+      std::sort(key.begin(), key.begin() + n);
+      auto it = open.find(key);
+      if (it == open.end()) {
+        open[key] = {e, lf};
+      } else {
+        nbr[(size_t)e * 5 + lf] = it->second.first;
+        nbr[(size_t)it->second.first * 5 + it->second.second] = e;
+        open.erase(it);
+      }
+    }
+  }
+  if (!open.empty()) { h->err = "interior face without a matching neighbour"; return EG_ERR_MESH; }
+  // extents, centroids, outward signs and the MGS basis (volume rule of p_max)
+  const int N = pn(h->pmax), Q = h->pmax + 2;
+  double g01[8], w01[8];
+  eg::gauss_rule01(Q, g01, w01);
+  h->geo.assign((size_t)ne * 6, 0.0);
+  h->vol.assign(ne, 0.0);
+  h->S.assign((size_t)ne * N * N, 0.0);
+  std::vector<double> pts, wts, chi, phi;
+  for (int e = 0; e < ne; ++e) {
+    const int typ = m->elem_type[e], nvt = typ == 0 ? 4 : 6;
+    double X[6][3], lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, cE[3] = {0, 0, 0};
+    for (int k = 0; k < nvt; ++k)
+      for (int c = 0; c < 3; ++c) {
+        X[k][c] = m->xyz[(size_t)m->elem_vert[(size_t)e * 6 + k] * 3 + c];
+        lo[c] = std::min(lo[c], X[k][c]);
+        hi[c] = std::max(hi[c], X[k][c]);
+        cE[c] += X[k][c] / nvt;
+      }
+    {
+      double J[3][3];
+      for (int c = 0; c < 3; ++c) { J[0][c] = X[1][c] - X[0][c]; J[1][c] = X[2][c] - X[0][c]; J[2][c] = X[3][c] - X[0][c]; }
+      const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                         J[1][0] * (J[0][1] * J[2][2] - J[0][2] * J[2][1]) +
+                         J[2][0] * (J[0][1] * J[1][2] - J[0][2] * J[1][1]);
+      if (!(det > 0.0)) { h->err = "element with non-positive orientation"; return EG_ERR_MESH; }
+    }
+    host_vol_points(typ, X, Q, g01, w01, pts, wts);
+    const int nq = (int)wts.size();
+    double vol = 0.0, mx[3] = {0, 0, 0};
+    for (int q = 0; q < nq; ++q) {
+      vol += wts[q];
+      for (int c = 0; c < 3; ++c) mx[c] += wts[q] * pts[q * 3 + c];
+    }
+    double* g = &h->geo[(size_t)e * 6];
+    for (int c = 0; c < 3; ++c) {
+      g[c] = mx[c] / vol;
+      g[3 + c] = 0.5 * (hi[c] - lo[c]);
+    }
+    h->vol[e] = vol;
+    // monomial values at the points
+    chi.assign((size_t)N * nq, 0.0);
+    for (int j = 0; j < N; ++j) {
+      int ax, ay, az;
+      mono_exp(j, ax, ay, az);
+      for (int q = 0; q < nq; ++q) {
+        double c = 1.0;
+        for (int k = 0; k < ax; ++k) c *= (pts[q * 3] - g[0]) / g[3];
+        for (int k = 0; k < ay; ++k) c *= (pts[q * 3 + 1] - g[1]) / g[4];
+        for (int k = 0; k < az; ++k) c *= (pts[q * 3 + 2] - g[2]) / g[5];
+        chi[(size_t)j * nq + q] = c;
+      }
+    }
+    // modified Gram-Schmidt: phi_i starts as chi_i and loses its component
+    // along every finished phi_j in turn; S tracks phi in the chi basis
+    phi = chi;
+    double* Se = &h->S[(size_t)e * N * N];
+    for (int i = 0; i < N; ++i) Se[(size_t)i * N + i] = 1.0;
+    for (int i = 0; i < N; ++i) {
+      double* pi = &phi[(size_t)i * nq];
+      for (int j = 0; j < i; ++j) {
+        const double* pj = &phi[(size_t)j * nq];
+        double hij = 0.0;
+        for (int q = 0; q < nq; ++q) hij += wts[q] * pi[q] * pj[q];
+        for (int q = 0; q < nq; ++q) pi[q] -= hij * pj[q];
+        for (int k = 0; k <= j; ++k) Se[(size_t)i * N + k] -= hij * Se[(size_t)j * N + k];
+      }
+      double nn = 0.0;
+      for (int q = 0; q < nq; ++q) nn += wts[q] * pi[q] * pi[q];
+      if (!(nn > 0.0) || !std::isfinite(nn)) { h->err = "degenerate element basis"; return EG_ERR_MESH; }
+      const double sc = 1.0 / std::sqrt(nn);
+      for (int q = 0; q < nq; ++q) pi[q] *= sc;
+      for (int k = 0; k <= i; ++k) Se[(size_t)i * N + k] *= sc;
+    }
+    // outward sign of each face's canonical normal
+    for (int lf = 0; lf < (typ == 0 ? 4 : 5); ++lf) {
+      const int32_t* cv = &fcv[((size_t)e * 5 + lf) * 4];
+      const int n = cv[3] < 0 ? 3 : 4;
+      double C[4][3], cF[3] = {0, 0, 0};
+      for (int k = 0; k < n; ++k)
+        for (int c = 0; c < 3; ++c) { C[k][c] = m->xyz[(size_t)cv[k] * 3 + c]; cF[c] += C[k][c] / n; }
+      double a[3], b[3], nvv[3];
+      for (int c = 0; c < 3; ++c) {
+        a[c] = n == 3 ? C[1][c] - C[0][c] : 0.5 * (C[1][c] + C[2][c] - C[0][c] - C[3][c]);
+        b[c] = n == 3 ? C[2][c] - C[0][c] : 0.5 * (C[3][c] + C[2][c] - C[0][c] - C[1][c]);
+      }
+      nvv[0] = a[1] * b[2] - a[2] * b[1];
+      nvv[1] = a[2] * b[0] - a[0] * b[2];
+      nvv[2] = a[0] * b[1] - a[1] * b[0];
+      const double s = nvv[0] * (cF[0] - cE[0]) + nvv[1] * (cF[1] - cE[1]) + nvv[2] * (cF[2] - cE[2]);
+      fsg[(size_t)e * 5 + lf] = s < 0.0 ? -1 : 1;
+    }
+  }
+  // reference tables of every order
+  std::vector<double> tab;
+  for (int p = 0; p <= h->pmax; ++p) {
+    const int q = p + 2;
+    double x[8], w[8];
+    eg::gauss_rule01(q, x, w);
+    tab.clear();
+    const int nv3 = q * q * q, nv2 = q * q;
+    for (int i3 = 0; i3 < q; ++i3)
+      for (int i2 = 0; i2 < q; ++i2)
+        for (int i1 = 0; i1 < q; ++i1) {
+          const double t1 = x[i1], t2 = x[i2], t3 = x[i3];
+          tab.insert(tab.end(), {t1 * (1 - t2) * (1 - t3), t2 * (1 - t3), t3,
+                                 w[i1] * w[i2] * w[i3] * (1 - t2) * (1 - t3) * (1 - t3)});
+        }
+    for (int i3 = 0; i3 < q; ++i3)
+      for (int i2 = 0; i2 < q; ++i2)
+        for (int i1 = 0; i1 < q; ++i1) {
+          const double t1 = x[i1], t2 = x[i2], t3 = x[i3];
+          tab.insert(tab.end(), {t1 * (1 - t2), t2, t3, w[i1] * w[i2] * w[i3] * (1 - t2)});
+        }
+    for (int i2 = 0; i2 < q; ++i2)
+      for (int i1 = 0; i1 < q; ++i1) tab.insert(tab.end(), {x[i1] * (1 - x[i2]), x[i2], w[i1] * w[i2] * (1 - x[i2])});
+    for (int i2 = 0; i2 < q; ++i2)
+      for (int i1 = 0; i1 < q; ++i1) tab.insert(tab.end(), {x[i1], x[i2], w[i1] * w[i2]});
+    if (dev_copy(&h->d_rule[p], tab.data(), tab.size()) != hipSuccess) { h->err = "rule upload failed"; return EG_ERR_HIP; }
+    h->rule[p].tet = h->d_rule[p];
+    h->rule[p].pri = h->d_rule[p] + 4 * nv3;
+    h->rule[p].tri = h->d_rule[p] + 8 * nv3;
+    h->rule[p].quad = h->d_rule[p] + 8 * nv3 + 3 * nv2;
+  }
+  std::vector<int32_t> ev(m->elem_vert, m->elem_vert + (size_t)ne * 6);
+  for (int e = 0; e < ne; ++e)
+    if (m->elem_type[e] == 0) ev[(size_t)e * 6 + 4] = ev[(size_t)e * 6 + 5] = 0;
+  if (dev_copy(&h->d_xyz, m->xyz, (size_t)nv * 3) != hipSuccess || dev_copy(&h->d_ev, ev.data(), ev.size()) != hipSuccess ||
+      dev_copy(&h->d_typ, m->elem_type, (size_t)ne) != hipSuccess ||
+      dev_copy(&h->d_nbr, nbr.data(), nbr.size()) != hipSuccess ||
+      dev_copy(&h->d_fcv, fcv.data(), fcv.size()) != hipSuccess ||
+      dev_copy(&h->d_fsg, fsg.data(), fsg.size()) != hipSuccess ||
+      dev_copy(&h->d_geo, h->geo.data(), h->geo.size()) != hipSuccess ||
+      dev_copy(&h->d_S, h->S.data(), h->S.size()) != hipSuccess) {
+    h->err = "device allocation or upload failed";
+    return EG_ERR_ALLOC;
+  }
+  if (hipMalloc((void**)&h->d_a, sizeof(double) * (size_t)ne * PV * N) != hipSuccess) {
+    h->err = "device allocation failed";
+    return EG_ERR_ALLOC;
+  }
+  return EG_OK;
+}
+
+PolyDev dev_of(const eg_poly_handle* h) {
+  PolyDev M;
+  M.xyz = h->d_xyz;
+  M.ev = h->d_ev;
+  M.typ = h->d_typ;
+  M.nbr = h->d_nbr;
+  M.fcv = h->d_fcv;
+  M.fsg = h->d_fsg;
+  M.geo = h->d_geo;
+  M.S = h->d_S;
+  M.ne = h->ne;
+  M.nmax = h->nmax;
+  return M;
+}
+
+template <int P> hipError_t launch_residual(eg_poly_handle* h, const double* u, double* r) {
+  const PolyDev M = dev_of(h);
+  const long long n = (long long)h->ne * pn(P);
+  hipLaunchKernelGGL(k_poly_mono<P>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->st, M, u, h->d_a);
+  const unsigned blocks = 8u * (unsigned)((h->ne + 7) / 8);
+  hipLaunchKernelGGL(k_poly_residual<P>, dim3(blocks), dim3(64), 0, h->st, M, h->rule[P], h->gas,
+                     (const double*)h->d_a, r);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+eg_status eg_poly_init(const eg_poly_mesh* mesh, const eg_params* prm, void* hip_stream, eg_poly_handle** out) {
+  if (!out) return EG_ERR_ARG;
+  *out = nullptr;
+  if (!mesh || !prm || !mesh->xyz || !mesh->elem_type || !mesh->elem_vert || !mesh->bface_tag) return EG_ERR_ARG;
+  if (mesh->n_vert <= 0 || mesh->n_elem <= 0 || mesh->n_elem > (1 << 26)) return EG_ERR_ARG;
+  if (prm->p_max < 0 || prm->p_max > PMAX_POLY || !(prm->gamma > 1.0) || !(prm->mach >= 0.0) ||
+      (prm->flux != EG_FLUX_RUSANOV && prm->flux != EG_FLUX_ROE))
+    return EG_ERR_ARG;
+  eg_poly_handle* h = new (std::nothrow) eg_poly_handle;
+  if (!h) return EG_ERR_ALLOC;
+  *out = h;
+  hipGetDevice(&h->dev);
+  h->st = (hipStream_t)hip_stream;
+  h->pmax = prm->p_max;
+  h->ne = mesh->n_elem;
+  h->nv = mesh->n_vert;
+  h->nmax = pn(prm->p_max);
+  const double al = prm->alpha_deg * M_PI / 180.0, be = prm->beta_deg * M_PI / 180.0;
+  const double v[3] = {prm->mach * std::cos(al) * std::cos(be), prm->mach * std::sin(al) * std::cos(be),
+                       prm->mach * std::sin(be)};
+  h->gas.g = prm->gamma;
+  h->gas.flux = prm->flux;
+  h->gas.Uinf[0] = 1.0;
+  double ke = 0.0;
+  for (int a = 0; a < 3; ++a) { h->gas.Uinf[1 + a] = v[a]; ke += v[a] * v[a]; }
+  h->gas.Uinf[4] = 1.0 / (prm->gamma * (prm->gamma - 1.0)) + 0.5 * ke;
+  return poly_setup(h, mesh);
+}
+
+void eg_poly_free(eg_poly_handle* h) {
+  if (!h) return;
+  int cur = 0;
+  hipGetDevice(&cur);
+  hipSetDevice(h->dev);
+  void* bufs[] = {h->d_xyz, h->d_ev, h->d_typ, h->d_nbr, h->d_fcv, h->d_fsg, h->d_geo, h->d_S, h->d_a};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  for (auto* b : h->d_rule)
+    if (b) hipFree(b);
+  hipSetDevice(cur);
+  delete h;
+}
+
+const char* eg_poly_last_error(const eg_poly_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+eg_status eg_poly_freestream(eg_poly_handle* h, int p, double* u_dev) {
+  if (!h || !u_dev || p < 0 || p > h->pmax) return EG_ERR_ARG;
+  const long long n = (long long)h->ne * PV * pn(p);
+  hipLaunchKernelGGL(k_poly_freestream, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->st, h->ne, pn(p),
+                     h->nmax, (const double*)h->d_S, h->gas, u_dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
+  return EG_OK;
+}
+
+eg_status eg_poly_residual(eg_poly_handle* h, int p, const double* u_dev, double* r_dev) {
+  if (!h || !u_dev || !r_dev || p < 0 || p > h->pmax || (const double*)r_dev == u_dev) return EG_ERR_ARG;
+  hipError_t e;
+  switch (p) {
+    case 0: e = launch_residual<0>(h, u_dev, r_dev); break;
+    case 1: e = launch_residual<1>(h, u_dev, r_dev); break;
+    case 2: e = launch_residual<2>(h, u_dev, r_dev); break;
+    default: e = launch_residual<3>(h, u_dev, r_dev); break;
+  }
+  if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
+  return EG_OK;
+}
+
+eg_status eg_poly_basis(const eg_poly_handle* h, double* S_host, double* xc_host, double* L_host, double* vol_host) {
+  if (!h) return EG_ERR_ARG;
+  if (S_host) std::memcpy(S_host, h->S.data(), h->S.size() * sizeof(double));
+  for (int e = 0; e < h->ne; ++e) {
+    for (int c = 0; c < 3; ++c) {
+      if (xc_host) xc_host[e * 3 + c] = h->geo[(size_t)e * 6 + c];
+      if (L_host) L_host[e * 3 + c] = h->geo[(size_t)e * 6 + 3 + c];
+    }
+    if (vol_host) vol_host[e] = h->vol[e];
+  }
+  return EG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+"""GPU parity of the tetrahedron / prism path (Cartesian P_p basis
+orthonormalised by MGS, Section 3.2) against the FP64 oracle, through the
+C ABI (eg_poly_*).
+
+Tolerances.  Both sides compute in FP64; the library contracts to FMA,
+evaluates the state from monomial coefficients a = S^T u and forms the
+residual as S times monomial moments, while the oracle evaluates psi = S chi
+at every point.  The two orders of summation differ by a few ulps times the
+size of S (entries up to ~1e2 on these elements) and the cancellation
+between volume and face terms, so residuals are compared at 1e-11 of their
+largest entry and the set-up (S, centroids, extents, volumes) at 1e-12."""
+
+import numpy as np
+import pytest
+
+import oracle
+from eg_inputs import box_poly, sphere_poly
+from tests.gpu_util import to_dev, to_host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _tagged(m, seed):
+    """Boundary faces re-tagged at random among wall, far-field and symmetry."""
+    rng = np.random.default_rng(seed)
+    t = m.bface_tag.copy()
+    b = t != 0
+    t[b] = rng.choice(np.array([1, 2, 4], dtype=np.int8), size=int(b.sum()))
+    m.bface_tag = t
+    return m
+
+
+def _state(O, p, seed, amp=0.03):
+    """Free stream plus a seeded perturbation scaled by sqrt|E| / 4^deg."""
+    rng = np.random.default_rng(seed)
+    u = O.freestream(p)
+    vol, _, _ = O.geometry()
+    deg = np.sum(oracle.poly_monomials(p), axis=1)
+    u = u + amp * rng.uniform(-1, 1, u.shape) * (np.sqrt(vol)[:, None, None] * 0.25 ** deg[None, None, :])
+    assert np.all(np.isfinite(O.residual(p, u)))
+    return u
+
+
+MESHES = [
+    ("box3-mixed-skew", lambda: _tagged(box_poly(3, "mixed", tag=2, skew=0.15, seed=1), 11)),
+    ("box2-tet-skew", lambda: _tagged(box_poly(2, "tet", tag=2, skew=0.2, seed=4), 12)),
+    ("box2-prism", lambda: _tagged(box_poly(2, "prism", tag=2), 13)),
+    ("sphere2-1p1t", lambda: sphere_poly(2, 1, 1)),
+    ("one-hex-6tets", lambda: box_poly(1, "tet", tag=2)),
+]
+
+
+@pytest.mark.parametrize("name,make", MESHES, ids=[m[0] for m in MESHES])
+@pytest.mark.parametrize("flux", ["rusanov", "roe"])
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+def test_poly_residual_parity(name, make, flux, p):
+    import paper_1807_01151_amd as P
+    m = make()
+    O = oracle.PolyOracle(m, 3, alpha_deg=8.0, beta_deg=-4.0, flux=flux)
+    S = P.PolySolver(m, 3, alpha_deg=8.0, beta_deg=-4.0, flux=flux)
+    u = _state(O, p, seed=100 + p)
+    r_o = O.residual(p, u)
+    r_g = to_host(S.residual(p, to_dev(u)))
+    err = rel_err(r_g, r_o)
+    print(f"{name} {flux} p={p}: residual rel err {err:.2e}", flush=True)
+    assert err < 1e-11, err
+
+
+def test_poly_setup_matches_oracle():
+    import paper_1807_01151_amd as P
+    m = _tagged(box_poly(3, "mixed", tag=2, skew=0.15, seed=1), 11)
+    O = oracle.PolyOracle(m, 3)
+    S = P.PolySolver(m, 3)
+    Sg, xg, Lg, vg = S.basis()
+    vo, xo, Lo = O.geometry()
+    assert rel_err(Sg, O.basis_S()) < 1e-12
+    assert rel_err(xg, xo) < 1e-13 and rel_err(Lg, Lo) < 1e-15 and rel_err(vg, vo) < 1e-13
+
+
+def test_poly_freestream_and_levels():
+    """The library's free stream is the oracle's, preserved at every level;
+    a level-p residual uses the leading block of the p_max basis."""
+    import paper_1807_01151_amd as P
+    m = box_poly(3, "mixed", tag=2, skew=0.15, seed=1)
+    O = oracle.PolyOracle(m, 3, alpha_deg=10.0, beta_deg=5.0)
+    S = P.PolySolver(m, 3, alpha_deg=10.0, beta_deg=5.0)
+    for p in range(4):
+        uf = S.freestream(p)
+        assert rel_err(to_host(uf), O.freestream(p)) < 1e-14
+        assert np.abs(to_host(S.residual(p, uf))).max() < 1e-12
+
+
+def test_poly_sphere_fullsize_parity():
+    """The 13 824-element sphere shell (9216 tetrahedra, 4608 prisms) at
+    p = 3, Roe flux, every element compared."""
+    import paper_1807_01151_amd as P
+    m = sphere_poly(8, 6, 4)
+    O = oracle.PolyOracle(m, 3, alpha_deg=2.0, flux="roe")
+    S = P.PolySolver(m, 3, alpha_deg=2.0, flux="roe")
+    u = _state(O, 3, seed=7)
+    r_o = O.residual(3, u)
+    r_g = to_host(S.residual(3, to_dev(u)))
+    err = rel_err(r_g, r_o)
+    print(f"sphere 13824 p=3 roe: residual rel err {err:.2e}", flush=True)
+    assert err < 1e-11, err
+
+
+def test_poly_errors():
+    import torch
+    import paper_1807_01151_amd as P
+    m = box_poly(2, "tet", tag=2)
+    bad = box_poly(2, "tet", tag=2)
+    bad.bface_tag = bad.bface_tag.copy()
+    bad.bface_tag[bad.bface_tag == 2] = 0  # boundary faces claimed interior: unmatched
+    with pytest.raises(P.EgError, match="EG_ERR_MESH"):
+        P.PolySolver(bad, 1)
+    with pytest.raises(P.EgError, match="EG_ERR_ARG"):
+        P.PolySolver(m, 4)
+    S = P.PolySolver(m, 2)
+    with pytest.raises(ValueError):
+        S.residual(3, S.empty(2))
+    with pytest.raises(ValueError):
+        S.residual(1, torch.zeros(m.n_elem, 5, 10, dtype=torch.float64, device="cuda"))
+    u = S.freestream(1)
+    with pytest.raises(ValueError):
+        S.residual(1, u, out=u)
