@@ -31,6 +31,7 @@
 
 #include "../../include/eg.h"
 #include "eg_common.h"
+#include "eg_device.h"
 #include "eg_physics.h"
 
 namespace eg {
@@ -68,8 +69,8 @@ struct PolyDev {
   const int32_t* fcv;    // [E][5][4] canonical face vertices (-1 pads a triangle)
   const int8_t* fsg;     // [E][5] +1 / -1: orientation of the canonical normal
   const double* geo;     // [E][6]: xc, L
-  const double* S;       // [E][nmax][nmax]
-  int ne, nmax;
+  const double* S;       // [E][spk]: row-major packed lower triangle of S, spk = Nmax (Nmax+1) / 2
+  int ne, spk;
 };
 
 // Reference tables of one order: tetrahedron and prism volume points
@@ -87,28 +88,25 @@ __device__ __forceinline__ double det3(const double* c0, const double* c1, const
          c2[0] * (c0[1] * c1[2] - c0[2] * c1[1]);
 }
 
-// a[e][v][j] = sum_{i >= j} S[e][i][j] u[e][v][i] (monomial coefficients);
-// one thread per (e, j), so each column of S is read once for all five
-// variables (consecutive threads read consecutive entries of a row of S).
+// a[e][v][j] = sum_{i >= j} S[e][i][j] u[e][v][i] (monomial coefficients).
+// One wavefront per element: the element's packed triangle of S (the level-p
+// block is its leading N(N+1)/2 entries) and its state are staged in LDS
+// with contiguous loads, then the lanes take the outputs (v, j).
 template <int P>
-__global__ __launch_bounds__(256) void k_poly_mono(PolyDev M, const double* __restrict__ u, double* __restrict__ a) {
-  constexpr int N = pn(P);
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)M.ne * N) return;
-  const int j = (int)(idx % N);
-  const long long e = idx / N;
-  const double* Se = M.S + (size_t)e * M.nmax * M.nmax;
-  const double* ue = u + (size_t)e * PV * N;
-  double s[PV];
-#pragma unroll
-  for (int v = 0; v < PV; ++v) s[v] = 0.0;
-  for (int i = j; i < N; ++i) {
-    const double c = Se[(size_t)i * M.nmax + j];
-#pragma unroll
-    for (int v = 0; v < PV; ++v) s[v] += c * ue[v * N + i];
+__global__ __launch_bounds__(64) void k_poly_mono(PolyDev M, const double* __restrict__ u, double* __restrict__ a) {
+  constexpr int N = pn(P), NO = PV * N, NS = N * (N + 1) / 2;
+  __shared__ double sS[NS], su[NO];
+  const int e = blockIdx.x, t = threadIdx.x;
+  if (e >= M.ne) return;
+  for (int k = t; k < NS; k += 64) sS[k] = M.S[(size_t)e * M.spk + k];
+  for (int k = t; k < NO; k += 64) su[k] = u[(size_t)e * NO + k];
+  __syncthreads();
+  for (int o = t; o < NO; o += 64) {
+    const int v = o / N, j = o % N;
+    double s = 0.0;
+    for (int i = j; i < N; ++i) s += sS[i * (i + 1) / 2 + j] * su[v * N + i];
+    a[(size_t)e * NO + o] = s;
   }
-#pragma unroll
-  for (int v = 0; v < PV; ++v) a[((size_t)e * PV + v) * N + j] = s[v];
 }
 
 // Scaled coordinates and monomial powers at a point.
@@ -190,14 +188,18 @@ __device__ __forceinline__ void mono_values(const double (*pw)[P + 1], double* o
 //  1. volume points, in chunks of 64 (one per lane): state from the monomial
 //     coefficients, Euler fluxes; LDS gets G[q][d*5+v] = w F_dv / L_d and the
 //     monomials of degree < p at the point;
-//  2. after each chunk, flux moments M[d*5+v][k] += sum_q G[q][.] chi_k(q)
-//     (lanes over (d*5+v, k), accumulated in registers) -- since
+//  2. after each chunk, flux moments M[d*5+v][k] += sum_q G[q][.] chi_k(q),
+//     accumulated in registers over the chunks: at p = 3 on the FP64 matrix
+//     cores (one 16 x 16 tile, 16 steps of 4 points), at p <= 2 by the lanes
+//     over (d*5+v, k) -- since
 //     grad chi_j = (a_d chi_{j-e_d} / L_d)_d, they carry the whole volume term;
 //  3. face points of every face, in chunks of 64: own and neighbour (or
 //     ghost) traces, the numerical flux; LDS gets w F~_v and all monomials at
 //     the point, in the space phase 1 used;
-//  4. after each chunk, m_vj -= sum_q w F~_v chi_j (lanes over (v, j)); then
-//     m_vj += sum_d a_d M[d*5+v][j-e_d];
+//  4. after each chunk, the face moments sum_q w F~_v chi_j (p = 3: matrix
+//     cores, rows v, one 16-column tile per 16 modes; p <= 2: lanes over
+//     (v, j)); then
+//     m_vj = sum_d a_d M[d*5+v][j-e_d] - face moments;
 //  5. R = S m.
 // Blocks are mapped to elements so that each XCD (blocks b, b+8, ...) gets a
 // contiguous range of elements, whose neighbours' coefficients then share
@@ -206,10 +208,10 @@ template <int P>
 __global__ __launch_bounds__(64) void k_poly_residual(PolyDev M, PolyRule R, eg::Gas gas,
                                                      const double* __restrict__ a_all, double* __restrict__ r) {
   constexpr int N = pn(P), NL = pn(P - 1), NL1 = NL > 0 ? NL : 1, Q = P + 2, QV = Q * Q * Q, QF = Q * Q;
-  constexpr int NO = PV * N, NM = 15 * NL;
+  constexpr int NO = PV * N;
+  static_assert(NL <= 16 && 15 <= 16, "one 16 x 16 tile of flux moments");
   constexpr int CH = 64;  // points per chunk: one per lane
   constexpr int W1 = 15 + NL, W3 = PV + N;
-  constexpr int MPL = (NM + 63) / 64 > 0 ? (NM + 63) / 64 : 1, OPL = (NO + 63) / 64;
   __shared__ double sbuf[CH * (W1 > W3 ? W1 : W3)];
   __shared__ double sa[NO], sm[NO], sM[15 * NL1];
   __shared__ double sn[5][NO];
@@ -238,9 +240,16 @@ __global__ __launch_bounds__(64) void k_poly_residual(PolyDev M, PolyRule R, eg:
   // ---- 1 + 2. volume points and flux moments
   double* sG = sbuf;               // [CH][15]
   double* sC = sbuf + CH * 15;     // [CH][NL]
-  double accM[MPL];
+  const int li = t & 15, lk = t >> 4;
+  // the contractions run on the matrix cores at p = 3; at p <= 2 the padded
+  // 16 x 16 tiles cost more registers (one wavefront per SIMD less) than
+  // they save, and the lanes contract over the points directly
+  constexpr bool MF = P >= 3;
+  constexpr int NM = 15 * NL, MPL = (NM + 63) / 64 > 0 ? (NM + 63) / 64 : 1, OPL = (NO + 63) / 64;
+  eg::dbl4_t accM = {0.0, 0.0, 0.0, 0.0};
+  double accV[MF ? 1 : MPL];
 #pragma unroll
-  for (int m = 0; m < MPL; ++m) accM[m] = 0.0;
+  for (int m = 0; m < (MF ? 1 : MPL); ++m) accV[m] = 0.0;
   for (int q0 = 0; NL > 0 && q0 < QV; q0 += CH) {
     // keeps the coefficient reads from LDS inside the loop (hoisted, they
     // would hold V N registers for the whole loop)
@@ -297,27 +306,53 @@ __global__ __launch_bounds__(64) void k_poly_residual(PolyDev M, PolyRule R, eg:
       for (int k = 0; k < NL; ++k) sC[t * NL1 + k] = cv_[k];
     }
     __syncthreads();
+    // M (16 x 16, rows d*5+v, columns k) += G^T (16 x 64) C (64 x 16) on the
+    // FP64 matrix cores: at step st lane l supplies G[4 st + l/16][l%16] and
+    // C[4 st + l/16][l%16] (zero past the chunk, row 15 and column NL)
     const int nq = QV - q0 < CH ? QV - q0 : CH;
+    if constexpr (MF) {
 #pragma unroll
-    for (int m = 0; m < MPL; ++m) {
-      const int o = t + 64 * m;
-      if (o < NM) {
-        const int c = o / NL1, k = o % NL1;
-        double acc = accM[m];
-        for (int qq = 0; qq < nq; ++qq) acc += sG[qq * 15 + c] * sC[qq * NL1 + k];
-        accM[m] = acc;
+      for (int st = 0; st < CH / 4; ++st) {
+        const int qq = 4 * st + lk;
+        const double av = (li < 15 && qq < nq) ? sG[qq * 15 + li] : 0.0;
+        const double bv = (li < NL && qq < nq) ? sC[qq * NL1 + li] : 0.0;
+        accM = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accM, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < MPL; ++m) {
+        const int o = t + 64 * m;
+        if (o < NM) {
+          const int c = o / NL1, k = o % NL1;
+          double acc = accV[m];
+          for (int qq = 0; qq < nq; ++qq) acc += sG[qq * 15 + c] * sC[qq * NL1 + k];
+          accV[m] = acc;
+        }
       }
     }
   }
+  if constexpr (MF) {
+    // lane l holds rows l/16 + 4 r of column l%16
 #pragma unroll
-  for (int m = 0; m < MPL; ++m)
-    if (t + 64 * m < NM) sM[t + 64 * m] = accM[m];
+    for (int rr = 0; rr < 4; ++rr) {
+      const int c = lk + 4 * rr;
+      if (c < 15 && li < NL) sM[c * NL1 + li] = accM[rr];
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < MPL; ++m)
+      if (t + 64 * m < NM) sM[t + 64 * m] = accV[m];
+  }
   // ---- 3 + 4. face points of all faces and their moments
   double* sH = sbuf;               // [CH][5]
   double* sX = sbuf + CH * PV;     // [CH][N]
-  double accF[OPL];
+  constexpr int NT = MF ? (N + 15) / 16 : 1;  // 16-column tiles of the face moments
+  eg::dbl4_t accF[NT];
 #pragma unroll
-  for (int m = 0; m < OPL; ++m) accF[m] = 0.0;
+  for (int T = 0; T < NT; ++T) accF[T] = eg::dbl4_t{0.0, 0.0, 0.0, 0.0};
+  double accW[MF ? 1 : OPL];
+#pragma unroll
+  for (int m = 0; m < (MF ? 1 : OPL); ++m) accW[m] = 0.0;
   const int nfq = nf * QF;
   for (int q0 = 0; q0 < nfq; q0 += CH) {
     asm volatile("" ::: "memory");
@@ -386,45 +421,73 @@ __global__ __launch_bounds__(64) void k_poly_residual(PolyDev M, PolyRule R, eg:
     for (int j = 0; j < N; ++j) sX[t * N + j] = xv_[j];
     }
     __syncthreads();
+    // F (16 x 16 per tile, rows v, columns j) += H^T (16 x 64) X (64 x 16)
     const int nq = nfq - q0 < CH ? nfq - q0 : CH;
+    if constexpr (MF) {
 #pragma unroll
-    for (int m = 0; m < OPL; ++m) {
-      const int o = t + 64 * m;
-      if (o < NO) {
-        const int v = o / N, j = o % N;
-        double acc = accF[m];
-        for (int qq = 0; qq < nq; ++qq) acc -= sH[qq * PV + v] * sX[qq * N + j];
-        accF[m] = acc;
+      for (int st = 0; st < CH / 4; ++st) {
+        const int qq = 4 * st + lk;
+        const double av = (li < PV && qq < nq) ? sH[qq * PV + li] : 0.0;
+#pragma unroll
+        for (int T = 0; T < NT; ++T) {
+          const int j = 16 * T + li;
+          const double bv = (j < N && qq < nq) ? sX[qq * N + j] : 0.0;
+          accF[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, accF[T], 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < OPL; ++m) {
+        const int o = t + 64 * m;
+        if (o < NO) {
+          const int v = o / N, j = o % N;
+          double acc = accW[m];
+          for (int qq = 0; qq < nq; ++qq) acc += sH[qq * PV + v] * sX[qq * N + j];
+          accW[m] = acc;
+        }
       }
     }
   }
   __syncthreads();  // sM complete (written before the face loop)
+  // m_vj = sum_d a_d M[d*5+v][j-e_d] - (face moments)_vj
+  auto finish = [&](int v, int j, double fm) {
+    double acc = -fm;
 #pragma unroll
-  for (int m = 0; m < OPL; ++m) {
-    const int o = t + 64 * m;
-    if (o < NO) {
-      const int v = o / N, j = o % N;
-      double acc = accF[m];
+    for (int d = 0; d < 3; ++d) {
+      const int lo = kMono.lo[j][d];
+      if (lo >= 0) acc += (double)kMono.ex[j][d] * sM[(d * 5 + v) * NL1 + lo];
+    }
+    sm[v * N + j] = acc;
+  };
+  if constexpr (MF) {
+    // lane l holds rows v = l/16 + 4 r of column j = 16 T + l%16
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int lo = kMono.lo[j][d];
-        if (lo >= 0) acc += (double)kMono.ex[j][d] * sM[(d * 5 + v) * NL1 + lo];
+    for (int T = 0; T < NT; ++T)
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr) {
+        const int v = lk + 4 * rr, j = 16 * T + li;
+        if (v < PV && j < N) finish(v, j, accF[T][rr]);
       }
-      sm[o] = acc;
+  } else {
+#pragma unroll
+    for (int m = 0; m < OPL; ++m) {
+      const int o = t + 64 * m;
+      if (o < NO) finish(o / N, o % N, accW[m]);
     }
   }
   __syncthreads();
   // ---- 5. R = S m
-  const double* Se = M.S + (size_t)e * M.nmax * M.nmax;
+  const double* Se = M.S + (size_t)e * M.spk;
   for (int o = t; o < NO; o += 64) {
     const int v = o / N, i = o % N;
+    const double* Si = Se + i * (i + 1) / 2;
     double s = 0.0;
-    for (int j = 0; j <= i; ++j) s += Se[(size_t)i * M.nmax + j] * sm[v * N + j];
+    for (int j = 0; j <= i; ++j) s += Si[j] * sm[v * N + j];
     r[(size_t)e * NO + o] = s;
   }
 }
 
-__global__ void k_poly_freestream(int ne, int N, int nmax, const double* __restrict__ S, eg::Gas gas,
+__global__ void k_poly_freestream(int ne, int N, int spk, const double* __restrict__ S, eg::Gas gas,
                                   double* __restrict__ u) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long long)ne * PV * N) return;
@@ -432,7 +495,7 @@ __global__ void k_poly_freestream(int ne, int N, int nmax, const double* __restr
   const long long ev = idx / N;
   const int v = (int)(ev % PV);
   const long long e = ev / PV;
-  u[idx] = i == 0 ? gas.Uinf[v] / S[(size_t)e * nmax * nmax] : 0.0;
+  u[idx] = i == 0 ? gas.Uinf[v] / S[(size_t)e * spk] : 0.0;
 }
 
 }  // namespace
@@ -700,6 +763,11 @@ eg_status poly_setup(eg_poly_handle* h, const eg_poly_mesh* m) {
     h->rule[p].tri = h->d_rule[p] + 8 * nv3;
     h->rule[p].quad = h->d_rule[p] + 8 * nv3 + 3 * nv2;
   }
+  // S packed row by row (lower triangle): the level-p block is a prefix
+  std::vector<double> spk((size_t)ne * (N * (N + 1) / 2));
+  for (int e = 0; e < ne; ++e)
+    for (int i = 0, k = 0; i < N; ++i)
+      for (int j = 0; j <= i; ++j, ++k) spk[(size_t)e * (N * (N + 1) / 2) + k] = h->S[((size_t)e * N + i) * N + j];
   std::vector<int32_t> ev(m->elem_vert, m->elem_vert + (size_t)ne * 6);
   for (int e = 0; e < ne; ++e)
     if (m->elem_type[e] == 0) ev[(size_t)e * 6 + 4] = ev[(size_t)e * 6 + 5] = 0;
@@ -709,7 +777,7 @@ eg_status poly_setup(eg_poly_handle* h, const eg_poly_mesh* m) {
       dev_copy(&h->d_fcv, fcv.data(), fcv.size()) != hipSuccess ||
       dev_copy(&h->d_fsg, fsg.data(), fsg.size()) != hipSuccess ||
       dev_copy(&h->d_geo, h->geo.data(), h->geo.size()) != hipSuccess ||
-      dev_copy(&h->d_S, h->S.data(), h->S.size()) != hipSuccess) {
+      dev_copy(&h->d_S, spk.data(), spk.size()) != hipSuccess) {
     h->err = "device allocation or upload failed";
     return EG_ERR_ALLOC;
   }
@@ -731,14 +799,13 @@ PolyDev dev_of(const eg_poly_handle* h) {
   M.geo = h->d_geo;
   M.S = h->d_S;
   M.ne = h->ne;
-  M.nmax = h->nmax;
+  M.spk = h->nmax * (h->nmax + 1) / 2;
   return M;
 }
 
 template <int P> hipError_t launch_residual(eg_poly_handle* h, const double* u, double* r) {
   const PolyDev M = dev_of(h);
-  const long long n = (long long)h->ne * pn(P);
-  hipLaunchKernelGGL(k_poly_mono<P>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->st, M, u, h->d_a);
+  hipLaunchKernelGGL(k_poly_mono<P>, dim3((unsigned)h->ne), dim3(64), 0, h->st, M, u, h->d_a);
   const unsigned blocks = 8u * (unsigned)((h->ne + 7) / 8);
   hipLaunchKernelGGL(k_poly_residual<P>, dim3(blocks), dim3(64), 0, h->st, M, h->rule[P], h->gas,
                      (const double*)h->d_a, r);
@@ -798,7 +865,7 @@ eg_status eg_poly_freestream(eg_poly_handle* h, int p, double* u_dev) {
   if (!h || !u_dev || p < 0 || p > h->pmax) return EG_ERR_ARG;
   const long long n = (long long)h->ne * PV * pn(p);
   hipLaunchKernelGGL(k_poly_freestream, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->st, h->ne, pn(p),
-                     h->nmax, (const double*)h->d_S, h->gas, u_dev);
+                     h->nmax * (h->nmax + 1) / 2, (const double*)h->d_S, h->gas, u_dev);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
   return EG_OK;
