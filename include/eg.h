@@ -446,6 +446,28 @@ eg_status eg_poly_freestream(eg_poly_handle* h, int p, double* u_dev);
  * Enqueued on the handle's stream, no synchronisation. */
 eg_status eg_poly_residual(eg_poly_handle* h, int p, const double* u_dev, double* r_dev);
 
+/* Pseudo-time step (Section 4, eq. (x3d)), the definition of the
+ * hexahedra: dtau_E = cfl h_E / ((2p+1)(|v| + c)), h_E = 2 d |E| / |dE|,
+ * v and c from the cell-mean state u_{E,.,0} psi_0.  u_dev: n_elem * 5 * N_p
+ * doubles, dtau_dev: n_elem doubles (device).  No synchronisation. */
+eg_status eg_poly_timestep(eg_poly_handle* h, int p, double cfl, const double* u_dev, double* dtau_dev);
+
+/* Density-residual norm (Section 4, the norm under eq. (cfl)):
+ * (1/|Omega|) (sum over elements and modes of r_{E,0,i}^2)^(1/2), the L2
+ * norm of the density residual in the orthonormal basis.  r_dev: level-p
+ * vector (device); *rn_host receives the value.  Synchronises the stream;
+ * uses a small buffer of the handle, so calls on one handle must not
+ * overlap. */
+eg_status eg_poly_rnorm(eg_poly_handle* h, int p, const double* r_dev, double* rn_host);
+
+/* Transfers between levels pc <= pf (Section 2.4, modal truncation): with
+ * the hierarchical basis, restriction copies the leading N_pc modes of each
+ * [elem][var] row (yc_dev: level pc, xf_dev: level pf), prolongation adds
+ * the coarse vector to those leading modes (zero padding).  Device buffers,
+ * distinct; no synchronisation. */
+eg_status eg_poly_restrict(eg_poly_handle* h, int pf, int pc, const double* xf_dev, double* yc_dev);
+eg_status eg_poly_prolong_add(eg_poly_handle* h, int pc, int pf, const double* yc_dev, double* xf_dev);
+
 /* Copies of the set-up (host buffers): S [n_elem][N_pmax][N_pmax] (row i
  * holds S_ij, j <= i), xc [n_elem][3], L [n_elem][3], vol [n_elem]; any
  * pointer may be NULL. */

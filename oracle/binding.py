@@ -110,6 +110,10 @@ def lib():
         L.porc_residual_complex.argtypes = [C.c_void_p, C.c_int, _d, _d, _d, _d]
         L.porc_mms_project.argtypes = [C.c_void_p, C.c_int, _d]
         L.porc_mms_forcing.argtypes = [C.c_void_p, C.c_int, _d]
+        L.porc_timestep.argtypes = [C.c_void_p, C.c_int, C.c_double, _d, _d]
+        L.porc_rnorm.restype = C.c_double
+        L.porc_rnorm.argtypes = [C.c_void_p, C.c_int, _d]
+        L.porc_surface.argtypes = [C.c_void_p, _d, _d]
         _lib = L
     return _lib
 
@@ -510,6 +514,24 @@ class PolyOracle:
         rre, rim = np.zeros_like(ure), np.zeros_like(ure)
         lib().porc_residual_complex(self._h, p, _p(ure), _p(uim), _p(rre), _p(rim))
         return rre + 1j * rim
+
+    def surface(self):
+        """(|dE| [E], h_E = 6 |E| / |dE| [E])."""
+        surf, hE = np.zeros(self.ne), np.zeros(self.ne)
+        lib().porc_surface(self._h, _p(surf), _p(hE))
+        return surf, hE
+
+    def timestep(self, p: int, cfl: float, u: np.ndarray) -> np.ndarray:
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        assert u.shape == (self.ne, 5, self.N(p))
+        dt = np.zeros(self.ne)
+        lib().porc_timestep(self._h, p, cfl, _p(u), _p(dt))
+        return dt
+
+    def rnorm(self, p: int, r: np.ndarray) -> float:
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        assert r.shape == (self.ne, 5, self.N(p))
+        return lib().porc_rnorm(self._h, p, _p(r))
 
     def mms_project(self, p):
         u = self.zeros(p)

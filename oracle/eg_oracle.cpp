@@ -1736,6 +1736,8 @@ struct Poly {
   std::vector<PFace> faces;
   std::vector<int> efc, eside;       // [E][5]
   std::vector<double> xc, Ls, vol;   // [E][3], [E][3], [E]
+  std::vector<double> surf, hE;      // [E]: |dE|, h_E = 2 d |E| / |dE|
+  double omega = 0.0;                // |Omega|
   std::vector<double> S;             // [E][Nmax][Nmax], lower triangular
   std::vector<std::array<int, 3>> mono;
   std::string err;
@@ -2027,6 +2029,23 @@ bool poly_setup(Poly& P) {
     for (int k = 0; k < 3; ++k) s += Nh[k] * (cF[k] - cE[k]);
     F.sgn = s < 0.0 ? -1.0 : 1.0;
   }
+  // surfaces (the face rule of p_max) and the length scale of the
+  // pseudo-time step, as on the hexahedra: h_E = 2 d |E| / |dE|
+  P.surf.assign(P.ne, 0.0);
+  for (const auto& F : P.faces) {
+    std::vector<double> X, W, Nh;
+    poly_face_rule(P, F, Q, X, W, Nh);
+    double a = 0.0;
+    for (double w : W) a += w;
+    P.surf[F.eL] += a;
+    if (F.eR >= 0) P.surf[F.eR] += a;
+  }
+  P.hE.assign(P.ne, 0.0);
+  P.omega = 0.0;
+  for (int e = 0; e < P.ne; ++e) {
+    P.hE[e] = 6.0 * P.vol[e] / P.surf[e];
+    P.omega += P.vol[e];
+  }
   double vinf[3] = {O.mach * std::cos(O.alpha) * std::cos(O.beta), O.mach * std::sin(O.alpha) * std::cos(O.beta),
                     O.mach * std::sin(O.beta)};
   O.Uinf[0] = 1.0;
@@ -2261,6 +2280,42 @@ void porc_residual_complex(void* h, int p, const double* ure, const double* uim,
   for (size_t i = 0; i < n; ++i) u[i] = cd(ure[i], uim[i]);
   poly_residual_t(P, p, u.data(), r.data());
   for (size_t i = 0; i < n; ++i) { rre[i] = r[i].real(); rim[i] = r[i].imag(); }
+}
+
+// Pseudo-time step on the tetrahedra and prisms (Section 4, eq. (x3d)), the
+// definition of the hexahedra: dtau_E = CFL h_E / ((2p+1)(|v| + c)) with v, c
+// from the cell-mean state u_0 psi_0 (psi_0 = S_00, chi_0 = 1).
+void porc_timestep(void* h, int p, double cfl, const double* u, double* dtau) {
+  const Poly& P = *static_cast<Poly*>(h);
+  const int Np = pnmodes(p);
+  for (int e = 0; e < P.ne; ++e) {
+    const double psi0 = P.S[(size_t)e * P.Nmax * P.Nmax];
+    double U[MAXV];
+    for (int v = 0; v < 5; ++v) U[v] = u[((size_t)e * 5 + v) * Np] * psi0;
+    double q2 = 0.0;
+    for (int a = 0; a < 3; ++a) q2 += (U[1 + a] / U[0]) * (U[1 + a] / U[0]);
+    const double c = std::sqrt(P.base.gam * pressure(3, P.base.gam, U) / U[0]);
+    dtau[e] = cfl * P.hE[e] / ((2.0 * p + 1.0) * (std::sqrt(q2) + c));
+  }
+}
+
+// Density-residual norm (Section 4, norm under eq. (cfl)): with the
+// orthonormal basis, (1/|Omega|) (sum of the squared density coefficients)^(1/2).
+double porc_rnorm(void* h, int p, const double* r) {
+  const Poly& P = *static_cast<Poly*>(h);
+  const int Np = pnmodes(p);
+  double s = 0.0;
+  for (int e = 0; e < P.ne; ++e)
+    for (int i = 0; i < Np; ++i) {
+      const double x = r[((size_t)e * 5 + 0) * Np + i];
+      s += x * x;
+    }
+  return std::sqrt(s) / P.omega;
+}
+
+void porc_surface(void* h, double* surf, double* hE) {
+  const Poly& P = *static_cast<Poly*>(h);
+  for (int e = 0; e < P.ne; ++e) { surf[e] = P.surf[e]; hE[e] = P.hE[e]; }
 }
 
 void porc_mms_project(void* h, int p, double* u) { poly_mms(*static_cast<Poly*>(h), p, 0, u); }

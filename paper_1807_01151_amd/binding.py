@@ -18,7 +18,7 @@ EXPORTED_SYMBOLS = (
     "eg_set_graphs", "eg_measure_peak", "eg_rnorm_noalloc",
     "eg_param_sensitivity", "eg_jacobian_apply", "eg_solve_multi",
     "eg_poly_init", "eg_poly_free", "eg_poly_last_error", "eg_poly_freestream", "eg_poly_residual",
-    "eg_poly_basis",
+    "eg_poly_basis", "eg_poly_timestep", "eg_poly_rnorm", "eg_poly_restrict", "eg_poly_prolong_add",
 )
 
 KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
@@ -130,6 +130,14 @@ def lib():
         L.eg_poly_residual.restype = i
         L.eg_poly_basis.argtypes = [vp, pd, pd, pd, pd]
         L.eg_poly_basis.restype = i
+        L.eg_poly_timestep.argtypes = [vp, i, d, vp, vp]
+        L.eg_poly_timestep.restype = i
+        L.eg_poly_rnorm.argtypes = [vp, i, vp, pd]
+        L.eg_poly_rnorm.restype = i
+        L.eg_poly_restrict.argtypes = [vp, i, i, vp, vp]
+        L.eg_poly_restrict.restype = i
+        L.eg_poly_prolong_add.argtypes = [vp, i, i, vp, vp]
+        L.eg_poly_prolong_add.restype = i
         for name in ("eg_sizes", "eg_set_freestream", "eg_residual", "eg_timestep", "eg_element_jacobian",
                      "eg_prk_step", "eg_jacobian_p0", "eg_exp1_step", "eg_rnorm", "eg_vcycle",
                      "eg_solve_steady", "eg_solve_resume", "eg_profile", "eg_profile_read"):
@@ -634,6 +642,37 @@ class PolySolver:
             raise ValueError("out must not alias u")
         self._chk(lib().eg_poly_residual(self._h, p, pu, pr))
         return r
+
+    def timestep(self, p: int, cfl: float, u):
+        import torch
+        pu = self._vec(u, p, "u")
+        dt = torch.empty(self.n_elem, dtype=torch.float64, device="cuda")
+        self._chk(lib().eg_poly_timestep(self._h, p, float(cfl), pu,
+                                         check_tensor(dt, self.n_elem, "float64", self.device, "dtau")))
+        return dt
+
+    def rnorm(self, p: int, r) -> float:
+        out = C.c_double(0.0)
+        self._chk(lib().eg_poly_rnorm(self._h, p, self._vec(r, p, "r"), C.byref(out)))
+        return out.value
+
+    def restrict(self, pf: int, pc: int, x, out=None):
+        if not 0 <= pc <= pf:
+            raise ValueError("restrict needs 0 <= pc <= pf")
+        px = self._vec(x, pf, "x")
+        y = self.empty(pc) if out is None else out
+        self._chk(lib().eg_poly_restrict(self._h, pf, pc, px, self._vec(y, pc, "out")))
+        return y
+
+    def prolong_add(self, pc: int, pf: int, y, x):
+        """x (level pf) += zero-padded y (level pc), in place."""
+        if not 0 <= pc <= pf:
+            raise ValueError("prolong_add needs 0 <= pc <= pf")
+        py, px = self._vec(y, pc, "y"), self._vec(x, pf, "x")
+        if px.value == py.value:
+            raise ValueError("x must not alias y")
+        self._chk(lib().eg_poly_prolong_add(self._h, pc, pf, py, px))
+        return x
 
     def basis(self):
         """(S [n_elem, N_pmax, N_pmax], xc [n_elem, 3], L [n_elem, 3], vol [n_elem]) of the set-up."""

@@ -498,6 +498,71 @@ __global__ void k_poly_freestream(int ne, int N, int spk, const double* __restri
   u[idx] = i == 0 ? gas.Uinf[v] / S[(size_t)e * spk] : 0.0;
 }
 
+
+// Pseudo-time step (Section 4, eq. (x3d)): dtau_E = CFL h_E / ((2p+1)(|v| + c))
+// from the cell-mean state u_0 psi_0 (psi_0 = S_00), one thread per element.
+__global__ void k_poly_timestep(int ne, int N, int spk, const double* __restrict__ S, const double* __restrict__ hE,
+                                eg::Gas gas, double cfl, int p, const double* __restrict__ u,
+                                double* __restrict__ dtau) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const double psi0 = S[(size_t)e * spk];
+  double U[PV];
+#pragma unroll
+  for (int v = 0; v < PV; ++v) U[v] = u[((size_t)e * PV + v) * N] * psi0;
+  const double ir = 1.0 / U[0];
+  const double q2 = (U[1] * ir) * (U[1] * ir) + (U[2] * ir) * (U[2] * ir) + (U[3] * ir) * (U[3] * ir);
+  const double c = sqrt(gas.g * eg::pressure<3>(U, gas.g) * ir);
+  dtau[e] = cfl * hE[e] / ((2.0 * p + 1.0) * (sqrt(q2) + c));
+}
+
+// Density-residual norm: per-block partial sums of the squared density
+// coefficients (fixed grid, fixed order), then one block sums the partials.
+constexpr int NORM_BLOCKS = 256;
+__global__ __launch_bounds__(256) void k_poly_norm_partial(long long ne, int N, const double* __restrict__ r,
+                                                           double* __restrict__ part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  const long long n = ne * N;
+  for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
+    const double x = r[(k / N) * PV * N + (k % N)];
+    s += x * x;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_poly_norm_final(const double* __restrict__ part, double omega,
+                                                         double* __restrict__ out) {
+  __shared__ double red[256];
+  red[threadIdx.x] = threadIdx.x < NORM_BLOCKS ? part[threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(red[0]) / omega;
+}
+
+// Transfers between levels (Section 2.4): with the hierarchical basis the
+// level-pc space is the leading Nc modes of every [elem][var] row, so
+// restriction is truncation (y = leading slice of x) and prolongation is
+// zero padding (x_fine += y_coarse on the leading slice).
+__global__ void k_poly_transfer(long long ne, int Nf, int Nc, const double* __restrict__ src, double* __restrict__ dst,
+                                int prolong_add) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ne * PV * Nc) return;
+  const int i = (int)(idx % Nc);
+  const long long ev = idx / Nc;
+  if (prolong_add) dst[ev * Nf + i] += src[idx];
+  else dst[idx] = src[ev * Nf + i];
+}
+
 }  // namespace
 
 struct eg_poly_handle {
@@ -517,6 +582,9 @@ struct eg_poly_handle {
   double* d_geo = nullptr;
   double* d_S = nullptr;
   double* d_a = nullptr;  // [E][5][nmax] monomial coefficients
+  double* d_hE = nullptr;    // [E] h_E = 6 |E| / |dE|
+  double* d_norm = nullptr;  // [NORM_BLOCKS + 1] norm partials and result
+  double omega = 0.0;        // |Omega|
   double* d_rule[PMAX_POLY + 1] = {};
   PolyRule rule[PMAX_POLY + 1] = {};
 };
@@ -732,6 +800,39 @@ eg_status poly_setup(eg_poly_handle* h, const eg_poly_mesh* m) {
       fsg[(size_t)e * 5 + lf] = s < 0.0 ? -1 : 1;
     }
   }
+  // |dE| by the face rule of p_max and h_E = 2 d |E| / |dE| (the length
+  // scale of the pseudo-time step on the hexahedra)
+  std::vector<double> hE(ne, 0.0);
+  for (int e = 0; e < ne; ++e) {
+    const int typ = m->elem_type[e];
+    double surf = 0.0;
+    for (int lf = 0; lf < (typ == 0 ? 4 : 5); ++lf) {
+      const int32_t* cv = &fcv[((size_t)e * 5 + lf) * 4];
+      const int n = cv[3] < 0 ? 3 : 4;
+      double C[4][3];
+      for (int k = 0; k < n; ++k)
+        for (int c = 0; c < 3; ++c) C[k][c] = m->xyz[(size_t)cv[k] * 3 + c];
+      for (int i2 = 0; i2 < Q; ++i2)
+        for (int i1 = 0; i1 < Q; ++i1) {
+          double a[3], b[3], wf;
+          if (n == 3) {
+            for (int c = 0; c < 3; ++c) { a[c] = C[1][c] - C[0][c]; b[c] = C[2][c] - C[0][c]; }
+            wf = w01[i1] * w01[i2] * (1 - g01[i2]);
+          } else {
+            const double s = g01[i1], t = g01[i2];
+            for (int c = 0; c < 3; ++c) {
+              a[c] = (1 - t) * (C[1][c] - C[0][c]) + t * (C[2][c] - C[3][c]);
+              b[c] = (1 - s) * (C[3][c] - C[0][c]) + s * (C[2][c] - C[1][c]);
+            }
+            wf = w01[i1] * w01[i2];
+          }
+          const double nx = a[1] * b[2] - a[2] * b[1], ny = a[2] * b[0] - a[0] * b[2], nz = a[0] * b[1] - a[1] * b[0];
+          surf += wf * std::sqrt(nx * nx + ny * ny + nz * nz);
+        }
+    }
+    hE[e] = 6.0 * h->vol[e] / surf;
+    h->omega += h->vol[e];
+  }
   // reference tables of every order
   std::vector<double> tab;
   for (int p = 0; p <= h->pmax; ++p) {
@@ -779,6 +880,11 @@ eg_status poly_setup(eg_poly_handle* h, const eg_poly_mesh* m) {
       dev_copy(&h->d_geo, h->geo.data(), h->geo.size()) != hipSuccess ||
       dev_copy(&h->d_S, spk.data(), spk.size()) != hipSuccess) {
     h->err = "device allocation or upload failed";
+    return EG_ERR_ALLOC;
+  }
+  if (dev_copy(&h->d_hE, hE.data(), hE.size()) != hipSuccess ||
+      hipMalloc((void**)&h->d_norm, sizeof(double) * (NORM_BLOCKS + 1)) != hipSuccess) {
+    h->err = "device allocation failed";
     return EG_ERR_ALLOC;
   }
   if (hipMalloc((void**)&h->d_a, sizeof(double) * (size_t)ne * PV * N) != hipSuccess) {
@@ -850,7 +956,7 @@ void eg_poly_free(eg_poly_handle* h) {
   int cur = 0;
   hipGetDevice(&cur);
   hipSetDevice(h->dev);
-  void* bufs[] = {h->d_xyz, h->d_ev, h->d_typ, h->d_nbr, h->d_fcv, h->d_fsg, h->d_geo, h->d_S, h->d_a};
+  void* bufs[] = {h->d_xyz, h->d_ev, h->d_typ, h->d_nbr, h->d_fcv, h->d_fsg, h->d_geo, h->d_S, h->d_a, h->d_hE, h->d_norm};
   for (void* b : bufs)
     if (b) hipFree(b);
   for (auto* b : h->d_rule)
@@ -880,6 +986,50 @@ eg_status eg_poly_residual(eg_poly_handle* h, int p, const double* u_dev, double
     case 2: e = launch_residual<2>(h, u_dev, r_dev); break;
     default: e = launch_residual<3>(h, u_dev, r_dev); break;
   }
+  if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
+  return EG_OK;
+}
+
+eg_status eg_poly_timestep(eg_poly_handle* h, int p, double cfl, const double* u_dev, double* dtau_dev) {
+  if (!h || !u_dev || !dtau_dev || p < 0 || p > h->pmax || !(cfl > 0.0)) return EG_ERR_ARG;
+  hipLaunchKernelGGL(k_poly_timestep, dim3((unsigned)((h->ne + 255) / 256)), dim3(256), 0, h->st, h->ne, pn(p),
+                     h->nmax * (h->nmax + 1) / 2, (const double*)h->d_S, (const double*)h->d_hE, h->gas, cfl, p,
+                     u_dev, dtau_dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
+  return EG_OK;
+}
+
+eg_status eg_poly_rnorm(eg_poly_handle* h, int p, const double* r_dev, double* rn_host) {
+  if (!h || !r_dev || !rn_host || p < 0 || p > h->pmax) return EG_ERR_ARG;
+  hipLaunchKernelGGL(k_poly_norm_partial, dim3(NORM_BLOCKS), dim3(256), 0, h->st, (long long)h->ne, pn(p), r_dev,
+                     h->d_norm);
+  hipLaunchKernelGGL(k_poly_norm_final, dim3(1), dim3(256), 0, h->st, (const double*)h->d_norm, h->omega,
+                     h->d_norm + NORM_BLOCKS);
+  hipError_t e = hipMemcpyAsync(rn_host, h->d_norm + NORM_BLOCKS, sizeof(double), hipMemcpyDeviceToHost, h->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+  if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
+  return EG_OK;
+}
+
+eg_status eg_poly_restrict(eg_poly_handle* h, int pf, int pc, const double* xf_dev, double* yc_dev) {
+  if (!h || !xf_dev || !yc_dev || pc < 0 || pc > pf || pf > h->pmax || xf_dev == (const double*)yc_dev)
+    return EG_ERR_ARG;
+  const long long n = (long long)h->ne * PV * pn(pc);
+  hipLaunchKernelGGL(k_poly_transfer, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->st, (long long)h->ne,
+                     pn(pf), pn(pc), xf_dev, yc_dev, 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
+  return EG_OK;
+}
+
+eg_status eg_poly_prolong_add(eg_poly_handle* h, int pc, int pf, const double* yc_dev, double* xf_dev) {
+  if (!h || !xf_dev || !yc_dev || pc < 0 || pc > pf || pf > h->pmax || yc_dev == (const double*)xf_dev)
+    return EG_ERR_ARG;
+  const long long n = (long long)h->ne * PV * pn(pc);
+  hipLaunchKernelGGL(k_poly_transfer, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->st, (long long)h->ne,
+                     pn(pf), pn(pc), yc_dev, xf_dev, 1);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
   return EG_OK;
 }

@@ -124,3 +124,49 @@ def test_poly_errors():
     u = S.freestream(1)
     with pytest.raises(ValueError):
         S.residual(1, u, out=u)
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+def test_poly_timestep_parity(p):
+    import paper_1807_01151_amd as P
+    m = _tagged(box_poly(3, "mixed", tag=2, skew=0.15, seed=1), 11)
+    O = oracle.PolyOracle(m, 3, alpha_deg=8.0, beta_deg=-4.0)
+    S = P.PolySolver(m, 3, alpha_deg=8.0, beta_deg=-4.0)
+    u = _state(O, p, seed=40 + p, amp=0.1)
+    d_o = O.timestep(p, 37.0, u)
+    d_g = to_host(S.timestep(p, 37.0, to_dev(u)))
+    assert rel_err(d_g, d_o) < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_poly_rnorm_parity(p):
+    import paper_1807_01151_amd as P
+    m = sphere_poly(2, 1, 1)
+    O = oracle.PolyOracle(m, 3, flux="roe")
+    S = P.PolySolver(m, 3, flux="roe")
+    u = _state(O, p, seed=60 + p)
+    r_o = O.residual(p, u)
+    rn_o = O.rnorm(p, r_o)
+    rn_g = S.rnorm(p, S.residual(p, to_dev(u)))
+    assert abs(rn_g - rn_o) < 1e-12 * rn_o, (rn_g, rn_o)
+
+
+def test_poly_transfers_are_truncation_and_padding():
+    """Restriction keeps the leading N_pc modes, prolongation adds into them
+    (exact copies: bit-identical)."""
+    import paper_1807_01151_amd as P
+    m = box_poly(2, "mixed", tag=2)
+    S = P.PolySolver(m, 3)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-1, 1, (m.n_elem, 5, 20))
+    y = rng.uniform(-1, 1, (m.n_elem, 5, 4))
+    for pc, nc in ((0, 1), (1, 4), (2, 10), (3, 20)):
+        yc = to_host(S.restrict(3, pc, to_dev(x)))
+        assert np.array_equal(yc, x[:, :, :nc])
+    xd = to_dev(x)
+    S.prolong_add(1, 3, to_dev(y), xd)
+    ref = x.copy()
+    ref[:, :, :4] += y
+    assert np.array_equal(to_host(xd), ref)
+    with pytest.raises(ValueError):
+        S.prolong_add(1, 3, xd, xd)

@@ -256,3 +256,47 @@ def test_sphere_shell_counts_and_freestream():
     m.bface_tag[m.bface_tag == 1] = 2
     O = oracle.PolyOracle(m, 1, alpha_deg=4.0)
     assert np.abs(O.residual(1, O.freestream(1))).max() < 1e-12
+
+
+def _numpy_volume_surface(m):
+    """|E| and |dE| from the vertices (planar faces; straight prisms of an
+    unskewed box are right prisms)."""
+    vol, surf = np.zeros(m.n_elem), np.zeros(m.n_elem)
+    for e in range(m.n_elem):
+        X = m.xyz[m.elem_vert[e, :4 if m.elem_type[e] == TET else 6]]
+        if m.elem_type[e] == TET:
+            vol[e] = abs(np.linalg.det(np.stack([X[1] - X[0], X[2] - X[0], X[3] - X[0]]))) / 6.0
+        else:
+            vol[e] = 0.5 * np.linalg.norm(np.cross(X[1] - X[0], X[2] - X[0])) * abs(X[3, 2] - X[0, 2])
+        for f in (TET_FACES if m.elem_type[e] == TET else PRISM_FACES):
+            P = X[list(f)]
+            if len(f) == 3:
+                surf[e] += 0.5 * np.linalg.norm(np.cross(P[1] - P[0], P[2] - P[0]))
+            else:
+                surf[e] += 0.5 * np.linalg.norm(np.cross(P[2] - P[0], P[3] - P[1]))
+    return vol, surf
+
+
+@pytest.mark.parametrize("kind,skew", [("tet", 0.2), ("mixed", 0.0)])
+def test_timestep_length_scale_and_free_stream(kind, skew):
+    """h_E = 6 |E| / |dE| from numpy volumes and face areas; on the free stream
+    (rho = 1, c = 1) dtau_E = CFL h_E / ((2p+1)(Ma + 1))."""
+    m = box_poly(3, kind, tag=2, skew=skew, seed=5)
+    O = oracle.PolyOracle(m, 3, mach=0.3, alpha_deg=20.0, beta_deg=10.0)
+    vol, surf = _numpy_volume_surface(m)
+    vo, _, _ = O.geometry()
+    so, ho = O.surface()
+    assert np.allclose(vo, vol, rtol=1e-13) and np.allclose(so, surf, rtol=1e-13)
+    assert np.allclose(ho, 6.0 * vol / surf, rtol=1e-13)
+    for p in (0, 2, 3):
+        dt = O.timestep(p, 7.0, O.freestream(p))
+        assert np.allclose(dt, 7.0 * ho / ((2 * p + 1) * 1.3), rtol=1e-13)
+
+
+def test_rnorm_definition():
+    """(1/|Omega|) (sum of squared density coefficients)^(1/2), |Omega| = 1
+    for the unit box."""
+    m = box_poly(2, "mixed", tag=2)
+    O = oracle.PolyOracle(m, 2)
+    r = np.random.default_rng(4).uniform(-1, 1, (m.n_elem, 5, 10))
+    assert abs(O.rnorm(2, r) - math.sqrt(np.sum(r[:, 0, :] ** 2)) / 1.0) < 1e-13 * math.sqrt(np.sum(r[:, 0, :] ** 2))
