@@ -446,6 +446,15 @@ eg_status eg_poly_freestream(eg_poly_handle* h, int p, double* u_dev);
  * Enqueued on the handle's stream, no synchronisation. */
 eg_status eg_poly_residual(eg_poly_handle* h, int p, const double* u_dev, double* r_dev);
 
+/* Element block D_E = dR_E / du_E of the level-p residual (Section 3.3,
+ * eq. (jac1): volume term and the own-side derivative of every face flux,
+ * ghost states included; neighbours held fixed), exact (forward-mode dual
+ * numbers at the quadrature points).  D_dev: n_elem * n * n doubles,
+ * n = 5 N_p, element after element, each block row-major with rows and
+ * columns ordered (v, i) (variable-major, the layout of a coefficient
+ * vector).  u_dev: level-p state (device).  No synchronisation. */
+eg_status eg_poly_element_block(eg_poly_handle* h, int p, const double* u_dev, double* D_dev);
+
 /* Pseudo-time step (Section 4, eq. (x3d)), the definition of the
  * hexahedra: dtau_E = cfl h_E / ((2p+1)(|v| + c)), h_E = 2 d |E| / |dE|,
  * v and c from the cell-mean state u_{E,.,0} psi_0.  u_dev: n_elem * 5 * N_p

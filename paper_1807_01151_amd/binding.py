@@ -19,6 +19,7 @@ EXPORTED_SYMBOLS = (
     "eg_param_sensitivity", "eg_jacobian_apply", "eg_solve_multi",
     "eg_poly_init", "eg_poly_free", "eg_poly_last_error", "eg_poly_freestream", "eg_poly_residual",
     "eg_poly_basis", "eg_poly_timestep", "eg_poly_rnorm", "eg_poly_restrict", "eg_poly_prolong_add",
+    "eg_poly_element_block",
 )
 
 KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
@@ -130,6 +131,8 @@ def lib():
         L.eg_poly_residual.restype = i
         L.eg_poly_basis.argtypes = [vp, pd, pd, pd, pd]
         L.eg_poly_basis.restype = i
+        L.eg_poly_element_block.argtypes = [vp, i, vp, vp]
+        L.eg_poly_element_block.restype = i
         L.eg_poly_timestep.argtypes = [vp, i, d, vp, vp]
         L.eg_poly_timestep.restype = i
         L.eg_poly_rnorm.argtypes = [vp, i, vp, pd]
@@ -642,6 +645,16 @@ class PolySolver:
             raise ValueError("out must not alias u")
         self._chk(lib().eg_poly_residual(self._h, p, pu, pr))
         return r
+
+    def element_block(self, p: int, u, out=None):
+        """D_E = dR_E/du_E for every element: float64 [n_elem, 5 N_p, 5 N_p]."""
+        import torch
+        n = 5 * self.N(p)
+        pu = self._vec(u, p, "u")
+        D = torch.empty((self.n_elem, n, n), dtype=torch.float64, device="cuda") if out is None else out
+        self._chk(lib().eg_poly_element_block(self._h, p, pu,
+                                              check_tensor(D, self.n_elem * n * n, "float64", self.device, "out")))
+        return D
 
     def timestep(self, p: int, cfl: float, u):
         import torch

@@ -209,7 +209,7 @@ __global__ __launch_bounds__(64) void k_poly_residual(PolyDev M, PolyRule R, eg:
                                                      const double* __restrict__ a_all, double* __restrict__ r) {
   constexpr int N = pn(P), NL = pn(P - 1), NL1 = NL > 0 ? NL : 1, Q = P + 2, QV = Q * Q * Q, QF = Q * Q;
   constexpr int NO = PV * N;
-  static_assert(NL <= 16 && 15 <= 16, "one 16 x 16 tile of flux moments");
+  static_assert(NL <= 16, "the flux moments fit one 16 x 16 tile (15 rows d*5+v, NL columns)");
   constexpr int CH = 64;  // points per chunk: one per lane
   constexpr int W1 = 15 + NL, W3 = PV + N;
   __shared__ double sbuf[CH * (W1 > W3 ? W1 : W3)];
@@ -484,6 +484,257 @@ __global__ __launch_bounds__(64) void k_poly_residual(PolyDev M, PolyRule R, eg:
     double s = 0.0;
     for (int j = 0; j <= i; ++j) s += Si[j] * sm[v * N + j];
     r[(size_t)e * NO + o] = s;
+  }
+}
+
+// Element block D_E = dR_E / du_E (Section 3.3, eq. (jac1): the volume
+// term and the own-side derivative of every face flux, ghost states
+// included) on the tetrahedra and prisms, one workgroup of four wavefronts
+// per element.  In monomial coordinates, with A_d = dF_d/dU at the volume
+// points and B = dF~/dU_own at the face points (forward-mode dual numbers),
+//   K_vw[k][l] = sum_d a_d(k) sum_q w A_d,vw chi_{k-e_d} chi_l / L_d
+//              - sum_faces sum_q w B_vw chi_k chi_l,
+// and D_vw = S K_vw S^T (R = S m, a = S^T u).  The pointwise Jacobians and
+// monomials are staged in LDS, the K entries accumulated by the threads that
+// own them; D is written row-major, n = 5 N, rows and columns (v, i).
+template <int P>
+__global__ __launch_bounds__(256) void k_poly_block(PolyDev M, PolyRule R, eg::Gas gas,
+                                                   const double* __restrict__ a_all, double* __restrict__ Dout) {
+  constexpr int N = pn(P), Q = P + 2, QV = Q * Q * Q, QF = Q * Q, NO = PV * N, NB = NO * NO;
+  constexpr int NK = 25 * N * N, OPT = (NK + 255) / 256, NFQ = 5 * QF;
+  constexpr int RJ = QV * 75 + QV * N;          // volume: w A_d / L_d and monomials per point
+  constexpr int RF = NFQ * 25 + NFQ * N;        // faces: w B and monomials per point
+  constexpr int REG = RJ > RF + NK ? RJ : RF + NK;
+  static_assert(QV <= 256 && NFQ <= 256, "one point per thread");
+  __shared__ double sbuf[REG];
+  __shared__ double sa[NO], sS[N * (N + 1) / 2];
+  __shared__ double sn[5][NO];
+  __shared__ double sg[6], sgn[5][6];
+  __shared__ int snb[5];
+  const int t = threadIdx.x;
+  const int per = (M.ne + 7) / 8;
+  const int e = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (e >= M.ne) return;
+  const int typ = M.typ[e];
+  const int nf = typ == 0 ? 4 : 5;
+  for (int o = t; o < NO; o += 256) sa[o] = a_all[(size_t)e * NO + o];
+  for (int k = t; k < N * (N + 1) / 2; k += 256) sS[k] = M.S[(size_t)e * M.spk + k];
+  if (t < 6) sg[t] = M.geo[(size_t)e * 6 + t];
+  if (t < 5) snb[t] = t < nf ? M.nbr[(size_t)e * 5 + t] : PB_WALL;
+  __syncthreads();
+  for (int f = 0; f < nf; ++f) {
+    const int nb = snb[f];
+    if (nb < 0) continue;
+    for (int o = t; o < NO; o += 256) sn[f][o] = a_all[(size_t)nb * NO + o];
+    if (t < 6) sgn[f][t] = M.geo[(size_t)nb * 6 + t];
+  }
+  using D5 = eg::Dual<PV, double>;
+  // ---- volume points: w A_d,vw / L_d and the monomials
+  double* sJ = sbuf;
+  double* sX = sbuf + QV * 75;
+  if (t < QV) {
+    double Xv[6][3];
+    const int nvt = typ == 0 ? 4 : 6;
+    for (int k = 0; k < 6; ++k)
+      for (int c = 0; c < 3; ++c) Xv[k][c] = k < nvt ? M.xyz[(size_t)M.ev[(size_t)e * 6 + k] * 3 + c] : 0.0;
+    double x[3], w, J[3][3];
+    if (typ == 0) {
+      const double* rq = R.tet + t * 4;
+      for (int c = 0; c < 3; ++c) {
+        J[0][c] = Xv[1][c] - Xv[0][c];
+        J[1][c] = Xv[2][c] - Xv[0][c];
+        J[2][c] = Xv[3][c] - Xv[0][c];
+        x[c] = Xv[0][c] + rq[0] * J[0][c] + rq[1] * J[1][c] + rq[2] * J[2][c];
+      }
+      w = rq[3] * fabs(det3(J[0], J[1], J[2]));
+    } else {
+      const double* rq = R.pri + t * 4;
+      const double l1 = rq[0], l2 = rq[1], z = rq[2], l0 = 1.0 - l1 - l2;
+      const double lam[3] = {l0, l1, l2};
+      for (int c = 0; c < 3; ++c) {
+        double xs = 0.0, dz = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          xs += lam[k] * ((1.0 - z) * Xv[k][c] + z * Xv[k + 3][c]);
+          dz += lam[k] * (Xv[k + 3][c] - Xv[k][c]);
+        }
+        x[c] = xs;
+        J[0][c] = (1.0 - z) * (Xv[1][c] - Xv[0][c]) + z * (Xv[4][c] - Xv[3][c]);
+        J[1][c] = (1.0 - z) * (Xv[2][c] - Xv[0][c]) + z * (Xv[5][c] - Xv[3][c]);
+        J[2][c] = dz;
+      }
+      w = rq[3] * fabs(det3(J[0], J[1], J[2]));
+    }
+    double pw[3][P + 1];
+    powers<P>(x, sg, pw);
+    double U[PV];
+    state_at<P>(pw, sa, U);
+    D5 Ud[PV];
+#pragma unroll
+    for (int v = 0; v < PV; ++v) {
+      Ud[v] = D5(U[v]);
+      Ud[v].d[v] = 1.0;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double nd[3] = {0.0, 0.0, 0.0};
+      nd[d] = 1.0;
+      D5 F[PV];
+      eg::flux_n<3>(Ud, nd, F, gas.g);
+      const double sc = w / sg[3 + d];
+#pragma unroll
+      for (int v = 0; v < PV; ++v)
+#pragma unroll
+        for (int ww = 0; ww < PV; ++ww) sJ[t * 75 + d * 25 + v * 5 + ww] = sc * F[v].d[ww];
+    }
+    double xv_[N];
+    mono_values<P, P>(pw, xv_);
+#pragma unroll
+    for (int j = 0; j < N; ++j) sX[t * N + j] = xv_[j];
+  }
+  __syncthreads();
+  double acc[OPT];
+#pragma unroll
+  for (int m = 0; m < OPT; ++m) {
+    acc[m] = 0.0;
+    const int o = t + 256 * m;
+    if (o < NK) {
+      const int vw = o / (N * N), k = (o / N) % N, l = o % N;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int ex = kMono.ex[k][d], lo = kMono.lo[k][d];
+        if (ex > 0) {
+          double s = 0.0;
+          for (int q = 0; q < QV; ++q) s += sJ[q * 75 + d * 25 + vw] * sX[q * N + lo] * sX[q * N + l];
+          acc[m] += (double)ex * s;
+        }
+      }
+    }
+  }
+  __syncthreads();  // the volume staging is dead from here
+  double* sK = sbuf + RF;
+#pragma unroll
+  for (int m = 0; m < OPT; ++m)
+    if (t + 256 * m < NK) sK[t + 256 * m] = acc[m];
+  // ---- face points: w dF~/dU_own and the monomials
+  double* sB = sbuf;
+  double* sY = sbuf + NFQ * 25;
+  const int nfq = nf * QF;
+  if (t < nfq) {
+    const int f = t / QF, q = t % QF;
+    const int nb = snb[f];
+    const int32_t* cv = M.fcv + ((size_t)e * 5 + f) * 4;
+    const double sgnf = (double)M.fsg[(size_t)e * 5 + f];
+    const int ncv = cv[3] < 0 ? 3 : 4;
+    double C[4][3];
+    for (int k = 0; k < 4; ++k)
+      for (int c = 0; c < 3; ++c) C[k][c] = k < ncv ? M.xyz[(size_t)cv[k] * 3 + c] : 0.0;
+    double x[3], nv[3], w;
+    if (ncv == 3) {
+      const double* rq = R.tri + q * 3;
+      double e1[3], e2[3];
+      for (int c = 0; c < 3; ++c) {
+        e1[c] = C[1][c] - C[0][c];
+        e2[c] = C[2][c] - C[0][c];
+        x[c] = C[0][c] + rq[0] * e1[c] + rq[1] * e2[c];
+      }
+      nv[0] = e1[1] * e2[2] - e1[2] * e2[1];
+      nv[1] = e1[2] * e2[0] - e1[0] * e2[2];
+      nv[2] = e1[0] * e2[1] - e1[1] * e2[0];
+      w = rq[2];
+    } else {
+      const double* rq = R.quad + q * 3;
+      const double s = rq[0], tt = rq[1];
+      double xs[3], xt[3];
+      for (int c = 0; c < 3; ++c) {
+        x[c] = (1 - s) * (1 - tt) * C[0][c] + s * (1 - tt) * C[1][c] + s * tt * C[2][c] + (1 - s) * tt * C[3][c];
+        xs[c] = (1 - tt) * (C[1][c] - C[0][c]) + tt * (C[2][c] - C[3][c]);
+        xt[c] = (1 - s) * (C[3][c] - C[0][c]) + s * (C[2][c] - C[1][c]);
+      }
+      nv[0] = xs[1] * xt[2] - xs[2] * xt[1];
+      nv[1] = xs[2] * xt[0] - xs[0] * xt[2];
+      nv[2] = xs[0] * xt[1] - xs[1] * xt[0];
+      w = rq[2];
+    }
+    const double area = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+    double nh[3];
+    for (int c = 0; c < 3; ++c) nh[c] = sgnf * (nv[c] / area);
+    w *= area;
+    double pw[3][P + 1];
+    powers<P>(x, sg, pw);
+    double UL[PV];
+    state_at<P>(pw, sa, UL);
+    D5 ULd[PV], Fd[PV];
+#pragma unroll
+    for (int v = 0; v < PV; ++v) {
+      ULd[v] = D5(UL[v]);
+      ULd[v].d[v] = 1.0;
+    }
+    if (nb >= 0) {
+      double pn_[3][P + 1], UR[PV];
+      powers<P>(x, sgn[f], pn_);
+      state_at<P>(pn_, sn[f], UR);
+      if (gas.flux == eg::FLUX_ROE) eg::roe<3>(ULd, UR, nh, Fd, gas.g);
+      else eg::rusanov<3>(ULd, UR, nh, Fd, gas.g);
+    } else {
+      D5 UG[PV];
+      if (nb == PB_FAR) eg::ghost_far<3>(ULd, nh, UG, gas.Uinf, gas.g);
+      else eg::ghost_wall<3>(ULd, nh, UG);
+      if (gas.flux == eg::FLUX_ROE) eg::roe<3>(ULd, UG, nh, Fd, gas.g);
+      else eg::rusanov<3>(ULd, UG, nh, Fd, gas.g);
+    }
+#pragma unroll
+    for (int v = 0; v < PV; ++v)
+#pragma unroll
+      for (int ww = 0; ww < PV; ++ww) sB[t * 25 + v * 5 + ww] = w * Fd[v].d[ww];
+    double xv_[N];
+    mono_values<P, P>(pw, xv_);
+#pragma unroll
+    for (int j = 0; j < N; ++j) sY[t * N + j] = xv_[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < OPT; ++m) {
+    const int o = t + 256 * m;
+    if (o < NK) {
+      const int vw = o / (N * N), k = (o / N) % N, l = o % N;
+      double s = 0.0;
+      for (int q = 0; q < nfq; ++q) s += sB[q * 25 + vw] * sY[q * N + k] * sY[q * N + l];
+      acc[m] = sK[o] - s;
+    }
+  }
+  // ---- T = S K (rows i), then D = T S^T (columns j)
+#pragma unroll
+  for (int m = 0; m < OPT; ++m) {
+    const int o = t + 256 * m;
+    if (o < NK) sK[o] = acc[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < OPT; ++m) {
+    const int o = t + 256 * m;
+    if (o < NK) {
+      const int vw = o / (N * N), i = (o / N) % N, l = o % N;
+      const double* Si = sS + i * (i + 1) / 2;
+      double s = 0.0;
+      for (int k = 0; k <= i; ++k) s += Si[k] * sK[vw * N * N + k * N + l];
+      acc[m] = s;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < OPT; ++m) {
+    const int o = t + 256 * m;
+    if (o < NK) sK[o] = acc[m];
+  }
+  __syncthreads();
+  for (int o = t; o < NB; o += 256) {
+    const int row = o / NO, col = o % NO;
+    const int v = row / N, i = row % N, ww = col / N, j = col % N;
+    const double* Tr = sK + (v * 5 + ww) * N * N + i * N;
+    const double* Sj = sS + j * (j + 1) / 2;
+    double s = 0.0;
+    for (int l = 0; l <= j; ++l) s += Tr[l] * Sj[l];
+    Dout[(size_t)e * NB + o] = s;
   }
 }
 
@@ -918,9 +1169,32 @@ template <int P> hipError_t launch_residual(eg_poly_handle* h, const double* u, 
   return hipGetLastError();
 }
 
+template <int P> hipError_t launch_block(eg_poly_handle* h, const double* u, double* D) {
+  const PolyDev M = dev_of(h);
+  hipLaunchKernelGGL(k_poly_mono<P>, dim3((unsigned)h->ne), dim3(64), 0, h->st, M, u, h->d_a);
+  const unsigned blocks = 8u * (unsigned)((h->ne + 7) / 8);
+  hipLaunchKernelGGL(k_poly_block<P>, dim3(blocks), dim3(256), 0, h->st, M, h->rule[P], h->gas,
+                     (const double*)h->d_a, D);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 extern "C" {
+
+eg_status eg_poly_element_block(eg_poly_handle* h, int p, const double* u_dev, double* D_dev) {
+  if (!h || !u_dev || !D_dev || p < 0 || p > h->pmax) return EG_ERR_ARG;
+  hipError_t e;
+  switch (p) {
+    case 0: e = launch_block<0>(h, u_dev, D_dev); break;
+    case 1: e = launch_block<1>(h, u_dev, D_dev); break;
+    case 2: e = launch_block<2>(h, u_dev, D_dev); break;
+    default: e = launch_block<3>(h, u_dev, D_dev); break;
+  }
+  if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
+  return EG_OK;
+}
+
 
 eg_status eg_poly_init(const eg_poly_mesh* mesh, const eg_params* prm, void* hip_stream, eg_poly_handle** out) {
   if (!out) return EG_ERR_ARG;

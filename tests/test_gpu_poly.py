@@ -170,3 +170,38 @@ def test_poly_transfers_are_truncation_and_padding():
     assert np.array_equal(to_host(xd), ref)
     with pytest.raises(ValueError):
         S.prolong_add(1, 3, xd, xd)
+
+
+def _oracle_block(O, p, u, e):
+    """D_E by its definition: the complex-step derivative of the oracle's
+    residual of element e with respect to e's own coefficients."""
+    N = O.N(p)
+    n = 5 * N
+    D = np.zeros((n, n))
+    h = 1e-30
+    for c in range(n):
+        v, j = divmod(c, N)
+        uc = u.astype(complex)
+        uc[e, v, j] += 1j * h
+        D[:, c] = O.residual_complex(p, uc)[e].imag.reshape(-1) / h
+    return D
+
+
+@pytest.mark.parametrize("flux", ["rusanov", "roe"])
+@pytest.mark.parametrize("p", [0, 1, 2, 3])
+def test_poly_element_block_parity(p, flux):
+    """Every entry of D_E for a tetrahedron and a prism with wall / far-field
+    / symmetry faces and for interior elements of a skewed mixed mesh."""
+    import paper_1807_01151_amd as P
+    m = _tagged(box_poly(2, "mixed", tag=2, skew=0.15, seed=3), 21)
+    O = oracle.PolyOracle(m, 3, alpha_deg=8.0, beta_deg=-4.0, flux=flux)
+    S = P.PolySolver(m, 3, alpha_deg=8.0, beta_deg=-4.0, flux=flux)
+    u = _state(O, p, seed=80 + p)
+    Dg = to_host(S.element_block(p, to_dev(u)))
+    tets = np.nonzero(m.elem_type == 0)[0]
+    prisms = np.nonzero(m.elem_type == 1)[0]
+    for e in (int(prisms[0]), int(prisms[-1]), int(tets[0]), int(tets[len(tets) // 2])):
+        Do = _oracle_block(O, p, u, e)
+        err = rel_err(Dg[e], Do)
+        print(f"{flux} p={p} element {e} (type {m.elem_type[e]}): block rel err {err:.2e}", flush=True)
+        assert err < 1e-11, (e, err)
