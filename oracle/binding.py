@@ -111,6 +111,9 @@ def lib():
         L.porc_mms_project.argtypes = [C.c_void_p, C.c_int, _d]
         L.porc_mms_forcing.argtypes = [C.c_void_p, C.c_int, _d]
         L.porc_timestep.argtypes = [C.c_void_p, C.c_int, C.c_double, _d, _d]
+        L.porc_element_blocks.argtypes = [C.c_void_p, C.c_int, _d, _d]
+        L.porc_prk.restype = C.c_int
+        L.porc_prk.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, _d, _d]
         L.porc_rnorm.restype = C.c_double
         L.porc_rnorm.argtypes = [C.c_void_p, C.c_int, _d]
         L.porc_surface.argtypes = [C.c_void_p, _d, _d]
@@ -532,6 +535,21 @@ class PolyOracle:
         r = np.ascontiguousarray(r, dtype=np.float64)
         assert r.shape == (self.ne, 5, self.N(p))
         return lib().porc_rnorm(self._h, p, _p(r))
+
+    def element_blocks(self, p: int, u: np.ndarray) -> np.ndarray:
+        """D_E = dR_E/du_E by complex step: [E, 5 N, 5 N], rows / columns (v, i)."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        n = 5 * self.N(p)
+        D = np.zeros((self.ne, n, n))
+        lib().porc_element_blocks(self._h, p, _p(u), _p(D))
+        return D
+
+    def prk(self, p: int, s: int, cfl: float, u: np.ndarray, f=None):
+        """One s-stage PRK step from u (returns the new state and the status)."""
+        u = np.array(u, dtype=np.float64, copy=True, order="C")
+        f = None if f is None else np.ascontiguousarray(f, dtype=np.float64)
+        st = lib().porc_prk(self._h, p, s, cfl, _p(u), _p(f))
+        return u, st
 
     def mms_project(self, p):
         u = self.zeros(p)

@@ -2173,6 +2173,136 @@ void poly_mms(const Poly& P, int p, int mode, double* out) {
   }
 }
 
+// Pseudo-time step on the tetrahedra and prisms (Section 4, eq. (x3d)), the
+// definition of the hexahedra: dtau_E = CFL h_E / ((2p+1)(|v| + c)) with v, c
+// from the cell-mean state u_0 psi_0 (psi_0 = S_00, chi_0 = 1).
+void porc_timestep_impl(const Poly& P, int p, double cfl, const double* u, double* dtau) {
+  const int Np = pnmodes(p);
+  for (int e = 0; e < P.ne; ++e) {
+    const double psi0 = P.S[(size_t)e * P.Nmax * P.Nmax];
+    double U[MAXV];
+    for (int v = 0; v < 5; ++v) U[v] = u[((size_t)e * 5 + v) * Np] * psi0;
+    double q2 = 0.0;
+    for (int a = 0; a < 3; ++a) q2 += (U[1 + a] / U[0]) * (U[1 + a] / U[0]);
+    const double c = std::sqrt(P.base.gam * pressure(3, P.base.gam, U) / U[0]);
+    dtau[e] = cfl * P.hE[e] / ((2.0 * p + 1.0) * (std::sqrt(q2) + c));
+  }
+}
+
+// The residual of element e alone (Section 3.1, eq. (euler3)): its volume
+// term and its faces, with the flux taken from e's side (own state first,
+// e's outward normal); the neighbours' states are real.  Equal to the rows
+// of e in poly_residual_t up to rounding (the numerical fluxes are
+// conservative: F~(a, b; n) = -F~(b, a; -n)).
+template <class S> void poly_elem_residual(const Poly& P, int p, int e, const S* ue, const double* u, S* re) {
+  const Oracle& O = P.base;
+  const int V = 5, N = pnmodes(p), Q = p + 2;
+  for (int i = 0; i < V * N; ++i) re[i] = 0.0;
+  std::vector<double> X, W, Nh;
+  poly_vol_rule(P, e, Q, X, W);
+  double psi[64], gpsi[64 * 3];
+  auto state = [&](const auto* c, S* U) {
+    for (int v = 0; v < V; ++v) {
+      S t = 0.0;
+      for (int i = 0; i < N; ++i) t += c[v * N + i] * psi[i];
+      U[v] = t;
+    }
+  };
+  for (size_t q = 0; q < W.size(); ++q) {
+    poly_psi(P, e, N, &X[q * 3], psi, gpsi);
+    S U[MAXV], F[3][MAXV];
+    state(ue, U);
+    for (int a = 0; a < 3; ++a) {
+      double ea[3] = {0, 0, 0};
+      ea[a] = 1.0;
+      flux_n(3, O.gam, U, ea, F[a]);
+    }
+    for (int v = 0; v < V; ++v)
+      for (int i = 0; i < N; ++i) {
+        S t = 0.0;
+        for (int a = 0; a < 3; ++a) t += F[a][v] * gpsi[i * 3 + a];
+        re[v * N + i] += W[q] * t;
+      }
+  }
+  for (int lf = 0; lf < pnfaces(P.typ[e]); ++lf) {
+    const int fc = P.efc[(size_t)e * 5 + lf], side = P.eside[(size_t)e * 5 + lf];
+    const PFace& F = P.faces[fc];
+    poly_face_rule(P, F, Q, X, W, Nh);
+    const double so = (side == 0 ? 1.0 : -1.0) * F.sgn;  // e's outward orientation
+    const int nb = side == 0 ? F.eR : F.eL;
+    double psin[64];
+    for (size_t k = 0; k < W.size(); ++k) {
+      double nh[3];
+      for (int a = 0; a < 3; ++a) nh[a] = so * Nh[k * 3 + a];
+      poly_psi(P, e, N, &X[k * 3], psi, nullptr);
+      S Ue[MAXV], Un[MAXV], Fl[MAXV];
+      state(ue, Ue);
+      if (nb >= 0) {
+        poly_psi(P, nb, N, &X[k * 3], psin, nullptr);
+        for (int v = 0; v < V; ++v) {
+          double t = 0.0;
+          for (int i = 0; i < N; ++i) t += u[((size_t)nb * V + v) * N + i] * psin[i];
+          Un[v] = t;
+        }
+      } else {
+        ghost_any(O, F.tag, Ue, nh, &X[k * 3], Un);
+      }
+      num_flux(O, Ue, Un, nh, Fl);
+      for (int v = 0; v < V; ++v)
+        for (int i = 0; i < N; ++i) re[v * N + i] -= W[k] * psi[i] * Fl[v];
+    }
+  }
+}
+
+// Element blocks D_E = dR_E/du_E (Section 3.3, eq. (jac1)) by complex step
+// on poly_elem_residual, one column per own coefficient; [E][n][n] row-major,
+// n = 5 N, rows and columns (v, i).
+void poly_blocks(const Poly& P, int p, const double* u, double* D) {
+  const int N = pnmodes(p), n = 5 * N;
+  const double h = 1e-30;
+#pragma omp parallel for schedule(dynamic)
+  for (int e = 0; e < P.ne; ++e) {
+    std::vector<cd> ue(n), re(n);
+    for (int c = 0; c < n; ++c) {
+      for (int i = 0; i < n; ++i) ue[i] = cd(u[(size_t)e * n + i], i == c ? h : 0.0);
+      poly_elem_residual<cd>(P, p, e, ue.data(), u, re.data());
+      for (int i = 0; i < n; ++i) D[((size_t)e * n + i) * n + c] = re[i].imag() / h;
+    }
+  }
+}
+
+// s-stage preconditioned Runge-Kutta step on the tetrahedra and prisms
+// (Section 2.3, eq. (prk_scalar)), the same step as on the hexahedra:
+//   u^(k) = u^n + beta_k P^{-1}(u^n) [R(u^(k-1)) + f],  beta_k = 1/(s-k+1),
+// P = I/dtau_E - D_E frozen at u^n (the basis is orthonormal: mass = I).
+bool poly_prk(const Poly& P, int p, int s, double cfl, double* u, const double* f) {
+  const int N = pnmodes(p), n = 5 * N;
+  const size_t K = (size_t)P.ne * n;
+  std::vector<double> dtau(P.ne), D((size_t)P.ne * n * n), un(u, u + K), R(K);
+  std::vector<int> piv((size_t)P.ne * n);
+  porc_timestep_impl(P, p, cfl, u, dtau.data());
+  poly_blocks(P, p, u, D.data());
+  bool ok = true;
+  for (int e = 0; e < P.ne; ++e) {
+    double* A = &D[(size_t)e * n * n];
+    for (int i = 0; i < n * n; ++i) A[i] = -A[i];
+    for (int i = 0; i < n; ++i) A[i * n + i] += 1.0 / dtau[e];
+    if (!lu_factor(n, A, &piv[(size_t)e * n])) ok = false;
+  }
+  if (!ok) return false;
+  for (int k = 1; k <= s; ++k) {
+    poly_residual_t<double>(P, p, u, R.data());
+    add_forcing(K, R.data(), f);
+    const double bk = 1.0 / (s - k + 1.0);
+    for (int e = 0; e < P.ne; ++e) {
+      std::vector<double> x(R.begin() + (size_t)e * n, R.begin() + (size_t)(e + 1) * n);
+      lu_solve(n, &D[(size_t)e * n * n], &piv[(size_t)e * n], x.data());
+      for (int i = 0; i < n; ++i) u[(size_t)e * n + i] = un[(size_t)e * n + i] + bk * x[i];
+    }
+  }
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2282,21 +2412,14 @@ void porc_residual_complex(void* h, int p, const double* ure, const double* uim,
   for (size_t i = 0; i < n; ++i) { rre[i] = r[i].real(); rim[i] = r[i].imag(); }
 }
 
-// Pseudo-time step on the tetrahedra and prisms (Section 4, eq. (x3d)), the
-// definition of the hexahedra: dtau_E = CFL h_E / ((2p+1)(|v| + c)) with v, c
-// from the cell-mean state u_0 psi_0 (psi_0 = S_00, chi_0 = 1).
 void porc_timestep(void* h, int p, double cfl, const double* u, double* dtau) {
-  const Poly& P = *static_cast<Poly*>(h);
-  const int Np = pnmodes(p);
-  for (int e = 0; e < P.ne; ++e) {
-    const double psi0 = P.S[(size_t)e * P.Nmax * P.Nmax];
-    double U[MAXV];
-    for (int v = 0; v < 5; ++v) U[v] = u[((size_t)e * 5 + v) * Np] * psi0;
-    double q2 = 0.0;
-    for (int a = 0; a < 3; ++a) q2 += (U[1 + a] / U[0]) * (U[1 + a] / U[0]);
-    const double c = std::sqrt(P.base.gam * pressure(3, P.base.gam, U) / U[0]);
-    dtau[e] = cfl * P.hE[e] / ((2.0 * p + 1.0) * (std::sqrt(q2) + c));
-  }
+  porc_timestep_impl(*static_cast<Poly*>(h), p, cfl, u, dtau);
+}
+
+void porc_element_blocks(void* h, int p, const double* u, double* D) { poly_blocks(*static_cast<Poly*>(h), p, u, D); }
+
+int porc_prk(void* h, int p, int s, double cfl, double* u, const double* f) {
+  return poly_prk(*static_cast<Poly*>(h), p, s, cfl, u, f) ? 0 : 1;
 }
 
 // Density-residual norm (Section 4, norm under eq. (cfl)): with the
