@@ -455,6 +455,17 @@ eg_status eg_poly_residual(eg_poly_handle* h, int p, const double* u_dev, double
  * vector).  u_dev: level-p state (device).  No synchronisation. */
 eg_status eg_poly_element_block(eg_poly_handle* h, int p, const double* u_dev, double* D_dev);
 
+/* One s-stage PRK step on the tetrahedra and prisms (Section 2.3,
+ * eq. (prk_scalar)), in place on the level-p state u_dev (device, p >= 1):
+ * u^(k) = u^n + beta_k P^{-1} [R(u^(k-1)) + f], beta_k = 1/(s-k+1), with
+ * P = I/dtau_E - D_E (dtau of eg_poly_timestep at this cfl, D_E of
+ * eg_poly_element_block, both at u^n) factorised by LU with partial
+ * pivoting.  f_dev: forcing (level p, device) or NULL; must not alias u_dev.
+ * The first call allocates the handle's work buffers for p_max
+ * (n_elem (5 N)^2 doubles for the blocks).  Synchronises the stream.
+ * EG_ERR_DIVERGED (message set) if a block has a zero or non-finite pivot. */
+eg_status eg_poly_prk_step(eg_poly_handle* h, int p, int s, double cfl, double* u_dev, const double* f_dev);
+
 /* Pseudo-time step (Section 4, eq. (x3d)), the definition of the
  * hexahedra: dtau_E = cfl h_E / ((2p+1)(|v| + c)), h_E = 2 d |E| / |dE|,
  * v and c from the cell-mean state u_{E,.,0} psi_0.  u_dev: n_elem * 5 * N_p

@@ -19,7 +19,7 @@ EXPORTED_SYMBOLS = (
     "eg_param_sensitivity", "eg_jacobian_apply", "eg_solve_multi",
     "eg_poly_init", "eg_poly_free", "eg_poly_last_error", "eg_poly_freestream", "eg_poly_residual",
     "eg_poly_basis", "eg_poly_timestep", "eg_poly_rnorm", "eg_poly_restrict", "eg_poly_prolong_add",
-    "eg_poly_element_block",
+    "eg_poly_element_block", "eg_poly_prk_step",
 )
 
 KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
@@ -132,6 +132,8 @@ def lib():
         L.eg_poly_basis.argtypes = [vp, pd, pd, pd, pd]
         L.eg_poly_basis.restype = i
         L.eg_poly_element_block.argtypes = [vp, i, vp, vp]
+        L.eg_poly_prk_step.argtypes = [vp, i, i, d, vp, vp]
+        L.eg_poly_prk_step.restype = i
         L.eg_poly_element_block.restype = i
         L.eg_poly_timestep.argtypes = [vp, i, d, vp, vp]
         L.eg_poly_timestep.restype = i
@@ -655,6 +657,15 @@ class PolySolver:
         self._chk(lib().eg_poly_element_block(self._h, p, pu,
                                               check_tensor(D, self.n_elem * n * n, "float64", self.device, "out")))
         return D
+
+    def prk_step(self, p: int, s: int, cfl: float, u, f=None):
+        """One s-stage PRK step on u (level p >= 1), in place."""
+        pu = self._vec(u, p, "u")
+        pf = None if f is None else self._vec(f, p, "f")
+        if pf is not None and pf.value == pu.value:
+            raise ValueError("f must not alias u")
+        self._chk(lib().eg_poly_prk_step(self._h, p, int(s), float(cfl), pu, pf))
+        return u
 
     def timestep(self, p: int, cfl: float, u):
         import torch

@@ -738,6 +738,111 @@ __global__ __launch_bounds__(256) void k_poly_block(PolyDev M, PolyRule R, eg::G
   }
 }
 
+// LU with partial pivoting of the PRK block P_E = I/dtau_E - D_E
+// (Section 2.3, eq. (prk_scalar); the mass matrix is I), one workgroup per
+// element with the block in LDS: at step k the largest |a_ik|, i >= k (the
+// lowest row on ties) is swapped into row k, the multipliers are stored below
+// the diagonal and the trailing block is updated.  In place, row-major;
+// piv[k] = the row exchanged with row k at step k.  A zero pivot sets *fail.
+template <int P>
+__global__ __launch_bounds__(256) void k_poly_lu(int ne, double* __restrict__ D, const double* __restrict__ dtau,
+                                                int* __restrict__ piv, int* __restrict__ fail) {
+  constexpr int n = PV * pn(P);
+  __shared__ double A[n * n];
+  __shared__ double rv[256];
+  __shared__ int ri[256];
+  const int e = blockIdx.x, t = threadIdx.x;
+  if (e >= ne) return;
+  double* De = D + (size_t)e * n * n;
+  const double idt = 1.0 / dtau[e];
+  for (int k = t; k < n * n; k += 256) A[k] = (k / n == k % n ? idt : 0.0) - De[k];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = n;
+    for (int i = k + t; i < n; i += 256) {
+      const double a = fabs(A[i * n + k]);
+      if (a > best) { best = a; bi = i; }
+    }
+    rv[t] = best;
+    ri[t] = bi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w && (rv[t + w] > rv[t] || (rv[t + w] == rv[t] && ri[t + w] < ri[t]))) {
+        rv[t] = rv[t + w];
+        ri[t] = ri[t + w];
+      }
+      __syncthreads();
+    }
+    // no row wins only if the column is all NaN: keep row k (flagged below)
+    const int pr = ri[0] < n ? ri[0] : k;
+    if (t == 0) {
+      piv[(size_t)e * n + k] = pr;
+      if (!(rv[0] > 0.0) || !isfinite(rv[0])) atomicOr(fail, 1);
+    }
+    if (pr != k)
+      for (int j = t; j < n; j += 256) {
+        const double tmp = A[k * n + j];
+        A[k * n + j] = A[pr * n + j];
+        A[pr * n + j] = tmp;
+      }
+    __syncthreads();
+    const double ip = 1.0 / A[k * n + k];
+    for (int i = k + 1 + t; i < n; i += 256) A[i * n + k] *= ip;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int idx = t; idx < m * m; idx += 256) {
+      const int i = k + 1 + idx / m, j = k + 1 + idx % m;
+      A[i * n + j] -= A[i * n + k] * A[k * n + j];
+    }
+    __syncthreads();
+  }
+  for (int k = t; k < n * n; k += 256) De[k] = A[k];
+}
+
+// One PRK stage: x = P^{-1} (R + f) by the factors (row exchanges, unit
+// lower then upper substitution, each row's dot product split over the lanes
+// of one wavefront), then u = u^n + beta x.
+template <int P>
+__global__ __launch_bounds__(64) void k_poly_stage(int ne, const double* __restrict__ LU, const int* __restrict__ piv,
+                                                  const double* __restrict__ R, const double* __restrict__ f,
+                                                  const double* __restrict__ un, double beta, double* __restrict__ u) {
+  constexpr int n = PV * pn(P);
+  __shared__ double x[n];
+  const int e = blockIdx.x, t = threadIdx.x;
+  if (e >= ne) return;
+  const double* A = LU + (size_t)e * n * n;
+  for (int i = t; i < n; i += 64) x[i] = R[(size_t)e * n + i] + (f ? f[(size_t)e * n + i] : 0.0);
+  __syncthreads();
+  if (t == 0)
+    for (int k = 0; k < n; ++k) {
+      const int pr = piv[(size_t)e * n + k];
+      if (pr != k) {
+        const double tmp = x[k];
+        x[k] = x[pr];
+        x[pr] = tmp;
+      }
+    }
+  __syncthreads();
+  for (int i = 1; i < n; ++i) {
+    double s = 0.0;
+    for (int j = t; j < i; j += 64) s += A[(size_t)i * n + j] * x[j];
+    for (int w = 32; w > 0; w >>= 1) s += __shfl_xor(s, w, 64);
+    if (t == 0) x[i] -= s;
+    __syncthreads();
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = 0.0;
+    for (int j = i + 1 + t; j < n; j += 64) s += A[(size_t)i * n + j] * x[j];
+    for (int w = 32; w > 0; w >>= 1) s += __shfl_xor(s, w, 64);
+    if (t == 0) x[i] = (x[i] - s) / A[(size_t)i * n + i];
+    __syncthreads();
+  }
+  for (int i = t; i < n; i += 64) u[(size_t)e * n + i] = un[(size_t)e * n + i] + beta * x[i];
+}
+
+__global__ void k_poly_zero_flag(int* flag) { *flag = 0; }
+
 __global__ void k_poly_freestream(int ne, int N, int spk, const double* __restrict__ S, eg::Gas gas,
                                   double* __restrict__ u) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -836,6 +941,13 @@ struct eg_poly_handle {
   double* d_hE = nullptr;    // [E] h_E = 6 |E| / |dE|
   double* d_norm = nullptr;  // [NORM_BLOCKS + 1] norm partials and result
   double omega = 0.0;        // |Omega|
+  // PRK work buffers, allocated at the first eg_poly_prk_step for p_max
+  double* d_un = nullptr;    // [E][n] u^n
+  double* d_R = nullptr;     // [E][n] stage residual
+  double* d_P = nullptr;     // [E][n][n] blocks, then their LU factors
+  double* d_dtau = nullptr;  // [E]
+  int* d_piv = nullptr;      // [E][n]
+  int* d_fail = nullptr;     // zero-pivot flag
   double* d_rule[PMAX_POLY + 1] = {};
   PolyRule rule[PMAX_POLY + 1] = {};
 };
@@ -1178,9 +1290,60 @@ template <int P> hipError_t launch_block(eg_poly_handle* h, const double* u, dou
   return hipGetLastError();
 }
 
+template <int P> hipError_t launch_prk(eg_poly_handle* h, int s, double cfl, double* u, const double* f) {
+  constexpr int n = PV * pn(P);
+  const size_t K = (size_t)h->ne * n;
+  hipError_t e = hipMemcpyAsync(h->d_un, u, K * sizeof(double), hipMemcpyDeviceToDevice, h->st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_poly_timestep, dim3((unsigned)((h->ne + 255) / 256)), dim3(256), 0, h->st, h->ne, pn(P),
+                     h->nmax * (h->nmax + 1) / 2, (const double*)h->d_S, (const double*)h->d_hE, h->gas, cfl, P,
+                     (const double*)u, h->d_dtau);
+  e = launch_block<P>(h, u, h->d_P);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_poly_zero_flag, dim3(1), dim3(1), 0, h->st, h->d_fail);
+  hipLaunchKernelGGL(k_poly_lu<P>, dim3((unsigned)h->ne), dim3(256), 0, h->st, h->ne, h->d_P,
+                     (const double*)h->d_dtau, h->d_piv, h->d_fail);
+  for (int k = 1; k <= s; ++k) {
+    e = launch_residual<P>(h, u, h->d_R);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_poly_stage<P>, dim3((unsigned)h->ne), dim3(64), 0, h->st, h->ne, (const double*)h->d_P,
+                       (const int*)h->d_piv, (const double*)h->d_R, f, (const double*)h->d_un, 1.0 / (s - k + 1.0), u);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 extern "C" {
+
+eg_status eg_poly_prk_step(eg_poly_handle* h, int p, int s, double cfl, double* u_dev, const double* f_dev) {
+  if (!h || !u_dev || p < 1 || p > h->pmax || s < 1 || !(cfl > 0.0) || f_dev == (const double*)u_dev)
+    return EG_ERR_ARG;
+  if (!h->d_P) {
+    const size_t n = (size_t)PV * h->nmax, E = (size_t)h->ne;
+    if (hipMalloc((void**)&h->d_un, sizeof(double) * E * n) != hipSuccess ||
+        hipMalloc((void**)&h->d_R, sizeof(double) * E * n) != hipSuccess ||
+        hipMalloc((void**)&h->d_P, sizeof(double) * E * n * n) != hipSuccess ||
+        hipMalloc((void**)&h->d_dtau, sizeof(double) * E) != hipSuccess ||
+        hipMalloc((void**)&h->d_piv, sizeof(int) * E * n) != hipSuccess ||
+        hipMalloc((void**)&h->d_fail, sizeof(int)) != hipSuccess) {
+      h->err = "device allocation of the PRK buffers failed";
+      return EG_ERR_ALLOC;
+    }
+  }
+  hipError_t e;
+  switch (p) {
+    case 1: e = launch_prk<1>(h, s, cfl, u_dev, f_dev); break;
+    case 2: e = launch_prk<2>(h, s, cfl, u_dev, f_dev); break;
+    default: e = launch_prk<3>(h, s, cfl, u_dev, f_dev); break;
+  }
+  int fail = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&fail, h->d_fail, sizeof(int), hipMemcpyDeviceToHost, h->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+  if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
+  if (fail) { h->err = "zero or non-finite pivot in a PRK block"; return EG_ERR_DIVERGED; }
+  return EG_OK;
+}
 
 eg_status eg_poly_element_block(eg_poly_handle* h, int p, const double* u_dev, double* D_dev) {
   if (!h || !u_dev || !D_dev || p < 0 || p > h->pmax) return EG_ERR_ARG;
@@ -1230,7 +1393,8 @@ void eg_poly_free(eg_poly_handle* h) {
   int cur = 0;
   hipGetDevice(&cur);
   hipSetDevice(h->dev);
-  void* bufs[] = {h->d_xyz, h->d_ev, h->d_typ, h->d_nbr, h->d_fcv, h->d_fsg, h->d_geo, h->d_S, h->d_a, h->d_hE, h->d_norm};
+  void* bufs[] = {h->d_xyz, h->d_ev, h->d_typ, h->d_nbr, h->d_fcv, h->d_fsg, h->d_geo, h->d_S, h->d_a, h->d_hE, h->d_norm,
+                  h->d_un, h->d_R, h->d_P, h->d_dtau, h->d_piv, h->d_fail};
   for (void* b : bufs)
     if (b) hipFree(b);
   for (auto* b : h->d_rule)
