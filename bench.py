@@ -412,6 +412,25 @@ def poly_measurements(P, steps):
                                   "frac_fp64_vector_peak": round(fl / ms / 1e9 / 78.6, 4),
                                   "algorithmic_bytes": by, "achieved_GBps": round(by / ms / 1e6, 1)}
         log(f"[bench] tet/prism residual p={p}: {ms * 1e3:.1f} us, {fl / ms / 1e9:.2f} TFLOP/s")
+        # one 4-stage PRK smoother step at CFL 100 (time step, element blocks,
+        # block LU, four residuals and stage solves) from a free stream
+        # perturbed by 0.1 %
+        up = S.freestream(p)
+        up.mul_(1.0 + 0.001 * (2.0 * torch.rand_like(up) - 1.0))
+        try:
+            S.prk_step(p, 4, 100.0, up)
+            e0.record(st)
+            for _ in range(3):
+                S.prk_step(p, 4, 100.0, up)
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms_prk = e0.elapsed_time(e1) / 3
+            out["levels"][f"p{p}"]["ms_per_prk_step_s4"] = round(ms_prk, 3)
+            log(f"[bench] tet/prism PRK step p={p}: {ms_prk:.3f} ms")
+        except P.EgError as err:
+            out["levels"][f"p{p}"]["prk_step_error"] = str(err)
+            log(f"[bench] tet/prism PRK step p={p} failed: {err}")
+        del up
     return out
 
 

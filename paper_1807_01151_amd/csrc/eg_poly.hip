@@ -502,6 +502,8 @@ __global__ __launch_bounds__(256) void k_poly_block(PolyDev M, PolyRule R, eg::G
                                                    const double* __restrict__ a_all, double* __restrict__ Dout) {
   constexpr int N = pn(P), Q = P + 2, QV = Q * Q * Q, QF = Q * Q, NO = PV * N, NB = NO * NO;
   constexpr int NK = 25 * N * N, OPT = (NK + 255) / 256, NFQ = 5 * QF;
+  constexpr int NN = N * N, NG0 = NN >= 256 ? 1 : 256 / NN, NG = NG0 > 25 ? 25 : NG0;
+  constexpr int VPT = (25 + NG - 1) / NG, OPT2 = (NN * NG + 255) / 256;
   constexpr int RJ = QV * 75 + QV * N;          // volume: w A_d / L_d and monomials per point
   constexpr int RF = NFQ * 25 + NFQ * N;        // faces: w B and monomials per point
   constexpr int REG = RJ > RF + NK ? RJ : RF + NK;
@@ -592,20 +594,30 @@ __global__ __launch_bounds__(256) void k_poly_block(PolyDev M, PolyRule R, eg::G
     for (int j = 0; j < N; ++j) sX[t * N + j] = xv_[j];
   }
   __syncthreads();
-  double acc[OPT];
+  // each thread owns a mode pair (k, l) and a group of VPT of the 25 (v, w):
+  // the two monomial values are read once per point for the whole group, the
+  // group's Jacobian entries are contiguous (NG groups keep the 256 threads
+  // busy at the low orders)
+  double acc[OPT2][VPT];
 #pragma unroll
-  for (int m = 0; m < OPT; ++m) {
-    acc[m] = 0.0;
-    const int o = t + 256 * m;
-    if (o < NK) {
-      const int vw = o / (N * N), k = (o / N) % N, l = o % N;
+  for (int m = 0; m < OPT2; ++m) {
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) acc[m][j] = 0.0;
+    const int idx = t + 256 * m;
+    if (idx < NN * NG) {
+      const int kl = idx % NN, vw0 = (idx / NN) * VPT;
+      const int k = kl / N, l = kl % N;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const int ex = kMono.ex[k][d], lo = kMono.lo[k][d];
         if (ex > 0) {
-          double s = 0.0;
-          for (int q = 0; q < QV; ++q) s += sJ[q * 75 + d * 25 + vw] * sX[q * N + lo] * sX[q * N + l];
-          acc[m] += (double)ex * s;
+          for (int q = 0; q < QV; ++q) {
+            const double c = (double)ex * sX[q * N + lo] * sX[q * N + l];
+            const double* Jq = sJ + q * 75 + d * 25 + vw0;
+#pragma unroll
+            for (int j = 0; j < VPT; ++j)
+              if (vw0 + j < 25) acc[m][j] += Jq[j] * c;
+          }
         }
       }
     }
@@ -613,8 +625,15 @@ __global__ __launch_bounds__(256) void k_poly_block(PolyDev M, PolyRule R, eg::G
   __syncthreads();  // the volume staging is dead from here
   double* sK = sbuf + RF;
 #pragma unroll
-  for (int m = 0; m < OPT; ++m)
-    if (t + 256 * m < NK) sK[t + 256 * m] = acc[m];
+  for (int m = 0; m < OPT2; ++m) {
+    const int idx = t + 256 * m;
+    if (idx < NN * NG) {
+      const int kl = idx % NN, vw0 = (idx / NN) * VPT;
+#pragma unroll
+      for (int j = 0; j < VPT; ++j)
+        if (vw0 + j < 25) sK[(vw0 + j) * NN + kl] = acc[m][j];
+    }
+  }
   // ---- face points: w dF~/dU_own and the monomials
   double* sB = sbuf;
   double* sY = sbuf + NFQ * 25;
@@ -693,38 +712,45 @@ __global__ __launch_bounds__(256) void k_poly_block(PolyDev M, PolyRule R, eg::G
   }
   __syncthreads();
 #pragma unroll
-  for (int m = 0; m < OPT; ++m) {
-    const int o = t + 256 * m;
-    if (o < NK) {
-      const int vw = o / (N * N), k = (o / N) % N, l = o % N;
-      double s = 0.0;
-      for (int q = 0; q < nfq; ++q) s += sB[q * 25 + vw] * sY[q * N + k] * sY[q * N + l];
-      acc[m] = sK[o] - s;
+  for (int m = 0; m < OPT2; ++m) {
+    const int idx = t + 256 * m;
+    if (idx < NN * NG) {
+      const int kl = idx % NN, vw0 = (idx / NN) * VPT;
+      const int k = kl / N, l = kl % N;
+#pragma unroll
+      for (int j = 0; j < VPT; ++j) acc[m][j] = 0.0;
+      for (int q = 0; q < nfq; ++q) {
+        const double c = sY[q * N + k] * sY[q * N + l];
+        const double* Bq = sB + q * 25 + vw0;
+#pragma unroll
+        for (int j = 0; j < VPT; ++j)
+          if (vw0 + j < 25) acc[m][j] += Bq[j] * c;
+      }
+#pragma unroll
+      for (int j = 0; j < VPT; ++j)
+        if (vw0 + j < 25) sK[(vw0 + j) * NN + kl] -= acc[m][j];
     }
   }
-  // ---- T = S K (rows i), then D = T S^T (columns j)
-#pragma unroll
-  for (int m = 0; m < OPT; ++m) {
-    const int o = t + 256 * m;
-    if (o < NK) sK[o] = acc[m];
-  }
   __syncthreads();
+  // ---- T = S K (rows i), then D = T S^T (columns j)
+  double acc1[OPT];
 #pragma unroll
   for (int m = 0; m < OPT; ++m) {
     const int o = t + 256 * m;
+    acc1[m] = 0.0;
     if (o < NK) {
       const int vw = o / (N * N), i = (o / N) % N, l = o % N;
       const double* Si = sS + i * (i + 1) / 2;
       double s = 0.0;
       for (int k = 0; k <= i; ++k) s += Si[k] * sK[vw * N * N + k * N + l];
-      acc[m] = s;
+      acc1[m] = s;
     }
   }
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < OPT; ++m) {
     const int o = t + 256 * m;
-    if (o < NK) sK[o] = acc[m];
+    if (o < NK) sK[o] = acc1[m];
   }
   __syncthreads();
   for (int o = t; o < NB; o += 256) {
@@ -749,8 +775,7 @@ __global__ __launch_bounds__(256) void k_poly_lu(int ne, double* __restrict__ D,
                                                 int* __restrict__ piv, int* __restrict__ fail) {
   constexpr int n = PV * pn(P);
   __shared__ double A[n * n];
-  __shared__ double rv[256];
-  __shared__ int ri[256];
+  __shared__ int s_pr;
   const int e = blockIdx.x, t = threadIdx.x;
   if (e >= ne) return;
   double* De = D + (size_t)e * n * n;
@@ -758,28 +783,29 @@ __global__ __launch_bounds__(256) void k_poly_lu(int ne, double* __restrict__ D,
   for (int k = t; k < n * n; k += 256) A[k] = (k / n == k % n ? idt : 0.0) - De[k];
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    double best = -1.0;
-    int bi = n;
-    for (int i = k + t; i < n; i += 256) {
-      const double a = fabs(A[i * n + k]);
-      if (a > best) { best = a; bi = i; }
-    }
-    rv[t] = best;
-    ri[t] = bi;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (t < w && (rv[t + w] > rv[t] || (rv[t + w] == rv[t] && ri[t + w] < ri[t]))) {
-        rv[t] = rv[t + w];
-        ri[t] = ri[t + w];
+    // pivot search by the first wavefront: (|a|, lowest row) maximum by
+    // butterfly shuffles, so every lane ends with the same winner
+    if (t < 64) {
+      double best = -1.0;
+      int bi = n;
+      for (int i = k + t; i < n; i += 64) {
+        const double a = fabs(A[i * n + k]);
+        if (a > best) { best = a; bi = i; }
       }
-      __syncthreads();
+      for (int w = 32; w > 0; w >>= 1) {
+        const double ob = __shfl_xor(best, w, 64);
+        const int oi = __shfl_xor(bi, w, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (t == 0) {
+        // no row wins only if the column is all NaN: keep row k (flagged)
+        s_pr = bi < n ? bi : k;
+        piv[(size_t)e * n + k] = s_pr;
+        if (!(best > 0.0) || !isfinite(best)) atomicOr(fail, 1);
+      }
     }
-    // no row wins only if the column is all NaN: keep row k (flagged below)
-    const int pr = ri[0] < n ? ri[0] : k;
-    if (t == 0) {
-      piv[(size_t)e * n + k] = pr;
-      if (!(rv[0] > 0.0) || !isfinite(rv[0])) atomicOr(fail, 1);
-    }
+    __syncthreads();
+    const int pr = s_pr;
     if (pr != k)
       for (int j = t; j < n; j += 256) {
         const double tmp = A[k * n + j];
