@@ -112,6 +112,13 @@ def lib():
         L.porc_mms_forcing.argtypes = [C.c_void_p, C.c_int, _d]
         L.porc_timestep.argtypes = [C.c_void_p, C.c_int, C.c_double, _d, _d]
         L.porc_element_blocks.argtypes = [C.c_void_p, C.c_int, _d, _d]
+        L.porc_exp1.restype = C.c_int
+        L.porc_exp1.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, _d, _d]
+        L.porc_vcycle.restype = C.c_int
+        L.porc_vcycle.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, _d, _d, _d]
+        L.porc_solve.restype = C.c_int
+        L.porc_solve.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, _d, _d,
+                                 C.POINTER(C.c_int)]
         L.porc_prk.restype = C.c_int
         L.porc_prk.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, _d, _d]
         L.porc_rnorm.restype = C.c_double
@@ -543,6 +550,27 @@ class PolyOracle:
         D = np.zeros((self.ne, n, n))
         lib().porc_element_blocks(self._h, p, _p(u), _p(D))
         return D
+
+    def exp1(self, m: int, cfl: float, u0: np.ndarray, f0=None):
+        """EXP1 on the level-0 state u0 (time steps at p_max), returns (u0 new, status)."""
+        u = np.array(u0, dtype=np.float64, copy=True, order="C")
+        f = None if f0 is None else np.ascontiguousarray(f0, dtype=np.float64)
+        st = lib().porc_exp1(self._h, self.pmax, m, cfl, _p(u), _p(f))
+        return u, st
+
+    def vcycle(self, u, n, s=4, m=30, cfl_max=100.0, rref=0.0):
+        """One V-cycle from the level-p_max state u: (u new, r_n, cfl, status)."""
+        u = np.array(u, dtype=np.float64, copy=True, order="C")
+        rn, cfl = C.c_double(0.0), C.c_double(0.0)
+        st = lib().porc_vcycle(self._h, self.pmax, s, m, cfl_max, rref, n, _p(u), C.byref(rn), C.byref(cfl))
+        return u, rn.value, cfl.value, st
+
+    def solve(self, u, s=4, m=30, cfl_max=100.0, drop=1e-10, max_cycles=200):
+        u = np.array(u, dtype=np.float64, copy=True, order="C")
+        hist = np.zeros(max_cycles + 1)
+        nc = C.c_int(0)
+        st = lib().porc_solve(self._h, self.pmax, s, m, cfl_max, drop, max_cycles, _p(u), _p(hist), C.byref(nc))
+        return u, hist[: nc.value + 1], st
 
     def prk(self, p: int, s: int, cfl: float, u: np.ndarray, f=None):
         """One s-stage PRK step from u (returns the new state and the status)."""

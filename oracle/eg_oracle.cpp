@@ -2176,8 +2176,8 @@ void poly_mms(const Poly& P, int p, int mode, double* out) {
 // Pseudo-time step on the tetrahedra and prisms (Section 4, eq. (x3d)), the
 // definition of the hexahedra: dtau_E = CFL h_E / ((2p+1)(|v| + c)) with v, c
 // from the cell-mean state u_0 psi_0 (psi_0 = S_00, chi_0 = 1).
-void porc_timestep_impl(const Poly& P, int p, double cfl, const double* u, double* dtau) {
-  const int Np = pnmodes(p);
+// Np: modes per row of u (the cell mean is mode 0); p enters the formula.
+void porc_timestep_impl(const Poly& P, int p, int Np, double cfl, const double* u, double* dtau) {
   for (int e = 0; e < P.ne; ++e) {
     const double psi0 = P.S[(size_t)e * P.Nmax * P.Nmax];
     double U[MAXV];
@@ -2280,7 +2280,7 @@ bool poly_prk(const Poly& P, int p, int s, double cfl, double* u, const double* 
   const size_t K = (size_t)P.ne * n;
   std::vector<double> dtau(P.ne), D((size_t)P.ne * n * n), un(u, u + K), R(K);
   std::vector<int> piv((size_t)P.ne * n);
-  porc_timestep_impl(P, p, cfl, u, dtau.data());
+  porc_timestep_impl(P, p, pnmodes(p), cfl, u, dtau.data());
   poly_blocks(P, p, u, D.data());
   bool ok = true;
   for (int e = 0; e < P.ne; ++e) {
@@ -2301,6 +2301,79 @@ bool poly_prk(const Poly& P, int p, int s, double cfl, double* u, const double* 
     }
   }
   return true;
+}
+
+// EXP1 on the p = 0 level of the tetrahedra and prisms (Section 2.1,
+// eq. (EXP1); Section 2.2), the step of the hexahedra: u <- u + phi_1(A) b,
+// A = T J_0, b = T (R_0(u) + f), T = diag((p_max+1) dtau_E) with dtau at
+// p_max from the cell means; J_0 applied as the complex-step derivative of
+// the p = 0 residual (exact for the linearisation).
+bool poly_exp1(const Poly& P, int pmax, int m, double cfl, double* u0, const double* f0) {
+  const size_t K = (size_t)P.ne * 5;
+  std::vector<double> dt(P.ne), R(K), b(K);
+  // the cell-mean state at level p_max has the coefficients of level 0
+  porc_timestep_impl(P, pmax, 1, cfl, u0, dt.data());
+  for (int e = 0; e < P.ne; ++e) dt[e] *= (pmax + 1.0);
+  poly_residual_t<double>(P, 0, u0, R.data());
+  add_forcing(K, R.data(), f0);
+  for (size_t k = 0; k < K; ++k) b[k] = dt[k / 5] * R[k];
+  const double h = 1e-30;
+  std::vector<cd> uc(K), rc(K);
+  auto Av = [&](const double* x, double* y) {
+    for (size_t k = 0; k < K; ++k) uc[k] = cd(u0[k], h * x[k]);
+    poly_residual_t<cd>(P, 0, uc.data(), rc.data());
+    for (size_t k = 0; k < K; ++k) y[k] = dt[k / 5] * rc[k].imag() / h;
+  };
+  std::vector<double> Vb, H;
+  double beta = 0.0;
+  const int mu = arnoldi(K, m, b.data(), Av, Vb, H, beta);
+  if (mu == 0) return true;
+  std::vector<double> Hm((size_t)mu * mu), y(mu);
+  for (int i = 0; i < mu; ++i)
+    for (int j = 0; j < mu; ++j) Hm[(size_t)i * mu + j] = H[(size_t)i * m + j];
+  if (!phi1_e1(mu, Hm.data(), y.data())) return false;
+  for (size_t k = 0; k < K; ++k) {
+    double t = 0.0;
+    for (int j = 0; j < mu; ++j) t += Vb[(size_t)j * K + k] * y[j];
+    u0[k] += beta * t;
+  }
+  return true;
+}
+
+// V-cycle on the tetrahedra and prisms (Section 2.4), the cycle of the
+// hexahedra: PRK on p >= 1, FAS forcing f_{p-1} = Trunc(R_p(u) + f_p) -
+// R_{p-1}(Trunc u), EXP1 on p = 0, prolongation of the coarse correction.
+bool poly_vcycle_rec(const Poly& P, int pmax, int s, int m, int p, double cfl, double* u, const double* f) {
+  if (p == 0) return poly_exp1(P, pmax, m, cfl, u, f);
+  if (!poly_prk(P, p, s, cfl, u, f)) return false;
+  const int N = pnmodes(p), Nc = pnmodes(p - 1);
+  const size_t K = (size_t)P.ne * 5 * N, Kc = (size_t)P.ne * 5 * Nc;
+  std::vector<double> r(K), v0(Kc), rc(Kc), fc(Kc), Rc(Kc);
+  poly_residual_t<double>(P, p, u, r.data());
+  add_forcing(K, r.data(), f);
+  for (size_t ev = 0; ev < (size_t)P.ne * 5; ++ev)
+    for (int i = 0; i < Nc; ++i) {
+      v0[ev * Nc + i] = u[ev * N + i];
+      rc[ev * Nc + i] = r[ev * N + i];
+    }
+  poly_residual_t<double>(P, p - 1, v0.data(), Rc.data());
+  for (size_t i = 0; i < Kc; ++i) fc[i] = rc[i] - Rc[i];
+  std::vector<double> v(v0);
+  if (!poly_vcycle_rec(P, pmax, s, m, p - 1, cfl, v.data(), fc.data())) return false;
+  for (size_t ev = 0; ev < (size_t)P.ne * 5; ++ev)
+    for (int i = 0; i < Nc; ++i) u[ev * N + i] += v[ev * Nc + i] - v0[ev * Nc + i];
+  return true;
+}
+
+double poly_rnorm_impl(const Poly& P, int p, const double* r) {
+  const int Np = pnmodes(p);
+  double t = 0.0;
+  for (int e = 0; e < P.ne; ++e)
+    for (int i = 0; i < Np; ++i) {
+      const double x = r[((size_t)e * 5 + 0) * Np + i];
+      t += x * x;
+    }
+  return std::sqrt(t) / P.omega;
 }
 
 }  // namespace
@@ -2413,7 +2486,7 @@ void porc_residual_complex(void* h, int p, const double* ure, const double* uim,
 }
 
 void porc_timestep(void* h, int p, double cfl, const double* u, double* dtau) {
-  porc_timestep_impl(*static_cast<Poly*>(h), p, cfl, u, dtau);
+  porc_timestep_impl(*static_cast<Poly*>(h), p, pnmodes(p), cfl, u, dtau);
 }
 
 void porc_element_blocks(void* h, int p, const double* u, double* D) { poly_blocks(*static_cast<Poly*>(h), p, u, D); }
@@ -2439,6 +2512,47 @@ double porc_rnorm(void* h, int p, const double* r) {
 void porc_surface(void* h, double* surf, double* hE) {
   const Poly& P = *static_cast<Poly*>(h);
   for (int e = 0; e < P.ne; ++e) { surf[e] = P.surf[e]; hE[e] = P.hE[e]; }
+}
+
+int porc_exp1(void* h, int pmax, int m, double cfl, double* u0, const double* f0) {
+  return poly_exp1(*static_cast<Poly*>(h), pmax, m, cfl, u0, f0) ? 0 : 1;
+}
+
+// One V-cycle (entry norm and CFL as on the hexahedra) and the steady solve
+// (same stopping rules: r_n <= drop r_1 -> 0, max_cycles -> 3, non-finite
+// norm -> 2, failed step -> 1).
+int porc_vcycle(void* h, int pmax, int s, int m, double cfl_max, double rref, int n, double* u, double* rn_out,
+                double* cfl_out) {
+  const Poly& P = *static_cast<Poly*>(h);
+  const size_t K = (size_t)P.ne * 5 * pnmodes(pmax);
+  std::vector<double> R(K);
+  poly_residual_t<double>(P, pmax, u, R.data());
+  const double rn = poly_rnorm_impl(P, pmax, R.data());
+  if (rn_out) *rn_out = rn;
+  if (!std::isfinite(rn)) return 2;
+  const double cfl = cfl_ramp(cfl_max, rn, rref > 0.0 ? rref : rn, n, pmax);
+  if (cfl_out) *cfl_out = cfl;
+  return poly_vcycle_rec(P, pmax, s, m, pmax, cfl, u, nullptr) ? 0 : 1;
+}
+
+int porc_solve(void* h, int pmax, int s, int m, double cfl_max, double drop, int max_cycles, double* u, double* hist,
+               int* n_cycles) {
+  const Poly& P = *static_cast<Poly*>(h);
+  const size_t K = (size_t)P.ne * 5 * pnmodes(pmax);
+  std::vector<double> R(K);
+  double r1 = 0.0;
+  for (int n = 1;; ++n) {
+    poly_residual_t<double>(P, pmax, u, R.data());
+    const double rn = poly_rnorm_impl(P, pmax, R.data());
+    hist[n - 1] = rn;
+    if (n == 1) r1 = rn;
+    *n_cycles = n - 1;
+    if (!std::isfinite(rn)) return 2;
+    if (rn <= drop * r1) return 0;
+    if (n - 1 == max_cycles) return 3;
+    const double cfl = cfl_ramp(cfl_max, rn, r1, n, pmax);
+    if (!poly_vcycle_rec(P, pmax, s, m, pmax, cfl, u, nullptr)) return 1;
+  }
 }
 
 void porc_mms_project(void* h, int p, double* u) { poly_mms(*static_cast<Poly*>(h), p, 0, u); }

@@ -355,3 +355,49 @@ def test_prk_step_solves_the_block_systems_and_keeps_the_free_stream():
     uf = O.freestream(2)
     u4, st = O.prk(2, 4, 100.0, uf)
     assert st == 0 and np.abs(u4 - uf).max() < 1e-13
+
+
+def test_exp1_exhausted_krylov_equals_dense_phi1():
+    """With m = K (the whole p = 0 space) the Krylov EXP1 is exact:
+    u0 + phi_1(A) b with A = T J_0, b = T R_0, J_0 assembled here column by
+    column from the complex-step residual, T = diag((p_max+1) dtau_E), and
+    phi_1(A) b the last column of expm([[A, b], [0, 0]]) (scipy)."""
+    import scipy.linalg
+    m = box_poly(1, "tet", tag=2, skew=0.0)
+    m.bface_tag[0, 0] = 1 if m.bface_tag[0, 0] else m.bface_tag[0, 0]
+    O = oracle.PolyOracle(m, 2, alpha_deg=6.0, flux="roe")
+    rng = np.random.default_rng(12)
+    vol, _, _ = O.geometry()
+    u0 = O.freestream(0) * (1.0 + 0.02 * rng.uniform(-1, 1, (m.n_elem, 5, 1)))
+    K = m.n_elem * 5
+    J = np.zeros((K, K))
+    for c in range(K):
+        uc = u0.astype(complex).reshape(-1)
+        uc[c] += 1e-30j
+        J[:, c] = O.residual_complex(0, uc.reshape(u0.shape)).imag.reshape(-1) / 1e-30
+    dt = 3.0 * O.timestep(2, 40.0, np.concatenate([u0, np.zeros((m.n_elem, 5, 9))], axis=2))
+    T = np.repeat(dt, 5)
+    A = T[:, None] * J
+    b = T * O.residual(0, u0).reshape(-1)
+    Z = np.zeros((K + 1, K + 1))
+    Z[:K, :K] = A
+    Z[:K, K] = b
+    ref = u0.reshape(-1) + scipy.linalg.expm(Z)[:K, K]
+    got, st = O.exp1(K, 40.0, u0)
+    assert st == 0
+    assert np.abs(got.reshape(-1) - ref).max() < 1e-9 * np.abs(ref - u0.reshape(-1)).max()
+
+
+def test_vcycle_free_stream_fixed_point_and_sphere_convergence():
+    """The free stream is a fixed point of the V-cycle with far-field
+    boundaries; on the smallest tetrahedron / prism sphere shell (wall inside)
+    the eMG solve reaches the 1e-10 drop at p = 1."""
+    m = box_poly(2, "mixed", tag=2, skew=0.1, seed=2)
+    O = oracle.PolyOracle(m, 2, alpha_deg=4.0)
+    u = O.freestream(2)
+    u1, rn, cfl, st = O.vcycle(u, 1)
+    assert st == 0 and np.abs(u1 - u).max() < 1e-13
+    ms = sphere_poly(1, 1, 1)
+    Os = oracle.PolyOracle(ms, 1, flux="roe")
+    _, hist, st = Os.solve(Os.freestream(1), s=4, m=30, cfl_max=100.0, drop=1e-10, max_cycles=600)
+    assert st == 0, (st, hist[-1] / hist[0], len(hist))
