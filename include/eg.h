@@ -425,8 +425,8 @@ typedef struct {
 
 /* Set-up on the current device: face matching, centroids, extents and the
  * per-element MGS basis (on the host), device copies.  Uses p_max (0..3),
- * gamma, mach, alpha_deg, beta_deg and flux of prm; the other fields are
- * ignored.  EG_ERR_ARG for bad sizes or parameters, EG_ERR_MESH for an
+ * rk_stages (>= 1), krylov_m (1..48), cfl_max (> 0), gamma, mach,
+ * alpha_deg, beta_deg and flux of prm; the other fields are ignored.  EG_ERR_ARG for bad sizes or parameters, EG_ERR_MESH for an
  * unmatched face, a bad tag or vertex id, a non-positive element or a
  * degenerate basis; EG_ERR_ALLOC / EG_ERR_HIP for device failures.  *out is
  * set (and must be freed) whenever the status is not EG_ERR_ARG from a null
@@ -465,6 +465,33 @@ eg_status eg_poly_element_block(eg_poly_handle* h, int p, const double* u_dev, d
  * (n_elem (5 N)^2 doubles for the blocks).  Synchronises the stream.
  * EG_ERR_DIVERGED (message set) if a block has a zero or non-finite pivot. */
 eg_status eg_poly_prk_step(eg_poly_handle* h, int p, int s, double cfl, double* u_dev, const double* f_dev);
+
+/* EXP1 on the p = 0 level (Section 2.1, eq. (EXP1); Section 2.2), the step
+ * of the hexahedra: u0 += phi_1(A) b approximated by beta V_m phi_1(H_m) e_1
+ * (krylov_m of eg_poly_init), A = T J_0 with the exact p = 0 Jacobian J_0
+ * (element and neighbour blocks), b = T (R_0(u0) + f0),
+ * T = diag((p_max+1) dtau_E), dtau at p_max and this cfl from the cell means.
+ * u0_dev: level-0 state (device), updated in place; f0_dev: forcing or NULL
+ * (not aliasing u0_dev).  Synchronises the stream.  EG_ERR_DIVERGED if phi_1
+ * fails (non-finite Hessenberg matrix). */
+eg_status eg_poly_exp1_step(eg_poly_handle* h, double cfl, double* u0_dev, const double* f0_dev);
+
+/* One eMG V-cycle (Section 2.4) on the level-p_max state u_dev (p_max >= 1),
+ * the cycle of the hexahedra with the parameters of eg_poly_init
+ * (rk_stages, krylov_m, cfl_max): PRK on p >= 1, FAS forcing
+ * f_{p-1} = Trunc(R_p(u) + f_p) - R_{p-1}(Trunc u), EXP1 on p = 0, the coarse
+ * correction added to the leading modes.  Cycle n >= 1 and the reference
+ * norm rref (0: the entry norm) enter the CFL ramp of eq. (cfl); rn_host and
+ * cfl_host (may be NULL) receive the entry norm and the CFL.  The first call
+ * allocates the level and Krylov buffers.  Synchronises.  EG_ERR_DIVERGED on
+ * a non-finite norm, a zero pivot or a failed phi_1. */
+eg_status eg_poly_vcycle(eg_poly_handle* h, double* u_dev, int n, double rref, double* rn_host, double* cfl_host);
+
+/* Steady solve: V-cycles until r_n <= drop_tol r_1 (EG_OK) or max_cycles
+ * (EG_ERR_NOT_CONVERGED); hist_host[0..*n_cycles_host] receives r_1, r_2, ...
+ * (max_cycles + 1 entries); the ramp uses r_1 as its reference. */
+eg_status eg_poly_solve_steady(eg_poly_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
+                               int* n_cycles_host);
 
 /* Pseudo-time step (Section 4, eq. (x3d)), the definition of the
  * hexahedra: dtau_E = cfl h_E / ((2p+1)(|v| + c)), h_E = 2 d |E| / |dE|,

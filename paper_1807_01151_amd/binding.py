@@ -19,7 +19,7 @@ EXPORTED_SYMBOLS = (
     "eg_param_sensitivity", "eg_jacobian_apply", "eg_solve_multi",
     "eg_poly_init", "eg_poly_free", "eg_poly_last_error", "eg_poly_freestream", "eg_poly_residual",
     "eg_poly_basis", "eg_poly_timestep", "eg_poly_rnorm", "eg_poly_restrict", "eg_poly_prolong_add",
-    "eg_poly_element_block", "eg_poly_prk_step",
+    "eg_poly_element_block", "eg_poly_prk_step", "eg_poly_exp1_step", "eg_poly_vcycle", "eg_poly_solve_steady",
 )
 
 KERNEL_CLASSES = ("residual", "jacobian_lu", "prk_stage", "transfer", "timestep", "p0_setup", "arnoldi",
@@ -133,6 +133,12 @@ def lib():
         L.eg_poly_basis.restype = i
         L.eg_poly_element_block.argtypes = [vp, i, vp, vp]
         L.eg_poly_prk_step.argtypes = [vp, i, i, d, vp, vp]
+        L.eg_poly_exp1_step.argtypes = [vp, d, vp, vp]
+        L.eg_poly_exp1_step.restype = i
+        L.eg_poly_vcycle.argtypes = [vp, vp, i, d, pd, pd]
+        L.eg_poly_vcycle.restype = i
+        L.eg_poly_solve_steady.argtypes = [vp, vp, d, i, pd, C.POINTER(i)]
+        L.eg_poly_solve_steady.restype = i
         L.eg_poly_prk_step.restype = i
         L.eg_poly_element_block.restype = i
         L.eg_poly_timestep.argtypes = [vp, i, d, vp, vp]
@@ -578,8 +584,9 @@ class PolySolver:
     points).  Level-p tensors are float64 [n_elem, 5, N_p] on the device,
     N_p = (p+1)(p+2)(p+3)/6."""
 
-    def __init__(self, mesh, p_max: int, gamma: float = 1.4, mach: float = 0.3, alpha_deg: float = 0.0,
-                 beta_deg: float = 0.0, flux: str = "rusanov", stream=None):
+    def __init__(self, mesh, p_max: int, rk_stages: int = 4, cfl_max: float = 100.0, krylov_m: int = 30,
+                 gamma: float = 1.4, mach: float = 0.3, alpha_deg: float = 0.0, beta_deg: float = 0.0,
+                 flux: str = "rusanov", stream=None):
         import torch
         L = lib()
         m = mesh.contiguous()
@@ -592,7 +599,7 @@ class PolySolver:
                        m.elem_type.ctypes.data_as(C.POINTER(C.c_int8)),
                        m.elem_vert.ctypes.data_as(C.POINTER(C.c_int32)),
                        m.bface_tag.ctypes.data_as(C.POINTER(C.c_int8)))
-        cp = _Params(p_max, 1, 1.0, 1, 1, gamma, mach, alpha_deg, beta_deg, 0, FLUXES[flux])
+        cp = _Params(p_max, rk_stages, cfl_max, krylov_m, 1, gamma, mach, alpha_deg, beta_deg, 0, FLUXES[flux])
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         st = L.eg_poly_init(C.byref(cm), C.byref(cp), C.c_void_p(self.stream.cuda_stream), C.byref(h))
@@ -666,6 +673,33 @@ class PolySolver:
             raise ValueError("f must not alias u")
         self._chk(lib().eg_poly_prk_step(self._h, p, int(s), float(cfl), pu, pf))
         return u
+
+    def exp1_step(self, cfl: float, u0, f0=None):
+        """EXP1 on the level-0 state u0, in place."""
+        pu = self._vec(u0, 0, "u0")
+        pf = None if f0 is None else self._vec(f0, 0, "f0")
+        if pf is not None and pf.value == pu.value:
+            raise ValueError("f0 must not alias u0")
+        self._chk(lib().eg_poly_exp1_step(self._h, float(cfl), pu, pf))
+        return u0
+
+    def vcycle(self, u, n: int, rref: float = 0.0):
+        """One V-cycle on the level-p_max state u, in place: (r_n, cfl)."""
+        rn, cfl = C.c_double(0.0), C.c_double(0.0)
+        self._chk(lib().eg_poly_vcycle(self._h, self._vec(u, self.p_max, "u"), int(n), float(rref),
+                                       C.byref(rn), C.byref(cfl)))
+        return rn.value, cfl.value
+
+    def solve_steady(self, u, drop_tol: float = 1e-10, max_cycles: int = 1000):
+        """V-cycles in place until the drop or max_cycles: (history, status)."""
+        import numpy as np
+        hist = np.zeros(max_cycles + 1)
+        nc = C.c_int(0)
+        st = lib().eg_poly_solve_steady(self._h, self._vec(u, self.p_max, "u"), float(drop_tol), int(max_cycles),
+                                        hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nc))
+        if st not in (0, 5, 6):
+            self._chk(st)
+        return hist[: nc.value + 1], st
 
     def timestep(self, p: int, cfl: float, u):
         import torch

@@ -32,6 +32,7 @@
 #include "../../include/eg.h"
 #include "eg_common.h"
 #include "eg_device.h"
+#include "eg_launch.h"
 #include "eg_physics.h"
 
 namespace eg {
@@ -869,6 +870,131 @@ __global__ __launch_bounds__(64) void k_poly_stage(int ne, const double* __restr
 
 __global__ void k_poly_zero_flag(int* flag) { *flag = 0; }
 
+// p = 0 neighbour blocks of J_0 (Section 3.3, eq. (jac2)): for face lf of
+// element e with neighbour nb, O[v][w] = -psi0_e psi0_nb sum_q w dF~_v/dU_nb,w
+// (the level-0 states are constant, U = a_0 = psi0 u); [E][6][5][5], the
+// slots of boundary faces and the sixth slot zero.  One thread per (e, lf).
+__global__ void k_poly_p0_off(PolyDev M, PolyRule R, eg::Gas gas, const double* __restrict__ a0,
+                              double* __restrict__ Ao) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)M.ne * 6) return;
+  const int e = (int)(idx / 6), lf = (int)(idx % 6);
+  double* O = Ao + (size_t)idx * 25;
+  const int nf = M.typ[e] == 0 ? 4 : 5;
+  const int nb = lf < nf ? M.nbr[(size_t)e * 5 + lf] : PB_WALL;
+  double acc[25];
+#pragma unroll
+  for (int k = 0; k < 25; ++k) acc[k] = 0.0;
+  if (nb >= 0) {
+    using D5 = eg::Dual<PV, double>;
+    const int32_t* cv = M.fcv + ((size_t)e * 5 + lf) * 4;
+    const double sgnf = (double)M.fsg[(size_t)e * 5 + lf];
+    const int ncv = cv[3] < 0 ? 3 : 4;
+    double C[4][3];
+    for (int k = 0; k < 4; ++k)
+      for (int c = 0; c < 3; ++c) C[k][c] = k < ncv ? M.xyz[(size_t)cv[k] * 3 + c] : 0.0;
+    double UL[PV];
+    D5 URd[PV];
+#pragma unroll
+    for (int v = 0; v < PV; ++v) {
+      UL[v] = a0[(size_t)e * PV + v];
+      URd[v] = D5(a0[(size_t)nb * PV + v]);
+      URd[v].d[v] = 1.0;
+    }
+    for (int q = 0; q < 4; ++q) {  // the 2 x 2 face rule of p = 0
+      double nv[3], w;
+      if (ncv == 3) {
+        const double* rq = R.tri + q * 3;
+        double e1[3], e2[3];
+        for (int c = 0; c < 3; ++c) { e1[c] = C[1][c] - C[0][c]; e2[c] = C[2][c] - C[0][c]; }
+        nv[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        nv[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        nv[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        w = rq[2];
+      } else {
+        const double* rq = R.quad + q * 3;
+        const double s = rq[0], tt = rq[1];
+        double xs[3], xt[3];
+        for (int c = 0; c < 3; ++c) {
+          xs[c] = (1 - tt) * (C[1][c] - C[0][c]) + tt * (C[2][c] - C[3][c]);
+          xt[c] = (1 - s) * (C[3][c] - C[0][c]) + s * (C[2][c] - C[1][c]);
+        }
+        nv[0] = xs[1] * xt[2] - xs[2] * xt[1];
+        nv[1] = xs[2] * xt[0] - xs[0] * xt[2];
+        nv[2] = xs[0] * xt[1] - xs[1] * xt[0];
+        w = rq[2];
+      }
+      const double area = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+      double nh[3];
+      for (int c = 0; c < 3; ++c) nh[c] = sgnf * (nv[c] / area);
+      w *= area;
+      D5 Fd[PV];
+      if (gas.flux == eg::FLUX_ROE) eg::roe<3>(UL, URd, nh, Fd, gas.g);
+      else eg::rusanov<3>(UL, URd, nh, Fd, gas.g);
+#pragma unroll
+      for (int v = 0; v < PV; ++v)
+#pragma unroll
+        for (int ww = 0; ww < PV; ++ww) acc[v * 5 + ww] += w * Fd[v].d[ww];
+    }
+    const double sc = -M.S[(size_t)e * M.spk] * M.S[(size_t)nb * M.spk];
+#pragma unroll
+    for (int k = 0; k < 25; ++k) acc[k] *= sc;
+  }
+#pragma unroll
+  for (int k = 0; k < 25; ++k) O[k] = acc[k];
+}
+
+// The EXP1 operands (Section 2.1, eq. (EXP1)): dt_E = (p_max+1) dtau_E with
+// dtau at p_max from the cell mean, A = T J_0 (Ad = dt D_0, Ao *= dt),
+// b = T (R_0 + f); one thread per element.
+__global__ void k_poly_p0_scale(int ne, int pmax, double cfl, const double* __restrict__ S, int spk,
+                                const double* __restrict__ hE, eg::Gas gas, const double* __restrict__ u0,
+                                const double* __restrict__ R0, const double* __restrict__ f0,
+                                const double* __restrict__ D0, double* __restrict__ Ad, double* __restrict__ Ao,
+                                double* __restrict__ b) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const double psi0 = S[(size_t)e * spk];
+  double U[PV];
+#pragma unroll
+  for (int v = 0; v < PV; ++v) U[v] = u0[(size_t)e * PV + v] * psi0;
+  const double ir = 1.0 / U[0];
+  const double q2 = (U[1] * ir) * (U[1] * ir) + (U[2] * ir) * (U[2] * ir) + (U[3] * ir) * (U[3] * ir);
+  const double c = sqrt(gas.g * eg::pressure<3>(U, gas.g) * ir);
+  const double dt = (pmax + 1.0) * (cfl * hE[e] / ((2.0 * pmax + 1.0) * (sqrt(q2) + c)));
+  for (int k = 0; k < 25; ++k) Ad[(size_t)e * 25 + k] = dt * D0[(size_t)e * 25 + k];
+  for (int k = 0; k < 150; ++k) Ao[(size_t)e * 150 + k] *= dt;
+#pragma unroll
+  for (int v = 0; v < PV; ++v)
+    b[(size_t)e * PV + v] = dt * (R0[(size_t)e * PV + v] + (f0 ? f0[(size_t)e * PV + v] : 0.0));
+}
+
+// u0 += beta V_m y (the Krylov combination of EXP1), one thread per row.
+__global__ void k_poly_exp1_update(int K, const double* __restrict__ Vb, const double* __restrict__ y,
+                                   const double* __restrict__ info, double* __restrict__ u0) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int mu = (int)info[0];
+  const double beta = info[1];
+  double t = 0.0;
+  for (int j = 0; j < mu; ++j) t += Vb[(size_t)j * K + k] * y[j];
+  u0[k] += beta * t;
+}
+
+// Element-wise helpers of the V-cycle: z = x + s y (y may be null), and the
+// coarse correction x[:Nc] += v - v0 of every [elem][var] row.
+__global__ void k_poly_axpy(long long n, const double* __restrict__ x, double s, const double* __restrict__ y,
+                            double* __restrict__ z) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z[i] = x[i] + (y ? s * y[i] : 0.0);
+}
+__global__ void k_poly_correct(long long rows, int Nf, int Nc, const double* __restrict__ v,
+                               const double* __restrict__ v0, double* __restrict__ x) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * Nc) return;
+  x[(i / Nc) * Nf + (i % Nc)] += v[i] - v0[i];
+}
+
 __global__ void k_poly_freestream(int ne, int N, int spk, const double* __restrict__ S, eg::Gas gas,
                                   double* __restrict__ u) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -954,6 +1080,7 @@ struct eg_poly_handle {
   std::string err;
   // host copies of the set-up
   std::vector<double> S, geo, vol;
+  std::vector<int32_t> nbr_host;  // [E][5]
   // device
   double* d_xyz = nullptr;
   int32_t* d_ev = nullptr;
@@ -974,6 +1101,17 @@ struct eg_poly_handle {
   double* d_dtau = nullptr;  // [E]
   int* d_piv = nullptr;      // [E][n]
   int* d_fail = nullptr;     // zero-pivot flag
+  // V-cycle: smoother parameters, p = 0 operator, Arnoldi work, level buffers
+  int s = 4, m = 30;
+  double cfl_max = 100.0;
+  int nblk_arn = 0;
+  int32_t* d_nbr6 = nullptr;  // [E][6] neighbours for the Arnoldi product (negative: none)
+  double *d_D0 = nullptr, *d_Ad = nullptr, *d_Ao = nullptr, *d_b = nullptr, *d_R0 = nullptr;
+  double *d_Vb = nullptr, *d_H = nullptr, *d_H2 = nullptr, *d_part1 = nullptr, *d_part2 = nullptr;
+  double *d_info = nullptr, *d_wn0 = nullptr, *d_W = nullptr, *d_y = nullptr;
+  int *d_arn_st = nullptr, *d_pfail = nullptr;
+  double* d_lv[PMAX_POLY + 1][4] = {};  // per level: v, v0, f, r
+  double* d_rtop = nullptr;              // R at p_max
   double* d_rule[PMAX_POLY + 1] = {};
   PolyRule rule[PMAX_POLY + 1] = {};
 };
@@ -1097,6 +1235,7 @@ eg_status poly_setup(eg_poly_handle* h, const eg_poly_mesh* m) {
     }
   }
   if (!open.empty()) { h->err = "interior face without a matching neighbour"; return EG_ERR_MESH; }
+  h->nbr_host = nbr;
   // extents, centroids, outward signs and the MGS basis (volume rule of p_max)
   const int N = pn(h->pmax), Q = h->pmax + 2;
   double g01[8], w01[8];
@@ -1326,7 +1465,6 @@ template <int P> hipError_t launch_prk(eg_poly_handle* h, int s, double cfl, dou
                      (const double*)u, h->d_dtau);
   e = launch_block<P>(h, u, h->d_P);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_poly_zero_flag, dim3(1), dim3(1), 0, h->st, h->d_fail);
   hipLaunchKernelGGL(k_poly_lu<P>, dim3((unsigned)h->ne), dim3(256), 0, h->st, h->ne, h->d_P,
                      (const double*)h->d_dtau, h->d_piv, h->d_fail);
   for (int k = 1; k <= s; ++k) {
@@ -1338,6 +1476,172 @@ template <int P> hipError_t launch_prk(eg_poly_handle* h, int s, double cfl, dou
   return hipGetLastError();
 }
 
+eg_status ensure_prk_buffers(eg_poly_handle* h) {
+  if (h->d_P) return EG_OK;
+  const size_t n = (size_t)PV * h->nmax, E = (size_t)h->ne;
+  if (hipMalloc((void**)&h->d_un, sizeof(double) * E * n) != hipSuccess ||
+      hipMalloc((void**)&h->d_R, sizeof(double) * E * n) != hipSuccess ||
+      hipMalloc((void**)&h->d_P, sizeof(double) * E * n * n) != hipSuccess ||
+      hipMalloc((void**)&h->d_dtau, sizeof(double) * E) != hipSuccess ||
+      hipMalloc((void**)&h->d_piv, sizeof(int) * E * n) != hipSuccess ||
+      hipMalloc((void**)&h->d_fail, sizeof(int)) != hipSuccess) {
+    h->err = "device allocation of the PRK buffers failed";
+    return EG_ERR_ALLOC;
+  }
+  return EG_OK;
+}
+
+eg_status ensure_vc_buffers(eg_poly_handle* h) {
+  eg_status st = ensure_prk_buffers(h);
+  if (st != EG_OK || h->d_nbr6) return st;
+  const size_t E = (size_t)h->ne, K = E * PV, m = (size_t)h->m;
+  h->nblk_arn = eg::arnoldi_blocks((int)K);
+  std::vector<int32_t> nb6(E * 6, -1);
+  for (size_t e = 0; e < E; ++e)
+    for (int lf = 0; lf < 5; ++lf) nb6[e * 6 + lf] = h->nbr_host[e * 5 + lf] >= 0 ? h->nbr_host[e * 5 + lf] : -1;
+  bool ok = dev_copy(&h->d_nbr6, nb6.data(), nb6.size()) == hipSuccess;
+#define PA(ptr, count) ok = ok && hipMalloc((void**)&(ptr), sizeof(*(ptr)) * (count) + 16) == hipSuccess
+  PA(h->d_D0, E * 25);
+  PA(h->d_Ad, E * 25);
+  PA(h->d_Ao, E * 150);
+  PA(h->d_b, K);
+  PA(h->d_R0, K);
+  PA(h->d_Vb, (m + 1) * K);
+  PA(h->d_H, (m + 1) * m);
+  PA(h->d_H2, (m + 1) * m);
+  PA(h->d_part1, (size_t)h->nblk_arn * (m + 2));
+  PA(h->d_part2, (size_t)h->nblk_arn * (m + 2));
+  PA(h->d_info, 2);
+  PA(h->d_wn0, 2);
+  PA(h->d_W, 2 * K);
+  PA(h->d_y, m + 1);
+  PA(h->d_arn_st, 2);
+  PA(h->d_pfail, 1);
+  PA(h->d_rtop, E * PV * h->nmax);
+  for (int p = 0; p < h->pmax; ++p)
+    for (int k = 0; k < 4; ++k) PA(h->d_lv[p][k], E * PV * pn(p));
+#undef PA
+  if (ok) ok = hipMemset(h->d_info, 0, 2 * sizeof(double)) == hipSuccess &&
+               hipMemset(h->d_arn_st, 0, 2 * sizeof(int)) == hipSuccess &&
+               hipMemset(h->d_wn0, 0, 2 * sizeof(double)) == hipSuccess &&
+               hipMemset(h->d_pfail, 0, sizeof(int)) == hipSuccess;
+  if (!ok) {
+    h->err = "device allocation of the V-cycle buffers failed";
+    return EG_ERR_ALLOC;
+  }
+  return EG_OK;
+}
+
+hipError_t residual_any(eg_poly_handle* h, int p, const double* u, double* r) {
+  switch (p) {
+    case 0: return launch_residual<0>(h, u, r);
+    case 1: return launch_residual<1>(h, u, r);
+    case 2: return launch_residual<2>(h, u, r);
+    default: return launch_residual<3>(h, u, r);
+  }
+}
+
+hipError_t prk_any(eg_poly_handle* h, int p, int s, double cfl, double* u, const double* f) {
+  switch (p) {
+    case 1: return launch_prk<1>(h, s, cfl, u, f);
+    case 2: return launch_prk<2>(h, s, cfl, u, f);
+    default: return launch_prk<3>(h, s, cfl, u, f);
+  }
+}
+
+// EXP1 on the level-0 state u0 with forcing f0 (Section 2.1, eq. (EXP1);
+// Section 2.2): the operands by k_poly_block<0>, k_poly_p0_off and
+// k_poly_p0_scale, then the library's Arnoldi (two grid-wide kernels per
+// step) and phi_1 (Pade on the matrix cores) on the p = 0 operator, then
+// u0 += beta V y.
+hipError_t poly_exp1_run(eg_poly_handle* h, double cfl, double* u0, const double* f0) {
+  const PolyDev M = dev_of(h);
+  const int K = h->ne * PV;
+  hipError_t e = launch_block<0>(h, u0, h->d_D0);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_poly_p0_off, dim3((unsigned)((h->ne * 6 + 255) / 256)), dim3(256), 0, h->st, M, h->rule[0],
+                     h->gas, (const double*)h->d_a, h->d_Ao);
+  e = launch_residual<0>(h, u0, h->d_R0);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_poly_p0_scale, dim3((unsigned)((h->ne + 255) / 256)), dim3(256), 0, h->st, h->ne, h->pmax,
+                     cfl, (const double*)h->d_S, h->nmax * (h->nmax + 1) / 2, (const double*)h->d_hE, h->gas,
+                     (const double*)u0, (const double*)h->d_R0, f0, (const double*)h->d_D0, h->d_Ad, h->d_Ao,
+                     h->d_b);
+  eg::DevMesh Mv;
+  Mv.d = 3;
+  Mv.V = PV;
+  Mv.ne = h->ne;
+  Mv.NF = 6;
+  Mv.nbr = h->d_nbr6;
+  e = eg::launch_arnoldi(Mv, h->m, h->nblk_arn, h->d_Ad, h->d_Ao, h->d_b, h->d_Vb, h->d_H, h->d_part1, h->d_part2,
+                         h->d_info, h->d_arn_st, h->d_wn0, h->d_W, h->d_H2, h->st);
+  if (e != hipSuccess) return e;
+  e = eg::launch_phi1(h->m, 1, h->d_H, h->d_H2, h->d_info, h->d_y, h->d_pfail, h->st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_poly_exp1_update, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, h->st, K,
+                     (const double*)h->d_Vb, (const double*)h->d_y, (const double*)h->d_info, u0);
+  return hipGetLastError();
+}
+
+// The V-cycle below level p (Section 2.4), as on the hexahedra: PRK, the FAS
+// forcing f_{p-1} = Trunc(R_p(u) + f_p) - R_{p-1}(Trunc u), recursion, EXP1
+// on p = 0, prolongation of the coarse correction.
+hipError_t poly_vc(eg_poly_handle* h, int p, double cfl, double* u, const double* f) {
+  if (p == 0) return poly_exp1_run(h, cfl, u, f);
+  hipError_t e = prk_any(h, p, h->s, cfl, u, f);
+  if (e != hipSuccess) return e;
+  const long long rows = (long long)h->ne * PV;
+  const int Nf = pn(p), Nc = pn(p - 1);
+  double *v = h->d_lv[p - 1][0], *v0 = h->d_lv[p - 1][1], *fc = h->d_lv[p - 1][2], *rc = h->d_lv[p - 1][3];
+  double* r = p == h->pmax ? h->d_rtop : h->d_lv[p][3];
+  const long long nf = rows * Nf, nc = rows * Nc;
+  const unsigned gf = (unsigned)((nf + 255) / 256), gc = (unsigned)((nc + 255) / 256);
+  if ((e = residual_any(h, p, u, r)) != hipSuccess) return e;
+  if (f) hipLaunchKernelGGL(k_poly_axpy, dim3(gf), dim3(256), 0, h->st, nf, (const double*)r, 1.0, f, r);
+  hipLaunchKernelGGL(k_poly_transfer, dim3(gc), dim3(256), 0, h->st, (long long)h->ne, Nf, Nc, (const double*)u, v0, 0);
+  hipLaunchKernelGGL(k_poly_transfer, dim3(gc), dim3(256), 0, h->st, (long long)h->ne, Nf, Nc, (const double*)r, rc, 0);
+  if ((e = residual_any(h, p - 1, v0, fc)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_poly_axpy, dim3(gc), dim3(256), 0, h->st, nc, (const double*)rc, -1.0, (const double*)fc, fc);
+  hipLaunchKernelGGL(k_poly_axpy, dim3(gc), dim3(256), 0, h->st, nc, (const double*)v0, 0.0, (const double*)nullptr, v);
+  if ((e = poly_vc(h, p - 1, cfl, v, fc)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_poly_correct, dim3(gc), dim3(256), 0, h->st, rows, Nf, Nc, (const double*)v, (const double*)v0, u);
+  return hipGetLastError();
+}
+
+double poly_cfl_ramp(double cfl_max, double rn, double rref, int n, int pmax) {
+  const double a = rn > 0.0 ? rref / rn : HUGE_VAL;
+  const double b = 1.0 + (n - 1.0) / (2.0 * pmax + 1.0);
+  return std::min(cfl_max, std::max(a, b));
+}
+
+}  // namespace
+extern "C" eg_status eg_poly_rnorm(eg_poly_handle* h, int p, const double* r_dev, double* rn_host);
+namespace {
+
+// r_n of the state at level p_max (one synchronisation).
+eg_status entry_norm(eg_poly_handle* h, const double* u, double* rn) {
+  eg_status st = ensure_vc_buffers(h);
+  if (st != EG_OK) return st;
+  const hipError_t e = residual_any(h, h->pmax, u, h->d_rtop);
+  if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
+  return eg_poly_rnorm(h, h->pmax, h->d_rtop, rn);
+}
+
+// One V-cycle at the given CFL; reads the failure flags (one synchronisation).
+eg_status run_cycle(eg_poly_handle* h, double* u, double cfl) {
+  // the failure flags cover the whole cycle (every level's blocks and phi_1)
+  hipLaunchKernelGGL(k_poly_zero_flag, dim3(1), dim3(1), 0, h->st, h->d_fail);
+  hipLaunchKernelGGL(k_poly_zero_flag, dim3(1), dim3(1), 0, h->st, h->d_pfail);
+  hipError_t e = poly_vc(h, h->pmax, cfl, u, nullptr);
+  int fail[2] = {0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(&fail[0], h->d_fail, sizeof(int), hipMemcpyDeviceToHost, h->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&fail[1], h->d_pfail, sizeof(int), hipMemcpyDeviceToHost, h->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+  if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
+  if (fail[0] || fail[1]) { h->err = "zero pivot or failed phi_1 in the V-cycle"; return EG_ERR_DIVERGED; }
+  return EG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1345,18 +1649,11 @@ extern "C" {
 eg_status eg_poly_prk_step(eg_poly_handle* h, int p, int s, double cfl, double* u_dev, const double* f_dev) {
   if (!h || !u_dev || p < 1 || p > h->pmax || s < 1 || !(cfl > 0.0) || f_dev == (const double*)u_dev)
     return EG_ERR_ARG;
-  if (!h->d_P) {
-    const size_t n = (size_t)PV * h->nmax, E = (size_t)h->ne;
-    if (hipMalloc((void**)&h->d_un, sizeof(double) * E * n) != hipSuccess ||
-        hipMalloc((void**)&h->d_R, sizeof(double) * E * n) != hipSuccess ||
-        hipMalloc((void**)&h->d_P, sizeof(double) * E * n * n) != hipSuccess ||
-        hipMalloc((void**)&h->d_dtau, sizeof(double) * E) != hipSuccess ||
-        hipMalloc((void**)&h->d_piv, sizeof(int) * E * n) != hipSuccess ||
-        hipMalloc((void**)&h->d_fail, sizeof(int)) != hipSuccess) {
-      h->err = "device allocation of the PRK buffers failed";
-      return EG_ERR_ALLOC;
-    }
+  {
+    const eg_status st = ensure_prk_buffers(h);
+    if (st != EG_OK) return st;
   }
+  hipLaunchKernelGGL(k_poly_zero_flag, dim3(1), dim3(1), 0, h->st, h->d_fail);
   hipError_t e;
   switch (p) {
     case 1: e = launch_prk<1>(h, s, cfl, u_dev, f_dev); break;
@@ -1369,6 +1666,51 @@ eg_status eg_poly_prk_step(eg_poly_handle* h, int p, int s, double cfl, double* 
   if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
   if (fail) { h->err = "zero or non-finite pivot in a PRK block"; return EG_ERR_DIVERGED; }
   return EG_OK;
+}
+
+eg_status eg_poly_exp1_step(eg_poly_handle* h, double cfl, double* u0_dev, const double* f0_dev) {
+  if (!h || !u0_dev || !(cfl > 0.0) || f0_dev == (const double*)u0_dev) return EG_ERR_ARG;
+  eg_status st = ensure_vc_buffers(h);
+  if (st != EG_OK) return st;
+  hipLaunchKernelGGL(k_poly_zero_flag, dim3(1), dim3(1), 0, h->st, h->d_pfail);
+  hipError_t e = poly_exp1_run(h, cfl, u0_dev, f0_dev);
+  int fail = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&fail, h->d_pfail, sizeof(int), hipMemcpyDeviceToHost, h->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+  if (e != hipSuccess) { h->err = hipGetErrorString(e); return EG_ERR_HIP; }
+  if (fail) { h->err = "phi_1 evaluation failed (non-finite Hessenberg matrix)"; return EG_ERR_DIVERGED; }
+  return EG_OK;
+}
+
+eg_status eg_poly_vcycle(eg_poly_handle* h, double* u_dev, int n, double rref, double* rn_host, double* cfl_host) {
+  if (!h || !u_dev || n < 1 || h->pmax < 1) return EG_ERR_ARG;
+  double rn = 0.0;
+  eg_status st = entry_norm(h, u_dev, &rn);
+  if (rn_host) *rn_host = rn;
+  if (st != EG_OK) return st;
+  if (!std::isfinite(rn)) { h->err = "non-finite residual norm"; return EG_ERR_DIVERGED; }
+  const double cfl = poly_cfl_ramp(h->cfl_max, rn, rref > 0.0 ? rref : rn, n, h->pmax);
+  if (cfl_host) *cfl_host = cfl;
+  return run_cycle(h, u_dev, cfl);
+}
+
+eg_status eg_poly_solve_steady(eg_poly_handle* h, double* u_dev, double drop_tol, int max_cycles, double* hist_host,
+                               int* n_cycles_host) {
+  if (!h || !u_dev || !hist_host || !n_cycles_host || max_cycles < 0 || h->pmax < 1) return EG_ERR_ARG;
+  double r1 = 0.0;
+  for (int n = 1;; ++n) {
+    double rn = 0.0;
+    const eg_status st = entry_norm(h, u_dev, &rn);
+    if (st != EG_OK) return st;
+    hist_host[n - 1] = rn;
+    if (n == 1) r1 = rn;
+    *n_cycles_host = n - 1;
+    if (!std::isfinite(rn)) { h->err = "non-finite residual norm"; return EG_ERR_DIVERGED; }
+    if (rn <= drop_tol * r1) return EG_OK;
+    if (n - 1 == max_cycles) return EG_ERR_NOT_CONVERGED;
+    const eg_status sc = run_cycle(h, u_dev, poly_cfl_ramp(h->cfl_max, rn, r1, n, h->pmax));
+    if (sc != EG_OK) return sc;
+  }
 }
 
 eg_status eg_poly_element_block(eg_poly_handle* h, int p, const double* u_dev, double* D_dev) {
@@ -1391,6 +1733,7 @@ eg_status eg_poly_init(const eg_poly_mesh* mesh, const eg_params* prm, void* hip
   if (!mesh || !prm || !mesh->xyz || !mesh->elem_type || !mesh->elem_vert || !mesh->bface_tag) return EG_ERR_ARG;
   if (mesh->n_vert <= 0 || mesh->n_elem <= 0 || mesh->n_elem > (1 << 26)) return EG_ERR_ARG;
   if (prm->p_max < 0 || prm->p_max > PMAX_POLY || !(prm->gamma > 1.0) || !(prm->mach >= 0.0) ||
+      prm->rk_stages < 1 || prm->krylov_m < 1 || prm->krylov_m > 48 || !(prm->cfl_max > 0.0) ||
       (prm->flux != EG_FLUX_RUSANOV && prm->flux != EG_FLUX_ROE))
     return EG_ERR_ARG;
   eg_poly_handle* h = new (std::nothrow) eg_poly_handle;
@@ -1402,6 +1745,9 @@ eg_status eg_poly_init(const eg_poly_mesh* mesh, const eg_params* prm, void* hip
   h->ne = mesh->n_elem;
   h->nv = mesh->n_vert;
   h->nmax = pn(prm->p_max);
+  h->s = prm->rk_stages;
+  h->m = prm->krylov_m;
+  h->cfl_max = prm->cfl_max;
   const double al = prm->alpha_deg * M_PI / 180.0, be = prm->beta_deg * M_PI / 180.0;
   const double v[3] = {prm->mach * std::cos(al) * std::cos(be), prm->mach * std::sin(al) * std::cos(be),
                        prm->mach * std::sin(be)};
@@ -1420,11 +1766,16 @@ void eg_poly_free(eg_poly_handle* h) {
   hipGetDevice(&cur);
   hipSetDevice(h->dev);
   void* bufs[] = {h->d_xyz, h->d_ev, h->d_typ, h->d_nbr, h->d_fcv, h->d_fsg, h->d_geo, h->d_S, h->d_a, h->d_hE, h->d_norm,
-                  h->d_un, h->d_R, h->d_P, h->d_dtau, h->d_piv, h->d_fail};
+                  h->d_un, h->d_R, h->d_P, h->d_dtau, h->d_piv, h->d_fail, h->d_nbr6, h->d_D0, h->d_Ad, h->d_Ao,
+                  h->d_b, h->d_R0, h->d_Vb, h->d_H, h->d_H2, h->d_part1, h->d_part2, h->d_info, h->d_wn0, h->d_W,
+                  h->d_y, h->d_arn_st, h->d_pfail, h->d_rtop};
   for (void* b : bufs)
     if (b) hipFree(b);
   for (auto* b : h->d_rule)
     if (b) hipFree(b);
+  for (auto& lv : h->d_lv)
+    for (auto* b : lv)
+      if (b) hipFree(b);
   hipSetDevice(cur);
   delete h;
 }

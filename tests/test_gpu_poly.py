@@ -272,3 +272,69 @@ def test_poly_prk_sphere_shell():
     err = rel_err(to_host(ug) - u, uo - u)
     print(f"sphere p=1, 3 PRK steps: rel err {err:.2e}", flush=True)
     assert err < 1e-10, err
+
+
+@pytest.mark.parametrize("flux", ["rusanov", "roe"])
+def test_poly_exp1_parity(flux):
+    """EXP1 on the level-0 state (p_max = 2 time steps, CFL 20, m = 30, with a
+    forcing): the update against the oracle's (CGS2 on the device vs twice
+    swept MGS in the oracle, equal in exact arithmetic) at 1e-10."""
+    import paper_1807_01151_amd as P
+    m = _side_tags(box_poly(2, "mixed", tag=2, skew=0.15, seed=3))
+    O = oracle.PolyOracle(m, 2, alpha_deg=8.0, beta_deg=-4.0, flux=flux)
+    S = P.PolySolver(m, 2, alpha_deg=8.0, beta_deg=-4.0, flux=flux)
+    u0 = _state(O, 0, seed=31)
+    f0 = 0.1 * O.residual(0, _state(O, 0, seed=32))
+    uo, st = O.exp1(30, 20.0, u0, f0)
+    assert st == 0
+    ug = to_dev(u0)
+    S.exp1_step(20.0, ug, to_dev(f0))
+    err = rel_err(to_host(ug) - u0, uo - u0)
+    print(f"{flux}: EXP1 update rel err {err:.2e}", flush=True)
+    assert err < 1e-10, err
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_poly_vcycle_map_parity(p):
+    """Three V-cycles (s = 4, m = 30, CFL ramp to 100) from the free stream on
+    the 48-element tetrahedron / prism sphere shell, Roe flux: entry norms
+    and states after every cycle against the oracle's cycle map."""
+    import paper_1807_01151_amd as P
+    m = sphere_poly(1, 1, 1)
+    O = oracle.PolyOracle(m, p, flux="roe")
+    S = P.PolySolver(m, p, flux="roe")
+    uo = O.freestream(p)
+    ug = S.freestream(p)
+    r1 = 0.0
+    for n in range(1, 4):
+        u_prev = uo.copy()
+        uo, rn_o, cfl_o, st = O.vcycle(uo, n, rref=r1)
+        assert st == 0
+        rn_g, cfl_g = S.vcycle(ug, n, rref=r1)
+        if n == 1:
+            r1 = rn_o
+        assert abs(rn_g - rn_o) <= 1e-12 * rn_o and abs(cfl_g - cfl_o) <= 1e-12 * cfl_o
+        err = rel_err(to_host(ug) - u_prev, uo - u_prev)
+        print(f"p={p} cycle {n}: rn {rn_o:.3e}, update rel err {err:.2e}", flush=True)
+        assert err < 1e-9, (n, err)
+        ug = to_dev(uo)  # next cycle from the common state
+
+
+def test_poly_solve_reaches_the_drop():
+    """The eMG steady solve on the 192-element tetrahedron / prism sphere
+    shell at p = 1 (Roe flux, wall on the body) reaches the 1e-10 drop on the
+    device; the history and the converged state agree with the oracle's."""
+    import paper_1807_01151_amd as P
+    m = sphere_poly(2, 1, 1)
+    O = oracle.PolyOracle(m, 1, flux="roe")
+    S = P.PolySolver(m, 1, flux="roe")
+    uo, h_o, st_o = O.solve(O.freestream(1), s=4, m=30, cfl_max=100.0, drop=1e-10, max_cycles=600)
+    assert st_o == 0
+    ug = S.freestream(1)
+    h_g, st = S.solve_steady(ug, drop_tol=1e-10, max_cycles=600)
+    print(f"sphere p=1: oracle {len(h_o) - 1} cycles, device {len(h_g) - 1} cycles", flush=True)
+    assert st == 0
+    assert abs(len(h_g) - len(h_o)) <= 2
+    k = min(len(h_g), len(h_o), 40)
+    assert np.allclose(h_g[:k], h_o[:k], rtol=1e-6)
+    assert rel_err(to_host(ug), uo) < 1e-8
