@@ -431,6 +431,28 @@ def poly_measurements(P, steps):
             out["levels"][f"p{p}"]["prk_step_error"] = str(err)
             log(f"[bench] tet/prism PRK step p={p} failed: {err}")
         del up
+    # the eMG steady solve on the same shell (s = 4, m = 30, CFL_max 100):
+    # seconds per V-cycle at every order, time to the 1e-10 drop at p = 1, 2
+    out["solve"] = {}
+    for p in (1, 2, 3):
+        Sv = P.PolySolver(m, p, rk_stages=4, cfl_max=100.0, krylov_m=30, mach=0.3, flux="roe")
+        u = Sv.freestream(p)
+        Sv.vcycle(u, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in range(2, 7):
+            Sv.vcycle(u, n)
+        torch.cuda.synchronize()
+        ent = {"ms_per_vcycle": round((time.perf_counter() - t0) / 5 * 1e3, 3)}
+        if p <= 2:
+            u = Sv.freestream(p)
+            t0 = time.perf_counter()
+            hist, st = Sv.solve_steady(u, drop_tol=1e-10, max_cycles=1500)
+            ent.update({"converged": st == 0, "cycles": len(hist) - 1, "drop_reached": float(hist[-1] / hist[0]),
+                        "time_s": round(time.perf_counter() - t0, 2)})
+        out["solve"][f"p{p}"] = ent
+        log(f"[bench] tet/prism eMG solve p={p}: {ent}")
+        del Sv, u
     return out
 
 

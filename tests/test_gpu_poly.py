@@ -338,3 +338,27 @@ def test_poly_solve_reaches_the_drop():
     k = min(len(h_g), len(h_o), 40)
     assert np.allclose(h_g[:k], h_o[:k], rtol=1e-6)
     assert rel_err(to_host(ug), uo) < 1e-8
+
+
+def test_poly_vcycle_fullsize_map():
+    """Two V-cycles on the 13 824-element shell at p = 1 (Roe): entry norms
+    and states against the oracle's cycle map."""
+    import paper_1807_01151_amd as P
+    m = sphere_poly(8, 6, 4)
+    O = oracle.PolyOracle(m, 1, flux="roe")
+    S = P.PolySolver(m, 1, flux="roe")
+    uo = O.freestream(1)
+    ug = S.freestream(1)
+    r1 = 0.0
+    for n in (1, 2):
+        u_prev = uo.copy()
+        uo, rn_o, _, st = O.vcycle(uo, n, rref=r1)
+        assert st == 0
+        rn_g, _ = S.vcycle(ug, n, rref=r1)
+        if n == 1:
+            r1 = rn_o
+        assert abs(rn_g - rn_o) <= 1e-12 * rn_o
+        err = rel_err(to_host(ug) - u_prev, uo - u_prev)
+        print(f"full shell p=1 cycle {n}: update rel err {err:.2e}", flush=True)
+        assert err < 1e-9, (n, err)
+        ug = to_dev(uo)
