@@ -294,7 +294,7 @@ def test_poly_exp1_parity(flux):
     assert err < 1e-10, err
 
 
-@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("p", [1, 2, 3])
 def test_poly_vcycle_map_parity(p):
     """Three V-cycles (s = 4, m = 30, CFL ramp to 100) from the free stream on
     the 48-element tetrahedron / prism sphere shell, Roe flux: entry norms
