@@ -41,12 +41,40 @@ def _state(O, p, seed, amp=0.03):
     return u
 
 
+def _relabel(m, seed):
+    """The same elements with re-labelled local vertices: a seeded even
+    permutation of every tetrahedron's four vertices (orientation kept), a
+    seeded cyclic rotation of every prism's triangles; boundary tags follow
+    their faces.  The collapsed volume rules follow the element's vertex
+    order, so this changes the quadrature points (both sides alike)."""
+    import itertools
+    rng = np.random.default_rng(seed)
+    even = [pp for pp in itertools.permutations(range(4))
+            if sum(1 for i in range(4) for j in range(i + 1, 4) if pp[i] > pp[j]) % 2 == 0]
+    ev, tg = m.elem_vert.copy(), m.bface_tag.copy()
+    for e in range(m.n_elem):
+        if m.elem_type[e] == 0:
+            pp = even[rng.integers(len(even))]
+            ev[e, :4] = m.elem_vert[e, list(pp)]
+            # face k omits vertex k: the new face k omits old vertex pp[k]
+            tg[e, :4] = [m.bface_tag[e, pp[k]] for k in range(4)]
+        else:
+            r = int(rng.integers(3))
+            rot = [(a + r) % 3 for a in range(3)]
+            ev[e, :6] = m.elem_vert[e, rot + [a + 3 for a in rot]]
+            tg[e, 2:5] = [m.bface_tag[e, 2 + (a + r) % 3] for a in range(3)]
+    m.elem_vert, m.bface_tag = ev, tg
+    m.name += f"+relabel{seed}"
+    return m
+
+
 MESHES = [
     ("box3-mixed-skew", lambda: _tagged(box_poly(3, "mixed", tag=2, skew=0.15, seed=1), 11)),
     ("box2-tet-skew", lambda: _tagged(box_poly(2, "tet", tag=2, skew=0.2, seed=4), 12)),
     ("box2-prism", lambda: _tagged(box_poly(2, "prism", tag=2), 13)),
     ("sphere2-1p1t", lambda: sphere_poly(2, 1, 1)),
     ("one-hex-6tets", lambda: box_poly(1, "tet", tag=2)),
+    ("box3-mixed-relabelled", lambda: _relabel(_tagged(box_poly(3, "mixed", tag=2, skew=0.15, seed=1), 11), 5)),
 ]
 
 
@@ -338,6 +366,27 @@ def test_poly_solve_reaches_the_drop():
     k = min(len(h_g), len(h_o), 40)
     assert np.allclose(h_g[:k], h_o[:k], rtol=1e-6)
     assert rel_err(to_host(ug), uo) < 1e-8
+
+
+def test_poly_prk_relabelled_mesh():
+    """A PRK step and a V-cycle on a mesh with re-labelled local vertices
+    (p = 2, Roe) against the oracle."""
+    import paper_1807_01151_amd as P
+    m = _relabel(_side_tags(box_poly(2, "mixed", tag=2, skew=0.15, seed=3)), 9)
+    O = oracle.PolyOracle(m, 2, alpha_deg=8.0, beta_deg=-4.0, flux="roe")
+    S = P.PolySolver(m, 2, alpha_deg=8.0, beta_deg=-4.0, flux="roe")
+    u = _state(O, 2, seed=95)
+    uo, st = O.prk(2, 4, 20.0, u)
+    assert st == 0
+    ug = to_dev(u)
+    S.prk_step(2, 4, 20.0, ug)
+    assert rel_err(to_host(ug) - u, uo - u) < 1e-10
+    uo2, rn_o, _, st = O.vcycle(u, 1)
+    assert st == 0
+    ug = to_dev(u)
+    rn_g, _ = S.vcycle(ug, 1)
+    assert abs(rn_g - rn_o) <= 1e-12 * rn_o
+    assert rel_err(to_host(ug) - u, uo2 - u) < 1e-9
 
 
 def test_poly_vcycle_fullsize_map():
