@@ -817,10 +817,11 @@ __global__ __launch_bounds__(256) void k_poly_lu(int ne, double* __restrict__ D,
     const double ip = 1.0 / A[k * n + k];
     for (int i = k + 1 + t; i < n; i += 256) A[i * n + k] *= ip;
     __syncthreads();
-    const int m = n - k - 1;
-    for (int idx = t; idx < m * m; idx += 256) {
-      const int i = k + 1 + idx / m, j = k + 1 + idx % m;
-      A[i * n + j] -= A[i * n + k] * A[k * n + j];
+    // trailing update on a 16 x 16 grid of threads (rows t / 16, columns
+    // t % 16, strided by 16)
+    for (int i = k + 1 + (t >> 4); i < n; i += 16) {
+      const double l = A[i * n + k];
+      for (int j = k + 1 + (t & 15); j < n; j += 16) A[i * n + j] -= l * A[k * n + j];
     }
     __syncthreads();
   }
