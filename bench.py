@@ -380,7 +380,7 @@ def poly_work(p, n_tet, n_prism):
     return flops, byts
 
 
-def poly_measurements(P, steps):
+def poly_measurements(P, steps, solve=True):
     """The DG residual with the paper's Cartesian P_p basis on the
     tetrahedron / prism sphere shell (9216 tetrahedra, 4608 prisms; Section
     3.2, Section 5.2's element types), p = 1..3, Roe flux: event-timed
@@ -444,7 +444,7 @@ def poly_measurements(P, steps):
             Sv.vcycle(u, n)
         torch.cuda.synchronize()
         ent = {"ms_per_vcycle": round((time.perf_counter() - t0) / 5 * 1e3, 3)}
-        if p <= 2:
+        if p <= 2 and solve:
             u = Sv.freestream(p)
             t0 = time.perf_counter()
             hist, st = Sv.solve_steady(u, drop_tol=1e-10, max_cycles=1500)
@@ -488,6 +488,8 @@ def main():
     ap.add_argument("--batch-budget", type=float, default=30.0, help="seconds cap of the batched convergence run")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured-peak kernels")
     ap.add_argument("--no-poly", action="store_true", help="skip the tetrahedron / prism residual timing")
+    ap.add_argument("--no-poly-solve", action="store_true",
+                    help="tetrahedron / prism section: time V-cycles but skip the runs to the drop (profiling runs)")
     ap.add_argument("--poly-only", action="store_true",
                     help="only the tetrahedron / prism residual timing (profiling runs); prints its JSON")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -510,7 +512,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.poly_only:
-        res = poly_measurements(P, args.steps)
+        res = poly_measurements(P, args.steps, solve=not args.no_poly_solve)
         if args.calibrate:
             nb = 256 << 20
             x = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
@@ -634,7 +636,7 @@ def main():
     if not args.no_batched:
         extras["batched"] = batched_measurements(P, 10, args.batch_budget)
     if not args.no_poly:
-        extras["tet_prism_residual"] = poly_measurements(P, args.steps)
+        extras["tet_prism_residual"] = poly_measurements(P, args.steps, solve=not args.no_poly_solve)
     if args.c5:
         extras["c5_adjoint"] = c5_adjoint(P, args.c5_budget)
     if args.calibrate:
