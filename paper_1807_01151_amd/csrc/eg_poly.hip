@@ -945,6 +945,96 @@ __global__ void k_poly_p0_off(PolyDev M, PolyRule R, eg::Gas gas, const double* 
   for (int k = 0; k < 25; ++k) O[k] = acc[k];
 }
 
+// The p = 0 element block of J_0 (Section 3.3, eq. (jac2)): at p = 0 the
+// volume term vanishes (grad chi_0 = 0) and the state is the constant
+// U = a_0 = psi0 u, so D[v][w] = -psi0^2 sum_faces sum_q w dF~_v/dU_own,w over
+// the 2 x 2 face points, ghost states included; [E][25].  Eight lanes per
+// element, lane lf taking local face lf (lanes past the element's faces add
+// zero), summed over the eight lanes by shuffles in a fixed order.
+__global__ __launch_bounds__(256) void k_poly_p0_diag(PolyDev M, PolyRule R, eg::Gas gas,
+                                                     const double* __restrict__ a0, double* __restrict__ D0) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = (int)(idx >> 3), lf = (int)(idx & 7);
+  const bool live = e < M.ne;
+  const int nf = live ? (M.typ[e] == 0 ? 4 : 5) : 0;
+  double acc[25];
+#pragma unroll
+  for (int k = 0; k < 25; ++k) acc[k] = 0.0;
+  if (lf < nf) {
+    using D5 = eg::Dual<PV, double>;
+    const int nb = M.nbr[(size_t)e * 5 + lf];
+    const int32_t* cv = M.fcv + ((size_t)e * 5 + lf) * 4;
+    const double sgnf = (double)M.fsg[(size_t)e * 5 + lf];
+    const int ncv = cv[3] < 0 ? 3 : 4;
+    double C[4][3];
+    for (int k = 0; k < 4; ++k)
+      for (int c = 0; c < 3; ++c) C[k][c] = k < ncv ? M.xyz[(size_t)cv[k] * 3 + c] : 0.0;
+    D5 ULd[PV];
+    double URn[PV];
+#pragma unroll
+    for (int v = 0; v < PV; ++v) {
+      ULd[v] = D5(a0[(size_t)e * PV + v]);
+      ULd[v].d[v] = 1.0;
+      URn[v] = nb >= 0 ? a0[(size_t)nb * PV + v] : 0.0;
+    }
+    for (int q = 0; q < 4; ++q) {  // the 2 x 2 face rule of p = 0
+      double nv[3], w;
+      if (ncv == 3) {
+        const double* rq = R.tri + q * 3;
+        double e1[3], e2[3];
+        for (int c = 0; c < 3; ++c) { e1[c] = C[1][c] - C[0][c]; e2[c] = C[2][c] - C[0][c]; }
+        nv[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        nv[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        nv[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        w = rq[2];
+      } else {
+        const double* rq = R.quad + q * 3;
+        const double s = rq[0], tt = rq[1];
+        double xs[3], xt[3];
+        for (int c = 0; c < 3; ++c) {
+          xs[c] = (1 - tt) * (C[1][c] - C[0][c]) + tt * (C[2][c] - C[3][c]);
+          xt[c] = (1 - s) * (C[3][c] - C[0][c]) + s * (C[2][c] - C[1][c]);
+        }
+        nv[0] = xs[1] * xt[2] - xs[2] * xt[1];
+        nv[1] = xs[2] * xt[0] - xs[0] * xt[2];
+        nv[2] = xs[0] * xt[1] - xs[1] * xt[0];
+        w = rq[2];
+      }
+      const double area = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+      double nh[3];
+      for (int c = 0; c < 3; ++c) nh[c] = sgnf * (nv[c] / area);
+      w *= area;
+      D5 UG[PV], Fd[PV];
+      if (nb >= 0) {
+#pragma unroll
+        for (int v = 0; v < PV; ++v) UG[v] = D5(URn[v]);
+      } else if (nb == PB_FAR) {
+        eg::ghost_far<3>(ULd, nh, UG, gas.Uinf, gas.g);
+      } else {
+        eg::ghost_wall<3>(ULd, nh, UG);
+      }
+      if (gas.flux == eg::FLUX_ROE) eg::roe<3>(ULd, UG, nh, Fd, gas.g);
+      else eg::rusanov<3>(ULd, UG, nh, Fd, gas.g);
+#pragma unroll
+      for (int v = 0; v < PV; ++v)
+#pragma unroll
+        for (int ww = 0; ww < PV; ++ww) acc[v * 5 + ww] += w * Fd[v].d[ww];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 25; ++k) {
+    acc[k] += __shfl_xor(acc[k], 1, 64);
+    acc[k] += __shfl_xor(acc[k], 2, 64);
+    acc[k] += __shfl_xor(acc[k], 4, 64);
+  }
+  if (!live) return;
+  const double p0 = M.S[(size_t)e * M.spk];
+  const double sc = -p0 * p0;
+#pragma unroll
+  for (int k = 0; k < 25; ++k)
+    if ((k & 7) == lf) D0[(size_t)e * 25 + k] = sc * acc[k];
+}
+
 // The EXP1 operands (Section 2.1, eq. (EXP1)): dt_E = (p_max+1) dtau_E with
 // dtau at p_max from the cell mean, A = T J_0 (Ad = dt D_0, Ao *= dt),
 // b = T (R_0 + f); one thread per element.
@@ -1551,19 +1641,19 @@ hipError_t prk_any(eg_poly_handle* h, int p, int s, double cfl, double* u, const
 }
 
 // EXP1 on the level-0 state u0 with forcing f0 (Section 2.1, eq. (EXP1);
-// Section 2.2): the operands by k_poly_block<0>, k_poly_p0_off and
+// Section 2.2): the operands by k_poly_p0_diag, k_poly_p0_off and
 // k_poly_p0_scale, then the library's Arnoldi (two grid-wide kernels per
 // step) and phi_1 (Pade on the matrix cores) on the p = 0 operator, then
 // u0 += beta V y.
 hipError_t poly_exp1_run(eg_poly_handle* h, double cfl, double* u0, const double* f0) {
   const PolyDev M = dev_of(h);
   const int K = h->ne * PV;
-  hipError_t e = launch_block<0>(h, u0, h->d_D0);
+  hipError_t e = launch_residual<0>(h, u0, h->d_R0);  // also leaves a = S^T u0 in d_a
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_poly_p0_diag, dim3((unsigned)((h->ne * 8 + 255) / 256)), dim3(256), 0, h->st, M, h->rule[0],
+                     h->gas, (const double*)h->d_a, h->d_D0);
   hipLaunchKernelGGL(k_poly_p0_off, dim3((unsigned)((h->ne * 6 + 255) / 256)), dim3(256), 0, h->st, M, h->rule[0],
                      h->gas, (const double*)h->d_a, h->d_Ao);
-  e = launch_residual<0>(h, u0, h->d_R0);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_poly_p0_scale, dim3((unsigned)((h->ne + 255) / 256)), dim3(256), 0, h->st, h->ne, h->pmax,
                      cfl, (const double*)h->d_S, h->nmax * (h->nmax + 1) / 2, (const double*)h->d_hE, h->gas,
                      (const double*)u0, (const double*)h->d_R0, f0, (const double*)h->d_D0, h->d_Ad, h->d_Ao,
