@@ -875,8 +875,8 @@ __global__ void k_poly_zero_flag(int* flag) { *flag = 0; }
 // element e with neighbour nb, O[v][w] = -psi0_e psi0_nb sum_q w dF~_v/dU_nb,w
 // (the level-0 states are constant, U = a_0 = psi0 u); [E][6][5][5], the
 // slots of boundary faces and the sixth slot zero.  One thread per (e, lf).
-__global__ void k_poly_p0_off(PolyDev M, PolyRule R, eg::Gas gas, const double* __restrict__ a0,
-                              double* __restrict__ Ao) {
+__global__ __launch_bounds__(256) void k_poly_p0_off(PolyDev M, PolyRule R, eg::Gas gas,
+                                                     const double* __restrict__ a0, double* __restrict__ Ao) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long long)M.ne * 6) return;
   const int e = (int)(idx / 6), lf = (int)(idx % 6);
