@@ -507,8 +507,19 @@ __global__ __launch_bounds__(256) void k_poly_block(PolyDev M, PolyRule R, eg::G
   constexpr int VPT = (25 + NG - 1) / NG, OPT2 = (NN * NG + 255) / 256;
   constexpr int RJ = QV * 75 + QV * N;          // volume: w A_d / L_d and monomials per point
   constexpr int RF = NFQ * 25 + NFQ * N;        // faces: w B and monomials per point
-  constexpr int REG = RJ > RF + NK ? RJ : RF + NK;
-  static_assert(QV <= 256 && NFQ <= 256, "one point per thread");
+  // at p <= 2 a thread takes one (volume point, direction) pair, so each
+  // thread makes one dual-number flux evaluation; at p <= 1 both stagings
+  // also fit in LDS side by side (faces and K first, the volume points after
+  // them), and the face points run at the same time on wavefronts of their
+  // own (a wavefront that took both would run the two one after the other)
+  constexpr bool VSPLIT = 3 * QV <= 256;
+  constexpr int NVT = VSPLIT ? 3 * QV : QV;
+  constexpr bool CONC = P <= 1;
+  constexpr int VOFF = CONC ? RF + NK : 0;
+  constexpr int FOFF = CONC ? (NVT + 63) / 64 * 64 : 0;
+  constexpr int REG = CONC ? RF + NK + RJ : (RJ > RF + NK ? RJ : RF + NK);
+  static_assert(NVT <= 256 && NFQ <= 256, "one point per thread");
+  static_assert(!CONC || FOFF + NFQ <= 256, "volume and face points side by side");
   __shared__ double sbuf[REG];
   __shared__ double sa[NO], sS[N * (N + 1) / 2];
   __shared__ double sn[5][NO];
@@ -531,11 +542,16 @@ __global__ __launch_bounds__(256) void k_poly_block(PolyDev M, PolyRule R, eg::G
     for (int o = t; o < NO; o += 256) sn[f][o] = a_all[(size_t)nb * NO + o];
     if (t < 6) sgn[f][t] = M.geo[(size_t)nb * 6 + t];
   }
+  if constexpr (CONC) __syncthreads();  // the face points read sn, sgn next
   using D5 = eg::Dual<PV, double>;
   // ---- volume points: w A_d,vw / L_d and the monomials
-  double* sJ = sbuf;
-  double* sX = sbuf + QV * 75;
-  if (t < QV) {
+  double* sJ = sbuf + VOFF;
+  double* sX = sbuf + VOFF + QV * 75;
+  // ---- face points: w dF~/dU_own and the monomials
+  double* sB = sbuf;
+  double* sY = sbuf + NFQ * 25;
+  const int nfq = nf * QF;
+  auto vol_point = [&](const int t, const int dsel) {
     double Xv[6][3];
     const int nvt = typ == 0 ? 4 : 6;
     for (int k = 0; k < 6; ++k)
@@ -577,69 +593,39 @@ __global__ __launch_bounds__(256) void k_poly_block(PolyDev M, PolyRule R, eg::G
       Ud[v] = D5(U[v]);
       Ud[v].d[v] = 1.0;
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      double nd[3] = {0.0, 0.0, 0.0};
-      nd[d] = 1.0;
+    if constexpr (VSPLIT) {
+      // direction dsel only, the unit normal a run-time value so that the
+      // lanes of one wavefront share one code path
+      const double nd[3] = {dsel == 0 ? 1.0 : 0.0, dsel == 1 ? 1.0 : 0.0, dsel == 2 ? 1.0 : 0.0};
       D5 F[PV];
       eg::flux_n<3>(Ud, nd, F, gas.g);
-      const double sc = w / sg[3 + d];
+      const double sc = w / sg[3 + dsel];
 #pragma unroll
       for (int v = 0; v < PV; ++v)
 #pragma unroll
-        for (int ww = 0; ww < PV; ++ww) sJ[t * 75 + d * 25 + v * 5 + ww] = sc * F[v].d[ww];
-    }
-    double xv_[N];
-    mono_values<P, P>(pw, xv_);
-#pragma unroll
-    for (int j = 0; j < N; ++j) sX[t * N + j] = xv_[j];
-  }
-  __syncthreads();
-  // each thread owns a mode pair (k, l) and a group of VPT of the 25 (v, w):
-  // the two monomial values are read once per point for the whole group, the
-  // group's Jacobian entries are contiguous (NG groups keep the 256 threads
-  // busy at the low orders)
-  double acc[OPT2][VPT];
-#pragma unroll
-  for (int m = 0; m < OPT2; ++m) {
-#pragma unroll
-    for (int j = 0; j < VPT; ++j) acc[m][j] = 0.0;
-    const int idx = t + 256 * m;
-    if (idx < NN * NG) {
-      const int kl = idx % NN, vw0 = (idx / NN) * VPT;
-      const int k = kl / N, l = kl % N;
+        for (int ww = 0; ww < PV; ++ww) sJ[t * 75 + dsel * 25 + v * 5 + ww] = sc * F[v].d[ww];
+    } else {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const int ex = kMono.ex[k][d], lo = kMono.lo[k][d];
-        if (ex > 0) {
-          for (int q = 0; q < QV; ++q) {
-            const double c = (double)ex * sX[q * N + lo] * sX[q * N + l];
-            const double* Jq = sJ + q * 75 + d * 25 + vw0;
+        double nd[3] = {0.0, 0.0, 0.0};
+        nd[d] = 1.0;
+        D5 F[PV];
+        eg::flux_n<3>(Ud, nd, F, gas.g);
+        const double sc = w / sg[3 + d];
 #pragma unroll
-            for (int j = 0; j < VPT; ++j)
-              if (vw0 + j < 25) acc[m][j] += Jq[j] * c;
-          }
-        }
+        for (int v = 0; v < PV; ++v)
+#pragma unroll
+          for (int ww = 0; ww < PV; ++ww) sJ[t * 75 + d * 25 + v * 5 + ww] = sc * F[v].d[ww];
       }
     }
-  }
-  __syncthreads();  // the volume staging is dead from here
-  double* sK = sbuf + RF;
+    if (dsel <= 0) {
+      double xv_[N];
+      mono_values<P, P>(pw, xv_);
 #pragma unroll
-  for (int m = 0; m < OPT2; ++m) {
-    const int idx = t + 256 * m;
-    if (idx < NN * NG) {
-      const int kl = idx % NN, vw0 = (idx / NN) * VPT;
-#pragma unroll
-      for (int j = 0; j < VPT; ++j)
-        if (vw0 + j < 25) sK[(vw0 + j) * NN + kl] = acc[m][j];
+      for (int j = 0; j < N; ++j) sX[t * N + j] = xv_[j];
     }
-  }
-  // ---- face points: w dF~/dU_own and the monomials
-  double* sB = sbuf;
-  double* sY = sbuf + NFQ * 25;
-  const int nfq = nf * QF;
-  if (t < nfq) {
+  };
+  auto face_point = [&](const int t) {
     const int f = t / QF, q = t % QF;
     const int nb = snb[f];
     const int32_t* cv = M.fcv + ((size_t)e * 5 + f) * 4;
@@ -710,6 +696,56 @@ __global__ __launch_bounds__(256) void k_poly_block(PolyDev M, PolyRule R, eg::G
     mono_values<P, P>(pw, xv_);
 #pragma unroll
     for (int j = 0; j < N; ++j) sY[t * N + j] = xv_[j];
+  };
+  if (t < NVT) {
+    if constexpr (VSPLIT) vol_point(t / 3, t % 3);
+    else vol_point(t, -1);
+  } else if (CONC && t >= FOFF && t - FOFF < nfq) {
+    face_point(t - FOFF);
+  }
+  __syncthreads();
+  // each thread owns a mode pair (k, l) and a group of VPT of the 25 (v, w):
+  // the two monomial values are read once per point for the whole group, the
+  // group's Jacobian entries are contiguous (NG groups keep the 256 threads
+  // busy at the low orders)
+  double acc[OPT2][VPT];
+#pragma unroll
+  for (int m = 0; m < OPT2; ++m) {
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) acc[m][j] = 0.0;
+    const int idx = t + 256 * m;
+    if (idx < NN * NG) {
+      const int kl = idx % NN, vw0 = (idx / NN) * VPT;
+      const int k = kl / N, l = kl % N;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int ex = kMono.ex[k][d], lo = kMono.lo[k][d];
+        if (ex > 0) {
+          for (int q = 0; q < QV; ++q) {
+            const double c = (double)ex * sX[q * N + lo] * sX[q * N + l];
+            const double* Jq = sJ + q * 75 + d * 25 + vw0;
+#pragma unroll
+            for (int j = 0; j < VPT; ++j)
+              if (vw0 + j < 25) acc[m][j] += Jq[j] * c;
+          }
+        }
+      }
+    }
+  }
+  if constexpr (!CONC) __syncthreads();  // the volume staging is dead from here
+  double* sK = sbuf + RF;
+#pragma unroll
+  for (int m = 0; m < OPT2; ++m) {
+    const int idx = t + 256 * m;
+    if (idx < NN * NG) {
+      const int kl = idx % NN, vw0 = (idx / NN) * VPT;
+#pragma unroll
+      for (int j = 0; j < VPT; ++j)
+        if (vw0 + j < 25) sK[(vw0 + j) * NN + kl] = acc[m][j];
+    }
+  }
+  if constexpr (!CONC) {
+    if (t < nfq) face_point(t);
   }
   __syncthreads();
 #pragma unroll
